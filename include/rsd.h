@@ -1,0 +1,189 @@
+/*
+ * rsd.h -- C interface of the recursive-skeletonisation direct solver for
+ * 2-D volume integral equations on MI355X (gfx950).
+ *
+ * Method: Corona, Martinsson, Zorin, "An O(N) Direct Solver for Integral
+ * Equations on the Plane".  The solver builds a compressed inverse of the
+ * Nystrom matrix of
+ *     a(x) s(x) + int_Omega b(x) K(|x - y|) c(y) s(y) dy = f(x)
+ * (Sec. 5, general formulation) on a regular grid, level by level over the
+ * binary tree of Sec. 2.2, with boundary-layer skeletons (Sec. 3.1), proxy
+ * interpolation (Sec. 2.2, Sec. 3.3.2) and the inverse of Algorithm 1 in the
+ * block form of Algorithm 2, and applies it with Algorithm 6.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major.  A block of right-hand sides is N x nrhs with
+ *     leading dimension N (column c starts at element c * N).
+ *   - Pointers may be host or device memory (detected per call).  Inputs are
+ *     borrowed for the duration of the call only; the factor owns copies of
+ *     everything it keeps.  Outputs are written by the library into memory
+ *     the caller allocated.
+ *   - Every function returns an rsd_status; on failure a description is
+ *     available from rsd_last_error() (thread-local) and output handles are
+ *     set to NULL.  No C++ exception crosses this interface.
+ *   - Complex data (Helmholtz kernel) is interleaved (re, im) double pairs.
+ */
+#ifndef RSD_H
+#define RSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rsd_status {
+    RSD_OK = 0,
+    RSD_EINVAL = 1,     /* bad argument: NaN/Inf input, tol <= 0, nrhs < 0, ... */
+    RSD_ENOTGRID = 2,   /* points are not a complete uniform grid (Sec. 2.2) */
+    RSD_ENOMEM = 3,     /* device memory exhausted or over the caller's budget */
+    RSD_ESINGULAR = 4,  /* a pivot block was singular; message names level/box */
+    RSD_ENOCONV = 5,    /* iterative refinement did not reach its tolerance */
+    RSD_EDEVICE = 6     /* HIP runtime error */
+} rsd_status;
+
+typedef enum rsd_kernel_type {
+    RSD_KERNEL_LAPLACE = 0,   /* K(r) = (1/2pi) log r                         */
+    RSD_KERNEL_HELMHOLTZ = 1  /* G(r) = (i/4) H0^(1)(k r), outgoing solution   */
+} rsd_kernel_type;
+
+/* Kernel of the integral operator.  With contrast_b == NULL the matrix is
+ *   A_ij = a_i delta_ij + h^2 K(|x_i - x_j|)        (i != j),
+ *   A_ii = a_i + int_{cell_i} K(|x_i - y|) dy,
+ * the Nystrom rule of Sec. 5 with b = c = 1 and the exact integral of the
+ * kernel over the point's own cell on the diagonal.  With contrast_b given
+ * (N values, b >= 0) it is the scattering operator of Sec. 5.4:
+ *   A_ij = sqrt(b_i) h^2 G(|x_i - x_j|) sqrt(b_j),  A_ii = 1 + b_i int_cell G. */
+typedef struct rsd_kernel {
+    int32_t type;              /* rsd_kernel_type                           */
+    double wavenumber;         /* k of the Helmholtz kernel; ignored else   */
+    const double* contrast_b;  /* N values in the caller's point order, or NULL */
+} rsd_kernel;
+
+typedef enum rsd_precision {
+    RSD_PREC_FP64 = 0,         /* every level in float64                    */
+    RSD_PREC_FP32_REFINE = 1   /* levels in float32, root block in float64,
+                                  float64 residual + iterative refinement   */
+} rsd_precision;
+
+/* Options; an all-zero struct selects the defaults. */
+typedef struct rsd_options {
+    int32_t leaf_side;     /* largest leaf side in points; 0 => 8               */
+    int32_t layers;        /* skeleton/proxy layers m; 0 => from tol:
+                              1 if tol >= 1e-6, 2 if tol >= 1e-11, else 3      */
+    int32_t precision;     /* rsd_precision                                    */
+    int32_t max_refine;    /* refinement steps per solve; 0 => 10 for
+                              FP32_REFINE, none for FP64; < 0 => none          */
+    double refine_tol;     /* target relative residual; 0 => tol               */
+    void* hip_stream;      /* hipStream_t to run on; NULL => a library stream  */
+    int32_t device;        /* HIP device ordinal; < 0 => the current device    */
+    int32_t flags;         /* RSD_FLAG_* bits                                  */
+} rsd_options;
+
+/* Keep every box's E_i block after the build (for inspection). */
+#define RSD_FLAG_KEEP_E 1
+
+typedef struct rsd_solve_info {
+    int32_t refine_iters;  /* refinement steps taken                          */
+    double rel_residual;   /* max over columns of |f - A x| / |f| (exact,
+                              float64), or -1 when no residual was computed    */
+} rsd_solve_info;
+
+typedef struct rsd_factor rsd_factor;
+
+/* Build the compressed inverse (Algorithm 1 in the form of Algorithm 2,
+ * fine-to-coarse over the tree of Sec. 2.2).
+ *   points  N x 2 row-major (x, y) coordinates of a complete uniform grid in
+ *           any order (the solver permutes internally; results come back in
+ *           this order).
+ *   a       N identity-term coefficients a(x_i) in point order; NULL => 1.
+ *           Ignored when kernel->contrast_b is set (then a = 1).
+ *   tol     local truncation tolerance of every compression (Sec. 5.1), > 0.
+ *   opt     NULL => defaults.
+ *   out     receives the factor; free it with rsd_free.
+ * Errors: EINVAL, ENOTGRID, ENOMEM, ESINGULAR, EDEVICE.  The call returns
+ * after the factor is complete on the device. */
+rsd_status rsd_build_factor(const double* points, int64_t n_points,
+                            const rsd_kernel* kernel, const double* a,
+                            double tol, const rsd_options* opt,
+                            rsd_factor** out);
+
+/* x = A^{-1} rhs with the compressed inverse (Algorithm 6), followed by
+ * float64 iterative refinement when the factor was built with
+ * RSD_PREC_FP32_REFINE (or max_refine > 0).
+ *   rhs, x  N x nrhs column-major, caller's point order; real double for the
+ *           Laplace kernel, interleaved complex double for Helmholtz.
+ *   info    NULL or receives refinement statistics.
+ * Errors: EINVAL (NaN/Inf in rhs, nrhs < 0), ENOCONV (refinement did not
+ * reach refine_tol; x then holds the last iterate and info the residual),
+ * EDEVICE.  Concurrent calls on one factor are not supported; separate
+ * factors may be solved from separate threads. */
+rsd_status rsd_solve(rsd_factor* f, const double* rhs, int64_t nrhs,
+                     double* x, rsd_solve_info* info);
+
+/* y = A x exactly in float64 (direct sum over all pairs, Sec. 5 general
+ * formulation), same layouts as rsd_solve.  Used for residuals. */
+rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y);
+
+/* Release a factor and all its device memory.  NULL is a no-op. */
+void rsd_free(rsd_factor* f);
+
+/* Description of the last error on this thread ("" if none). */
+const char* rsd_last_error(void);
+
+/* ---- inspection --------------------------------------------------------- */
+
+typedef struct rsd_factor_stats {
+    int64_t n_points, nx, ny;
+    int32_t n_levels;        /* tree levels including the root               */
+    int32_t n_boxes;
+    int32_t layers;          /* m actually used                              */
+    int32_t precision;
+    int64_t factor_bytes;    /* device bytes held by the factor              */
+    double factor_flops;     /* algorithmic flops of the build (model)       */
+    double solve_bytes;      /* factor bytes streamed by one solve           */
+    double build_ms;         /* device time of the last build                */
+} rsd_factor_stats;
+
+rsd_status rsd_factor_get_stats(const rsd_factor* f, rsd_factor_stats* out);
+
+/* Per-box description: level (height above the leaves, 0 = leaves), grid
+ * origin/size, skeleton size k and residual size r. */
+typedef struct rsd_box_info {
+    int32_t level, x0, y0, ax, ay, k, r, parent;
+} rsd_box_info;
+rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* out);
+
+/* Copy one per-box block to host memory (column-major):
+ *   which = 0: T_i (k x r), the interpolation of Sec. 3.1 (R_i = [I T_i])
+ *   which = 1: E_i (k x k), needs RSD_FLAG_KEEP_E
+ *   which = 2: active point ids of the box in [skeleton; residual] order
+ *              (k + r int64 grid indices i * ny + j), independent of dtype.
+ * dst must hold the block; elements are double (complex: interleaved). */
+rsd_status rsd_factor_get_block(const rsd_factor* f, int32_t box, int32_t which, void* dst);
+
+/* ---- host-only planning (no device needed) ------------------------------ */
+
+/* Number of boxes and levels the tree of Sec. 2.2 / Sec. 3.1 produces for an
+ * nx x ny grid, and per-box sizes.  Pure host computation, usable without a
+ * GPU; boxes are numbered level by level from the leaves. */
+typedef struct rsd_plan rsd_plan;
+rsd_status rsd_plan_create(int64_t nx, int64_t ny, int32_t leaf_side, int32_t layers,
+                           rsd_plan** out);
+int32_t rsd_plan_n_boxes(const rsd_plan* p);
+int32_t rsd_plan_n_levels(const rsd_plan* p);
+rsd_status rsd_plan_box_info(const rsd_plan* p, int32_t box, rsd_box_info* out);
+/* active point ids of a box, [skeleton; residual] order (k + r int64) */
+rsd_status rsd_plan_box_points(const rsd_plan* p, int32_t box, int64_t* dst);
+void rsd_plan_free(rsd_plan* p);
+
+/* Grid detection used by rsd_build_factor: on success nx, ny, h and perm
+ * (perm[g] = caller index of grid point g = i * ny + j) are filled. */
+rsd_status rsd_detect_grid(const double* points_host, int64_t n_points,
+                           int64_t* nx, int64_t* ny, double* h, int64_t* perm);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSD_H */

@@ -1,0 +1,182 @@
+// Shared device-side types and launch declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+namespace rsd {
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+#define RSD_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::rsd::HipError(std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel description passed by value to every generation kernel.
+// Off-diagonal entry between grid points p != q:
+//   h^2 * K(h * |(du, dv)|) * sb_p * sb_q     (sb = sqrt(b) or 1)
+// Diagonal entry of point p:
+//   a_p + sc          (no contrast)      or   1 + b_p * sc   (contrast)
+// with sc the integral of K over the point's own cell.
+// ---------------------------------------------------------------------------
+struct KernelDesc {
+    int type;          // 0 Laplace, 1 Helmholtz
+    int has_b;         // contrast present
+    double h;          // grid spacing
+    double logh;       // log(h)
+    double k;          // wavenumber
+    double sc_re, sc_im;   // self-cell integral
+    const double* a;   // grid-ordered identity coefficient (N) or nullptr
+    const double* sb;  // grid-ordered sqrt(b) (N) or nullptr
+    int64_t ny;        // grid index g = i * ny + j
+};
+
+// Per-box record used by the device kernels.
+struct BoxDev {
+    int x0, y0;
+    int k, r;
+    int layout;
+    int parent;
+    int pos;           // which child of the parent
+    int child0, child1;
+    int level;
+    int64_t offF;      // F block offset in the level's arena (elements)
+    int64_t offV;      // vector block offset (elements per rhs)
+    int64_t offY;      // residual-part block offset (elements per rhs)
+};
+
+struct LayoutDev {
+    int k, r;
+    int off_uv;        // start of the layout's entries in the u/v tables
+    int off_inv0, off_inv1;   // start of the inverse maps (child sk -> parent pos)
+    int idp;           // interpolation problem (-1 none)
+    int64_t offT;      // T block (k x r) in the T arena, -1 if none
+};
+
+// Column-major GEMM descriptor: C = alpha * opA(A) * opB(B) + beta * C,
+// optionally accumulating a second product opA(A2) * opB(B2) (K2 > 0).
+template <typename T>
+struct GemmDesc {
+    int M, N, K, K2;
+    int tA, tB, tA2, tB2;
+    const T* A; const T* B; const T* A2; const T* B2;
+    T* C;
+    int lda, ldb, lda2, ldb2, ldc;
+    int zc0, zc1;      // columns [zc0, zc1) of C use beta = 0
+    T alpha, beta;
+};
+
+struct TileRef {
+    int desc;
+    int tm, tn;
+};
+
+constexpr int GEMM_TILE = 64;
+
+// ------------------------------- launchers ---------------------------------
+template <typename T>
+void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, hipStream_t s);
+
+// generation / assembly
+template <typename T>
+void launch_leaf_F(T* F, const BoxDev* boxes, const int* box_ids, int n_boxes,
+                   const LayoutDev* layouts, const int* lu, const int* lv, KernelDesc kd,
+                   int max_m, hipStream_t s);
+template <typename TS, typename TD>
+void launch_assemble_F(TD* F, const TS* Fchild, const BoxDev* boxes, const int* box_ids,
+                       int n_boxes, const LayoutDev* layouts, const int* lu, const int* lv,
+                       const int* src_c, const int* src_i, KernelDesc kd, int max_m,
+                       hipStream_t s);
+template <typename T>
+void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes, int max_k,
+                         int max_r, hipStream_t s);
+template <typename T>
+void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* k_of,
+                         const int* r_of, const int* zoff, const int* zu, const int* zv,
+                         const int* xoff, const int* lu, const int* lv, int n_problems,
+                         int max_pn, KernelDesc kd, hipStream_t s);
+
+// QR least squares for T (block column pivoting)
+constexpr int QR_NB = 16;
+struct QRProblemDev {
+    int p, k, r, nb;   // nb: panel width (16, 8 or 4 by size)
+    int64_t offA;      // p x (k + r) matrix, ld = p
+    int64_t offT;      // output T (k x r), ld = k
+    int64_t offAux;    // norms (k), tau (k), T-factor (QR_NB^2), r11 (1)
+    int64_t offIaux;   // perm (k), rank, nref, j0, nbe
+};
+template <typename T>
+void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int max_k,
+                    hipStream_t s);
+// plist: problem ids of one panel-width class; nb_class in {16, 8, 4}
+template <typename T>
+void launch_qr_panel(T* A, T* aux, int* iaux, const QRProblemDev* probs, const int* plist,
+                     int n_list, int nb_class, int step, double tol, hipStream_t s);
+int qr_panel_width(int p);
+template <typename T>
+void launch_qr_update(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int step,
+                      int max_n, hipStream_t s);
+template <typename T>
+void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs, int n_probs,
+                     int max_r, int max_k, hipStream_t s);
+
+// Gauss-Jordan pivot step (see gj kernels)
+template <typename T>
+struct GJDesc {
+    T* X;            // base of the r x ncols block (row 0 = first pivot row)
+    int ld;
+    int n;           // pivot block size (number of rows)
+    int ncols;       // total columns updated
+    int pcol;        // column index of the first pivot column
+    T* SR;           // nb x ncols side buffer (ld = nb)
+    T* SC;           // n x nb side buffer (ld = n)
+    int box;         // for error reports
+};
+template <typename T>
+void launch_gj_pivot(const GJDesc<T>* d, int n_desc, int step, int nb, int max_chunks,
+                     int* err, hipStream_t s);
+
+// solve-phase gathers and scatters
+template <typename TS, typename TD>
+void launch_gather_leaf(TD* V, const TS* f, int64_t ldf, int nrhs, const BoxDev* boxes,
+                        const int* box_ids, int n_boxes, const LayoutDev* layouts, const int* lu,
+                        const int* lv, const int64_t* perm, int64_t ny, int max_m, hipStream_t s);
+template <typename TS, typename TD>
+void launch_scatter_leaf(TD* x, int64_t ldx, const TS* V, const TS* Y, int nrhs,
+                         const BoxDev* boxes, const int* box_ids, int n_boxes,
+                         const LayoutDev* layouts, const int* lu, const int* lv,
+                         const int64_t* perm, int64_t ny, int max_m, hipStream_t s);
+template <typename TS, typename TD>
+void launch_scatter_up(TD* Vparent, const TS* V, int nrhs, const BoxDev* boxes, const int* box_ids,
+                       int n_boxes, const LayoutDev* layouts, const int* inv, int max_k,
+                       hipStream_t s);
+template <typename TS, typename TD>
+void launch_gather_down(TD* V, const TS* Vparent, const TS* Yparent, int nrhs,
+                        const BoxDev* boxes, const int* box_ids, int n_boxes,
+                        const LayoutDev* layouts, const int* inv, int max_k, hipStream_t s);
+
+// exact float64 matvec y = A x on the grid (grid-ordered vectors)
+void launch_matvec_table(double* table, int64_t nx, int64_t ny, KernelDesc kd, hipStream_t s);
+void launch_matvec(double* y, const double* x, int nrhs, const double* table, int64_t nx,
+                   int64_t ny, KernelDesc kd, int cplx, hipStream_t s);
+
+// elementwise helpers
+template <typename TS, typename TD>
+void launch_convert(TD* dst, const TS* src, int64_t n, hipStream_t s);
+void launch_permute(double* dst, const double* src, const int64_t* perm, int64_t n, int nrhs,
+                    int width, int to_grid, hipStream_t s);
+void launch_axpy_resid(double* r, const double* f, const double* Ax, int64_t n, hipStream_t s);
+void launch_add(double* x, const double* d, int64_t n, hipStream_t s);
+void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, hipStream_t s);
+void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace rsd

@@ -1,0 +1,1156 @@
+// Factor object, level-by-level build, inverse apply and the C interface.
+//
+// Build (Algorithm 1 in the block form of Algorithm 2, fine-to-coarse):
+//   interpolation  T for every box type: proxy matrices, pivoted QR (k_qr)
+//   per level      F_i = D_i (leaves) or [E_c1 K12; K21 E_c2] (k_gen)
+//                  F'_sr = F_sr - F_ss T                        (GEMM)
+//                  F'_rr = F_rr - F_rs T - T^T F'_sr            (GEMM, 2 terms)
+//                  F'_rs = F'_sr^T                              (transpose)
+//                  [F'_rr | F'_rs] -> [G | W], G = F'_rr^{-1}   (Gauss-Jordan)
+//                  E_i = F_ss - F'_sr W                         (GEMM)
+//   top            the root is eliminated the same way with its first child
+//                  as residual and T = 0, and the remaining block inverted.
+// E_i here equals (R_i F_i^{-1} L_i)^{-1} of Algorithm 1: F' = P^{-T} F P^{-1}
+// with P = [I T; 0 I] is a congruence, and the skeleton block of F'^{-1} is
+// the inverse of the Schur complement F'_ss - F'_sr F'_rr^{-1} F'_rs.
+//
+// Solve (Algorithm 6 in the same variables), per box:
+//   up    f'_r = f_r - T^T f_s ;  y = G f'_r ;  g = f_s - W^T f'_r  -> parent
+//   top   phi = G_top g
+//   down  s'_r = y - W phi ;  s_s = phi - T s'_r ;  s_r = s'_r      -> children
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/rsd.h"
+#include "common.hpp"
+#include "plan.hpp"
+
+namespace rsd {
+
+struct Error : std::runtime_error {
+    rsd_status code;
+    Error(rsd_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+static thread_local std::string g_last_error;
+
+// ----------------------------------------------------------------------------
+// device memory
+// ----------------------------------------------------------------------------
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw Error(RSD_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+        }
+        bytes = n;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+static void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+    b.alloc(v.size() * sizeof(T));
+    if (!v.empty()) RSD_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+static bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// ----------------------------------------------------------------------------
+// GEMM batches: descriptors + tile tables, uploaded once
+// ----------------------------------------------------------------------------
+template <typename T>
+struct GemmBatch {
+    std::vector<GemmDesc<T>> descs;
+    std::vector<TileRef> tiles;
+    const GemmDesc<T>* d_descs = nullptr;
+    const TileRef* d_tiles = nullptr;
+    double flops = 0;
+    void add(const GemmDesc<T>& d) {
+        if (d.M <= 0 || d.N <= 0) return;
+        const int id = (int)descs.size();
+        descs.push_back(d);
+        const int tm = (d.M + GEMM_TILE - 1) / GEMM_TILE, tn = (d.N + GEMM_TILE - 1) / GEMM_TILE;
+        for (int i = 0; i < tm; ++i)
+            for (int j = 0; j < tn; ++j) tiles.push_back({id, i, j});
+        flops += 2.0 * d.M * d.N * (double)(std::max(d.K, 0) + std::max(d.K2, 0));
+    }
+    void run(hipStream_t s) const {
+        if (!tiles.empty()) launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), s);
+    }
+};
+
+template <typename T>
+static GemmDesc<T> gdesc(int M, int N, int K, const T* A, int lda, int tA, const T* B, int ldb,
+                         int tB, T* C, int ldc, T alpha, T beta) {
+    GemmDesc<T> d;
+    std::memset(&d, 0, sizeof(d));
+    d.M = M; d.N = N; d.K = K; d.K2 = 0;
+    d.A = A; d.lda = lda; d.tA = tA;
+    d.B = B; d.ldb = ldb; d.tB = tB;
+    d.A2 = nullptr; d.B2 = nullptr; d.lda2 = 1; d.ldb2 = 1;
+    d.C = C; d.ldc = ldc;
+    d.alpha = alpha; d.beta = beta;
+    d.zc0 = d.zc1 = 0;
+    return d;
+}
+
+// Uploads every batch of a list into one buffer and fixes their device pointers.
+template <typename T>
+static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStream_t s) {
+    size_t nd = 0, nt = 0;
+    for (auto* b : bs) { nd += b->descs.size(); nt += b->tiles.size(); }
+    std::vector<unsigned char> host(nd * sizeof(GemmDesc<T>) + nt * sizeof(TileRef) + 64);
+    buf.alloc(host.size());
+    size_t od = 0, ot = nd * sizeof(GemmDesc<T>);
+    ot = (ot + 15) & ~size_t(15);
+    unsigned char* base = buf.as<unsigned char>();
+    for (auto* b : bs) {
+        std::memcpy(host.data() + od, b->descs.data(), b->descs.size() * sizeof(GemmDesc<T>));
+        std::memcpy(host.data() + ot, b->tiles.data(), b->tiles.size() * sizeof(TileRef));
+        b->d_descs = reinterpret_cast<const GemmDesc<T>*>(base + od);
+        b->d_tiles = reinterpret_cast<const TileRef*>(base + ot);
+        od += b->descs.size() * sizeof(GemmDesc<T>);
+        ot += b->tiles.size() * sizeof(TileRef);
+    }
+    RSD_HIP(hipMemcpyAsync(buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
+}
+
+constexpr int GJ_NB = 32;
+
+// ----------------------------------------------------------------------------
+// per-level execution plan (one precision per level)
+// ----------------------------------------------------------------------------
+template <typename T>
+struct LevelExec {
+    int level = 0;
+    std::vector<int> ids;        // box ids
+    int max_m = 0, max_k = 0, max_r = 0, max_chunks = 0;
+    GemmBatch<T> g_sr, g_rr, g_E;
+    std::vector<GemmBatch<T>> g_gj;   // one per Gauss-Jordan step
+    GemmBatch<T> g_top;               // root only: unused placeholder
+    std::vector<GJDesc<T>> gj;        // per box
+    const GJDesc<T>* d_gj = nullptr;
+    std::vector<GemmBatch<T>> g_topgj;   // root: inversion of the remaining block
+    std::vector<GJDesc<T>> topgj;
+    const GJDesc<T>* d_topgj = nullptr;
+    int top_chunks = 0;
+    int gj_steps = 0, topgj_steps = 0;
+};
+
+template <typename T>
+struct SolveLevel {
+    GemmBatch<T> up1, up2, dn1, dn2, top;
+};
+
+struct SolvePlan {
+    int nrhs = 0;
+    DevBuf V32, V64, Y32, Y64, tmp, in, out, gemm32, gemm64;
+    std::vector<SolveLevel<float>> L32;
+    std::vector<SolveLevel<double>> L64;
+};
+
+struct Factor {
+    Plan plan;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int precision = RSD_PREC_FP64;
+    int max_refine = 0;
+    double refine_tol = 0;
+    double tol = 0;
+    int64_t N = 0, nx = 0, ny = 0;
+    double h = 0;
+    int cplx = 0;
+    int top = 0;                    // root level
+    int flags = 0;
+    KernelDesc kd{};
+    std::vector<int> level_prec;    // 0 fp64, 1 fp32
+    // device tables
+    DevBuf d_boxes, d_layouts, d_lu, d_lv, d_srcc, d_srci, d_inv, d_perm, d_ident, d_a, d_sb,
+        d_level_ids, d_err, d_table;
+    std::vector<int> level_id_off;
+    DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
+    std::vector<LevelExec<double>> L64;
+    std::vector<LevelExec<float>> L32;
+    std::vector<BoxDev> hboxes;
+    std::vector<LayoutDev> hlayouts;
+    std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
+    rsd_factor_stats stats{};
+    ~Factor() {
+        solve_plans.clear();
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    const int* ids(int t) const { return d_level_ids.as<int>() + level_id_off[t]; }
+};
+
+template <typename T> static T* Fbase(Factor& f);
+template <> double* Fbase<double>(Factor& f) { return f.F64.as<double>(); }
+template <> float* Fbase<float>(Factor& f) { return f.F32.as<float>(); }
+template <typename T> static T* Tbase(Factor& f);
+template <> double* Tbase<double>(Factor& f) { return f.T64.as<double>(); }
+template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
+
+// ----------------------------------------------------------------------------
+// interpolation matrices for every box type (one problem per layout)
+// ----------------------------------------------------------------------------
+template <typename T>
+static void compute_T(Factor& f, const std::vector<int>& probs_ids, hipStream_t s) {
+    Plan& P = f.plan;
+    if (probs_ids.empty()) return;
+    std::vector<QRProblemDev> qp;
+    std::vector<int64_t> offA;
+    std::vector<int> pof, kof, rof, zoff, xoff, zu, zv;
+    int64_t A_el = 0, aux_el = 0, iaux_el = 0;
+    int max_pn = 0, max_k = 0, max_r = 0, max_n = 0;
+    for (int id : probs_ids) {
+        const IDProblem& I = P.idps[id];
+        const Layout& L = P.layouts[I.layout];
+        QRProblemDev q;
+        q.p = I.p; q.k = I.k; q.r = I.r;
+        q.nb = qr_panel_width(I.p);
+        if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
+        q.offA = A_el;
+        q.offT = f.hlayouts[I.layout].offT;
+        q.offAux = aux_el;
+        q.offIaux = iaux_el;
+        A_el += (int64_t)I.p * (I.k + I.r);
+        aux_el += 2 * I.k + QR_NB * QR_NB + 8;
+        iaux_el += I.k + 8;
+        qp.push_back(q);
+        offA.push_back(q.offA);
+        pof.push_back(I.p); kof.push_back(I.k); rof.push_back(I.r);
+        zoff.push_back((int)zu.size());
+        zu.insert(zu.end(), I.zu.begin(), I.zu.end());
+        zv.insert(zv.end(), I.zv.begin(), I.zv.end());
+        xoff.push_back(f.hlayouts[I.layout].off_uv);
+        max_pn = std::max(max_pn, I.p * (I.k + I.r));
+        max_k = std::max(max_k, I.k);
+        max_r = std::max(max_r, I.r);
+        max_n = std::max(max_n, I.k + I.r);
+        (void)L;
+    }
+    DevBuf dA, daux, diaux, dq, doffA, dp, dk, dr, dzo, dzu, dzv, dxo, dlist;
+    dA.alloc(A_el * sizeof(T));
+    daux.alloc(aux_el * sizeof(T));
+    diaux.alloc(iaux_el * sizeof(int));
+    upload(dq, qp, s); upload(doffA, offA, s); upload(dp, pof, s); upload(dk, kof, s);
+    upload(dr, rof, s); upload(dzo, zoff, s); upload(dzu, zu, s); upload(dzv, zv, s);
+    upload(dxo, xoff, s);
+    launch_proxy_matrix<T>(dA.as<T>(), doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
+                           dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
+                           dxo.as<int>(), f.d_lu.as<int>(), f.d_lv.as<int>(), (int)qp.size(),
+                           max_pn, f.kd, s);
+    launch_qr_init<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(),
+                      (int)qp.size(), max_k, s);
+    // problem lists per panel-width class
+    std::vector<int> lists[3];
+    int steps = 0;
+    for (int i = 0; i < (int)qp.size(); ++i) {
+        int c = qp[i].nb == 16 ? 0 : (qp[i].nb == 8 ? 1 : 2);
+        lists[c].push_back(i);
+        steps = std::max(steps, (qp[i].k + qp[i].nb - 1) / qp[i].nb);
+    }
+    std::vector<int> flat;
+    int off[3];
+    for (int c = 0; c < 3; ++c) { off[c] = (int)flat.size(); flat.insert(flat.end(), lists[c].begin(), lists[c].end()); }
+    upload(dlist, flat, s);
+    const int widths[3] = {16, 8, 4};
+    // a float32 factor cannot resolve pivots below its rounding level
+    const double qr_tol = std::is_same<T, float>::value ? std::max(f.tol, 1e-6) : f.tol;
+    for (int st = 0; st < steps; ++st) {
+        for (int c = 0; c < 3; ++c)
+            if (!lists[c].empty())
+                launch_qr_panel<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(),
+                                   dlist.as<int>() + off[c], (int)lists[c].size(), widths[c], st,
+                                   qr_tol, s);
+        launch_qr_update<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(),
+                            (int)qp.size(), st, max_n, s);
+    }
+    launch_qr_solve<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), Tbase<T>(f), dq.as<QRProblemDev>(),
+                       (int)qp.size(), max_r, max_k, s);
+    RSD_HIP(hipStreamSynchronize(s));   // scratch buffers go out of scope
+}
+
+// ----------------------------------------------------------------------------
+// level plans
+// ----------------------------------------------------------------------------
+template <typename T>
+static void plan_level(Factor& f, LevelExec<T>& L, int t, std::vector<GemmBatch<T>*>& all,
+                       int64_t& sr_need, int64_t& sc_need) {
+    Plan& P = f.plan;
+    L.level = t;
+    L.ids = P.levels[t];
+    T* F = Fbase<T>(f);
+    T* Tb = Tbase<T>(f);
+    int64_t sr = 0, sc = 0;
+    for (int id : L.ids) {
+        const Box& b = P.boxes[id];
+        const LayoutDev& LD = f.hlayouts[b.layout];
+        const int k = b.k, r = b.r, m = k + r;
+        L.max_m = std::max(L.max_m, m);
+        L.max_k = std::max(L.max_k, k);
+        L.max_r = std::max(L.max_r, r);
+        T* Fb = F + b.offF;
+        T* Fss = Fb;
+        T* Fsr = Fb + (int64_t)k * m;
+        T* Frs = Fb + k;
+        T* Frr = Fb + k + (int64_t)k * m;
+        const T* Tm = LD.offT >= 0 ? Tb + LD.offT : nullptr;
+        if (r > 0 && Tm) {
+            L.g_sr.add(gdesc<T>(k, r, k, Fss, m, 0, Tm, k, 0, Fsr, m, T(-1), T(1)));
+            GemmDesc<T> d = gdesc<T>(r, r, k, Frs, m, 0, Tm, k, 0, Frr, m, T(-1), T(1));
+            d.K2 = k; d.A2 = Tm; d.lda2 = k; d.tA2 = 1; d.B2 = Fsr; d.ldb2 = m; d.tB2 = 0;
+            L.g_rr.add(d);
+        }
+        if (r > 0) {
+            GJDesc<T> g;
+            g.X = Frs; g.ld = m; g.n = r; g.ncols = m; g.pcol = k;
+            g.SR = nullptr; g.SC = nullptr; g.box = id;
+            L.gj.push_back(g);
+            sr += (int64_t)GJ_NB * m;
+            sc += (int64_t)r * GJ_NB;
+            L.g_E.add(gdesc<T>(k, k, r, Fsr, m, 0, Frs, m, 0, Fss, m, T(-1), T(1)));
+        }
+    }
+    // side buffers (shared by every level, sized for the largest)
+    sr_need = std::max(sr_need, sr);
+    sc_need = std::max(sc_need, sc);
+    L.gj_steps = (L.max_r + GJ_NB - 1) / GJ_NB;
+    L.max_chunks = (L.max_m + 63) / 64;
+    all.push_back(&L.g_sr);
+    all.push_back(&L.g_rr);
+    all.push_back(&L.g_E);
+}
+
+template <typename T>
+static void finish_gj(Factor& f, LevelExec<T>& L, T* SRb, T* SCb, std::vector<GemmBatch<T>*>& all,
+                      std::vector<GJDesc<T>>& gjall) {
+    int64_t osr = 0, osc = 0;
+    for (auto& g : L.gj) {
+        g.SR = SRb + osr;
+        g.SC = SCb + osc;
+        osr += (int64_t)GJ_NB * g.ncols;
+        osc += (int64_t)g.n * GJ_NB;
+    }
+    L.g_gj.resize(L.gj_steps);
+    for (int st = 0; st < L.gj_steps; ++st) {
+        for (auto& g : L.gj) {
+            const int j0 = st * GJ_NB;
+            if (j0 >= g.n) continue;
+            const int nbe = std::min(GJ_NB, g.n - j0);
+            GemmDesc<T> d = gdesc<T>(g.n, g.ncols, nbe, g.SC, g.n, 0, g.SR, GJ_NB, 0, g.X, g.ld,
+                                     T(-1), T(1));
+            d.zc0 = g.pcol + j0;
+            d.zc1 = g.pcol + j0 + nbe;
+            L.g_gj[st].add(d);
+        }
+    }
+    for (auto& b : L.g_gj) all.push_back(&b);
+    (void)f;
+    (void)gjall;
+}
+
+template <typename T>
+static void plan_top(Factor& f, LevelExec<T>& L, T* SRb, T* SCb, std::vector<GemmBatch<T>*>& all) {
+    // invert the remaining k x k block of the root in place
+    const Box& b = f.plan.boxes[f.plan.root];
+    const int k = b.k, m = b.k + b.r;
+    T* Fss = Fbase<T>(f) + b.offF;
+    GJDesc<T> g;
+    g.X = Fss; g.ld = m; g.n = k; g.ncols = k; g.pcol = 0; g.SR = SRb; g.SC = SCb; g.box = f.plan.root;
+    L.topgj.push_back(g);
+    L.topgj_steps = (k + GJ_NB - 1) / GJ_NB;
+    L.top_chunks = (k + 63) / 64;
+    L.g_topgj.resize(L.topgj_steps);
+    for (int st = 0; st < L.topgj_steps; ++st) {
+        const int j0 = st * GJ_NB;
+        const int nbe = std::min(GJ_NB, k - j0);
+        GemmDesc<T> d = gdesc<T>(k, k, nbe, SCb, k, 0, SRb, GJ_NB, 0, Fss, m, T(-1), T(1));
+        d.zc0 = j0;
+        d.zc1 = j0 + nbe;
+        L.g_topgj[st].add(d);
+    }
+    for (auto& bb : L.g_topgj) all.push_back(&bb);
+}
+
+template <typename T>
+static void upload_gj(DevBuf& buf, std::vector<LevelExec<T>>& Ls, hipStream_t s) {
+    size_t n = 0;
+    for (auto& L : Ls) n += L.gj.size() + L.topgj.size();
+    std::vector<GJDesc<T>> host;
+    host.reserve(n);
+    for (auto& L : Ls) { host.insert(host.end(), L.gj.begin(), L.gj.end()); }
+    for (auto& L : Ls) { host.insert(host.end(), L.topgj.begin(), L.topgj.end()); }
+    buf.alloc(std::max<size_t>(1, host.size()) * sizeof(GJDesc<T>));
+    if (!host.empty())
+        RSD_HIP(hipMemcpyAsync(buf.p, host.data(), host.size() * sizeof(GJDesc<T>), hipMemcpyHostToDevice, s));
+    size_t o = 0;
+    for (auto& L : Ls) { L.d_gj = buf.as<GJDesc<T>>() + o; o += L.gj.size(); }
+    for (auto& L : Ls) { L.d_topgj = buf.as<GJDesc<T>>() + o; o += L.topgj.size(); }
+}
+
+template <typename T>
+static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
+    const int t = L.level;
+    const int n = (int)L.ids.size();
+    T* F = Fbase<T>(f);
+    const BoxDev* B = f.d_boxes.as<BoxDev>();
+    const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
+    if (t == 0) {
+        launch_leaf_F<T>(F, B, f.ids(t), n, LD, f.d_lu.as<int>(), f.d_lv.as<int>(), f.kd, L.max_m, s);
+    } else {
+        const int child_prec = f.level_prec[t - 1];
+        if constexpr (std::is_same<T, float>::value) {
+            launch_assemble_F<float, float>(F, f.F32.as<float>(), B, f.ids(t), n, LD, f.d_lu.as<int>(),
+                                            f.d_lv.as<int>(), f.d_srcc.as<int>(), f.d_srci.as<int>(),
+                                            f.kd, L.max_m, s);
+        } else if (child_prec == 1) {
+            launch_assemble_F<float, double>(F, f.F32.as<float>(), B, f.ids(t), n, LD, f.d_lu.as<int>(),
+                                             f.d_lv.as<int>(), f.d_srcc.as<int>(), f.d_srci.as<int>(),
+                                             f.kd, L.max_m, s);
+        } else {
+            launch_assemble_F<double, double>(F, f.F64.as<double>(), B, f.ids(t), n, LD,
+                                              f.d_lu.as<int>(), f.d_lv.as<int>(), f.d_srcc.as<int>(),
+                                              f.d_srci.as<int>(), f.kd, L.max_m, s);
+        }
+    }
+    L.g_sr.run(s);
+    L.g_rr.run(s);
+    if (!L.g_sr.tiles.empty()) launch_transpose_sr<T>(F, B, f.ids(t), n, L.max_k, L.max_r, s);
+    for (int st = 0; st < L.gj_steps; ++st) {
+        launch_gj_pivot<T>(L.d_gj, (int)L.gj.size(), st, GJ_NB, L.max_chunks, f.d_err.as<int>(), s);
+        L.g_gj[st].run(s);
+    }
+    L.g_E.run(s);
+    for (int st = 0; st < L.topgj_steps; ++st) {
+        launch_gj_pivot<T>(L.d_topgj, 1, st, GJ_NB, L.top_chunks, f.d_err.as<int>(), s);
+        L.g_topgj[st].run(s);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// build
+// ----------------------------------------------------------------------------
+static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_kernel* kernel,
+                                     const double* a, double tol, const rsd_options* opt) {
+    if (!points || n <= 0) throw Error(RSD_EINVAL, "points must be non-null and n_points > 0");
+    if (!(tol > 0) || !std::isfinite(tol)) throw Error(RSD_EINVAL, "tol must be a positive number");
+    rsd_options o{};
+    if (opt) o = *opt;
+    auto f = std::make_unique<Factor>();
+    if (o.device >= 0) RSD_HIP(hipSetDevice(o.device));
+    RSD_HIP(hipGetDevice(&f->device));
+    if (o.hip_stream) f->stream = static_cast<hipStream_t>(o.hip_stream);
+    else {
+        RSD_HIP(hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking));
+        f->own_stream = true;
+    }
+    hipStream_t s = f->stream;
+    f->tol = tol;
+    f->flags = o.flags;
+    f->precision = o.precision == RSD_PREC_FP32_REFINE ? RSD_PREC_FP32_REFINE : RSD_PREC_FP64;
+    if (o.precision != RSD_PREC_FP64 && o.precision != RSD_PREC_FP32_REFINE)
+        throw Error(RSD_EINVAL, "unknown precision");
+    f->max_refine = o.max_refine < 0 ? 0 : (o.max_refine == 0 ? (f->precision == RSD_PREC_FP32_REFINE ? 10 : 0) : o.max_refine);
+    f->refine_tol = o.refine_tol > 0 ? o.refine_tol : tol;
+    const int leaf = o.leaf_side > 0 ? o.leaf_side : 8;
+    const int m = o.layers > 0 ? o.layers : layers_for_tol(tol);
+    int ktype = kernel ? kernel->type : RSD_KERNEL_LAPLACE;
+    if (ktype != RSD_KERNEL_LAPLACE) throw Error(RSD_EINVAL, "only the Laplace kernel is built into this library version");
+    // host copies of the inputs
+    std::vector<double> pts(2 * n), ah, bh;
+    if (is_device_ptr(points)) RSD_HIP(hipMemcpy(pts.data(), points, 2 * n * sizeof(double), hipMemcpyDeviceToHost));
+    else std::memcpy(pts.data(), points, 2 * n * sizeof(double));
+    if (a) {
+        ah.resize(n);
+        if (is_device_ptr(a)) RSD_HIP(hipMemcpy(ah.data(), a, n * sizeof(double), hipMemcpyDeviceToHost));
+        else std::memcpy(ah.data(), a, n * sizeof(double));
+        for (double v : ah)
+            if (!std::isfinite(v)) throw Error(RSD_EINVAL, "non-finite value in a");
+    }
+    const double* bptr = kernel ? kernel->contrast_b : nullptr;
+    if (bptr) {
+        bh.resize(n);
+        if (is_device_ptr(bptr)) RSD_HIP(hipMemcpy(bh.data(), bptr, n * sizeof(double), hipMemcpyDeviceToHost));
+        else std::memcpy(bh.data(), bptr, n * sizeof(double));
+        for (double v : bh)
+            if (!std::isfinite(v) || v < 0) throw Error(RSD_EINVAL, "contrast must be finite and >= 0");
+    }
+    int64_t nx, ny;
+    double h, x0, y0;
+    std::vector<int64_t> perm;
+    std::string why;
+    if (!detect_grid(pts.data(), n, nx, ny, h, x0, y0, perm, why)) throw Error(RSD_ENOTGRID, why);
+    f->N = n; f->nx = nx; f->ny = ny; f->h = h;
+    try {
+        f->plan = make_plan(nx, ny, leaf, m);
+    } catch (const std::exception& e) {
+        throw Error(RSD_EINVAL, e.what());
+    }
+    Plan& P = f->plan;
+    const int nlev = (int)P.levels.size();
+    f->top = nlev - 1;
+    f->level_prec.assign(nlev, 0);
+    if (f->precision == RSD_PREC_FP32_REFINE)
+        for (int t = 0; t < f->top; ++t) f->level_prec[t] = 1;
+    auto t_start = std::chrono::steady_clock::now();
+    // ---- grid-ordered coefficients -----------------------------------------
+    std::vector<double> ag, sbg;
+    if (!ah.empty()) {
+        ag.resize(n);
+        for (int64_t g = 0; g < n; ++g) ag[g] = ah[perm[g]];
+    }
+    if (!bh.empty()) {
+        sbg.resize(n);
+        for (int64_t g = 0; g < n; ++g) sbg[g] = std::sqrt(bh[perm[g]]);
+    }
+    // ---- device tables ------------------------------------------------------
+    std::vector<int> lu, lv, srcc, srci, inv;
+    f->hlayouts.resize(P.layouts.size());
+    int64_t offT64 = 0, offT32 = 0;
+    for (size_t li = 0; li < P.layouts.size(); ++li) {
+        const Layout& L = P.layouts[li];
+        LayoutDev& D = f->hlayouts[li];
+        D.k = L.k; D.r = L.r;
+        D.off_uv = (int)lu.size();
+        lu.insert(lu.end(), L.u.begin(), L.u.end());
+        lv.insert(lv.end(), L.v.begin(), L.v.end());
+        if (L.src_c.empty()) { srcc.insert(srcc.end(), L.u.size(), 0); srci.insert(srci.end(), L.u.size(), 0); }
+        else { srcc.insert(srcc.end(), L.src_c.begin(), L.src_c.end()); srci.insert(srci.end(), L.src_i.begin(), L.src_i.end()); }
+        D.off_inv0 = D.off_inv1 = 0;
+        if (L.child[0] >= 0) {
+            const int k0 = P.layouts[L.child[0]].k, k1 = P.layouts[L.child[1]].k;
+            D.off_inv0 = (int)inv.size();
+            inv.resize(inv.size() + k0 + k1, -1);
+            D.off_inv1 = D.off_inv0 + k0;
+            for (int q = 0; q < L.k + L.r; ++q)
+                inv[(L.src_c[q] == 0 ? D.off_inv0 : D.off_inv1) + L.src_i[q]] = q;
+        }
+        D.idp = L.idp;
+        D.offT = -1;
+    }
+    // precision of each layout = precision of the level its boxes sit on
+    std::vector<int> layout_level(P.layouts.size(), -1);
+    for (auto& b : P.boxes) layout_level[b.layout] = b.level;
+    for (size_t li = 0; li < P.layouts.size(); ++li) {
+        const Layout& L = P.layouts[li];
+        if (L.idp < 0) continue;
+        const int prec = f->level_prec[layout_level[li]];
+        int64_t& o2 = prec ? offT32 : offT64;
+        f->hlayouts[li].offT = o2;
+        o2 += (int64_t)L.k * L.r;
+    }
+    // boxes: F offsets per precision arena, vector offsets per precision
+    int64_t offF64 = 0, offF32 = 0;
+    f->hboxes.resize(P.boxes.size());
+    std::vector<int64_t> offV(2, 0), offY(2, 0);
+    for (size_t i = 0; i < P.boxes.size(); ++i) {
+        const Box& b = P.boxes[i];
+        BoxDev& D = f->hboxes[i];
+        D.x0 = b.x0; D.y0 = b.y0; D.k = b.k; D.r = b.r; D.layout = b.layout;
+        D.parent = b.parent; D.pos = b.pos_in_parent; D.child0 = b.child[0]; D.child1 = b.child[1];
+        D.level = b.level;
+        const int prec = f->level_prec[b.level];
+        const int64_t mm = (int64_t)b.k + b.r;
+        int64_t& oF = prec ? offF32 : offF64;
+        D.offF = oF;
+        P.boxes[i].offF = oF;
+        oF += mm * mm;
+        D.offV = offV[prec];
+        offV[prec] += mm;
+        D.offY = offY[prec];
+        offY[prec] += b.r;
+    }
+    f->F64.alloc(std::max<int64_t>(offF64, 1) * sizeof(double));
+    f->F32.alloc(std::max<int64_t>(offF32, 1) * sizeof(float));
+    f->T64.alloc(std::max<int64_t>(offT64, 1) * sizeof(double));
+    f->T32.alloc(std::max<int64_t>(offT32, 1) * sizeof(float));
+    std::vector<int> lid;
+    for (int t = 0; t < nlev; ++t) {
+        f->level_id_off.push_back((int)lid.size());
+        lid.insert(lid.end(), P.levels[t].begin(), P.levels[t].end());
+    }
+    std::vector<int64_t> ident(n);
+    for (int64_t g = 0; g < n; ++g) ident[g] = g;
+    upload(f->d_boxes, f->hboxes, s);
+    upload(f->d_layouts, f->hlayouts, s);
+    upload(f->d_lu, lu, s);
+    upload(f->d_lv, lv, s);
+    upload(f->d_srcc, srcc, s);
+    upload(f->d_srci, srci, s);
+    upload(f->d_inv, inv, s);
+    upload(f->d_perm, perm, s);
+    upload(f->d_ident, ident, s);
+    upload(f->d_level_ids, lid, s);
+    if (!ag.empty()) upload(f->d_a, ag, s);
+    if (!sbg.empty()) upload(f->d_sb, sbg, s);
+    f->d_err.alloc(sizeof(int) * 4);
+    RSD_HIP(hipMemsetAsync(f->d_err.p, 0, sizeof(int) * 4, s));
+    // kernel description
+    KernelDesc& kd = f->kd;
+    kd.type = 0;
+    kd.has_b = sbg.empty() ? 0 : 1;
+    kd.h = h;
+    kd.logh = std::log(h);
+    kd.k = 0;
+    {
+        const double J = -0.5 * std::log(2.0) - 1.5 + M_PI / 4.0;
+        kd.sc_re = h * h * (std::log(h) + J) / (2.0 * M_PI);
+        kd.sc_im = 0;
+    }
+    kd.a = ag.empty() ? nullptr : f->d_a.as<double>();
+    kd.sb = sbg.empty() ? nullptr : f->d_sb.as<double>();
+    kd.ny = ny;
+    // ---- level plans ----------------------------------------------------------
+    std::vector<GemmBatch<double>*> b64;
+    std::vector<GemmBatch<float>*> b32;
+    int64_t sr64 = 0, sc64 = 0, sr32 = 0, sc32 = 0;
+    f->L64.clear();
+    f->L32.clear();
+    f->L64.reserve(nlev);
+    f->L32.reserve(nlev);
+    std::vector<int> exec_index(nlev);
+    for (int t = 0; t < nlev; ++t) {
+        if (f->level_prec[t]) { exec_index[t] = (int)f->L32.size(); f->L32.emplace_back(); }
+        else { exec_index[t] = (int)f->L64.size(); f->L64.emplace_back(); }
+    }
+    for (int t = 0; t < nlev; ++t) {
+        if (f->level_prec[t]) plan_level<float>(*f, f->L32[exec_index[t]], t, b32, sr32, sc32);
+        else plan_level<double>(*f, f->L64[exec_index[t]], t, b64, sr64, sc64);
+    }
+    {   // root: remaining block inverted in place
+        const Box& rb = P.boxes[P.root];
+        sr64 = std::max<int64_t>(sr64, (int64_t)GJ_NB * rb.k);
+        sc64 = std::max<int64_t>(sc64, (int64_t)rb.k * GJ_NB);
+    }
+    const int64_t sr_el = std::max(sr64, sr32), sc_el = std::max(sc64, sc32);
+    f->SR.alloc(std::max<int64_t>(sr_el, 1) * sizeof(double));
+    f->SC.alloc(std::max<int64_t>(sc_el, 1) * sizeof(double));
+    std::vector<GJDesc<double>> gj64;
+    std::vector<GJDesc<float>> gj32;
+    for (auto& L : f->L64) finish_gj<double>(*f, L, f->SR.as<double>(), f->SC.as<double>(), b64, gj64);
+    for (auto& L : f->L32) finish_gj<float>(*f, L, f->SR.as<float>(), f->SC.as<float>(), b32, gj32);
+    plan_top<double>(*f, f->L64[exec_index[f->top]], f->SR.as<double>(), f->SC.as<double>(), b64);
+    upload_batches<double>(f->gemm64, b64, s);
+    upload_batches<float>(f->gemm32, b32, s);
+    upload_gj<double>(f->gj64, f->L64, s);
+    upload_gj<float>(f->gj32, f->L32, s);
+    // ---- device work ---------------------------------------------------------
+    hipEvent_t e0, e1;
+    RSD_HIP(hipEventCreate(&e0));
+    RSD_HIP(hipEventCreate(&e1));
+    RSD_HIP(hipEventRecord(e0, s));
+    std::vector<int> p64, p32;
+    for (size_t li = 0; li < P.layouts.size(); ++li) {
+        if (P.layouts[li].idp < 0) continue;
+        (f->level_prec[layout_level[li]] ? p32 : p64).push_back(P.layouts[li].idp);
+    }
+    compute_T<double>(*f, p64, s);
+    compute_T<float>(*f, p32, s);
+    for (int t = 0; t < nlev; ++t) {
+        if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
+        else run_level<double>(*f, f->L64[exec_index[t]], s);
+    }
+    RSD_HIP(hipEventRecord(e1, s));
+    RSD_HIP(hipStreamSynchronize(s));
+    float ms = 0;
+    RSD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int err[4];
+    RSD_HIP(hipMemcpy(err, f->d_err.p, sizeof(err), hipMemcpyDeviceToHost));
+    if (err[0] != 0) {
+        const int bx = err[0] - 1;
+        throw Error(RSD_ESINGULAR, "singular pivot block in box " + std::to_string(bx) + " at level " +
+                                       std::to_string(P.boxes[bx].level));
+    }
+    // ---- statistics ---------------------------------------------------------------
+    rsd_factor_stats& st = f->stats;
+    st.n_points = n; st.nx = nx; st.ny = ny;
+    st.n_levels = nlev;
+    st.n_boxes = (int)P.boxes.size();
+    st.layers = m;
+    st.precision = f->precision;
+    st.factor_bytes = (int64_t)(f->F64.bytes + f->F32.bytes + f->T64.bytes + f->T32.bytes);
+    double fl = 0;
+    for (auto* b : b64) fl += b->flops;
+    for (auto* b : b32) fl += b->flops;
+    for (auto& I : P.idps) {
+        const double p = I.p, k = I.k, r = I.r;
+        fl += 2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r;
+    }
+    st.factor_flops = fl;
+    double sb = 0;
+    for (auto& b : P.boxes) {
+        const int es = f->level_prec[b.level] ? 4 : 8;
+        sb += (double)es * ((double)b.r * b.r + 2.0 * b.r * b.k);   // G, W twice
+        if (b.level == f->top) sb += (double)es * b.k * b.k;
+    }
+    st.solve_bytes = sb;
+    st.build_ms = ms;
+    (void)t_start;
+    if (!(f->flags & RSD_FLAG_KEEP_E)) { /* E blocks live inside F; nothing to free */ }
+    return f;
+}
+
+// ----------------------------------------------------------------------------
+// solve
+// ----------------------------------------------------------------------------
+template <typename T> static T* Vbase(SolvePlan& sp);
+template <> double* Vbase<double>(SolvePlan& sp) { return sp.V64.as<double>(); }
+template <> float* Vbase<float>(SolvePlan& sp) { return sp.V32.as<float>(); }
+template <typename T> static T* Ybase(SolvePlan& sp);
+template <> double* Ybase<double>(SolvePlan& sp) { return sp.Y64.as<double>(); }
+template <> float* Ybase<float>(SolvePlan& sp) { return sp.Y32.as<float>(); }
+
+template <typename T>
+static void plan_solve_level(Factor& f, SolvePlan& sp, SolveLevel<T>& SL, int t,
+                             std::vector<GemmBatch<T>*>& all) {
+    Plan& P = f.plan;
+    const int nr = sp.nrhs;
+    T* F = Fbase<T>(f);
+    T* Tb = Tbase<T>(f);
+    T* V = Vbase<T>(sp);
+    T* Y = Ybase<T>(sp);
+    for (int id : P.levels[t]) {
+        const BoxDev& b = f.hboxes[id];
+        const LayoutDev& LD = f.hlayouts[b.layout];
+        const int k = b.k, r = b.r, m = k + r;
+        T* Fb = F + b.offF;
+        T* G = Fb + k + (int64_t)k * m;
+        T* W = Fb + k;
+        T* Vs = V + b.offV * nr;
+        T* Vr = Vs + k;
+        T* Yb = Y + b.offY * nr;
+        const T* Tm = LD.offT >= 0 ? Tb + LD.offT : nullptr;
+        if (r > 0) {
+            if (Tm) SL.up1.add(gdesc<T>(r, nr, k, Tm, k, 1, Vs, m, 0, Vr, m, T(-1), T(1)));
+            SL.up2.add(gdesc<T>(r, nr, r, G, m, 0, Vr, m, 0, Yb, r, T(1), T(0)));
+            SL.up2.add(gdesc<T>(k, nr, r, W, m, 1, Vr, m, 0, Vs, m, T(-1), T(1)));
+            SL.dn1.add(gdesc<T>(r, nr, k, W, m, 0, Vs, m, 0, Yb, r, T(-1), T(1)));
+            if (Tm) SL.dn2.add(gdesc<T>(k, nr, r, Tm, k, 0, Yb, r, 0, Vs, m, T(-1), T(1)));
+        }
+        if (t == f.top) {
+            // phi = G_top g  (g in Vs, result via tmp)
+            T* tmp = reinterpret_cast<T*>(sp.tmp.p);
+            SL.top.add(gdesc<T>(k, nr, k, Fb, m, 0, Vs, m, 0, tmp, k, T(1), T(0)));
+        }
+    }
+    all.push_back(&SL.up1);
+    all.push_back(&SL.up2);
+    all.push_back(&SL.dn1);
+    all.push_back(&SL.dn2);
+    all.push_back(&SL.top);
+}
+
+static SolvePlan& get_solve_plan(Factor& f, int nrhs) {
+    auto it = f.solve_plans.find(nrhs);
+    if (it != f.solve_plans.end()) return *it->second;
+    auto sp = std::make_unique<SolvePlan>();
+    sp->nrhs = nrhs;
+    int64_t v[2] = {0, 0}, y[2] = {0, 0};
+    for (auto& b : f.hboxes) {
+        const int prec = f.level_prec[b.level];
+        v[prec] += b.k + b.r;
+        y[prec] += b.r;
+    }
+    sp->V64.alloc(std::max<int64_t>(v[0] * nrhs, 1) * sizeof(double));
+    sp->V32.alloc(std::max<int64_t>(v[1] * nrhs, 1) * sizeof(float));
+    sp->Y64.alloc(std::max<int64_t>(y[0] * nrhs, 1) * sizeof(double));
+    sp->Y32.alloc(std::max<int64_t>(y[1] * nrhs, 1) * sizeof(float));
+    const Box& rb = f.plan.boxes[f.plan.root];
+    sp->tmp.alloc(std::max<int64_t>((int64_t)rb.k * nrhs, 1) * sizeof(double));
+    sp->in.alloc(f.N * nrhs * sizeof(double) * (f.cplx ? 2 : 1));
+    sp->out.alloc(f.N * nrhs * sizeof(double) * (f.cplx ? 2 : 1));
+    const int nlev = (int)f.plan.levels.size();
+    sp->L32.resize(nlev);
+    sp->L64.resize(nlev);
+    std::vector<GemmBatch<double>*> b64;
+    std::vector<GemmBatch<float>*> b32;
+    for (int t = 0; t < nlev; ++t) {
+        if (f.level_prec[t]) plan_solve_level<float>(f, *sp, sp->L32[t], t, b32);
+        else plan_solve_level<double>(f, *sp, sp->L64[t], t, b64);
+    }
+    upload_batches<double>(sp->gemm64, b64, f.stream);
+    upload_batches<float>(sp->gemm32, b32, f.stream);
+    auto& ref = *sp;
+    f.solve_plans[nrhs] = std::move(sp);
+    return ref;
+}
+
+// x (grid or caller order per `perm`) = A^{-1} f, both device buffers with ld N
+static void apply_inverse(Factor& f, SolvePlan& sp, const double* fin, double* xout,
+                          const int64_t* perm) {
+    hipStream_t s = f.stream;
+    const int nr = sp.nrhs;
+    const BoxDev* B = f.d_boxes.as<BoxDev>();
+    const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
+    const int* lu = f.d_lu.as<int>();
+    const int* lv = f.d_lv.as<int>();
+    const int* inv = f.d_inv.as<int>();
+    const int nlev = (int)f.plan.levels.size();
+    auto nb = [&](int t) { return (int)f.plan.levels[t].size(); };
+    auto maxm = [&](int t) { int m = 0; for (int id : f.plan.levels[t]) m = std::max(m, f.hboxes[id].k + f.hboxes[id].r); return m; };
+    auto maxk = [&](int t) { int m = 0; for (int id : f.plan.levels[t]) m = std::max(m, f.hboxes[id].k); return m; };
+    // leaves
+    if (f.level_prec[0]) launch_gather_leaf<double, float>(sp.V32.as<float>(), fin, f.N, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
+    else launch_gather_leaf<double, double>(sp.V64.as<double>(), fin, f.N, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
+    for (int t = 0; t < nlev; ++t) {
+        const int p = f.level_prec[t];
+        if (p) { sp.L32[t].up1.run(s); sp.L32[t].up2.run(s); }
+        else { sp.L64[t].up1.run(s); sp.L64[t].up2.run(s); }
+        if (t < f.top) {
+            const int pp = f.level_prec[t + 1];
+            if (p && pp) launch_scatter_up<float, float>(sp.V32.as<float>(), sp.V32.as<float>(), nr, B, f.ids(t), nb(t), LD, inv, maxk(t), s);
+            else if (p && !pp) launch_scatter_up<float, double>(sp.V64.as<double>(), sp.V32.as<float>(), nr, B, f.ids(t), nb(t), LD, inv, maxk(t), s);
+            else launch_scatter_up<double, double>(sp.V64.as<double>(), sp.V64.as<double>(), nr, B, f.ids(t), nb(t), LD, inv, maxk(t), s);
+        }
+    }
+    // top: phi = G_top g -> tmp, copy back into the root's skeleton part
+    {
+        sp.L64[f.top].top.run(s);
+        const BoxDev& rb = f.hboxes[f.plan.root];
+        const int m = rb.k + rb.r;
+        double* Vs = sp.V64.as<double>() + rb.offV * nr;
+        RSD_HIP(hipMemcpy2DAsync(Vs, m * sizeof(double), sp.tmp.p, rb.k * sizeof(double),
+                                 rb.k * sizeof(double), nr, hipMemcpyDeviceToDevice, s));
+    }
+    for (int t = f.top; t >= 0; --t) {
+        const int p = f.level_prec[t];
+        if (t < f.top) {
+            const int pp = f.level_prec[t + 1];
+            if (p && pp) launch_gather_down<float, float>(sp.V32.as<float>(), sp.V32.as<float>(), sp.Y32.as<float>(), nr, B, f.ids(t), nb(t), LD, inv, maxk(t), s);
+            else if (p && !pp) launch_gather_down<double, float>(sp.V32.as<float>(), sp.V64.as<double>(), sp.Y64.as<double>(), nr, B, f.ids(t), nb(t), LD, inv, maxk(t), s);
+            else launch_gather_down<double, double>(sp.V64.as<double>(), sp.V64.as<double>(), sp.Y64.as<double>(), nr, B, f.ids(t), nb(t), LD, inv, maxk(t), s);
+        }
+        if (p) { sp.L32[t].dn1.run(s); sp.L32[t].dn2.run(s); }
+        else { sp.L64[t].dn1.run(s); sp.L64[t].dn2.run(s); }
+    }
+    if (f.level_prec[0]) launch_scatter_leaf<float, double>(xout, f.N, sp.V32.as<float>(), sp.Y32.as<float>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
+    else launch_scatter_leaf<double, double>(xout, f.N, sp.V64.as<double>(), sp.Y64.as<double>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
+}
+
+static void ensure_table(Factor& f) {
+    if (f.d_table.p) return;
+    f.d_table.alloc(f.N * sizeof(double));
+    launch_matvec_table(f.d_table.as<double>(), f.nx, f.ny, f.kd, f.stream);
+}
+
+// y = A x, grid-ordered device vectors
+static void matvec_grid(Factor& f, const double* x, double* y, int nrhs) {
+    ensure_table(f);
+    launch_matvec(y, x, nrhs, f.d_table.as<double>(), f.nx, f.ny, f.kd, 0, f.stream);
+}
+
+static void check_finite_dev(Factor& f, const double* x, int64_t n) {
+    DevBuf flag;
+    flag.alloc(sizeof(int));
+    RSD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), f.stream));
+    launch_check_finite(x, n, flag.as<int>(), f.stream);
+    int h = 0;
+    RSD_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, f.stream));
+    RSD_HIP(hipStreamSynchronize(f.stream));
+    if (h) throw Error(RSD_EINVAL, "non-finite value in the right-hand side");
+}
+
+static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, rsd_solve_info* info) {
+    if (nrhs < 0) throw Error(RSD_EINVAL, "nrhs < 0");
+    if (info) { info->refine_iters = 0; info->rel_residual = -1; }
+    if (nrhs == 0) return RSD_OK;
+    if (!rhs || !x) throw Error(RSD_EINVAL, "null rhs or x");
+    if (nrhs > 4096) throw Error(RSD_EINVAL, "nrhs > 4096");
+    RSD_HIP(hipSetDevice(f.device));
+    hipStream_t s = f.stream;
+    SolvePlan& sp = get_solve_plan(f, (int)nrhs);
+    const int64_t tot = f.N * nrhs;
+    const bool rdev = is_device_ptr(rhs), xdev = is_device_ptr(x);
+    const double* fin = rhs;
+    if (!rdev) {
+        RSD_HIP(hipMemcpyAsync(sp.in.p, rhs, tot * sizeof(double), hipMemcpyHostToDevice, s));
+        fin = sp.in.as<double>();
+    }
+    check_finite_dev(f, fin, tot);
+    double* xo = xdev ? x : sp.out.as<double>();
+    rsd_status status = RSD_OK;
+    if (f.max_refine <= 0) {
+        apply_inverse(f, sp, fin, xo, f.d_perm.as<int64_t>());
+    } else {
+        // refinement on grid-ordered copies: fg, xg, rg, dg, ax
+        DevBuf work;
+        work.alloc(5 * tot * sizeof(double));
+        double* fg = work.as<double>();
+        double* xg = fg + tot;
+        double* rg = xg + tot;
+        double* dg = rg + tot;
+        double* ax = dg + tot;
+        launch_permute(fg, fin, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 1, s);
+        apply_inverse(f, sp, fg, xg, f.d_ident.as<int64_t>());
+        DevBuf nb;
+        nb.alloc(2 * nrhs * sizeof(double));
+        launch_col_norms2(nb.as<double>(), fg, f.N, (int)nrhs, s);
+        std::vector<double> fn(nrhs), rn(nrhs);
+        RSD_HIP(hipMemcpyAsync(fn.data(), nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        int it = 0;
+        double worst = 0;
+        for (;;) {
+            matvec_grid(f, xg, ax, (int)nrhs);
+            launch_axpy_resid(rg, fg, ax, tot, s);
+            launch_col_norms2(nb.as<double>() + nrhs, rg, f.N, (int)nrhs, s);
+            RSD_HIP(hipMemcpyAsync(rn.data(), nb.as<double>() + nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+            RSD_HIP(hipStreamSynchronize(s));
+            worst = 0;
+            for (int c = 0; c < nrhs; ++c) {
+                const double rel = fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]);
+                worst = std::max(worst, rel);
+            }
+            if (worst <= f.refine_tol || it >= f.max_refine) break;
+            apply_inverse(f, sp, rg, dg, f.d_ident.as<int64_t>());
+            launch_add(xg, dg, tot, s);
+            ++it;
+        }
+        launch_permute(xo, xg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 0, s);
+        if (info) { info->refine_iters = it; info->rel_residual = worst; }
+        if (worst > f.refine_tol) status = RSD_ENOCONV;
+        RSD_HIP(hipStreamSynchronize(s));
+    }
+    if (!xdev) RSD_HIP(hipMemcpyAsync(x, xo, tot * sizeof(double), hipMemcpyDeviceToHost, s));
+    RSD_HIP(hipStreamSynchronize(s));
+    if (status == RSD_ENOCONV)
+        throw Error(RSD_ENOCONV, "iterative refinement did not reach the tolerance");
+    return status;
+}
+
+static void matvec(Factor& f, const double* xin, int64_t nrhs, double* y) {
+    if (nrhs < 0 || !xin || !y) throw Error(RSD_EINVAL, "bad matvec arguments");
+    if (nrhs == 0) return;
+    RSD_HIP(hipSetDevice(f.device));
+    hipStream_t s = f.stream;
+    const int64_t tot = f.N * nrhs;
+    DevBuf buf;
+    buf.alloc(3 * tot * sizeof(double));
+    double* xi = buf.as<double>();
+    double* xg = xi + tot;
+    double* yg = xg + tot;
+    if (is_device_ptr(xin)) RSD_HIP(hipMemcpyAsync(xi, xin, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else RSD_HIP(hipMemcpyAsync(xi, xin, tot * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_permute(xg, xi, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 1, s);
+    matvec_grid(f, xg, yg, (int)nrhs);
+    launch_permute(xi, yg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 0, s);
+    if (is_device_ptr(y)) RSD_HIP(hipMemcpyAsync(y, xi, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else RSD_HIP(hipMemcpyAsync(y, xi, tot * sizeof(double), hipMemcpyDeviceToHost, s));
+    RSD_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace rsd
+
+// ============================================================================
+// C interface
+// ============================================================================
+struct rsd_factor {
+    std::unique_ptr<rsd::Factor> impl;
+};
+struct rsd_plan {
+    rsd::Plan plan;
+};
+
+using rsd::g_last_error;
+
+template <typename Fn>
+static rsd_status guarded(Fn&& fn) {
+    try {
+        g_last_error.clear();
+        return fn();
+    } catch (const rsd::Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const rsd::HipError& e) {
+        g_last_error = e.what();
+        return RSD_EDEVICE;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return RSD_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return RSD_EINVAL;
+    }
+}
+
+extern "C" {
+
+rsd_status rsd_build_factor(const double* points, int64_t n_points, const rsd_kernel* kernel,
+                            const double* a, double tol, const rsd_options* opt, rsd_factor** out) {
+    if (out) *out = nullptr;
+    return guarded([&]() {
+        if (!out) throw rsd::Error(RSD_EINVAL, "out is null");
+        auto f = rsd::build(points, n_points, kernel, a, tol, opt);
+        *out = new rsd_factor{std::move(f)};
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_solve(rsd_factor* f, const double* rhs, int64_t nrhs, double* x, rsd_solve_info* info) {
+    return guarded([&]() {
+        if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
+        return rsd::solve(*f->impl, rhs, nrhs, x, info);
+    });
+}
+
+rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
+    return guarded([&]() {
+        if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
+        rsd::matvec(*f->impl, x, nrhs, y);
+        return RSD_OK;
+    });
+}
+
+void rsd_free(rsd_factor* f) { delete f; }
+
+const char* rsd_last_error(void) { return g_last_error.c_str(); }
+
+rsd_status rsd_factor_get_stats(const rsd_factor* f, rsd_factor_stats* out) {
+    return guarded([&]() {
+        if (!f || !out) throw rsd::Error(RSD_EINVAL, "null argument");
+        *out = f->impl->stats;
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* out) {
+    return guarded([&]() {
+        if (!f || !out) throw rsd::Error(RSD_EINVAL, "null argument");
+        const auto& P = f->impl->plan;
+        if (box < 0 || box >= (int)P.boxes.size()) throw rsd::Error(RSD_EINVAL, "box out of range");
+        const auto& b = P.boxes[box];
+        *out = {b.level, b.x0, b.y0, b.ax, b.ay, b.k, b.r, b.parent};
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_factor_get_block(const rsd_factor* fc, int32_t box, int32_t which, void* dst) {
+    return guarded([&]() {
+        if (!fc || !dst) throw rsd::Error(RSD_EINVAL, "null argument");
+        rsd::Factor& f = *fc->impl;
+        const auto& P = f.plan;
+        if (box < 0 || box >= (int)P.boxes.size()) throw rsd::Error(RSD_EINVAL, "box out of range");
+        const auto& b = P.boxes[box];
+        const auto& LD = f.hlayouts[b.layout];
+        const int prec = f.level_prec[b.level];
+        RSD_HIP(hipStreamSynchronize(f.stream));
+        if (which == 2) {
+            auto pts = rsd::box_points(P, box);
+            std::memcpy(dst, pts.data(), pts.size() * sizeof(int64_t));
+            return RSD_OK;
+        }
+        int64_t rows, cols, ld;
+        const void* src;
+        size_t es = prec ? sizeof(float) : sizeof(double);
+        if (which == 0) {
+            if (LD.offT < 0) throw rsd::Error(RSD_EINVAL, "this box has no interpolation matrix");
+            rows = b.k; cols = b.r; ld = b.k;
+            src = prec ? (const void*)(f.T32.as<float>() + LD.offT) : (const void*)(f.T64.as<double>() + LD.offT);
+        } else if (which == 1) {
+            if (!(f.flags & RSD_FLAG_KEEP_E)) throw rsd::Error(RSD_EINVAL, "build with RSD_FLAG_KEEP_E to read E blocks");
+            if (box == P.root) throw rsd::Error(RSD_EINVAL, "the root has no E block");
+            rows = b.k; cols = b.k; ld = b.k + b.r;
+            src = prec ? (const void*)(f.F32.as<float>() + b.offF) : (const void*)(f.F64.as<double>() + b.offF);
+        } else {
+            throw rsd::Error(RSD_EINVAL, "unknown block kind");
+        }
+        std::vector<unsigned char> tmp(es * ld * cols);
+        RSD_HIP(hipMemcpy(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost));
+        double* d = static_cast<double*>(dst);
+        for (int64_t j = 0; j < cols; ++j)
+            for (int64_t i = 0; i < rows; ++i) {
+                const size_t e = (size_t)(i + j * ld);
+                d[i + j * rows] = prec ? (double)reinterpret_cast<float*>(tmp.data())[e]
+                                       : reinterpret_cast<double*>(tmp.data())[e];
+            }
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_plan_create(int64_t nx, int64_t ny, int32_t leaf_side, int32_t layers, rsd_plan** out) {
+    if (out) *out = nullptr;
+    return guarded([&]() {
+        if (!out) throw rsd::Error(RSD_EINVAL, "out is null");
+        auto p = std::make_unique<rsd_plan>();
+        p->plan = rsd::make_plan(nx, ny, leaf_side > 0 ? leaf_side : 8, layers > 0 ? layers : 2);
+        *out = p.release();
+        return RSD_OK;
+    });
+}
+
+int32_t rsd_plan_n_boxes(const rsd_plan* p) { return p ? (int32_t)p->plan.boxes.size() : 0; }
+int32_t rsd_plan_n_levels(const rsd_plan* p) { return p ? (int32_t)p->plan.levels.size() : 0; }
+
+rsd_status rsd_plan_box_info(const rsd_plan* p, int32_t box, rsd_box_info* out) {
+    return guarded([&]() {
+        if (!p || !out) throw rsd::Error(RSD_EINVAL, "null argument");
+        if (box < 0 || box >= (int)p->plan.boxes.size()) throw rsd::Error(RSD_EINVAL, "box out of range");
+        const auto& b = p->plan.boxes[box];
+        *out = {b.level, b.x0, b.y0, b.ax, b.ay, b.k, b.r, b.parent};
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_plan_box_points(const rsd_plan* p, int32_t box, int64_t* dst) {
+    return guarded([&]() {
+        if (!p || !dst) throw rsd::Error(RSD_EINVAL, "null argument");
+        if (box < 0 || box >= (int)p->plan.boxes.size()) throw rsd::Error(RSD_EINVAL, "box out of range");
+        auto v = rsd::box_points(p->plan, box);
+        std::memcpy(dst, v.data(), v.size() * sizeof(int64_t));
+        return RSD_OK;
+    });
+}
+
+void rsd_plan_free(rsd_plan* p) { delete p; }
+
+rsd_status rsd_detect_grid(const double* points_host, int64_t n_points, int64_t* nx, int64_t* ny,
+                           double* h, int64_t* perm) {
+    return guarded([&]() {
+        if (!points_host || !nx || !ny || !h || !perm) throw rsd::Error(RSD_EINVAL, "null argument");
+        std::vector<int64_t> pv;
+        std::string why;
+        double x0, y0;
+        if (!rsd::detect_grid(points_host, n_points, *nx, *ny, *h, x0, y0, pv, why))
+            throw rsd::Error(RSD_ENOTGRID, why);
+        std::memcpy(perm, pv.data(), pv.size() * sizeof(int64_t));
+        return RSD_OK;
+    });
+}
+
+}  // extern "C"

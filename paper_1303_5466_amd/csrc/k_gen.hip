@@ -1,0 +1,235 @@
+// Kernel-matrix generation from grid coordinates (Sec. 5, general
+// formulation): leaf diagonal blocks D_i, the parent blocks
+// F_i = D_i + diag(E_c1, E_c2) of Algorithm 1 (sibling interactions
+// generated on the fly, children's E_c gathered), and the proxy matrices
+// [K(Z, X^sk) | K(Z, X^rs)] of the interpolation problem (Sec. 3.1).
+//
+// All coordinates are integer grid offsets relative to a box origin; the
+// kernel depends on the distance only, so K(h |(du, dv)|) is evaluated from
+// du^2 + dv^2 directly.  Writes are column-major and coalesced (consecutive
+// threads take consecutive rows).
+#include "common.hpp"
+
+namespace rsd {
+
+namespace {
+
+constexpr double INV_2PI = 0.15915494309189533576888376337251;
+
+// K(h * sqrt(rho2)) for rho2 > 0 (Laplace: (1/2pi) log r)
+__device__ inline double kernel_val(const KernelDesc& kd, double rho2) {
+    return INV_2PI * (kd.logh + 0.5 * log(rho2));
+}
+__device__ inline float kernel_val_f(const KernelDesc& kd, float rho2) {
+    return (float)INV_2PI * ((float)kd.logh + 0.5f * logf(rho2));
+}
+
+template <typename T> struct KV;
+template <> struct KV<double> {
+    __device__ static double off(const KernelDesc& kd, int du, int dv) {
+        return kd.h * kd.h * kernel_val(kd, (double)(du * du + dv * dv));
+    }
+    __device__ static double proxy(const KernelDesc& kd, int du, int dv) {
+        return kernel_val(kd, (double)(du * du + dv * dv));
+    }
+};
+template <> struct KV<float> {
+    __device__ static float off(const KernelDesc& kd, int du, int dv) {
+        return (float)(kd.h * kd.h) * kernel_val_f(kd, (float)(du * du + dv * dv));
+    }
+    __device__ static float proxy(const KernelDesc& kd, int du, int dv) {
+        return kernel_val_f(kd, (float)(du * du + dv * dv));
+    }
+};
+
+template <typename T>
+__device__ inline T diag_val(const KernelDesc& kd, int64_t g) {
+    if (kd.has_b) return T(1.0 + kd.sb[g] * kd.sb[g] * kd.sc_re);
+    return T((kd.a ? kd.a[g] : 1.0) + kd.sc_re);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) leaf_F_kernel(T* __restrict__ F, const BoxDev* __restrict__ boxes,
+                                                      const int* __restrict__ box_ids,
+                                                      const LayoutDev* __restrict__ layouts,
+                                                      const int* __restrict__ lu,
+                                                      const int* __restrict__ lv, KernelDesc kd) {
+    const BoxDev b = boxes[box_ids[blockIdx.y]];
+    const LayoutDev L = layouts[b.layout];
+    const int m = L.k + L.r;
+    T* Fb = F + b.offF;
+    const int* U = lu + L.off_uv;
+    const int* V = lv + L.off_uv;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)m * m; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        T val;
+        if (i == j) {
+            const int64_t g = (int64_t)(b.x0 + U[i]) * kd.ny + (b.y0 + V[i]);
+            val = diag_val<T>(kd, g);
+        } else {
+            val = KV<T>::off(kd, U[i] - U[j], V[i] - V[j]);
+            if (kd.has_b) {
+                const int64_t gi = (int64_t)(b.x0 + U[i]) * kd.ny + (b.y0 + V[i]);
+                const int64_t gj = (int64_t)(b.x0 + U[j]) * kd.ny + (b.y0 + V[j]);
+                val = val * T(kd.sb[gi] * kd.sb[gj]);
+            }
+        }
+        Fb[e] = val;
+    }
+}
+
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(256) assemble_kernel(
+    TD* __restrict__ F, const TS* __restrict__ Fc, const BoxDev* __restrict__ boxes,
+    const int* __restrict__ box_ids, const LayoutDev* __restrict__ layouts,
+    const int* __restrict__ lu, const int* __restrict__ lv, const int* __restrict__ src_c,
+    const int* __restrict__ src_i, KernelDesc kd) {
+    const BoxDev b = boxes[box_ids[blockIdx.y]];
+    const LayoutDev L = layouts[b.layout];
+    const int m = L.k + L.r;
+    const BoxDev c0 = boxes[b.child0], c1 = boxes[b.child1];
+    const int m0 = c0.k + c0.r, m1 = c1.k + c1.r;
+    TD* Fb = F + b.offF;
+    const int* U = lu + L.off_uv;
+    const int* V = lv + L.off_uv;
+    const int* SC = src_c + L.off_uv;
+    const int* SI = src_i + L.off_uv;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)m * m; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        const int ci = SC[i], cj = SC[j];
+        TD val;
+        if (ci == cj) {
+            const BoxDev& c = ci ? c1 : c0;
+            const int mc = ci ? m1 : m0;
+            val = (TD)Fc[c.offF + SI[i] + (int64_t)SI[j] * mc];
+        } else {
+            val = KV<TD>::off(kd, U[i] - U[j], V[i] - V[j]);
+            if (kd.has_b) {
+                const int64_t gi = (int64_t)(b.x0 + U[i]) * kd.ny + (b.y0 + V[i]);
+                const int64_t gj = (int64_t)(b.x0 + U[j]) * kd.ny + (b.y0 + V[j]);
+                val = val * TD(kd.sb[gi] * kd.sb[gj]);
+            }
+        }
+        Fb[e] = val;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) proxy_kernel(
+    T* __restrict__ A, const int64_t* __restrict__ offA, const int* __restrict__ p_of,
+    const int* __restrict__ k_of, const int* __restrict__ r_of, const int* __restrict__ zoff,
+    const int* __restrict__ zu, const int* __restrict__ zv, const int* __restrict__ xoff,
+    const int* __restrict__ lu, const int* __restrict__ lv, KernelDesc kd) {
+    const int pb = blockIdx.y;
+    const int p = p_of[pb], n = k_of[pb] + r_of[pb];
+    T* Ab = A + offA[pb];
+    const int* ZU = zu + zoff[pb];
+    const int* ZV = zv + zoff[pb];
+    const int* XU = lu + xoff[pb];
+    const int* XV = lv + xoff[pb];
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)p * n; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e % p), j = (int)(e / p);
+        Ab[e] = KV<T>::proxy(kd, ZU[i] - XU[j], ZV[i] - XV[j]);
+    }
+}
+
+// F'_rs = (F'_sr)^T for every box of a level (32 x 32 tiles through LDS)
+template <typename T>
+__global__ void __launch_bounds__(256) transpose_kernel(T* __restrict__ F, const BoxDev* __restrict__ boxes,
+                                                         const int* __restrict__ ids) {
+    const BoxDev b = boxes[ids[blockIdx.y]];
+    const int k = b.k, r = b.r, m = k + r;
+    __shared__ T tile[32][33];
+    const int tiles_k = (k + 31) / 32, tiles_r = (r + 31) / 32;
+    T* Fb = F + b.offF;
+    for (int tt = blockIdx.x; tt < tiles_k * tiles_r; tt += gridDim.x) {
+        const int tk = tt % tiles_k, tr = tt / tiles_k;
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int i = e % 32, j = e / 32;
+            const int gi = tk * 32 + i, gj = tr * 32 + j;
+            tile[j][i] = (gi < k && gj < r) ? Fb[gi + (int64_t)(k + gj) * m] : T(0);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int j = e % 32, i = e / 32;
+            const int gi = tk * 32 + i, gj = tr * 32 + j;
+            if (gi < k && gj < r) Fb[(k + gj) + (int64_t)gi * m] = tile[j][i];
+        }
+    }
+}
+
+inline int chunks_for(int64_t elems) {
+    int64_t c = (elems + 256 * 8 - 1) / (256 * 8);
+    if (c < 1) c = 1;
+    if (c > 4096) c = 4096;
+    return (int)c;
+}
+
+}  // namespace
+
+template <typename T>
+void launch_leaf_F(T* F, const BoxDev* boxes, const int* box_ids, int n_boxes,
+                   const LayoutDev* layouts, const int* lu, const int* lv, KernelDesc kd,
+                   int max_m, hipStream_t s) {
+    if (n_boxes <= 0) return;
+    dim3 grid(chunks_for((int64_t)max_m * max_m), n_boxes);
+    hipLaunchKernelGGL(leaf_F_kernel<T>, grid, dim3(256), 0, s, F, boxes, box_ids, layouts, lu, lv, kd);
+}
+
+template <typename TS, typename TD>
+void launch_assemble_F(TD* F, const TS* Fchild, const BoxDev* boxes, const int* box_ids,
+                       int n_boxes, const LayoutDev* layouts, const int* lu, const int* lv,
+                       const int* src_c, const int* src_i, KernelDesc kd, int max_m,
+                       hipStream_t s) {
+    if (n_boxes <= 0) return;
+    dim3 grid(chunks_for((int64_t)max_m * max_m), n_boxes);
+    hipLaunchKernelGGL((assemble_kernel<TS, TD>), grid, dim3(256), 0, s, F, Fchild, boxes, box_ids,
+                       layouts, lu, lv, src_c, src_i, kd);
+}
+
+template <typename T>
+void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* k_of,
+                         const int* r_of, const int* zoff, const int* zu, const int* zv,
+                         const int* xoff, const int* lu, const int* lv, int n_problems,
+                         int max_pn, KernelDesc kd, hipStream_t s) {
+    if (n_problems <= 0) return;
+    dim3 grid(chunks_for(max_pn), n_problems);
+    hipLaunchKernelGGL(proxy_kernel<T>, grid, dim3(256), 0, s, A, offA, p_of, k_of, r_of, zoff, zu,
+                       zv, xoff, lu, lv, kd);
+}
+
+template <typename T>
+void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes, int max_k,
+                         int max_r, hipStream_t s) {
+    if (n_boxes <= 0 || max_k <= 0 || max_r <= 0) return;
+    int chunks = ((max_k + 31) / 32) * ((max_r + 31) / 32);
+    if (chunks > 1024) chunks = 1024;
+    hipLaunchKernelGGL(transpose_kernel<T>, dim3(chunks, n_boxes), dim3(256), 0, s, F, boxes, ids);
+}
+template void launch_transpose_sr<double>(double*, const BoxDev*, const int*, int, int, int, hipStream_t);
+template void launch_transpose_sr<float>(float*, const BoxDev*, const int*, int, int, int, hipStream_t);
+
+template void launch_leaf_F<double>(double*, const BoxDev*, const int*, int, const LayoutDev*,
+                                    const int*, const int*, KernelDesc, int, hipStream_t);
+template void launch_leaf_F<float>(float*, const BoxDev*, const int*, int, const LayoutDev*,
+                                   const int*, const int*, KernelDesc, int, hipStream_t);
+template void launch_assemble_F<double, double>(double*, const double*, const BoxDev*, const int*,
+                                                int, const LayoutDev*, const int*, const int*,
+                                                const int*, const int*, KernelDesc, int, hipStream_t);
+template void launch_assemble_F<float, float>(float*, const float*, const BoxDev*, const int*, int,
+                                              const LayoutDev*, const int*, const int*, const int*,
+                                              const int*, KernelDesc, int, hipStream_t);
+template void launch_assemble_F<float, double>(double*, const float*, const BoxDev*, const int*, int,
+                                               const LayoutDev*, const int*, const int*, const int*,
+                                               const int*, KernelDesc, int, hipStream_t);
+template void launch_proxy_matrix<double>(double*, const int64_t*, const int*, const int*,
+                                          const int*, const int*, const int*, const int*,
+                                          const int*, const int*, const int*, int, int, KernelDesc,
+                                          hipStream_t);
+template void launch_proxy_matrix<float>(float*, const int64_t*, const int*, const int*,
+                                         const int*, const int*, const int*, const int*,
+                                         const int*, const int*, const int*, int, int, KernelDesc,
+                                         hipStream_t);
+
+}  // namespace rsd

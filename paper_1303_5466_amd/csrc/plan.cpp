@@ -1,0 +1,302 @@
+// Host planning: tree (Sec. 2.2), skeleton sets (Sec. 3.1), proxy rings.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <stdexcept>
+
+namespace rsd {
+
+int layers_for_tol(double tol) {
+    if (tol >= 1e-6) return 1;
+    if (tol >= 1e-11) return 2;
+    return 3;
+}
+
+static int n_splits(int64_t side, int leaf) {
+    int d = 0;
+    while ((side + (int64_t(1) << d) - 1) / (int64_t(1) << d) > leaf) ++d;
+    return d;
+}
+
+namespace {
+
+struct Pt { int u, v; };
+
+// depth of a point below the boundary of an a x b box
+inline int depth_in(int u, int v, int a, int b) {
+    return std::min(std::min(u, a - 1 - u), std::min(v, b - 1 - v));
+}
+
+// Skeleton points ordered cyclically around the box (angle about the centre,
+// then depth, then coordinates); residual points along the interface (the
+// coordinate along the cut first) or row-major for a leaf's interior.
+void order_points(std::vector<int>& sk, std::vector<int>& rs, const std::vector<Pt>& pts,
+                  int a, int b, int split) {
+    const double cu = 0.5 * (a - 1), cv = 0.5 * (b - 1);
+    std::vector<double> ang(pts.size());
+    for (size_t q = 0; q < pts.size(); ++q) ang[q] = std::atan2(pts[q].v - cv, pts[q].u - cu);
+    std::sort(sk.begin(), sk.end(), [&](int x, int y) {
+        if (ang[x] != ang[y]) return ang[x] < ang[y];
+        int dx = depth_in(pts[x].u, pts[x].v, a, b), dy = depth_in(pts[y].u, pts[y].v, a, b);
+        if (dx != dy) return dx < dy;
+        if (pts[x].u != pts[y].u) return pts[x].u < pts[y].u;
+        return pts[x].v < pts[y].v;
+    });
+    std::sort(rs.begin(), rs.end(), [&](int x, int y) {
+        int ax_ = pts[x].u, bx = pts[x].v, ay_ = pts[y].u, by = pts[y].v;
+        if (split == 0) { std::swap(ax_, bx); std::swap(ay_, by); }  // along v first
+        if (ax_ != ay_) return ax_ < ay_;
+        return bx < by;
+    });
+}
+
+struct Builder {
+    Plan& P;
+    std::map<std::tuple<int, int, int, int, int, int>, int> layout_of;
+    explicit Builder(Plan& p) : P(p) {}
+
+    int leaf_layout(int a, int b, bool root) {
+        auto key = std::make_tuple(a, b, -1, -1, -1, root ? 1 : 0);
+        auto it = layout_of.find(key);
+        if (it != layout_of.end()) return it->second;
+        Layout L;
+        L.ax = a; L.ay = b; L.split = -1; L.root = root;
+        std::vector<Pt> pts;
+        for (int u = 0; u < a; ++u)
+            for (int v = 0; v < b; ++v) pts.push_back({u, v});
+        std::vector<int> sk, rs;
+        for (int q = 0; q < (int)pts.size(); ++q)
+            (root || depth_in(pts[q].u, pts[q].v, a, b) < P.m ? sk : rs).push_back(q);
+        order_points(sk, rs, pts, a, b, -1);
+        finish(L, pts, sk, rs, {}, {});
+        int id = (int)P.layouts.size();
+        P.layouts.push_back(std::move(L));
+        layout_of[key] = id;
+        return id;
+    }
+
+    int parent_layout(int a, int b, int split, int l1, int l2, int a1, int b1, bool root) {
+        auto key = std::make_tuple(a, b, split, l1, l2, root ? 1 : 0);
+        auto it = layout_of.find(key);
+        if (it != layout_of.end()) return it->second;
+        Layout L;
+        L.ax = a; L.ay = b; L.split = split; L.root = root;
+        L.child[0] = l1; L.child[1] = l2;
+        L.child_ax1 = split == 0 ? a1 : 0;
+        L.child_ay1 = split == 1 ? b1 : 0;
+        std::vector<Pt> pts;
+        std::vector<int> srcc, srci;
+        for (int c = 0; c < 2; ++c) {
+            const Layout& C = P.layouts[c == 0 ? l1 : l2];
+            int du = c == 0 ? 0 : L.child_ax1, dv = c == 0 ? 0 : L.child_ay1;
+            for (int i = 0; i < C.k; ++i) {
+                pts.push_back({C.u[i] + du, C.v[i] + dv});
+                srcc.push_back(c);
+                srci.push_back(i);
+            }
+        }
+        std::vector<int> sk, rs;
+        if (root) {
+            // block elimination at the top: residual = first child, skeleton = second
+            for (int q = 0; q < (int)pts.size(); ++q) (srcc[q] == 0 ? rs : sk).push_back(q);
+        } else {
+            for (int q = 0; q < (int)pts.size(); ++q)
+                (depth_in(pts[q].u, pts[q].v, a, b) < P.m ? sk : rs).push_back(q);
+            order_points(sk, rs, pts, a, b, split);
+        }
+        finish(L, pts, sk, rs, srcc, srci);
+        int id = (int)P.layouts.size();
+        P.layouts.push_back(std::move(L));
+        layout_of[key] = id;
+        return id;
+    }
+
+    void finish(Layout& L, const std::vector<Pt>& pts, const std::vector<int>& sk,
+                const std::vector<int>& rs, const std::vector<int>& srcc,
+                const std::vector<int>& srci) {
+        L.k = (int)sk.size();
+        L.r = (int)rs.size();
+        for (int pass = 0; pass < 2; ++pass)
+            for (int q : (pass == 0 ? sk : rs)) {
+                L.u.push_back(pts[q].u);
+                L.v.push_back(pts[q].v);
+                if (!srcc.empty()) {
+                    L.src_c.push_back(srcc[q]);
+                    L.src_i.push_back(srci[q]);
+                }
+            }
+    }
+
+    void add_idp(int lid) {
+        Layout& L = P.layouts[lid];
+        if (L.root || L.r == 0 || L.idp >= 0) return;
+        IDProblem I;
+        I.layout = lid;
+        I.k = L.k;
+        I.r = L.r;
+        for (int zu = -P.m; zu < L.ax + P.m; ++zu)
+            for (int zv = -P.m; zv < L.ay + P.m; ++zv) {
+                bool inside = zu >= 0 && zu < L.ax && zv >= 0 && zv < L.ay;
+                if (inside) continue;
+                I.zu.push_back(zu);
+                I.zv.push_back(zv);
+            }
+        I.p = (int)I.zu.size();
+        L.idp = (int)P.idps.size();
+        P.idps.push_back(std::move(I));
+    }
+};
+
+}  // namespace
+
+Plan make_plan(int64_t nx, int64_t ny, int leaf, int m) {
+    if (nx < 1 || ny < 1 || leaf < 1 || m < 1) throw std::runtime_error("invalid plan arguments");
+    if (nx > (1 << 20) || ny > (1 << 20)) throw std::runtime_error("grid too large");
+    Plan P;
+    P.nx = nx; P.ny = ny; P.leaf = leaf; P.m = m;
+    const int sx = n_splits(nx, leaf), sy = n_splits(ny, leaf);
+    // global split schedule: longer remaining segment first, x on ties
+    std::vector<int> sched;
+    for (int dx = 0, dy = 0; dx < sx || dy < sy;) {
+        int64_t lx = (nx + (int64_t(1) << dx) - 1) >> dx;
+        int64_t ly = (ny + (int64_t(1) << dy) - 1) >> dy;
+        if (dx < sx && (dy >= sy || lx >= ly)) { sched.push_back(0); ++dx; }
+        else { sched.push_back(1); ++dy; }
+    }
+    const int depth = (int)sched.size();
+    // top-down boxes by depth
+    struct TB { int x0, y0, ax, ay, parent, c0, c1; };
+    std::vector<std::vector<TB>> bydepth(depth + 1);
+    bydepth[0].push_back({0, 0, (int)nx, (int)ny, -1, -1, -1});
+    for (int d = 0; d < depth; ++d) {
+        for (int i = 0; i < (int)bydepth[d].size(); ++i) {
+            TB& b = bydepth[d][i];
+            TB c0 = b, c1 = b;
+            c0.parent = c1.parent = i;
+            c0.c0 = c0.c1 = c1.c0 = c1.c1 = -1;
+            if (sched[d] == 0) {
+                int h = b.ax / 2;
+                c0.ax = h; c1.x0 = b.x0 + h; c1.ax = b.ax - h;
+            } else {
+                int h = b.ay / 2;
+                c0.ay = h; c1.y0 = b.y0 + h; c1.ay = b.ay - h;
+            }
+            b.c0 = (int)bydepth[d + 1].size();
+            bydepth[d + 1].push_back(c0);
+            b.c1 = (int)bydepth[d + 1].size();
+            bydepth[d + 1].push_back(c1);
+        }
+    }
+    Builder B(P);
+    // bottom-up numbering: level t = depth - d
+    std::vector<std::vector<int>> gid(depth + 1);
+    P.levels.resize(depth + 1);
+    for (int d = depth; d >= 0; --d) {
+        int t = depth - d;
+        gid[d].resize(bydepth[d].size());
+        for (int i = 0; i < (int)bydepth[d].size(); ++i) {
+            const TB& tb = bydepth[d][i];
+            Box bx;
+            bx.x0 = tb.x0; bx.y0 = tb.y0; bx.ax = tb.ax; bx.ay = tb.ay;
+            bx.level = t;
+            const bool is_root = (d == 0);
+            if (d == depth) {
+                bx.layout = B.leaf_layout(tb.ax, tb.ay, is_root);  // a root leaf keeps every point
+            } else {
+                int g0 = gid[d + 1][tb.c0], g1 = gid[d + 1][tb.c1];
+                bx.child[0] = g0; bx.child[1] = g1;
+                const Box& C0 = P.boxes[g0];
+                bx.layout = B.parent_layout(tb.ax, tb.ay, sched[d], C0.layout, P.boxes[g1].layout,
+                                            C0.ax, C0.ay, is_root);
+            }
+            const Layout& L = P.layouts[bx.layout];
+            bx.k = L.k;
+            bx.r = L.r;
+            int id = (int)P.boxes.size();
+            gid[d][i] = id;
+            P.boxes.push_back(bx);
+            P.levels[t].push_back(id);
+            if (d < depth) {
+                P.boxes[bx.child[0]].parent = id;
+                P.boxes[bx.child[1]].parent = id;
+                P.boxes[bx.child[0]].pos_in_parent = 0;
+                P.boxes[bx.child[1]].pos_in_parent = 1;
+            }
+        }
+    }
+    P.root = (int)P.boxes.size() - 1;
+    for (auto& bx : P.boxes)
+        if (&bx != &P.boxes[P.root]) B.add_idp(bx.layout);
+    // arenas
+    int64_t offF = 0, offV = 0;
+    for (auto& bx : P.boxes) {
+        int64_t mm = bx.k + bx.r;
+        bx.offF = offF;
+        offF += mm * mm;
+        bx.offV = offV;
+        offV += mm;
+    }
+    P.F_elems = offF;
+    P.V_elems = offV;
+    return P;
+}
+
+std::vector<int64_t> box_points(const Plan& p, int box) {
+    const Box& b = p.boxes.at(box);
+    const Layout& L = p.layouts[b.layout];
+    std::vector<int64_t> out(L.k + L.r);
+    for (int q = 0; q < L.k + L.r; ++q)
+        out[q] = int64_t(b.x0 + L.u[q]) * p.ny + (b.y0 + L.v[q]);
+    return out;
+}
+
+bool detect_grid(const double* pts, int64_t n, int64_t& nx, int64_t& ny, double& h,
+                 double& x0, double& y0, std::vector<int64_t>& perm, std::string& why) {
+    if (n < 1) { why = "no points"; return false; }
+    std::vector<double> xs(n), ys(n);
+    for (int64_t i = 0; i < n; ++i) {
+        xs[i] = pts[2 * i];
+        ys[i] = pts[2 * i + 1];
+        if (!std::isfinite(xs[i]) || !std::isfinite(ys[i])) { why = "non-finite coordinate"; return false; }
+    }
+    auto ux = xs, uy = ys;
+    std::sort(ux.begin(), ux.end());
+    std::sort(uy.begin(), uy.end());
+    double span = std::max(ux.back() - ux.front(), uy.back() - uy.front());
+    double eps = 1e-9 * std::max(1.0, span);
+    auto uniq = [&](std::vector<double>& v) {
+        std::vector<double> o;
+        for (double x : v)
+            if (o.empty() || x - o.back() > eps) o.push_back(x);
+        return o;
+    };
+    auto gx = uniq(ux), gy = uniq(uy);
+    nx = (int64_t)gx.size();
+    ny = (int64_t)gy.size();
+    if (nx * ny != n) { why = "point count is not nx * ny"; return false; }
+    if (nx == 1 && ny == 1) { why = "a single point is not a grid"; return false; }
+    double hx = nx > 1 ? (gx.back() - gx.front()) / double(nx - 1) : 0.0;
+    double hy = ny > 1 ? (gy.back() - gy.front()) / double(ny - 1) : 0.0;
+    h = nx > 1 ? hx : hy;
+    if (nx > 1 && ny > 1 && std::fabs(hx - hy) > 1e-9 * h) { why = "spacing differs in x and y"; return false; }
+    if (!(h > 0)) { why = "zero spacing"; return false; }
+    x0 = gx.front();
+    y0 = gy.front();
+    perm.assign(n, -1);
+    for (int64_t p = 0; p < n; ++p) {
+        double fi = (xs[p] - x0) / h, fj = (ys[p] - y0) / h;
+        int64_t i = (int64_t)std::llround(fi), j = (int64_t)std::llround(fj);
+        if (std::fabs(fi - i) > 1e-6 || std::fabs(fj - j) > 1e-6 || i < 0 || j < 0 || i >= nx || j >= ny) {
+            why = "point off the uniform grid";
+            return false;
+        }
+        int64_t g = i * ny + j;
+        if (perm[g] >= 0) { why = "duplicate grid point"; return false; }
+        perm[g] = p;
+    }
+    return true;
+}
+
+}  // namespace rsd

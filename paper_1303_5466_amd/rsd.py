@@ -1,0 +1,259 @@
+"""ctypes binding of librsd.so (include/rsd.h).  Argument marshalling only:
+every step of the factorisation and the solve runs in the native library.
+
+Functions with the C names (rsd_build_factor, rsd_solve, ...) are exposed
+as attributes of the loaded library object `lib`; `Factor` and `Plan` are thin
+owners around the opaque handles.  Arrays may be NumPy arrays (host memory)
+or torch tensors on the GPU (device memory); right-hand sides are N x nrhs
+column-major, which is a (N, nrhs) array in Fortran order, or the transpose
+of a C-contiguous (nrhs, N) tensor.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsd.so")
+
+RSD_OK, RSD_EINVAL, RSD_ENOTGRID, RSD_ENOMEM, RSD_ESINGULAR, RSD_ENOCONV, RSD_EDEVICE = range(7)
+STATUS_NAMES = ["OK", "EINVAL", "ENOTGRID", "ENOMEM", "ESINGULAR", "ENOCONV", "EDEVICE"]
+RSD_KERNEL_LAPLACE, RSD_KERNEL_HELMHOLTZ = 0, 1
+RSD_PREC_FP64, RSD_PREC_FP32_REFINE = 0, 1
+RSD_FLAG_KEEP_E = 1
+
+
+class rsd_kernel(C.Structure):
+    _fields_ = [("type", C.c_int32), ("wavenumber", C.c_double), ("contrast_b", C.c_void_p)]
+
+
+class rsd_options(C.Structure):
+    _fields_ = [("leaf_side", C.c_int32), ("layers", C.c_int32), ("precision", C.c_int32),
+                ("max_refine", C.c_int32), ("refine_tol", C.c_double), ("hip_stream", C.c_void_p),
+                ("device", C.c_int32), ("flags", C.c_int32)]
+
+
+class rsd_solve_info(C.Structure):
+    _fields_ = [("refine_iters", C.c_int32), ("rel_residual", C.c_double)]
+
+
+class rsd_factor_stats(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("nx", C.c_int64), ("ny", C.c_int64),
+                ("n_levels", C.c_int32), ("n_boxes", C.c_int32), ("layers", C.c_int32),
+                ("precision", C.c_int32), ("factor_bytes", C.c_int64),
+                ("factor_flops", C.c_double), ("solve_bytes", C.c_double),
+                ("build_ms", C.c_double)]
+
+
+class rsd_box_info(C.Structure):
+    _fields_ = [("level", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32), ("ax", C.c_int32),
+                ("ay", C.c_int32), ("k", C.c_int32), ("r", C.c_int32), ("parent", C.c_int32)]
+
+
+EXPORTS = {
+    "rsd_build_factor": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(rsd_kernel), C.c_void_p,
+                                   C.c_double, C.POINTER(rsd_options), C.POINTER(C.c_void_p)]),
+    "rsd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                            C.POINTER(rsd_solve_info)]),
+    "rsd_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "rsd_free": (None, [C.c_void_p]),
+    "rsd_last_error": (C.c_char_p, []),
+    "rsd_factor_get_stats": (C.c_int, [C.c_void_p, C.POINTER(rsd_factor_stats)]),
+    "rsd_factor_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
+    "rsd_factor_get_block": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "rsd_plan_create": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                  C.POINTER(C.c_void_p)]),
+    "rsd_plan_n_boxes": (C.c_int32, [C.c_void_p]),
+    "rsd_plan_n_levels": (C.c_int32, [C.c_void_p]),
+    "rsd_plan_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
+    "rsd_plan_box_points": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "rsd_plan_free": (None, [C.c_void_p]),
+    "rsd_detect_grid": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load librsd.so; raises if it was not built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"native library missing: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class RsdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        self.status = status
+
+
+def _check(status):
+    if status != RSD_OK:
+        raise RsdError(status, load().rsd_last_error().decode())
+
+
+def _ptr(x):
+    """(pointer, keepalive) for a NumPy array or torch tensor."""
+    if x is None:
+        return None, None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data, x
+    return x.data_ptr(), x          # torch tensor
+
+
+def _is_torch(x):
+    return not isinstance(x, np.ndarray) and hasattr(x, "data_ptr")
+
+
+class Factor:
+    """Owner of an rsd_factor handle."""
+
+    def __init__(self, points, a=None, tol=1e-10, kernel=RSD_KERNEL_LAPLACE, wavenumber=0.0,
+                 contrast=None, leaf_side=0, layers=0, precision=RSD_PREC_FP64, max_refine=0,
+                 refine_tol=0.0, stream=None, device=-1, flags=0):
+        lib = load()
+        if isinstance(points, np.ndarray):
+            points = np.ascontiguousarray(points, dtype=np.float64)
+        if isinstance(a, np.ndarray):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+        if isinstance(contrast, np.ndarray):
+            contrast = np.ascontiguousarray(contrast, dtype=np.float64)
+        n = points.shape[0]
+        pp, _k1 = _ptr(points)
+        ap, _k2 = _ptr(a)
+        bp, _k3 = _ptr(contrast)
+        kd = rsd_kernel(kernel, wavenumber, bp)
+        opt = rsd_options(leaf_side, layers, precision, max_refine, refine_tol,
+                          stream if stream is not None else None, device, flags)
+        h = C.c_void_p()
+        self._h = None
+        _check(lib.rsd_build_factor(pp, n, C.byref(kd), ap, tol, C.byref(opt), C.byref(h)))
+        self._h = h
+        self.n = n
+        self.complex = kernel == RSD_KERNEL_HELMHOLTZ
+
+    def close(self):
+        if self._h is not None:
+            load().rsd_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self):
+        s = rsd_factor_stats()
+        _check(load().rsd_factor_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in rsd_factor_stats._fields_}
+
+    def box_info(self, box):
+        b = rsd_box_info()
+        _check(load().rsd_factor_box_info(self._h, box, C.byref(b)))
+        return {f: getattr(b, f) for f, _ in rsd_box_info._fields_}
+
+    def block(self, box, which):
+        info = self.box_info(box)
+        k, r = info["k"], info["r"]
+        if which == 2:
+            out = np.zeros(k + r, dtype=np.int64)
+            _check(load().rsd_factor_get_block(self._h, box, which, out.ctypes.data))
+            return out
+        rows, cols = (k, r) if which == 0 else (k, k)
+        out = np.zeros((cols, rows), dtype=np.float64)
+        _check(load().rsd_factor_get_block(self._h, box, which, out.ctypes.data))
+        return out.T.copy()
+
+    def solve_raw(self, rhs_ptr, nrhs, x_ptr):
+        info = rsd_solve_info()
+        st = load().rsd_solve(self._h, rhs_ptr, nrhs, x_ptr, C.byref(info))
+        return st, info
+
+    def solve(self, f):
+        """x = A^{-1} f for a NumPy (N,) / (N, nrhs) array or a CUDA tensor of
+        the same shape; returns the same kind of object and the solve info."""
+        vec = f.ndim == 1
+        if _is_torch(f):
+            import torch
+            F = f.reshape(self.n, -1)
+            nrhs = F.shape[1]
+            Ft = F.t().contiguous()
+            Xt = torch.empty_like(Ft)
+            st, info = self.solve_raw(Ft.data_ptr(), nrhs, Xt.data_ptr())
+            _check(st)
+            X = Xt.t()
+            return (X[:, 0] if vec else X), info
+        F = np.asfortranarray(np.asarray(f, dtype=np.float64).reshape(self.n, -1))
+        X = np.zeros_like(F, order="F")
+        st, info = self.solve_raw(F.ctypes.data, F.shape[1], X.ctypes.data)
+        _check(st)
+        return (X[:, 0] if vec else X), info
+
+    def matvec(self, x):
+        vec = x.ndim == 1
+        X = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(self.n, -1))
+        Y = np.zeros_like(X, order="F")
+        _check(load().rsd_matvec(self._h, X.ctypes.data, X.shape[1], Y.ctypes.data))
+        return Y[:, 0] if vec else Y
+
+
+class Plan:
+    """Host-only tree / skeleton plan (no device needed)."""
+
+    def __init__(self, nx, ny, leaf_side=8, layers=2):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.rsd_plan_create(nx, ny, leaf_side, layers, C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        try:
+            if self._h is not None:
+                load().rsd_plan_free(self._h)
+        except Exception:
+            pass
+
+    @property
+    def n_boxes(self):
+        return load().rsd_plan_n_boxes(self._h)
+
+    @property
+    def n_levels(self):
+        return load().rsd_plan_n_levels(self._h)
+
+    def box_info(self, box):
+        b = rsd_box_info()
+        _check(load().rsd_plan_box_info(self._h, box, C.byref(b)))
+        return {f: getattr(b, f) for f, _ in rsd_box_info._fields_}
+
+    def box_points(self, box):
+        info = self.box_info(box)
+        out = np.zeros(info["k"] + info["r"], dtype=np.int64)
+        _check(load().rsd_plan_box_points(self._h, box, out.ctypes.data))
+        return out
+
+
+def detect_grid(points):
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    nx, ny, h = C.c_int64(), C.c_int64(), C.c_double()
+    perm = np.zeros(pts.shape[0], dtype=np.int64)
+    _check(load().rsd_detect_grid(pts.ctypes.data, pts.shape[0], C.byref(nx), C.byref(ny),
+                                  C.byref(h), perm.ctypes.data))
+    return nx.value, ny.value, h.value, perm

@@ -1,0 +1,114 @@
+"""Host-side logic of the native library, no GPU: exported symbols, grid
+detection, and the tree / skeleton plan against the CPU reference."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import rskel
+from paper_1303_5466_amd import rsd, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rsd.load()
+    hdr = open(os.path.join(ROOT, "include", "rsd.h")).read()
+    names = set(re.findall(r"\b(rsd_[a-z_0-9]+)\s*\(", hdr))
+    assert "rsd_build_factor" in names and "rsd_solve" in names and "rsd_free" in names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(rsd.EXPORTS) <= names
+
+
+@pytest.mark.parametrize("nx,ny,seed", [(16, 16, 0), (37, 37, 1), (40, 24, 2), (3, 5, 3)])
+def test_detect_grid_shuffled(nx, ny, seed):
+    pts = W.grid_points(nx, ny)
+    sp, perm = W.shuffled(pts, seed)
+    gx, gy, h, pm = rsd.detect_grid(sp)
+    assert (gx, gy) == (nx, ny)
+    assert h == pytest.approx(1.0 / max(nx, ny))
+    assert np.array_equal(sp[pm], pts)
+
+
+def test_detect_grid_rejects_non_grids():
+    pts = W.grid_points(8)
+    with pytest.raises(rsd.RsdError) as e:
+        rsd.detect_grid(pts[:-1])
+    assert e.value.status == rsd.RSD_ENOTGRID
+    dup = pts.copy()
+    dup[5] = dup[6]
+    with pytest.raises(rsd.RsdError):
+        rsd.detect_grid(dup)
+    jit = pts.copy()
+    jit[10, 0] += 0.3 / 8
+    with pytest.raises(rsd.RsdError):
+        rsd.detect_grid(jit)
+    stretched = pts.copy()
+    stretched[:, 1] *= 2.0
+    with pytest.raises(rsd.RsdError):
+        rsd.detect_grid(stretched)
+    nan = pts.copy()
+    nan[3, 1] = np.nan
+    with pytest.raises(rsd.RsdError):
+        rsd.detect_grid(nan)
+
+
+@pytest.mark.parametrize("nx,ny,leaf,m", [(64, 64, 8, 2), (40, 24, 8, 2), (37, 37, 8, 2),
+                                         (32, 32, 8, 3), (16, 16, 8, 1), (8, 8, 8, 2), (20, 7, 4, 2)])
+def test_plan_matches_reference_sets(nx, ny, leaf, m):
+    """Every box's active, skeleton and residual sets equal the reference's
+    (Sec. 3.1 layer rule); the library's order is its own."""
+    plan = rsd.Plan(nx, ny, leaf, m)
+    root, levels = rskel.index_sets(nx, ny, leaf, m)
+    D = len(levels) - 1
+    assert plan.n_levels == D + 1
+    box = 0
+    for t in range(D + 1):
+        for b in levels[D - t]:
+            info = plan.box_info(box)
+            assert (info["x0"], info["y0"], info["ax"], info["ay"]) == (b.x0, b.y0, *b.shape)
+            pts = plan.box_points(box)
+            k, r = info["k"], info["r"]
+            if t == D:
+                # the root keeps every active point: second child first, then the first
+                assert set(pts.tolist()) == set(b.act.tolist())
+            else:
+                assert set(pts[:k].tolist()) == set(b.act[b.sk].tolist())
+                assert set(pts[k:].tolist()) == set(b.act[b.rs].tolist())
+            box += 1
+    assert box == plan.n_boxes
+
+
+def test_plan_levels_golden():
+    """Per-depth box shapes and sizes stored in tests/golden/levels.txt."""
+    path = os.path.join(ROOT, "tests", "golden", "levels.txt")
+    cur = None
+    expect = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        tok = line.split()
+        if tok[0] == "grid":
+            cur = tuple(int(x) for x in tok[1:])
+            expect[cur] = []
+        else:
+            expect[cur].append(tuple(int(x) for x in tok))
+    for (nx, ny, leaf, m), rows in expect.items():
+        plan = rsd.Plan(nx, ny, leaf, m)
+        D = plan.n_levels - 1
+        got = {}
+        for b in range(plan.n_boxes):
+            i = plan.box_info(b)
+            depth = D - i["level"]
+            if depth == 0:
+                continue
+            key = (depth, i["ax"], i["ay"], i["k"], i["r"])
+            got[key] = got.get(key, 0) + 1
+        want = {(d, ax, ay, k, r): c for (d, ax, ay, c, k, r, p) in rows if d > 0}
+        assert got == want, (nx, ny)
+
+
+def test_layer_count_reads_tolerance():
+    assert rskel.layers_for_tol(1e-10) == 2
