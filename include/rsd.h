@@ -162,6 +162,21 @@ rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* o
  * dst must hold the block; elements are double (complex: interleaved). */
 rsd_status rsd_factor_get_block(const rsd_factor* f, int32_t box, int32_t which, void* dst);
 
+/* ---- dense building blocks ------------------------------------------------ */
+
+/* C = alpha op(A) op(B) + beta C with the library's MFMA grouped-GEMM kernel
+ * (one product).  dtype 0 = float64, 1 = float32.  Column-major; op = transpose
+ * when tA / tB is 1.  Pointers host or device; the call is synchronous. */
+rsd_status rsd_gemm(int32_t dtype, int32_t M, int32_t N, int32_t K, int32_t tA, int32_t tB,
+                    double alpha, const void* A, int32_t lda, const void* B, int32_t ldb,
+                    double beta, void* C, int32_t ldc);
+
+/* In-place inverse of an n x n matrix by the library's blocked Gauss-Jordan
+ * elimination in natural order (no pivoting: for symmetric positive definite
+ * or diagonally dominant matrices, the blocks the solver inverts).
+ * Returns ESINGULAR when a pivot block is singular. */
+rsd_status rsd_gj_invert(int32_t dtype, int32_t n, void* A, int32_t lda);
+
 /* ---- host-only planning (no device needed) ------------------------------ */
 
 /* Number of boxes and levels the tree of Sec. 2.2 / Sec. 3.1 produces for an

@@ -975,6 +975,72 @@ static void matvec(Factor& f, const double* xin, int64_t nrhs, double* y) {
     RSD_HIP(hipStreamSynchronize(s));
 }
 
+// ---- dense building blocks exposed for direct use ---------------------------
+template <typename T>
+static void dense_gemm(int M, int N, int K, int tA, int tB, double alpha, const void* A, int lda,
+                       const void* B, int ldb, double beta, void* C, int ldc) {
+    if (M < 0 || N < 0 || K < 0) throw Error(RSD_EINVAL, "negative size");
+    if (M == 0 || N == 0) return;
+    const int ra = tA ? K : M, ca = tA ? M : K, rb = tB ? N : K, cb = tB ? K : N;
+    if (lda < std::max(1, ra) || ldb < std::max(1, rb) || ldc < std::max(1, M))
+        throw Error(RSD_EINVAL, "leading dimension too small");
+    hipStream_t s = nullptr;
+    DevBuf dA, dB, dC, dd;
+    const T* pA = static_cast<const T*>(A);
+    const T* pB = static_cast<const T*>(B);
+    T* pC = static_cast<T*>(C);
+    const bool hc = !is_device_ptr(C);
+    if (!is_device_ptr(A)) { dA.alloc((size_t)lda * ca * sizeof(T)); RSD_HIP(hipMemcpy(dA.p, A, (size_t)lda * ca * sizeof(T), hipMemcpyHostToDevice)); pA = dA.as<T>(); }
+    if (!is_device_ptr(B)) { dB.alloc((size_t)ldb * cb * sizeof(T)); RSD_HIP(hipMemcpy(dB.p, B, (size_t)ldb * cb * sizeof(T), hipMemcpyHostToDevice)); pB = dB.as<T>(); }
+    if (hc) { dC.alloc((size_t)ldc * N * sizeof(T)); RSD_HIP(hipMemcpy(dC.p, C, (size_t)ldc * N * sizeof(T), hipMemcpyHostToDevice)); pC = dC.as<T>(); }
+    GemmBatch<T> b;
+    b.add(gdesc<T>(M, N, K, pA, lda, tA, pB, ldb, tB, pC, ldc, (T)alpha, (T)beta));
+    std::vector<GemmBatch<T>*> all{&b};
+    upload_batches<T>(dd, all, s);
+    b.run(s);
+    RSD_HIP(hipStreamSynchronize(s));
+    if (hc) RSD_HIP(hipMemcpy(C, pC, (size_t)ldc * N * sizeof(T), hipMemcpyDeviceToHost));
+}
+
+template <typename T>
+static void dense_gj(int n, void* A, int lda) {
+    if (n < 0 || lda < std::max(1, n)) throw Error(RSD_EINVAL, "bad size");
+    if (n == 0) return;
+    hipStream_t s = nullptr;
+    DevBuf dA, sr, sc, err, dd, dg;
+    T* pA = static_cast<T*>(A);
+    const bool host = !is_device_ptr(A);
+    if (host) { dA.alloc((size_t)lda * n * sizeof(T)); RSD_HIP(hipMemcpy(dA.p, A, (size_t)lda * n * sizeof(T), hipMemcpyHostToDevice)); pA = dA.as<T>(); }
+    sr.alloc((size_t)GJ_NB * n * sizeof(T));
+    sc.alloc((size_t)n * GJ_NB * sizeof(T));
+    err.alloc(4 * sizeof(int));
+    RSD_HIP(hipMemset(err.p, 0, 4 * sizeof(int)));
+    GJDesc<T> g;
+    g.X = pA; g.ld = lda; g.n = n; g.ncols = n; g.pcol = 0; g.SR = sr.as<T>(); g.SC = sc.as<T>(); g.box = 0;
+    dg.alloc(sizeof(g));
+    RSD_HIP(hipMemcpy(dg.p, &g, sizeof(g), hipMemcpyHostToDevice));
+    const int steps = (n + GJ_NB - 1) / GJ_NB;
+    std::vector<GemmBatch<T>> bs(steps);
+    std::vector<GemmBatch<T>*> all;
+    for (int st = 0; st < steps; ++st) {
+        const int j0 = st * GJ_NB, nbe = std::min(GJ_NB, n - j0);
+        GemmDesc<T> d = gdesc<T>(n, n, nbe, g.SC, n, 0, g.SR, GJ_NB, 0, pA, lda, T(-1), T(1));
+        d.zc0 = j0; d.zc1 = j0 + nbe;
+        bs[st].add(d);
+        all.push_back(&bs[st]);
+    }
+    upload_batches<T>(dd, all, s);
+    for (int st = 0; st < steps; ++st) {
+        launch_gj_pivot<T>(dg.as<GJDesc<T>>(), 1, st, GJ_NB, (n + 63) / 64, err.as<int>(), s);
+        bs[st].run(s);
+    }
+    RSD_HIP(hipStreamSynchronize(s));
+    int e[4];
+    RSD_HIP(hipMemcpy(e, err.p, sizeof(e), hipMemcpyDeviceToHost));
+    if (host) RSD_HIP(hipMemcpy(A, pA, (size_t)lda * n * sizeof(T), hipMemcpyDeviceToHost));
+    if (e[0]) throw Error(RSD_ESINGULAR, "singular pivot block");
+}
+
 }  // namespace rsd
 
 // ============================================================================
@@ -1038,6 +1104,28 @@ rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
 }
 
 void rsd_free(rsd_factor* f) { delete f; }
+
+rsd_status rsd_gemm(int32_t dtype, int32_t M, int32_t N, int32_t K, int32_t tA, int32_t tB,
+                    double alpha, const void* A, int32_t lda, const void* B, int32_t ldb,
+                    double beta, void* C, int32_t ldc) {
+    return guarded([&]() {
+        if (!A || !B || !C) throw rsd::Error(RSD_EINVAL, "null matrix");
+        if (dtype == 0) rsd::dense_gemm<double>(M, N, K, tA, tB, alpha, A, lda, B, ldb, beta, C, ldc);
+        else if (dtype == 1) rsd::dense_gemm<float>(M, N, K, tA, tB, alpha, A, lda, B, ldb, beta, C, ldc);
+        else throw rsd::Error(RSD_EINVAL, "dtype must be 0 or 1");
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_gj_invert(int32_t dtype, int32_t n, void* A, int32_t lda) {
+    return guarded([&]() {
+        if (!A) throw rsd::Error(RSD_EINVAL, "null matrix");
+        if (dtype == 0) rsd::dense_gj<double>(n, A, lda);
+        else if (dtype == 1) rsd::dense_gj<float>(n, A, lda);
+        else throw rsd::Error(RSD_EINVAL, "dtype must be 0 or 1");
+        return RSD_OK;
+    });
+}
 
 const char* rsd_last_error(void) { return g_last_error.c_str(); }
 

@@ -17,14 +17,20 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
+// Accumulator layout (16 x 16 block, lane l, element v):
+//   f64 16x16x4: row = (l / 16) + 4 v,  column = l % 16
+//   f32 16x16x4: row = 4 (l / 16) + v,  column = l % 16
+// Inputs: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] in both.
 template <> struct Mfma<double> {
     typedef d4 acc_t;
+    __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
     __device__ static inline acc_t step(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
 };
 template <> struct Mfma<float> {
     typedef f4 acc_t;
+    __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
     __device__ static inline acc_t step(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -132,7 +138,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gi = row0 + wr + bi * 16 + 4 * (lane >> 4) + v;
+                const int gi = row0 + wr + bi * 16 + Mfma<T>::row(lane, v);
                 const int gj = col0 + wc + bj * 16 + (lane & 15);
                 if (gi < d.M && gj < d.N) {
                     T* c = d.C + gi + (int64_t)gj * d.ldc;

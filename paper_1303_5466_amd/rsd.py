@@ -59,6 +59,10 @@ EXPORTS = {
                             C.POINTER(rsd_solve_info)]),
     "rsd_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "rsd_free": (None, [C.c_void_p]),
+    "rsd_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                           C.c_double, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
+                           C.c_void_p, C.c_int32]),
+    "rsd_gj_invert": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
     "rsd_last_error": (C.c_char_p, []),
     "rsd_factor_get_stats": (C.c_int, [C.c_void_p, C.POINTER(rsd_factor_stats)]),
     "rsd_factor_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
@@ -248,6 +252,29 @@ class Plan:
         out = np.zeros(info["k"] + info["r"], dtype=np.int64)
         _check(load().rsd_plan_box_points(self._h, box, out.ctypes.data))
         return out
+
+
+def gemm(A, B, C=None, alpha=1.0, beta=0.0, tA=False, tB=False):
+    """C = alpha op(A) op(B) + beta C on the device (NumPy in and out)."""
+    dt = A.dtype
+    code = 0 if dt == np.float64 else 1
+    A = np.asfortranarray(A)
+    B = np.asfortranarray(B.astype(dt))
+    M = A.shape[1] if tA else A.shape[0]
+    K = A.shape[0] if tA else A.shape[1]
+    N = B.shape[0] if tB else B.shape[1]
+    C = np.zeros((M, N), dtype=dt, order="F") if C is None else np.asfortranarray(C.astype(dt))
+    _check(load().rsd_gemm(code, M, N, K, int(tA), int(tB), alpha, A.ctypes.data, A.shape[0],
+                           B.ctypes.data, B.shape[0], beta, C.ctypes.data, C.shape[0]))
+    return C
+
+
+def gj_invert(A):
+    """Inverse by the library's blocked Gauss-Jordan (NumPy in and out)."""
+    code = 0 if A.dtype == np.float64 else 1
+    X = np.asfortranarray(A.copy())
+    _check(load().rsd_gj_invert(code, X.shape[0], X.ctypes.data, X.shape[0]))
+    return X
 
 
 def detect_grid(points):

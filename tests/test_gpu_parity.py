@@ -22,6 +22,30 @@ def _need_gpu():
     rsd.load()
 
 
+# --- dense building blocks ---------------------------------------------------
+@pytest.mark.parametrize("dt,tol", [(np.float64, 1e-13), (np.float32, 2e-5)])
+@pytest.mark.parametrize("M,N,K,tA,tB", [(64, 64, 16, 0, 0), (1, 1, 1, 0, 0), (77, 130, 45, 0, 0),
+                                         (150, 33, 70, 1, 0), (65, 97, 129, 0, 1), (40, 50, 60, 1, 1),
+                                         (300, 17, 3, 0, 0)])
+def test_gemm_matches_numpy(dt, tol, M, N, K, tA, tB):
+    rng = np.random.default_rng(M * 1000 + N)
+    A = rng.standard_normal((K, M) if tA else (M, K)).astype(dt)
+    B = rng.standard_normal((N, K) if tB else (K, N)).astype(dt)
+    C0 = rng.standard_normal((M, N)).astype(dt)
+    C = rsd.gemm(A, B, C0, alpha=-0.5, beta=2.0, tA=bool(tA), tB=bool(tB))
+    ref = -0.5 * ((A.T if tA else A).astype(np.float64) @ (B.T if tB else B).astype(np.float64)) + 2.0 * C0
+    assert np.abs(C - ref).max() <= tol * (np.abs(ref).max() + 1) * max(1, K) ** 0.5
+
+
+@pytest.mark.parametrize("n", [1, 5, 32, 33, 100, 257])
+def test_gj_inverse_matches_numpy(n):
+    rng = np.random.default_rng(n)
+    B = rng.standard_normal((n, n))
+    A = B @ B.T + n * np.eye(n)
+    X = rsd.gj_invert(A)
+    assert np.abs(X - np.linalg.inv(A)).max() <= 1e-12 * np.abs(np.linalg.inv(A)).max()
+
+
 # --- interpolation matrices (Sec. 3.1 proxy least squares) ----------------
 def test_interpolation_matches_reference_qr():
     pts = W.grid_points(64)
