@@ -162,6 +162,34 @@ rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* o
  * dst must hold the block; elements are double (complex: interleaved). */
 rsd_status rsd_factor_get_block(const rsd_factor* f, int32_t box, int32_t which, void* dst);
 
+/* ---- kernel timing -------------------------------------------------------- */
+
+/* Kernel classes timed by the built-in profiler. */
+typedef enum rsd_prof_class {
+    RSD_PROF_FACTOR_GEMM_F64 = 0,  /* block updates of the build, float64 MFMA    */
+    RSD_PROF_FACTOR_GEMM_F32 = 1,  /* block updates of the build, float32 MFMA    */
+    RSD_PROF_INTERP = 2,           /* proxy matrices + pivoted QR for T           */
+    RSD_PROF_GJ_PIVOT = 3,         /* Gauss-Jordan pivot-block steps              */
+    RSD_PROF_ASSEMBLY = 4,         /* leaf blocks, parent assembly, transposes    */
+    RSD_PROF_SOLVE_GEMM = 5,       /* level sweeps of the inverse apply           */
+    RSD_PROF_SOLVE_MOVE = 6,       /* gathers/scatters between levels             */
+    RSD_PROF_MATVEC = 7,           /* exact float64 residual products             */
+    RSD_PROF_NCLASS = 8
+} rsd_prof_class;
+
+/* Enable (on != 0) or disable the profiler and clear its records.  While
+ * enabled, every launch of a timed class is bracketed by HIP events on the
+ * stream it runs on; totals are read with rsd_profile_query.  The profiler is
+ * process-wide and not thread-safe. */
+rsd_status rsd_profile_enable(int32_t on);
+
+/* Totals for one class since the last enable: summed device time of its
+ * launches (ms), launch count, algorithmic flops and algorithmic bytes
+ * (operands read + written once) of those launches.  Synchronises the
+ * device. */
+rsd_status rsd_profile_query(int32_t cls, double* total_ms, int64_t* launches,
+                             double* flops, double* bytes);
+
 /* ---- dense building blocks ------------------------------------------------ */
 
 /* C = alpha op(A) op(B) + beta C with the library's MFMA grouped-GEMM kernel

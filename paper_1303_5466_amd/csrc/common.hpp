@@ -72,6 +72,7 @@ struct GemmDesc {
     T* C;
     int lda, ldb, lda2, ldb2, ldc;
     int zc0, zc1;      // columns [zc0, zc1) of C use beta = 0
+    const int* guard;  // if non-null and *guard != 0 the product is skipped
     T alpha, beta;
 };
 
@@ -106,28 +107,47 @@ void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* 
                          int max_pn, KernelDesc kd, hipStream_t s);
 
 // QR least squares for T (block column pivoting)
-constexpr int QR_NB = 16;
+constexpr int QR_NB = 16;     // largest sub-panel width
+constexpr int QR_WIN = 64;    // pivoting window / block width of the trailing update
+constexpr int QR_RC = 256;    // row chunk of the split-K reflector products
 struct QRProblemDev {
-    int p, k, r, nb;   // nb: panel width (16, 8 or 4 by size)
+    int p, k, r, nb;   // nb: sub-panel width (16, 8, 4 or 2 by the LDS budget)
     int64_t offA;      // p x (k + r) matrix, ld = p
     int64_t offT;      // output T (k x r), ld = k
-    int64_t offAux;    // norms (k), tau (k), T-factor (QR_NB^2), r11 (1)
-    int64_t offIaux;   // perm (k), rank, nref, j0, nbe
+    int64_t offAux;    // norms (k), tau (k), sub-panel WY (QR_NB^2), window WY (QR_WIN^2), r11
+    int64_t offIaux;   // perm (k), state (8), moves (4 * QR_WIN)
+    int64_t offV;      // V workspace p x QR_WIN (unit lower trapezoidal)
+    int64_t offTmp;    // column staging for the window permutation, p x 2 QR_WIN
+    int64_t offW;      // split-K partials nch x QR_WIN x (QR_WIN + k + r)
+    int64_t offWs;     // reduced W, QR_WIN x (QR_WIN + k + r); then W' after the trailing block
 };
 template <typename T>
 void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int max_k,
                     hipStream_t s);
-// plist: problem ids of one panel-width class; nb_class in {16, 8, 4}
 template <typename T>
-void launch_qr_panel(T* A, T* aux, int* iaux, const QRProblemDev* probs, const int* plist,
-                     int n_list, int nb_class, int step, double tol, hipStream_t s);
+void launch_qr_select(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_probs,
+                      int outer, int max_k, hipStream_t s);
+template <typename T>
+void launch_qr_move(T* A, int* iaux, T* ws, const QRProblemDev* probs, int n_probs, int phase,
+                    hipStream_t s);
+// plist: problem ids of one sub-panel width class
+template <typename T>
+void launch_qr_panel(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, const int* plist,
+                     int n_list, int nb_class, int max_p, int outer, int sub, double tol,
+                     hipStream_t s);
+template <typename T>
+void launch_qr_inner(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, const int* plist,
+                     int n_list, int nb_class, int outer, int sub, hipStream_t s);
+template <typename T>
+void launch_qr_wsum(T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_probs, int outer,
+                    int max_n, int max_nch, hipStream_t s);
+template <typename T>
+void launch_qr_norms(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int outer,
+                     int max_k, hipStream_t s);
 int qr_panel_width(int p);
 template <typename T>
-void launch_qr_update(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int step,
-                      int max_n, hipStream_t s);
-template <typename T>
-void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs, int n_probs,
-                     int max_r, int max_k, hipStream_t s);
+void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
+                     const int* plist, int n_probs, int max_r, int max_k, hipStream_t s);
 
 // Gauss-Jordan pivot step (see gj kernels)
 template <typename T>

@@ -90,6 +90,48 @@ static bool is_device_ptr(const void* p) {
 }
 
 // ----------------------------------------------------------------------------
+// kernel-class profiler (HIP events around launches, enabled on demand)
+// ----------------------------------------------------------------------------
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double flops, bytes;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e;
+        RSD_HIP(hipEventCreate(&e));
+        return e;
+    }
+    void clear() {
+        for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+        recs.clear();
+    }
+};
+static Profiler g_prof;
+
+struct ProfScope {
+    bool act;
+    ProfRec rec;
+    hipStream_t s;
+    ProfScope(int cls, hipStream_t st, double flops = 0, double bytes = 0) : act(g_prof.on), s(st) {
+        if (!act) return;
+        rec.cls = cls; rec.flops = flops; rec.bytes = bytes;
+        rec.a = g_prof.get();
+        rec.b = g_prof.get();
+        RSD_HIP(hipEventRecord(rec.a, s));
+    }
+    ~ProfScope() {
+        if (!act) return;
+        if (hipEventRecord(rec.b, s) == hipSuccess) g_prof.recs.push_back(rec);
+    }
+};
+
+// ----------------------------------------------------------------------------
 // GEMM batches: descriptors + tile tables, uploaded once
 // ----------------------------------------------------------------------------
 template <typename T>
@@ -98,7 +140,8 @@ struct GemmBatch {
     std::vector<TileRef> tiles;
     const GemmDesc<T>* d_descs = nullptr;
     const TileRef* d_tiles = nullptr;
-    double flops = 0;
+    double flops = 0, bytes = 0;
+    int prof_cls = -1;
     void add(const GemmDesc<T>& d) {
         if (d.M <= 0 || d.N <= 0) return;
         const int id = (int)descs.size();
@@ -106,10 +149,14 @@ struct GemmBatch {
         const int tm = (d.M + GEMM_TILE - 1) / GEMM_TILE, tn = (d.N + GEMM_TILE - 1) / GEMM_TILE;
         for (int i = 0; i < tm; ++i)
             for (int j = 0; j < tn; ++j) tiles.push_back({id, i, j});
-        flops += 2.0 * d.M * d.N * (double)(std::max(d.K, 0) + std::max(d.K2, 0));
+        const double kk = (double)(std::max(d.K, 0) + std::max(d.K2, 0));
+        flops += 2.0 * d.M * d.N * kk;
+        bytes += sizeof(T) * ((double)d.M * kk + kk * d.N + 2.0 * d.M * d.N);
     }
     void run(hipStream_t s) const {
-        if (!tiles.empty()) launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), s);
+        if (tiles.empty()) return;
+        ProfScope ps(prof_cls, s, flops, bytes);
+        launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), s);
     }
 };
 
@@ -125,6 +172,7 @@ static GemmDesc<T> gdesc(int M, int N, int K, const T* A, int lda, int tA, const
     d.C = C; d.ldc = ldc;
     d.alpha = alpha; d.beta = beta;
     d.zc0 = d.zc1 = 0;
+    d.guard = nullptr;
     return d;
 }
 
@@ -149,7 +197,7 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
     RSD_HIP(hipMemcpyAsync(buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
 }
 
-constexpr int GJ_NB = 32;
+constexpr int GJ_NB = 64;   // Gauss-Jordan panel width (matches k_gj)
 
 // ----------------------------------------------------------------------------
 // per-level execution plan (one precision per level)
@@ -204,6 +252,9 @@ struct Factor {
         d_level_ids, d_err, d_table;
     std::vector<int> level_id_off;
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
+    hipStream_t qr_stream = nullptr;            // interpolation problems run here
+    std::vector<hipEvent_t> level_ready;        // T of every box type of a level solved
+    std::vector<std::unique_ptr<DevBuf>> scratch;   // freed after the build
     std::vector<LevelExec<double>> L64;
     std::vector<LevelExec<float>> L32;
     std::vector<BoxDev> hboxes;
@@ -212,7 +263,13 @@ struct Factor {
     rsd_factor_stats stats{};
     ~Factor() {
         solve_plans.clear();
+        for (auto e : level_ready) (void)hipEventDestroy(e);
+        if (qr_stream) (void)hipStreamDestroy(qr_stream);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    DevBuf& tmp() {
+        scratch.push_back(std::make_unique<DevBuf>());
+        return *scratch.back();
     }
     const int* ids(int t) const { return d_level_ids.as<int>() + level_id_off[t]; }
 };
@@ -228,28 +285,36 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 // interpolation matrices for every box type (one problem per layout)
 // ----------------------------------------------------------------------------
 template <typename T>
-static void compute_T(Factor& f, const std::vector<int>& probs_ids, hipStream_t s) {
+static void compute_T(Factor& f, const std::vector<int>& probs_ids,
+                      const std::vector<int>& prob_level, std::vector<int>& level_pending,
+                      hipStream_t s) {
     Plan& P = f.plan;
     if (probs_ids.empty()) return;
     std::vector<QRProblemDev> qp;
     std::vector<int64_t> offA;
     std::vector<int> pof, kof, rof, zoff, xoff, zu, zv;
-    int64_t A_el = 0, aux_el = 0, iaux_el = 0;
-    int max_pn = 0, max_k = 0, max_r = 0, max_n = 0;
+    int64_t A_el = 0, aux_el = 0, iaux_el = 0, ws_el = 0;
+    int max_pn = 0, max_k = 0, max_r = 0, max_n = 0, max_nch = 0, S = 0;
     for (int id : probs_ids) {
         const IDProblem& I = P.idps[id];
-        const Layout& L = P.layouts[I.layout];
         QRProblemDev q;
         q.p = I.p; q.k = I.k; q.r = I.r;
         q.nb = qr_panel_width(I.p);
         if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
+        const int n = I.k + I.r;
+        const int nch = (I.p + QR_RC - 1) / QR_RC;
         q.offA = A_el;
         q.offT = f.hlayouts[I.layout].offT;
         q.offAux = aux_el;
         q.offIaux = iaux_el;
-        A_el += (int64_t)I.p * (I.k + I.r);
-        aux_el += 2 * I.k + QR_NB * QR_NB + 8;
-        iaux_el += I.k + 8;
+        q.offV = ws_el;
+        q.offTmp = q.offV + (int64_t)I.p * QR_WIN;
+        q.offW = q.offTmp + (int64_t)I.p * 2 * QR_WIN;
+        q.offWs = q.offW + (int64_t)nch * QR_WIN * (QR_WIN + n);
+        ws_el = q.offWs + (int64_t)QR_WIN * (QR_WIN + n);
+        A_el += (int64_t)I.p * n;
+        aux_el += 2 * I.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
+        iaux_el += I.k + 8 + 4 * QR_WIN;
         qp.push_back(q);
         offA.push_back(q.offA);
         pof.push_back(I.p); kof.push_back(I.k); rof.push_back(I.r);
@@ -257,52 +322,146 @@ static void compute_T(Factor& f, const std::vector<int>& probs_ids, hipStream_t 
         zu.insert(zu.end(), I.zu.begin(), I.zu.end());
         zv.insert(zv.end(), I.zv.begin(), I.zv.end());
         xoff.push_back(f.hlayouts[I.layout].off_uv);
-        max_pn = std::max(max_pn, I.p * (I.k + I.r));
+        max_pn = std::max(max_pn, I.p * n);
         max_k = std::max(max_k, I.k);
         max_r = std::max(max_r, I.r);
-        max_n = std::max(max_n, I.k + I.r);
-        (void)L;
+        max_n = std::max(max_n, n);
+        max_nch = std::max(max_nch, nch);
+        S = std::max(S, (I.k + QR_WIN - 1) / QR_WIN);
     }
-    DevBuf dA, daux, diaux, dq, doffA, dp, dk, dr, dzo, dzu, dzv, dxo, dlist;
+    DevBuf &dA = f.tmp(), &daux = f.tmp(), &diaux = f.tmp(), &dws = f.tmp(), &dq = f.tmp(),
+           &doffA = f.tmp(), &dp = f.tmp(), &dk = f.tmp(), &dr = f.tmp(), &dzo = f.tmp(),
+           &dzu = f.tmp(), &dzv = f.tmp(), &dxo = f.tmp(), &dlist = f.tmp(), &dsolve = f.tmp(),
+           &dgemm = f.tmp();
     dA.alloc(A_el * sizeof(T));
     daux.alloc(aux_el * sizeof(T));
     diaux.alloc(iaux_el * sizeof(int));
+    dws.alloc(ws_el * sizeof(T));
     upload(dq, qp, s); upload(doffA, offA, s); upload(dp, pof, s); upload(dk, kof, s);
     upload(dr, rof, s); upload(dzo, zoff, s); upload(dzu, zu, s); upload(dzv, zv, s);
     upload(dxo, xoff, s);
-    launch_proxy_matrix<T>(dA.as<T>(), doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
+    // trailing-update products of every window, guarded by the problem's skip flag
+    T* Ab = dA.as<T>();
+    T* W = dws.as<T>();
+    std::vector<GemmBatch<T>> g1(S), gt(S), g2(S);
+    double qr_flops = 0, qr_bytes = 0;
+    for (size_t i = 0; i < qp.size(); ++i) {
+        const QRProblemDev& q = qp[i];
+        const int n = q.k + q.r;
+        const int* guard = diaux.as<int>() + q.offIaux + q.k + 1;
+        T* V = W + q.offV;
+        T* Wp = W + q.offW;
+        T* Ws = W + q.offWs;
+        T* Tw = daux.as<T>() + q.offAux + 2 * q.k + QR_NB * QR_NB;
+        const int64_t chunk = (int64_t)QR_WIN * (QR_WIN + n);
+        for (int sw = 0; sw * QR_WIN < q.k; ++sw) {
+            const int J0 = sw * QR_WIN, WO = std::min(QR_WIN, q.k - J0);
+            const int ntrail = n - J0 - WO, pr = q.p - J0;
+            const int nch = (pr + QR_RC - 1) / QR_RC;
+            for (int c = 0; c < nch; ++c) {
+                const int r0 = J0 + c * QR_RC, kr = std::min(QR_RC, q.p - r0);
+                GemmDesc<T> da = gdesc<T>(QR_WIN, QR_WIN, kr, V + r0, q.p, 1, V + r0, q.p, 0,
+                                          Wp + c * chunk, QR_WIN, T(1), T(0));
+                da.guard = guard;
+                g1[sw].add(da);
+                if (ntrail > 0) {
+                    GemmDesc<T> db = gdesc<T>(QR_WIN, ntrail, kr, V + r0, q.p, 1,
+                                              Ab + q.offA + r0 + (int64_t)(J0 + WO) * q.p, q.p, 0,
+                                              Wp + c * chunk + QR_WIN * QR_WIN, QR_WIN, T(1), T(0));
+                    db.guard = guard;
+                    g1[sw].add(db);
+                }
+            }
+            if (ntrail > 0) {
+                GemmDesc<T> dt = gdesc<T>(QR_WIN, ntrail, QR_WIN, Tw, QR_WIN, 1, Ws + QR_WIN * QR_WIN,
+                                          QR_WIN, 0, Wp, QR_WIN, T(1), T(0));
+                dt.guard = guard;
+                gt[sw].add(dt);
+                GemmDesc<T> d2 = gdesc<T>(pr, ntrail, QR_WIN, V + J0, q.p, 0, Wp, QR_WIN, 0,
+                                          Ab + q.offA + J0 + (int64_t)(J0 + WO) * q.p, q.p, T(-1), T(1));
+                d2.guard = guard;
+                g2[sw].add(d2);
+            }
+        }
+        const double p = q.p, k = q.k, r = q.r;
+        qr_flops += 2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r;
+        qr_bytes += sizeof(T) * (2 * p * (k + r) + k * r);
+    }
+    std::vector<GemmBatch<T>*> all;
+    for (int sw = 0; sw < S; ++sw) { all.push_back(&g1[sw]); all.push_back(&gt[sw]); all.push_back(&g2[sw]); }
+    upload_batches<T>(dgemm, all, s);
+    ProfScope ps(RSD_PROF_INTERP, s, qr_flops, qr_bytes);
+    launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
                            dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
                            dxo.as<int>(), f.d_lu.as<int>(), f.d_lv.as<int>(), (int)qp.size(),
                            max_pn, f.kd, s);
-    launch_qr_init<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(),
-                      (int)qp.size(), max_k, s);
-    // problem lists per panel-width class
-    std::vector<int> lists[3];
-    int steps = 0;
+    launch_qr_init<T>(Ab, daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(), (int)qp.size(), max_k, s);
+    // sub-panel width classes
+    const int widths[4] = {16, 8, 4, 2};
+    std::vector<int> lists[4];
+    int maxp[4] = {0, 0, 0, 0};
     for (int i = 0; i < (int)qp.size(); ++i) {
-        int c = qp[i].nb == 16 ? 0 : (qp[i].nb == 8 ? 1 : 2);
+        int c = 0;
+        while (widths[c] != qp[i].nb) ++c;
         lists[c].push_back(i);
-        steps = std::max(steps, (qp[i].k + qp[i].nb - 1) / qp[i].nb);
+        maxp[c] = std::max(maxp[c], qp[i].p);
     }
     std::vector<int> flat;
-    int off[3];
-    for (int c = 0; c < 3; ++c) { off[c] = (int)flat.size(); flat.insert(flat.end(), lists[c].begin(), lists[c].end()); }
+    int off[4];
+    int max_subs = 0;
+    for (int c = 0; c < 4; ++c) {
+        off[c] = (int)flat.size();
+        flat.insert(flat.end(), lists[c].begin(), lists[c].end());
+        if (!lists[c].empty()) max_subs = std::max(max_subs, QR_WIN / widths[c]);
+    }
     upload(dlist, flat, s);
-    const int widths[3] = {16, 8, 4};
+    // problems grouped by the window after which they are complete
+    std::vector<std::vector<int>> done_after(S);
+    for (int i = 0; i < (int)qp.size(); ++i) done_after[(qp[i].k + QR_WIN - 1) / QR_WIN - 1].push_back(i);
+    std::vector<int> sflat;
+    std::vector<int> soff(S + 1, 0);
+    for (int sw = 0; sw < S; ++sw) {
+        soff[sw] = (int)sflat.size();
+        sflat.insert(sflat.end(), done_after[sw].begin(), done_after[sw].end());
+    }
+    soff[S] = (int)sflat.size();
+    upload(dsolve, sflat, s);
     // a float32 factor cannot resolve pivots below its rounding level
     const double qr_tol = std::is_same<T, float>::value ? std::max(f.tol, 1e-6) : f.tol;
-    for (int st = 0; st < steps; ++st) {
-        for (int c = 0; c < 3; ++c)
-            if (!lists[c].empty())
-                launch_qr_panel<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(),
-                                   dlist.as<int>() + off[c], (int)lists[c].size(), widths[c], st,
-                                   qr_tol, s);
-        launch_qr_update<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(),
-                            (int)qp.size(), st, max_n, s);
+    const int np = (int)qp.size();
+    for (int sw = 0; sw < S; ++sw) {
+        launch_qr_select<T>(Ab, daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(), np, sw, max_k, s);
+        launch_qr_move<T>(Ab, diaux.as<int>(), W, dq.as<QRProblemDev>(), np, 0, s);
+        launch_qr_move<T>(Ab, diaux.as<int>(), W, dq.as<QRProblemDev>(), np, 1, s);
+        for (int sub = 0; sub < max_subs; ++sub)
+            for (int c = 0; c < 4; ++c) {
+                if (lists[c].empty() || sub * widths[c] >= QR_WIN) continue;
+                launch_qr_panel<T>(Ab, daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(),
+                                   dlist.as<int>() + off[c], (int)lists[c].size(), widths[c], maxp[c],
+                                   sw, sub, qr_tol, s);
+                launch_qr_inner<T>(Ab, daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(),
+                                   dlist.as<int>() + off[c], (int)lists[c].size(), widths[c], sw, sub, s);
+            }
+        g1[sw].run(s);
+        launch_qr_wsum<T>(daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(), np, sw, max_n, max_nch, s);
+        gt[sw].run(s);
+        g2[sw].run(s);
+        launch_qr_norms<T>(Ab, daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(), np, sw, max_k, s);
+        const int ng = soff[sw + 1] - soff[sw];
+        if (ng > 0) {
+            int gr = 0, gk = 0;
+            for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
+                gr = std::max(gr, qp[sflat[g]].r);
+                gk = std::max(gk, qp[sflat[g]].k);
+            }
+            launch_qr_solve<T>(Ab, daux.as<T>(), diaux.as<int>(), Tbase<T>(f), dq.as<QRProblemDev>(),
+                               dsolve.as<int>() + soff[sw], ng, gr, gk, s);
+            for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
+                const int lev = prob_level[sflat[g]];
+                if (--level_pending[lev] == 0) RSD_HIP(hipEventRecord(f.level_ready[lev], s));
+            }
+        }
     }
-    launch_qr_solve<T>(dA.as<T>(), daux.as<T>(), diaux.as<int>(), Tbase<T>(f), dq.as<QRProblemDev>(),
-                       (int)qp.size(), max_r, max_k, s);
-    RSD_HIP(hipStreamSynchronize(s));   // scratch buffers go out of scope
 }
 
 // ----------------------------------------------------------------------------
@@ -351,6 +510,8 @@ static void plan_level(Factor& f, LevelExec<T>& L, int t, std::vector<GemmBatch<
     sc_need = std::max(sc_need, sc);
     L.gj_steps = (L.max_r + GJ_NB - 1) / GJ_NB;
     L.max_chunks = (L.max_m + 63) / 64;
+    const int cls = std::is_same<T, double>::value ? RSD_PROF_FACTOR_GEMM_F64 : RSD_PROF_FACTOR_GEMM_F32;
+    L.g_sr.prof_cls = L.g_rr.prof_cls = L.g_E.prof_cls = cls;
     all.push_back(&L.g_sr);
     all.push_back(&L.g_rr);
     all.push_back(&L.g_E);
@@ -379,7 +540,10 @@ static void finish_gj(Factor& f, LevelExec<T>& L, T* SRb, T* SCb, std::vector<Ge
             L.g_gj[st].add(d);
         }
     }
-    for (auto& b : L.g_gj) all.push_back(&b);
+    for (auto& b : L.g_gj) {
+        b.prof_cls = std::is_same<T, double>::value ? RSD_PROF_FACTOR_GEMM_F64 : RSD_PROF_FACTOR_GEMM_F32;
+        all.push_back(&b);
+    }
     (void)f;
     (void)gjall;
 }
@@ -404,7 +568,10 @@ static void plan_top(Factor& f, LevelExec<T>& L, T* SRb, T* SCb, std::vector<Gem
         d.zc1 = j0 + nbe;
         L.g_topgj[st].add(d);
     }
-    for (auto& bb : L.g_topgj) all.push_back(&bb);
+    for (auto& bb : L.g_topgj) {
+        bb.prof_cls = RSD_PROF_FACTOR_GEMM_F64;
+        all.push_back(&bb);
+    }
 }
 
 template <typename T>
@@ -430,6 +597,8 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
     T* F = Fbase<T>(f);
     const BoxDev* B = f.d_boxes.as<BoxDev>();
     const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
+    {
+    ProfScope ps(RSD_PROF_ASSEMBLY, s);
     if (t == 0) {
         launch_leaf_F<T>(F, B, f.ids(t), n, LD, f.d_lu.as<int>(), f.d_lv.as<int>(), f.kd, L.max_m, s);
     } else {
@@ -448,16 +617,26 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
                                               f.d_srci.as<int>(), f.kd, L.max_m, s);
         }
     }
+    }
     L.g_sr.run(s);
     L.g_rr.run(s);
-    if (!L.g_sr.tiles.empty()) launch_transpose_sr<T>(F, B, f.ids(t), n, L.max_k, L.max_r, s);
+    if (!L.g_sr.tiles.empty()) {
+        ProfScope ps(RSD_PROF_ASSEMBLY, s);
+        launch_transpose_sr<T>(F, B, f.ids(t), n, L.max_k, L.max_r, s);
+    }
     for (int st = 0; st < L.gj_steps; ++st) {
-        launch_gj_pivot<T>(L.d_gj, (int)L.gj.size(), st, GJ_NB, L.max_chunks, f.d_err.as<int>(), s);
+        {
+            ProfScope ps(RSD_PROF_GJ_PIVOT, s);
+            launch_gj_pivot<T>(L.d_gj, (int)L.gj.size(), st, GJ_NB, L.max_chunks, f.d_err.as<int>(), s);
+        }
         L.g_gj[st].run(s);
     }
     L.g_E.run(s);
     for (int st = 0; st < L.topgj_steps; ++st) {
-        launch_gj_pivot<T>(L.d_topgj, 1, st, GJ_NB, L.top_chunks, f.d_err.as<int>(), s);
+        {
+            ProfScope ps(RSD_PROF_GJ_PIVOT, s);
+            launch_gj_pivot<T>(L.d_topgj, 1, st, GJ_NB, L.top_chunks, f.d_err.as<int>(), s);
+        }
         L.g_topgj[st].run(s);
     }
 }
@@ -674,19 +853,39 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
     RSD_HIP(hipEventCreate(&e0));
     RSD_HIP(hipEventCreate(&e1));
     RSD_HIP(hipEventRecord(e0, s));
-    std::vector<int> p64, p32;
+    // interpolation problems on their own stream, overlapping the level pipeline
+    RSD_HIP(hipStreamCreateWithFlags(&f->qr_stream, hipStreamNonBlocking));
+    f->level_ready.resize(nlev, nullptr);
+    for (int t = 0; t < nlev; ++t) RSD_HIP(hipEventCreateWithFlags(&f->level_ready[t], hipEventDisableTiming));
+    {
+        hipEvent_t go;
+        RSD_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
+        RSD_HIP(hipEventRecord(go, s));
+        RSD_HIP(hipStreamWaitEvent(f->qr_stream, go, 0));
+        (void)hipEventDestroy(go);
+    }
+    std::vector<int> p64, p32, l64, l32;
+    std::vector<int> pending(nlev, 0);
     for (size_t li = 0; li < P.layouts.size(); ++li) {
         if (P.layouts[li].idp < 0) continue;
-        (f->level_prec[layout_level[li]] ? p32 : p64).push_back(P.layouts[li].idp);
+        const int lev = layout_level[li];
+        if (f->level_prec[lev]) { p32.push_back(P.layouts[li].idp); l32.push_back(lev); }
+        else { p64.push_back(P.layouts[li].idp); l64.push_back(lev); }
+        ++pending[lev];
     }
-    compute_T<double>(*f, p64, s);
-    compute_T<float>(*f, p32, s);
+    for (int t = 0; t < nlev; ++t)
+        if (pending[t] == 0) RSD_HIP(hipEventRecord(f->level_ready[t], f->qr_stream));
+    compute_T<double>(*f, p64, l64, pending, f->qr_stream);
+    compute_T<float>(*f, p32, l32, pending, f->qr_stream);
     for (int t = 0; t < nlev; ++t) {
+        RSD_HIP(hipStreamWaitEvent(s, f->level_ready[t], 0));
         if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
         else run_level<double>(*f, f->L64[exec_index[t]], s);
     }
     RSD_HIP(hipEventRecord(e1, s));
     RSD_HIP(hipStreamSynchronize(s));
+    RSD_HIP(hipStreamSynchronize(f->qr_stream));
+    f->scratch.clear();
     float ms = 0;
     RSD_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -770,11 +969,10 @@ static void plan_solve_level(Factor& f, SolvePlan& sp, SolveLevel<T>& SL, int t,
             SL.top.add(gdesc<T>(k, nr, k, Fb, m, 0, Vs, m, 0, tmp, k, T(1), T(0)));
         }
     }
-    all.push_back(&SL.up1);
-    all.push_back(&SL.up2);
-    all.push_back(&SL.dn1);
-    all.push_back(&SL.dn2);
-    all.push_back(&SL.top);
+    for (auto* b : {&SL.up1, &SL.up2, &SL.dn1, &SL.dn2, &SL.top}) {
+        b->prof_cls = RSD_PROF_SOLVE_GEMM;
+        all.push_back(b);
+    }
 }
 
 static SolvePlan& get_solve_plan(Factor& f, int nrhs) {
@@ -873,6 +1071,8 @@ static void ensure_table(Factor& f) {
 // y = A x, grid-ordered device vectors
 static void matvec_grid(Factor& f, const double* x, double* y, int nrhs) {
     ensure_table(f);
+    const double nn = (double)f.N;
+    ProfScope ps(RSD_PROF_MATVEC, f.stream, 2.0 * nn * nn * nrhs, 16.0 * nn * nrhs);
     launch_matvec(y, x, nrhs, f.d_table.as<double>(), f.nx, f.ny, f.kd, 0, f.stream);
 }
 
@@ -1104,6 +1304,39 @@ rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
 }
 
 void rsd_free(rsd_factor* f) { delete f; }
+
+rsd_status rsd_profile_enable(int32_t on) {
+    return guarded([&]() {
+        if (!rsd::g_prof.recs.empty()) RSD_HIP(hipDeviceSynchronize());
+        rsd::g_prof.clear();
+        rsd::g_prof.on = on != 0;
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_profile_query(int32_t cls, double* total_ms, int64_t* launches, double* flops,
+                             double* bytes) {
+    return guarded([&]() {
+        if (cls < 0 || cls >= RSD_PROF_NCLASS) throw rsd::Error(RSD_EINVAL, "unknown class");
+        double ms = 0, fl = 0, by = 0;
+        int64_t n = 0;
+        for (auto& r : rsd::g_prof.recs) {
+            if (r.cls != cls) continue;
+            RSD_HIP(hipEventSynchronize(r.b));
+            float e = 0;
+            RSD_HIP(hipEventElapsedTime(&e, r.a, r.b));
+            ms += e;
+            fl += r.flops;
+            by += r.bytes;
+            ++n;
+        }
+        if (total_ms) *total_ms = ms;
+        if (launches) *launches = n;
+        if (flops) *flops = fl;
+        if (bytes) *bytes = by;
+        return RSD_OK;
+    });
+}
 
 rsd_status rsd_gemm(int32_t dtype, int32_t M, int32_t N, int32_t K, int32_t tA, int32_t tB,
                     double alpha, const void* A, int32_t lda, const void* B, int32_t ldb,

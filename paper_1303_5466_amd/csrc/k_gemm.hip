@@ -121,6 +121,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
     __shared__ T Bs[BK][LDS_W];
     const TileRef tr = tiles[blockIdx.x];
     const GemmDesc<T> d = descs[tr.desc];
+    if (d.guard && *d.guard) return;
     const int row0 = tr.tm * TILE, col0 = tr.tn * TILE;
     typename Mfma<T>::acc_t acc[2][2];
 #pragma unroll

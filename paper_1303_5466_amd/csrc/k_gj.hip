@@ -21,9 +21,13 @@ namespace rsd {
 
 namespace {
 
-constexpr int GJ_NB = 32;
+constexpr int GJ_NB = 64;
 constexpr int CHUNK = 64;
 
+// Inversion of the pivot block: thread t keeps the 4 x 4 tile (rows 4(t/16),
+// columns 4(t%16)) of P in registers; step c needs only pivot row c and pivot
+// column c, which their owners publish in a double-buffered LDS strip, so each
+// elimination step costs one barrier.
 template <typename T>
 __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restrict__ descs, int step,
                                                         int nb, int* __restrict__ err) {
@@ -34,64 +38,124 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
     const int c_lo = blockIdx.x * CHUNK;
     if (c_lo >= d.ncols) return;
     const int t = threadIdx.x;
-    __shared__ T P[GJ_NB][GJ_NB + 1];
+    const int ri = 4 * (t >> 4), cj = 4 * (t & 15);
+    __shared__ T Pi[GJ_NB][GJ_NB + 1];
     __shared__ T Xp[GJ_NB][CHUNK + 1];
-    __shared__ T rowbuf[GJ_NB];
-    __shared__ T colbuf[GJ_NB];
+    __shared__ T rowb[2][GJ_NB];
+    __shared__ T colb[2][GJ_NB];
     __shared__ int bad;
     const int pc0 = d.pcol + j0;
+    T p[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ri + a, j = cj + b;
+            p[a][b] = (i < nbe && j < nbe) ? d.X[(j0 + i) + (int64_t)(pc0 + j) * d.ld]
+                                           : (i == j ? T(1) : T(0));
+        }
+    for (int e = t; e < GJ_NB * CHUNK; e += 256) {
+        const int q = e & (GJ_NB - 1), cc = e / GJ_NB;
+        const int c = c_lo + cc;
+        Xp[q][cc] = (q < nbe && c < d.ncols) ? d.X[(j0 + q) + (int64_t)c * d.ld] : T(0);
+    }
     if (t == 0) bad = 0;
-    for (int e = t; e < nbe * nbe; e += 256) {
-        const int i = e % nbe, j = e / nbe;
-        P[i][j] = d.X[(j0 + i) + (int64_t)(pc0 + j) * d.ld];
-    }
-    for (int e = t; e < nbe * CHUNK; e += 256) {
-        const int q = e % nbe, cc = e / nbe;
-        const int c = c_lo + cc;
-        Xp[q][cc] = c < d.ncols ? d.X[(j0 + q) + (int64_t)c * d.ld] : T(0);
-    }
+    // publish row 0 and column 0
+    if (ri == 0)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) rowb[0][cj + b] = p[0][b];
+    if (cj == 0)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) colb[0][ri + a] = p[a][0];
     __syncthreads();
-    // in-place inversion of P (natural order)
     for (int c = 0; c < nbe; ++c) {
-        const T piv = P[c][c];
-        if (t < nbe) {
-            rowbuf[t] = (t == c ? T(1) : P[c][t]) / piv;
-            colbuf[t] = P[t][c];
-        }
+        const int buf = c & 1;
+        const T piv = rowb[buf][c];
         if (t == 0 && !(fabs((double)piv) > 1e-300 && isfinite((double)piv))) bad = 1;
-        __syncthreads();
-        for (int e = t; e < nbe * nbe; e += 256) {
-            const int i = e % nbe, j = e / nbe;
-            if (i == c) P[i][j] = rowbuf[j];
-            else P[i][j] = (j == c ? T(0) : P[i][j]) - colbuf[i] * rowbuf[j];
+        const T inv = T(1) / piv;
+        T pr[4], pcv[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pr[b] = rowb[buf][cj + b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) pcv[a] = colb[buf][ri + a];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = ri + a, j = cj + b;
+                T v;
+                if (i == c) v = (j == c) ? inv : pr[b] * inv;
+                else v = (j == c) ? -pcv[a] * inv : p[a][b] - pcv[a] * (pr[b] * inv);
+                p[a][b] = v;
+            }
+        const int c1 = c + 1, nb2 = buf ^ 1;
+        if (c1 < nbe) {
+            if (c1 >= ri && c1 < ri + 4)
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    if (ri + a == c1)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) rowb[nb2][cj + b] = p[a][b];
+            if (c1 >= cj && c1 < cj + 4)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (cj + b == c1)
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) colb[nb2][ri + a] = p[a][b];
         }
         __syncthreads();
     }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Pi[ri + a][cj + b] = p[a][b];
+    __syncthreads();
     if (t == 0 && bad && blockIdx.x == 0) atomicCAS(err, 0, d.box + 1);
-    // SR for this column chunk, zero the pivot rows of non-pivot columns
-    for (int e = t; e < nbe * CHUNK; e += 256) {
-        const int q = e % nbe, cc = e / nbe;
-        const int c = c_lo + cc;
-        if (c >= d.ncols) continue;
-        T v;
-        if (c >= pc0 && c < pc0 + nbe) {
-            v = P[q][c - pc0];
-        } else {
-            v = T(0);
-            for (int s2 = 0; s2 < nbe; ++s2) v += P[q][s2] * Xp[s2][cc];
-            d.X[(j0 + q) + (int64_t)c * d.ld] = T(0);
+    // SR = P^{-1} X[piv rows, chunk]: 4 x 4 output tile per thread
+    {
+        T acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+        for (int s2 = 0; s2 < nbe; ++s2) {
+            T pa[4], xb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) pa[a] = Pi[ri + a][s2];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) xb[b] = Xp[s2][cj + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += pa[a] * xb[b];
         }
-        d.SR[q + (int64_t)c * nb] = v;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int c = c_lo + cj + b;
+            if (c >= d.ncols) continue;
+            const bool pivc = c >= pc0 && c < pc0 + nbe;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int q = ri + a;
+                if (q >= nbe) continue;
+                d.SR[q + (int64_t)c * nb] = pivc ? Pi[q][c - pc0] : acc[a][b];
+                if (!pivc) d.X[(j0 + q) + (int64_t)c * d.ld] = T(0);
+            }
+        }
     }
-    // owner of pivot columns: SC = old column, -I in the pivot rows
-    const int lo = max(pc0, c_lo), hi = min(pc0 + nbe, min(c_lo + CHUNK, d.ncols));
-    for (int c = lo; c < hi; ++c) {
-        const int q = c - pc0;
-        for (int i = t; i < d.n; i += 256) {
+    // SC = old pivot columns with -I in the pivot rows; rows split over the
+    // workgroups of this box (nobody writes those columns in this kernel)
+    const int nwg = (d.ncols + CHUNK - 1) / CHUNK;
+    const int rows_per = (d.n + nwg - 1) / nwg;
+    const int r0 = blockIdx.x * rows_per, r1 = min(d.n, r0 + rows_per);
+    for (int q2 = 0; q2 < nbe; ++q2) {
+        const T* src = d.X + (int64_t)(pc0 + q2) * d.ld;
+        T* dst = d.SC + (int64_t)q2 * d.n;
+        for (int i = r0 + t; i < r1; i += 256) {
             T v;
-            if (i >= j0 && i < j0 + nbe) v = (i - j0 == q) ? T(-1) : T(0);
-            else v = d.X[i + (int64_t)c * d.ld];
-            d.SC[i + (int64_t)q * d.n] = v;
+            if (i >= j0 && i < j0 + nbe) v = (i - j0 == q2) ? T(-1) : T(0);
+            else v = src[i];
+            dst[i] = v;
         }
     }
 }

@@ -6,21 +6,25 @@
 // column-pivoted QR truncated where |R_jj| <= tol |R_11|; the solution is
 // T = Pi [R11^{-1} Q1^T K(Z, X^rs); 0].
 //
-// GPU formulation (all interpolation problems of all levels advance
-// together, one launch per panel step):
-//   qr_init    column norms of K(Z, X^sk), identity permutation;
-//   qr_panel   one 1024-thread workgroup per problem: picks the QR_NB
-//              columns of largest remaining norm (wavefront argmax, lowest
-//              index on ties), factors that panel in registers with
-//              Businger-Golub pivoting inside the panel, checks the
-//              truncation rule, and forms the compact-WY factor;
-//   qr_update  applies the panel's reflectors to every trailing column
-//              (candidates and right-hand sides) and recomputes the exact
-//              trailing norms used by the next panel's selection;
-//   qr_solve   back substitution with R11 and the scatter through Pi.
-// Pivoting is therefore exact within a panel and by block (largest norms
-// first) across panels; see the design notes for why this replaces strict
-// column-by-column pivoting.
+// GPU formulation: a blocked Householder QR whose pivoting is exact inside
+// a window of QR_WIN columns and by block across windows.  All problems of
+// all levels advance together; per window:
+//   qr_select   the QR_WIN candidates of largest exact trailing norm
+//               (wavefront argmax, lowest index on ties) and the column
+//               moves that bring them to the window, in that order;
+//   qr_move     the moves (staged through a buffer, so any permutation);
+//   qr_panel    sub-panels of 16/8/4 columns factored in LDS with
+//               Businger-Golub pivoting and the truncation rule
+//               |R_jj| <= tol |R_11|, reflectors copied to a V workspace;
+//   qr_inner    each sub-panel's reflectors applied to the rest of the window;
+//   trailing    W = V^T [V | C] by split-K MFMA GEMMs, qr_wsum / qr_tbuild
+//               reduce it and form the window's compact-WY factor, then
+//               C -= V (Tw^T W) as two more GEMMs (the grouped GEMM kernel);
+//   qr_norms    exact trailing norms for the next window.
+// qr_solve finally back-substitutes with R11 and scatters through Pi.
+#include <map>
+#include <mutex>
+
 #include "common.hpp"
 
 namespace rsd {
@@ -28,26 +32,108 @@ namespace rsd {
 namespace {
 
 constexpr int NB = QR_NB;
-constexpr int PT = 512;    // panel workgroup size
+constexpr int WIN = QR_WIN;
+constexpr int PT = 256;
+
+// Wave-wide sum through DPP lane shifts (register to register): inclusive
+// sums within rows of 16 lanes, then row broadcasts 15 and 31 carry the row
+// totals up to lane 63, which is read back into every lane.
+__device__ inline float dpp_f(float v, int ctrl_sel) {
+    int x = __float_as_int(v), r;
+    switch (ctrl_sel) {
+        case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true); break;  // row_shr:1
+        case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true); break;  // row_shr:2
+        case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true); break;  // row_shr:4
+        case 3: r = __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true); break;  // row_shr:8
+        case 4: r = __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); break; // row_bcast:15
+        default: r = __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); break; // row_bcast:31
+    }
+    return __int_as_float(r);
+}
+__device__ inline double dpp_d(double v, int ctrl_sel) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int rl, rh;
+    switch (ctrl_sel) {
+        case 0: rl = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, true); break;
+        case 1: rl = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, true); break;
+        case 2: rl = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, true); break;
+        case 3: rl = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, true); break;
+        case 4: rl = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false); rh = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false); break;
+        default: rl = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false); rh = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false); break;
+    }
+    return __hiloint2double(rh, rl);
+}
+__device__ inline float dpp(float v, int c) { return dpp_f(v, c); }
+__device__ inline double dpp(double v, int c) { return dpp_d(v, c); }
+__device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+__device__ inline double lane63(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// DPP max of non-negative doubles (zero fill is the identity) and min of ints
+__device__ inline double wave_max_nonneg(double v) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v = fmax(v, dpp_d(v, c));
+    return lane63(v);
+}
+__device__ inline int dpp_i_min(int x, int c) {
+    switch (c) {
+        case 0: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x111, 0xf, 0xf, false);
+        case 1: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x112, 0xf, 0xf, false);
+        case 2: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x114, 0xf, 0xf, false);
+        case 3: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x118, 0xf, 0xf, false);
+        case 4: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x142, 0xa, 0xf, false);
+        default: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x143, 0xc, 0xf, false);
+    }
+}
+__device__ inline int wave_min_int(int v) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v = min(v, dpp_i_min(v, c));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ inline float read_lane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double read_lane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
 
 template <typename T>
 __device__ inline T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp(v, 0);
+    v += dpp(v, 1);
+    v += dpp(v, 2);
+    v += dpp(v, 3);
+    v += dpp(v, 4);
+    v += dpp(v, 5);
+    return lane63(v);
 }
 
-// aux layout per problem
+// Per-problem state: physical column order equals pivoted order; perm holds
+// the original column index of each position.
 template <typename T> struct Aux {
-    T* norms; T* tau; T* Tf; T* r11;
-    int* perm; int* state;   // state: rank, nref, j0, nbe
-    __device__ Aux(T* aux, int* iaux, const QRProblemDev& q) {
+    T* norms; T* tau; T* Tf; T* Tw; T* r11;
+    int* perm; int* state;   // state: rank, skip, J0, WO, nref, nmoves, j0, nbe
+    int* moves;              // (src, dst) pairs
+    T* V; T* Tmp; T* Wp; T* Ws;
+    __device__ Aux(T* aux, int* iaux, T* ws, const QRProblemDev& q) {
         norms = aux + q.offAux;
         tau = norms + q.k;
         Tf = tau + q.k;
-        r11 = Tf + NB * NB;
+        Tw = Tf + NB * NB;
+        r11 = Tw + WIN * WIN;
         perm = iaux + q.offIaux;
         state = perm + q.k;
+        moves = state + 8;
+        V = ws ? ws + q.offV : nullptr;
+        Tmp = ws ? ws + q.offTmp : nullptr;
+        Wp = ws ? ws + q.offW : nullptr;
+        Ws = ws ? ws + q.offWs : nullptr;
     }
 };
 
@@ -56,11 +142,12 @@ __global__ void __launch_bounds__(256) qr_init_kernel(T* __restrict__ A, T* __re
                                                        int* __restrict__ iaux,
                                                        const QRProblemDev* __restrict__ probs) {
     const QRProblemDev q = probs[blockIdx.y];
-    Aux<T> X(aux, iaux, q);
+    Aux<T> X(aux, iaux, nullptr, q);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + wave;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        X.state[0] = -1; X.state[1] = 0; X.state[2] = 0; X.state[3] = 0;
+        for (int i = 0; i < 8; ++i) X.state[i] = 0;
+        X.state[0] = -1;
         X.r11[0] = T(0);
     }
     if (c >= q.k) return;
@@ -71,222 +158,256 @@ __global__ void __launch_bounds__(256) qr_init_kernel(T* __restrict__ A, T* __re
     if (lane == 0) { X.norms[c] = s; X.perm[c] = c; }
 }
 
-// block-wide reduction of NV values (each thread supplies v[0..NV)), result
-// broadcast to every thread in a fixed order (identical in every thread)
-template <typename T, int NV>
-__device__ inline void block_sum(T (&v)[NV], T* red /* [PT/64][NV] */) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+// Window selection and the permutation that realises it (one wave).
+template <typename T>
+__global__ void __launch_bounds__(64) qr_select_kernel(T* __restrict__ A, T* __restrict__ aux,
+                                                        int* __restrict__ iaux, T* __restrict__ ws,
+                                                        const QRProblemDev* __restrict__ probs,
+                                                        int outer) {
+    extern __shared__ unsigned char smem_raw[];
+    T* vals = reinterpret_cast<T*>(smem_raw);
+    const QRProblemDev q = probs[blockIdx.x];
+    Aux<T> X(aux, iaux, ws, q);
+    const int lane = threadIdx.x;
+    __shared__ int chosen[WIN];
+    __shared__ int inwin[WIN];
+    __shared__ int mv[4 * WIN];
+    __shared__ T nv[2 * WIN];
+    __shared__ int pv[2 * WIN];
+    const int J0 = outer * WIN;
+    int skip = 0;
+    if (X.state[0] >= 0) skip = 1;
+    else if (J0 >= q.k) skip = 2;
     __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) red[wave * NV + j] = v[j];
+    if (lane == 0) {
+        if (skip == 2) X.state[0] = q.k;
+        X.state[1] = skip ? 1 : 0;
+        X.state[5] = 0;
+    }
+    if (skip) return;
+    const int WO = min(WIN, q.k - J0);
+    const int nrem = q.k - J0;
+    for (int i = lane; i < nrem; i += 64) vals[i] = X.norms[J0 + i];
+    if (lane < WIN && J0 + lane < q.k) X.tau[J0 + lane] = T(0);
+    inwin[lane] = 0;
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        T s = T(0);
-        for (int w = 0; w < PT / 64; ++w) s += red[w * NV + j];
-        v[j] = s;
+    for (int c = 0; c < WO; ++c) {
+        T best = T(-1);
+        int bi = 0x7fffffff;
+        for (int i = lane; i < nrem; i += 64) {
+            const T v = vals[i];
+            if (v > best) { best = v; bi = i; }
+        }
+        const T m = (T)wave_max_nonneg((double)(best > T(0) ? best : T(0)));
+        const int cand = (best == m && best >= T(0)) ? bi : 0x7fffffff;
+        const int win = wave_min_int(cand);
+        if (lane == 0) { chosen[c] = win; vals[win] = T(-2); }
+        __syncthreads();
+    }
+    // slot c <- chosen[c]; displaced window columns -> the outside chosen slots
+    const int ch = lane < WO ? chosen[lane] : -1;
+    if (lane < WO && ch < WO) inwin[ch] = 1;
+    __syncthreads();
+    const bool disp = lane < WO && !inwin[lane];
+    const bool outc = lane < WO && ch >= WO;
+    const unsigned long long bd = __ballot(disp), bo = __ballot(outc);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int nmove1 = __popcll(__ballot(lane < WO && ch != lane));
+    const int i1 = __popcll(__ballot(lane < WO && ch != lane) & below);
+    if (lane < WO && ch != lane) { mv[2 * i1] = J0 + ch; mv[2 * i1 + 1] = J0 + lane; }
+    // pair the j-th displaced slot with the j-th outside chosen slot
+    __shared__ int dlist[WIN], olist[WIN];
+    if (disp) dlist[__popcll(bd & below)] = lane;
+    if (outc) olist[__popcll(bo & below)] = ch;
+    __syncthreads();
+    const int nd = __popcll(bd);
+    if (lane < nd) { mv[2 * (nmove1 + lane)] = J0 + dlist[lane]; mv[2 * (nmove1 + lane) + 1] = J0 + olist[lane]; }
+    __syncthreads();
+    const int nm = nmove1 + nd;
+    for (int m = lane; m < nm; m += 64) { nv[m] = X.norms[mv[2 * m]]; pv[m] = X.perm[mv[2 * m]]; }
+    __syncthreads();
+    for (int m = lane; m < nm; m += 64) {
+        X.norms[mv[2 * m + 1]] = nv[m];
+        X.perm[mv[2 * m + 1]] = pv[m];
+        X.moves[2 * m] = mv[2 * m];
+        X.moves[2 * m + 1] = mv[2 * m + 1];
+    }
+    if (lane == 0) { X.state[2] = J0; X.state[3] = WO; X.state[5] = nm; }
+}
+
+// phase 0: stage the source columns of the moves; phase 1: write them to their slots
+template <typename T>
+__global__ void __launch_bounds__(256) qr_move_kernel(T* __restrict__ A, int* __restrict__ iaux,
+                                                       T* __restrict__ ws,
+                                                       const QRProblemDev* __restrict__ probs,
+                                                       int phase) {
+    const QRProblemDev q = probs[blockIdx.y];
+    const int* state = iaux + q.offIaux + q.k;
+    if (state[1]) return;
+    const int m = blockIdx.x;
+    if (m >= 2 * WIN) {                 // phase 0 only: clear one V column of the window
+        T* v = ws + q.offV + (int64_t)(m - 2 * WIN) * q.p;
+        for (int i = threadIdx.x; i < q.p; i += 256) v[i] = T(0);
+        return;
+    }
+    if (m >= state[5]) return;
+    const int* moves = state + 8;
+    T* tmp = ws + q.offTmp + (int64_t)m * q.p;
+    T* Ab = A + q.offA;
+    if (phase == 0) {
+        const T* src = Ab + (int64_t)moves[2 * m] * q.p;
+        for (int i = threadIdx.x; i < q.p; i += 256) tmp[i] = src[i];
+    } else {
+        T* dst = Ab + (int64_t)moves[2 * m + 1] * q.p;
+        for (int i = threadIdx.x; i < q.p; i += 256) dst[i] = tmp[i];
     }
 }
 
-template <typename T, int W, int MAXR>
+// block-wide sum of W values per thread, broadcast (same order in every thread)
+template <typename T, int W>
+__device__ inline void block_sum(T (&v)[W], T* red /* [PT/64][W] */) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < W; ++j) v[j] = wave_sum(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < W; ++j) red[wave * W + j] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        T s = T(0);
+#pragma unroll
+        for (int w = 0; w < PT / 64; ++w) s += red[w * W + j];
+        v[j] = s;
+    }
+    __syncthreads();
+}
+
+// One sub-panel (W columns of the current window) factored in LDS.
+template <typename T, int W>
 __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __restrict__ aux,
-                                                       int* __restrict__ iaux,
+                                                       int* __restrict__ iaux, T* __restrict__ ws,
                                                        const QRProblemDev* __restrict__ probs,
-                                                       const int* __restrict__ plist, int step,
+                                                       const int* __restrict__ plist, int sub,
                                                        double tol) {
+    extern __shared__ unsigned char smem_raw[];
+    T* P = reinterpret_cast<T*>(smem_raw);
     const QRProblemDev q = probs[plist[blockIdx.x]];
-    Aux<T> X(aux, iaux, q);
+    Aux<T> X(aux, iaux, ws, q);
     const int t = threadIdx.x;
     __shared__ T red[(PT / 64) * W];
     __shared__ T Tfs[W][W];
-    __shared__ T bx0;
-    __shared__ int bidx[PT / 64];
-    __shared__ T bnorm[PT / 64];
+    __shared__ T sx0;
     __shared__ int lperm[W];
     __shared__ int gperm_old[W];
-    const int j0 = step * W;
-    if (X.state[0] >= 0 || j0 >= q.k) {
-        __syncthreads();
-        if (t == 0) {
-            if (X.state[0] < 0) X.state[0] = q.k;
-            X.state[1] = 0;
-        }
+    if (X.state[1] || X.state[0] >= 0) {
+        if (t == 0) X.state[4] = 0;
         return;
     }
-    const int nbe = min(W, q.k - j0);
+    const int J0 = X.state[2], WO = X.state[3];
+    const int j0 = J0 + sub * W;
+    if (sub * W >= WO) {
+        if (t == 0) X.state[4] = 0;
+        return;
+    }
+    const int nbe = min(W, WO - sub * W);
     const int pr = q.p - j0;
     T* Ab = A + q.offA;
-    // ---- (1) block selection: the nbe largest remaining column norms -----
-    for (int c = 0; c < nbe; ++c) {
-        T best = T(-1);
-        int bi = 0x7fffffff;
-        for (int j = j0 + c + t; j < q.k; j += PT) {
-            const T v = X.norms[j];
-            if (v > best) { best = v; bi = j; }
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const T ov = __shfl_xor(best, o, 64);
-            const int oi = __shfl_xor(bi, o, 64);
-            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-        }
-        if ((t & 63) == 0) { bnorm[t >> 6] = best; bidx[t >> 6] = bi; }
-        __syncthreads();
-        if (t == 0) {
-            T b = bnorm[0];
-            int i = bidx[0];
-            for (int w = 1; w < PT / 64; ++w)
-                if (bnorm[w] > b || (bnorm[w] == b && bidx[w] < i)) { b = bnorm[w]; i = bidx[w]; }
-            bidx[0] = i;
-        }
-        __syncthreads();
-        const int jm = bidx[0];
-        const int jc = j0 + c;
-        if (jm != jc) {
-            T* ca = Ab + (int64_t)jc * q.p;
-            T* cb = Ab + (int64_t)jm * q.p;
-            for (int i = t; i < q.p; i += PT) { const T x = ca[i]; ca[i] = cb[i]; cb[i] = x; }
-            if (t == 0) {
-                const T x = X.norms[jc]; X.norms[jc] = X.norms[jm]; X.norms[jm] = x;
-                const int y = X.perm[jc]; X.perm[jc] = X.perm[jm]; X.perm[jm] = y;
-            }
-        }
-        __syncthreads();
+    for (int j = 0; j < nbe; ++j) {
+        const T* col = Ab + (int64_t)(j0 + j) * q.p + j0;
+        for (int i = t; i < pr; i += PT) P[j * pr + i] = col[i];
     }
-    // ---- (2) panel into registers: thread t holds panel rows t + s*PT ----
-    T a[MAXR][W];
-#pragma unroll
-    for (int s = 0; s < MAXR; ++s) {
-        const int i = t + s * PT;
-#pragma unroll
-        for (int j = 0; j < W; ++j)
-            a[s][j] = (i < pr && j < nbe) ? Ab[(j0 + i) + (int64_t)(j0 + j) * q.p] : T(0);
-    }
+    for (int e = t; e < W * W; e += PT) Tfs[e % W][e / W] = T(0);
+    __syncthreads();
     int perm_loc[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) perm_loc[j] = j;
-    T taus[W];
-#pragma unroll
-    for (int j = 0; j < W; ++j) taus[j] = T(0);
-    for (int e = t; e < W * W; e += PT) Tfs[e % W][e / W] = T(0);
     int nref = nbe;
-    T r11 = step == 0 ? T(0) : X.r11[0];
-    bool stop = false;
-    // ---- (3) Householder QR of the panel, pivoting inside the panel ------
+    T r11 = (j0 == 0) ? T(0) : X.r11[0];
+    for (int c = 0; c < nbe; ++c) {
+        T nrm[W];
 #pragma unroll
-    for (int c = 0; c < W; ++c) {
-        if (c < nbe && !stop) {
-            T nrm[W];
-#pragma unroll
-            for (int j = 0; j < W; ++j) {
-                T s2 = T(0);
-                if (j >= c) {
-#pragma unroll
-                    for (int s = 0; s < MAXR; ++s) {
-                        const int i = t + s * PT;
-                        if (i >= c && i < pr) s2 += a[s][j] * a[s][j];
-                    }
-                }
-                nrm[j] = s2;
-            }
-            block_sum<T, W>(nrm, red);
-            int pv = c;
-            T pn = nrm[c];
-#pragma unroll
-            for (int j = c + 1; j < W; ++j)
-                if (j < nbe && nrm[j] > pn) { pn = nrm[j]; pv = j; }
-            if (pv != c) {
-#pragma unroll
-                for (int j = c + 1; j < W; ++j) {
-                    if (j == pv) {
-#pragma unroll
-                        for (int s = 0; s < MAXR; ++s) { const T x = a[s][c]; a[s][c] = a[s][j]; a[s][j] = x; }
-                        const int x = perm_loc[c]; perm_loc[c] = perm_loc[j]; perm_loc[j] = x;
-                    }
-                }
-            }
-            const T normx = sqrt(pn);
-            if (step == 0 && c == 0) r11 = normx;
-            if (!(normx > T(tol) * r11)) {
-                stop = true;
-                nref = c;
-            } else {
-                // x0 = panel row c, held by thread c (slot 0)
-                if (t == c) bx0 = a[0][c];
-                __syncthreads();
-                const T x0 = bx0;
-                const T beta = x0 >= T(0) ? -normx : normx;
-                const T tau = (beta - x0) / beta;
-                const T scl = T(1) / (x0 - beta);
-#pragma unroll
-                for (int s = 0; s < MAXR; ++s) {
-                    const int i = t + s * PT;
-                    if (i == c) a[s][c] = beta;
-                    else if (i > c && i < pr) a[s][c] *= scl;
-                }
-                taus[c] = tau;
-                // d[j] = v_c^T a_j (j > c); d[i] = v_i^T v_c (i < c, for the WY factor)
-                T d[W];
-#pragma unroll
-                for (int j = 0; j < W; ++j) {
-                    T s2 = T(0);
-                    if (j != c) {
-#pragma unroll
-                        for (int s = 0; s < MAXR; ++s) {
-                            const int i = t + s * PT;
-                            const T vc = (i == c) ? T(1) : ((i > c && i < pr) ? a[s][c] : T(0));
-                            T other;
-                            if (j > c) other = a[s][j];
-                            else other = (i == j) ? T(1) : ((i > j && i < pr) ? a[s][j] : T(0));
-                            s2 += vc * other;
-                        }
-                    }
-                    d[j] = s2;
-                }
-                block_sum<T, W>(d, red);
-#pragma unroll
-                for (int j = 0; j < W; ++j) {
-                    if (j > c && j < nbe) {
-                        const T f = tau * d[j];
-#pragma unroll
-                        for (int s = 0; s < MAXR; ++s) {
-                            const int i = t + s * PT;
-                            const T vc = (i == c) ? T(1) : ((i > c && i < pr) ? a[s][c] : T(0));
-                            a[s][j] -= f * vc;
-                        }
-                    }
-                }
-                // compact-WY column c: Tf[0:c, c] = -tau Tf[0:c, 0:c] d[0:c]
-                if (t < c) {
-                    T s2 = T(0);
-#pragma unroll
-                    for (int l = 0; l < W; ++l)
-                        if (l >= t && l < c) s2 += Tfs[t][l] * d[l];
-                    Tfs[t][c] = -tau * s2;
-                }
-                if (t == c) Tfs[c][c] = tau;
-                __syncthreads();
-            }
-        }
-    }
-    // ---- (4) write back panel, tau, permutation ---------------------------
-#pragma unroll
-    for (int s = 0; s < MAXR; ++s) {
-        const int i = t + s * PT;
-        if (i < pr)
+        for (int j = 0; j < W; ++j) nrm[j] = T(0);
+        for (int i = c + t; i < pr; i += PT) {
 #pragma unroll
             for (int j = 0; j < W; ++j)
-                if (j < nbe) Ab[(j0 + i) + (int64_t)(j0 + j) * q.p] = a[s][j];
+                if (j >= c && j < nbe) { const T x = P[j * pr + i]; nrm[j] += x * x; }
+        }
+        block_sum<T, W>(nrm, red);
+        int pv = c;
+        T pn = T(-1);
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (j >= c && j < nbe && nrm[j] > pn) { pn = nrm[j]; pv = j; }
+        if (pv != c) {
+            for (int i = t; i < pr; i += PT) {
+                const T x = P[c * pr + i]; P[c * pr + i] = P[pv * pr + i]; P[pv * pr + i] = x;
+            }
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                if (j == pv) { const int y = perm_loc[c]; perm_loc[c] = perm_loc[j]; perm_loc[j] = y; }
+            __syncthreads();
+        }
+        const T normx = sqrt(pn);
+        if (j0 + c == 0) r11 = normx;
+        if (!(normx > T(tol) * r11)) { nref = c; break; }
+        if (t == 0) sx0 = P[c * pr + c];
+        __syncthreads();
+        const T x0 = sx0;
+        const T beta = x0 >= T(0) ? -normx : normx;
+        const T tau = (beta - x0) / beta;
+        const T scl = T(1) / (x0 - beta);
+        for (int i = c + 1 + t; i < pr; i += PT) P[c * pr + i] *= scl;
+        __syncthreads();
+        T d[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) d[j] = T(0);
+        for (int i = c + t; i < pr; i += PT) {
+            const T vc = (i == c) ? T(1) : P[c * pr + i];
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                if (j == c || j >= nbe) continue;
+                T o;
+                if (j > c) o = P[j * pr + i];
+                else o = (i == j) ? T(1) : (i > j ? P[j * pr + i] : T(0));
+                d[j] += vc * o;
+            }
+        }
+        block_sum<T, W>(d, red);
+        for (int i = c + t; i < pr; i += PT) {
+            const T vc = (i == c) ? T(1) : P[c * pr + i];
+#pragma unroll
+            for (int j = 0; j < W; ++j)
+                if (j > c && j < nbe) P[j * pr + i] -= (tau * d[j]) * vc;
+        }
+        if (t < c) {
+            T s2 = T(0);
+#pragma unroll
+            for (int l = 0; l < W; ++l)
+                if (l >= t && l < c) s2 += Tfs[t][l] * d[l];
+            Tfs[t][c] = -tau * s2;
+        }
+        if (t == c) { Tfs[c][c] = tau; X.tau[j0 + c] = tau; }
+        __syncthreads();
+        if (t == 0) P[c * pr + c] = beta;
+        __syncthreads();
+    }
+    // write back: R and reflectors to A, reflectors (unit lower) to the V workspace
+    for (int j = 0; j < nbe; ++j) {
+        T* col = Ab + (int64_t)(j0 + j) * q.p + j0;
+        T* vcol = X.V + (int64_t)(sub * W + j) * q.p + j0;
+        for (int i = t; i < pr; i += PT) {
+            const T x = P[j * pr + i];
+            col[i] = x;
+            if (j < nref) vcol[i] = (i == j) ? T(1) : (i > j ? x : T(0));
+        }
     }
     if (t < W) {
         lperm[t] = perm_loc[t];
         if (t < nbe) gperm_old[t] = X.perm[j0 + t];
     }
     __syncthreads();
-    // rows above the panel hold earlier R entries of these columns
+    // rows above the sub-panel hold earlier R entries of these columns
     for (int i = t; i < j0; i += PT) {
         T tmp[W];
 #pragma unroll
@@ -302,160 +423,234 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
             }
         }
     }
-    if (t < nbe) {
-        X.perm[j0 + t] = gperm_old[lperm[t]];
-        X.tau[j0 + t] = taus[t];
-    }
+    if (t < nbe) X.perm[j0 + t] = gperm_old[lperm[t]];
     for (int e = t; e < NB * NB; e += PT) {
         const int i = e % NB, j = e / NB;
-        X.Tf[e] = (i < W && j < W && i < nref && j < nref) ? Tfs[i][j] : T(0);
+        X.Tf[e] = (i < nref && j < nref && i < W && j < W) ? Tfs[i][j] : T(0);
     }
     if (t == 0) {
-        if (step == 0) X.r11[0] = r11;
-        X.state[1] = nref;
-        X.state[2] = j0;
-        X.state[3] = nbe;
+        if (j0 == 0) X.r11[0] = r11;
+        X.state[4] = nref;
+        X.state[6] = j0;
+        X.state[7] = nbe;
         if (nref < nbe) X.state[0] = j0 + nref;
         else if (j0 + nbe >= q.k) X.state[0] = q.k;
     }
 }
 
-// Apply the panel reflectors to the trailing columns [j0 + nbe, k + r) and
-// recompute trailing norms (rows >= j0 + nref) of candidate columns.
-template <typename T>
-__global__ void __launch_bounds__(256) qr_update_kernel(T* __restrict__ A, T* __restrict__ aux,
-                                                         int* __restrict__ iaux,
-                                                         const QRProblemDev* __restrict__ probs) {
-    const QRProblemDev q = probs[blockIdx.y];
-    Aux<T> X(aux, iaux, q);
-    const int nref = X.state[1];
+// Apply the sub-panel's reflectors to the remaining columns of the window.
+// One wave per column; reflectors read from the V workspace.
+template <typename T, int W>
+__global__ void __launch_bounds__(256) qr_inner_kernel(T* __restrict__ A, T* __restrict__ aux,
+                                                        int* __restrict__ iaux, T* __restrict__ ws,
+                                                        const QRProblemDev* __restrict__ probs,
+                                                        const int* __restrict__ plist, int sub) {
+    const QRProblemDev q = probs[plist[blockIdx.y]];
+    Aux<T> X(aux, iaux, ws, q);
+    if (X.state[1]) return;
+    const int nref = X.state[4];
     if (nref == 0) return;
-    const int j0 = X.state[2], nbe = X.state[3];
-    const int n = q.k + q.r;
-    const int cstart = j0 + nbe + blockIdx.x * 16;
-    if (cstart >= n) return;
-    const int pr = q.p - j0;
+    const int j0 = X.state[6], nbe = X.state[7];
+    const int J0 = X.state[2], WO = X.state[3];
+    if (j0 != J0 + sub * W) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    T* Ab = A + q.offA;
-    __shared__ T Vs[64][NB + 1];
-    __shared__ T Tf[NB][NB];
-    for (int e = threadIdx.x; e < NB * NB; e += 256) Tf[e % NB][e / NB] = X.Tf[e];
-    T acc[4][NB];
+    const int col = j0 + nbe + blockIdx.x * 4 + wave;
+    if (col >= J0 + WO) return;
+    const int pr = q.p - j0;
+    T* a = A + q.offA + (int64_t)col * q.p + j0;
+    const T* Vb = X.V + (int64_t)(sub * W) * q.p + j0;
+    T acc[W];
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc)
+    for (int j = 0; j < W; ++j) acc[j] = T(0);
+    for (int i = lane; i < pr; i += 64) {
+        const T x = a[i];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[cc][j] = T(0);
-    // pass 1: W = V^T A_slab
-    for (int r0 = 0; r0 < pr; r0 += 64) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-            const int i = e & 63, j = e >> 6;
-            const int r = r0 + i;
-            T v = T(0);
-            if (j < nref && r < pr) v = (r == j) ? T(1) : (r > j ? Ab[(j0 + r) + (int64_t)(j0 + j) * q.p] : T(0));
-            Vs[i][j] = v;
-        }
-        __syncthreads();
-        const int r = r0 + lane;
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-            const int col = cstart + wave + 4 * cc;
-            if (col < n && r < pr) {
-                const T x = Ab[(j0 + r) + (int64_t)col * q.p];
-#pragma unroll
-                for (int j = 0; j < NB; ++j) acc[cc][j] += Vs[lane][j] * x;
-            }
-        }
-    }
-    // reduce over lanes, then W' = Tf^T W
-    T wv[4][NB];
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) acc[cc][j] = wave_sum(acc[cc][j]);
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            T s2 = T(0);
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (i <= j) s2 += Tf[i][j] * acc[cc][i];
-            wv[cc][j] = j < nref ? s2 : T(0);
-        }
-    }
-    // pass 2: A_slab -= V W', trailing norms
-    T nr[4] = {T(0), T(0), T(0), T(0)};
-    for (int r0 = 0; r0 < pr; r0 += 64) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < 64 * NB; e += 256) {
-            const int i = e & 63, j = e >> 6;
-            const int r = r0 + i;
-            T v = T(0);
-            if (j < nref && r < pr) v = (r == j) ? T(1) : (r > j ? Ab[(j0 + r) + (int64_t)(j0 + j) * q.p] : T(0));
-            Vs[i][j] = v;
-        }
-        __syncthreads();
-        const int r = r0 + lane;
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-            const int col = cstart + wave + 4 * cc;
-            if (col < n && r < pr) {
-                T* px = Ab + (j0 + r) + (int64_t)col * q.p;
-                T x = *px;
-#pragma unroll
-                for (int j = 0; j < NB; ++j) x -= Vs[lane][j] * wv[cc][j];
-                *px = x;
-                if (r >= nref) nr[cc] += x * x;
-            }
-        }
+        for (int j = 0; j < W; ++j)
+            if (j < nref) acc[j] += Vb[(int64_t)j * q.p + i] * x;
     }
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-        const T s2 = wave_sum(nr[cc]);
-        const int col = cstart + wave + 4 * cc;
-        if (lane == 0 && col < q.k) X.norms[col] = s2;
+    for (int j = 0; j < W; ++j) acc[j] = wave_sum(acc[j]);
+    T w[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        T s2 = T(0);
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+            if (i <= j) s2 += X.Tf[i + j * NB] * acc[i];
+        w[j] = j < nref ? s2 : T(0);
+    }
+    for (int i = lane; i < pr; i += 64) {
+        T x = a[i];
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (j < nref) x -= Vb[(int64_t)j * q.p + i] * w[j];
+        a[i] = x;
     }
 }
 
-// R11 X = (Q^T K(Z, X^rs))[0:rank, :], then T[perm[i], :] = X[i, :].
+// Sum the split-K partials of W = V^T C (trailing columns, fixed order).
+template <typename T>
+__global__ void __launch_bounds__(256) qr_wsum_kernel(T* __restrict__ aux, int* __restrict__ iaux,
+                                                       T* __restrict__ ws,
+                                                       const QRProblemDev* __restrict__ probs) {
+    const QRProblemDev q = probs[blockIdx.y];
+    Aux<T> X(aux, iaux, ws, q);
+    if (X.state[1]) return;
+    const int J0 = X.state[2], WO = X.state[3];
+    const int n = q.k + q.r;
+    const int ncols = WIN + n - (J0 + WO);
+    const int nch = (q.p - J0 + QR_RC - 1) / QR_RC;
+    const int64_t chunk = (int64_t)WIN * (WIN + n);
+    for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < (int64_t)WIN * ncols;
+         e += (int64_t)gridDim.x * 256) {
+        T s = T(0);
+        for (int c = 0; c < nch; ++c) s += X.Wp[c * chunk + e];
+        X.Ws[e] = s;
+    }
+}
+
+// Window compact-WY factor from the Gram matrix V^T V (first WIN columns of
+// the reduced W): Tw[j][j] = tau_j, Tw[0:j, j] = -tau_j Tw[0:j, 0:j] G[0:j, j].
+template <typename T>
+__global__ void __launch_bounds__(64) qr_tbuild_kernel(T* __restrict__ aux, int* __restrict__ iaux,
+                                                        T* __restrict__ ws,
+                                                        const QRProblemDev* __restrict__ probs) {
+    const QRProblemDev q = probs[blockIdx.x];
+    Aux<T> X(aux, iaux, ws, q);
+    if (X.state[1]) return;
+    const int J0 = X.state[2];
+    const int lane = threadIdx.x;
+    __shared__ T Tt[WIN][WIN + 1];
+    __shared__ T G[WIN][WIN + 1];
+    for (int j = 0; j < WIN; ++j) {
+        G[lane][j] = X.Ws[lane + (int64_t)j * WIN];
+        Tt[lane][j] = T(0);
+    }
+    __syncthreads();
+    for (int j = 0; j < WIN; ++j) {
+        const T tau = (J0 + j < q.k) ? X.tau[J0 + j] : T(0);
+        T s2 = T(0);
+        if (lane < j)
+            for (int l = lane; l < j; ++l) s2 += Tt[lane][l] * G[l][j];
+        __syncthreads();
+        if (lane < j) Tt[lane][j] = -tau * s2;
+        if (lane == j) Tt[j][j] = tau;
+        __syncthreads();
+    }
+    for (int j = 0; j < WIN; ++j) X.Tw[lane + j * WIN] = Tt[lane][j];
+}
+
+// Exact trailing norms (rows >= J0 + WO) of the remaining candidates.
+template <typename T>
+__global__ void __launch_bounds__(256) qr_norms_kernel(T* __restrict__ A, T* __restrict__ aux,
+                                                        int* __restrict__ iaux,
+                                                        const QRProblemDev* __restrict__ probs) {
+    const QRProblemDev q = probs[blockIdx.y];
+    Aux<T> X(aux, iaux, nullptr, q);
+    if (X.state[1] || X.state[0] >= 0) return;
+    const int J0 = X.state[2], WO = X.state[3];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = J0 + WO + blockIdx.x * 4 + wave;
+    if (col >= q.k) return;
+    const T* a = A + q.offA + (int64_t)col * q.p;
+    T s = T(0);
+    for (int i = J0 + WO + lane; i < q.p; i += 64) s += a[i] * a[i];
+    s = wave_sum(s);
+    if (lane == 0) X.norms[col] = s;
+}
+
+// R11 X = (Q^T K(Z, X^rs))[0:rank, :], then T[perm[i], :] = X[i, :] with zero
+// rows for truncated columns.  Blocked back substitution from the bottom: a
+// 64-row diagonal block of R is staged in LDS and solved by one wave per
+// right-hand side, then every row above is updated with that block's columns
+// (coalesced reads of R, all threads busy).
 template <typename T>
 __global__ void __launch_bounds__(256) qr_solve_kernel(T* __restrict__ A, T* __restrict__ aux,
                                                         int* __restrict__ iaux, T* __restrict__ Tout,
                                                         const QRProblemDev* __restrict__ probs,
+                                                        const int* __restrict__ plist,
                                                         int cols_per_wg) {
     extern __shared__ unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);
-    const QRProblemDev q = probs[blockIdx.y];
-    Aux<T> X(aux, iaux, q);
+    T* xs = reinterpret_cast<T*>(smem_raw);               // rank x nc
+    __shared__ T Rb[64][65];
+    __shared__ int cpb[64];
+    const QRProblemDev q = probs[plist[blockIdx.y]];
+    Aux<T> X(aux, iaux, nullptr, q);
     const int rank = X.state[0] < 0 ? q.k : X.state[0];
     const int c0 = blockIdx.x * cols_per_wg;
     if (c0 >= q.r) return;
     const int nc = min(cols_per_wg, q.r - c0);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const T* Ab = A + q.offA;
-    for (int e = threadIdx.x; e < rank * nc; e += 256) {
-        const int i = e % rank, c = e / rank;
-        xs[i + c * rank] = Ab[i + (int64_t)(q.k + c0 + c) * q.p];
+    for (int c = 0; c < nc; ++c) {
+        const T* col = Ab + (int64_t)(q.k + c0 + c) * q.p;
+        for (int i = t; i < rank; i += 256) xs[c * rank + i] = col[i];
     }
-    __syncthreads();
-    for (int i = rank - 1; i >= 0; --i) {
-        const T* Ri = Ab + (int64_t)i * q.p;     // column i of R
-        const T rii = Ri[i];
-        for (int c = 0; c < nc; ++c) {
-            const T xi = xs[i + c * rank] / rii;
-            for (int l = threadIdx.x; l < i; l += 256) xs[l + c * rank] -= xi * Ri[l];
+    for (int i1 = rank; i1 > 0; i1 -= 64) {
+        const int i0 = max(0, i1 - 64), nb = i1 - i0;
+        __syncthreads();
+        if (t < nb) cpb[t] = i0 + t;
+        __syncthreads();
+        for (int e = t; e < 64 * 64; e += 256) {
+            const int r = e & 63, c = e >> 6;
+            Rb[r][c] = (r < nb && c < nb) ? Ab[(i0 + r) + (int64_t)cpb[c] * q.p] : T(0);
         }
         __syncthreads();
-        if (threadIdx.x < nc) xs[i + threadIdx.x * rank] = xs[i + threadIdx.x * rank] / rii;
+        // triangular solve of the block: wave w handles right-hand sides w, w+4, ...
+        for (int c = wave; c < nc; c += 4) {
+            T* xc = xs + c * rank + i0;
+            T xv = lane < nb ? xc[lane] : T(0);
+            for (int i = nb - 1; i >= 0; --i) {
+                const T xi = read_lane(xv, i) / Rb[i][i];
+                if (lane < i) xv -= xi * Rb[lane][i];
+                if (lane == i) xv = xi;
+            }
+            if (lane < nb) xc[lane] = xv;
+        }
         __syncthreads();
+        // rows above: x[0:i0] -= R[0:i0, block] x[block]
+        for (int r = t; r < i0; r += 256) {
+            T acc[8];
+            for (int c = 0; c < nc; ++c) acc[c] = T(0);
+            for (int j = 0; j < nb; ++j) {
+                const T rv = Ab[r + (int64_t)cpb[j] * q.p];
+                for (int c = 0; c < nc; ++c) acc[c] += rv * xs[c * rank + i0 + j];
+            }
+            for (int c = 0; c < nc; ++c) xs[c * rank + r] -= acc[c];
+        }
     }
+    __syncthreads();
     T* To = Tout + q.offT;
-    for (int e = threadIdx.x; e < q.k * nc; e += 256) {
-        const int i = e % q.k, c = e / q.k;
-        const T v = i < rank ? xs[i + c * rank] : T(0);
-        To[X.perm[i] + (int64_t)(c0 + c) * q.k] = v;
-    }
+    for (int c = 0; c < nc; ++c)
+        for (int i = t; i < q.k; i += 256)
+            To[X.perm[i] + (int64_t)(c0 + c) * q.k] = i < rank ? xs[c * rank + i] : T(0);
+}
+
+constexpr size_t LDS_BUDGET = 150 * 1024;
+
+// raise a kernel's dynamic-LDS limit once per process to what the 160 KB of
+// a gfx950 CU leaves next to the kernel's static LDS; returns that limit
+static size_t allow_lds(const void* fn) {
+    static std::mutex mu;
+    static std::map<const void*, size_t> done;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = done.find(fn);
+    if (it != done.end()) return it->second;
+    hipFuncAttributes at;
+    RSD_HIP(hipFuncGetAttributes(&at, fn));
+    const size_t lim = 160 * 1024 - at.sharedSizeBytes;
+    RSD_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim));
+    done[fn] = lim;
+    return lim;
 }
 
 }  // namespace
+
+int qr_panel_width(int p) {
+    for (int w : {16, 8, 4, 2})
+        if ((size_t)w * p * 8 <= LDS_BUDGET) return w;
+    return 0;
+}
 
 template <typename T>
 void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int max_k,
@@ -465,57 +660,105 @@ void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_pr
                        iaux, probs);
 }
 
-int qr_panel_width(int p) {
-    if (p <= 2 * PT * 2) return 16;      // MAXR 4
-    if (p <= 8 * PT) return 8;           // MAXR 8
-    if (p <= 16 * PT) return 4;          // MAXR 16
-    return 0;
-}
-
 template <typename T>
-void launch_qr_panel(T* A, T* aux, int* iaux, const QRProblemDev* probs, const int* plist,
-                     int n_list, int nb_class, int step, double tol, hipStream_t s) {
-    if (n_list <= 0) return;
-    if (nb_class == 16)
-        hipLaunchKernelGGL((qr_panel_kernel<T, 16, 4>), dim3(n_list), dim3(PT), 0, s, A, aux, iaux, probs, plist, step, tol);
-    else if (nb_class == 8)
-        hipLaunchKernelGGL((qr_panel_kernel<T, 8, 8>), dim3(n_list), dim3(PT), 0, s, A, aux, iaux, probs, plist, step, tol);
-    else if (nb_class == 4)
-        hipLaunchKernelGGL((qr_panel_kernel<T, 4, 16>), dim3(n_list), dim3(PT), 0, s, A, aux, iaux, probs, plist, step, tol);
-    else
-        throw HipError("interpolation problem too large for the panel kernel");
-}
-
-template <typename T>
-void launch_qr_update(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int step,
-                      int max_n, hipStream_t s) {
+void launch_qr_select(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_probs,
+                      int outer, int max_k, hipStream_t s) {
     if (n_probs <= 0) return;
-    (void)step;
-    hipLaunchKernelGGL(qr_update_kernel<T>, dim3((max_n + 15) / 16, n_probs), dim3(256), 0, s, A,
-                       aux, iaux, probs);
+    const size_t shm = sizeof(T) * (size_t)std::max(max_k, 1);
+    if (allow_lds((const void*)qr_select_kernel<T>) < shm) throw HipError("window selection exceeds LDS");
+    hipLaunchKernelGGL(qr_select_kernel<T>, dim3(n_probs), dim3(64), shm, s, A, aux, iaux, ws, probs, outer);
 }
 
 template <typename T>
-void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs, int n_probs,
-                     int max_r, int max_k, hipStream_t s) {
+void launch_qr_move(T* A, int* iaux, T* ws, const QRProblemDev* probs, int n_probs, int phase,
+                    hipStream_t s) {
+    if (n_probs <= 0) return;
+    hipLaunchKernelGGL(qr_move_kernel<T>, dim3(phase == 0 ? 3 * WIN : 2 * WIN, n_probs), dim3(256), 0, s,
+                       A, iaux, ws, probs, phase);
+}
+
+template <typename T, int W>
+static void panel_launch(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs,
+                         const int* plist, int n_list, int sub, double tol, size_t shm,
+                         hipStream_t s) {
+    auto kfn = qr_panel_kernel<T, W>;
+    if (allow_lds((const void*)kfn) < shm) throw HipError("interpolation panel exceeds LDS");
+    hipLaunchKernelGGL(kfn, dim3(n_list), dim3(PT), shm, s, A, aux, iaux, ws, probs, plist, sub, tol);
+}
+
+template <typename T>
+void launch_qr_panel(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, const int* plist,
+                     int n_list, int nb_class, int max_p, int outer, int sub, double tol,
+                     hipStream_t s) {
+    (void)outer;
+    if (n_list <= 0) return;
+    const size_t shm = (size_t)nb_class * max_p * sizeof(T);
+    if (nb_class == 16) panel_launch<T, 16>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
+    else if (nb_class == 8) panel_launch<T, 8>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
+    else if (nb_class == 4) panel_launch<T, 4>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
+    else if (nb_class == 2) panel_launch<T, 2>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
+    else throw HipError("bad panel width");
+}
+
+template <typename T>
+void launch_qr_inner(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, const int* plist,
+                     int n_list, int nb_class, int outer, int sub, hipStream_t s) {
+    (void)outer;
+    if (n_list <= 0) return;
+    const dim3 grid(WIN / 4, n_list);
+    if (nb_class == 16) hipLaunchKernelGGL((qr_inner_kernel<T, 16>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
+    else if (nb_class == 8) hipLaunchKernelGGL((qr_inner_kernel<T, 8>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
+    else if (nb_class == 4) hipLaunchKernelGGL((qr_inner_kernel<T, 4>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
+    else if (nb_class == 2) hipLaunchKernelGGL((qr_inner_kernel<T, 2>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
+    else throw HipError("bad panel width");
+}
+
+template <typename T>
+void launch_qr_wsum(T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_probs, int outer,
+                    int max_n, int max_nch, hipStream_t s) {
+    (void)outer; (void)max_nch;
+    if (n_probs <= 0) return;
+    int blocks = (int)std::min<int64_t>(1024, ((int64_t)WIN * (WIN + max_n) + 255) / 256);
+    hipLaunchKernelGGL(qr_wsum_kernel<T>, dim3(std::max(blocks, 1), n_probs), dim3(256), 0, s, aux, iaux, ws, probs);
+    hipLaunchKernelGGL(qr_tbuild_kernel<T>, dim3(n_probs), dim3(64), 0, s, aux, iaux, ws, probs);
+}
+
+template <typename T>
+void launch_qr_norms(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int outer,
+                     int max_k, hipStream_t s) {
+    (void)outer;
+    if (n_probs <= 0) return;
+    hipLaunchKernelGGL(qr_norms_kernel<T>, dim3((max_k + 3) / 4, n_probs), dim3(256), 0, s, A, aux, iaux, probs);
+}
+
+template <typename T>
+void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
+                     const int* plist, int n_probs, int max_r, int max_k, hipStream_t s) {
     if (n_probs <= 0 || max_r <= 0) return;
-    const int budget = 60 * 1024;
-    int cols = budget / (int)(sizeof(T) * (max_k > 0 ? max_k : 1));
+    const size_t budget = allow_lds((const void*)qr_solve_kernel<T>);
+    int cols = (int)(budget / (sizeof(T) * (size_t)(max_k > 0 ? max_k : 1)));
     if (cols > 8) cols = 8;
     if (cols < 1) throw HipError("interpolation problem too large for the solve kernel");
     const size_t shm = sizeof(T) * (size_t)max_k * cols;
     hipLaunchKernelGGL(qr_solve_kernel<T>, dim3((max_r + cols - 1) / cols, n_probs), dim3(256), shm,
-                       s, A, aux, iaux, Tout, probs, cols);
+                       s, A, aux, iaux, Tout, probs, plist, cols);
 }
 
 #define INST(T)                                                                                   \
     template void launch_qr_init<T>(T*, T*, int*, const QRProblemDev*, int, int, hipStream_t);     \
-    template void launch_qr_panel<T>(T*, T*, int*, const QRProblemDev*, const int*, int, int, int, \
-                                     double, hipStream_t);                                        \
-    template void launch_qr_update<T>(T*, T*, int*, const QRProblemDev*, int, int, int,            \
+    template void launch_qr_select<T>(T*, T*, int*, T*, const QRProblemDev*, int, int, int,        \
                                       hipStream_t);                                               \
-    template void launch_qr_solve<T>(T*, T*, int*, T*, const QRProblemDev*, int, int, int,         \
-                                     hipStream_t);
+    template void launch_qr_move<T>(T*, int*, T*, const QRProblemDev*, int, int, hipStream_t);     \
+    template void launch_qr_panel<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,  \
+                                     int, int, int, double, hipStream_t);                         \
+    template void launch_qr_inner<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,  \
+                                     int, int, hipStream_t);                                      \
+    template void launch_qr_wsum<T>(T*, int*, T*, const QRProblemDev*, int, int, int, int,         \
+                                    hipStream_t);                                                 \
+    template void launch_qr_norms<T>(T*, T*, int*, const QRProblemDev*, int, int, int,             \
+                                     hipStream_t);                                                \
+    template void launch_qr_solve<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,  \
+                                     int, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

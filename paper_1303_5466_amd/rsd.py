@@ -64,6 +64,9 @@ EXPORTS = {
                            C.c_void_p, C.c_int32]),
     "rsd_gj_invert": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
     "rsd_last_error": (C.c_char_p, []),
+    "rsd_profile_enable": (C.c_int, [C.c_int32]),
+    "rsd_profile_query": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rsd_factor_get_stats": (C.c_int, [C.c_void_p, C.POINTER(rsd_factor_stats)]),
     "rsd_factor_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
     "rsd_factor_get_block": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
@@ -252,6 +255,24 @@ class Plan:
         out = np.zeros(info["k"] + info["r"], dtype=np.int64)
         _check(load().rsd_plan_box_points(self._h, box, out.ctypes.data))
         return out
+
+
+PROF_CLASSES = ["factor_gemm_f64", "factor_gemm_f32", "interp", "gj_pivot", "assembly",
+                "solve_gemm", "solve_move", "matvec"]
+
+
+def profile_enable(on=True):
+    _check(load().rsd_profile_enable(1 if on else 0))
+
+
+def profile_query():
+    """{class name: dict(ms, launches, flops, bytes)} since the last enable."""
+    out = {}
+    for i, name in enumerate(PROF_CLASSES):
+        ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        _check(load().rsd_profile_query(i, C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+        out[name] = dict(ms=ms.value, launches=n.value, flops=fl.value, bytes=by.value)
+    return out
 
 
 def gemm(A, B, C=None, alpha=1.0, beta=0.0, tA=False, tB=False):
