@@ -24,6 +24,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -253,6 +254,8 @@ struct Factor {
     std::vector<int> level_id_off;
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
     hipStream_t qr_stream = nullptr;            // interpolation problems run here
+    hipStream_t tsolve_stream = nullptr;        // their back substitutions
+    std::vector<hipEvent_t> tmp_events;
     std::vector<hipEvent_t> level_ready;        // T of every box type of a level solved
     std::vector<std::unique_ptr<DevBuf>> scratch;   // freed after the build
     std::vector<LevelExec<double>> L64;
@@ -264,7 +267,9 @@ struct Factor {
     ~Factor() {
         solve_plans.clear();
         for (auto e : level_ready) (void)hipEventDestroy(e);
+        for (auto e : tmp_events) (void)hipEventDestroy(e);
         if (qr_stream) (void)hipStreamDestroy(qr_stream);
+        if (tsolve_stream) (void)hipStreamDestroy(tsolve_stream);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
     DevBuf& tmp() {
@@ -287,7 +292,7 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 template <typename T>
 static void compute_T(Factor& f, const std::vector<int>& probs_ids,
                       const std::vector<int>& prob_level, std::vector<int>& level_pending,
-                      hipStream_t s) {
+                      hipStream_t s, const std::function<void()>& on_progress) {
     Plan& P = f.plan;
     if (probs_ids.empty()) return;
     std::vector<QRProblemDev> qp;
@@ -449,17 +454,25 @@ static void compute_T(Factor& f, const std::vector<int>& probs_ids,
         launch_qr_norms<T>(Ab, daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(), np, sw, max_k, s);
         const int ng = soff[sw + 1] - soff[sw];
         if (ng > 0) {
+            // back substitution for the problems finished in this window, off the
+            // critical path of the remaining windows
             int gr = 0, gk = 0;
             for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
                 gr = std::max(gr, qp[sflat[g]].r);
                 gk = std::max(gk, qp[sflat[g]].k);
             }
+            hipEvent_t done;
+            RSD_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+            RSD_HIP(hipEventRecord(done, s));
+            RSD_HIP(hipStreamWaitEvent(f.tsolve_stream, done, 0));
+            f.tmp_events.push_back(done);
             launch_qr_solve<T>(Ab, daux.as<T>(), diaux.as<int>(), Tbase<T>(f), dq.as<QRProblemDev>(),
-                               dsolve.as<int>() + soff[sw], ng, gr, gk, s);
+                               dsolve.as<int>() + soff[sw], ng, gr, gk, f.tsolve_stream);
             for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
                 const int lev = prob_level[sflat[g]];
-                if (--level_pending[lev] == 0) RSD_HIP(hipEventRecord(f.level_ready[lev], s));
+                if (--level_pending[lev] == 0) RSD_HIP(hipEventRecord(f.level_ready[lev], f.tsolve_stream));
             }
+            on_progress();
         }
     }
 }
@@ -855,6 +868,7 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
     RSD_HIP(hipEventRecord(e0, s));
     // interpolation problems on their own stream, overlapping the level pipeline
     RSD_HIP(hipStreamCreateWithFlags(&f->qr_stream, hipStreamNonBlocking));
+    RSD_HIP(hipStreamCreateWithFlags(&f->tsolve_stream, hipStreamNonBlocking));
     f->level_ready.resize(nlev, nullptr);
     for (int t = 0; t < nlev; ++t) RSD_HIP(hipEventCreateWithFlags(&f->level_ready[t], hipEventDisableTiming));
     {
@@ -862,6 +876,7 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
         RSD_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
         RSD_HIP(hipEventRecord(go, s));
         RSD_HIP(hipStreamWaitEvent(f->qr_stream, go, 0));
+        RSD_HIP(hipStreamWaitEvent(f->tsolve_stream, go, 0));
         (void)hipEventDestroy(go);
     }
     std::vector<int> p64, p32, l64, l32;
@@ -874,18 +889,29 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
         ++pending[lev];
     }
     for (int t = 0; t < nlev; ++t)
-        if (pending[t] == 0) RSD_HIP(hipEventRecord(f->level_ready[t], f->qr_stream));
-    compute_T<double>(*f, p64, l64, pending, f->qr_stream);
-    compute_T<float>(*f, p32, l32, pending, f->qr_stream);
-    for (int t = 0; t < nlev; ++t) {
-        RSD_HIP(hipStreamWaitEvent(s, f->level_ready[t], 0));
-        if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
-        else run_level<double>(*f, f->L64[exec_index[t]], s);
-    }
+        if (pending[t] == 0) RSD_HIP(hipEventRecord(f->level_ready[t], f->tsolve_stream));
+    // levels are enqueued as soon as the events of their box types exist, so the
+    // level pipeline runs alongside the interpolation problems
+    int next_level = 0;
+    auto enqueue_ready = [&]() {
+        while (next_level < nlev && pending[next_level] == 0) {
+            const int t = next_level++;
+            RSD_HIP(hipStreamWaitEvent(s, f->level_ready[t], 0));
+            if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
+            else run_level<double>(*f, f->L64[exec_index[t]], s);
+        }
+    };
+    compute_T<double>(*f, p64, l64, pending, f->qr_stream, enqueue_ready);
+    compute_T<float>(*f, p32, l32, pending, f->qr_stream, enqueue_ready);
+    enqueue_ready();
+    if (next_level != nlev) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
     RSD_HIP(hipEventRecord(e1, s));
     RSD_HIP(hipStreamSynchronize(s));
     RSD_HIP(hipStreamSynchronize(f->qr_stream));
+    RSD_HIP(hipStreamSynchronize(f->tsolve_stream));
     f->scratch.clear();
+    for (auto e : f->tmp_events) (void)hipEventDestroy(e);
+    f->tmp_events.clear();
     float ms = 0;
     RSD_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);

@@ -438,8 +438,8 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     }
 }
 
-// Apply the sub-panel's reflectors to the remaining columns of the window.
-// One wave per column; reflectors read from the V workspace.
+// Apply the sub-panel's reflectors to the remaining columns of the window:
+// one workgroup per column, its four waves splitting the rows.
 template <typename T, int W>
 __global__ void __launch_bounds__(256) qr_inner_kernel(T* __restrict__ A, T* __restrict__ aux,
                                                         int* __restrict__ iaux, T* __restrict__ ws,
@@ -453,16 +453,17 @@ __global__ void __launch_bounds__(256) qr_inner_kernel(T* __restrict__ A, T* __r
     const int j0 = X.state[6], nbe = X.state[7];
     const int J0 = X.state[2], WO = X.state[3];
     if (j0 != J0 + sub * W) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = j0 + nbe + blockIdx.x * 4 + wave;
+    const int col = j0 + nbe + blockIdx.x;
     if (col >= J0 + WO) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int pr = q.p - j0;
     T* a = A + q.offA + (int64_t)col * q.p + j0;
     const T* Vb = X.V + (int64_t)(sub * W) * q.p + j0;
+    __shared__ T part[4][W];
     T acc[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) acc[j] = T(0);
-    for (int i = lane; i < pr; i += 64) {
+    for (int i = threadIdx.x; i < pr; i += 256) {
         const T x = a[i];
 #pragma unroll
         for (int j = 0; j < W; ++j)
@@ -470,6 +471,12 @@ __global__ void __launch_bounds__(256) qr_inner_kernel(T* __restrict__ A, T* __r
     }
 #pragma unroll
     for (int j = 0; j < W; ++j) acc[j] = wave_sum(acc[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < W; ++j) part[wave][j] = acc[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < W; ++j) acc[j] = part[0][j] + part[1][j] + part[2][j] + part[3][j];
     T w[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
@@ -479,7 +486,7 @@ __global__ void __launch_bounds__(256) qr_inner_kernel(T* __restrict__ A, T* __r
             if (i <= j) s2 += X.Tf[i + j * NB] * acc[i];
         w[j] = j < nref ? s2 : T(0);
     }
-    for (int i = lane; i < pr; i += 64) {
+    for (int i = threadIdx.x; i < pr; i += 256) {
         T x = a[i];
 #pragma unroll
         for (int j = 0; j < W; ++j)
@@ -705,7 +712,7 @@ void launch_qr_inner(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, 
                      int n_list, int nb_class, int outer, int sub, hipStream_t s) {
     (void)outer;
     if (n_list <= 0) return;
-    const dim3 grid(WIN / 4, n_list);
+    const dim3 grid(WIN, n_list);
     if (nb_class == 16) hipLaunchKernelGGL((qr_inner_kernel<T, 16>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
     else if (nb_class == 8) hipLaunchKernelGGL((qr_inner_kernel<T, 8>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
     else if (nb_class == 4) hipLaunchKernelGGL((qr_inner_kernel<T, 4>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
