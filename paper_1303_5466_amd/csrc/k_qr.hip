@@ -263,41 +263,132 @@ __global__ void __launch_bounds__(256) qr_move_kernel(T* __restrict__ A, int* __
     }
 }
 
-// block-wide sum of W values per thread, broadcast (same order in every thread)
-template <typename T, int W>
-__device__ inline void block_sum(T (&v)[W], T* red /* [PT/64][W] */) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+// Block-wide sums of N values per thread (N a power of two, at most 64),
+// returned in every thread in the same order.  Within a wave a butterfly
+// halves the values held per lane at each exchange (lanes whose bit b is set
+// keep the upper half), so N values cost N - 1 + 6 - log2 N exchanges instead
+// of 6 N; the four wave partials meet in LDS.  red alternates between two
+// halves (parity) so that one barrier per call suffices.
+// An empty asm statement the optimiser cannot look through: it keeps a
+// select between two register-array elements from being rewritten as an
+// indexed load, which would move the whole array to scratch memory.
+__device__ inline void opaque(double& x) { asm("" : "+v"(x)); }
+__device__ inline void opaque(float& x) { asm("" : "+v"(x)); }
+
+template <int N> struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
+template <> struct Log2<1> { static constexpr int v = 0; };
+
+template <typename T, int N, int RS>
+__device__ inline const T* block_sum_n(T (&v)[N], T* red /* [2][RS] */, int& parity) {
+    constexpr int LN = Log2<N>::v;
+    static_assert((1 << LN) == N && LN <= 6 && N * (PT / 64) <= RS, "power of two up to 64");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < W; ++j) v[j] = wave_sum(v[j]);
-    if (lane == 0)
+    for (int s = 0; s < LN; ++s) {
+        const int b = 5 - s;
+        const bool hi = (lane >> b) & 1;
+        const int h = N >> (s + 1);
 #pragma unroll
-        for (int j = 0; j < W; ++j) red[wave * W + j] = v[j];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-        T s = T(0);
-#pragma unroll
-        for (int w = 0; w < PT / 64; ++w) s += red[w * W + j];
-        v[j] = s;
+        for (int j = 0; j < N / 2; ++j) {
+            if (j < h) {
+                T lo_v = v[j], hi_v = v[j + h];
+                opaque(lo_v);
+                opaque(hi_v);   // keeps the selects on values, not on array slots
+                const T send = hi ? lo_v : hi_v;
+                const T keep = hi ? hi_v : lo_v;
+                v[j] = keep + __shfl_xor(send, 1 << b);
+            }
+        }
     }
+#pragma unroll
+    for (int b = 5 - LN; b >= 0; --b) v[0] += __shfl_xor(v[0], 1 << b);
+    T* r = red + parity * RS;
+    if ((lane & ((64 >> LN) - 1)) == 0) r[(lane >> (6 - LN)) * (PT / 64) + wave] = v[0];
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        T s2 = T(0);
+#pragma unroll
+        for (int w = 0; w < PT / 64; ++w) s2 += r[j * (PT / 64) + w];
+        v[j] = s2;
+    }
+    parity ^= 1;
+    return r;   // the wave partials of value j at r[j * (PT / 64) + w]
+}
+
+// Sub-panel rows in LDS: row-major, W entries per row, the row stride padded
+// to 4 (mod 8) dwords so that 16-byte row reads by consecutive lanes are
+// free of bank conflicts.
+template <typename T, int W>
+constexpr int panel_stride() {
+    int s = (int)(W * sizeof(T) / 4);
+    while (s % 8 != 4) ++s;
+    return s * 4 / (int)sizeof(T);
+}
+
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct Vec16<float> { typedef float __attribute__((ext_vector_type(4))) type; };
+
+template <typename T, int W>
+__device__ inline void load_row(const T* p, T (&x)[W]) {
+    constexpr int n = 16 / sizeof(T);
+    if constexpr (W % n == 0) {
+        typedef typename Vec16<T>::type V;
+#pragma unroll
+        for (int j = 0; j < W / n; ++j) {
+            const V v = reinterpret_cast<const V*>(p)[j];
+#pragma unroll
+            for (int e = 0; e < n; ++e) x[j * n + e] = v[e];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) x[j] = p[j];
+    }
+}
+
+template <typename T, int W>
+__device__ inline void store_row(T* p, const T (&x)[W]) {
+    constexpr int n = 16 / sizeof(T);
+    if constexpr (W % n == 0) {
+        typedef typename Vec16<T>::type V;
+#pragma unroll
+        for (int j = 0; j < W / n; ++j) {
+            V v;
+#pragma unroll
+            for (int e = 0; e < n; ++e) v[e] = x[j * n + e];
+            reinterpret_cast<V*>(p)[j] = v;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) p[j] = x[j];
+    }
 }
 
 // One sub-panel (W columns of the current window) factored in LDS.
+//
+// Thread t owns rows i = t (mod PT) of the sub-panel for the whole call, so
+// the per-column passes (pivot swap, reflector dot products, rank-1 update)
+// touch only the owner's rows and need no barrier between them; the two
+// block sums per column carry everything shared: the trailing norms together
+// with row c of every column (which gives the pivot's leading entry), then
+// the dot products of the reflector with every column.  The norms for the
+// next column are accumulated during the update.  Thread t < W owns row t of
+// the compact-WY factor, thread 0 the local pivot order.
 template <typename T, int W>
 __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __restrict__ aux,
-                                                       int* __restrict__ iaux, T* __restrict__ ws,
-                                                       const QRProblemDev* __restrict__ probs,
-                                                       const int* __restrict__ plist, int sub,
-                                                       double tol) {
-    extern __shared__ unsigned char smem_raw[];
+                                                      int* __restrict__ iaux, T* __restrict__ ws,
+                                                      const QRProblemDev* __restrict__ probs,
+                                                      const int* __restrict__ plist, int sub,
+                                                      double tol) {
+    constexpr int S = panel_stride<T, W>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     T* P = reinterpret_cast<T*>(smem_raw);
     const QRProblemDev q = probs[plist[blockIdx.x]];
     Aux<T> X(aux, iaux, ws, q);
     const int t = threadIdx.x;
-    __shared__ T red[(PT / 64) * W];
-    __shared__ T Tfs[W][W];
-    __shared__ T sx0;
+    __shared__ T red[2 * 2 * W * (PT / 64)];
+    __shared__ T Tfs[W][W + 1];
     __shared__ int lperm[W];
     __shared__ int gperm_old[W];
     if (X.state[1] || X.state[0] >= 0) {
@@ -312,122 +403,134 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     }
     const int nbe = min(W, WO - sub * W);
     const int pr = q.p - j0;
-    T* Ab = A + q.offA;
-    for (int j = 0; j < nbe; ++j) {
-        const T* col = Ab + (int64_t)(j0 + j) * q.p + j0;
-        for (int i = t; i < pr; i += PT) P[j * pr + i] = col[i];
-    }
-    for (int e = t; e < W * W; e += PT) Tfs[e % W][e / W] = T(0);
-    __syncthreads();
-    int perm_loc[W];
+    T* Ab = A + q.offA + (int64_t)j0 * q.p + j0;    // sub-panel origin
+    // load (columns past nbe zero-filled); first norms and row 0 on the fly
+    T nr[2 * W];   // [0, W): trailing norms^2, [W, 2W): row c of each column
 #pragma unroll
-    for (int j = 0; j < W; ++j) perm_loc[j] = j;
+    for (int j = 0; j < 2 * W; ++j) nr[j] = T(0);
+    for (int i = t; i < pr; i += PT) {
+        T x[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) x[j] = j < nbe ? Ab[(int64_t)j * q.p + i] : T(0);
+        store_row<T, W>(P + i * S, x);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            nr[j] += x[j] * x[j];
+            if (i == 0) nr[W + j] = x[j];
+        }
+    }
+    if (t < W) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) Tfs[t][j] = T(0);
+    }
+    if (t == 0)
+        for (int j = 0; j < W; ++j) lperm[j] = j;
+    int parity = 0;
     int nref = nbe;
     T r11 = (j0 == 0) ? T(0) : X.r11[0];
     for (int c = 0; c < nbe; ++c) {
-        T nrm[W];
-#pragma unroll
-        for (int j = 0; j < W; ++j) nrm[j] = T(0);
-        for (int i = c + t; i < pr; i += PT) {
-#pragma unroll
-            for (int j = 0; j < W; ++j)
-                if (j >= c && j < nbe) { const T x = P[j * pr + i]; nrm[j] += x * x; }
-        }
-        block_sum<T, W>(nrm, red);
+        const T* rp = block_sum_n<T, 2 * W, 2 * W * (PT / 64)>(nr, red, parity);
         int pv = c;
         T pn = T(-1);
 #pragma unroll
         for (int j = 0; j < W; ++j)
-            if (j >= c && j < nbe && nrm[j] > pn) { pn = nrm[j]; pv = j; }
+            if (j >= c && j < nbe && nr[j] > pn) { pn = nr[j]; pv = j; }
+        // the pivot's entry in row c, summed from the partials as in block_sum_n
+        T x0 = T(0);
+#pragma unroll
+        for (int w = 0; w < PT / 64; ++w) x0 += rp[(W + pv) * (PT / 64) + w];
         if (pv != c) {
             for (int i = t; i < pr; i += PT) {
-                const T x = P[c * pr + i]; P[c * pr + i] = P[pv * pr + i]; P[pv * pr + i] = x;
+                const T a = P[i * S + c], b = P[i * S + pv];
+                P[i * S + c] = b;
+                P[i * S + pv] = a;
             }
-#pragma unroll
-            for (int j = 0; j < W; ++j)
-                if (j == pv) { const int y = perm_loc[c]; perm_loc[c] = perm_loc[j]; perm_loc[j] = y; }
-            __syncthreads();
+            if (t == 0) { const int y = lperm[c]; lperm[c] = lperm[pv]; lperm[pv] = y; }
         }
         const T normx = sqrt(pn);
         if (j0 + c == 0) r11 = normx;
         if (!(normx > T(tol) * r11)) { nref = c; break; }
-        if (t == 0) sx0 = P[c * pr + c];
-        __syncthreads();
-        const T x0 = sx0;
         const T beta = x0 >= T(0) ? -normx : normx;
         const T tau = (beta - x0) / beta;
         const T scl = T(1) / (x0 - beta);
-        for (int i = c + 1 + t; i < pr; i += PT) P[c * pr + i] *= scl;
-        __syncthreads();
+        // d_j = v^T P_j over rows >= c (for j < c: the earlier reflectors)
         T d[W];
 #pragma unroll
         for (int j = 0; j < W; ++j) d[j] = T(0);
-        for (int i = c + t; i < pr; i += PT) {
-            const T vc = (i == c) ? T(1) : P[c * pr + i];
+        const int ib = t >= c ? t : t + ((c - t + PT - 1) / PT) * PT;   // first owned row >= c
+        for (int i = ib; i < pr; i += PT) {
+            T x[W];
+            load_row<T, W>(P + i * S, x);
+            const T vc = (i == c) ? T(1) : P[i * S + c] * scl;
 #pragma unroll
-            for (int j = 0; j < W; ++j) {
-                if (j == c || j >= nbe) continue;
-                T o;
-                if (j > c) o = P[j * pr + i];
-                else o = (i == j) ? T(1) : (i > j ? P[j * pr + i] : T(0));
-                d[j] += vc * o;
-            }
+            for (int j = 0; j < W; ++j) d[j] += vc * x[j];
         }
-        block_sum<T, W>(d, red);
-        for (int i = c + t; i < pr; i += PT) {
-            const T vc = (i == c) ? T(1) : P[c * pr + i];
-#pragma unroll
-            for (int j = 0; j < W; ++j)
-                if (j > c && j < nbe) P[j * pr + i] -= (tau * d[j]) * vc;
-        }
-        if (t < c) {
+        block_sum_n<T, W, 2 * W * (PT / 64)>(d, red, parity);
+        // compact-WY factor column c: T[:c, c] = -tau T[:c, :c] (V[:, :c]^T v_c)
+        if (t <= c && t < W) {
             T s2 = T(0);
 #pragma unroll
             for (int l = 0; l < W; ++l)
-                if (l >= t && l < c) s2 += Tfs[t][l] * d[l];
-            Tfs[t][c] = -tau * s2;
+                if (l < c) s2 += Tfs[t][l] * d[l];
+            Tfs[t][c] = (t < c) ? -tau * s2 : tau;
         }
-        if (t == c) { Tfs[c][c] = tau; X.tau[j0 + c] = tau; }
-        __syncthreads();
-        if (t == 0) P[c * pr + c] = beta;
-        __syncthreads();
-    }
-    // write back: R and reflectors to A, reflectors (unit lower) to the V workspace
-    for (int j = 0; j < nbe; ++j) {
-        T* col = Ab + (int64_t)(j0 + j) * q.p + j0;
-        T* vcol = X.V + (int64_t)(sub * W + j) * q.p + j0;
-        for (int i = t; i < pr; i += PT) {
-            const T x = P[j * pr + i];
-            col[i] = x;
-            if (j < nref) vcol[i] = (i == j) ? T(1) : (i > j ? x : T(0));
+        T cf[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) cf[j] = (j > c) ? tau * d[j] : T(0);
+#pragma unroll
+        for (int j = 0; j < 2 * W; ++j) nr[j] = T(0);
+        for (int i = ib; i < pr; i += PT) {
+            T x[W];
+            load_row<T, W>(P + i * S, x);
+            const T vc = (i == c) ? T(1) : P[i * S + c] * scl;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                x[j] -= cf[j] * vc;
+                nr[j] += (i > c) ? x[j] * x[j] : T(0);
+                nr[W + j] = (i == c + 1) ? x[j] : nr[W + j];
+            }
+            store_row<T, W>(P + i * S, x);
+            P[i * S + c] = (i == c) ? beta : vc;
         }
     }
-    if (t < W) {
-        lperm[t] = perm_loc[t];
-        if (t < nbe) gperm_old[t] = X.perm[j0 + t];
+    // write back (owned rows): R and reflectors to A, reflectors (unit lower) to V
+    T* Vb = X.V + (int64_t)(sub * W) * q.p + j0;
+    for (int i = t; i < pr; i += PT) {
+        T x[W];
+        load_row<T, W>(P + i * S, x);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            if (j < nbe) {
+                Ab[(int64_t)j * q.p + i] = x[j];
+                if (j < nref) Vb[(int64_t)j * q.p + i] = (i == j) ? T(1) : (i > j ? x[j] : T(0));
+            }
+        }
     }
+    if (t < nbe) gperm_old[t] = X.perm[j0 + t];
     __syncthreads();
     // rows above the sub-panel hold earlier R entries of these columns
+    T* Ac = A + q.offA + (int64_t)j0 * q.p;
     for (int i = t; i < j0; i += PT) {
         T tmp[W];
 #pragma unroll
-        for (int j = 0; j < W; ++j) tmp[j] = j < nbe ? Ab[i + (int64_t)(j0 + j) * q.p] : T(0);
+        for (int j = 0; j < W; ++j) tmp[j] = j < nbe ? Ac[i + (int64_t)j * q.p] : T(0);
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             if (j < nbe) {
                 T v = T(0);
+                const int src = lperm[j];
 #pragma unroll
-                for (int jj = 0; jj < W; ++jj)
-                    if (jj == lperm[j]) v = tmp[jj];
-                Ab[i + (int64_t)(j0 + j) * q.p] = v;
+                for (int jj = 0; jj < W; ++jj) v = (jj == src) ? tmp[jj] : v;
+                Ac[i + (int64_t)j * q.p] = v;
             }
         }
     }
     if (t < nbe) X.perm[j0 + t] = gperm_old[lperm[t]];
     for (int e = t; e < NB * NB; e += PT) {
         const int i = e % NB, j = e / NB;
-        X.Tf[e] = (i < nref && j < nref && i < W && j < W) ? Tfs[i][j] : T(0);
+        X.Tf[e] = (i < nref && j < nref && i < W && j < W) ? Tfs[i < W ? i : 0][j < W ? j : 0] : T(0);
     }
+    if (t < nref) X.tau[j0 + t] = Tfs[t][t];
     if (t == 0) {
         if (j0 == 0) X.r11[0] = r11;
         X.state[4] = nref;
@@ -654,8 +757,10 @@ static size_t allow_lds(const void* fn) {
 }  // namespace
 
 int qr_panel_width(int p) {
-    for (int w : {16, 8, 4, 2})
-        if ((size_t)w * p * 8 <= LDS_BUDGET) return w;
+    if ((size_t)panel_stride<double, 16>() * p * 8 <= LDS_BUDGET) return 16;
+    if ((size_t)panel_stride<double, 8>() * p * 8 <= LDS_BUDGET) return 8;
+    if ((size_t)panel_stride<double, 4>() * p * 8 <= LDS_BUDGET) return 4;
+    if ((size_t)panel_stride<double, 2>() * p * 8 <= LDS_BUDGET) return 2;
     return 0;
 }
 
@@ -686,9 +791,10 @@ void launch_qr_move(T* A, int* iaux, T* ws, const QRProblemDev* probs, int n_pro
 
 template <typename T, int W>
 static void panel_launch(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs,
-                         const int* plist, int n_list, int sub, double tol, size_t shm,
+                         const int* plist, int n_list, int sub, double tol, int max_p,
                          hipStream_t s) {
     auto kfn = qr_panel_kernel<T, W>;
+    const size_t shm = (size_t)max_p * panel_stride<T, W>() * sizeof(T);
     if (allow_lds((const void*)kfn) < shm) throw HipError("interpolation panel exceeds LDS");
     hipLaunchKernelGGL(kfn, dim3(n_list), dim3(PT), shm, s, A, aux, iaux, ws, probs, plist, sub, tol);
 }
@@ -699,11 +805,10 @@ void launch_qr_panel(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, 
                      hipStream_t s) {
     (void)outer;
     if (n_list <= 0) return;
-    const size_t shm = (size_t)nb_class * max_p * sizeof(T);
-    if (nb_class == 16) panel_launch<T, 16>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
-    else if (nb_class == 8) panel_launch<T, 8>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
-    else if (nb_class == 4) panel_launch<T, 4>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
-    else if (nb_class == 2) panel_launch<T, 2>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, shm, s);
+    if (nb_class == 16) panel_launch<T, 16>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
+    else if (nb_class == 8) panel_launch<T, 8>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
+    else if (nb_class == 4) panel_launch<T, 4>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
+    else if (nb_class == 2) panel_launch<T, 2>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
     else throw HipError("bad panel width");
 }
 
