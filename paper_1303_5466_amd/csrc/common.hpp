@@ -146,8 +146,8 @@ void launch_qr_norms(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_p
                      int max_k, hipStream_t s);
 int qr_panel_width(int p);
 template <typename T>
-void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
-                     const int* plist, int n_probs, int max_r, int max_k, hipStream_t s);
+void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
+                    const int* plist, int n_probs, int max_r, int step, hipStream_t s);
 
 // Gauss-Jordan pivot step (see gj kernels)
 template <typename T>

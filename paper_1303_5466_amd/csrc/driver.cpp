@@ -392,8 +392,34 @@ static void compute_T(Factor& f, const std::vector<int>& probs_ids,
         qr_flops += 2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r;
         qr_bytes += sizeof(T) * (2 * p * (k + r) + k * r);
     }
+    // problems grouped by the window after which they are complete
+    std::vector<std::vector<int>> done_after(S);
+    for (int i = 0; i < (int)qp.size(); ++i) done_after[(qp[i].k + QR_WIN - 1) / QR_WIN - 1].push_back(i);
+    // blocked back substitution per group: after solving 64-row block I in
+    // place, the rows above take  B[0:64I, :] -= R[0:64I, block I] X_I
+    std::vector<std::vector<GemmBatch<T>>> gsolve(S);
+    for (int sw = 0; sw < S; ++sw) {
+        int nblk = 0;
+        for (int i : done_after[sw]) nblk = std::max(nblk, (qp[i].k + 63) / 64);
+        gsolve[sw].resize(nblk);
+        for (int i : done_after[sw]) {
+            const QRProblemDev& q = qp[i];
+            const int nb_i = (q.k + 63) / 64;
+            T* Aq = Ab + q.offA;
+            for (int st = 0; st < nb_i; ++st) {
+                const int I = nb_i - 1 - st;
+                if (I == 0) continue;
+                const int i0 = I * 64, kb = std::min(64, q.k - i0);
+                gsolve[sw][st].add(gdesc<T>(i0, q.r, kb, Aq + (int64_t)i0 * q.p, q.p, 0,
+                                            Aq + (int64_t)q.k * q.p + i0, q.p, 0,
+                                            Aq + (int64_t)q.k * q.p, q.p, T(-1), T(1)));
+            }
+        }
+    }
     std::vector<GemmBatch<T>*> all;
     for (int sw = 0; sw < S; ++sw) { all.push_back(&g1[sw]); all.push_back(&gt[sw]); all.push_back(&g2[sw]); }
+    for (auto& v : gsolve)
+        for (auto& b : v) all.push_back(&b);
     upload_batches<T>(dgemm, all, s);
     ProfScope ps(RSD_PROF_INTERP, s, qr_flops, qr_bytes);
     launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
@@ -420,9 +446,6 @@ static void compute_T(Factor& f, const std::vector<int>& probs_ids,
         if (!lists[c].empty()) max_subs = std::max(max_subs, QR_WIN / widths[c]);
     }
     upload(dlist, flat, s);
-    // problems grouped by the window after which they are complete
-    std::vector<std::vector<int>> done_after(S);
-    for (int i = 0; i < (int)qp.size(); ++i) done_after[(qp[i].k + QR_WIN - 1) / QR_WIN - 1].push_back(i);
     std::vector<int> sflat;
     std::vector<int> soff(S + 1, 0);
     for (int sw = 0; sw < S; ++sw) {
@@ -456,18 +479,18 @@ static void compute_T(Factor& f, const std::vector<int>& probs_ids,
         if (ng > 0) {
             // back substitution for the problems finished in this window, off the
             // critical path of the remaining windows
-            int gr = 0, gk = 0;
-            for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
-                gr = std::max(gr, qp[sflat[g]].r);
-                gk = std::max(gk, qp[sflat[g]].k);
-            }
+            int gr = 0;
+            for (int g = soff[sw]; g < soff[sw + 1]; ++g) gr = std::max(gr, qp[sflat[g]].r);
             hipEvent_t done;
             RSD_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
             RSD_HIP(hipEventRecord(done, s));
             RSD_HIP(hipStreamWaitEvent(f.tsolve_stream, done, 0));
             f.tmp_events.push_back(done);
-            launch_qr_solve<T>(Ab, daux.as<T>(), diaux.as<int>(), Tbase<T>(f), dq.as<QRProblemDev>(),
-                               dsolve.as<int>() + soff[sw], ng, gr, gk, f.tsolve_stream);
+            for (int st = 0; st < (int)gsolve[sw].size(); ++st) {
+                launch_qr_trsm<T>(Ab, daux.as<T>(), diaux.as<int>(), Tbase<T>(f), dq.as<QRProblemDev>(),
+                                  dsolve.as<int>() + soff[sw], ng, gr, st, f.tsolve_stream);
+                gsolve[sw][st].run(f.tsolve_stream);
+            }
             for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
                 const int lev = prob_level[sflat[g]];
                 if (--level_pending[lev] == 0) RSD_HIP(hipEventRecord(f.level_ready[lev], f.tsolve_stream));

@@ -21,7 +21,8 @@
 //               reduce it and form the window's compact-WY factor, then
 //               C -= V (Tw^T W) as two more GEMMs (the grouped GEMM kernel);
 //   qr_norms    exact trailing norms for the next window.
-// qr_solve finally back-substitutes with R11 and scatters through Pi.
+// qr_trsm finally back-substitutes with R11, one 64-row block per call with
+// the rows above updated by grouped GEMMs in between, and scatters through Pi.
 #include <map>
 #include <mutex>
 
@@ -670,70 +671,48 @@ __global__ void __launch_bounds__(256) qr_norms_kernel(T* __restrict__ A, T* __r
 }
 
 // R11 X = (Q^T K(Z, X^rs))[0:rank, :], then T[perm[i], :] = X[i, :] with zero
-// rows for truncated columns.  Blocked back substitution from the bottom: a
-// 64-row diagonal block of R is staged in LDS and solved by one wave per
-// right-hand side, then every row above is updated with that block's columns
-// (coalesced reads of R, all threads busy).
+// rows for truncated columns.  Blocked back substitution from the bottom, one
+// 64-row block per call: the block's right-hand sides (already updated by the
+// blocks below, in place in the K(Z, X^rs) columns) are solved against the
+// diagonal block of R staged in LDS, one wave per right-hand side and one
+// lane per row, and the solution rows are written both in place (for the
+// update of the rows above, a grouped GEMM between calls) and to T through
+// the pivot order.  Rows at or past the rank get zeros.
 template <typename T>
-__global__ void __launch_bounds__(256) qr_solve_kernel(T* __restrict__ A, T* __restrict__ aux,
-                                                        int* __restrict__ iaux, T* __restrict__ Tout,
-                                                        const QRProblemDev* __restrict__ probs,
-                                                        const int* __restrict__ plist,
-                                                        int cols_per_wg) {
-    extern __shared__ unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);               // rank x nc
+__global__ void __launch_bounds__(256) qr_trsm_kernel(T* __restrict__ A, T* __restrict__ aux,
+                                                       int* __restrict__ iaux, T* __restrict__ Tout,
+                                                       const QRProblemDev* __restrict__ probs,
+                                                       const int* __restrict__ plist, int step) {
     __shared__ T Rb[64][65];
-    __shared__ int cpb[64];
     const QRProblemDev q = probs[plist[blockIdx.y]];
+    const int nblk = (q.k + 63) / 64;
+    const int I = nblk - 1 - step;
+    if (I < 0) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + wave;
+    if (blockIdx.x * 4 >= q.r) return;
     Aux<T> X(aux, iaux, nullptr, q);
     const int rank = X.state[0] < 0 ? q.k : X.state[0];
-    const int c0 = blockIdx.x * cols_per_wg;
-    if (c0 >= q.r) return;
-    const int nc = min(cols_per_wg, q.r - c0);
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int i0 = I * 64, nb = min(64, q.k - i0);
     const T* Ab = A + q.offA;
-    for (int c = 0; c < nc; ++c) {
-        const T* col = Ab + (int64_t)(q.k + c0 + c) * q.p;
-        for (int i = t; i < rank; i += 256) xs[c * rank + i] = col[i];
-    }
-    for (int i1 = rank; i1 > 0; i1 -= 64) {
-        const int i0 = max(0, i1 - 64), nb = i1 - i0;
-        __syncthreads();
-        if (t < nb) cpb[t] = i0 + t;
-        __syncthreads();
-        for (int e = t; e < 64 * 64; e += 256) {
-            const int r = e & 63, c = e >> 6;
-            Rb[r][c] = (r < nb && c < nb) ? Ab[(i0 + r) + (int64_t)cpb[c] * q.p] : T(0);
-        }
-        __syncthreads();
-        // triangular solve of the block: wave w handles right-hand sides w, w+4, ...
-        for (int c = wave; c < nc; c += 4) {
-            T* xc = xs + c * rank + i0;
-            T xv = lane < nb ? xc[lane] : T(0);
-            for (int i = nb - 1; i >= 0; --i) {
-                const T xi = read_lane(xv, i) / Rb[i][i];
-                if (lane < i) xv -= xi * Rb[lane][i];
-                if (lane == i) xv = xi;
-            }
-            if (lane < nb) xc[lane] = xv;
-        }
-        __syncthreads();
-        // rows above: x[0:i0] -= R[0:i0, block] x[block]
-        for (int r = t; r < i0; r += 256) {
-            T acc[8];
-            for (int c = 0; c < nc; ++c) acc[c] = T(0);
-            for (int j = 0; j < nb; ++j) {
-                const T rv = Ab[r + (int64_t)cpb[j] * q.p];
-                for (int c = 0; c < nc; ++c) acc[c] += rv * xs[c * rank + i0 + j];
-            }
-            for (int c = 0; c < nc; ++c) xs[c * rank + r] -= acc[c];
-        }
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        Rb[r][c] = (r < nb && c < nb) ? Ab[(i0 + r) + (int64_t)(i0 + c) * q.p] : T(0);
     }
     __syncthreads();
-    T* To = Tout + q.offT;
-    for (int c = 0; c < nc; ++c)
-        for (int i = t; i < q.k; i += 256)
-            To[X.perm[i] + (int64_t)(c0 + c) * q.k] = i < rank ? xs[c * rank + i] : T(0);
+    if (col >= q.r) return;
+    T* xc = A + q.offA + (int64_t)(q.k + col) * q.p + i0;
+    T xv = (lane < nb && i0 + lane < rank) ? xc[lane] : T(0);
+    const int top = min(nb, rank - i0);       // rows of the block inside the rank
+    for (int i = top - 1; i >= 0; --i) {
+        const T xi = read_lane(xv, i) / Rb[i][i];
+        if (lane < i) xv -= xi * Rb[lane][i];
+        if (lane == i) xv = xi;
+    }
+    if (lane < nb) {
+        xc[lane] = xv;
+        Tout[q.offT + X.perm[i0 + lane] + (int64_t)col * q.k] = xv;
+    }
 }
 
 constexpr size_t LDS_BUDGET = 150 * 1024;
@@ -844,16 +823,11 @@ void launch_qr_norms(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_p
 }
 
 template <typename T>
-void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
-                     const int* plist, int n_probs, int max_r, int max_k, hipStream_t s) {
+void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
+                    const int* plist, int n_probs, int max_r, int step, hipStream_t s) {
     if (n_probs <= 0 || max_r <= 0) return;
-    const size_t budget = allow_lds((const void*)qr_solve_kernel<T>);
-    int cols = (int)(budget / (sizeof(T) * (size_t)(max_k > 0 ? max_k : 1)));
-    if (cols > 8) cols = 8;
-    if (cols < 1) throw HipError("interpolation problem too large for the solve kernel");
-    const size_t shm = sizeof(T) * (size_t)max_k * cols;
-    hipLaunchKernelGGL(qr_solve_kernel<T>, dim3((max_r + cols - 1) / cols, n_probs), dim3(256), shm,
-                       s, A, aux, iaux, Tout, probs, plist, cols);
+    hipLaunchKernelGGL(qr_trsm_kernel<T>, dim3((max_r + 3) / 4, n_probs), dim3(256), 0, s, A, aux,
+                       iaux, Tout, probs, plist, step);
 }
 
 #define INST(T)                                                                                   \
@@ -869,8 +843,8 @@ void launch_qr_solve(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs
                                     hipStream_t);                                                 \
     template void launch_qr_norms<T>(T*, T*, int*, const QRProblemDev*, int, int, int,             \
                                      hipStream_t);                                                \
-    template void launch_qr_solve<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,  \
-                                     int, hipStream_t);
+    template void launch_qr_trsm<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,   \
+                                    int, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
