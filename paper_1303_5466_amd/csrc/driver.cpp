@@ -253,10 +253,9 @@ struct Factor {
         d_level_ids, d_err, d_table;
     std::vector<int> level_id_off;
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
-    hipStream_t qr_stream = nullptr;            // interpolation problems run here
-    hipStream_t tsolve_stream = nullptr;        // their back substitutions
+    hipStream_t qr_stream[2] = {nullptr, nullptr};   // interpolation chains run here
+    hipStream_t tsolve_stream = nullptr;             // their back substitutions
     std::vector<hipEvent_t> tmp_events;
-    std::vector<hipEvent_t> level_ready;        // T of every box type of a level solved
     std::vector<std::unique_ptr<DevBuf>> scratch;   // freed after the build
     std::vector<LevelExec<double>> L64;
     std::vector<LevelExec<float>> L32;
@@ -266,9 +265,9 @@ struct Factor {
     rsd_factor_stats stats{};
     ~Factor() {
         solve_plans.clear();
-        for (auto e : level_ready) (void)hipEventDestroy(e);
         for (auto e : tmp_events) (void)hipEventDestroy(e);
-        if (qr_stream) (void)hipStreamDestroy(qr_stream);
+        for (auto q : qr_stream)
+            if (q) (void)hipStreamDestroy(q);
         if (tsolve_stream) (void)hipStreamDestroy(tsolve_stream);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -289,216 +288,246 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 // ----------------------------------------------------------------------------
 // interpolation matrices for every box type (one problem per layout)
 // ----------------------------------------------------------------------------
+// One chain of interpolation problems: every problem of the chain advances
+// window by window through the same launches on the chain's stream, and the
+// problems finished after a window get their back substitution on the
+// factor's solve stream.  Problems of different sub-panel widths form
+// separate chains on separate streams, so a wide chain does not wait for the
+// narrow sub-panels of the largest boxes.
 template <typename T>
-static void compute_T(Factor& f, const std::vector<int>& probs_ids,
-                      const std::vector<int>& prob_level, std::vector<int>& level_pending,
-                      hipStream_t s, const std::function<void()>& on_progress) {
-    Plan& P = f.plan;
-    if (probs_ids.empty()) return;
+struct QRChain {
+    Factor* f = nullptr;
+    hipStream_t s = nullptr;
     std::vector<QRProblemDev> qp;
-    std::vector<int64_t> offA;
-    std::vector<int> pof, kof, rof, zoff, xoff, zu, zv;
-    int64_t A_el = 0, aux_el = 0, iaux_el = 0, ws_el = 0;
-    int max_pn = 0, max_k = 0, max_r = 0, max_n = 0, max_nch = 0, S = 0;
-    for (int id : probs_ids) {
-        const IDProblem& I = P.idps[id];
-        QRProblemDev q;
-        q.p = I.p; q.k = I.k; q.r = I.r;
-        q.nb = qr_panel_width(I.p);
-        if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
-        const int n = I.k + I.r;
-        const int nch = (I.p + QR_RC - 1) / QR_RC;
-        q.offA = A_el;
-        q.offT = f.hlayouts[I.layout].offT;
-        q.offAux = aux_el;
-        q.offIaux = iaux_el;
-        q.offV = ws_el;
-        q.offTmp = q.offV + (int64_t)I.p * QR_WIN;
-        q.offW = q.offTmp + (int64_t)I.p * 2 * QR_WIN;
-        q.offWs = q.offW + (int64_t)nch * QR_WIN * (QR_WIN + n);
-        ws_el = q.offWs + (int64_t)QR_WIN * (QR_WIN + n);
-        A_el += (int64_t)I.p * n;
-        aux_el += 2 * I.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
-        iaux_el += I.k + 8 + 4 * QR_WIN;
-        qp.push_back(q);
-        offA.push_back(q.offA);
-        pof.push_back(I.p); kof.push_back(I.k); rof.push_back(I.r);
-        zoff.push_back((int)zu.size());
-        zu.insert(zu.end(), I.zu.begin(), I.zu.end());
-        zv.insert(zv.end(), I.zv.begin(), I.zv.end());
-        xoff.push_back(f.hlayouts[I.layout].off_uv);
-        max_pn = std::max(max_pn, I.p * n);
-        max_k = std::max(max_k, I.k);
-        max_r = std::max(max_r, I.r);
-        max_n = std::max(max_n, n);
-        max_nch = std::max(max_nch, nch);
-        S = std::max(S, (I.k + QR_WIN - 1) / QR_WIN);
-    }
-    DevBuf &dA = f.tmp(), &daux = f.tmp(), &diaux = f.tmp(), &dws = f.tmp(), &dq = f.tmp(),
-           &doffA = f.tmp(), &dp = f.tmp(), &dk = f.tmp(), &dr = f.tmp(), &dzo = f.tmp(),
-           &dzu = f.tmp(), &dzv = f.tmp(), &dxo = f.tmp(), &dlist = f.tmp(), &dsolve = f.tmp(),
-           &dgemm = f.tmp();
-    dA.alloc(A_el * sizeof(T));
-    daux.alloc(aux_el * sizeof(T));
-    diaux.alloc(iaux_el * sizeof(int));
-    dws.alloc(ws_el * sizeof(T));
-    upload(dq, qp, s); upload(doffA, offA, s); upload(dp, pof, s); upload(dk, kof, s);
-    upload(dr, rof, s); upload(dzo, zoff, s); upload(dzu, zu, s); upload(dzv, zv, s);
-    upload(dxo, xoff, s);
-    // trailing-update products of every window, guarded by the problem's skip flag
-    T* Ab = dA.as<T>();
-    T* W = dws.as<T>();
-    std::vector<GemmBatch<T>> g1(S), gt(S), g2(S);
-    double qr_flops = 0, qr_bytes = 0;
-    for (size_t i = 0; i < qp.size(); ++i) {
-        const QRProblemDev& q = qp[i];
-        const int n = q.k + q.r;
-        const int* guard = diaux.as<int>() + q.offIaux + q.k + 1;
-        T* V = W + q.offV;
-        T* Wp = W + q.offW;
-        T* Ws = W + q.offWs;
-        T* Tw = daux.as<T>() + q.offAux + 2 * q.k + QR_NB * QR_NB;
-        const int64_t chunk = (int64_t)QR_WIN * (QR_WIN + n);
-        for (int sw = 0; sw * QR_WIN < q.k; ++sw) {
-            const int J0 = sw * QR_WIN, WO = std::min(QR_WIN, q.k - J0);
-            const int ntrail = n - J0 - WO, pr = q.p - J0;
-            const int nch = (pr + QR_RC - 1) / QR_RC;
-            for (int c = 0; c < nch; ++c) {
-                const int r0 = J0 + c * QR_RC, kr = std::min(QR_RC, q.p - r0);
-                GemmDesc<T> da = gdesc<T>(QR_WIN, QR_WIN, kr, V + r0, q.p, 1, V + r0, q.p, 0,
-                                          Wp + c * chunk, QR_WIN, T(1), T(0));
-                da.guard = guard;
-                g1[sw].add(da);
+    std::vector<int> prob_level;
+    int S = 0, np = 0, max_k = 0, max_n = 0, max_nch = 0, max_subs = 0;
+    DevBuf *dA = nullptr, *daux = nullptr, *diaux = nullptr, *dws = nullptr, *dq = nullptr,
+           *dlist = nullptr, *dsolve = nullptr;
+    std::vector<GemmBatch<T>> g1, gt, g2;
+    std::vector<std::vector<GemmBatch<T>>> gsolve;
+    std::vector<int> lists[4];
+    int off[4] = {0, 0, 0, 0}, maxp[4] = {0, 0, 0, 0};
+    std::vector<int> sflat, soff;
+    double qr_tol = 0;
+    double flops = 0, bytes = 0;
+
+    void setup(Factor& fac, const std::vector<int>& probs_ids, const std::vector<int>& levels,
+               hipStream_t stream) {
+        f = &fac;
+        s = stream;
+        Plan& P = f->plan;
+        std::vector<int64_t> offA;
+        std::vector<int> pof, kof, rof, zoff, xoff, zu, zv;
+        int64_t A_el = 0, aux_el = 0, iaux_el = 0, ws_el = 0;
+        int max_pn = 0, max_r = 0;
+        prob_level = levels;
+        for (int id : probs_ids) {
+            const IDProblem& I = P.idps[id];
+            QRProblemDev q;
+            q.p = I.p; q.k = I.k; q.r = I.r;
+            q.nb = qr_panel_width(I.p);
+            if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
+            const int n = I.k + I.r;
+            const int nch = (I.p + QR_RC - 1) / QR_RC;
+            q.offA = A_el;
+            q.offT = f->hlayouts[I.layout].offT;
+            q.offAux = aux_el;
+            q.offIaux = iaux_el;
+            q.offV = ws_el;
+            q.offTmp = q.offV + (int64_t)I.p * QR_WIN;
+            q.offW = q.offTmp + (int64_t)I.p * 2 * QR_WIN;
+            q.offWs = q.offW + (int64_t)nch * QR_WIN * (QR_WIN + n);
+            ws_el = q.offWs + (int64_t)QR_WIN * (QR_WIN + n);
+            A_el += (int64_t)I.p * n;
+            aux_el += 2 * I.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
+            iaux_el += I.k + 8 + 4 * QR_WIN;
+            qp.push_back(q);
+            offA.push_back(q.offA);
+            pof.push_back(I.p); kof.push_back(I.k); rof.push_back(I.r);
+            zoff.push_back((int)zu.size());
+            zu.insert(zu.end(), I.zu.begin(), I.zu.end());
+            zv.insert(zv.end(), I.zv.begin(), I.zv.end());
+            xoff.push_back(f->hlayouts[I.layout].off_uv);
+            max_pn = std::max(max_pn, I.p * n);
+            max_k = std::max(max_k, I.k);
+            max_r = std::max(max_r, I.r);
+            max_n = std::max(max_n, n);
+            max_nch = std::max(max_nch, nch);
+            S = std::max(S, (I.k + QR_WIN - 1) / QR_WIN);
+        }
+        np = (int)qp.size();
+        DevBuf &doffA = f->tmp(), &dp = f->tmp(), &dk = f->tmp(), &dr = f->tmp(), &dzo = f->tmp(),
+               &dzu = f->tmp(), &dzv = f->tmp(), &dxo = f->tmp(), &dgemm = f->tmp();
+        dA = &f->tmp(); daux = &f->tmp(); diaux = &f->tmp(); dws = &f->tmp(); dq = &f->tmp();
+        dlist = &f->tmp(); dsolve = &f->tmp();
+        dA->alloc(A_el * sizeof(T));
+        daux->alloc(aux_el * sizeof(T));
+        diaux->alloc(iaux_el * sizeof(int));
+        dws->alloc(ws_el * sizeof(T));
+        upload(*dq, qp, s); upload(doffA, offA, s); upload(dp, pof, s); upload(dk, kof, s);
+        upload(dr, rof, s); upload(dzo, zoff, s); upload(dzu, zu, s); upload(dzv, zv, s);
+        upload(dxo, xoff, s);
+        // trailing-update products of every window, guarded by the problem's skip flag
+        T* Ab = dA->as<T>();
+        T* W = dws->as<T>();
+        g1.resize(S); gt.resize(S); g2.resize(S);
+        for (size_t i = 0; i < qp.size(); ++i) {
+            const QRProblemDev& q = qp[i];
+            const int n = q.k + q.r;
+            const int* guard = diaux->as<int>() + q.offIaux + q.k + 1;
+            T* V = W + q.offV;
+            T* Wp = W + q.offW;
+            T* Ws = W + q.offWs;
+            T* Tw = daux->as<T>() + q.offAux + 2 * q.k + QR_NB * QR_NB;
+            const int64_t chunk = (int64_t)QR_WIN * (QR_WIN + n);
+            for (int sw = 0; sw * QR_WIN < q.k; ++sw) {
+                const int J0 = sw * QR_WIN, WO = std::min(QR_WIN, q.k - J0);
+                const int ntrail = n - J0 - WO, pr = q.p - J0;
+                const int nch = (pr + QR_RC - 1) / QR_RC;
+                for (int c = 0; c < nch; ++c) {
+                    const int r0 = J0 + c * QR_RC, kr = std::min(QR_RC, q.p - r0);
+                    GemmDesc<T> da = gdesc<T>(QR_WIN, QR_WIN, kr, V + r0, q.p, 1, V + r0, q.p, 0,
+                                              Wp + c * chunk, QR_WIN, T(1), T(0));
+                    da.guard = guard;
+                    g1[sw].add(da);
+                    if (ntrail > 0) {
+                        GemmDesc<T> db = gdesc<T>(QR_WIN, ntrail, kr, V + r0, q.p, 1,
+                                                  Ab + q.offA + r0 + (int64_t)(J0 + WO) * q.p, q.p, 0,
+                                                  Wp + c * chunk + QR_WIN * QR_WIN, QR_WIN, T(1), T(0));
+                        db.guard = guard;
+                        g1[sw].add(db);
+                    }
+                }
                 if (ntrail > 0) {
-                    GemmDesc<T> db = gdesc<T>(QR_WIN, ntrail, kr, V + r0, q.p, 1,
-                                              Ab + q.offA + r0 + (int64_t)(J0 + WO) * q.p, q.p, 0,
-                                              Wp + c * chunk + QR_WIN * QR_WIN, QR_WIN, T(1), T(0));
-                    db.guard = guard;
-                    g1[sw].add(db);
+                    GemmDesc<T> dt = gdesc<T>(QR_WIN, ntrail, QR_WIN, Tw, QR_WIN, 1, Ws + QR_WIN * QR_WIN,
+                                              QR_WIN, 0, Wp, QR_WIN, T(1), T(0));
+                    dt.guard = guard;
+                    gt[sw].add(dt);
+                    GemmDesc<T> d2 = gdesc<T>(pr, ntrail, QR_WIN, V + J0, q.p, 0, Wp, QR_WIN, 0,
+                                              Ab + q.offA + J0 + (int64_t)(J0 + WO) * q.p, q.p, T(-1), T(1));
+                    d2.guard = guard;
+                    g2[sw].add(d2);
                 }
             }
-            if (ntrail > 0) {
-                GemmDesc<T> dt = gdesc<T>(QR_WIN, ntrail, QR_WIN, Tw, QR_WIN, 1, Ws + QR_WIN * QR_WIN,
-                                          QR_WIN, 0, Wp, QR_WIN, T(1), T(0));
-                dt.guard = guard;
-                gt[sw].add(dt);
-                GemmDesc<T> d2 = gdesc<T>(pr, ntrail, QR_WIN, V + J0, q.p, 0, Wp, QR_WIN, 0,
-                                          Ab + q.offA + J0 + (int64_t)(J0 + WO) * q.p, q.p, T(-1), T(1));
-                d2.guard = guard;
-                g2[sw].add(d2);
+            const double p = q.p, k = q.k, r = q.r;
+            flops += 2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r;
+            bytes += sizeof(T) * (2 * p * (k + r) + k * r);
+        }
+        // problems grouped by the window after which they are complete
+        std::vector<std::vector<int>> done_after(S);
+        for (int i = 0; i < np; ++i) done_after[(qp[i].k + QR_WIN - 1) / QR_WIN - 1].push_back(i);
+        // blocked back substitution per group: after solving 64-row block I in
+        // place, the rows above take  B[0:64I, :] -= R[0:64I, block I] X_I
+        gsolve.resize(S);
+        for (int sw = 0; sw < S; ++sw) {
+            int nblk = 0;
+            for (int i : done_after[sw]) nblk = std::max(nblk, (qp[i].k + 63) / 64);
+            gsolve[sw].resize(nblk);
+            for (int i : done_after[sw]) {
+                const QRProblemDev& q = qp[i];
+                const int nb_i = (q.k + 63) / 64;
+                T* Aq = Ab + q.offA;
+                for (int st = 0; st < nb_i; ++st) {
+                    const int I = nb_i - 1 - st;
+                    if (I == 0) continue;
+                    const int i0 = I * 64, kb = std::min(64, q.k - i0);
+                    gsolve[sw][st].add(gdesc<T>(i0, q.r, kb, Aq + (int64_t)i0 * q.p, q.p, 0,
+                                                Aq + (int64_t)q.k * q.p + i0, q.p, 0,
+                                                Aq + (int64_t)q.k * q.p, q.p, T(-1), T(1)));
+                }
             }
         }
-        const double p = q.p, k = q.k, r = q.r;
-        qr_flops += 2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r;
-        qr_bytes += sizeof(T) * (2 * p * (k + r) + k * r);
-    }
-    // problems grouped by the window after which they are complete
-    std::vector<std::vector<int>> done_after(S);
-    for (int i = 0; i < (int)qp.size(); ++i) done_after[(qp[i].k + QR_WIN - 1) / QR_WIN - 1].push_back(i);
-    // blocked back substitution per group: after solving 64-row block I in
-    // place, the rows above take  B[0:64I, :] -= R[0:64I, block I] X_I
-    std::vector<std::vector<GemmBatch<T>>> gsolve(S);
-    for (int sw = 0; sw < S; ++sw) {
-        int nblk = 0;
-        for (int i : done_after[sw]) nblk = std::max(nblk, (qp[i].k + 63) / 64);
-        gsolve[sw].resize(nblk);
-        for (int i : done_after[sw]) {
-            const QRProblemDev& q = qp[i];
-            const int nb_i = (q.k + 63) / 64;
-            T* Aq = Ab + q.offA;
-            for (int st = 0; st < nb_i; ++st) {
-                const int I = nb_i - 1 - st;
-                if (I == 0) continue;
-                const int i0 = I * 64, kb = std::min(64, q.k - i0);
-                gsolve[sw][st].add(gdesc<T>(i0, q.r, kb, Aq + (int64_t)i0 * q.p, q.p, 0,
-                                            Aq + (int64_t)q.k * q.p + i0, q.p, 0,
-                                            Aq + (int64_t)q.k * q.p, q.p, T(-1), T(1)));
-            }
+        std::vector<GemmBatch<T>*> all;
+        for (int sw = 0; sw < S; ++sw) { all.push_back(&g1[sw]); all.push_back(&gt[sw]); all.push_back(&g2[sw]); }
+        for (auto& v : gsolve)
+            for (auto& b : v) all.push_back(&b);
+        upload_batches<T>(dgemm, all, s);
+        // sub-panel width classes
+        const int widths[4] = {16, 8, 4, 2};
+        for (int i = 0; i < np; ++i) {
+            int c = 0;
+            while (widths[c] != qp[i].nb) ++c;
+            lists[c].push_back(i);
+            maxp[c] = std::max(maxp[c], qp[i].p);
         }
+        std::vector<int> flat;
+        for (int c = 0; c < 4; ++c) {
+            off[c] = (int)flat.size();
+            flat.insert(flat.end(), lists[c].begin(), lists[c].end());
+            if (!lists[c].empty()) max_subs = std::max(max_subs, QR_WIN / widths[c]);
+        }
+        upload(*dlist, flat, s);
+        soff.assign(S + 1, 0);
+        for (int sw = 0; sw < S; ++sw) {
+            soff[sw] = (int)sflat.size();
+            sflat.insert(sflat.end(), done_after[sw].begin(), done_after[sw].end());
+        }
+        soff[S] = (int)sflat.size();
+        upload(*dsolve, sflat, s);
+        // a float32 factor cannot resolve pivots below its rounding level
+        qr_tol = std::is_same<T, float>::value ? std::max(f->tol, 1e-6) : f->tol;
+        launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
+                               dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
+                               dxo.as<int>(), f->d_lu.as<int>(), f->d_lv.as<int>(), np,
+                               max_pn, f->kd, s);
+        launch_qr_init<T>(Ab, daux->as<T>(), diaux->as<int>(), dq->as<QRProblemDev>(), np, max_k, s);
     }
-    std::vector<GemmBatch<T>*> all;
-    for (int sw = 0; sw < S; ++sw) { all.push_back(&g1[sw]); all.push_back(&gt[sw]); all.push_back(&g2[sw]); }
-    for (auto& v : gsolve)
-        for (auto& b : v) all.push_back(&b);
-    upload_batches<T>(dgemm, all, s);
-    ProfScope ps(RSD_PROF_INTERP, s, qr_flops, qr_bytes);
-    launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
-                           dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
-                           dxo.as<int>(), f.d_lu.as<int>(), f.d_lv.as<int>(), (int)qp.size(),
-                           max_pn, f.kd, s);
-    launch_qr_init<T>(Ab, daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(), (int)qp.size(), max_k, s);
-    // sub-panel width classes
-    const int widths[4] = {16, 8, 4, 2};
-    std::vector<int> lists[4];
-    int maxp[4] = {0, 0, 0, 0};
-    for (int i = 0; i < (int)qp.size(); ++i) {
-        int c = 0;
-        while (widths[c] != qp[i].nb) ++c;
-        lists[c].push_back(i);
-        maxp[c] = std::max(maxp[c], qp[i].p);
-    }
-    std::vector<int> flat;
-    int off[4];
-    int max_subs = 0;
-    for (int c = 0; c < 4; ++c) {
-        off[c] = (int)flat.size();
-        flat.insert(flat.end(), lists[c].begin(), lists[c].end());
-        if (!lists[c].empty()) max_subs = std::max(max_subs, QR_WIN / widths[c]);
-    }
-    upload(dlist, flat, s);
-    std::vector<int> sflat;
-    std::vector<int> soff(S + 1, 0);
-    for (int sw = 0; sw < S; ++sw) {
-        soff[sw] = (int)sflat.size();
-        sflat.insert(sflat.end(), done_after[sw].begin(), done_after[sw].end());
-    }
-    soff[S] = (int)sflat.size();
-    upload(dsolve, sflat, s);
-    // a float32 factor cannot resolve pivots below its rounding level
-    const double qr_tol = std::is_same<T, float>::value ? std::max(f.tol, 1e-6) : f.tol;
-    const int np = (int)qp.size();
-    for (int sw = 0; sw < S; ++sw) {
-        launch_qr_select<T>(Ab, daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(), np, sw, max_k, s);
-        launch_qr_move<T>(Ab, diaux.as<int>(), W, dq.as<QRProblemDev>(), np, 0, s);
-        launch_qr_move<T>(Ab, diaux.as<int>(), W, dq.as<QRProblemDev>(), np, 1, s);
+
+    // Enqueues window sw; returns the levels whose problems all finished
+    // (their back substitutions are enqueued on the solve stream, followed
+    // by an event recorded into level_waits).
+    void window(int sw, std::vector<int>& level_pending,
+                std::vector<std::vector<hipEvent_t>>& level_waits) {
+        if (sw >= S) return;
+        T* Ab = dA->as<T>();
+        T* W = dws->as<T>();
+        T* aux = daux->as<T>();
+        int* iaux = diaux->as<int>();
+        const QRProblemDev* q = dq->as<QRProblemDev>();
+        const int widths[4] = {16, 8, 4, 2};
+        launch_qr_select<T>(Ab, aux, iaux, W, q, np, sw, max_k, s);
+        launch_qr_move<T>(Ab, iaux, W, q, np, 0, s);
+        launch_qr_move<T>(Ab, iaux, W, q, np, 1, s);
         for (int sub = 0; sub < max_subs; ++sub)
             for (int c = 0; c < 4; ++c) {
                 if (lists[c].empty() || sub * widths[c] >= QR_WIN) continue;
-                launch_qr_panel<T>(Ab, daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(),
-                                   dlist.as<int>() + off[c], (int)lists[c].size(), widths[c], maxp[c],
-                                   sw, sub, qr_tol, s);
-                launch_qr_inner<T>(Ab, daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(),
-                                   dlist.as<int>() + off[c], (int)lists[c].size(), widths[c], sw, sub, s);
+                launch_qr_panel<T>(Ab, aux, iaux, W, q, dlist->as<int>() + off[c], (int)lists[c].size(),
+                                   widths[c], maxp[c], sw, sub, qr_tol, s);
+                launch_qr_inner<T>(Ab, aux, iaux, W, q, dlist->as<int>() + off[c], (int)lists[c].size(),
+                                   widths[c], sw, sub, s);
             }
         g1[sw].run(s);
-        launch_qr_wsum<T>(daux.as<T>(), diaux.as<int>(), W, dq.as<QRProblemDev>(), np, sw, max_n, max_nch, s);
+        launch_qr_wsum<T>(aux, iaux, W, q, np, sw, max_n, max_nch, s);
         gt[sw].run(s);
         g2[sw].run(s);
-        launch_qr_norms<T>(Ab, daux.as<T>(), diaux.as<int>(), dq.as<QRProblemDev>(), np, sw, max_k, s);
+        launch_qr_norms<T>(Ab, aux, iaux, q, np, sw, max_k, s);
         const int ng = soff[sw + 1] - soff[sw];
-        if (ng > 0) {
-            // back substitution for the problems finished in this window, off the
-            // critical path of the remaining windows
-            int gr = 0;
-            for (int g = soff[sw]; g < soff[sw + 1]; ++g) gr = std::max(gr, qp[sflat[g]].r);
-            hipEvent_t done;
-            RSD_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-            RSD_HIP(hipEventRecord(done, s));
-            RSD_HIP(hipStreamWaitEvent(f.tsolve_stream, done, 0));
-            f.tmp_events.push_back(done);
-            for (int st = 0; st < (int)gsolve[sw].size(); ++st) {
-                launch_qr_trsm<T>(Ab, daux.as<T>(), diaux.as<int>(), Tbase<T>(f), dq.as<QRProblemDev>(),
-                                  dsolve.as<int>() + soff[sw], ng, gr, st, f.tsolve_stream);
-                gsolve[sw][st].run(f.tsolve_stream);
-            }
-            for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
-                const int lev = prob_level[sflat[g]];
-                if (--level_pending[lev] == 0) RSD_HIP(hipEventRecord(f.level_ready[lev], f.tsolve_stream));
-            }
-            on_progress();
+        if (ng == 0) return;
+        // back substitution for the problems finished in this window, off the
+        // critical path of the remaining windows
+        int gr = 0;
+        for (int g = soff[sw]; g < soff[sw + 1]; ++g) gr = std::max(gr, qp[sflat[g]].r);
+        hipStream_t ts = f->tsolve_stream;
+        hipEvent_t done;
+        RSD_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        RSD_HIP(hipEventRecord(done, s));
+        RSD_HIP(hipStreamWaitEvent(ts, done, 0));
+        f->tmp_events.push_back(done);
+        for (int st = 0; st < (int)gsolve[sw].size(); ++st) {
+            launch_qr_trsm<T>(Ab, aux, iaux, Tbase<T>(*f), q, dsolve->as<int>() + soff[sw], ng, gr, st, ts);
+            gsolve[sw][st].run(ts);
+        }
+        hipEvent_t solved;
+        RSD_HIP(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
+        RSD_HIP(hipEventRecord(solved, ts));
+        f->tmp_events.push_back(solved);
+        for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
+            const int lev = prob_level[sflat[g]];
+            if (level_waits[lev].empty() || level_waits[lev].back() != solved) level_waits[lev].push_back(solved);
+            --level_pending[lev];
         }
     }
-}
+};
 
 // ----------------------------------------------------------------------------
 // level plans
@@ -889,48 +918,71 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
     RSD_HIP(hipEventCreate(&e0));
     RSD_HIP(hipEventCreate(&e1));
     RSD_HIP(hipEventRecord(e0, s));
-    // interpolation problems on their own stream, overlapping the level pipeline
-    RSD_HIP(hipStreamCreateWithFlags(&f->qr_stream, hipStreamNonBlocking));
+    // interpolation problems on their own streams, overlapping the level pipeline
+    for (auto& q : f->qr_stream) RSD_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
     RSD_HIP(hipStreamCreateWithFlags(&f->tsolve_stream, hipStreamNonBlocking));
-    f->level_ready.resize(nlev, nullptr);
-    for (int t = 0; t < nlev; ++t) RSD_HIP(hipEventCreateWithFlags(&f->level_ready[t], hipEventDisableTiming));
     {
         hipEvent_t go;
         RSD_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
         RSD_HIP(hipEventRecord(go, s));
-        RSD_HIP(hipStreamWaitEvent(f->qr_stream, go, 0));
+        for (auto q : f->qr_stream) RSD_HIP(hipStreamWaitEvent(q, go, 0));
         RSD_HIP(hipStreamWaitEvent(f->tsolve_stream, go, 0));
         (void)hipEventDestroy(go);
     }
-    std::vector<int> p64, p32, l64, l32;
+    // chains: (precision, narrow sub-panels) -> problems; the narrow chain
+    // holds the boxes too tall for 16-column sub-panels
+    std::vector<int> cp[2][2], cl[2][2];
     std::vector<int> pending(nlev, 0);
     for (size_t li = 0; li < P.layouts.size(); ++li) {
         if (P.layouts[li].idp < 0) continue;
         const int lev = layout_level[li];
-        if (f->level_prec[lev]) { p32.push_back(P.layouts[li].idp); l32.push_back(lev); }
-        else { p64.push_back(P.layouts[li].idp); l64.push_back(lev); }
+        const int pr = f->level_prec[lev];
+        const int narrow = qr_panel_width(P.idps[P.layouts[li].idp].p) < 16 ? 1 : 0;
+        cp[pr][narrow].push_back(P.layouts[li].idp);
+        cl[pr][narrow].push_back(lev);
         ++pending[lev];
     }
-    for (int t = 0; t < nlev; ++t)
-        if (pending[t] == 0) RSD_HIP(hipEventRecord(f->level_ready[t], f->tsolve_stream));
+    std::vector<std::vector<hipEvent_t>> level_waits(nlev);
     // levels are enqueued as soon as the events of their box types exist, so the
     // level pipeline runs alongside the interpolation problems
     int next_level = 0;
     auto enqueue_ready = [&]() {
         while (next_level < nlev && pending[next_level] == 0) {
             const int t = next_level++;
-            RSD_HIP(hipStreamWaitEvent(s, f->level_ready[t], 0));
+            for (auto e : level_waits[t]) RSD_HIP(hipStreamWaitEvent(s, e, 0));
             if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
             else run_level<double>(*f, f->L64[exec_index[t]], s);
         }
     };
-    compute_T<double>(*f, p64, l64, pending, f->qr_stream, enqueue_ready);
-    compute_T<float>(*f, p32, l32, pending, f->qr_stream, enqueue_ready);
+    {
+        QRChain<double> c64[2];
+        QRChain<float> c32[2];
+        int S = 0;
+        for (int nw = 0; nw < 2; ++nw) {
+            if (!cp[0][nw].empty()) { c64[nw].setup(*f, cp[0][nw], cl[0][nw], f->qr_stream[nw]); S = std::max(S, c64[nw].S); }
+            if (!cp[1][nw].empty()) { c32[nw].setup(*f, cp[1][nw], cl[1][nw], f->qr_stream[nw]); S = std::max(S, c32[nw].S); }
+        }
+        ProfScope ps(RSD_PROF_INTERP, f->qr_stream[1], c64[0].flops + c64[1].flops + c32[0].flops + c32[1].flops,
+                     c64[0].bytes + c64[1].bytes + c32[0].bytes + c32[1].bytes);
+        for (int sw = 0; sw < S; ++sw) {
+            for (int nw = 0; nw < 2; ++nw) {
+                c32[nw].window(sw, pending, level_waits);
+                c64[nw].window(sw, pending, level_waits);
+            }
+            enqueue_ready();
+        }
+        // the interpolation profile ends when both chains have
+        hipEvent_t both;
+        RSD_HIP(hipEventCreateWithFlags(&both, hipEventDisableTiming));
+        RSD_HIP(hipEventRecord(both, f->qr_stream[0]));
+        RSD_HIP(hipStreamWaitEvent(f->qr_stream[1], both, 0));
+        f->tmp_events.push_back(both);
+    }
     enqueue_ready();
     if (next_level != nlev) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
     RSD_HIP(hipEventRecord(e1, s));
     RSD_HIP(hipStreamSynchronize(s));
-    RSD_HIP(hipStreamSynchronize(f->qr_stream));
+    for (auto q : f->qr_stream) RSD_HIP(hipStreamSynchronize(q));
     RSD_HIP(hipStreamSynchronize(f->tsolve_stream));
     f->scratch.clear();
     for (auto e : f->tmp_events) (void)hipEventDestroy(e);

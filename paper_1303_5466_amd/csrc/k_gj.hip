@@ -24,10 +24,23 @@ namespace {
 constexpr int GJ_NB = 64;
 constexpr int CHUNK = 64;
 
+// An empty asm statement the optimiser cannot look through: it keeps a
+// select between register-array elements from being rewritten as an indexed
+// load, which would move the array to scratch memory.
+__device__ inline void opaque(double& x) { asm("" : "+v"(x)); }
+__device__ inline void opaque(float& x) { asm("" : "+v"(x)); }
+
+template <typename T>
+__device__ inline T pick4(T v0, T v1, T v2, T v3, int k) {
+    opaque(v0); opaque(v1); opaque(v2); opaque(v3);
+    return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
+}
+
 // Inversion of the pivot block: thread t keeps the 4 x 4 tile (rows 4(t/16),
 // columns 4(t%16)) of P in registers; step c needs only pivot row c and pivot
 // column c, which their owners publish in a double-buffered LDS strip, so each
-// elimination step costs one barrier.
+// elimination step costs one barrier.  The step is straight-line code: every
+// element computes the generic update and selects the pivot-row/column forms.
 template <typename T>
 __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restrict__ descs, int step,
                                                         int nb, int* __restrict__ err) {
@@ -41,8 +54,8 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
     const int ri = 4 * (t >> 4), cj = 4 * (t & 15);
     __shared__ T Pi[GJ_NB][GJ_NB + 1];
     __shared__ T Xp[GJ_NB][CHUNK + 1];
-    __shared__ T rowb[2][GJ_NB];
-    __shared__ T colb[2][GJ_NB];
+    __shared__ __align__(16) T rowb[2][GJ_NB];
+    __shared__ __align__(16) T colb[2][GJ_NB];
     __shared__ int bad;
     const int pc0 = d.pcol + j0;
     T p[4][4];
@@ -78,30 +91,27 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         for (int b = 0; b < 4; ++b) pr[b] = rowb[buf][cj + b];
 #pragma unroll
         for (int a = 0; a < 4; ++a) pcv[a] = colb[buf][ri + a];
+        const int rc = c - ri, cc = c - cj;    // local row / column of the pivot (if in [0, 4))
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            const T prs = pr[b] * inv;
+            const T rowv = (cc == b) ? inv : prs;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int i = ri + a, j = cj + b;
-                T v;
-                if (i == c) v = (j == c) ? inv : pr[b] * inv;
-                else v = (j == c) ? -pcv[a] * inv : p[a][b] - pcv[a] * (pr[b] * inv);
-                p[a][b] = v;
+            for (int a = 0; a < 4; ++a) {
+                const T upd = p[a][b] - pcv[a] * prs;
+                const T oth = (cc == b) ? -pcv[a] * inv : upd;
+                p[a][b] = (rc == a) ? rowv : oth;
             }
+        }
         const int c1 = c + 1, nb2 = buf ^ 1;
         if (c1 < nbe) {
-            if (c1 >= ri && c1 < ri + 4)
+            const int r1 = c1 - ri, k1 = c1 - cj;
+            if (r1 >= 0 && r1 < 4)
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    if (ri + a == c1)
+                for (int b = 0; b < 4; ++b) rowb[nb2][cj + b] = pick4(p[0][b], p[1][b], p[2][b], p[3][b], r1);
+            if (k1 >= 0 && k1 < 4)
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) rowb[nb2][cj + b] = p[a][b];
-            if (c1 >= cj && c1 < cj + 4)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    if (cj + b == c1)
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) colb[nb2][ri + a] = p[a][b];
+                for (int a = 0; a < 4; ++a) colb[nb2][ri + a] = pick4(p[a][0], p[a][1], p[a][2], p[a][3], k1);
         }
         __syncthreads();
     }
@@ -118,7 +128,9 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-        for (int s2 = 0; s2 < nbe; ++s2) {
+        // entries past nbe are zero in both operands, so the loop runs to 64
+#pragma unroll 8
+        for (int s2 = 0; s2 < GJ_NB; ++s2) {
             T pa[4], xb[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) pa[a] = Pi[ri + a][s2];
@@ -144,18 +156,29 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         }
     }
     // SC = old pivot columns with -I in the pivot rows; rows split over the
-    // workgroups of this box (nobody writes those columns in this kernel)
+    // workgroups of this box (nobody writes those columns in this kernel).
+    // Unrolled so that eight independent loads are in flight per thread.
     const int nwg = (d.ncols + CHUNK - 1) / CHUNK;
     const int rows_per = (d.n + nwg - 1) / nwg;
     const int r0 = blockIdx.x * rows_per, r1 = min(d.n, r0 + rows_per);
-    for (int q2 = 0; q2 < nbe; ++q2) {
-        const T* src = d.X + (int64_t)(pc0 + q2) * d.ld;
-        T* dst = d.SC + (int64_t)q2 * d.n;
-        for (int i = r0 + t; i < r1; i += 256) {
-            T v;
-            if (i >= j0 && i < j0 + nbe) v = (i - j0 == q2) ? T(-1) : T(0);
-            else v = src[i];
-            dst[i] = v;
+    const int nr = max(0, r1 - r0);
+    const int tot = nr * nbe;
+    for (int e0 = 0; e0 < tot; e0 += 8 * 256) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256 + t;
+            const int q2 = e / max(nr, 1), i = r0 + (e - q2 * nr);
+            v[u] = (e < tot && !(i >= j0 && i < j0 + nbe)) ? d.X[i + (int64_t)(pc0 + q2) * d.ld] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256 + t;
+            if (e < tot) {
+                const int q2 = e / nr, i = r0 + (e - q2 * nr);
+                const T w = (i >= j0 && i < j0 + nbe) ? ((i - j0 == q2) ? T(-1) : T(0)) : v[u];
+                d.SC[i + (int64_t)q2 * d.n] = w;
+            }
         }
     }
 }
