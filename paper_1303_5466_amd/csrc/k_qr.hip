@@ -159,28 +159,35 @@ __global__ void __launch_bounds__(256) qr_init_kernel(T* __restrict__ A, T* __re
     if (lane == 0) { X.norms[c] = s; X.perm[c] = c; }
 }
 
-// Window selection and the permutation that realises it (one wave).
+// Window selection and the permutation that realises it.  The remaining
+// candidates are ordered by (trailing norm descending, column ascending) with
+// a bitonic sort in LDS (nsort, a power of two at least the number of
+// candidates, padded with keys below every norm); the first QR_WIN entries
+// are the window, in that order.  The moves are then derived by wave 0.
 template <typename T>
-__global__ void __launch_bounds__(64) qr_select_kernel(T* __restrict__ A, T* __restrict__ aux,
-                                                        int* __restrict__ iaux, T* __restrict__ ws,
-                                                        const QRProblemDev* __restrict__ probs,
-                                                        int outer) {
-    extern __shared__ unsigned char smem_raw[];
-    T* vals = reinterpret_cast<T*>(smem_raw);
+__global__ void __launch_bounds__(256) qr_select_kernel(T* __restrict__ A, T* __restrict__ aux,
+                                                         int* __restrict__ iaux, T* __restrict__ ws,
+                                                         const QRProblemDev* __restrict__ probs,
+                                                         int outer, int nsort) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* key = reinterpret_cast<T*>(smem_raw);
+    int* idx = reinterpret_cast<int*>(key + nsort);
     const QRProblemDev q = probs[blockIdx.x];
     Aux<T> X(aux, iaux, ws, q);
-    const int lane = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
+    const bool w0 = t < 64;
     __shared__ int chosen[WIN];
     __shared__ int inwin[WIN];
     __shared__ int mv[4 * WIN];
     __shared__ T nv[2 * WIN];
     __shared__ int pv[2 * WIN];
+    __shared__ int dlist[WIN], olist[WIN];
     const int J0 = outer * WIN;
     int skip = 0;
     if (X.state[0] >= 0) skip = 1;
     else if (J0 >= q.k) skip = 2;
     __syncthreads();
-    if (lane == 0) {
+    if (t == 0) {
         if (skip == 2) X.state[0] = q.k;
         X.state[1] = skip ? 1 : 0;
         X.state[5] = 0;
@@ -188,46 +195,52 @@ __global__ void __launch_bounds__(64) qr_select_kernel(T* __restrict__ A, T* __r
     if (skip) return;
     const int WO = min(WIN, q.k - J0);
     const int nrem = q.k - J0;
-    for (int i = lane; i < nrem; i += 64) vals[i] = X.norms[J0 + i];
-    if (lane < WIN && J0 + lane < q.k) X.tau[J0 + lane] = T(0);
-    inwin[lane] = 0;
-    __syncthreads();
-    for (int c = 0; c < WO; ++c) {
-        T best = T(-1);
-        int bi = 0x7fffffff;
-        for (int i = lane; i < nrem; i += 64) {
-            const T v = vals[i];
-            if (v > best) { best = v; bi = i; }
-        }
-        const T m = (T)wave_max_nonneg((double)(best > T(0) ? best : T(0)));
-        const int cand = (best == m && best >= T(0)) ? bi : 0x7fffffff;
-        const int win = wave_min_int(cand);
-        if (lane == 0) { chosen[c] = win; vals[win] = T(-2); }
-        __syncthreads();
+    for (int i = t; i < nsort; i += 256) {
+        key[i] = i < nrem ? X.norms[J0 + i] : T(-1);
+        idx[i] = i;
     }
-    // slot c <- chosen[c]; displaced window columns -> the outside chosen slots
-    const int ch = lane < WO ? chosen[lane] : -1;
-    if (lane < WO && ch < WO) inwin[ch] = 1;
+    if (t < WIN && J0 + t < q.k) X.tau[J0 + t] = T(0);
+    if (w0) inwin[lane] = 0;
     __syncthreads();
-    const bool disp = lane < WO && !inwin[lane];
-    const bool outc = lane < WO && ch >= WO;
-    const unsigned long long bd = __ballot(disp), bo = __ballot(outc);
+    for (int size = 2; size <= nsort; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = t; e < (nsort >> 1); e += 256) {
+                const int i = 2 * stride * (e / stride) + (e % stride), j = i + stride;
+                const T ki = key[i], kj = key[j];
+                const int ii = idx[i], ij = idx[j];
+                // does j belong before i?
+                const bool jfirst = kj > ki || (kj == ki && ij < ii);
+                const bool swap = ((i & size) == 0) ? jfirst : !jfirst;
+                if (swap) { key[i] = kj; key[j] = ki; idx[i] = ij; idx[j] = ii; }
+            }
+            __syncthreads();
+        }
+    }
+    if (t < WO) chosen[t] = idx[t];
+    __syncthreads();
+    // slot c <- chosen[c]; displaced window columns -> the outside chosen slots
+    const int ch = (w0 && lane < WO) ? chosen[lane] : -1;
+    if (w0 && lane < WO && ch < WO) inwin[ch] = 1;
+    __syncthreads();
+    const bool disp = w0 && lane < WO && !inwin[lane];
+    const bool outc = w0 && lane < WO && ch >= WO;
+    const bool mov = w0 && lane < WO && ch != lane;
+    const unsigned long long bd = __ballot(disp), bo = __ballot(outc), bm = __ballot(mov);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int nmove1 = __popcll(__ballot(lane < WO && ch != lane));
-    const int i1 = __popcll(__ballot(lane < WO && ch != lane) & below);
-    if (lane < WO && ch != lane) { mv[2 * i1] = J0 + ch; mv[2 * i1 + 1] = J0 + lane; }
+    const int nmove1 = __popcll(bm);
+    const int i1 = __popcll(bm & below);
+    if (mov) { mv[2 * i1] = J0 + ch; mv[2 * i1 + 1] = J0 + lane; }
     // pair the j-th displaced slot with the j-th outside chosen slot
-    __shared__ int dlist[WIN], olist[WIN];
     if (disp) dlist[__popcll(bd & below)] = lane;
     if (outc) olist[__popcll(bo & below)] = ch;
     __syncthreads();
     const int nd = __popcll(bd);
-    if (lane < nd) { mv[2 * (nmove1 + lane)] = J0 + dlist[lane]; mv[2 * (nmove1 + lane) + 1] = J0 + olist[lane]; }
+    if (w0 && lane < nd) { mv[2 * (nmove1 + lane)] = J0 + dlist[lane]; mv[2 * (nmove1 + lane) + 1] = J0 + olist[lane]; }
     __syncthreads();
+    if (!w0) return;
     const int nm = nmove1 + nd;
     for (int m = lane; m < nm; m += 64) { nv[m] = X.norms[mv[2 * m]]; pv[m] = X.perm[mv[2 * m]]; }
-    __syncthreads();
-    for (int m = lane; m < nm; m += 64) {
+    for (int m = lane; m < nm; m += 64) {   // each lane re-reads only what it staged
         X.norms[mv[2 * m + 1]] = nv[m];
         X.perm[mv[2 * m + 1]] = pv[m];
         X.moves[2 * m] = mv[2 * m];
@@ -620,8 +633,12 @@ __global__ void __launch_bounds__(256) qr_wsum_kernel(T* __restrict__ aux, int* 
     }
 }
 
-// Window compact-WY factor from the Gram matrix V^T V (first WIN columns of
-// the reduced W): Tw[j][j] = tau_j, Tw[0:j, j] = -tau_j Tw[0:j, 0:j] G[0:j, j].
+// Window compact-WY factor from the Gram matrix G = V^T V (first WIN columns
+// of the reduced W).  Its inverse is upper triangular with 1 / tau_j on the
+// diagonal and G above it (Joffrain et al., "Accumulating Householder
+// transformations, revisited", 2006), so lane j back-substitutes column j of
+// the factor against that matrix, all 64 columns at once; an absent
+// reflector (tau = 0) gets a zero row and column.
 template <typename T>
 __global__ void __launch_bounds__(64) qr_tbuild_kernel(T* __restrict__ aux, int* __restrict__ iaux,
                                                         T* __restrict__ ws,
@@ -630,25 +647,25 @@ __global__ void __launch_bounds__(64) qr_tbuild_kernel(T* __restrict__ aux, int*
     Aux<T> X(aux, iaux, ws, q);
     if (X.state[1]) return;
     const int J0 = X.state[2];
-    const int lane = threadIdx.x;
+    const int j = threadIdx.x;
+    __shared__ __align__(16) T Gc[WIN][WIN];    // Gc[i][l] = G[l][i]
     __shared__ T Tt[WIN][WIN + 1];
-    __shared__ T G[WIN][WIN + 1];
-    for (int j = 0; j < WIN; ++j) {
-        G[lane][j] = X.Ws[lane + (int64_t)j * WIN];
-        Tt[lane][j] = T(0);
+    __shared__ T tau_s[WIN];
+    for (int i = 0; i < WIN; ++i) Gc[i][j] = X.Ws[j + (int64_t)i * WIN];
+    tau_s[j] = (J0 + j < q.k) ? X.tau[J0 + j] : T(0);
+    __syncthreads();
+    T r[WIN];
+#pragma unroll
+    for (int l = 0; l < WIN; ++l) r[l] = (l == j) ? T(1) : T(0);
+#pragma unroll
+    for (int i = WIN - 1; i >= 0; --i) {
+        const T x = r[i] * tau_s[i];
+        Tt[i][j] = x;
+#pragma unroll
+        for (int l = 0; l < i; ++l) r[l] -= Gc[i][l] * x;
     }
     __syncthreads();
-    for (int j = 0; j < WIN; ++j) {
-        const T tau = (J0 + j < q.k) ? X.tau[J0 + j] : T(0);
-        T s2 = T(0);
-        if (lane < j)
-            for (int l = lane; l < j; ++l) s2 += Tt[lane][l] * G[l][j];
-        __syncthreads();
-        if (lane < j) Tt[lane][j] = -tau * s2;
-        if (lane == j) Tt[j][j] = tau;
-        __syncthreads();
-    }
-    for (int j = 0; j < WIN; ++j) X.Tw[lane + j * WIN] = Tt[lane][j];
+    for (int c = 0; c < WIN; ++c) X.Tw[j + c * WIN] = Tt[j][c];
 }
 
 // Exact trailing norms (rows >= J0 + WO) of the remaining candidates.
@@ -755,9 +772,11 @@ template <typename T>
 void launch_qr_select(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_probs,
                       int outer, int max_k, hipStream_t s) {
     if (n_probs <= 0) return;
-    const size_t shm = sizeof(T) * (size_t)std::max(max_k, 1);
+    int nsort = 2;
+    while (nsort < max_k - outer * WIN) nsort <<= 1;
+    const size_t shm = (sizeof(T) + sizeof(int)) * (size_t)nsort;
     if (allow_lds((const void*)qr_select_kernel<T>) < shm) throw HipError("window selection exceeds LDS");
-    hipLaunchKernelGGL(qr_select_kernel<T>, dim3(n_probs), dim3(64), shm, s, A, aux, iaux, ws, probs, outer);
+    hipLaunchKernelGGL(qr_select_kernel<T>, dim3(n_probs), dim3(256), shm, s, A, aux, iaux, ws, probs, outer, nsort);
 }
 
 template <typename T>
