@@ -36,65 +36,6 @@ constexpr int NB = QR_NB;
 constexpr int WIN = QR_WIN;
 constexpr int PT = 256;
 
-// Wave-wide sum through DPP lane shifts (register to register): inclusive
-// sums within rows of 16 lanes, then row broadcasts 15 and 31 carry the row
-// totals up to lane 63, which is read back into every lane.
-__device__ inline float dpp_f(float v, int ctrl_sel) {
-    int x = __float_as_int(v), r;
-    switch (ctrl_sel) {
-        case 0: r = __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true); break;  // row_shr:1
-        case 1: r = __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true); break;  // row_shr:2
-        case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true); break;  // row_shr:4
-        case 3: r = __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true); break;  // row_shr:8
-        case 4: r = __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); break; // row_bcast:15
-        default: r = __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); break; // row_bcast:31
-    }
-    return __int_as_float(r);
-}
-__device__ inline double dpp_d(double v, int ctrl_sel) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    int rl, rh;
-    switch (ctrl_sel) {
-        case 0: rl = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, true); break;
-        case 1: rl = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, true); break;
-        case 2: rl = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, true); break;
-        case 3: rl = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, true); rh = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, true); break;
-        case 4: rl = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false); rh = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false); break;
-        default: rl = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false); rh = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false); break;
-    }
-    return __hiloint2double(rh, rl);
-}
-__device__ inline float dpp(float v, int c) { return dpp_f(v, c); }
-__device__ inline double dpp(double v, int c) { return dpp_d(v, c); }
-__device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
-__device__ inline double lane63(double v) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
-}
-
-// DPP max of non-negative doubles (zero fill is the identity) and min of ints
-__device__ inline double wave_max_nonneg(double v) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) v = fmax(v, dpp_d(v, c));
-    return lane63(v);
-}
-__device__ inline int dpp_i_min(int x, int c) {
-    switch (c) {
-        case 0: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x111, 0xf, 0xf, false);
-        case 1: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x112, 0xf, 0xf, false);
-        case 2: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x114, 0xf, 0xf, false);
-        case 3: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x118, 0xf, 0xf, false);
-        case 4: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x142, 0xa, 0xf, false);
-        default: return __builtin_amdgcn_update_dpp(0x7fffffff, x, 0x143, 0xc, 0xf, false);
-    }
-}
-__device__ inline int wave_min_int(int v) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) v = min(v, dpp_i_min(v, c));
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
 __device__ inline float read_lane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
@@ -104,15 +45,40 @@ __device__ inline double read_lane(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// Value of the partner lane l ^ m, with m = 1, 2, 7, 8, 16, 32 for b = 0..5:
+// quad permutes, row half-mirror and row rotate-by-8 through DPP, then the
+// gfx950 row-pair and half-wave swaps (each returns both halves; the lane
+// keeps the other one).  All register to register.
+__device__ inline int xchg_i(int x, int b) {
+    const int lane = threadIdx.x & 63;
+    switch (b) {
+        case 0: return __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+        case 1: return __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false);   // quad_perm 2,3,0,1
+        case 2: return __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false);  // row_half_mirror
+        case 3: return __builtin_amdgcn_update_dpp(0, x, 0x128, 0xf, 0xf, false);  // row_ror:8
+        case 4: {
+            const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+            return (lane & 16) ? (int)r[0] : (int)r[1];
+        }
+        default: {
+            const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+            return (lane & 32) ? (int)r[0] : (int)r[1];
+        }
+    }
+}
+__device__ inline float xchg(float v, int b) { return __int_as_float(xchg_i(__float_as_int(v), b)); }
+__device__ inline double xchg(double v, int b) {
+    const int lo = xchg_i(__double2loint(v), b), hi = xchg_i(__double2hiint(v), b);
+    return __hiloint2double(hi, lo);
+}
+
+// Wave-wide sum by a butterfly over the six exchanges: every lane ends with
+// the same (bitwise) total.
 template <typename T>
 __device__ inline T wave_sum(T v) {
-    v += dpp(v, 0);
-    v += dpp(v, 1);
-    v += dpp(v, 2);
-    v += dpp(v, 3);
-    v += dpp(v, 4);
-    v += dpp(v, 5);
-    return lane63(v);
+#pragma unroll
+    for (int b = 0; b < 6; ++b) v += xchg(v, b);
+    return v;
 }
 
 // Per-problem state: physical column order equals pivoted order; perm holds
@@ -279,10 +245,11 @@ __global__ void __launch_bounds__(256) qr_move_kernel(T* __restrict__ A, int* __
 
 // Block-wide sums of N values per thread (N a power of two, at most 64),
 // returned in every thread in the same order.  Within a wave a butterfly
-// halves the values held per lane at each exchange (lanes whose bit b is set
-// keep the upper half), so N values cost N - 1 + 6 - log2 N exchanges instead
-// of 6 N; the four wave partials meet in LDS.  red alternates between two
-// halves (parity) so that one barrier per call suffices.
+// halves the values held per lane at each exchange (lanes on the set side of
+// the exchange keep the upper half), so N values cost N - 1 + 6 - log2 N
+// register exchanges instead of 6 N; the four wave partials meet in LDS.
+// red alternates between two halves (parity) so that one barrier per call
+// suffices.
 // An empty asm statement the optimiser cannot look through: it keeps a
 // select between two register-array elements from being rewritten as an
 // indexed load, which would move the whole array to scratch memory.
@@ -299,7 +266,7 @@ __device__ inline const T* block_sum_n(T (&v)[N], T* red /* [2][RS] */, int& par
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int s = 0; s < LN; ++s) {
-        const int b = 5 - s;
+        const int b = 5 - s;                    // exchange b flips lane bit b (and lower ones)
         const bool hi = (lane >> b) & 1;
         const int h = N >> (s + 1);
 #pragma unroll
@@ -310,12 +277,12 @@ __device__ inline const T* block_sum_n(T (&v)[N], T* red /* [2][RS] */, int& par
                 opaque(hi_v);   // keeps the selects on values, not on array slots
                 const T send = hi ? lo_v : hi_v;
                 const T keep = hi ? hi_v : lo_v;
-                v[j] = keep + __shfl_xor(send, 1 << b);
+                v[j] = keep + xchg(send, b);
             }
         }
     }
 #pragma unroll
-    for (int b = 5 - LN; b >= 0; --b) v[0] += __shfl_xor(v[0], 1 << b);
+    for (int b = 5 - LN; b >= 0; --b) v[0] += xchg(v[0], b);
     T* r = red + parity * RS;
     if ((lane & ((64 >> LN) - 1)) == 0) r[(lane >> (6 - LN)) * (PT / 64) + wave] = v[0];
     __syncthreads();
@@ -401,7 +368,8 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     const QRProblemDev q = probs[plist[blockIdx.x]];
     Aux<T> X(aux, iaux, ws, q);
     const int t = threadIdx.x;
-    __shared__ T red[2 * 2 * W * (PT / 64)];
+    __shared__ T red[2 * W * (PT / 64)];
+    __shared__ T rowc[W];     // row c of the sub-panel, published by its owner
     __shared__ T Tfs[W][W + 1];
     __shared__ int lperm[W];
     __shared__ int gperm_old[W];
@@ -419,19 +387,19 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     const int pr = q.p - j0;
     T* Ab = A + q.offA + (int64_t)j0 * q.p + j0;    // sub-panel origin
     // load (columns past nbe zero-filled); first norms and row 0 on the fly
-    T nr[2 * W];   // [0, W): trailing norms^2, [W, 2W): row c of each column
+    T nr[W];   // trailing norms^2 of the columns (rows >= c)
 #pragma unroll
-    for (int j = 0; j < 2 * W; ++j) nr[j] = T(0);
+    for (int j = 0; j < W; ++j) nr[j] = T(0);
     for (int i = t; i < pr; i += PT) {
         T x[W];
 #pragma unroll
         for (int j = 0; j < W; ++j) x[j] = j < nbe ? Ab[(int64_t)j * q.p + i] : T(0);
         store_row<T, W>(P + i * S, x);
 #pragma unroll
-        for (int j = 0; j < W; ++j) {
-            nr[j] += x[j] * x[j];
-            if (i == 0) nr[W + j] = x[j];
-        }
+        for (int j = 0; j < W; ++j) nr[j] += x[j] * x[j];
+        if (i == 0)
+#pragma unroll
+            for (int j = 0; j < W; ++j) rowc[j] = x[j];
     }
     if (t < W) {
 #pragma unroll
@@ -443,16 +411,13 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     int nref = nbe;
     T r11 = (j0 == 0) ? T(0) : X.r11[0];
     for (int c = 0; c < nbe; ++c) {
-        const T* rp = block_sum_n<T, 2 * W, 2 * W * (PT / 64)>(nr, red, parity);
+        block_sum_n<T, W, W * (PT / 64)>(nr, red, parity);
         int pv = c;
         T pn = T(-1);
 #pragma unroll
         for (int j = 0; j < W; ++j)
             if (j >= c && j < nbe && nr[j] > pn) { pn = nr[j]; pv = j; }
-        // the pivot's entry in row c, summed from the partials as in block_sum_n
-        T x0 = T(0);
-#pragma unroll
-        for (int w = 0; w < PT / 64; ++w) x0 += rp[(W + pv) * (PT / 64) + w];
+        const T x0 = rowc[pv];   // the pivot column's entry in row c
         if (pv != c) {
             for (int i = t; i < pr; i += PT) {
                 const T a = P[i * S + c], b = P[i * S + pv];
@@ -467,19 +432,25 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
         const T beta = x0 >= T(0) ? -normx : normx;
         const T tau = (beta - x0) / beta;
         const T scl = T(1) / (x0 - beta);
-        // d_j = v^T P_j over rows >= c (for j < c: the earlier reflectors)
+        // d_j = v^T P_j over rows >= c (for j < c: the earlier reflectors);
+        // the owner of row c (where v is 1) peels it off
         T d[W];
+        int ib = t >= c ? t : t + ((c - t + PT - 1) / PT) * PT;   // first owned row >= c
+        const bool own_c = ib == c;
+        {
+            T x[W];
+            if (own_c) load_row<T, W>(P + c * S, x);
 #pragma unroll
-        for (int j = 0; j < W; ++j) d[j] = T(0);
-        const int ib = t >= c ? t : t + ((c - t + PT - 1) / PT) * PT;   // first owned row >= c
-        for (int i = ib; i < pr; i += PT) {
+            for (int j = 0; j < W; ++j) d[j] = own_c ? x[j] : T(0);
+        }
+        for (int i = own_c ? ib + PT : ib; i < pr; i += PT) {
             T x[W];
             load_row<T, W>(P + i * S, x);
-            const T vc = (i == c) ? T(1) : P[i * S + c] * scl;
+            const T vc = P[i * S + c] * scl;
 #pragma unroll
             for (int j = 0; j < W; ++j) d[j] += vc * x[j];
         }
-        block_sum_n<T, W, 2 * W * (PT / 64)>(d, red, parity);
+        block_sum_n<T, W, W * (PT / 64)>(d, red, parity);
         // compact-WY factor column c: T[:c, c] = -tau T[:c, :c] (V[:, :c]^T v_c)
         if (t <= c && t < W) {
             T s2 = T(0);
@@ -492,19 +463,29 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
 #pragma unroll
         for (int j = 0; j < W; ++j) cf[j] = (j > c) ? tau * d[j] : T(0);
 #pragma unroll
-        for (int j = 0; j < 2 * W; ++j) nr[j] = T(0);
-        for (int i = ib; i < pr; i += PT) {
+        for (int j = 0; j < W; ++j) nr[j] = T(0);
+        if (own_c) {
+            T x[W];
+            load_row<T, W>(P + c * S, x);
+#pragma unroll
+            for (int j = 0; j < W; ++j) x[j] -= cf[j];
+            store_row<T, W>(P + c * S, x);
+            P[c * S + c] = beta;
+        }
+        for (int i = own_c ? ib + PT : ib; i < pr; i += PT) {
             T x[W];
             load_row<T, W>(P + i * S, x);
-            const T vc = (i == c) ? T(1) : P[i * S + c] * scl;
+            const T vc = P[i * S + c] * scl;
 #pragma unroll
             for (int j = 0; j < W; ++j) {
                 x[j] -= cf[j] * vc;
-                nr[j] += (i > c) ? x[j] * x[j] : T(0);
-                nr[W + j] = (i == c + 1) ? x[j] : nr[W + j];
+                nr[j] += x[j] * x[j];
             }
             store_row<T, W>(P + i * S, x);
-            P[i * S + c] = (i == c) ? beta : vc;
+            P[i * S + c] = vc;
+            if (i == c + 1)
+#pragma unroll
+                for (int j = 0; j < W; ++j) rowc[j] = x[j];
         }
     }
     // write back (owned rows): R and reflectors to A, reflectors (unit lower) to V
