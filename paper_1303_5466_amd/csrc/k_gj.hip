@@ -24,18 +24,6 @@ namespace {
 constexpr int GJ_NB = 64;
 constexpr int CHUNK = 64;
 
-// An empty asm statement the optimiser cannot look through: it keeps a
-// select between register-array elements from being rewritten as an indexed
-// load, which would move the array to scratch memory.
-__device__ inline void opaque(double& x) { asm("" : "+v"(x)); }
-__device__ inline void opaque(float& x) { asm("" : "+v"(x)); }
-
-template <typename T>
-__device__ inline T pick4(T v0, T v1, T v2, T v3, int k) {
-    opaque(v0); opaque(v1); opaque(v2); opaque(v3);
-    return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
-}
-
 // Inversion of the pivot block: thread t keeps the 4 x 4 tile (rows 4(t/16),
 // columns 4(t%16)) of P in registers; step c needs only pivot row c and pivot
 // column c, which their owners publish in a double-buffered LDS strip, so each
@@ -81,39 +69,49 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
 #pragma unroll
         for (int a = 0; a < 4; ++a) colb[0][ri + a] = p[a][0];
     __syncthreads();
-    for (int c = 0; c < nbe; ++c) {
-        const int buf = c & 1;
-        const T piv = rowb[buf][c];
-        if (t == 0 && !(fabs((double)piv) > 1e-300 && isfinite((double)piv))) bad = 1;
-        const T inv = T(1) / piv;
-        T pr[4], pcv[4];
+    // All 64 steps run (past nbe the block is the identity, which they leave
+    // unchanged); unrolled by four so that the pivot's position inside a
+    // thread's 4 x 4 tile is a compile-time index and only the ownership test
+    // is dynamic.
+    for (int c4 = 0; c4 < GJ_NB; c4 += 4) {
+        const bool own_r = ri == c4, own_c = cj == c4;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) pr[b] = rowb[buf][cj + b];
+        for (int l = 0; l < 4; ++l) {
+            const int c = c4 + l;
+            const int buf = c & 1;
+            const T piv = rowb[buf][c];
+            if (t == 0 && !(fabs((double)piv) > 1e-300 && isfinite((double)piv))) bad = 1;
+            const T inv = T(1) / piv;
+            T prs[4], pcv[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) pcv[a] = colb[buf][ri + a];
-        const int rc = c - ri, cc = c - cj;    // local row / column of the pivot (if in [0, 4))
+            for (int b = 0; b < 4; ++b) prs[b] = rowb[buf][cj + b] * inv;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const T prs = pr[b] * inv;
-            const T rowv = (cc == b) ? inv : prs;
+            for (int a = 0; a < 4; ++a) pcv[a] = colb[buf][ri + a];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const T upd = p[a][b] - pcv[a] * prs;
-                const T oth = (cc == b) ? -pcv[a] * inv : upd;
-                p[a][b] = (rc == a) ? rowv : oth;
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) p[a][b] -= pcv[a] * prs[b];
+            if (own_c)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) p[a][l] = -pcv[a] * inv;
+            if (own_r)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) p[l][b] = prs[b];
+            if (own_r && own_c) p[l][l] = inv;
+            // publish row and column c + 1
+            const int c1 = c + 1, nb2 = buf ^ 1;
+            if (c1 < GJ_NB) {
+                const int l1 = (l + 1) & 3;
+                const bool r1 = ri == (c1 & ~3), k1 = cj == (c1 & ~3);
+                if (r1)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) rowb[nb2][cj + b] = p[l1][b];
+                if (k1)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) colb[nb2][ri + a] = p[a][l1];
             }
+            __syncthreads();
         }
-        const int c1 = c + 1, nb2 = buf ^ 1;
-        if (c1 < nbe) {
-            const int r1 = c1 - ri, k1 = c1 - cj;
-            if (r1 >= 0 && r1 < 4)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) rowb[nb2][cj + b] = pick4(p[0][b], p[1][b], p[2][b], p[3][b], r1);
-            if (k1 >= 0 && k1 < 4)
-#pragma unroll
-                for (int a = 0; a < 4; ++a) colb[nb2][ri + a] = pick4(p[a][0], p[a][1], p[a][2], p[a][3], k1);
-        }
-        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)

@@ -503,21 +503,22 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     }
     if (t < nbe) gperm_old[t] = X.perm[j0 + t];
     __syncthreads();
-    // rows above the sub-panel hold earlier R entries of these columns
-    T* Ac = A + q.offA + (int64_t)j0 * q.p;
-    for (int i = t; i < j0; i += PT) {
-        T tmp[W];
-#pragma unroll
-        for (int j = 0; j < W; ++j) tmp[j] = j < nbe ? Ac[i + (int64_t)j * q.p] : T(0);
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-            if (j < nbe) {
-                T v = T(0);
-                const int src = lperm[j];
-#pragma unroll
-                for (int jj = 0; jj < W; ++jj) v = (jj == src) ? tmp[jj] : v;
-                Ac[i + (int64_t)j * q.p] = v;
-            }
+    // rows above the sub-panel hold earlier R entries of these columns: all of
+    // them are staged in the (now free) LDS of the sub-panel, then written back
+    // in pivot order; nothing to do when the order did not change
+    bool moved = false;
+    for (int j = 0; j < W; ++j) moved |= lperm[j] != j;
+    if (moved && j0 > 0) {
+        T* Ac = A + q.offA + (int64_t)j0 * q.p;
+        T* Q = P;   // [W][j0]: j0 * W < p * S, within the allocation
+        for (int e = t; e < j0 * nbe; e += PT) {
+            const int j = e / j0, i = e - j * j0;
+            Q[e] = Ac[i + (int64_t)j * q.p];
+        }
+        __syncthreads();
+        for (int e = t; e < j0 * nbe; e += PT) {
+            const int j = e / j0, i = e - j * j0;
+            Ac[i + (int64_t)j * q.p] = Q[lperm[j] * j0 + i];
         }
     }
     if (t < nbe) X.perm[j0 + t] = gperm_old[lperm[t]];
