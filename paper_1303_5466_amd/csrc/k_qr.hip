@@ -24,6 +24,7 @@
 // qr_trsm finally back-substitutes with R11, one 64-row block per call with
 // the rows above updated by grouped GEMMs in between, and scatters through Pi.
 #include <map>
+#include <type_traits>
 #include <mutex>
 
 #include "common.hpp"
@@ -256,6 +257,15 @@ __global__ void __launch_bounds__(256) qr_move_kernel(T* __restrict__ A, int* __
 __device__ inline void opaque(double& x) { asm("" : "+v"(x)); }
 __device__ inline void opaque(float& x) { asm("" : "+v"(x)); }
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E, typename F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 template <int N> struct Log2 { static constexpr int v = 1 + Log2<N / 2>::v; };
 template <> struct Log2<1> { static constexpr int v = 0; };
 
@@ -410,7 +420,12 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     int parity = 0;
     int nref = nbe;
     T r11 = (j0 == 0) ? T(0) : X.r11[0];
-    for (int c = 0; c < nbe; ++c) {
+    // columns unrolled (static_for): every column index below is a
+    // compile-time constant; a truncation stops the remaining columns
+    bool stop = false;
+    static_for<0, W>([&](auto C) {
+        constexpr int c = decltype(C)::value;
+        if (stop || c >= nbe) return;
         block_sum_n<T, W, W * (PT / 64)>(nr, red, parity);
         int pv = c;
         T pn = T(-1);
@@ -428,7 +443,7 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
         }
         const T normx = sqrt(pn);
         if (j0 + c == 0) r11 = normx;
-        if (!(normx > T(tol) * r11)) { nref = c; break; }
+        if (!(normx > T(tol) * r11)) { nref = c; stop = true; return; }
         const T beta = x0 >= T(0) ? -normx : normx;
         const T tau = (beta - x0) / beta;
         const T scl = T(1) / (x0 - beta);
@@ -487,7 +502,7 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
 #pragma unroll
                 for (int j = 0; j < W; ++j) rowc[j] = x[j];
         }
-    }
+    });
     // write back (owned rows): R and reflectors to A, reflectors (unit lower) to V
     T* Vb = X.V + (int64_t)(sub * W) * q.p + j0;
     for (int i = t; i < pr; i += PT) {
