@@ -35,7 +35,7 @@ namespace {
 
 constexpr int NB = QR_NB;
 constexpr int WIN = QR_WIN;
-constexpr int PT = 256;
+constexpr int PT = 512;
 
 __device__ inline float read_lane(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
