@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-solves", type=int, default=30)
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -80,6 +82,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.pmc_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)      # one elementwise kernel: reads and writes nbytes
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
     pts, a, f, tol = W.make_workload(args.workload)
     n, nrhs = f.shape
     prec = rsd.RSD_PREC_FP64 if args.precision == "fp64" else rsd.RSD_PREC_FP32_REFINE
@@ -146,9 +157,17 @@ def main():
     dom = max(cls_time, key=cls_time.get)
     g = prof[gemm_cls]
     achieved = g["flops"] / (g["ms"] * 1e-3) if g["ms"] > 0 else 0.0
-    roof = {"bound": "mfma", "kernel": "gemm_kernel<" + ("double" if dt == "f64" else "float") + ">",
+    # HBM bytes per launch from the committed counter summary, valid only while
+    # the GEMM source is the one the counters were taken with
+    traffic = None
+    if args.workload == "laplace256" and dt == "f64":
+        from paper_1303_5466_amd import profsum
+        rec = profsum.read_traffic(os.path.join(ROOT, "profiles", "gemm_kernel_laplace256_traffic.md"))
+        if rec is not None and rec[1] == profsum.gemm_source_digest():
+            traffic = rec[0]
+    roof = {"bound": "mfma", "kernel": "gemm_kernel<" + ("double" if dt == "f64" else "float") + ", 0>",
             "class": gemm_cls, "achieved": achieved / 1e12, "peak": PEAK[dt] / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK[dt], "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK[dt], "traffic": traffic,
             "launches_per_step": g["launches"] // args.steps,
             "flops_per_launch": g["flops"] / max(g["launches"], 1),
             "avg_launch_us": g["ms"] * 1e3 / max(g["launches"], 1),

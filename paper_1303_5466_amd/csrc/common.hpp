@@ -85,7 +85,9 @@ constexpr int GEMM_TILE = 64;
 
 // ------------------------------- launchers ---------------------------------
 template <typename T>
-void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, hipStream_t s);
+// role: 0 factor levels, 1 interpolation, 2 solve sweeps, 3 library calls
+void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, hipStream_t s,
+                 int role);
 
 // generation / assembly
 template <typename T>

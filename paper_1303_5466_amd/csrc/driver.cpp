@@ -143,6 +143,7 @@ struct GemmBatch {
     const TileRef* d_tiles = nullptr;
     double flops = 0, bytes = 0;
     int prof_cls = -1;
+    int role = -1;      // kernel instantiation (see launch_gemm); -1: from prof_cls
     void add(const GemmDesc<T>& d) {
         if (d.M <= 0 || d.N <= 0) return;
         const int id = (int)descs.size();
@@ -157,7 +158,10 @@ struct GemmBatch {
     void run(hipStream_t s) const {
         if (tiles.empty()) return;
         ProfScope ps(prof_cls, s, flops, bytes);
-        launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), s);
+        const int r = role >= 0 ? role
+                    : (prof_cls == RSD_PROF_FACTOR_GEMM_F64 || prof_cls == RSD_PROF_FACTOR_GEMM_F32) ? 0
+                    : (prof_cls == RSD_PROF_SOLVE_GEMM ? 2 : 1);
+        launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), s, r);
     }
 };
 
@@ -254,7 +258,6 @@ struct Factor {
     std::vector<int> level_id_off;
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
     hipStream_t qr_stream[2] = {nullptr, nullptr};   // interpolation chains run here
-    hipStream_t tsolve_stream = nullptr;             // their back substitutions
     std::vector<hipEvent_t> tmp_events;
     std::vector<std::unique_ptr<DevBuf>> scratch;   // freed after the build
     std::vector<LevelExec<double>> L64;
@@ -268,7 +271,6 @@ struct Factor {
         for (auto e : tmp_events) (void)hipEventDestroy(e);
         for (auto q : qr_stream)
             if (q) (void)hipStreamDestroy(q);
-        if (tsolve_stream) (void)hipStreamDestroy(tsolve_stream);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
     DevBuf& tmp() {
@@ -503,23 +505,18 @@ struct QRChain {
         launch_qr_norms<T>(Ab, aux, iaux, q, np, sw, max_k, s);
         const int ng = soff[sw + 1] - soff[sw];
         if (ng == 0) return;
-        // back substitution for the problems finished in this window, off the
-        // critical path of the remaining windows
+        // back substitution for the problems finished in this window, on the
+        // chain's stream (four streams in all keep one hardware queue each
+        // under HIP's default of four)
         int gr = 0;
         for (int g = soff[sw]; g < soff[sw + 1]; ++g) gr = std::max(gr, qp[sflat[g]].r);
-        hipStream_t ts = f->tsolve_stream;
-        hipEvent_t done;
-        RSD_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-        RSD_HIP(hipEventRecord(done, s));
-        RSD_HIP(hipStreamWaitEvent(ts, done, 0));
-        f->tmp_events.push_back(done);
         for (int st = 0; st < (int)gsolve[sw].size(); ++st) {
-            launch_qr_trsm<T>(Ab, aux, iaux, Tbase<T>(*f), q, dsolve->as<int>() + soff[sw], ng, gr, st, ts);
-            gsolve[sw][st].run(ts);
+            launch_qr_trsm<T>(Ab, aux, iaux, Tbase<T>(*f), q, dsolve->as<int>() + soff[sw], ng, gr, st, s);
+            gsolve[sw][st].run(s);
         }
         hipEvent_t solved;
         RSD_HIP(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
-        RSD_HIP(hipEventRecord(solved, ts));
+        RSD_HIP(hipEventRecord(solved, s));
         f->tmp_events.push_back(solved);
         for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
             const int lev = prob_level[sflat[g]];
@@ -920,13 +917,11 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
     RSD_HIP(hipEventRecord(e0, s));
     // interpolation problems on their own streams, overlapping the level pipeline
     for (auto& q : f->qr_stream) RSD_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
-    RSD_HIP(hipStreamCreateWithFlags(&f->tsolve_stream, hipStreamNonBlocking));
     {
         hipEvent_t go;
         RSD_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
         RSD_HIP(hipEventRecord(go, s));
         for (auto q : f->qr_stream) RSD_HIP(hipStreamWaitEvent(q, go, 0));
-        RSD_HIP(hipStreamWaitEvent(f->tsolve_stream, go, 0));
         (void)hipEventDestroy(go);
     }
     // chains: (precision, narrow sub-panels) -> problems; the narrow chain
@@ -983,7 +978,6 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
     RSD_HIP(hipEventRecord(e1, s));
     RSD_HIP(hipStreamSynchronize(s));
     for (auto q : f->qr_stream) RSD_HIP(hipStreamSynchronize(q));
-    RSD_HIP(hipStreamSynchronize(f->tsolve_stream));
     f->scratch.clear();
     for (auto e : f->tmp_events) (void)hipEventDestroy(e);
     f->tmp_events.clear();
@@ -1295,6 +1289,7 @@ static void dense_gemm(int M, int N, int K, int tA, int tB, double alpha, const 
     if (!is_device_ptr(B)) { dB.alloc((size_t)ldb * cb * sizeof(T)); RSD_HIP(hipMemcpy(dB.p, B, (size_t)ldb * cb * sizeof(T), hipMemcpyHostToDevice)); pB = dB.as<T>(); }
     if (hc) { dC.alloc((size_t)ldc * N * sizeof(T)); RSD_HIP(hipMemcpy(dC.p, C, (size_t)ldc * N * sizeof(T), hipMemcpyHostToDevice)); pC = dC.as<T>(); }
     GemmBatch<T> b;
+    b.role = 3;
     b.add(gdesc<T>(M, N, K, pA, lda, tA, pB, ldb, tB, pC, ldc, (T)alpha, (T)beta));
     std::vector<GemmBatch<T>*> all{&b};
     upload_batches<T>(dd, all, s);

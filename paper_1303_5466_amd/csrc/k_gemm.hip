@@ -114,7 +114,10 @@ __device__ inline void run_segment(const T* A, int lda, int tA, const T* B, int 
     }
 }
 
-template <typename T>
+// ROLE only names the instantiation (factor levels 0, interpolation 1,
+// solve sweeps 2, library calls 3) so that profiles can tell the launch
+// sites apart; the code is the same.
+template <typename T, int ROLE>
 __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict__ descs,
                                                    const TileRef* __restrict__ tiles) {
     __shared__ T As[BK][LDS_W];
@@ -154,12 +157,18 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
 }  // namespace
 
 template <typename T>
-void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, hipStream_t s) {
+void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, hipStream_t s,
+                 int role) {
     if (n_tiles <= 0) return;
-    hipLaunchKernelGGL(gemm_kernel<T>, dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles);
+    switch (role) {
+        case 0: hipLaunchKernelGGL((gemm_kernel<T, 0>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
+        case 1: hipLaunchKernelGGL((gemm_kernel<T, 1>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
+        case 2: hipLaunchKernelGGL((gemm_kernel<T, 2>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
+        default: hipLaunchKernelGGL((gemm_kernel<T, 3>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
+    }
 }
 
-template void launch_gemm<double>(const GemmDesc<double>*, const TileRef*, int, hipStream_t);
-template void launch_gemm<float>(const GemmDesc<float>*, const TileRef*, int, hipStream_t);
+template void launch_gemm<double>(const GemmDesc<double>*, const TileRef*, int, hipStream_t, int);
+template void launch_gemm<float>(const GemmDesc<float>*, const TileRef*, int, hipStream_t, int);
 
 }  // namespace rsd
