@@ -170,6 +170,7 @@ def main():
             "unit": "TFLOP/s", "frac": achieved / PEAK[dt], "traffic": traffic,
             "launches_per_step": g["launches"] // args.steps,
             "flops_per_launch": g["flops"] / max(g["launches"], 1),
+            "algorithmic_bytes_per_launch": g["bytes"] / max(g["launches"], 1),
             "avg_launch_us": g["ms"] * 1e3 / max(g["launches"], 1),
             "dominant_class_by_time": dom}
     out = {
