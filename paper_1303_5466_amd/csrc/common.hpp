@@ -146,7 +146,7 @@ void launch_qr_wsum(T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_p
 template <typename T>
 void launch_qr_norms(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int outer,
                      int max_k, hipStream_t s);
-int qr_panel_width(int p);
+int qr_panel_width(int p, int elem_bytes);   // sub-panel width for a p-row problem
 template <typename T>
 void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
                     const int* plist, int n_probs, int max_r, int step, hipStream_t s);

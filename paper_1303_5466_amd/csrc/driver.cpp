@@ -327,7 +327,7 @@ struct QRChain {
             const IDProblem& I = P.idps[id];
             QRProblemDev q;
             q.p = I.p; q.k = I.k; q.r = I.r;
-            q.nb = qr_panel_width(I.p);
+            q.nb = qr_panel_width(I.p, (int)sizeof(T));
             if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
             const int n = I.k + I.r;
             const int nch = (I.p + QR_RC - 1) / QR_RC;
@@ -932,7 +932,7 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
         if (P.layouts[li].idp < 0) continue;
         const int lev = layout_level[li];
         const int pr = f->level_prec[lev];
-        const int narrow = qr_panel_width(P.idps[P.layouts[li].idp].p) < 16 ? 1 : 0;
+        const int narrow = qr_panel_width(P.idps[P.layouts[li].idp].p, pr ? 4 : 8) < 16 ? 1 : 0;
         cp[pr][narrow].push_back(P.layouts[li].idp);
         cl[pr][narrow].push_back(lev);
         ++pending[lev];

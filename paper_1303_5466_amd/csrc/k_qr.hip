@@ -749,11 +749,19 @@ static size_t allow_lds(const void* fn) {
 
 }  // namespace
 
-int qr_panel_width(int p) {
-    if ((size_t)panel_stride<double, 16>() * p * 8 <= LDS_BUDGET) return 16;
-    if ((size_t)panel_stride<double, 8>() * p * 8 <= LDS_BUDGET) return 8;
-    if ((size_t)panel_stride<double, 4>() * p * 8 <= LDS_BUDGET) return 4;
-    if ((size_t)panel_stride<double, 2>() * p * 8 <= LDS_BUDGET) return 2;
+int qr_panel_width(int p, int elem_bytes) {
+    const size_t eb = (size_t)elem_bytes;
+    if (elem_bytes == 4) {
+        if ((size_t)panel_stride<float, 16>() * p * eb <= LDS_BUDGET) return 16;
+        if ((size_t)panel_stride<float, 8>() * p * eb <= LDS_BUDGET) return 8;
+        if ((size_t)panel_stride<float, 4>() * p * eb <= LDS_BUDGET) return 4;
+        if ((size_t)panel_stride<float, 2>() * p * eb <= LDS_BUDGET) return 2;
+        return 0;
+    }
+    if ((size_t)panel_stride<double, 16>() * p * eb <= LDS_BUDGET) return 16;
+    if ((size_t)panel_stride<double, 8>() * p * eb <= LDS_BUDGET) return 8;
+    if ((size_t)panel_stride<double, 4>() * p * eb <= LDS_BUDGET) return 4;
+    if ((size_t)panel_stride<double, 2>() * p * eb <= LDS_BUDGET) return 2;
     return 0;
 }
 
