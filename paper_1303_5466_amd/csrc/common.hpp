@@ -188,6 +188,13 @@ void launch_gather_down(TD* V, const TS* Vparent, const TS* Yparent, int nrhs,
 
 // exact float64 matvec y = A x on the grid (grid-ordered vectors)
 void launch_matvec_table(double* table, int64_t nx, int64_t ny, KernelDesc kd, hipStream_t s);
+// FFT form of the exact product (circulant embedding, k_fft.hip); sizes are
+// powers of two >= twice the grid sides, false when a side exceeds 4096
+bool fft_matvec_sizes(int64_t nx, int64_t ny, int* Mx, int* My);
+void launch_fft_spectrum(double* Cr, double2* work, int64_t nx, int64_t ny, int Mx, int My,
+                         KernelDesc kd, hipStream_t s);
+void launch_fft_matvec(double* y, const double* x, int nrhs, const double* Cr, double2* work,
+                       int64_t nx, int64_t ny, int Mx, int My, KernelDesc kd, hipStream_t s);
 void launch_matvec(double* y, const double* x, int nrhs, const double* table, int64_t nx,
                    int64_t ny, KernelDesc kd, int cplx, hipStream_t s);
 

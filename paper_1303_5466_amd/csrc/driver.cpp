@@ -254,7 +254,8 @@ struct Factor {
     std::vector<int> level_prec;    // 0 fp64, 1 fp32
     // device tables
     DevBuf d_boxes, d_layouts, d_lu, d_lv, d_srcc, d_srci, d_inv, d_perm, d_ident, d_a, d_sb,
-        d_level_ids, d_err, d_table;
+        d_level_ids, d_err, d_table, d_spec, d_fftwork;
+    int fft_mx = 0, fft_my = 0;     // circulant sizes of the FFT product (0: not set up)
     std::vector<int> level_id_off;
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
     hipStream_t qr_stream[2] = {nullptr, nullptr};   // interpolation chains run here
@@ -1163,8 +1164,25 @@ static void ensure_table(Factor& f) {
     launch_matvec_table(f.d_table.as<double>(), f.nx, f.ny, f.kd, f.stream);
 }
 
-// y = A x, grid-ordered device vectors
+// y = A x, grid-ordered device vectors: the FFT form (circulant embedding)
+// when the grid sides allow it, else the direct sum
 static void matvec_grid(Factor& f, const double* x, double* y, int nrhs) {
+    int mx = 0, my = 0;
+    if (fft_matvec_sizes(f.nx, f.ny, &mx, &my)) {
+        const double n = (double)mx * my;
+        if (!f.fft_mx) {
+            f.d_spec.alloc((size_t)n * sizeof(double));
+            f.d_fftwork.alloc((size_t)n * 2 * sizeof(double));
+            launch_fft_spectrum(f.d_spec.as<double>(), f.d_fftwork.as<double2>(), f.nx, f.ny, mx, my, f.kd, f.stream);
+            f.fft_mx = mx;
+            f.fft_my = my;
+        }
+        const double pairs = (nrhs + 1) / 2;
+        ProfScope ps(RSD_PROF_MATVEC, f.stream, pairs * 2 * 5.0 * n * std::log2(n), pairs * 10.0 * 16.0 * n);
+        launch_fft_matvec(y, x, nrhs, f.d_spec.as<double>(), f.d_fftwork.as<double2>(), f.nx, f.ny, mx, my,
+                          f.kd, f.stream);
+        return;
+    }
     ensure_table(f);
     const double nn = (double)f.N;
     ProfScope ps(RSD_PROF_MATVEC, f.stream, 2.0 * nn * nn * nrhs, 16.0 * nn * nrhs);

@@ -160,6 +160,21 @@ def test_matvec_matches_reference():
     assert np.abs(y - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
 
 
+@pytest.mark.parametrize("nx,ny,contrast", [(33, 21, True), (600, 7, False), (1500, 3, False),
+                                             (2050, 3, False)])
+def test_fft_product_sizes_and_contrast(nx, ny, contrast):
+    # circulant FFT product: 128x64, 2048x16 (4-line workgroups), 4096x8 (one
+    # line per workgroup) and, past 4096, the direct-sum fallback
+    pts = W.grid_points(nx, ny)
+    a = W.coef_sine(pts)
+    b = (0.2 + W.coef_sine(pts)) if contrast else None
+    s = W.rhs_normal(len(pts), 3, 11)
+    fac = rsd.Factor(pts, None if contrast else a, 1e-10, contrast=b)
+    y = fac.matvec(s)
+    y_ref = nystrom.matvec_direct(pts, s, None if contrast else a, bvec=b)
+    assert np.abs(y - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
+
+
 def test_fp32_refined_matches_dense():
     pts = W.grid_points(64)
     a = W.coef_sine(pts)
