@@ -59,6 +59,42 @@ def cpu_baseline(pts, a, f, budget_s=30.0):
                       f"scaled to all {f.shape[1]}; a dense solver, not the paper's method"}
 
 
+def batched_measure(torch, rsd, W, reps=2):
+    """64 grids of uneven size (side 32..256), float32 factors + float64
+    refinement to 1e-8, one right-hand side each: build all (batched call) +
+    solve each; inputs resident in HBM.  Returns a dict for the JSON line."""
+    pts, coefs, rhs, tol = W.make_batch()
+    dev = torch.device("cuda:0")
+    d_pts = [torch.from_numpy(p).to(dev) for p in pts]
+    d_a = [torch.from_numpy(a).to(dev) for a in coefs]
+    d_f = [torch.from_numpy(np.ascontiguousarray(f)).to(dev) for f in rhs]
+    d_x = [torch.empty_like(f) for f in d_f]
+    n_tot = sum(p.shape[0] for p in pts)
+    lib = rsd.load()
+    worst = 0.0
+
+    def once():
+        nonlocal worst
+        facs = rsd.build_batched(d_pts, d_a, tol=tol, precision=rsd.RSD_PREC_FP32_REFINE)
+        for fac, f, x in zip(facs, d_f, d_x):
+            st, info = fac.solve_raw(f.data_ptr(), 1, x.data_ptr())
+            if st != rsd.RSD_OK:
+                raise rsd.RsdError(st, lib.rsd_last_error().decode())
+            worst = max(worst, info.rel_residual)
+            fac.close()
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "batch of 64 grids, side U{32..256}, bump coefficients, tol 1e-8, 1 RHS each",
+            "precision": "fp32+refine", "n_instances": len(pts), "n_unknowns": n_tot,
+            "ms_per_batch": dt * 1e3, "unknowns_per_s": n_tot / dt, "max_rel_residual": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +104,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-solves", type=int, default=30)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched many-grid measurement")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -186,6 +223,11 @@ def main():
         "kernels_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
         "roofline": roof,
     }
+    if not args.no_batched and args.workload == "laplace256":
+        log("batched builds: 64 grids of uneven size ...")
+        out["batched"] = batched_measure(torch, rsd, W)
+        log(f"  {out['batched']['ms_per_batch']:.1f} ms per batch, "
+            f"{out['batched']['unknowns_per_s']:.4g} unknowns/s, residual {out['batched']['max_rel_residual']:.2e}")
     if not args.no_cpu_baseline:
         log("timing the CPU reference on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(pts, a, f)

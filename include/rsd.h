@@ -108,6 +108,27 @@ rsd_status rsd_build_factor(const double* points, int64_t n_points,
                             double tol, const rsd_options* opt,
                             rsd_factor** out);
 
+/* Several independent factorizations in one call (many grids of uneven size,
+ * e.g. a batch of small problems).  Instance i is exactly what
+ * rsd_build_factor(points[i], n_points[i], kernel, a[i], tol, opt, &out[i])
+ * would build (same arithmetic, bitwise equal factors); the builds are
+ * enqueued back to back, each on its own streams, with at most max_inflight
+ * (<= 0 => 8) unfinished at once, so the host planning of one instance and
+ * the device work of the others overlap and small instances share the GPU.
+ *   points, n_points, a  arrays of n_inst entries (a may be NULL => all 1;
+ *                        a[i] may be NULL).  Host or device pointers.
+ *   opt                  shared by all instances; opt->hip_stream must be NULL.
+ *   out                  n_inst entries; on success each holds a factor to be
+ *                        freed with rsd_free.  On any error every out[i] is
+ *                        NULL, nothing leaks, and rsd_last_error names the
+ *                        failing instance.
+ * Errors: as rsd_build_factor, plus EINVAL for n_inst <= 0 or a stream in opt.
+ * Returns after every factor is complete on the device. */
+rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
+                                    const int64_t* n_points, const rsd_kernel* kernel,
+                                    const double* const* a, double tol, const rsd_options* opt,
+                                    int32_t max_inflight, rsd_factor** out);
+
 /* x = A^{-1} rhs with the compressed inverse (Algorithm 6), followed by
  * float64 iterative refinement when the factor was built with
  * RSD_PREC_FP32_REFINE (or max_refine > 0).

@@ -260,6 +260,7 @@ struct Factor {
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
     hipStream_t qr_stream[2] = {nullptr, nullptr};   // interpolation chains run here
     std::vector<hipEvent_t> tmp_events;
+    hipEvent_t build_ev[2] = {nullptr, nullptr};     // start / end of the device build
     std::vector<std::unique_ptr<DevBuf>> scratch;   // freed after the build
     std::vector<LevelExec<double>> L64;
     std::vector<LevelExec<float>> L32;
@@ -269,7 +270,12 @@ struct Factor {
     rsd_factor_stats stats{};
     ~Factor() {
         solve_plans.clear();
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (auto q : qr_stream)
+            if (q) (void)hipStreamSynchronize(q);
         for (auto e : tmp_events) (void)hipEventDestroy(e);
+        for (auto e : build_ev)
+            if (e) (void)hipEventDestroy(e);
         for (auto q : qr_stream)
             if (q) (void)hipStreamDestroy(q);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -707,8 +713,10 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
 // ----------------------------------------------------------------------------
 // build
 // ----------------------------------------------------------------------------
-static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_kernel* kernel,
-                                     const double* a, double tol, const rsd_options* opt) {
+// Host planning, uploads and every launch of a build; returns without waiting
+// for the device (build_finish does).
+static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, const rsd_kernel* kernel,
+                                             const double* a, double tol, const rsd_options* opt) {
     if (!points || n <= 0) throw Error(RSD_EINVAL, "points must be non-null and n_points > 0");
     if (!(tol > 0) || !std::isfinite(tol)) throw Error(RSD_EINVAL, "tol must be a positive number");
     rsd_options o{};
@@ -977,23 +985,9 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
     enqueue_ready();
     if (next_level != nlev) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
     RSD_HIP(hipEventRecord(e1, s));
-    RSD_HIP(hipStreamSynchronize(s));
-    for (auto q : f->qr_stream) RSD_HIP(hipStreamSynchronize(q));
-    f->scratch.clear();
-    for (auto e : f->tmp_events) (void)hipEventDestroy(e);
-    f->tmp_events.clear();
-    float ms = 0;
-    RSD_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    int err[4];
-    RSD_HIP(hipMemcpy(err, f->d_err.p, sizeof(err), hipMemcpyDeviceToHost));
-    if (err[0] != 0) {
-        const int bx = err[0] - 1;
-        throw Error(RSD_ESINGULAR, "singular pivot block in box " + std::to_string(bx) + " at level " +
-                                       std::to_string(P.boxes[bx].level));
-    }
-    // ---- statistics ---------------------------------------------------------------
+    f->build_ev[0] = e0;
+    f->build_ev[1] = e1;
+    // ---- statistics (the build time is filled in by build_finish) -------------------
     rsd_factor_stats& st = f->stats;
     st.n_points = n; st.nx = nx; st.ny = ny;
     st.n_levels = nlev;
@@ -1016,9 +1010,38 @@ static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_
         if (b.level == f->top) sb += (double)es * b.k * b.k;
     }
     st.solve_bytes = sb;
-    st.build_ms = ms;
     (void)t_start;
-    if (!(f->flags & RSD_FLAG_KEEP_E)) { /* E blocks live inside F; nothing to free */ }
+    return f;
+}
+
+// Waits for an enqueued build, releases its temporaries and reports a singular
+// pivot block if one was met.
+static void build_finish(Factor& f) {
+    RSD_HIP(hipStreamSynchronize(f.stream));
+    for (auto q : f.qr_stream) RSD_HIP(hipStreamSynchronize(q));
+    f.scratch.clear();
+    for (auto e : f.tmp_events) (void)hipEventDestroy(e);
+    f.tmp_events.clear();
+    float ms = 0;
+    if (f.build_ev[0] && f.build_ev[1]) RSD_HIP(hipEventElapsedTime(&ms, f.build_ev[0], f.build_ev[1]));
+    for (auto& e : f.build_ev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    f.stats.build_ms = ms;
+    int err[4];
+    RSD_HIP(hipMemcpy(err, f.d_err.p, sizeof(err), hipMemcpyDeviceToHost));
+    if (err[0] != 0) {
+        const int bx = err[0] - 1;
+        throw Error(RSD_ESINGULAR, "singular pivot block in box " + std::to_string(bx) + " at level " +
+                                       std::to_string(f.plan.boxes[bx].level));
+    }
+}
+
+static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_kernel* kernel,
+                                     const double* a, double tol, const rsd_options* opt) {
+    auto f = build_enqueue(points, n, kernel, a, tol, opt);
+    build_finish(*f);
     return f;
 }
 
@@ -1400,6 +1423,45 @@ rsd_status rsd_build_factor(const double* points, int64_t n_points, const rsd_ke
         *out = new rsd_factor{std::move(f)};
         return RSD_OK;
     });
+}
+
+rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
+                                    const int64_t* n_points, const rsd_kernel* kernel,
+                                    const double* const* a, double tol, const rsd_options* opt,
+                                    int32_t max_inflight, rsd_factor** out) {
+    if (out && n_inst > 0)
+        for (int32_t i = 0; i < n_inst; ++i) out[i] = nullptr;
+    std::vector<std::unique_ptr<rsd::Factor>> fs;
+    int32_t where = -1;
+    const rsd_status st = guarded([&]() {
+        if (!out || !points || !n_points) throw rsd::Error(RSD_EINVAL, "null argument");
+        if (n_inst <= 0) throw rsd::Error(RSD_EINVAL, "n_inst must be positive");
+        if (opt && opt->hip_stream) throw rsd::Error(RSD_EINVAL, "batched builds use their own streams");
+        const int32_t window = max_inflight > 0 ? max_inflight : 8;
+        fs.resize(n_inst);
+        int32_t done = 0;
+        for (int32_t i = 0; i < n_inst; ++i) {
+            where = i;
+            fs[i] = rsd::build_enqueue(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt);
+            while (i + 1 - done > window) {
+                where = done;
+                rsd::build_finish(*fs[done++]);
+            }
+        }
+        while (done < n_inst) {
+            where = done;
+            rsd::build_finish(*fs[done++]);
+        }
+        return RSD_OK;
+    });
+    if (st != RSD_OK) {
+        const std::string msg = rsd::g_last_error;
+        fs.clear();
+        rsd::g_last_error = "instance " + std::to_string(where) + ": " + msg;
+        return st;
+    }
+    for (int32_t i = 0; i < n_inst; ++i) out[i] = new rsd_factor{std::move(fs[i])};
+    return RSD_OK;
 }
 
 rsd_status rsd_solve(rsd_factor* f, const double* rhs, int64_t nrhs, double* x, rsd_solve_info* info) {

@@ -55,6 +55,9 @@ class rsd_box_info(C.Structure):
 EXPORTS = {
     "rsd_build_factor": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(rsd_kernel), C.c_void_p,
                                    C.c_double, C.POINTER(rsd_options), C.POINTER(C.c_void_p)]),
+    "rsd_build_factor_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                           C.POINTER(rsd_kernel), C.POINTER(C.c_void_p), C.c_double,
+                                           C.POINTER(rsd_options), C.c_int32, C.POINTER(C.c_void_p)]),
     "rsd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                             C.POINTER(rsd_solve_info)]),
     "rsd_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -151,6 +154,14 @@ class Factor:
         self.n = n
         self.complex = kernel == RSD_KERNEL_HELMHOLTZ
 
+    @classmethod
+    def _adopt(cls, handle, n, complex_=False):
+        obj = cls.__new__(cls)
+        obj._h = handle
+        obj.n = n
+        obj.complex = complex_
+        return obj
+
     def close(self):
         if self._h is not None:
             load().rsd_free(self._h)
@@ -219,6 +230,36 @@ class Factor:
         Y = np.zeros_like(X, order="F")
         _check(load().rsd_matvec(self._h, X.ctypes.data, X.shape[1], Y.ctypes.data))
         return Y[:, 0] if vec else Y
+
+
+def build_batched(points_list, a_list=None, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0,
+                  layers=0, max_refine=0, refine_tol=0.0, max_inflight=0, flags=0):
+    """rsd_build_factor_batched: one Factor per (points, a) instance."""
+    lib = load()
+    n_inst = len(points_list)
+    keep = []
+    pts_p = (C.c_void_p * n_inst)()
+    a_p = (C.c_void_p * n_inst)()
+    npts = (C.c_int64 * n_inst)()
+    for i, pts in enumerate(points_list):
+        if isinstance(pts, np.ndarray):
+            pts = np.ascontiguousarray(pts, dtype=np.float64)
+        p, k = _ptr(pts)
+        keep += [pts, k]
+        pts_p[i] = p
+        npts[i] = pts.shape[0]
+        a = a_list[i] if a_list is not None else None
+        if isinstance(a, np.ndarray):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+        ap, k2 = _ptr(a)
+        keep += [a, k2]
+        a_p[i] = ap
+    kd = rsd_kernel(RSD_KERNEL_LAPLACE, 0.0, None)
+    opt = rsd_options(leaf_side, layers, precision, max_refine, refine_tol, None, -1, flags)
+    out = (C.c_void_p * n_inst)()
+    _check(lib.rsd_build_factor_batched(n_inst, pts_p, npts, C.byref(kd), a_p, tol, C.byref(opt),
+                                        max_inflight, out))
+    return [Factor._adopt(C.c_void_p(out[i]), int(npts[i])) for i in range(n_inst)]
 
 
 class Plan:

@@ -80,6 +80,21 @@ WORKLOADS = {
 }
 
 
+def make_batch(n_inst: int = 64, seed: int = 3, side_lo: int = 32, side_hi: int = 256):
+    """Many independent square grids of uneven size (side ~ U{side_lo..side_hi}),
+    each with Gaussian-bump coefficients and one N(0,1) right-hand side.
+    Returns (list of points, list of a, list of f, tol)."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_lo, side_hi + 1, size=n_inst)
+    pts, coefs, rhs = [], [], []
+    for n in sides:
+        p = grid_points(int(n))
+        pts.append(p)
+        coefs.append(coef_bumps(p, rng))
+        rhs.append(rng.standard_normal(p.shape[0]))
+    return pts, coefs, rhs, 1e-8
+
+
 def make_workload(name: str):
     """Return (points, a, f, tol) for a named workload."""
     w = WORKLOADS[name]

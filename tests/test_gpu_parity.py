@@ -258,3 +258,43 @@ def test_laplace256_full_size_residual_and_sampled_columns():
     for c in (0, 9):
         ref, info = krylov.solve(pts, f[:, c], a, tol=1e-13)
         assert dense.rel_error(x[:, c], ref) < 1e-10
+
+
+# --- batched builds (many independent grids) -----------------------------------
+def test_batched_build_equals_single_builds():
+    shapes = [(16, 16), (37, 37), (24, 40), (64, 64), (9, 30), (48, 33)]
+    rng = np.random.default_rng(21)
+    pts = [W.grid_points(nx, ny) for nx, ny in shapes]
+    coefs = [W.coef_bumps(p, rng) for p in pts]
+    rhs = [rng.standard_normal((p.shape[0], 2)) for p in pts]
+    facs = rsd.build_batched(pts, coefs, tol=1e-10, max_inflight=3)
+    assert len(facs) == len(shapes)
+    for p, a, f, fac in zip(pts, coefs, rhs, facs):
+        x_b, _ = fac.solve(np.asfortranarray(f))
+        single = rsd.Factor(p, a, 1e-10)
+        x_s, _ = single.solve(np.asfortranarray(f))
+        # same arithmetic in the same order: bitwise equal
+        assert np.array_equal(x_b, x_s)
+        assert dense.rel_error(x_b, dense.solve(p, f, a)) < 1e-10
+        single.close()
+        fac.close()
+
+
+def test_batched_build_fp32_refine_and_host_device_mix():
+    pts, coefs, rhs, tol = W.make_batch(n_inst=5, seed=5, side_lo=20, side_hi=60)
+    dev_pts = [_dev(p) if i % 2 else p for i, p in enumerate(pts)]
+    facs = rsd.build_batched(dev_pts, coefs, tol=tol, precision=rsd.RSD_PREC_FP32_REFINE)
+    for p, a, f, fac in zip(pts, coefs, rhs, facs):
+        x, info = fac.solve(f)
+        assert info.rel_residual <= tol
+        assert dense.rel_error(x, dense.solve(p, f, a)) < 1e-7
+        fac.close()
+
+
+def test_batched_build_reports_failing_instance():
+    good = W.grid_points(16)
+    bad = W.grid_points(16)[:-3]          # not a complete grid
+    with pytest.raises(rsd.RsdError) as ei:
+        rsd.build_batched([good, bad, good], None, tol=1e-10)
+    assert ei.value.status == rsd.RSD_ENOTGRID
+    assert "instance 1" in str(ei.value)
