@@ -39,7 +39,8 @@ typedef enum rsd_status {
     RSD_ENOMEM = 3,     /* device memory exhausted or over the caller's budget */
     RSD_ESINGULAR = 4,  /* a pivot block was singular; message names level/box */
     RSD_ENOCONV = 5,    /* iterative refinement did not reach its tolerance */
-    RSD_EDEVICE = 6     /* HIP runtime error */
+    RSD_EDEVICE = 6,    /* HIP runtime error */
+    RSD_EAGAIN = 7      /* not finished within the timeout / no capacity now */
 } rsd_status;
 
 typedef enum rsd_kernel_type {
@@ -210,6 +211,67 @@ rsd_status rsd_profile_enable(int32_t on);
  * device. */
 rsd_status rsd_profile_query(int32_t cls, double* total_ms, int64_t* launches,
                              double* flops, double* bytes);
+
+/* ---- serving: resident factors, queued solves ------------------------------
+ *
+ * A server keeps factors resident in device memory and answers solve
+ * requests (Algorithm 6 applied to queued right-hand sides) from worker
+ * threads.  Requests for one factor that are waiting together are coalesced
+ * into one multi-RHS solve (padded to a power of two of columns, so each
+ * factor keeps at most seven solve plans); different factors are served
+ * concurrently, each on its own stream.  Admission is by memory and slots:
+ * a new factor evicts the least recently used idle factors (no queued or
+ * running solves) until it fits, else the submission fails with ENOMEM.
+ * Latency = submission to completion (host clock). */
+typedef struct rsd_server rsd_server;
+
+typedef struct rsd_server_options {
+    int64_t mem_budget;    /* device bytes for resident factors; 0 => 3/4 of free */
+    int32_t max_slots;     /* resident factors at most; 0 => 16                */
+    int32_t n_workers;     /* solve threads; 0 => 2                            */
+    int32_t max_coalesce;  /* right-hand sides per coalesced solve; 0 => 64    */
+    int32_t device;        /* HIP device; < 0 => the current device            */
+} rsd_server_options;
+
+typedef struct rsd_server_stats {
+    int64_t n_requests;    /* solve requests submitted                        */
+    int64_t n_done;        /* completed (any status)                          */
+    int64_t n_batches;     /* coalesced solves run                            */
+    int64_t n_factors;     /* resident factors                                */
+    int64_t n_evicted;     /* factors evicted for admission                   */
+    int64_t resident_bytes;
+    double p50_ms, p99_ms; /* request latency percentiles                     */
+    double mean_batch_rhs; /* right-hand sides per coalesced solve (unpadded) */
+    double rhs_per_s;      /* completed right-hand sides / seconds since the
+                              first submission                                 */
+} rsd_server_stats;
+
+/* opt NULL => defaults.  Starts the worker threads. */
+rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out);
+/* Builds a factor (as rsd_build_factor; opt->hip_stream must be NULL, the
+ * server gives each factor its own stream) and makes it resident.
+ * *factor_id receives its handle for submit_solve.  ENOMEM when it cannot be
+ * admitted even after evicting every idle factor. */
+rsd_status rsd_server_submit_factor(rsd_server* s, const double* points, int64_t n_points,
+                                    const rsd_kernel* kernel, const double* a, double tol,
+                                    const rsd_options* opt, int64_t* factor_id);
+/* Evicts a factor; EAGAIN while it has queued or running solves, EINVAL for
+ * an unknown id. */
+rsd_status rsd_server_release_factor(rsd_server* s, int64_t factor_id);
+/* Queues x = A^{-1} rhs (N x nrhs column-major, host or device pointers).
+ * Both buffers are borrowed until the request completes (rsd_server_wait).
+ * *ticket identifies the request.  EINVAL for an unknown factor. */
+rsd_status rsd_server_submit_solve(rsd_server* s, int64_t factor_id, const double* rhs,
+                                   int64_t nrhs, double* x, int64_t* ticket);
+/* Waits up to timeout_ms (< 0 => forever) for a request; returns its status
+ * (OK, ENOCONV, ...) and info, and forgets the ticket; EAGAIN on timeout
+ * (the ticket stays valid); EINVAL for an unknown ticket. */
+rsd_status rsd_server_wait(rsd_server* s, int64_t ticket, int32_t timeout_ms, rsd_solve_info* info);
+/* 1 when the request has completed, 0 while pending, -1 for an unknown ticket. */
+int32_t rsd_server_poll(rsd_server* s, int64_t ticket);
+rsd_status rsd_server_get_stats(rsd_server* s, rsd_server_stats* out);
+/* Finishes the queued requests, stops the workers and frees every factor. */
+void rsd_server_destroy(rsd_server* s);
 
 /* ---- dense building blocks ------------------------------------------------ */
 

@@ -27,6 +27,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -100,17 +101,24 @@ struct ProfRec {
 };
 struct Profiler {
     bool on = false;
+    std::mutex mu;              // solves of different factors may run on several threads
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     hipEvent_t get() {
+        std::lock_guard<std::mutex> lk(mu);
         if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
         hipEvent_t e;
         RSD_HIP(hipEventCreate(&e));
         return e;
     }
     void clear() {
+        std::lock_guard<std::mutex> lk(mu);
         for (auto& r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
         recs.clear();
+    }
+    void add(const ProfRec& r) {
+        std::lock_guard<std::mutex> lk(mu);
+        recs.push_back(r);
     }
 };
 static Profiler g_prof;
@@ -128,7 +136,7 @@ struct ProfScope {
     }
     ~ProfScope() {
         if (!act) return;
-        if (hipEventRecord(rec.b, s) == hipSuccess) g_prof.recs.push_back(rec);
+        if (hipEventRecord(rec.b, s) == hipSuccess) g_prof.add(rec);
     }
 };
 
@@ -232,6 +240,7 @@ struct SolveLevel {
 struct SolvePlan {
     int nrhs = 0;
     DevBuf V32, V64, Y32, Y64, tmp, in, out, gemm32, gemm64;
+    DevBuf refine_work, refine_norms;   // refinement vectors, allocated on first use
     std::vector<SolveLevel<float>> L32;
     std::vector<SolveLevel<double>> L64;
 };
@@ -254,7 +263,7 @@ struct Factor {
     std::vector<int> level_prec;    // 0 fp64, 1 fp32
     // device tables
     DevBuf d_boxes, d_layouts, d_lu, d_lv, d_srcc, d_srci, d_inv, d_perm, d_ident, d_a, d_sb,
-        d_level_ids, d_err, d_table, d_spec, d_fftwork;
+        d_level_ids, d_err, d_table, d_spec, d_fftwork, d_flag;
     int fft_mx = 0, fft_my = 0;     // circulant sizes of the FFT product (0: not set up)
     std::vector<int> level_id_off;
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
@@ -1213,8 +1222,8 @@ static void matvec_grid(Factor& f, const double* x, double* y, int nrhs) {
 }
 
 static void check_finite_dev(Factor& f, const double* x, int64_t n) {
-    DevBuf flag;
-    flag.alloc(sizeof(int));
+    DevBuf& flag = f.d_flag;
+    if (!flag.p) flag.alloc(sizeof(int));
     RSD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), f.stream));
     launch_check_finite(x, n, flag.as<int>(), f.stream);
     int h = 0;
@@ -1246,17 +1255,18 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
         apply_inverse(f, sp, fin, xo, f.d_perm.as<int64_t>());
     } else {
         // refinement on grid-ordered copies: fg, xg, rg, dg, ax
-        DevBuf work;
-        work.alloc(5 * tot * sizeof(double));
-        double* fg = work.as<double>();
+        if (!sp.refine_work.p) {
+            sp.refine_work.alloc(5 * tot * sizeof(double));
+            sp.refine_norms.alloc(2 * nrhs * sizeof(double));
+        }
+        double* fg = sp.refine_work.as<double>();
         double* xg = fg + tot;
         double* rg = xg + tot;
         double* dg = rg + tot;
         double* ax = dg + tot;
         launch_permute(fg, fin, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 1, s);
         apply_inverse(f, sp, fg, xg, f.d_ident.as<int64_t>());
-        DevBuf nb;
-        nb.alloc(2 * nrhs * sizeof(double));
+        DevBuf& nb = sp.refine_norms;
         launch_col_norms2(nb.as<double>(), fg, f.N, (int)nrhs, s);
         std::vector<double> fn(nrhs), rn(nrhs);
         RSD_HIP(hipMemcpyAsync(fn.data(), nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));

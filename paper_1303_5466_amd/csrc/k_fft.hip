@@ -11,6 +11,8 @@
 // up to 8 lines (rows, or 8 adjacent columns so that loads stay coalesced)
 // in bit-reversed order, runs log2 L butterfly stages in place with one
 // barrier each, and writes them back.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace rsd {
@@ -132,12 +134,11 @@ int ilog2(int v) {
 }
 
 void fft2(double2* X, int Mx, int My, int sign, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
+    static std::once_flag attr;
+    std::call_once(attr, [] {
         RSD_HIP(hipFuncSetAttribute((const void*)fft_lines_kernel,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)FFT_LDS));
-        attr = true;
-    }
+    });
     // rows: My-point transforms, one row after another in memory
     {
         const int L = My;

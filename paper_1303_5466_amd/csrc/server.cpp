@@ -1,0 +1,364 @@
+// Serving runtime: resident factors in device memory, queued solve requests
+// coalesced per factor and answered by worker threads (the inverse apply of
+// Algorithm 6 for many clients).  Built only on the public interface of the
+// library (rsd_build_factor / rsd_solve / rsd_free) plus HIP streams and
+// copies, so a factor here is exactly what a direct call would build.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/rsd.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    int64_t fid = 0;
+    const double* rhs = nullptr;
+    double* x = nullptr;
+    int64_t nrhs = 0;
+    Clock::time_point t_submit, t_done;
+    bool done = false;
+    rsd_status status = RSD_OK;
+    rsd_solve_info info{0, -1.0};
+};
+
+struct Slot {
+    rsd_factor* f = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t n = 0;
+    int64_t bytes = 0;
+    bool busy = false;
+    Clock::time_point last_use;
+    std::deque<int64_t> pending;     // tickets, oldest first
+    double* dbuf = nullptr;          // in | out, n x cap columns each
+    int64_t cap = 0;
+};
+
+int64_t pow2_at_least(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct rsd_server {
+    rsd_server_options opt{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::map<int64_t, Slot> slots;
+    std::unordered_map<int64_t, Request> reqs;
+    std::vector<std::thread> workers;
+    bool stop = false;
+    int64_t next_fid = 1, next_ticket = 1;
+    int64_t resident = 0;
+    // statistics
+    int64_t n_requests = 0, n_done = 0, n_batches = 0, n_evicted = 0, rhs_done = 0, rhs_batched = 0;
+    std::vector<double> lat_ms;
+    bool started = false;
+    Clock::time_point t_first;
+
+    // slot with queued work, not busy, whose oldest request is the oldest overall
+    Slot* ready(int64_t* fid) {
+        Slot* best = nullptr;
+        int64_t best_ticket = INT64_MAX;
+        for (auto& kv : slots) {
+            Slot& sl = kv.second;
+            if (sl.busy || sl.pending.empty()) continue;
+            if (sl.pending.front() < best_ticket) {
+                best_ticket = sl.pending.front();
+                best = &sl;
+                *fid = kv.first;
+            }
+        }
+        return best;
+    }
+
+    void free_slot(Slot& sl) {
+        if (sl.f) rsd_free(sl.f);
+        if (sl.dbuf) (void)hipFree(sl.dbuf);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        sl = Slot{};
+    }
+
+    void worker() {
+        if (opt.device >= 0) (void)hipSetDevice(opt.device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            int64_t fid = 0;
+            Slot* sl = nullptr;
+            cv_work.wait(lk, [&] { return (sl = ready(&fid)) != nullptr || stop; });
+            if (!sl) return;   // stop and nothing left
+            sl->busy = true;
+            std::vector<int64_t> batch;
+            int64_t cols = 0;
+            while (!sl->pending.empty()) {
+                const int64_t tk = sl->pending.front();
+                const int64_t c = reqs[tk].nrhs;
+                if (!batch.empty() && cols + c > opt.max_coalesce) break;
+                batch.push_back(tk);
+                cols += c;
+                sl->pending.pop_front();
+            }
+            std::vector<Request*> rq;
+            for (int64_t tk : batch) rq.push_back(&reqs[tk]);   // stable: nodes of an unordered_map
+            lk.unlock();
+            rsd_status st = run_batch(*sl, rq, cols);
+            lk.lock();
+            const auto now = Clock::now();
+            for (Request* r : rq) {
+                r->done = true;
+                r->t_done = now;
+                if (st != RSD_OK && r->status == RSD_OK) r->status = st;
+                lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
+                rhs_done += r->nrhs;
+            }
+            n_done += (int64_t)rq.size();
+            n_batches += 1;
+            rhs_batched += cols;
+            sl->busy = false;
+            sl->last_use = now;
+            (void)fid;
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
+    }
+
+    // one coalesced solve: gather the right-hand sides into n x P columns (P a
+    // power of two, zero padding), solve, scatter the solutions back
+    rsd_status run_batch(Slot& sl, std::vector<Request*>& rq, int64_t cols) {
+        const int64_t n = sl.n;
+        const int64_t P = pow2_at_least(cols);
+        if (P > sl.cap) {
+            if (sl.dbuf) (void)hipFree(sl.dbuf);
+            sl.dbuf = nullptr;
+            if (hipMalloc(&sl.dbuf, (size_t)(2 * n * P) * sizeof(double)) != hipSuccess) {
+                (void)hipGetLastError();
+                sl.cap = 0;
+                for (Request* r : rq) r->status = RSD_ENOMEM;
+                return RSD_ENOMEM;
+            }
+            sl.cap = P;
+        }
+        double* in = sl.dbuf;
+        double* out = sl.dbuf + n * sl.cap;
+        int64_t off = 0;
+        for (Request* r : rq) {
+            (void)hipMemcpyAsync(in + off * n, r->rhs, (size_t)(n * r->nrhs) * sizeof(double),
+                                 hipMemcpyDefault, sl.stream);
+            off += r->nrhs;
+        }
+        if (P > cols)
+            (void)hipMemsetAsync(in + cols * n, 0, (size_t)((P - cols) * n) * sizeof(double), sl.stream);
+        rsd_solve_info info{0, -1.0};
+        const rsd_status st = rsd_solve(sl.f, in, P, out, &info);
+        if (st == RSD_OK || st == RSD_ENOCONV) {
+            off = 0;
+            for (Request* r : rq) {
+                (void)hipMemcpyAsync(r->x, out + off * n, (size_t)(n * r->nrhs) * sizeof(double),
+                                     hipMemcpyDefault, sl.stream);
+                off += r->nrhs;
+                r->info = info;
+                r->status = st;
+            }
+        } else {
+            for (Request* r : rq) r->status = st;
+        }
+        if (hipStreamSynchronize(sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            for (Request* r : rq) r->status = RSD_EDEVICE;
+            return RSD_EDEVICE;
+        }
+        return st;
+    }
+};
+
+extern "C" {
+
+rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out) {
+    if (!out) return RSD_EINVAL;
+    *out = nullptr;
+    auto* s = new (std::nothrow) rsd_server();
+    if (!s) return RSD_ENOMEM;
+    if (opt) s->opt = *opt;
+    if (s->opt.device >= 0 && hipSetDevice(s->opt.device) != hipSuccess) {
+        delete s;
+        return RSD_EDEVICE;
+    }
+    if (s->opt.max_slots <= 0) s->opt.max_slots = 16;
+    if (s->opt.n_workers <= 0) s->opt.n_workers = 2;
+    if (s->opt.max_coalesce <= 0) s->opt.max_coalesce = 64;
+    if (s->opt.mem_budget <= 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return RSD_EDEVICE;
+        }
+        s->opt.mem_budget = (int64_t)(fr / 4 * 3);
+    }
+    for (int i = 0; i < s->opt.n_workers; ++i) s->workers.emplace_back([s] { s->worker(); });
+    *out = s;
+    return RSD_OK;
+}
+
+rsd_status rsd_server_submit_factor(rsd_server* s, const double* points, int64_t n_points,
+                                    const rsd_kernel* kernel, const double* a, double tol,
+                                    const rsd_options* opt, int64_t* factor_id) {
+    if (!s || !factor_id) return RSD_EINVAL;
+    if (opt && opt->hip_stream) return RSD_EINVAL;
+    Slot sl;
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return RSD_EDEVICE;
+    }
+    rsd_options o{};
+    if (opt) o = *opt;
+    o.hip_stream = sl.stream;
+    if (s->opt.device >= 0) o.device = s->opt.device;
+    rsd_status st = rsd_build_factor(points, n_points, kernel, a, tol, &o, &sl.f);
+    if (st != RSD_OK) {
+        (void)hipStreamDestroy(sl.stream);
+        return st;
+    }
+    rsd_factor_stats fs{};
+    (void)rsd_factor_get_stats(sl.f, &fs);
+    sl.n = n_points;
+    // the factor plus the coalescing buffers and solve vectors of a full batch
+    sl.bytes = fs.factor_bytes + (int64_t)(6 * n_points * s->opt.max_coalesce) * (int64_t)sizeof(double);
+    sl.last_use = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    while ((int64_t)s->slots.size() >= s->opt.max_slots || s->resident + sl.bytes > s->opt.mem_budget) {
+        auto victim = s->slots.end();
+        for (auto it = s->slots.begin(); it != s->slots.end(); ++it)
+            if (!it->second.busy && it->second.pending.empty() &&
+                (victim == s->slots.end() || it->second.last_use < victim->second.last_use))
+                victim = it;
+        if (victim == s->slots.end()) {
+            s->free_slot(sl);
+            return RSD_ENOMEM;
+        }
+        s->resident -= victim->second.bytes;
+        s->free_slot(victim->second);
+        s->slots.erase(victim);
+        ++s->n_evicted;
+    }
+    const int64_t id = s->next_fid++;
+    s->resident += sl.bytes;
+    s->slots.emplace(id, std::move(sl));
+    *factor_id = id;
+    return RSD_OK;
+}
+
+rsd_status rsd_server_release_factor(rsd_server* s, int64_t factor_id) {
+    if (!s) return RSD_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->slots.find(factor_id);
+    if (it == s->slots.end()) return RSD_EINVAL;
+    if (it->second.busy || !it->second.pending.empty()) return RSD_EAGAIN;
+    s->resident -= it->second.bytes;
+    s->free_slot(it->second);
+    s->slots.erase(it);
+    return RSD_OK;
+}
+
+rsd_status rsd_server_submit_solve(rsd_server* s, int64_t factor_id, const double* rhs,
+                                   int64_t nrhs, double* x, int64_t* ticket) {
+    if (!s || !ticket || !rhs || !x || nrhs <= 0) return RSD_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->slots.find(factor_id);
+    if (it == s->slots.end()) return RSD_EINVAL;
+    if (nrhs > s->opt.max_coalesce) return RSD_EINVAL;
+    const int64_t tk = s->next_ticket++;
+    Request& r = s->reqs[tk];
+    r.fid = factor_id;
+    r.rhs = rhs;
+    r.x = x;
+    r.nrhs = nrhs;
+    r.t_submit = Clock::now();
+    if (!s->started) {
+        s->started = true;
+        s->t_first = r.t_submit;
+    }
+    it->second.pending.push_back(tk);
+    ++s->n_requests;
+    *ticket = tk;
+    s->cv_work.notify_one();
+    return RSD_OK;
+}
+
+rsd_status rsd_server_wait(rsd_server* s, int64_t ticket, int32_t timeout_ms, rsd_solve_info* info) {
+    if (!s) return RSD_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return RSD_EINVAL;
+    auto is_done = [&] { return s->reqs[ticket].done; };
+    if (timeout_ms < 0) s->cv_done.wait(lk, is_done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), is_done)) return RSD_EAGAIN;
+    Request r = s->reqs[ticket];
+    s->reqs.erase(ticket);
+    if (info) *info = r.info;
+    return r.status;
+}
+
+int32_t rsd_server_poll(rsd_server* s, int64_t ticket) {
+    if (!s) return -1;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return -1;
+    return it->second.done ? 1 : 0;
+}
+
+rsd_status rsd_server_get_stats(rsd_server* s, rsd_server_stats* out) {
+    if (!s || !out) return RSD_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->n_requests = s->n_requests;
+    out->n_done = s->n_done;
+    out->n_batches = s->n_batches;
+    out->n_factors = (int64_t)s->slots.size();
+    out->n_evicted = s->n_evicted;
+    out->resident_bytes = s->resident;
+    if (!s->lat_ms.empty()) {
+        std::vector<double> v = s->lat_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) {
+            const size_t i = (size_t)std::min<double>((double)v.size() - 1, q * (double)(v.size() - 1) + 0.5);
+            return v[i];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+    }
+    out->mean_batch_rhs = s->n_batches ? (double)s->rhs_batched / (double)s->n_batches : 0.0;
+    if (s->started) {
+        const double el = std::chrono::duration<double>(Clock::now() - s->t_first).count();
+        out->rhs_per_s = el > 0 ? (double)s->rhs_done / el : 0.0;
+    }
+    return RSD_OK;
+}
+
+void rsd_server_destroy(rsd_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers) t.join();
+    for (auto& kv : s->slots) s->free_slot(kv.second);
+    delete s;
+}
+
+}  // extern "C"

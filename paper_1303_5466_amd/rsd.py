@@ -18,8 +18,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librsd.so")
 
-RSD_OK, RSD_EINVAL, RSD_ENOTGRID, RSD_ENOMEM, RSD_ESINGULAR, RSD_ENOCONV, RSD_EDEVICE = range(7)
-STATUS_NAMES = ["OK", "EINVAL", "ENOTGRID", "ENOMEM", "ESINGULAR", "ENOCONV", "EDEVICE"]
+RSD_OK, RSD_EINVAL, RSD_ENOTGRID, RSD_ENOMEM, RSD_ESINGULAR, RSD_ENOCONV, RSD_EDEVICE, RSD_EAGAIN = range(8)
+STATUS_NAMES = ["OK", "EINVAL", "ENOTGRID", "ENOMEM", "ESINGULAR", "ENOCONV", "EDEVICE", "EAGAIN"]
 RSD_KERNEL_LAPLACE, RSD_KERNEL_HELMHOLTZ = 0, 1
 RSD_PREC_FP64, RSD_PREC_FP32_REFINE = 0, 1
 RSD_FLAG_KEEP_E = 1
@@ -52,7 +52,30 @@ class rsd_box_info(C.Structure):
                 ("ay", C.c_int32), ("k", C.c_int32), ("r", C.c_int32), ("parent", C.c_int32)]
 
 
+class rsd_server_options(C.Structure):
+    _fields_ = [("mem_budget", C.c_int64), ("max_slots", C.c_int32), ("n_workers", C.c_int32),
+                ("max_coalesce", C.c_int32), ("device", C.c_int32)]
+
+
+class rsd_server_stats(C.Structure):
+    _fields_ = [("n_requests", C.c_int64), ("n_done", C.c_int64), ("n_batches", C.c_int64),
+                ("n_factors", C.c_int64), ("n_evicted", C.c_int64), ("resident_bytes", C.c_int64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_batch_rhs", C.c_double),
+                ("rhs_per_s", C.c_double)]
+
+
 EXPORTS = {
+    "rsd_server_create": (C.c_int, [C.POINTER(rsd_server_options), C.POINTER(C.c_void_p)]),
+    "rsd_server_submit_factor": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(rsd_kernel),
+                                           C.c_void_p, C.c_double, C.POINTER(rsd_options),
+                                           C.POINTER(C.c_int64)]),
+    "rsd_server_release_factor": (C.c_int, [C.c_void_p, C.c_int64]),
+    "rsd_server_submit_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                          C.POINTER(C.c_int64)]),
+    "rsd_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(rsd_solve_info)]),
+    "rsd_server_poll": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "rsd_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(rsd_server_stats)]),
+    "rsd_server_destroy": (None, [C.c_void_p]),
     "rsd_build_factor": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(rsd_kernel), C.c_void_p,
                                    C.c_double, C.POINTER(rsd_options), C.POINTER(C.c_void_p)]),
     "rsd_build_factor_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
@@ -105,7 +128,7 @@ def load():
 
 class RsdError(RuntimeError):
     def __init__(self, status, msg):
-        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
         self.status = status
 
 
@@ -260,6 +283,78 @@ def build_batched(points_list, a_list=None, tol=1e-10, precision=RSD_PREC_FP64, 
     _check(lib.rsd_build_factor_batched(n_inst, pts_p, npts, C.byref(kd), a_p, tol, C.byref(opt),
                                         max_inflight, out))
     return [Factor._adopt(C.c_void_p(out[i]), int(npts[i])) for i in range(n_inst)]
+
+
+class Server:
+    """Resident factors + queued, coalesced solves (rsd_server_*).  Buffers
+    passed to submit_solve are kept alive here until their ticket is waited."""
+
+    def __init__(self, mem_budget=0, max_slots=0, n_workers=0, max_coalesce=0, device=-1):
+        lib = load()
+        h = C.c_void_p()
+        opt = rsd_server_options(mem_budget, max_slots, n_workers, max_coalesce, device)
+        _check(lib.rsd_server_create(C.byref(opt), C.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def submit_factor(self, points, a=None, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0,
+                      layers=0, max_refine=0, refine_tol=0.0):
+        if isinstance(points, np.ndarray):
+            points = np.ascontiguousarray(points, dtype=np.float64)
+        if isinstance(a, np.ndarray):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+        pp, _k1 = _ptr(points)
+        ap, _k2 = _ptr(a)
+        kd = rsd_kernel(RSD_KERNEL_LAPLACE, 0.0, None)
+        opt = rsd_options(leaf_side, layers, precision, max_refine, refine_tol, None, -1, 0)
+        fid = C.c_int64()
+        _check(load().rsd_server_submit_factor(self._h, pp, points.shape[0], C.byref(kd), ap, tol,
+                                               C.byref(opt), C.byref(fid)))
+        return fid.value
+
+    def release_factor(self, fid):
+        _check(load().rsd_server_release_factor(self._h, fid))
+
+    def submit_solve(self, fid, rhs, out):
+        """rhs, out: N x nrhs column-major float64 (NumPy Fortran order or a
+        contiguous torch tensor of shape (nrhs, N))."""
+        if isinstance(rhs, np.ndarray):
+            nrhs = 1 if rhs.ndim == 1 else rhs.shape[1]
+        else:
+            nrhs = 1 if rhs.dim() == 1 else rhs.shape[0]
+        tk = C.c_int64()
+        _check(load().rsd_server_submit_solve(self._h, fid, _ptr(rhs)[0], nrhs, _ptr(out)[0],
+                                              C.byref(tk)))
+        self._live[tk.value] = (rhs, out)
+        return tk.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        """(status, rsd_solve_info); status EAGAIN on timeout."""
+        info = rsd_solve_info()
+        st = load().rsd_server_wait(self._h, ticket, timeout_ms, C.byref(info))
+        if st != RSD_EAGAIN:
+            self._live.pop(ticket, None)
+        return st, info
+
+    def poll(self, ticket):
+        return load().rsd_server_poll(self._h, ticket)
+
+    def stats(self):
+        s = rsd_server_stats()
+        _check(load().rsd_server_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in rsd_server_stats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            load().rsd_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

@@ -298,3 +298,64 @@ def test_batched_build_reports_failing_instance():
         rsd.build_batched([good, bad, good], None, tol=1e-10)
     assert ei.value.status == rsd.RSD_ENOTGRID
     assert "instance 1" in str(ei.value)
+
+
+# --- serving: resident factors, queued and coalesced solves ------------------------
+def test_server_coalesced_solves_match_dense():
+    srv = rsd.Server(n_workers=1, max_coalesce=16)
+    grids = [W.grid_points(24), W.grid_points(32, 40), W.grid_points(48)]
+    rng = np.random.default_rng(31)
+    coefs = [W.coef_bumps(p, rng) for p in grids]
+    fids = [srv.submit_factor(p, a, tol=1e-10) for p, a in zip(grids, coefs)]
+    reqs = []
+    for i in range(30):
+        g, nr = i % 3, 1 + (i % 4) // 2
+        f = np.asfortranarray(rng.standard_normal((grids[g].shape[0], nr)))
+        if i % 5 == 0:      # device buffers: (nrhs, N) contiguous = N x nrhs column-major
+            fd = _dev(f.T)
+            xd = torch.empty_like(fd)
+            reqs.append((g, f, xd, srv.submit_solve(fids[g], fd, xd)))
+        else:
+            x = np.zeros_like(f, order="F")
+            reqs.append((g, f, x, srv.submit_solve(fids[g], f, x)))
+    for g, f, x, tk in reqs:
+        st, info = srv.wait(tk)
+        assert st == rsd.RSD_OK
+        xs = x if isinstance(x, np.ndarray) else x.cpu().numpy().T
+        assert dense.rel_error(xs, dense.solve(grids[g], f, coefs[g])) < 1e-10
+    s = srv.stats()
+    assert s["n_done"] == 30 and s["n_requests"] == 30
+    assert s["n_batches"] < 30          # requests waiting together were coalesced
+    assert 0 < s["p50_ms"] <= s["p99_ms"]
+    assert s["n_factors"] == 3
+    srv.close()
+
+
+def test_server_admission_and_errors():
+    srv = rsd.Server(max_slots=2)
+    p16, p20, p24 = W.grid_points(16), W.grid_points(20), W.grid_points(24)
+    fa = srv.submit_factor(p16)
+    fb = srv.submit_factor(p20)
+    fc = srv.submit_factor(p24)            # evicts the least recently used idle factor (fa)
+    s = srv.stats()
+    assert s["n_factors"] == 2 and s["n_evicted"] == 1
+    f = np.ones((p16.shape[0], 1), order="F")
+    x = np.zeros_like(f)
+    with pytest.raises(rsd.RsdError) as ei:
+        srv.submit_solve(fa, f, x)
+    assert ei.value.status == rsd.RSD_EINVAL
+    st, _ = srv.wait(123456)
+    assert st == rsd.RSD_EINVAL
+    f20 = np.ones((p20.shape[0], 1), order="F")
+    x20 = np.zeros_like(f20)
+    tk = srv.submit_solve(fb, f20, x20)
+    st, info = srv.wait(tk, timeout_ms=60000)
+    assert st == rsd.RSD_OK
+    # a served factor is the one rsd_build_factor builds: same solution bits
+    direct = rsd.Factor(p20, None, 1e-10)
+    xd, _ = direct.solve(f20)
+    assert np.array_equal(x20, xd)
+    direct.close()
+    srv.release_factor(fc)
+    assert srv.stats()["n_factors"] == 1
+    srv.close()
