@@ -95,6 +95,53 @@ def batched_measure(torch, rsd, W, reps=2):
             "ms_per_batch": dt * 1e3, "unknowns_per_s": n_tot / dt, "max_rel_residual": worst}
 
 
+def serving_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4):
+    """Resident Laplace factors of sides 128 and 256 (float64, tol 1e-10);
+    single-RHS solve requests arrive as a Poisson process (rate per second)
+    on uniformly chosen factors, device buffers; returns latency percentiles
+    and throughput from the server's own statistics."""
+    rng = np.random.default_rng(seed)
+    dev = torch.device("cuda:0")
+    srv = rsd.Server(n_workers=2, max_coalesce=64)
+    sides = (128, 256)
+    fids, sizes = [], []
+    for n in sides:
+        pts = W.grid_points(n)
+        fids.append(srv.submit_factor(torch.from_numpy(pts).to(dev), torch.from_numpy(W.coef_sine(pts)).to(dev),
+                                      tol=1e-10))
+        sizes.append(pts.shape[0])
+    # request pool prepared up front (inputs resident in HBM)
+    pool = []
+    for i in range(64):
+        g = i % len(sides)
+        f = torch.from_numpy(rng.standard_normal((1, sizes[g]))).to(dev)
+        pool.append((g, f, torch.empty_like(f)))
+    torch.cuda.synchronize()
+    tickets = []
+    t0 = time.perf_counter()
+    t_next = t0
+    k = 0
+    while t_next - t0 < seconds:
+        now = time.perf_counter()
+        if now < t_next:
+            time.sleep(min(t_next - now, 0.002))
+            continue
+        g, f, x = pool[k % len(pool)]
+        tickets.append(srv.submit_solve(fids[g], f, x))
+        k += 1
+        t_next += rng.exponential(1.0 / rate)
+    bad = 0
+    for tk in tickets:
+        st, _ = srv.wait(tk)
+        bad += st != rsd.RSD_OK
+    st = srv.stats()
+    srv.close()
+    return {"workload": f"Poisson arrivals {rate:.0f}/s for {seconds:.0f} s, 1 RHS each, resident Laplace "
+                        f"factors of sides {list(sides)} (float64, tol 1e-10)",
+            "requests": st["n_done"], "failed": bad, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "mean_batch_rhs": st["mean_batch_rhs"], "rhs_per_s": st["rhs_per_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +152,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-solves", type=int, default=30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-grid measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -228,6 +276,12 @@ def main():
         out["batched"] = batched_measure(torch, rsd, W)
         log(f"  {out['batched']['ms_per_batch']:.1f} ms per batch, "
             f"{out['batched']['unknowns_per_s']:.4g} unknowns/s, residual {out['batched']['max_rel_residual']:.2e}")
+    if not args.no_serving and args.workload == "laplace256":
+        log("serving loop: Poisson solve requests on resident factors ...")
+        out["serving"] = serving_measure(torch, rsd, W)
+        sv = out["serving"]
+        log(f"  {sv['requests']} requests, p50 {sv['p50_ms']:.2f} ms, p99 {sv['p99_ms']:.2f} ms, "
+            f"{sv['mean_batch_rhs']:.2f} RHS per coalesced solve")
     if not args.no_cpu_baseline:
         log("timing the CPU reference on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(pts, a, f)
