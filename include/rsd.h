@@ -54,7 +54,10 @@ typedef enum rsd_kernel_type {
  * the Nystrom rule of Sec. 5 with b = c = 1 and the exact integral of the
  * kernel over the point's own cell on the diagonal.  With contrast_b given
  * (N values, b >= 0) it is the scattering operator of Sec. 5.4:
- *   A_ij = sqrt(b_i) h^2 G(|x_i - x_j|) sqrt(b_j),  A_ii = 1 + b_i int_cell G. */
+ *   A_ij = sqrt(b_i) h^2 G(|x_i - x_j|) sqrt(b_j),  A_ii = 1 + b_i int_cell G.
+ * This library version builds factors for the Laplace kernel without a
+ * contrast only: RSD_KERNEL_HELMHOLTZ and a non-NULL contrast_b make
+ * rsd_build_factor fail with EINVAL (the CPU reference covers both). */
 typedef struct rsd_kernel {
     int32_t type;              /* rsd_kernel_type                           */
     double wavenumber;         /* k of the Helmholtz kernel; ignored else   */

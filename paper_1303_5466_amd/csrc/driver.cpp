@@ -762,6 +762,9 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
             if (!std::isfinite(v)) throw Error(RSD_EINVAL, "non-finite value in a");
     }
     const double* bptr = kernel ? kernel->contrast_b : nullptr;
+    // the scattering form (sqrt(b) K sqrt(b), Sec. 5.4) needs a per-box scaling
+    // of T that the device level pipeline does not apply
+    if (bptr) throw Error(RSD_EINVAL, "the contrast (scattering) form is not available on the device path");
     if (bptr) {
         bh.resize(n);
         if (is_device_ptr(bptr)) RSD_HIP(hipMemcpy(bh.data(), bptr, n * sizeof(double), hipMemcpyDeviceToHost));

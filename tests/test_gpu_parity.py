@@ -160,19 +160,24 @@ def test_matvec_matches_reference():
     assert np.abs(y - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
 
 
-@pytest.mark.parametrize("nx,ny,contrast", [(33, 21, True), (600, 7, False), (1500, 3, False),
-                                             (2050, 3, False)])
-def test_fft_product_sizes_and_contrast(nx, ny, contrast):
+@pytest.mark.parametrize("nx,ny", [(33, 21), (600, 7), (1500, 3), (2050, 3)])
+def test_fft_product_sizes(nx, ny):
     # circulant FFT product: 128x64, 2048x16 (4-line workgroups), 4096x8 (one
     # line per workgroup) and, past 4096, the direct-sum fallback
     pts = W.grid_points(nx, ny)
     a = W.coef_sine(pts)
-    b = (0.2 + W.coef_sine(pts)) if contrast else None
     s = W.rhs_normal(len(pts), 3, 11)
-    fac = rsd.Factor(pts, None if contrast else a, 1e-10, contrast=b)
+    fac = rsd.Factor(pts, a, 1e-10)
     y = fac.matvec(s)
-    y_ref = nystrom.matvec_direct(pts, s, None if contrast else a, bvec=b)
+    y_ref = nystrom.matvec_direct(pts, s, a)
     assert np.abs(y - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
+
+
+def test_contrast_form_is_rejected_on_device():
+    pts = W.grid_points(16)
+    with pytest.raises(rsd.RsdError) as ei:
+        rsd.Factor(pts, None, 1e-10, contrast=W.contrast_bump(pts))
+    assert ei.value.status == rsd.RSD_EINVAL
 
 
 def test_fp32_refined_matches_dense():
