@@ -86,6 +86,10 @@ typedef struct rsd_options {
 
 /* Keep every box's E_i block after the build (for inspection). */
 #define RSD_FLAG_KEEP_E 1
+/* Solve every interpolation problem whole, without splitting mirror-symmetric
+ * box types into their four symmetry sectors (same T up to rounding for
+ * full-rank problems; for testing and comparison). */
+#define RSD_FLAG_NO_SYMMETRY 2
 
 typedef struct rsd_solve_info {
     int32_t refine_iters;  /* refinement steps taken                          */

@@ -103,10 +103,22 @@ template <typename T>
 void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes, int max_k,
                          int max_r, hipStream_t s);
 template <typename T>
+// geo per problem: ax, ay, sector (-1: plain problem; 0..3: symmetry sector
+// ab = a + 2b, entries summed over the four reflections with signs (-1)^(a gx + b gy))
 void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* k_of,
                          const int* r_of, const int* zoff, const int* zu, const int* zv,
-                         const int* xoff, const int* lu, const int* lv, int n_problems,
+                         const int* xoff, const int* xu, const int* xv, const int* geo, int n_problems,
                          int max_pn, KernelDesc kd, hipStream_t s);
+// T of every symmetric box type from its four sector solutions (see k_gen.hip)
+struct SymCombineDesc {
+    int64_t offT;      // layout T (k x r, ld k) in the T arena
+    int64_t offS;      // sector ab block (k/4 x r/4, ld k/4) at offS + ab k r / 16
+    int k, r;
+    int off_sk, off_rs;   // into the orbit / reflection tables
+};
+template <typename T>
+void launch_sym_combine(T* Tarena, const T* Tsec, const SymCombineDesc* d, int n_desc,
+                        const int* orb, const int* refl, int max_kr, hipStream_t s);
 
 // QR least squares for T (block column pivoting)
 constexpr int QR_NB = 16;     // largest sub-panel width
@@ -114,8 +126,9 @@ constexpr int QR_WIN = 64;    // pivoting window / block width of the trailing u
 constexpr int QR_RC = 256;    // row chunk of the split-K reflector products
 struct QRProblemDev {
     int p, k, r, nb;   // nb: sub-panel width (16, 8, 4 or 2 by the LDS budget)
+    int sec;           // -1: output to the T arena; else a symmetry sector (output to the sector arena)
     int64_t offA;      // p x (k + r) matrix, ld = p
-    int64_t offT;      // output T (k x r), ld = k
+    int64_t offT;      // output T (k x r), ld = k, in the arena sec selects
     int64_t offAux;    // norms (k), tau (k), sub-panel WY (QR_NB^2), window WY (QR_WIN^2), r11
     int64_t offIaux;   // perm (k), state (8), moves (4 * QR_WIN)
     int64_t offV;      // V workspace p x QR_WIN (unit lower trapezoidal)
@@ -148,7 +161,7 @@ void launch_qr_norms(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_p
                      int max_k, hipStream_t s);
 int qr_panel_width(int p, int elem_bytes);   // sub-panel width for a p-row problem
 template <typename T>
-void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
+void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, T* Tsec, const QRProblemDev* probs,
                     const int* plist, int n_probs, int max_r, int step, hipStream_t s);
 
 // Gauss-Jordan pivot step (see gj kernels)

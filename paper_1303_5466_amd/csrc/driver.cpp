@@ -306,6 +306,17 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 // ----------------------------------------------------------------------------
 // interpolation matrices for every box type (one problem per layout)
 // ----------------------------------------------------------------------------
+// The symmetry split is used where the proxy problems are full rank (float64
+// factors at tol <= 1e-9; measured rank = k at every level of the benchmark
+// grids), so the four sector solutions are the whole problem's unique
+// least-squares solution up to rounding.  Where truncation decides the rank
+// (float32 factors, looser tolerances) the whole problem is solved: the
+// window pivoting's truncation test sees only a sub-panel's columns, and on
+// the small sector problems that stops too early.
+static bool split_sym(const Factor& f, const IDProblem& I, int prec) {
+    return I.sym && prec == 0 && f.tol <= 1e-9;
+}
+
 // One chain of interpolation problems: every problem of the chain advances
 // window by window through the same launches on the chain's stream, and the
 // problems finished after a window get their back substitution on the
@@ -320,7 +331,11 @@ struct QRChain {
     std::vector<int> prob_level;
     int S = 0, np = 0, max_k = 0, max_n = 0, max_nch = 0, max_subs = 0;
     DevBuf *dA = nullptr, *daux = nullptr, *diaux = nullptr, *dws = nullptr, *dq = nullptr,
-           *dlist = nullptr, *dsolve = nullptr;
+           *dlist = nullptr, *dsolve = nullptr, *dsec = nullptr, *dcomb = nullptr, *dorb = nullptr,
+           *drefl = nullptr;
+    std::vector<int64_t> sym_sec0;     // sector-arena offset of every symmetric problem
+    std::vector<int> comb_off;         // combine descriptors per window
+    int comb_max_kr = 0;
     std::vector<GemmBatch<T>> g1, gt, g2;
     std::vector<std::vector<GemmBatch<T>>> gsolve;
     std::vector<int> lists[4];
@@ -335,56 +350,122 @@ struct QRChain {
         s = stream;
         Plan& P = f->plan;
         std::vector<int64_t> offA;
-        std::vector<int> pof, kof, rof, zoff, xoff, zu, zv;
-        int64_t A_el = 0, aux_el = 0, iaux_el = 0, ws_el = 0;
+        std::vector<int> pof, kof, rof, zoff, xoff, zu, zv, xu, xv, geo;
+        int64_t A_el = 0, aux_el = 0, iaux_el = 0, ws_el = 0, sec_el = 0;
         int max_pn = 0, max_r = 0;
-        prob_level = levels;
-        for (int id : probs_ids) {
+        // a symmetric interpolation problem becomes its four sector problems
+        // (orbit representatives; their solutions are combined into T after
+        // the back substitution)
+        std::vector<int> sym_ids;
+        for (size_t pi = 0; pi < probs_ids.size(); ++pi) {
+            const int id = probs_ids[pi];
             const IDProblem& I = P.idps[id];
-            QRProblemDev q;
-            q.p = I.p; q.k = I.k; q.r = I.r;
-            q.nb = qr_panel_width(I.p, (int)sizeof(T));
-            if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
-            const int n = I.k + I.r;
-            const int nch = (I.p + QR_RC - 1) / QR_RC;
-            q.offA = A_el;
-            q.offT = f->hlayouts[I.layout].offT;
-            q.offAux = aux_el;
-            q.offIaux = iaux_el;
-            q.offV = ws_el;
-            q.offTmp = q.offV + (int64_t)I.p * QR_WIN;
-            q.offW = q.offTmp + (int64_t)I.p * 2 * QR_WIN;
-            q.offWs = q.offW + (int64_t)nch * QR_WIN * (QR_WIN + n);
-            ws_el = q.offWs + (int64_t)QR_WIN * (QR_WIN + n);
-            A_el += (int64_t)I.p * n;
-            aux_el += 2 * I.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
-            iaux_el += I.k + 8 + 4 * QR_WIN;
-            qp.push_back(q);
-            offA.push_back(q.offA);
-            pof.push_back(I.p); kof.push_back(I.k); rof.push_back(I.r);
-            zoff.push_back((int)zu.size());
-            zu.insert(zu.end(), I.zu.begin(), I.zu.end());
-            zv.insert(zv.end(), I.zv.begin(), I.zv.end());
-            xoff.push_back(f->hlayouts[I.layout].off_uv);
-            max_pn = std::max(max_pn, I.p * n);
-            max_k = std::max(max_k, I.k);
-            max_r = std::max(max_r, I.r);
-            max_n = std::max(max_n, n);
-            max_nch = std::max(max_nch, nch);
-            S = std::max(S, (I.k + QR_WIN - 1) / QR_WIN);
+            const Layout& L = P.layouts[I.layout];
+            const bool sym = split_sym(*f, I, std::is_same<T, double>::value ? 0 : 1);
+            const int nsec = sym ? 4 : 1;
+            const int64_t sec0 = sec_el;
+            if (sym) {
+                sec_el += (int64_t)I.k * I.r / 4;
+                sym_ids.push_back(id);
+                sym_sec0.push_back(sec0);
+            }
+            for (int sc = 0; sc < nsec; ++sc) {
+                QRProblemDev q;
+                q.p = sym ? I.p / 4 : I.p;
+                q.k = sym ? I.k / 4 : I.k;
+                q.r = sym ? I.r / 4 : I.r;
+                q.sec = sym ? sc : -1;
+                q.nb = qr_panel_width(q.p, (int)sizeof(T));
+                if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
+                const int n = q.k + q.r;
+                const int nch = (q.p + QR_RC - 1) / QR_RC;
+                q.offA = A_el;
+                q.offT = sym ? sec0 + (int64_t)sc * q.k * q.r : f->hlayouts[I.layout].offT;
+                q.offAux = aux_el;
+                q.offIaux = iaux_el;
+                q.offV = ws_el;
+                q.offTmp = q.offV + (int64_t)q.p * QR_WIN;
+                q.offW = q.offTmp + (int64_t)q.p * 2 * QR_WIN;
+                q.offWs = q.offW + (int64_t)nch * QR_WIN * (QR_WIN + n);
+                ws_el = q.offWs + (int64_t)QR_WIN * (QR_WIN + n);
+                A_el += (int64_t)q.p * n;
+                aux_el += 2 * q.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
+                iaux_el += q.k + 8 + 4 * QR_WIN;
+                qp.push_back(q);
+                prob_level.push_back(levels[pi]);
+                offA.push_back(q.offA);
+                pof.push_back(q.p); kof.push_back(q.k); rof.push_back(q.r);
+                zoff.push_back((int)zu.size());
+                xoff.push_back((int)xu.size());
+                if (sym) {
+                    zu.insert(zu.end(), I.zr_u.begin(), I.zr_u.end());
+                    zv.insert(zv.end(), I.zr_v.begin(), I.zr_v.end());
+                    xu.insert(xu.end(), I.skr_u.begin(), I.skr_u.end());
+                    xu.insert(xu.end(), I.rsr_u.begin(), I.rsr_u.end());
+                    xv.insert(xv.end(), I.skr_v.begin(), I.skr_v.end());
+                    xv.insert(xv.end(), I.rsr_v.begin(), I.rsr_v.end());
+                } else {
+                    zu.insert(zu.end(), I.zu.begin(), I.zu.end());
+                    zv.insert(zv.end(), I.zv.begin(), I.zv.end());
+                    xu.insert(xu.end(), L.u.begin(), L.u.end());
+                    xv.insert(xv.end(), L.v.begin(), L.v.end());
+                }
+                geo.push_back(L.ax); geo.push_back(L.ay); geo.push_back(q.sec);
+                max_pn = std::max(max_pn, q.p * n);
+                max_k = std::max(max_k, q.k);
+                max_r = std::max(max_r, q.r);
+                max_n = std::max(max_n, n);
+                max_nch = std::max(max_nch, nch);
+                S = std::max(S, (q.k + QR_WIN - 1) / QR_WIN);
+            }
         }
         np = (int)qp.size();
         DevBuf &doffA = f->tmp(), &dp = f->tmp(), &dk = f->tmp(), &dr = f->tmp(), &dzo = f->tmp(),
-               &dzu = f->tmp(), &dzv = f->tmp(), &dxo = f->tmp(), &dgemm = f->tmp();
+               &dzu = f->tmp(), &dzv = f->tmp(), &dxo = f->tmp(), &dxu = f->tmp(), &dxv = f->tmp(),
+               &dgeo = f->tmp(), &dgemm = f->tmp();
         dA = &f->tmp(); daux = &f->tmp(); diaux = &f->tmp(); dws = &f->tmp(); dq = &f->tmp();
-        dlist = &f->tmp(); dsolve = &f->tmp();
+        dlist = &f->tmp(); dsolve = &f->tmp(); dsec = &f->tmp();
         dA->alloc(A_el * sizeof(T));
         daux->alloc(aux_el * sizeof(T));
         diaux->alloc(iaux_el * sizeof(int));
         dws->alloc(ws_el * sizeof(T));
+        dsec->alloc(std::max<int64_t>(sec_el, 1) * sizeof(T));
         upload(*dq, qp, s); upload(doffA, offA, s); upload(dp, pof, s); upload(dk, kof, s);
         upload(dr, rof, s); upload(dzo, zoff, s); upload(dzu, zu, s); upload(dzv, zv, s);
-        upload(dxo, xoff, s);
+        upload(dxo, xoff, s); upload(dxu, xu, s); upload(dxv, xv, s); upload(dgeo, geo, s);
+        // combination of sector solutions, grouped by the window after which
+        // the sectors are complete
+        {
+            std::vector<int> orb, refl;
+            std::vector<std::vector<SymCombineDesc>> by_win;
+            for (size_t si = 0; si < sym_ids.size(); ++si) {
+                const IDProblem& I = P.idps[sym_ids[si]];
+                SymCombineDesc cd;
+                cd.offT = f->hlayouts[I.layout].offT;
+                cd.offS = sym_sec0[si];
+                cd.k = I.k;
+                cd.r = I.r;
+                cd.off_sk = (int)orb.size();
+                orb.insert(orb.end(), I.sk_orb.begin(), I.sk_orb.end());
+                refl.insert(refl.end(), I.sk_g.begin(), I.sk_g.end());
+                cd.off_rs = (int)orb.size();
+                orb.insert(orb.end(), I.rs_orb.begin(), I.rs_orb.end());
+                refl.insert(refl.end(), I.rs_g.begin(), I.rs_g.end());
+                const int w = (I.k / 4 + QR_WIN - 1) / QR_WIN - 1;
+                if ((int)by_win.size() <= w) by_win.resize(w + 1);
+                by_win[w].push_back(cd);
+                comb_max_kr = std::max(comb_max_kr, I.k * I.r);
+            }
+            std::vector<SymCombineDesc> flatc;
+            comb_off.assign(S + 1, 0);
+            for (int w = 0; w < S; ++w) {
+                comb_off[w] = (int)flatc.size();
+                if (w < (int)by_win.size()) flatc.insert(flatc.end(), by_win[w].begin(), by_win[w].end());
+            }
+            comb_off[S] = (int)flatc.size();
+            dcomb = &f->tmp(); dorb = &f->tmp(); drefl = &f->tmp();
+            upload(*dcomb, flatc, s); upload(*dorb, orb, s); upload(*drefl, refl, s);
+        }
         // trailing-update products of every window, guarded by the problem's skip flag
         T* Ab = dA->as<T>();
         T* W = dws->as<T>();
@@ -486,7 +567,7 @@ struct QRChain {
         qr_tol = std::is_same<T, float>::value ? std::max(f->tol, 1e-6) : f->tol;
         launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
                                dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
-                               dxo.as<int>(), f->d_lu.as<int>(), f->d_lv.as<int>(), np,
+                               dxo.as<int>(), dxu.as<int>(), dxv.as<int>(), dgeo.as<int>(), np,
                                max_pn, f->kd, s);
         launch_qr_init<T>(Ab, daux->as<T>(), diaux->as<int>(), dq->as<QRProblemDev>(), np, max_k, s);
     }
@@ -527,9 +608,12 @@ struct QRChain {
         int gr = 0;
         for (int g = soff[sw]; g < soff[sw + 1]; ++g) gr = std::max(gr, qp[sflat[g]].r);
         for (int st = 0; st < (int)gsolve[sw].size(); ++st) {
-            launch_qr_trsm<T>(Ab, aux, iaux, Tbase<T>(*f), q, dsolve->as<int>() + soff[sw], ng, gr, st, s);
+            launch_qr_trsm<T>(Ab, aux, iaux, Tbase<T>(*f), dsec->as<T>(), q, dsolve->as<int>() + soff[sw], ng,
+                              gr, st, s);
             gsolve[sw][st].run(s);
         }
+        launch_sym_combine<T>(Tbase<T>(*f), dsec->as<T>(), dcomb->as<SymCombineDesc>() + comb_off[sw],
+                              comb_off[sw + 1] - comb_off[sw], dorb->as<int>(), drefl->as<int>(), comb_max_kr, s);
         hipEvent_t solved;
         RSD_HIP(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
         RSD_HIP(hipEventRecord(solved, s));
@@ -784,6 +868,8 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         throw Error(RSD_EINVAL, e.what());
     }
     Plan& P = f->plan;
+    if (o.flags & RSD_FLAG_NO_SYMMETRY)
+        for (auto& I : P.idps) I.sym = false;
     const int nlev = (int)P.levels.size();
     f->top = nlev - 1;
     f->level_prec.assign(nlev, 0);
@@ -953,10 +1039,12 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         if (P.layouts[li].idp < 0) continue;
         const int lev = layout_level[li];
         const int pr = f->level_prec[lev];
-        const int narrow = qr_panel_width(P.idps[P.layouts[li].idp].p, pr ? 4 : 8) < 16 ? 1 : 0;
+        const IDProblem& I = P.idps[P.layouts[li].idp];
+        const bool sym = split_sym(*f, I, pr);
+        const int narrow = qr_panel_width(sym ? I.p / 4 : I.p, pr ? 4 : 8) < 16 ? 1 : 0;
         cp[pr][narrow].push_back(P.layouts[li].idp);
         cl[pr][narrow].push_back(lev);
-        ++pending[lev];
+        pending[lev] += sym ? 4 : 1;     // one per (sector) problem
     }
     std::vector<std::vector<hipEvent_t>> level_waits(nlev);
     // levels are enqueued as soon as the events of their box types exist, so the
@@ -1011,8 +1099,9 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     for (auto* b : b64) fl += b->flops;
     for (auto* b : b32) fl += b->flops;
     for (auto& I : P.idps) {
-        const double p = I.p, k = I.k, r = I.r;
-        fl += 2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r;
+        const double ns = split_sym(*f, I, f->level_prec[layout_level[I.layout]]) ? 4 : 1;
+        const double p = I.p / ns, k = I.k / ns, r = I.r / ns;
+        fl += ns * (2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r);
     }
     st.factor_flops = fl;
     double sb = 0;
@@ -1284,7 +1373,7 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
             worst = 0;
             for (int c = 0; c < nrhs; ++c) {
                 const double rel = fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]);
-                worst = std::max(worst, rel);
+                if (!(rel <= worst)) worst = rel;      // a NaN residual stays NaN (never converged)
             }
             if (worst <= f.refine_tol || it >= f.max_refine) break;
             apply_inverse(f, sp, rg, dg, f.d_ident.as<int64_t>());

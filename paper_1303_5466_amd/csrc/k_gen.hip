@@ -114,22 +114,65 @@ __global__ void __launch_bounds__(256) assemble_kernel(
     }
 }
 
+// Proxy matrix [K(Z, X^sk) | K(Z, X^rs)] of every interpolation problem
+// (p x (k + r), ld p).  For a symmetry sector ab (geo[3 pb + 2] >= 0) rows and
+// columns are orbit representatives and an entry is the sector's block of the
+// kernel in the symmetry-adapted basis: sum over the four reflections g of
+// (-1)^(a gx + b gy) K(z - g x), evaluated in float64.
 template <typename T>
 __global__ void __launch_bounds__(256) proxy_kernel(
     T* __restrict__ A, const int64_t* __restrict__ offA, const int* __restrict__ p_of,
     const int* __restrict__ k_of, const int* __restrict__ r_of, const int* __restrict__ zoff,
     const int* __restrict__ zu, const int* __restrict__ zv, const int* __restrict__ xoff,
-    const int* __restrict__ lu, const int* __restrict__ lv, KernelDesc kd) {
+    const int* __restrict__ xu, const int* __restrict__ xv, const int* __restrict__ geo,
+    KernelDesc kd) {
     const int pb = blockIdx.y;
     const int p = p_of[pb], n = k_of[pb] + r_of[pb];
+    const int ax = geo[3 * pb], ay = geo[3 * pb + 1], sec = geo[3 * pb + 2];
     T* Ab = A + offA[pb];
     const int* ZU = zu + zoff[pb];
     const int* ZV = zv + zoff[pb];
-    const int* XU = lu + xoff[pb];
-    const int* XV = lv + xoff[pb];
+    const int* XU = xu + xoff[pb];
+    const int* XV = xv + xoff[pb];
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)p * n; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % p), j = (int)(e / p);
-        Ab[e] = KV<T>::proxy(kd, ZU[i] - XU[j], ZV[i] - XV[j]);
+        if (sec < 0) {
+            Ab[e] = KV<T>::proxy(kd, ZU[i] - XU[j], ZV[i] - XV[j]);
+        } else {
+            const int u = XU[j], v = XV[j], um = ax - 1 - u, vm = ay - 1 - v;
+            const double sa = (sec & 1) ? -1.0 : 1.0, sb = (sec & 2) ? -1.0 : 1.0;
+            const double val = KV<double>::proxy(kd, ZU[i] - u, ZV[i] - v) +
+                               sa * KV<double>::proxy(kd, ZU[i] - um, ZV[i] - v) +
+                               sb * KV<double>::proxy(kd, ZU[i] - u, ZV[i] - vm) +
+                               sa * sb * KV<double>::proxy(kd, ZU[i] - um, ZV[i] - vm);
+            Ab[e] = T(val);
+        }
+    }
+}
+
+// T of a symmetric box type from its sector solutions T^ab (orbit indices):
+// T[i, j] = 1/4 sum_ab chi_ab(g_i) chi_ab(h_j) T^ab[orb_i, orb_j], with
+// chi_ab(g) = (-1)^popcount(ab & g) (the symmetry-adapted basis is orthonormal).
+template <typename T>
+__global__ void __launch_bounds__(256) sym_combine_kernel(T* __restrict__ Ta, const T* __restrict__ Ts,
+                                                          const SymCombineDesc* __restrict__ descs,
+                                                          const int* __restrict__ orb,
+                                                          const int* __restrict__ refl) {
+    const SymCombineDesc d = descs[blockIdx.y];
+    const int k4 = d.k / 4, r4 = d.r / 4;
+    const int64_t blk = (int64_t)k4 * r4;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)d.k * d.r; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e % d.k), j = (int)(e / d.k);
+        const int oi = orb[d.off_sk + i], gi = refl[d.off_sk + i];
+        const int oj = orb[d.off_rs + j], gj = refl[d.off_rs + j];
+        const int64_t at = oi + (int64_t)oj * k4;
+        T acc = T(0);
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+            const T v = Ts[d.offS + ab * blk + at];
+            acc += (__popc(ab & (gi ^ gj)) & 1) ? -v : v;
+        }
+        Ta[d.offT + i + (int64_t)j * d.k] = T(0.25) * acc;
     }
 }
 
@@ -191,13 +234,25 @@ void launch_assemble_F(TD* F, const TS* Fchild, const BoxDev* boxes, const int* 
 template <typename T>
 void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* k_of,
                          const int* r_of, const int* zoff, const int* zu, const int* zv,
-                         const int* xoff, const int* lu, const int* lv, int n_problems,
+                         const int* xoff, const int* xu, const int* xv, const int* geo, int n_problems,
                          int max_pn, KernelDesc kd, hipStream_t s) {
     if (n_problems <= 0) return;
     dim3 grid(chunks_for(max_pn), n_problems);
     hipLaunchKernelGGL(proxy_kernel<T>, grid, dim3(256), 0, s, A, offA, p_of, k_of, r_of, zoff, zu,
-                       zv, xoff, lu, lv, kd);
+                       zv, xoff, xu, xv, geo, kd);
 }
+
+template <typename T>
+void launch_sym_combine(T* Tarena, const T* Tsec, const SymCombineDesc* d, int n_desc,
+                        const int* orb, const int* refl, int max_kr, hipStream_t s) {
+    if (n_desc <= 0) return;
+    dim3 grid(chunks_for(max_kr), n_desc);
+    hipLaunchKernelGGL(sym_combine_kernel<T>, grid, dim3(256), 0, s, Tarena, Tsec, d, orb, refl);
+}
+template void launch_sym_combine<double>(double*, const double*, const SymCombineDesc*, int, const int*,
+                                         const int*, int, hipStream_t);
+template void launch_sym_combine<float>(float*, const float*, const SymCombineDesc*, int, const int*,
+                                        const int*, int, hipStream_t);
 
 template <typename T>
 void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes, int max_k,
@@ -225,11 +280,11 @@ template void launch_assemble_F<float, double>(double*, const float*, const BoxD
                                                const int*, KernelDesc, int, hipStream_t);
 template void launch_proxy_matrix<double>(double*, const int64_t*, const int*, const int*,
                                           const int*, const int*, const int*, const int*,
-                                          const int*, const int*, const int*, int, int, KernelDesc,
-                                          hipStream_t);
+                                          const int*, const int*, const int*, const int*, int, int,
+                                          KernelDesc, hipStream_t);
 template void launch_proxy_matrix<float>(float*, const int64_t*, const int*, const int*,
                                          const int*, const int*, const int*, const int*,
-                                         const int*, const int*, const int*, int, int, KernelDesc,
-                                         hipStream_t);
+                                         const int*, const int*, const int*, const int*, int, int,
+                                         KernelDesc, hipStream_t);
 
 }  // namespace rsd

@@ -126,6 +126,35 @@ __global__ void __launch_bounds__(256) qr_init_kernel(T* __restrict__ A, T* __re
     if (lane == 0) { X.norms[c] = s; X.perm[c] = c; }
 }
 
+// Reference pivot of the truncation rule |R_jj| <= tol |R_11|: the largest
+// column norm of the problem, or, for the four sectors of a symmetric
+// problem (consecutive in the list), the largest over all four, so that a
+// split problem truncates against the same scale as the whole one.
+template <typename T>
+__global__ void __launch_bounds__(256) qr_r11_kernel(T* __restrict__ aux, int* __restrict__ iaux,
+                                                      const QRProblemDev* __restrict__ probs) {
+    const int pi = blockIdx.x;
+    const QRProblemDev q = probs[pi];
+    const int first = q.sec < 0 ? pi : pi - q.sec, count = q.sec < 0 ? 1 : 4;
+    T m = T(0);
+    for (int g = 0; g < count; ++g) {
+        const QRProblemDev qg = probs[first + g];
+        Aux<T> Y(aux, iaux, nullptr, qg);
+        for (int c = threadIdx.x; c < qg.k; c += 256) m = fmax(m, Y.norms[c]);
+    }
+    __shared__ T red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        Aux<T> X(aux, iaux, nullptr, q);
+        X.r11[0] = sqrt(red[0]);
+    }
+}
+
 // Window selection and the permutation that realises it.  The remaining
 // candidates are ordered by (trailing norm descending, column ascending) with
 // a bitonic sort in LDS (nsort, a power of two at least the number of
@@ -419,7 +448,7 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
         for (int j = 0; j < W; ++j) lperm[j] = j;
     int parity = 0;
     int nref = nbe;
-    T r11 = (j0 == 0) ? T(0) : X.r11[0];
+    const T r11 = X.r11[0];
     // columns unrolled (static_for): every column index below is a
     // compile-time constant; a truncation stops the remaining columns
     bool stop = false;
@@ -442,7 +471,6 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
             if (t == 0) { const int y = lperm[c]; lperm[c] = lperm[pv]; lperm[pv] = y; }
         }
         const T normx = sqrt(pn);
-        if (j0 + c == 0) r11 = normx;
         if (!(normx > T(tol) * r11)) { nref = c; stop = true; return; }
         const T beta = x0 >= T(0) ? -normx : normx;
         const T tau = (beta - x0) / beta;
@@ -543,7 +571,6 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     }
     if (t < nref) X.tau[j0 + t] = Tfs[t][t];
     if (t == 0) {
-        if (j0 == 0) X.r11[0] = r11;
         X.state[4] = nref;
         X.state[6] = j0;
         X.state[7] = nbe;
@@ -695,6 +722,7 @@ __global__ void __launch_bounds__(256) qr_norms_kernel(T* __restrict__ A, T* __r
 template <typename T>
 __global__ void __launch_bounds__(256) qr_trsm_kernel(T* __restrict__ A, T* __restrict__ aux,
                                                        int* __restrict__ iaux, T* __restrict__ Tout,
+                                                       T* __restrict__ Tsec,
                                                        const QRProblemDev* __restrict__ probs,
                                                        const int* __restrict__ plist, int step) {
     __shared__ T Rb[64][65];
@@ -725,7 +753,7 @@ __global__ void __launch_bounds__(256) qr_trsm_kernel(T* __restrict__ A, T* __re
     }
     if (lane < nb) {
         xc[lane] = xv;
-        Tout[q.offT + X.perm[i0 + lane] + (int64_t)col * q.k] = xv;
+        (q.sec < 0 ? Tout : Tsec)[q.offT + X.perm[i0 + lane] + (int64_t)col * q.k] = xv;
     }
 }
 
@@ -771,6 +799,7 @@ void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_pr
     if (n_probs <= 0) return;
     hipLaunchKernelGGL(qr_init_kernel<T>, dim3((max_k + 3) / 4, n_probs), dim3(256), 0, s, A, aux,
                        iaux, probs);
+    hipLaunchKernelGGL(qr_r11_kernel<T>, dim3(n_probs), dim3(256), 0, s, aux, iaux, probs);
 }
 
 template <typename T>
@@ -847,11 +876,11 @@ void launch_qr_norms(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_p
 }
 
 template <typename T>
-void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
+void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, T* Tsec, const QRProblemDev* probs,
                     const int* plist, int n_probs, int max_r, int step, hipStream_t s) {
     if (n_probs <= 0 || max_r <= 0) return;
     hipLaunchKernelGGL(qr_trsm_kernel<T>, dim3((max_r + 3) / 4, n_probs), dim3(256), 0, s, A, aux,
-                       iaux, Tout, probs, plist, step);
+                       iaux, Tout, Tsec, probs, plist, step);
 }
 
 #define INST(T)                                                                                   \
@@ -867,8 +896,8 @@ void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, const QRProblemDev* probs,
                                     hipStream_t);                                                 \
     template void launch_qr_norms<T>(T*, T*, int*, const QRProblemDev*, int, int, int,             \
                                      hipStream_t);                                                \
-    template void launch_qr_trsm<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,   \
-                                    int, hipStream_t);
+    template void launch_qr_trsm<T>(T*, T*, int*, T*, T*, const QRProblemDev*, const int*, int,    \
+                                    int, int, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

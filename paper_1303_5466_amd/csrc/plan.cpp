@@ -1,6 +1,9 @@
 // Host planning: tree (Sec. 2.2), skeleton sets (Sec. 3.1), proxy rings.
 #include "plan.hpp"
 
+#include <unordered_map>
+#include <unordered_set>
+
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -144,8 +147,52 @@ struct Builder {
                 I.zv.push_back(zv);
             }
         I.p = (int)I.zu.size();
+        if (L.ax % 2 == 0 && L.ay % 2 == 0) find_symmetry(L, I);
         L.idp = (int)P.idps.size();
         P.idps.push_back(std::move(I));
+    }
+
+    static void find_symmetry(const Layout& L, IDProblem& I) {
+        const int ax = L.ax, ay = L.ay;
+        auto key = [](int u, int v) { return ((int64_t)u << 32) ^ (int64_t)(uint32_t)v; };
+        auto closed = [&](const int32_t* U, const int32_t* V, int n) {
+            std::unordered_set<int64_t> s;
+            for (int i = 0; i < n; ++i) s.insert(key(U[i], V[i]));
+            for (int i = 0; i < n; ++i)
+                if (!s.count(key(ax - 1 - U[i], V[i])) || !s.count(key(U[i], ay - 1 - V[i]))) return false;
+            return true;
+        };
+        const int k = L.k, r = L.r;
+        if (!closed(I.zu.data(), I.zv.data(), I.p) || !closed(L.u.data(), L.v.data(), k) ||
+            !closed(L.u.data() + k, L.v.data() + k, r))
+            return;
+        // representatives in list order, then orbit / reflection of every point
+        auto orbits = [&](const int32_t* U, const int32_t* V, int n, std::vector<int32_t>& ru,
+                          std::vector<int32_t>& rv, std::vector<int32_t>* orb, std::vector<int32_t>* g) {
+            std::unordered_map<int64_t, int> rep;
+            for (int i = 0; i < n; ++i)
+                if (U[i] < ax / 2 && V[i] < ay / 2) {
+                    rep[key(U[i], V[i])] = (int)ru.size();
+                    ru.push_back(U[i]);
+                    rv.push_back(V[i]);
+                }
+            if (!orb) return;
+            for (int i = 0; i < n; ++i) {
+                const int gx = U[i] >= ax / 2 ? 1 : 0, gy = V[i] >= ay / 2 ? 1 : 0;
+                const int fu = gx ? ax - 1 - U[i] : U[i], fv = gy ? ay - 1 - V[i] : V[i];
+                orb->push_back(rep.at(key(fu, fv)));
+                g->push_back(gx + 2 * gy);
+            }
+        };
+        orbits(I.zu.data(), I.zv.data(), I.p, I.zr_u, I.zr_v, nullptr, nullptr);
+        orbits(L.u.data(), L.v.data(), k, I.skr_u, I.skr_v, &I.sk_orb, &I.sk_g);
+        orbits(L.u.data() + k, L.v.data() + k, r, I.rsr_u, I.rsr_v, &I.rs_orb, &I.rs_g);
+        if ((int)I.zr_u.size() * 4 != I.p || (int)I.skr_u.size() * 4 != k || (int)I.rsr_u.size() * 4 != r) {
+            I.zr_u.clear(); I.zr_v.clear(); I.skr_u.clear(); I.skr_v.clear(); I.rsr_u.clear(); I.rsr_v.clear();
+            I.sk_orb.clear(); I.sk_g.clear(); I.rs_orb.clear(); I.rs_g.clear();
+            return;
+        }
+        I.sym = true;
     }
 };
 

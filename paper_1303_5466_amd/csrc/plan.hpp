@@ -38,6 +38,19 @@ struct IDProblem {
     int layout = -1;
     int p = 0, k = 0, r = 0;
     std::vector<int32_t> zu, zv;   // proxy nodes relative to the box origin
+    // Mirror symmetry: when both reflections of the box (u -> ax-1-u,
+    // v -> ay-1-v) map Z, I^sk and I^rs onto themselves without fixed points,
+    // every point lies in an orbit of four and the problem splits into four
+    // independent sector problems of a quarter the size.  Orbit
+    // representatives are the points of the lower-left quadrant; g in 0..3
+    // names the reflection (bit 0: u, bit 1: v) carrying the representative
+    // to the point.
+    bool sym = false;
+    std::vector<int32_t> zr_u, zr_v;           // Z representatives (p / 4)
+    std::vector<int32_t> skr_u, skr_v;         // I^sk representatives (k / 4)
+    std::vector<int32_t> rsr_u, rsr_v;         // I^rs representatives (r / 4)
+    std::vector<int32_t> sk_orb, sk_g;         // per skeleton position: orbit, reflection
+    std::vector<int32_t> rs_orb, rs_g;         // per residual position
 };
 
 struct Box {

@@ -23,6 +23,7 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOTGRID", "ENOMEM", "ESINGULAR", "ENOCONV", "E
 RSD_KERNEL_LAPLACE, RSD_KERNEL_HELMHOLTZ = 0, 1
 RSD_PREC_FP64, RSD_PREC_FP32_REFINE = 0, 1
 RSD_FLAG_KEEP_E = 1
+RSD_FLAG_NO_SYMMETRY = 2
 
 
 class rsd_kernel(C.Structure):

@@ -364,3 +364,43 @@ def test_server_admission_and_errors():
     srv.release_factor(fc)
     assert srv.stats()["n_factors"] == 1
     srv.close()
+
+
+# --- symmetry split of the interpolation problems ------------------------------------
+def test_symmetry_split_matches_whole_problems():
+    pts = W.grid_points(64)
+    a = W.coef_sine(pts)
+    f = W.rhs_normal(len(pts), 2, 41)
+    fs = rsd.Factor(pts, a, 1e-10)
+    fw = rsd.Factor(pts, a, 1e-10, flags=rsd.RSD_FLAG_NO_SYMMETRY)
+    xs, _ = fs.solve(f)
+    xw, _ = fw.solve(f)
+    xd = dense.solve(pts, f, a)
+    assert dense.rel_error(xs, xd) < 1e-10 and dense.rel_error(xw, xd) < 1e-10
+    assert np.linalg.norm(xs - xw) <= 1e-11 * np.linalg.norm(xw)
+    # every level's T: the four sector solutions recombine to the whole problem's
+    seen = set()
+    for b in range(fs.stats()["n_boxes"]):
+        info = fs.box_info(b)
+        if info["level"] in seen or info["r"] == 0:
+            continue
+        seen.add(info["level"])
+        try:
+            Ts, Tw = fs.block(b, 0), fw.block(b, 0)
+        except rsd.RsdError:
+            continue
+        assert np.abs(Ts - Tw).max() <= 1e-6 * np.abs(Tw).max(), info["level"]
+    fs.close()
+    fw.close()
+
+
+@pytest.mark.parametrize("precision", [rsd.RSD_PREC_FP64, rsd.RSD_PREC_FP32_REFINE])
+def test_low_accuracy_tolerance(precision):
+    # tol 1e-6: one layer, truncation active in the interpolation problems
+    pts = W.grid_points(128)
+    a = W.coef_sine(pts)
+    f = W.rhs_normal(len(pts), 1, 43)
+    fac = rsd.Factor(pts, a, 1e-6, precision=precision)
+    x, info = fac.solve(f)
+    r = f - nystrom.matvec_fft(pts, x, a)
+    assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(f)
