@@ -109,15 +109,18 @@ void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* 
                          const int* r_of, const int* zoff, const int* zu, const int* zv,
                          const int* xoff, const int* xu, const int* xv, const int* geo, int n_problems,
                          int max_pn, KernelDesc kd, hipStream_t s);
-// T of every symmetric box type from its four sector solutions (see k_gen.hip)
+// T of a box type from solutions kept in a float64 sector arena: the four
+// sector solutions of a symmetric type combined, or a plain solution copied,
+// converted to the precision of the T arena (see k_gen.hip)
 struct SymCombineDesc {
     int64_t offT;      // layout T (k x r, ld k) in the T arena
-    int64_t offS;      // sector ab block (k/4 x r/4, ld k/4) at offS + ab k r / 16
+    int64_t offS;      // sym: sector ab block (k/4 x r/4, ld k/4) at offS + ab k r / 16; else k x r
     int k, r;
-    int off_sk, off_rs;   // into the orbit / reflection tables
+    int off_sk, off_rs;   // into the orbit / reflection tables (sym only)
+    int sym;
 };
-template <typename T>
-void launch_sym_combine(T* Tarena, const T* Tsec, const SymCombineDesc* d, int n_desc,
+template <typename TS, typename TD>
+void launch_sym_combine(TD* Tarena, const TS* Tsec, const SymCombineDesc* d, int n_desc,
                         const int* orb, const int* refl, int max_kr, hipStream_t s);
 
 // QR least squares for T (block column pivoting)
@@ -126,9 +129,10 @@ constexpr int QR_WIN = 64;    // pivoting window / block width of the trailing u
 constexpr int QR_RC = 256;    // row chunk of the split-K reflector products
 struct QRProblemDev {
     int p, k, r, nb;   // nb: sub-panel width (16, 8, 4 or 2 by the LDS budget)
-    int sec;           // -1: output to the T arena; else a symmetry sector (output to the sector arena)
+    int sec;           // -1, or the symmetry sector (0..3) this problem solves
+    int staged;        // 0: T goes to the T arena; 1: to the staging arena (sector, or another precision)
     int64_t offA;      // p x (k + r) matrix, ld = p
-    int64_t offT;      // output T (k x r), ld = k, in the arena sec selects
+    int64_t offT;      // output T (k x r), ld = k, in the arena staged selects
     int64_t offAux;    // norms (k), tau (k), sub-panel WY (QR_NB^2), window WY (QR_WIN^2), r11
     int64_t offIaux;   // perm (k), state (8), moves (4 * QR_WIN)
     int64_t offV;      // V workspace p x QR_WIN (unit lower trapezoidal)

@@ -333,8 +333,9 @@ struct QRChain {
     DevBuf *dA = nullptr, *daux = nullptr, *diaux = nullptr, *dws = nullptr, *dq = nullptr,
            *dlist = nullptr, *dsolve = nullptr, *dsec = nullptr, *dcomb = nullptr, *dorb = nullptr,
            *drefl = nullptr;
-    std::vector<int64_t> sym_sec0;     // sector-arena offset of every symmetric problem
-    std::vector<int> comb_off;         // combine descriptors per window
+    std::vector<int64_t> sym_sec0;     // staging-arena offset of every staged problem
+    std::vector<int> staged_prec;      // precision of its T arena (0 float64, 1 float32)
+    std::vector<int> comb_off[2];      // staging descriptors per window, per destination precision
     int comb_max_kr = 0;
     std::vector<GemmBatch<T>> g1, gt, g2;
     std::vector<std::vector<GemmBatch<T>>> gsolve;
@@ -356,18 +357,24 @@ struct QRChain {
         // a symmetric interpolation problem becomes its four sector problems
         // (orbit representatives; their solutions are combined into T after
         // the back substitution)
-        std::vector<int> sym_ids;
+        // staged solutions: symmetric problems (sectors, then combined) and
+        // problems whose level keeps T in another precision than this chain
+        std::vector<int> staged_ids, staged_sym;
         for (size_t pi = 0; pi < probs_ids.size(); ++pi) {
             const int id = probs_ids[pi];
             const IDProblem& I = P.idps[id];
             const Layout& L = P.layouts[I.layout];
-            const bool sym = split_sym(*f, I, std::is_same<T, double>::value ? 0 : 1);
+            const int chain_prec = std::is_same<T, double>::value ? 0 : 1;
+            const bool sym = split_sym(*f, I, chain_prec);
+            const bool convert = f->level_prec[levels[pi]] != chain_prec;
             const int nsec = sym ? 4 : 1;
             const int64_t sec0 = sec_el;
-            if (sym) {
-                sec_el += (int64_t)I.k * I.r / 4;
-                sym_ids.push_back(id);
+            if (sym || convert) {
+                sec_el += (int64_t)I.k * I.r / (sym ? 4 : 1);
+                staged_ids.push_back(id);
+                staged_sym.push_back(sym ? 1 : 0);
                 sym_sec0.push_back(sec0);
+                staged_prec.push_back(f->level_prec[levels[pi]]);
             }
             for (int sc = 0; sc < nsec; ++sc) {
                 QRProblemDev q;
@@ -375,12 +382,13 @@ struct QRChain {
                 q.k = sym ? I.k / 4 : I.k;
                 q.r = sym ? I.r / 4 : I.r;
                 q.sec = sym ? sc : -1;
+                q.staged = (sym || convert) ? 1 : 0;
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));
                 if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
                 const int n = q.k + q.r;
                 const int nch = (q.p + QR_RC - 1) / QR_RC;
                 q.offA = A_el;
-                q.offT = sym ? sec0 + (int64_t)sc * q.k * q.r : f->hlayouts[I.layout].offT;
+                q.offT = (sym || convert) ? sec0 + (int64_t)sc * q.k * q.r : f->hlayouts[I.layout].offT;
                 q.offAux = aux_el;
                 q.offIaux = iaux_el;
                 q.offV = ws_el;
@@ -433,36 +441,48 @@ struct QRChain {
         upload(*dq, qp, s); upload(doffA, offA, s); upload(dp, pof, s); upload(dk, kof, s);
         upload(dr, rof, s); upload(dzo, zoff, s); upload(dzu, zu, s); upload(dzv, zv, s);
         upload(dxo, xoff, s); upload(dxu, xu, s); upload(dxv, xv, s); upload(dgeo, geo, s);
-        // combination of sector solutions, grouped by the window after which
-        // the sectors are complete
+        // staged solutions into the T arenas (combined for symmetric types,
+        // converted to the level's precision), grouped by the window after
+        // which their problems are complete, one list per destination precision
         {
             std::vector<int> orb, refl;
-            std::vector<std::vector<SymCombineDesc>> by_win;
-            for (size_t si = 0; si < sym_ids.size(); ++si) {
-                const IDProblem& I = P.idps[sym_ids[si]];
+            std::vector<std::vector<SymCombineDesc>> by_win[2];
+            for (size_t si = 0; si < staged_ids.size(); ++si) {
+                const IDProblem& I = P.idps[staged_ids[si]];
+                const bool sym = staged_sym[si] != 0;
                 SymCombineDesc cd;
                 cd.offT = f->hlayouts[I.layout].offT;
                 cd.offS = sym_sec0[si];
                 cd.k = I.k;
                 cd.r = I.r;
+                cd.sym = sym ? 1 : 0;
                 cd.off_sk = (int)orb.size();
-                orb.insert(orb.end(), I.sk_orb.begin(), I.sk_orb.end());
-                refl.insert(refl.end(), I.sk_g.begin(), I.sk_g.end());
                 cd.off_rs = (int)orb.size();
-                orb.insert(orb.end(), I.rs_orb.begin(), I.rs_orb.end());
-                refl.insert(refl.end(), I.rs_g.begin(), I.rs_g.end());
-                const int w = (I.k / 4 + QR_WIN - 1) / QR_WIN - 1;
-                if ((int)by_win.size() <= w) by_win.resize(w + 1);
-                by_win[w].push_back(cd);
+                if (sym) {
+                    orb.insert(orb.end(), I.sk_orb.begin(), I.sk_orb.end());
+                    refl.insert(refl.end(), I.sk_g.begin(), I.sk_g.end());
+                    cd.off_rs = (int)orb.size();
+                    orb.insert(orb.end(), I.rs_orb.begin(), I.rs_orb.end());
+                    refl.insert(refl.end(), I.rs_g.begin(), I.rs_g.end());
+                }
+                const int kq = sym ? I.k / 4 : I.k;
+                const int w = (kq + QR_WIN - 1) / QR_WIN - 1;
+                auto& bw = by_win[staged_prec[si]];
+                if ((int)bw.size() <= w) bw.resize(w + 1);
+                bw[w].push_back(cd);
                 comb_max_kr = std::max(comb_max_kr, I.k * I.r);
             }
             std::vector<SymCombineDesc> flatc;
-            comb_off.assign(S + 1, 0);
-            for (int w = 0; w < S; ++w) {
-                comb_off[w] = (int)flatc.size();
-                if (w < (int)by_win.size()) flatc.insert(flatc.end(), by_win[w].begin(), by_win[w].end());
+            for (int pr = 0; pr < 2; ++pr) {
+                comb_off[pr].assign(S + 1, 0);
+                for (int w = 0; w < S; ++w) {
+                    comb_off[pr][w] = (int)flatc.size();
+                    if (w < (int)by_win[pr].size()) flatc.insert(flatc.end(), by_win[pr][w].begin(), by_win[pr][w].end());
+                }
+                comb_off[pr][S] = (int)flatc.size();
             }
-            comb_off[S] = (int)flatc.size();
+            orb.push_back(0);
+            refl.push_back(0);
             dcomb = &f->tmp(); dorb = &f->tmp(); drefl = &f->tmp();
             upload(*dcomb, flatc, s); upload(*dorb, orb, s); upload(*drefl, refl, s);
         }
@@ -612,8 +632,12 @@ struct QRChain {
                               gr, st, s);
             gsolve[sw][st].run(s);
         }
-        launch_sym_combine<T>(Tbase<T>(*f), dsec->as<T>(), dcomb->as<SymCombineDesc>() + comb_off[sw],
-                              comb_off[sw + 1] - comb_off[sw], dorb->as<int>(), drefl->as<int>(), comb_max_kr, s);
+        launch_sym_combine<T, double>(Tbase<double>(*f), dsec->as<T>(), dcomb->as<SymCombineDesc>() + comb_off[0][sw],
+                                      comb_off[0][sw + 1] - comb_off[0][sw], dorb->as<int>(), drefl->as<int>(),
+                                      comb_max_kr, s);
+        launch_sym_combine<T, float>(Tbase<float>(*f), dsec->as<T>(), dcomb->as<SymCombineDesc>() + comb_off[1][sw],
+                                     comb_off[1][sw + 1] - comb_off[1][sw], dorb->as<int>(), drefl->as<int>(),
+                                     comb_max_kr, s);
         hipEvent_t solved;
         RSD_HIP(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
         RSD_HIP(hipEventRecord(solved, s));
@@ -1039,11 +1063,14 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         if (P.layouts[li].idp < 0) continue;
         const int lev = layout_level[li];
         const int pr = f->level_prec[lev];
+        // every T is computed in float64 (geometry only, shared per box type)
+        // and rounded into a float32 level's arena when staged
+        (void)pr;
         const IDProblem& I = P.idps[P.layouts[li].idp];
-        const bool sym = split_sym(*f, I, pr);
-        const int narrow = qr_panel_width(sym ? I.p / 4 : I.p, pr ? 4 : 8) < 16 ? 1 : 0;
-        cp[pr][narrow].push_back(P.layouts[li].idp);
-        cl[pr][narrow].push_back(lev);
+        const bool sym = split_sym(*f, I, 0);
+        const int narrow = qr_panel_width(sym ? I.p / 4 : I.p, 8) < 16 ? 1 : 0;
+        cp[0][narrow].push_back(P.layouts[li].idp);
+        cl[0][narrow].push_back(lev);
         pending[lev] += sym ? 4 : 1;     // one per (sector) problem
     }
     std::vector<std::vector<hipEvent_t>> level_waits(nlev);
@@ -1099,7 +1126,7 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     for (auto* b : b64) fl += b->flops;
     for (auto* b : b32) fl += b->flops;
     for (auto& I : P.idps) {
-        const double ns = split_sym(*f, I, f->level_prec[layout_level[I.layout]]) ? 4 : 1;
+        const double ns = split_sym(*f, I, 0) ? 4 : 1;
         const double p = I.p / ns, k = I.k / ns, r = I.r / ns;
         fl += ns * (2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r);
     }

@@ -150,11 +150,13 @@ __global__ void __launch_bounds__(256) proxy_kernel(
     }
 }
 
-// T of a symmetric box type from its sector solutions T^ab (orbit indices):
-// T[i, j] = 1/4 sum_ab chi_ab(g_i) chi_ab(h_j) T^ab[orb_i, orb_j], with
-// chi_ab(g) = (-1)^popcount(ab & g) (the symmetry-adapted basis is orthonormal).
-template <typename T>
-__global__ void __launch_bounds__(256) sym_combine_kernel(T* __restrict__ Ta, const T* __restrict__ Ts,
+// T of a box type from float64 solutions in the sector arena, converted to
+// the level's precision.  Symmetric type (d.sym): from its sector solutions
+// T^ab (orbit indices), T[i, j] = 1/4 sum_ab chi_ab(g_i) chi_ab(h_j)
+// T^ab[orb_i, orb_j] with chi_ab(g) = (-1)^popcount(ab & g) (the
+// symmetry-adapted basis is orthonormal); otherwise a plain copy.
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, const TS* __restrict__ Ts,
                                                           const SymCombineDesc* __restrict__ descs,
                                                           const int* __restrict__ orb,
                                                           const int* __restrict__ refl) {
@@ -163,16 +165,20 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(T* __restrict__ Ta, co
     const int64_t blk = (int64_t)k4 * r4;
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)d.k * d.r; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % d.k), j = (int)(e / d.k);
+        if (!d.sym) {
+            Ta[d.offT + e] = TD(Ts[d.offS + e]);
+            continue;
+        }
         const int oi = orb[d.off_sk + i], gi = refl[d.off_sk + i];
         const int oj = orb[d.off_rs + j], gj = refl[d.off_rs + j];
         const int64_t at = oi + (int64_t)oj * k4;
-        T acc = T(0);
+        TS acc = TS(0);
 #pragma unroll
         for (int ab = 0; ab < 4; ++ab) {
-            const T v = Ts[d.offS + ab * blk + at];
+            const TS v = Ts[d.offS + ab * blk + at];
             acc += (__popc(ab & (gi ^ gj)) & 1) ? -v : v;
         }
-        Ta[d.offT + i + (int64_t)j * d.k] = T(0.25) * acc;
+        Ta[d.offT + i + (int64_t)j * d.k] = TD(TS(0.25) * acc);
     }
 }
 
@@ -242,17 +248,21 @@ void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* 
                        zv, xoff, xu, xv, geo, kd);
 }
 
-template <typename T>
-void launch_sym_combine(T* Tarena, const T* Tsec, const SymCombineDesc* d, int n_desc,
+template <typename TS, typename TD>
+void launch_sym_combine(TD* Tarena, const TS* Tsec, const SymCombineDesc* d, int n_desc,
                         const int* orb, const int* refl, int max_kr, hipStream_t s) {
     if (n_desc <= 0) return;
     dim3 grid(chunks_for(max_kr), n_desc);
-    hipLaunchKernelGGL(sym_combine_kernel<T>, grid, dim3(256), 0, s, Tarena, Tsec, d, orb, refl);
+    hipLaunchKernelGGL((sym_combine_kernel<TS, TD>), grid, dim3(256), 0, s, Tarena, Tsec, d, orb, refl);
 }
-template void launch_sym_combine<double>(double*, const double*, const SymCombineDesc*, int, const int*,
-                                         const int*, int, hipStream_t);
-template void launch_sym_combine<float>(float*, const float*, const SymCombineDesc*, int, const int*,
-                                        const int*, int, hipStream_t);
+template void launch_sym_combine<double, double>(double*, const double*, const SymCombineDesc*, int,
+                                                 const int*, const int*, int, hipStream_t);
+template void launch_sym_combine<double, float>(float*, const double*, const SymCombineDesc*, int,
+                                                const int*, const int*, int, hipStream_t);
+template void launch_sym_combine<float, float>(float*, const float*, const SymCombineDesc*, int,
+                                               const int*, const int*, int, hipStream_t);
+template void launch_sym_combine<float, double>(double*, const float*, const SymCombineDesc*, int,
+                                                const int*, const int*, int, hipStream_t);
 
 template <typename T>
 void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes, int max_k,

@@ -753,7 +753,7 @@ __global__ void __launch_bounds__(256) qr_trsm_kernel(T* __restrict__ A, T* __re
     }
     if (lane < nb) {
         xc[lane] = xv;
-        (q.sec < 0 ? Tout : Tsec)[q.offT + X.perm[i0 + lane] + (int64_t)col * q.k] = xv;
+        (q.staged ? Tsec : Tout)[q.offT + X.perm[i0 + lane] + (int64_t)col * q.k] = xv;
     }
 }
 
