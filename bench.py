@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="laplace256")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--fp32-interp", action="store_true",
+                    help="fp32 factors: solve the interpolation problems in float32 as well")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-solves", type=int, default=30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched many-grid measurement")
@@ -179,6 +181,7 @@ def main():
     pts, a, f, tol = W.make_workload(args.workload)
     n, nrhs = f.shape
     prec = rsd.RSD_PREC_FP64 if args.precision == "fp64" else rsd.RSD_PREC_FP32_REFINE
+    flags = rsd.RSD_FLAG_FP32_INTERP if args.fp32_interp else 0
     d_pts = torch.from_numpy(pts).to(dev)
     d_a = torch.from_numpy(a).to(dev)
     d_f = torch.from_numpy(np.ascontiguousarray(f.T)).to(dev)      # column-major N x nrhs
@@ -187,7 +190,7 @@ def main():
     lib = rsd.load()
 
     def step():
-        fac = rsd.Factor(d_pts, d_a, tol, precision=prec)
+        fac = rsd.Factor(d_pts, d_a, tol, precision=prec, flags=flags)
         st, info = fac.solve_raw(d_f.data_ptr(), nrhs, d_x.data_ptr())
         if st != rsd.RSD_OK:
             raise rsd.RsdError(st, lib.rsd_last_error().decode())
@@ -217,7 +220,7 @@ def main():
                 f"  {v['flops'] / max(v['ms'], 1e-9) / 1e9:9.1f} TF/s")
 
     # accuracy of the last step against the exact operator (FP64 residual on device)
-    fac = rsd.Factor(d_pts, d_a, tol, precision=prec)
+    fac = rsd.Factor(d_pts, d_a, tol, precision=prec, flags=flags)
     x = d_x.cpu().numpy().T
     r = f - fac.matvec(np.asfortranarray(x))
     rel_res = float((np.linalg.norm(r, axis=0) / np.linalg.norm(f, axis=0)).max())
@@ -265,6 +268,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": dt, "data": "synthetic",
         "config": {"workload": args.workload, "grid": f"{int(round(n ** 0.5))}x{int(round(n ** 0.5))}",
                    "n_unknowns": n, "nrhs": nrhs, "tol": tol, "precision": args.precision,
+                   "interp": "fp32" if args.fp32_interp and args.precision == "fp32" else "fp64",
                    "kernel": "laplace (1/2pi) log r", "leaf": "8x8", "layers": stats["layers"]},
         "solve_p50_ms": p50, "solve_p99_ms": p99, "max_rel_residual": rel_res,
         "factor_flops_model": stats["factor_flops"],

@@ -90,6 +90,12 @@ typedef struct rsd_options {
  * box types into their four symmetry sectors (same T up to rounding for
  * full-rank problems; for testing and comparison). */
 #define RSD_FLAG_NO_SYMMETRY 2
+/* FP32_REFINE factors: solve the interpolation problems of the float32 levels
+ * in float32 too, truncated at max(tol, 1e-6).  By default they are solved in
+ * float64 (to tol, symmetry split where full rank) and T is rounded to float32;
+ * the float32 form trades interpolation accuracy for a float32-only build and
+ * usually needs more refinement steps. */
+#define RSD_FLAG_FP32_INTERP 4
 
 typedef struct rsd_solve_info {
     int32_t refine_iters;  /* refinement steps taken                          */

@@ -310,11 +310,16 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 // factors at tol <= 1e-9; measured rank = k at every level of the benchmark
 // grids), so the four sector solutions are the whole problem's unique
 // least-squares solution up to rounding.  Where truncation decides the rank
-// (float32 factors, looser tolerances) the whole problem is solved: the
+// (float32 interpolation, looser tolerances) the whole problem is solved: the
 // window pivoting's truncation test sees only a sub-panel's columns, and on
 // the small sector problems that stops too early.
 static bool split_sym(const Factor& f, const IDProblem& I, int prec) {
     return I.sym && prec == 0 && f.tol <= 1e-9;
+}
+
+// Precision of the interpolation problems of a level (0 float64, 1 float32).
+static int interp_prec(const Factor& f, int level) {
+    return f.level_prec[level] && (f.flags & RSD_FLAG_FP32_INTERP) ? 1 : 0;
 }
 
 // One chain of interpolation problems: every problem of the chain advances
@@ -1062,15 +1067,15 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     for (size_t li = 0; li < P.layouts.size(); ++li) {
         if (P.layouts[li].idp < 0) continue;
         const int lev = layout_level[li];
-        const int pr = f->level_prec[lev];
-        // every T is computed in float64 (geometry only, shared per box type)
-        // and rounded into a float32 level's arena when staged
-        (void)pr;
+        // T depends on geometry only (one problem per box type), so it is
+        // computed in float64 and rounded into a float32 level's arena,
+        // unless the caller asks for float32 interpolation as well
+        const int ip = interp_prec(*f, lev);
         const IDProblem& I = P.idps[P.layouts[li].idp];
-        const bool sym = split_sym(*f, I, 0);
-        const int narrow = qr_panel_width(sym ? I.p / 4 : I.p, 8) < 16 ? 1 : 0;
-        cp[0][narrow].push_back(P.layouts[li].idp);
-        cl[0][narrow].push_back(lev);
+        const bool sym = split_sym(*f, I, ip);
+        const int narrow = qr_panel_width(sym ? I.p / 4 : I.p, ip ? 4 : 8) < 16 ? 1 : 0;
+        cp[ip][narrow].push_back(P.layouts[li].idp);
+        cl[ip][narrow].push_back(lev);
         pending[lev] += sym ? 4 : 1;     // one per (sector) problem
     }
     std::vector<std::vector<hipEvent_t>> level_waits(nlev);
@@ -1126,7 +1131,7 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     for (auto* b : b64) fl += b->flops;
     for (auto* b : b32) fl += b->flops;
     for (auto& I : P.idps) {
-        const double ns = split_sym(*f, I, 0) ? 4 : 1;
+        const double ns = split_sym(*f, I, interp_prec(*f, layout_level[I.layout])) ? 4 : 1;
         const double p = I.p / ns, k = I.k / ns, r = I.r / ns;
         fl += ns * (2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r);
     }

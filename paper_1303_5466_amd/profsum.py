@@ -52,15 +52,15 @@ def _dispatches(rows):
     return out
 
 
-def level_gemm_ids(disp):
+def level_gemm_ids(disp, gemm: str = GEMM):
     """Dispatch ids of the factor's level GEMM launches, and the number of builds."""
     starts = [d["start"] for d in disp if d["name"].startswith("leaf_F_kernel")]
-    return {d["dispatch"] for d in disp if d["name"] == GEMM}, len(starts)
+    return {d["dispatch"] for d in disp if d["name"] == gemm}, len(starts)
 
 
-def trace_summary(d: str, title: str, command: str) -> str:
+def trace_summary(d: str, title: str, command: str, gemm: str = GEMM) -> str:
     disp = _dispatches(_rows(d, "kernel_trace.csv"))
-    ids, nb = level_gemm_ids(disp)
+    ids, nb = level_gemm_ids(disp, gemm)
     agg = defaultdict(lambda: [0, 0.0])
     for x in disp:
         a = agg[x["name"]]
@@ -74,7 +74,7 @@ def trace_summary(d: str, title: str, command: str) -> str:
     for k, (n, us) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
         out.append(f"| `{k}` | {n / nb:.0f} | {us / 1e3 / nb:.3f} | {us / n:.1f} |")
     if lv:
-        out += ["", f"Level GEMM launches (`{GEMM}`: the factor's Schur, Gauss-Jordan, E and root products):",
+        out += ["", f"Level GEMM launches (`{gemm}`: the factor's Schur, Gauss-Jordan, E and root products):",
                 "", f"- launches: {len(lv)} ({len(lv) / nb:.0f} per build)",
                 f"- average duration: {sum(lv) / len(lv):.2f} us",
                 f"- total per build: {sum(lv) / 1e3 / nb:.3f} ms"]
@@ -112,7 +112,7 @@ def traffic_summary(a) -> str:
            "Commands (repository root, one MI355X; one counter per run):", "", "```"]
     out += a.command
     out += ["```", "",
-            f"Copy calibration: a {a.copy_bytes} B elementwise copy reads FETCH_SIZE = {cf_kib:.0f} KiB "
+            f"Copy calibration: a {a.copy_bytes:.0f} B elementwise copy reads FETCH_SIZE = {cf_kib:.0f} KiB "
             f"and WRITE_SIZE = {cw_kib:.0f} KiB, so the scale factors are {sf:.3f} (fetch) and "
             f"{sw:.3f} (write); per-launch counter values are divided by them.", "",
             f"- level GEMM launches sampled: {nf} (fetch), {nw} (write)",
@@ -148,6 +148,7 @@ def main(argv=None):
     t.add_argument("dir")
     t.add_argument("--title", default="Kernel statistics")
     t.add_argument("--command", default="")
+    t.add_argument("--gemm", default=GEMM, help="kernel name of the level GEMM to summarise")
     f = sub.add_parser("traffic")
     f.add_argument("--fetch", required=True)
     f.add_argument("--write", required=True)
@@ -158,7 +159,7 @@ def main(argv=None):
     f.add_argument("--command", action="append", default=[])
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        sys.stdout.write(trace_summary(a.dir, a.title, a.command))
+        sys.stdout.write(trace_summary(a.dir, a.title, a.command, a.gemm))
     else:
         sys.stdout.write(traffic_summary(a))
 

@@ -24,6 +24,7 @@ RSD_KERNEL_LAPLACE, RSD_KERNEL_HELMHOLTZ = 0, 1
 RSD_PREC_FP64, RSD_PREC_FP32_REFINE = 0, 1
 RSD_FLAG_KEEP_E = 1
 RSD_FLAG_NO_SYMMETRY = 2
+RSD_FLAG_FP32_INTERP = 4
 
 
 class rsd_kernel(C.Structure):

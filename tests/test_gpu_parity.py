@@ -180,11 +180,14 @@ def test_contrast_form_is_rejected_on_device():
     assert ei.value.status == rsd.RSD_EINVAL
 
 
-def test_fp32_refined_matches_dense():
+@pytest.mark.parametrize("flags", [0, rsd.RSD_FLAG_FP32_INTERP])
+def test_fp32_refined_matches_dense(flags):
+    # default: float64 interpolation rounded into the float32 levels;
+    # FP32_INTERP: the interpolation problems solved in float32 as well
     pts = W.grid_points(64)
     a = W.coef_sine(pts)
     f = W.rhs_normal(len(pts), 2, 6)
-    fac = rsd.Factor(pts, a, 1e-10, precision=rsd.RSD_PREC_FP32_REFINE)
+    fac = rsd.Factor(pts, a, 1e-10, precision=rsd.RSD_PREC_FP32_REFINE, flags=flags)
     x, info = fac.solve(f)
     assert info.rel_residual <= 1e-10
     assert dense.rel_error(x, dense.solve(pts, f, a)) < 1e-10
@@ -394,13 +397,14 @@ def test_symmetry_split_matches_whole_problems():
     fw.close()
 
 
-@pytest.mark.parametrize("precision", [rsd.RSD_PREC_FP64, rsd.RSD_PREC_FP32_REFINE])
-def test_low_accuracy_tolerance(precision):
+@pytest.mark.parametrize("precision,flags", [(rsd.RSD_PREC_FP64, 0), (rsd.RSD_PREC_FP32_REFINE, 0),
+                                             (rsd.RSD_PREC_FP32_REFINE, rsd.RSD_FLAG_FP32_INTERP)])
+def test_low_accuracy_tolerance(precision, flags):
     # tol 1e-6: one layer, truncation active in the interpolation problems
     pts = W.grid_points(128)
     a = W.coef_sine(pts)
     f = W.rhs_normal(len(pts), 1, 43)
-    fac = rsd.Factor(pts, a, 1e-6, precision=precision)
+    fac = rsd.Factor(pts, a, 1e-6, precision=precision, flags=flags)
     x, info = fac.solve(f)
     r = f - nystrom.matvec_fft(pts, x, a)
     assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(f)
