@@ -197,6 +197,28 @@ rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* o
  * dst must hold the block; elements are double (complex: interleaved). */
 rsd_status rsd_factor_get_block(const rsd_factor* f, int32_t box, int32_t which, void* dst);
 
+/* ---- device memory cache -------------------------------------------------
+ *
+ * Device buffers of builds, factors and solves come from a per-device cache:
+ * a freed buffer is kept and handed out again to a later request of about
+ * the same size (blocks are classed by size: powers of two up to 1 MiB, then
+ * 2 MiB multiples; a cached block at most 1/8 larger than the request is
+ * reused), so repeated builds do not pay hipMalloc / hipFree for their
+ * arenas.  A block enters the cache only after its last use has completed.
+ * At most `limit` bytes stay cached per device (default: the smaller of
+ * 16 GiB and 1/8 of the device memory); an allocation that fails first hands
+ * the device's cache back to HIP and tries again.  Thread-safe. */
+
+/* Hand every cached block of `device` (< 0: of every device) back to HIP. */
+rsd_status rsd_pool_trim(int32_t device);
+
+/* Set the per-device cache limit in bytes (< 0: back to the default);
+ * blocks beyond a smaller limit are handed back at once. */
+rsd_status rsd_pool_set_limit(int64_t bytes);
+
+/* Bytes currently cached (idle) for `device` (< 0: all devices). */
+rsd_status rsd_pool_cached_bytes(int32_t device, int64_t* out);
+
 /* ---- kernel timing -------------------------------------------------------- */
 
 /* Kernel classes timed by the built-in profiler. */
@@ -215,8 +237,15 @@ typedef enum rsd_prof_class {
 /* Enable (on != 0) or disable the profiler and clear its records.  While
  * enabled, every launch of a timed class is bracketed by HIP events on the
  * stream it runs on; totals are read with rsd_profile_query.  The profiler is
- * process-wide and not thread-safe. */
+ * process-wide; records from several threads are collected under a lock, but
+ * enabling or querying while other threads launch work is not supported. */
 rsd_status rsd_profile_enable(int32_t on);
+
+/* As rsd_profile_enable, but only the classes whose bit (1 << cls) is set in
+ * `mask` are bracketed (0 disables).  Events are reused across enables, so a
+ * run that enables the same classes twice creates no events the second
+ * time. */
+rsd_status rsd_profile_enable_mask(uint32_t mask);
 
 /* Totals for one class since the last enable: summed device time of its
  * launches (ms), launch count, algorithmic flops and algorithmic bytes
@@ -224,6 +253,14 @@ rsd_status rsd_profile_enable(int32_t on);
  * device. */
 rsd_status rsd_profile_query(int32_t cls, double* total_ms, int64_t* launches,
                              double* flops, double* bytes);
+
+/* Launches recorded since the last enable, in the order they were enqueued
+ * (per thread).  Record i: class, device time (ms), algorithmic flops and
+ * bytes, and work-groups launched (0 where not recorded).  Synchronises on
+ * that launch. */
+rsd_status rsd_profile_record_count(int64_t* n);
+rsd_status rsd_profile_record(int64_t i, int32_t* cls, double* ms, double* flops, double* bytes,
+                              int64_t* groups);
 
 /* ---- serving: resident factors, queued solves ------------------------------
  *

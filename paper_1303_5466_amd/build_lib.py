@@ -29,9 +29,15 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+# per-source code generation options: the GEMM keeps its MFMA accumulators in
+# ordinary vector registers (with accumulation registers the compiler copies
+# them between the two register files on every K panel)
+EXTRA = {"k_gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, *EXTRA.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj]
         if src in ("driver.cpp", "server.cpp"):

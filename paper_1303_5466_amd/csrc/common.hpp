@@ -76,18 +76,27 @@ struct GemmDesc {
     T alpha, beta;
 };
 
+// One work-group of a grouped GEMM launch: output tile (tm, tn) of product
+// `desc`, and its part `split` of `nsplit` of the K range; a split tile's
+// partials are tiles pbase .. pbase + nsplit - 1 of the workspace.
 struct TileRef {
     int desc;
     int tm, tn;
+    int split, nsplit, pbase;
 };
 
-constexpr int GEMM_TILE = 64;
+// Largest byte extent of one GEMM operand from its base pointer (the kernel
+// uses 32-bit buffer offsets).
+constexpr int64_t GEMM_MAX_OPERAND_BYTES = 0x7ffffff0;
 
 // ------------------------------- launchers ---------------------------------
-template <typename T>
+// tile: 64 or 128 (square output tiles); ws: split-K partial tiles;
+// reduce: 0 = products (d_tiles: one entry per work-group), 1 = sum the
+// partials of the split tiles listed in d_tiles into C
 // role: 0 factor levels, 1 interpolation, 2 solve sweeps, 3 library calls
-void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, hipStream_t s,
-                 int role);
+template <typename T>
+void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, int tile, T* ws,
+                 int reduce, hipStream_t s, int role);
 
 // generation / assembly
 template <typename T>

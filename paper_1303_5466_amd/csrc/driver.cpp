@@ -48,27 +48,191 @@ static thread_local std::string g_last_error;
 // ----------------------------------------------------------------------------
 // device memory
 // ----------------------------------------------------------------------------
+// Caching allocator: device blocks freed by one factor, solve or build are
+// kept per device and handed out again to a later request of about the same
+// size, so repeated builds do not pay hipMalloc / hipFree for their arenas
+// (freeing a large arena synchronises and unmaps, about a millisecond).
+// A block is cached only once its last use has completed: a release inside
+// an IdleScope (its owner has synchronised every stream that used it) is
+// immediate, any other release synchronises the device first, as hipFree
+// does.  At most `limit` bytes stay cached per device; an allocation that
+// fails returns the device's cache to HIP and tries again.
+static thread_local int g_idle_depth = 0;
+struct IdleScope {
+    IdleScope() { ++g_idle_depth; }
+    ~IdleScope() { --g_idle_depth; }
+};
+
+class DevicePool {
+public:
+    static DevicePool& get() {
+        static DevicePool* pool = new DevicePool();   // outlives static destructors
+        return *pool;
+    }
+    // size class: 512 B minimum, powers of two up to 1 MiB, then 2 MiB multiples
+    static size_t size_class(size_t n) {
+        if (n <= 512) return 512;
+        if (n <= (size_t(1) << 20)) {
+            size_t c = 512;
+            while (c < n) c <<= 1;
+            return c;
+        }
+        const size_t g = size_t(2) << 20;
+        return (n + g - 1) / g * g;
+    }
+    void* take(int dev, size_t want, size_t& cap) {
+        const size_t c = size_class(want);
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            Dev& d = devs_[dev];
+            auto it = d.blocks.lower_bound(c);
+            // small classes match exactly; large blocks up to 1/8 above the request
+            if (it != d.blocks.end() && it->first <= c + (c > (size_t(1) << 20) ? c / 8 : 0)) {
+                void* p = it->second;
+                cap = it->first;
+                d.cached -= cap;
+                d.blocks.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, c);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim(dev);
+            e = hipMalloc(&p, c);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        cap = c;
+        return p;
+    }
+    void give(int dev, void* p, size_t cap) {
+        if (g_idle_depth == 0) (void)hipDeviceSynchronize();
+        std::vector<void*> drop;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            Dev& d = devs_[dev];
+            const size_t lim = limit(dev);
+            if (cap > lim) {
+                drop.push_back(p);
+            } else {
+                d.blocks.emplace(cap, p);
+                d.cached += cap;
+                while (d.cached > lim) {          // evict the largest blocks first
+                    auto it = std::prev(d.blocks.end());
+                    d.cached -= it->first;
+                    drop.push_back(it->second);
+                    d.blocks.erase(it);
+                }
+            }
+        }
+        for (void* q : drop) (void)hipFree(q);
+    }
+    // hands every cached block of a device (dev < 0: all devices) back to HIP
+    void trim(int dev) {
+        std::vector<std::pair<int, void*>> drop;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (auto& kv : devs_) {
+                if (dev >= 0 && kv.first != dev) continue;
+                for (auto& b : kv.second.blocks) drop.emplace_back(kv.first, b.second);
+                kv.second.blocks.clear();
+                kv.second.cached = 0;
+            }
+        }
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        for (auto& q : drop) {
+            (void)hipSetDevice(q.first);
+            (void)hipFree(q.second);
+        }
+        (void)hipSetDevice(cur);
+    }
+    int64_t cached(int dev) {
+        std::lock_guard<std::mutex> lk(mu_);
+        int64_t t = 0;
+        for (auto& kv : devs_)
+            if (dev < 0 || kv.first == dev) t += (int64_t)kv.second.cached;
+        return t;
+    }
+    void set_limit(int64_t bytes) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            user_limit_ = bytes;
+        }
+        if (bytes >= 0) {
+            // apply at once: drop what no longer fits
+            std::vector<std::pair<int, void*>> drop;
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                for (auto& kv : devs_) {
+                    Dev& d = kv.second;
+                    while (d.cached > (size_t)bytes && !d.blocks.empty()) {
+                        auto it = std::prev(d.blocks.end());
+                        d.cached -= it->first;
+                        drop.emplace_back(kv.first, it->second);
+                        d.blocks.erase(it);
+                    }
+                }
+            }
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            for (auto& q : drop) {
+                (void)hipSetDevice(q.first);
+                (void)hipFree(q.second);
+            }
+            (void)hipSetDevice(cur);
+        }
+    }
+
+private:
+    struct Dev {
+        std::multimap<size_t, void*> blocks;
+        size_t cached = 0;
+        size_t total = 0;     // device memory, read once
+    };
+    // default: min(16 GiB, 1/8 of the device memory); called with mu_ held
+    size_t limit(int dev) {
+        if (user_limit_ >= 0) return (size_t)user_limit_;
+        Dev& d = devs_[dev];
+        if (d.total == 0) {
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+                (void)hipGetLastError();
+                tot = size_t(8) << 30;
+            }
+            d.total = tot;
+        }
+        return std::min<size_t>(size_t(16) << 30, d.total / 8);
+    }
+    std::mutex mu_;
+    std::map<int, Dev> devs_;
+    int64_t user_limit_ = -1;
+};
+
 struct DevBuf {
     void* p = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;     // requested size
+    size_t cap = 0;       // size of the pool block
+    int dev = 0;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) DevicePool::get().give(dev, p, cap);
         p = nullptr;
-        bytes = 0;
+        bytes = cap = 0;
     }
     void alloc(size_t n) {
         release();
         if (n == 0) n = 16;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            throw Error(RSD_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
-        }
+        RSD_HIP(hipGetDevice(&dev));
+        p = DevicePool::get().take(dev, n, cap);
+        if (!p) throw Error(RSD_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
         bytes = n;
     }
     template <typename T> T* as() const { return static_cast<T*>(p); }
@@ -98,9 +262,11 @@ struct ProfRec {
     int cls;
     hipEvent_t a, b;
     double flops, bytes;
+    int64_t groups;     // work-groups of the launch (0: not recorded)
 };
 struct Profiler {
     bool on = false;
+    uint32_t mask = ~0u;        // classes bracketed while on
     std::mutex mu;              // solves of different factors may run on several threads
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
@@ -127,9 +293,10 @@ struct ProfScope {
     bool act;
     ProfRec rec;
     hipStream_t s;
-    ProfScope(int cls, hipStream_t st, double flops = 0, double bytes = 0) : act(g_prof.on), s(st) {
+    ProfScope(int cls, hipStream_t st, double flops = 0, double bytes = 0, int64_t groups = 0)
+        : act(g_prof.on && ((g_prof.mask >> cls) & 1u)), s(st) {
         if (!act) return;
-        rec.cls = cls; rec.flops = flops; rec.bytes = bytes;
+        rec.cls = cls; rec.flops = flops; rec.bytes = bytes; rec.groups = groups;
         rec.a = g_prof.get();
         rec.b = g_prof.get();
         RSD_HIP(hipEventRecord(rec.a, s));
@@ -146,30 +313,91 @@ struct ProfScope {
 template <typename T>
 struct GemmBatch {
     std::vector<GemmDesc<T>> descs;
-    std::vector<TileRef> tiles;
+    std::vector<TileRef> tiles;            // built by finalize(): one per work-group
+    std::vector<TileRef> slots;            // split tiles (reduce dispatch), one each
     const GemmDesc<T>* d_descs = nullptr;
     const TileRef* d_tiles = nullptr;
+    const TileRef* d_slots = nullptr;
+    T* d_ws = nullptr;                     // split-K partial tiles (shared by a batch list)
+    int tile = 64;
+    int64_t ws_elems = 0;                  // partial-tile elements
     double flops = 0, bytes = 0;
     int prof_cls = -1;
     int role = -1;      // kernel instantiation (see launch_gemm); -1: from prof_cls
     void add(const GemmDesc<T>& d) {
         if (d.M <= 0 || d.N <= 0) return;
-        const int id = (int)descs.size();
         descs.push_back(d);
-        const int tm = (d.M + GEMM_TILE - 1) / GEMM_TILE, tn = (d.N + GEMM_TILE - 1) / GEMM_TILE;
-        for (int i = 0; i < tm; ++i)
-            for (int j = 0; j < tn; ++j) tiles.push_back({id, i, j});
         const double kk = (double)(std::max(d.K, 0) + std::max(d.K2, 0));
         flops += 2.0 * d.M * d.N * kk;
         bytes += sizeof(T) * ((double)d.M * kk + kk * d.N + 2.0 * d.M * d.N);
     }
+    bool empty() const { return descs.empty(); }
+    // Tile table.  128-wide tiles when the products are large and give every
+    // compute unit two tiles; otherwise 64.  When even the 64-wide tiles
+    // cannot give every compute unit one, long K ranges are split (at least
+    // eight panels per split, at most 16 splits) and summed by a second
+    // dispatch.
+    void finalize() {
+        constexpr int CUS = 256;
+        // the kernel addresses each operand with 32-bit byte offsets
+        auto extent = [](int rows, int cols, int ld, int tr) {
+            if (rows <= 0 || cols <= 0) return (int64_t)0;
+            return (int64_t)sizeof(T) * ((tr ? (int64_t)(cols - 1) + (int64_t)(rows - 1) * ld
+                                             : (int64_t)(rows - 1) + (int64_t)(cols - 1) * ld) + 1);
+        };
+        for (auto& d : descs) {
+            int64_t e = std::max(extent(d.M, d.K, d.lda, d.tA), extent(d.K, d.N, d.ldb, d.tB));
+            if (d.K2 > 0) e = std::max({e, extent(d.M, d.K2, d.lda2, d.tA2), extent(d.K2, d.N, d.ldb2, d.tB2)});
+            if (e + 16 > (int64_t)GEMM_MAX_OPERAND_BYTES)
+                throw Error(RSD_EINVAL, "matrix block too large for the GEMM kernel (2 GiB operand limit)");
+        }
+        tiles.clear();
+        slots.clear();
+        ws_elems = 0;
+        int64_t t64 = 0, t128 = 0;
+        double big = 0, tot = 0;
+        for (auto& d : descs) {
+            t64 += (int64_t)((d.M + 63) / 64) * ((d.N + 63) / 64);
+            t128 += (int64_t)((d.M + 127) / 128) * ((d.N + 127) / 128);
+            const double w = (double)d.M * d.N * (std::max(d.K, 0) + std::max(d.K2, 0));
+            tot += w;
+            if (d.M >= 128 && d.N >= 128) big += w;
+        }
+        tile = (t128 >= 2 * CUS && big >= 0.8 * tot) ? 128 : 64;
+        const int64_t nt = tile == 128 ? t128 : t64;
+        const int bk = (sizeof(T) == 8 && tile == 128) ? 8 : 16;
+        for (int id = 0; id < (int)descs.size(); ++id) {
+            const auto& d = descs[id];
+            const int steps = (std::max(d.K, 0) + bk - 1) / bk + (std::max(d.K2, 0) + bk - 1) / bk;
+            int S = 1;
+            if (nt < CUS) S = std::max(1, std::min<int>({(int)((2 * CUS + nt - 1) / nt), steps / 8, 16}));
+            const int tm = (d.M + tile - 1) / tile, tn = (d.N + tile - 1) / tile;
+            for (int i = 0; i < tm; ++i)
+                for (int j = 0; j < tn; ++j) {
+                    if (S == 1) {
+                        tiles.push_back({id, i, j, 0, 1, 0});
+                        continue;
+                    }
+                    const int pbase = (int)(ws_elems / ((int64_t)tile * tile));
+                    for (int sp = 0; sp < S; ++sp) tiles.push_back({id, i, j, sp, S, pbase});
+                    slots.push_back({id, i, j, 0, S, pbase});
+                    ws_elems += (int64_t)S * tile * tile;
+                }
+        }
+    }
     void run(hipStream_t s) const {
         if (tiles.empty()) return;
-        ProfScope ps(prof_cls, s, flops, bytes);
         const int r = role >= 0 ? role
                     : (prof_cls == RSD_PROF_FACTOR_GEMM_F64 || prof_cls == RSD_PROF_FACTOR_GEMM_F32) ? 0
                     : (prof_cls == RSD_PROF_SOLVE_GEMM ? 2 : 1);
-        launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), s, r);
+        {
+            ProfScope ps(prof_cls, s, flops, bytes, (int64_t)tiles.size());
+            launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), tile, d_ws, 0, s, r);
+        }
+        if (!slots.empty()) {
+            ProfScope ps(prof_cls, s, 0, 0, (int64_t)slots.size());
+            launch_gemm<T>(d_descs, d_slots, (int)slots.size(), tile, d_ws, 1, s, r);
+        }
     }
 };
 
@@ -189,23 +417,37 @@ static GemmDesc<T> gdesc(int M, int N, int K, const T* A, int lda, int tA, const
     return d;
 }
 
-// Uploads every batch of a list into one buffer and fixes their device pointers.
+// Uploads every batch of a list into one buffer and fixes their device
+// pointers.  The batches of one list run one after another on one stream, so
+// they share one split-K workspace, sized for the largest.
 template <typename T>
 static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStream_t s) {
     size_t nd = 0, nt = 0;
-    for (auto* b : bs) { nd += b->descs.size(); nt += b->tiles.size(); }
-    std::vector<unsigned char> host(nd * sizeof(GemmDesc<T>) + nt * sizeof(TileRef) + 64);
-    buf.alloc(host.size());
-    size_t od = 0, ot = nd * sizeof(GemmDesc<T>);
-    ot = (ot + 15) & ~size_t(15);
+    int64_t max_ws = 0;
+    for (auto* b : bs) {
+        b->finalize();
+        nd += b->descs.size();
+        nt += b->tiles.size() + b->slots.size();
+        max_ws = std::max(max_ws, b->ws_elems);
+    }
+    auto up = [](size_t x, size_t a) { return (x + a - 1) / a * a; };
+    const size_t o_tiles = up(nd * sizeof(GemmDesc<T>), 16);
+    const size_t o_ws = up(o_tiles + nt * sizeof(TileRef), 256);
+    std::vector<unsigned char> host(o_tiles + nt * sizeof(TileRef));
+    buf.alloc(o_ws + (size_t)max_ws * sizeof(T));
     unsigned char* base = buf.as<unsigned char>();
+    size_t od = 0, ot = o_tiles;
     for (auto* b : bs) {
         std::memcpy(host.data() + od, b->descs.data(), b->descs.size() * sizeof(GemmDesc<T>));
-        std::memcpy(host.data() + ot, b->tiles.data(), b->tiles.size() * sizeof(TileRef));
         b->d_descs = reinterpret_cast<const GemmDesc<T>*>(base + od);
-        b->d_tiles = reinterpret_cast<const TileRef*>(base + ot);
         od += b->descs.size() * sizeof(GemmDesc<T>);
+        std::memcpy(host.data() + ot, b->tiles.data(), b->tiles.size() * sizeof(TileRef));
+        b->d_tiles = reinterpret_cast<const TileRef*>(base + ot);
         ot += b->tiles.size() * sizeof(TileRef);
+        std::memcpy(host.data() + ot, b->slots.data(), b->slots.size() * sizeof(TileRef));
+        b->d_slots = reinterpret_cast<const TileRef*>(base + ot);
+        ot += b->slots.size() * sizeof(TileRef);
+        b->d_ws = reinterpret_cast<T*>(base + o_ws);
     }
     RSD_HIP(hipMemcpyAsync(buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
 }
@@ -278,10 +520,19 @@ struct Factor {
     std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
     rsd_factor_stats stats{};
     ~Factor() {
-        solve_plans.clear();
         if (stream) (void)hipStreamSynchronize(stream);
         for (auto q : qr_stream)
             if (q) (void)hipStreamSynchronize(q);
+        {
+            // every stream that touched the factor's memory has drained
+            IdleScope idle;
+            solve_plans.clear();
+            scratch.clear();
+            for (DevBuf* b : {&d_boxes, &d_layouts, &d_lu, &d_lv, &d_srcc, &d_srci, &d_inv, &d_perm,
+                              &d_ident, &d_a, &d_sb, &d_level_ids, &d_err, &d_table, &d_spec, &d_fftwork,
+                              &d_flag, &F64, &F32, &T64, &T32, &SR, &SC, &gemm64, &gemm32, &gj64, &gj32})
+                b->release();
+        }
         for (auto e : tmp_events) (void)hipEventDestroy(e);
         for (auto e : build_ev)
             if (e) (void)hipEventDestroy(e);
@@ -811,7 +1062,7 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
     }
     L.g_sr.run(s);
     L.g_rr.run(s);
-    if (!L.g_sr.tiles.empty()) {
+    if (!L.g_sr.empty()) {
         ProfScope ps(RSD_PROF_ASSEMBLY, s);
         launch_transpose_sr<T>(F, B, f.ids(t), n, L.max_k, L.max_r, s);
     }
@@ -1152,7 +1403,10 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
 static void build_finish(Factor& f) {
     RSD_HIP(hipStreamSynchronize(f.stream));
     for (auto q : f.qr_stream) RSD_HIP(hipStreamSynchronize(q));
-    f.scratch.clear();
+    {
+        IdleScope idle;     // the build's streams have drained
+        f.scratch.clear();
+    }
     for (auto e : f.tmp_events) (void)hipEventDestroy(e);
     f.tmp_events.clear();
     float ms = 0;
@@ -1548,6 +1802,28 @@ static rsd_status guarded(Fn&& fn) {
 
 extern "C" {
 
+rsd_status rsd_pool_trim(int32_t device) {
+    return guarded([&]() {
+        rsd::DevicePool::get().trim(device);
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_pool_set_limit(int64_t bytes) {
+    return guarded([&]() {
+        rsd::DevicePool::get().set_limit(bytes < 0 ? -1 : bytes);
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_pool_cached_bytes(int32_t device, int64_t* out) {
+    return guarded([&]() {
+        if (!out) throw rsd::Error(RSD_EINVAL, "out is null");
+        *out = rsd::DevicePool::get().cached(device);
+        return RSD_OK;
+    });
+}
+
 rsd_status rsd_build_factor(const double* points, int64_t n_points, const rsd_kernel* kernel,
                             const double* a, double tol, const rsd_options* opt, rsd_factor** out) {
     if (out) *out = nullptr;
@@ -1620,6 +1896,17 @@ rsd_status rsd_profile_enable(int32_t on) {
         if (!rsd::g_prof.recs.empty()) RSD_HIP(hipDeviceSynchronize());
         rsd::g_prof.clear();
         rsd::g_prof.on = on != 0;
+        rsd::g_prof.mask = ~0u;
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_profile_enable_mask(uint32_t mask) {
+    return guarded([&]() {
+        if (!rsd::g_prof.recs.empty()) RSD_HIP(hipDeviceSynchronize());
+        rsd::g_prof.clear();
+        rsd::g_prof.on = mask != 0;
+        rsd::g_prof.mask = mask;
         return RSD_OK;
     });
 }
@@ -1644,6 +1931,36 @@ rsd_status rsd_profile_query(int32_t cls, double* total_ms, int64_t* launches, d
         if (launches) *launches = n;
         if (flops) *flops = fl;
         if (bytes) *bytes = by;
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_profile_record_count(int64_t* n) {
+    return guarded([&]() {
+        if (!n) throw rsd::Error(RSD_EINVAL, "n is null");
+        std::lock_guard<std::mutex> lk(rsd::g_prof.mu);
+        *n = (int64_t)rsd::g_prof.recs.size();
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_profile_record(int64_t i, int32_t* cls, double* ms, double* flops, double* bytes,
+                              int64_t* groups) {
+    return guarded([&]() {
+        rsd::ProfRec r;
+        {
+            std::lock_guard<std::mutex> lk(rsd::g_prof.mu);
+            if (i < 0 || i >= (int64_t)rsd::g_prof.recs.size()) throw rsd::Error(RSD_EINVAL, "no such record");
+            r = rsd::g_prof.recs[(size_t)i];
+        }
+        RSD_HIP(hipEventSynchronize(r.b));
+        float e = 0;
+        RSD_HIP(hipEventElapsedTime(&e, r.a, r.b));
+        if (cls) *cls = r.cls;
+        if (ms) *ms = e;
+        if (flops) *flops = r.flops;
+        if (bytes) *bytes = r.bytes;
+        if (groups) *groups = r.groups;
         return RSD_OK;
     });
 }

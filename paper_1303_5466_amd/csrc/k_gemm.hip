@@ -2,11 +2,28 @@
 //
 // One launch runs a list of independent products (one per box of a tree
 // level, or two per box), each described by a GemmDesc; a flat tile table
-// maps workgroups to 64 x 64 output tiles, so boxes of different sizes share
-// one launch without idle workgroups.  Every per-box dense block update of
-// the factorisation (Schur complements, interpolation transforms, the
+// maps workgroups to output tiles, so boxes of different sizes share one
+// launch without idle workgroups.  Every per-box dense block update of the
+// factorisation (Schur complements, interpolation transforms, the
 // Gauss-Jordan rank-nb updates) and the level sweeps of the solve go through
 // this kernel.
+//
+// Work-group: 256 threads = 2 x 2 waves, each wave a (TILE/2)^2 sub-tile of
+// 16 x 16 MFMA blocks.  Operand panels (TILE x BK of op(A), BK x TILE of
+// op(B)) are staged through double-buffered LDS: the global loads of the
+// next panel are in flight while the MFMAs consume the current one, and one
+// barrier per panel suffices.  The MFMA is issued with its operands swapped
+// (it computes the transposed block), so that a lane's accumulators are
+// consecutive rows of one column of C: the epilogue's loads and stores of C
+// cover whole column segments.
+//
+// Split-K: when a launch has too few tiles to occupy the chip, a tile's
+// (concatenated) K range is split over `nsplit` work-groups, each of which
+// writes its partial tile to a workspace; a second dispatch of the same
+// kernel (reduce mode, one work-group per split tile) adds the partials in
+// split order, applies alpha / beta and stores C.  The kernel boundary orders
+// the two, so no fences or atomics are needed, and the sum does not depend on
+// which work-group ran first.
 #include "common.hpp"
 
 namespace rsd {
@@ -17,158 +34,285 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
-// Accumulator layout (16 x 16 block, lane l, element v):
-//   f64 16x16x4: row = (l / 16) + 4 v,  column = l % 16
-//   f32 16x16x4: row = 4 (l / 16) + v,  column = l % 16
-// Inputs: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] in both.
+// MFMA 16x16x4 (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// result element v of lane l is D[r][c]).  Called as step(b, a, acc) it
+// returns the transposed product, so C[l % 16][col(l, v)] is element v.
+//   f64: D row = l / 16 + 4 v, column = l % 16  ->  col(l, v) = l / 16 + 4 v
+//   f32: D row = 4 (l / 16) + v, column = l % 16 ->  col(l, v) = 4 (l / 16) + v
 template <> struct Mfma<double> {
     typedef d4 acc_t;
-    __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+    __device__ static inline int col(int lane, int v) { return (lane >> 4) + 4 * v; }
     __device__ static inline acc_t step(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
 };
 template <> struct Mfma<float> {
     typedef f4 acc_t;
-    __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+    __device__ static inline int col(int lane, int v) { return 4 * (lane >> 4) + v; }
     __device__ static inline acc_t step(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
 };
 
-constexpr int TILE = GEMM_TILE;   // 64
-constexpr int BK = 16;
-constexpr int PAD = 16;
-constexpr int LDS_W = TILE + PAD;
+template <typename T, int TILE>
+struct Cfg {
+    // k extent of one staged panel (two stages of both operands stay within
+    // 64 KB of LDS; 37 KB for the 128-wide tiles)
+    static constexpr int BK = (sizeof(T) == 8 && TILE == 128) ? 8 : 16;
+    static constexpr int LD = TILE + 16;          // LDS row stride: rows 128 B apart mod 256 B
+    static constexpr int NB = TILE / 32;          // 16 x 16 blocks per wave and dimension
+    static constexpr int LOADS = TILE * BK / 256; // elements per thread per operand panel
+};
 
+// Loads go through buffer instructions: an element outside the product
+// (row or column past M / N, k past K) gets an offset past the descriptor's
+// range, for which the hardware returns zero, so the masked loads need no
+// branches.  Offsets are 32-bit bytes from the operand's base pointer; the
+// host keeps every operand's extent below RSRC_RANGE, and a masked element's
+// offset is RSRC_RANGE itself, the first out-of-range byte.
+constexpr int RSRC_RANGE = 0x7ffffff0;
+constexpr int OFF_MASKED = RSRC_RANGE;
+constexpr int RSRC_WORD3 = 0x00020000;    // raw buffer, 32-bit data format
+
+template <typename T> struct BufLoad;
+template <> struct BufLoad<double> {
+    __device__ static inline double at(__amdgpu_buffer_rsrc_t r, int off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+};
+template <> struct BufLoad<float> {
+    __device__ static inline float at(__amdgpu_buffer_rsrc_t r, int off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    }
+};
+
+// Per-thread plan of one operand panel.  Because 256 is a multiple of TILE
+// and BK, a thread's elements of a panel share one row (or one k) and step
+// through the other index with a constant stride: element q of the thread
+// sits q * qs elements after the first (plus ps per panel), is valid while
+// r0 + q * rq < rmax and k0 + q * kq < K, and goes to LDS word l0 + q * lq.
 template <typename T>
-__device__ inline void load_tiles(const T* __restrict__ A, int lda, int tA, const T* __restrict__ B,
-                                  int ldb, int tB, int M, int N, int K, int row0, int col0, int k0,
-                                  T (&ra)[4], T (&rb)[4]) {
+struct PanelPlan {
+    __amdgpu_buffer_rsrc_t rs;
+    int off0, qs, ps;
+    int r0, rq, rmax, k0, kq, l0, lq;
+};
+
+// op(X) is rows x K (A: rows = M) or K x cols (B): `along_rows` says whether
+// memory is contiguous along the tile's row/column index (A without
+// transpose, B with transpose) or along k.
+template <typename T, int TILE>
+__device__ inline PanelPlan<T> panel_plan(const T* X, int ld, bool along_rows, int base, int lim) {
+    constexpr int BK = Cfg<T, TILE>::BK, LD = Cfg<T, TILE>::LD;
     const int t = threadIdx.x;
+    PanelPlan<T> P;
+    P.rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, RSRC_RANGE, RSRC_WORD3);
+    if (along_rows) {   // element (i = t % TILE, kk = t / TILE + q 256 / TILE)
+        const int i = t % TILE, kk = t / TILE;
+        P.off0 = base + i + kk * ld;
+        P.qs = (256 / TILE) * ld;
+        P.ps = BK * ld;
+        P.r0 = base + i; P.rq = 0; P.rmax = lim;
+        P.k0 = kk; P.kq = 256 / TILE;
+        P.l0 = kk * LD + i; P.lq = (256 / TILE) * LD;
+    } else {            // element (kk = t % BK, i = t / BK + q 256 / BK)
+        const int kk = t % BK, i = t / BK;
+        P.off0 = kk + (base + i) * ld;
+        P.qs = (256 / BK) * ld;
+        P.ps = BK;
+        P.r0 = base + i; P.rq = 256 / BK; P.rmax = lim;
+        P.k0 = kk; P.kq = 0;
+        P.l0 = kk * LD + i; P.lq = 256 / BK;
+    }
+    return P;
+}
+
+template <typename T, int TILE>
+__device__ inline void load_panel(const PanelPlan<T>& P, int K, int panel, T (&r)[Cfg<T, TILE>::LOADS]) {
+    constexpr int BK = Cfg<T, TILE>::BK;
+    const int kb = panel * BK;
+    const int o = P.off0 + panel * P.ps;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = t + 256 * q;
-        int i, kk;
-        if (tA == 0) { i = e & 63; kk = e >> 6; }
-        else { kk = e & 15; i = e >> 4; }
-        const int gi = row0 + i, gk = k0 + kk;
-        T v = T(0);
-        if (gi < M && gk < K) v = tA == 0 ? A[gi + (int64_t)gk * lda] : A[gk + (int64_t)gi * lda];
-        ra[q] = v;
-        int j, kb;
-        if (tB == 0) { kb = e & 15; j = e >> 4; }
-        else { j = e & 63; kb = e >> 6; }
-        const int gj = col0 + j, gkb = k0 + kb;
-        T w = T(0);
-        if (gj < N && gkb < K) w = tB == 0 ? B[gkb + (int64_t)gj * ldb] : B[gj + (int64_t)gkb * ldb];
-        rb[q] = w;
+    for (int q = 0; q < Cfg<T, TILE>::LOADS; ++q) {
+        const bool ok = (P.r0 + q * P.rq < P.rmax) & (kb + P.k0 + q * P.kq < K);
+        r[q] = BufLoad<T>::at(P.rs, ok ? (o + q * P.qs) * (int)sizeof(T) : OFF_MASKED);
     }
 }
 
-template <typename T>
-__device__ inline void store_tiles(T (*As)[LDS_W], T (*Bs)[LDS_W], int tA, int tB, const T (&ra)[4],
-                                   const T (&rb)[4]) {
-    const int t = threadIdx.x;
+template <typename T, int TILE>
+__device__ inline void store_panel(const PanelPlan<T>& P, T* S, const T (&r)[Cfg<T, TILE>::LOADS]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = t + 256 * q;
-        int i, kk;
-        if (tA == 0) { i = e & 63; kk = e >> 6; }
-        else { kk = e & 15; i = e >> 4; }
-        As[kk][i] = ra[q];
-        int j, kb;
-        if (tB == 0) { kb = e & 15; j = e >> 4; }
-        else { j = e & 63; kb = e >> 6; }
-        Bs[kb][j] = rb[q];
-    }
+    for (int q = 0; q < Cfg<T, TILE>::LOADS; ++q) S[P.l0 + q * P.lq] = r[q];
 }
 
-template <typename T>
+// Panels p0 .. p1 - 1 of one K segment, accumulated into acc.
+template <typename T, int TILE>
 __device__ inline void run_segment(const T* A, int lda, int tA, const T* B, int ldb, int tB, int M,
-                                   int N, int K, int row0, int col0, T (*As)[LDS_W],
-                                   T (*Bs)[LDS_W], typename Mfma<T>::acc_t (&acc)[2][2]) {
-    if (K <= 0) return;
+                                   int N, int K, int row0, int col0, int p0, int p1, T* lds,
+                                   typename Mfma<T>::acc_t (&acc)[Cfg<T, TILE>::NB][Cfg<T, TILE>::NB]) {
+    typedef Cfg<T, TILE> C_;
+    constexpr int LD = C_::LD, NB = C_::NB, BK = C_::BK, PANEL = BK * LD;
+    if (p0 >= p1) return;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    T ra[4], rb[4];
-    load_tiles(A, lda, tA, B, ldb, tB, M, N, K, row0, col0, 0, ra, rb);
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        __syncthreads();
-        store_tiles(As, Bs, tA, tB, ra, rb);
-        __syncthreads();
-        if (k0 + BK < K) load_tiles(A, lda, tA, B, ldb, tB, M, N, K, row0, col0, k0 + BK, ra, rb);
+    const int wr = (wave >> 1) * (TILE / 2), wc = (wave & 1) * (TILE / 2);
+    const PanelPlan<T> pa = panel_plan<T, TILE>(A, lda, !tA, row0, M);
+    const PanelPlan<T> pb = panel_plan<T, TILE>(B, ldb, tB, col0, N);
+    T ra[C_::LOADS], rb[C_::LOADS];
+    load_panel<T, TILE>(pa, K, p0, ra);
+    load_panel<T, TILE>(pb, K, p0, rb);
+    __syncthreads();            // the previous segment's last panel is consumed
+    store_panel<T, TILE>(pa, lds, ra);
+    store_panel<T, TILE>(pb, lds + PANEL, rb);
+    __syncthreads();
+    // The loop body has no branches (a branch here makes the compiler move
+    // the accumulators between register files every panel): the panel after
+    // the last one is loaded too (masked to zero past K, unused otherwise) and
+    // stored to the idle stage.
+    for (int p = p0; p < p1; ++p) {
+        const int cur = (p - p0) & 1;
+        load_panel<T, TILE>(pa, K, p + 1, ra);
+        load_panel<T, TILE>(pb, K, p + 1, rb);
+        const T* As = lds + cur * 2 * PANEL;
+        const T* Bs = As + PANEL;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4);
-            T a0 = As[kr][wr + (lane & 15)];
-            T a1 = As[kr][wr + 16 + (lane & 15)];
-            T b0 = Bs[kr][wc + (lane & 15)];
-            T b1 = Bs[kr][wc + 16 + (lane & 15)];
-            acc[0][0] = Mfma<T>::step(a0, b0, acc[0][0]);
-            acc[0][1] = Mfma<T>::step(a0, b1, acc[0][1]);
-            acc[1][0] = Mfma<T>::step(a1, b0, acc[1][0]);
-            acc[1][1] = Mfma<T>::step(a1, b1, acc[1][1]);
+            T a[NB], b[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) a[i] = As[kr * LD + wr + 16 * i + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) b[j] = Bs[kr * LD + wc + 16 * j + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[i][j] = Mfma<T>::step(b[j], a[i], acc[i][j]);
         }
+        T* Ns = lds + (cur ^ 1) * 2 * PANEL;
+        store_panel<T, TILE>(pa, Ns, ra);
+        store_panel<T, TILE>(pb, Ns + PANEL, rb);
+        __syncthreads();
     }
 }
 
-// ROLE only names the instantiation (factor levels 0, interpolation 1,
-// solve sweeps 2, library calls 3) so that profiles can tell the launch
-// sites apart; the code is the same.
-template <typename T, int ROLE>
+// C element of accumulator (i, j, v) of thread t in a TILE x TILE tile
+template <typename T, int TILE>
+__device__ inline void tile_coords(int t, int i, int j, int v, int& r, int& c) {
+    const int lane = t & 63, wave = t >> 6;
+    r = (wave >> 1) * (TILE / 2) + 16 * i + (lane & 15);
+    c = (wave & 1) * (TILE / 2) + 16 * j + Mfma<T>::col(lane, v);
+}
+
+template <typename T, int TILE>
+__device__ inline void store_c(const GemmDesc<T>& d, int gi, int gj, T sum) {
+    if (gi < d.M && gj < d.N) {
+        T* c = d.C + gi + (int64_t)gj * d.ldc;
+        T val = d.alpha * sum;
+        const bool zb = gj >= d.zc0 && gj < d.zc1;
+        if (d.beta != T(0) && !zb) val += d.beta * *c;
+        *c = val;
+    }
+}
+
+// reduce == 0: tiles[blockIdx.x] is a (split) tile of the product;
+// reduce == 1: tiles[blockIdx.x] names a split tile whose partials are summed.
+template <typename T, int ROLE, int TILE>
 __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict__ descs,
-                                                   const TileRef* __restrict__ tiles) {
-    __shared__ T As[BK][LDS_W];
-    __shared__ T Bs[BK][LDS_W];
+                                                   const TileRef* __restrict__ tiles,
+                                                   T* __restrict__ ws, int reduce) {
+    typedef Cfg<T, TILE> C_;
+    constexpr int NB = C_::NB, BK = C_::BK, PANEL = BK * C_::LD;
+    constexpr int PER = NB * NB * 4;               // accumulators per thread
+    __shared__ __align__(16) T lds[4 * PANEL];   // two stages of [A | B]
     const TileRef tr = tiles[blockIdx.x];
     const GemmDesc<T> d = descs[tr.desc];
     if (d.guard && *d.guard) return;
     const int row0 = tr.tm * TILE, col0 = tr.tn * TILE;
-    typename Mfma<T>::acc_t acc[2][2];
+    const int t = threadIdx.x;
+    // partial tiles in thread-major order: accumulator (i, j, v) of thread t
+    const T* part = ws + (int64_t)tr.pbase * (PER * 256);
+
+    if (reduce) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    run_segment(d.A, d.lda, d.tA, d.B, d.ldb, d.tB, d.M, d.N, d.K, row0, col0, As, Bs, acc);
-    run_segment(d.A2, d.lda2, d.tA2, d.B2, d.ldb2, d.tB2, d.M, d.N, d.K2, row0, col0, As, Bs, acc);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+            for (int j = 0; j < NB; ++j)
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+                for (int v = 0; v < 4; ++v) {
+                    const int e = ((i * NB + j) * 4 + v) * 256 + t;
+                    T sum = T(0);
+                    for (int sp = 0; sp < tr.nsplit; ++sp) sum += part[(int64_t)sp * (PER * 256) + e];
+                    int r, c;
+                    tile_coords<T, TILE>(t, i, j, v, r, c);
+                    store_c<T, TILE>(d, row0 + r, col0 + c, sum);
+                }
+        return;
+    }
+
+    const int n1 = d.K > 0 ? (d.K + BK - 1) / BK : 0;
+    const int n2 = d.K2 > 0 ? (d.K2 + BK - 1) / BK : 0;
+    const int nst = n1 + n2;
+    const int st0 = (int)((int64_t)tr.split * nst / tr.nsplit);
+    const int st1 = (int)((int64_t)(tr.split + 1) * nst / tr.nsplit);
+    typename Mfma<T>::acc_t acc[NB][NB];
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+
+    // panels [st0, st1) of the concatenated K range: first segment, then second
+    run_segment<T, TILE>(d.A, d.lda, d.tA, d.B, d.ldb, d.tB, d.M, d.N, d.K, row0, col0, min(st0, n1),
+                         min(st1, n1), lds, acc);
+    run_segment<T, TILE>(d.A2, d.lda2, d.tA2, d.B2, d.ldb2, d.tB2, d.M, d.N, d.K2, row0, col0,
+                         max(st0, n1) - n1, max(st1, n1) - n1, lds, acc);
+
+    if (tr.nsplit > 1) {
+        T* mine = ws + ((int64_t)tr.pbase + tr.split) * (PER * 256);
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) mine[((i * NB + j) * 4 + v) * 256 + t] = acc[i][j][v];
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gi = row0 + wr + bi * 16 + Mfma<T>::row(lane, v);
-                const int gj = col0 + wc + bj * 16 + (lane & 15);
-                if (gi < d.M && gj < d.N) {
-                    T* c = d.C + gi + (int64_t)gj * d.ldc;
-                    T val = d.alpha * acc[bi][bj][v];
-                    const bool zb = gj >= d.zc0 && gj < d.zc1;
-                    if (d.beta != T(0) && !zb) val += d.beta * *c;
-                    *c = val;
-                }
+                int r, c;
+                tile_coords<T, TILE>(t, i, j, v, r, c);
+                store_c<T, TILE>(d, row0 + r, col0 + c, acc[i][j][v]);
             }
+}
+
+template <typename T, int ROLE>
+void launch_role(const GemmDesc<T>* d, const TileRef* t, int n, int tile, T* ws, int reduce, hipStream_t s) {
+    if (tile == 128)
+        hipLaunchKernelGGL((gemm_kernel<T, ROLE, 128>), dim3(n), dim3(256), 0, s, d, t, ws, reduce);
+    else
+        hipLaunchKernelGGL((gemm_kernel<T, ROLE, 64>), dim3(n), dim3(256), 0, s, d, t, ws, reduce);
 }
 
 }  // namespace
 
 template <typename T>
-void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, hipStream_t s,
-                 int role) {
+void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, int tile, T* ws,
+                 int reduce, hipStream_t s, int role) {
     if (n_tiles <= 0) return;
     switch (role) {
-        case 0: hipLaunchKernelGGL((gemm_kernel<T, 0>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
-        case 1: hipLaunchKernelGGL((gemm_kernel<T, 1>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
-        case 2: hipLaunchKernelGGL((gemm_kernel<T, 2>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
-        default: hipLaunchKernelGGL((gemm_kernel<T, 3>), dim3(n_tiles), dim3(256), 0, s, d_descs, d_tiles); break;
+        case 0: launch_role<T, 0>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
+        case 1: launch_role<T, 1>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
+        case 2: launch_role<T, 2>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
+        default: launch_role<T, 3>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
     }
 }
 
-template void launch_gemm<double>(const GemmDesc<double>*, const TileRef*, int, hipStream_t, int);
-template void launch_gemm<float>(const GemmDesc<float>*, const TileRef*, int, hipStream_t, int);
+template void launch_gemm<double>(const GemmDesc<double>*, const TileRef*, int, int, double*, int,
+                                  hipStream_t, int);
+template void launch_gemm<float>(const GemmDesc<float>*, const TileRef*, int, int, float*, int,
+                                 hipStream_t, int);
 
 }  // namespace rsd

@@ -302,39 +302,48 @@ std::vector<int64_t> box_points(const Plan& p, int box) {
 bool detect_grid(const double* pts, int64_t n, int64_t& nx, int64_t& ny, double& h,
                  double& x0, double& y0, std::vector<int64_t>& perm, std::string& why) {
     if (n < 1) { why = "no points"; return false; }
-    std::vector<double> xs(n), ys(n);
+    // one pass for the extent, one for the second grid line of each axis (the
+    // smallest coordinate above the minimum), which gives the spacing; the
+    // placement pass below then checks every point against that grid
+    double xmin = pts[0], xmax = pts[0], ymin = pts[1], ymax = pts[1];
     for (int64_t i = 0; i < n; ++i) {
-        xs[i] = pts[2 * i];
-        ys[i] = pts[2 * i + 1];
-        if (!std::isfinite(xs[i]) || !std::isfinite(ys[i])) { why = "non-finite coordinate"; return false; }
+        const double x = pts[2 * i], y = pts[2 * i + 1];
+        if (!std::isfinite(x) || !std::isfinite(y)) { why = "non-finite coordinate"; return false; }
+        xmin = std::min(xmin, x); xmax = std::max(xmax, x);
+        ymin = std::min(ymin, y); ymax = std::max(ymax, y);
     }
-    auto ux = xs, uy = ys;
-    std::sort(ux.begin(), ux.end());
-    std::sort(uy.begin(), uy.end());
-    double span = std::max(ux.back() - ux.front(), uy.back() - uy.front());
-    double eps = 1e-9 * std::max(1.0, span);
-    auto uniq = [&](std::vector<double>& v) {
-        std::vector<double> o;
-        for (double x : v)
-            if (o.empty() || x - o.back() > eps) o.push_back(x);
-        return o;
+    const double span = std::max(xmax - xmin, ymax - ymin);
+    const double eps = 1e-9 * std::max(1.0, span);
+    double x1 = HUGE_VAL, y1 = HUGE_VAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = pts[2 * i], y = pts[2 * i + 1];
+        if (x - xmin > eps) x1 = std::min(x1, x);
+        if (y - ymin > eps) y1 = std::min(y1, y);
+    }
+    auto lines = [&](double lo, double hi, double second, int64_t& cnt) {
+        if (second == HUGE_VAL) { cnt = 1; return true; }
+        const double q = (hi - lo) / (second - lo);
+        if (!(q < (double)n)) return false;          // more lines than points
+        cnt = (int64_t)std::llround(q) + 1;
+        return true;
     };
-    auto gx = uniq(ux), gy = uniq(uy);
-    nx = (int64_t)gx.size();
-    ny = (int64_t)gy.size();
-    if (nx * ny != n) { why = "point count is not nx * ny"; return false; }
+    if (!lines(xmin, xmax, x1, nx) || !lines(ymin, ymax, y1, ny) || nx * ny != n) {
+        why = "point count is not nx * ny";
+        return false;
+    }
     if (nx == 1 && ny == 1) { why = "a single point is not a grid"; return false; }
-    double hx = nx > 1 ? (gx.back() - gx.front()) / double(nx - 1) : 0.0;
-    double hy = ny > 1 ? (gy.back() - gy.front()) / double(ny - 1) : 0.0;
+    const double hx = nx > 1 ? (xmax - xmin) / double(nx - 1) : 0.0;
+    const double hy = ny > 1 ? (ymax - ymin) / double(ny - 1) : 0.0;
     h = nx > 1 ? hx : hy;
     if (nx > 1 && ny > 1 && std::fabs(hx - hy) > 1e-9 * h) { why = "spacing differs in x and y"; return false; }
     if (!(h > 0)) { why = "zero spacing"; return false; }
-    x0 = gx.front();
-    y0 = gy.front();
+    x0 = xmin;
+    y0 = ymin;
     perm.assign(n, -1);
+    const double ih = 1.0 / h;
     for (int64_t p = 0; p < n; ++p) {
-        double fi = (xs[p] - x0) / h, fj = (ys[p] - y0) / h;
-        int64_t i = (int64_t)std::llround(fi), j = (int64_t)std::llround(fj);
+        const double fi = (pts[2 * p] - x0) * ih, fj = (pts[2 * p + 1] - y0) * ih;
+        const int64_t i = (int64_t)std::floor(fi + 0.5), j = (int64_t)std::floor(fj + 0.5);
         if (std::fabs(fi - i) > 1e-6 || std::fabs(fj - j) > 1e-6 || i < 0 || j < 0 || i >= nx || j >= ny) {
             why = "point off the uniform grid";
             return false;

@@ -93,6 +93,13 @@ EXPORTS = {
     "rsd_gj_invert": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32]),
     "rsd_last_error": (C.c_char_p, []),
     "rsd_profile_enable": (C.c_int, [C.c_int32]),
+    "rsd_profile_enable_mask": (C.c_int, [C.c_uint32]),
+    "rsd_profile_record_count": (C.c_int, [C.POINTER(C.c_int64)]),
+    "rsd_profile_record": (C.c_int, [C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "rsd_pool_trim": (C.c_int, [C.c_int32]),
+    "rsd_pool_set_limit": (C.c_int, [C.c_int64]),
+    "rsd_pool_cached_bytes": (C.c_int, [C.c_int32, C.POINTER(C.c_int64)]),
     "rsd_profile_query": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rsd_factor_get_stats": (C.c_int, [C.c_void_p, C.POINTER(rsd_factor_stats)]),
@@ -399,8 +406,47 @@ PROF_CLASSES = ["factor_gemm_f64", "factor_gemm_f32", "interp", "gj_pivot", "ass
                 "solve_gemm", "solve_move", "matvec"]
 
 
-def profile_enable(on=True):
-    _check(load().rsd_profile_enable(1 if on else 0))
+def pool_trim(device=-1):
+    """Hand the cached device blocks back to HIP (device < 0: every device)."""
+    _check(load().rsd_pool_trim(device))
+
+
+def pool_set_limit(nbytes):
+    """Per-device limit of cached bytes (< 0: the default)."""
+    _check(load().rsd_pool_set_limit(int(nbytes)))
+
+
+def pool_cached_bytes(device=-1):
+    out = C.c_int64()
+    _check(load().rsd_pool_cached_bytes(device, C.byref(out)))
+    return out.value
+
+
+def profile_enable(on=True, classes=None):
+    """Start (clearing earlier records) or stop the profiler; `classes` limits
+    the bracketed launches to those class names."""
+    if classes is None:
+        _check(load().rsd_profile_enable(1 if on else 0))
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << PROF_CLASSES.index(c)
+        _check(load().rsd_profile_enable_mask(mask if on else 0))
+
+
+def profile_records():
+    """Every recorded launch since the last enable, in enqueue order:
+    list of dict(cls, ms, flops, bytes, groups)."""
+    lib = load()
+    n = C.c_int64()
+    _check(lib.rsd_profile_record_count(C.byref(n)))
+    out = []
+    for i in range(n.value):
+        c, ms, fl, by, g = C.c_int32(), C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        _check(lib.rsd_profile_record(i, C.byref(c), C.byref(ms), C.byref(fl), C.byref(by), C.byref(g)))
+        out.append(dict(cls=PROF_CLASSES[c.value], ms=ms.value, flops=fl.value, bytes=by.value,
+                        groups=g.value))
+    return out
 
 
 def profile_query():

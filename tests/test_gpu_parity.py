@@ -26,7 +26,12 @@ def _need_gpu():
 @pytest.mark.parametrize("dt,tol", [(np.float64, 1e-13), (np.float32, 2e-5)])
 @pytest.mark.parametrize("M,N,K,tA,tB", [(64, 64, 16, 0, 0), (1, 1, 1, 0, 0), (77, 130, 45, 0, 0),
                                          (150, 33, 70, 1, 0), (65, 97, 129, 0, 1), (40, 50, 60, 1, 1),
-                                         (300, 17, 3, 0, 0)])
+                                         (300, 17, 3, 0, 0),
+                                         # 128-wide tiles (2048 x 2048), ragged edges
+                                         (2048, 2048, 64, 0, 0), (2050, 2047, 37, 1, 1),
+                                         # split K: two splits, sixteen splits, one tile of sixteen
+                                         (1024, 1024, 1024, 0, 1), (130, 70, 3000, 1, 0),
+                                         (16, 16, 5000, 0, 0)])
 def test_gemm_matches_numpy(dt, tol, M, N, K, tA, tB):
     rng = np.random.default_rng(M * 1000 + N)
     A = rng.standard_normal((K, M) if tA else (M, K)).astype(dt)
@@ -35,6 +40,16 @@ def test_gemm_matches_numpy(dt, tol, M, N, K, tA, tB):
     C = rsd.gemm(A, B, C0, alpha=-0.5, beta=2.0, tA=bool(tA), tB=bool(tB))
     ref = -0.5 * ((A.T if tA else A).astype(np.float64) @ (B.T if tB else B).astype(np.float64)) + 2.0 * C0
     assert np.abs(C - ref).max() <= tol * (np.abs(ref).max() + 1) * max(1, K) ** 0.5
+
+
+def test_split_k_gemm_is_repeatable():
+    # the partial tiles are summed in split order whichever work-group is last
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((90, 4000))
+    B = rng.standard_normal((4000, 70))
+    C1 = rsd.gemm(A, B)
+    for _ in range(3):
+        assert np.array_equal(rsd.gemm(A, B), C1)
 
 
 @pytest.mark.parametrize("n", [1, 5, 32, 33, 100, 257])
@@ -148,6 +163,36 @@ def test_repeat_solves_are_bitwise_identical():
     fac2 = rsd.Factor(pts, None, 1e-10)
     x3, _ = fac2.solve(f)
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+
+
+def test_cached_device_blocks_are_reused_safely():
+    # a freed factor's blocks go to the per-device cache and back to the next
+    # build; results stay bitwise equal, concurrent factors keep distinct
+    # memory, and trimming empties the cache
+    pts = W.grid_points(64, 40)
+    a = W.coef_sine(pts)
+    f = W.rhs_normal(len(pts), 2, 12)
+    fac = rsd.Factor(pts, a, 1e-10)
+    x1, _ = fac.solve(f)
+    fac.close()
+    assert rsd.pool_cached_bytes() > 0
+    held = rsd.Factor(pts, a, 1e-10)          # takes the cached blocks
+    other = rsd.Factor(W.grid_points(48), None, 1e-10)
+    x2, _ = held.solve(f)
+    x3, _ = other.solve(W.rhs_normal(48 * 48, 1, 2))
+    assert np.array_equal(x1, x2)
+    assert dense.rel_error(x3, dense.solve(W.grid_points(48), W.rhs_normal(48 * 48, 1, 2))) < 1e-10
+    held.close()
+    other.close()
+    rsd.pool_set_limit(0)                     # nothing may stay cached
+    assert rsd.pool_cached_bytes() == 0
+    rsd.pool_set_limit(-1)
+    fac = rsd.Factor(pts, a, 1e-10)
+    x4, _ = fac.solve(f)
+    fac.close()
+    assert np.array_equal(x1, x4)
+    rsd.pool_trim()
+    assert rsd.pool_cached_bytes() == 0
 
 
 def test_matvec_matches_reference():

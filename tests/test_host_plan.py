@@ -53,6 +53,28 @@ def test_detect_grid_rejects_non_grids():
     nan[3, 1] = np.nan
     with pytest.raises(rsd.RsdError):
         rsd.detect_grid(nan)
+    # uneven columns with a matching point count: x in {0, 1, 3, 4}
+    uneven = np.array([[x, y] for x in (0.0, 1.0, 3.0, 4.0) for y in range(4)], dtype=float)
+    with pytest.raises(rsd.RsdError):
+        rsd.detect_grid(uneven)
+    # one point moved half a spacing off its line
+    half = pts.copy()
+    half[20, 1] += 0.5 / 8
+    with pytest.raises(rsd.RsdError):
+        rsd.detect_grid(half)
+    with pytest.raises(rsd.RsdError):
+        rsd.detect_grid(pts[:1])
+
+
+def test_detect_grid_offset_and_line_grids():
+    # origin anywhere, spacing from the point set; single rows and columns
+    pts = W.grid_points(12, 9) * 3.0 - np.array([7.5, -2.25])
+    gx, gy, h, pm = rsd.detect_grid(pts[::-1].copy())
+    assert (gx, gy) == (12, 9) and h == pytest.approx(3.0 / 12)
+    assert np.array_equal(pts[::-1][pm], pts)
+    line = np.array([[0.25, 0.5 + 0.125 * j] for j in range(7)])
+    gx, gy, h, pm = rsd.detect_grid(line[::-1].copy())
+    assert (gx, gy) == (1, 7) and h == pytest.approx(0.125)
 
 
 @pytest.mark.parametrize("nx,ny,leaf,m", [(64, 64, 8, 2), (40, 24, 8, 2), (37, 37, 8, 2),
