@@ -263,7 +263,7 @@ def main():
         rec = profsum.read_traffic(os.path.join(ROOT, "profiles", "gemm_kernel_laplace256_traffic.md"))
         if rec is not None and rec[1] == profsum.gemm_source_digest():
             traffic = rec[0]
-    roof = {"bound": "mfma", "kernel": "gemm_kernel<" + ("double" if dt == "f64" else "float") + ", 0>",
+    roof = {"bound": "mfma", "kernel": "gemm_kernel<" + ("double" if dt == "f64" else "float") + ", 0, *>",
             "class": gemm_cls, "achieved": achieved / 1e12, "peak": PEAK[dt] / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK[dt], "traffic": traffic,
             "launches_per_step": g["launches"] // args.steps,

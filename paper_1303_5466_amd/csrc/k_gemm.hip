@@ -62,6 +62,17 @@ struct Cfg {
     static constexpr int LD = TILE + 16;          // LDS row stride: rows 128 B apart mod 256 B
     static constexpr int NB = TILE / 32;          // 16 x 16 blocks per wave and dimension
     static constexpr int LOADS = TILE * BK / 256; // elements per thread per operand panel
+    // Panels are [k][i] in LDS with the low four bits of i XORed by swz(k).
+    // Banks hold W words of T per row of the bank array and a panel row
+    // starts 16 words further along it, so R consecutive k-rows fill it; the
+    // swizzle moves each group of R rows to its own block of W / BK columns.
+    // A store whose lanes run along k (BK consecutive k, W / BK columns per
+    // group of BK lanes) then touches every bank once, and the MFMA operand
+    // reads (R rows x 16 consecutive columns per pass) stay conflict-free:
+    // the XOR permutes columns inside their 16-column block.
+    static constexpr int W = sizeof(T) == 8 ? 32 : 64;
+    static constexpr int R = W / 16;
+    __device__ static constexpr int swz(int k) { return (k / R) * (W / BK); }
 };
 
 // Loads go through buffer instructions: an element outside the product
@@ -90,22 +101,27 @@ template <> struct BufLoad<float> {
 // and BK, a thread's elements of a panel share one row (or one k) and step
 // through the other index with a constant stride: element q of the thread
 // sits q * qs elements after the first (plus ps per panel), is valid while
-// r0 + q * rq < rmax and k0 + q * kq < K, and goes to LDS word l0 + q * lq.
-template <typename T>
+// r0 + q * rq < rmax and k0 + q * kq < K, and goes to LDS word l[q].
+template <typename T, int LOADS>
 struct PanelPlan {
     __amdgpu_buffer_rsrc_t rs;
     int off0, qs, ps;
-    int r0, rq, rmax, k0, kq, l0, lq;
+    int r0, rq, rmax, k0, kq;
+    int l[LOADS];
 };
 
 // op(X) is rows x K (A: rows = M) or K x cols (B): `along_rows` says whether
 // memory is contiguous along the tile's row/column index (A without
 // transpose, B with transpose) or along k.
 template <typename T, int TILE>
-__device__ inline PanelPlan<T> panel_plan(const T* X, int ld, bool along_rows, int base, int lim) {
-    constexpr int BK = Cfg<T, TILE>::BK, LD = Cfg<T, TILE>::LD;
+using PlanOf = PanelPlan<T, Cfg<T, TILE>::LOADS>;
+
+template <typename T, int TILE>
+__device__ inline PlanOf<T, TILE> panel_plan(const T* X, int ld, bool along_rows, int base, int lim) {
+    typedef Cfg<T, TILE> C_;
+    constexpr int BK = C_::BK, LD = C_::LD;
     const int t = threadIdx.x;
-    PanelPlan<T> P;
+    PlanOf<T, TILE> P;
     P.rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, RSRC_RANGE, RSRC_WORD3);
     if (along_rows) {   // element (i = t % TILE, kk = t / TILE + q 256 / TILE)
         const int i = t % TILE, kk = t / TILE;
@@ -114,7 +130,11 @@ __device__ inline PanelPlan<T> panel_plan(const T* X, int ld, bool along_rows, i
         P.ps = BK * ld;
         P.r0 = base + i; P.rq = 0; P.rmax = lim;
         P.k0 = kk; P.kq = 256 / TILE;
-        P.l0 = kk * LD + i; P.lq = (256 / TILE) * LD;
+#pragma unroll
+        for (int q = 0; q < C_::LOADS; ++q) {
+            const int k = kk + q * (256 / TILE);
+            P.l[q] = k * LD + (i ^ C_::swz(k));
+        }
     } else {            // element (kk = t % BK, i = t / BK + q 256 / BK)
         const int kk = t % BK, i = t / BK;
         P.off0 = kk + (base + i) * ld;
@@ -122,13 +142,14 @@ __device__ inline PanelPlan<T> panel_plan(const T* X, int ld, bool along_rows, i
         P.ps = BK;
         P.r0 = base + i; P.rq = 256 / BK; P.rmax = lim;
         P.k0 = kk; P.kq = 0;
-        P.l0 = kk * LD + i; P.lq = 256 / BK;
+#pragma unroll
+        for (int q = 0; q < C_::LOADS; ++q) P.l[q] = kk * LD + ((i + q * (256 / BK)) ^ C_::swz(kk));
     }
     return P;
 }
 
 template <typename T, int TILE>
-__device__ inline void load_panel(const PanelPlan<T>& P, int K, int panel, T (&r)[Cfg<T, TILE>::LOADS]) {
+__device__ inline void load_panel(const PlanOf<T, TILE>& P, int K, int panel, T (&r)[Cfg<T, TILE>::LOADS]) {
     constexpr int BK = Cfg<T, TILE>::BK;
     const int kb = panel * BK;
     const int o = P.off0 + panel * P.ps;
@@ -140,9 +161,9 @@ __device__ inline void load_panel(const PanelPlan<T>& P, int K, int panel, T (&r
 }
 
 template <typename T, int TILE>
-__device__ inline void store_panel(const PanelPlan<T>& P, T* S, const T (&r)[Cfg<T, TILE>::LOADS]) {
+__device__ inline void store_panel(const PlanOf<T, TILE>& P, T* S, const T (&r)[Cfg<T, TILE>::LOADS]) {
 #pragma unroll
-    for (int q = 0; q < Cfg<T, TILE>::LOADS; ++q) S[P.l0 + q * P.lq] = r[q];
+    for (int q = 0; q < Cfg<T, TILE>::LOADS; ++q) S[P.l[q]] = r[q];
 }
 
 // Panels p0 .. p1 - 1 of one K segment, accumulated into acc.
@@ -156,8 +177,15 @@ __device__ inline void run_segment(const T* A, int lda, int tA, const T* B, int 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int wr = (wave >> 1) * (TILE / 2), wc = (wave & 1) * (TILE / 2);
-    const PanelPlan<T> pa = panel_plan<T, TILE>(A, lda, !tA, row0, M);
-    const PanelPlan<T> pb = panel_plan<T, TILE>(B, ldb, tB, col0, N);
+    const PlanOf<T, TILE> pa = panel_plan<T, TILE>(A, lda, !tA, row0, M);
+    const PlanOf<T, TILE> pb = panel_plan<T, TILE>(B, ldb, tB, col0, N);
+    // lane part of the MFMA operand reads for each 4-deep k step
+    int lo[BK / 4];
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        lo[kk / 4] = kr * LD + ((lane & 15) ^ C_::swz(kr));
+    }
     T ra[C_::LOADS], rb[C_::LOADS];
     load_panel<T, TILE>(pa, K, p0, ra);
     load_panel<T, TILE>(pb, K, p0, rb);
@@ -177,12 +205,11 @@ __device__ inline void run_segment(const T* A, int lda, int tA, const T* B, int 
         const T* Bs = As + PANEL;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            const int kr = kk + (lane >> 4);
             T a[NB], b[NB];
 #pragma unroll
-            for (int i = 0; i < NB; ++i) a[i] = As[kr * LD + wr + 16 * i + (lane & 15)];
+            for (int i = 0; i < NB; ++i) a[i] = As[lo[kk / 4] + wr + 16 * i];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) b[j] = Bs[kr * LD + wc + 16 * j + (lane & 15)];
+            for (int j = 0; j < NB; ++j) b[j] = Bs[lo[kk / 4] + wc + 16 * j];
 #pragma unroll
             for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -233,18 +260,24 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
     const T* part = ws + (int64_t)tr.pbase * (PER * 256);
 
     if (reduce) {
+        // split by split (all of a split's loads in flight at once), in order
+        T sum[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) sum[e] = T(0);
+        for (int sp = 0; sp < tr.nsplit; ++sp) {
+            const T* ps = part + (int64_t)sp * (PER * 256) + t;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) sum[e] += ps[e * 256];
+        }
 #pragma unroll
         for (int i = 0; i < NB; ++i)
 #pragma unroll
             for (int j = 0; j < NB; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int e = ((i * NB + j) * 4 + v) * 256 + t;
-                    T sum = T(0);
-                    for (int sp = 0; sp < tr.nsplit; ++sp) sum += part[(int64_t)sp * (PER * 256) + e];
                     int r, c;
                     tile_coords<T, TILE>(t, i, j, v, r, c);
-                    store_c<T, TILE>(d, row0 + r, col0 + c, sum);
+                    store_c<T, TILE>(d, row0 + r, col0 + c, sum[(i * NB + j) * 4 + v]);
                 }
         return;
     }

@@ -11,8 +11,9 @@
 
 A factor build starts at its leaf_F_kernel dispatch.  The factor's level
 GEMMs (Schur products, Gauss-Jordan updates, E blocks, root) are the
-gemm_kernel instantiation with role 0; interpolation, solve and library
-GEMMs are roles 1, 2 and 3 of the same code.
+gemm_kernel instantiations with role 0 (either tile width, product and
+split-K reduce dispatches alike); interpolation, solve and library GEMMs are
+roles 1, 2 and 3 of the same code.
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-GEMM = "gemm_kernel<double, 0>"
+GEMM = "gemm_kernel<double, 0"      # name prefix: gemm_kernel<double, 0, 64> and <double, 0, 128>
 
 
 def _short(name: str) -> str:
@@ -55,7 +56,7 @@ def _dispatches(rows):
 def level_gemm_ids(disp, gemm: str = GEMM):
     """Dispatch ids of the factor's level GEMM launches, and the number of builds."""
     starts = [d["start"] for d in disp if d["name"].startswith("leaf_F_kernel")]
-    return {d["dispatch"] for d in disp if d["name"] == gemm}, len(starts)
+    return {d["dispatch"] for d in disp if d["name"].startswith(gemm + ",")}, len(starts)
 
 
 def trace_summary(d: str, title: str, command: str, gemm: str = GEMM) -> str:
@@ -74,7 +75,7 @@ def trace_summary(d: str, title: str, command: str, gemm: str = GEMM) -> str:
     for k, (n, us) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
         out.append(f"| `{k}` | {n / nb:.0f} | {us / 1e3 / nb:.3f} | {us / n:.1f} |")
     if lv:
-        out += ["", f"Level GEMM launches (`{gemm}`: the factor's Schur, Gauss-Jordan, E and root products):",
+        out += ["", f"Level GEMM dispatches (`{gemm}, *>`: the factor's Schur, Gauss-Jordan, E and root products):",
                 "", f"- launches: {len(lv)} ({len(lv) / nb:.0f} per build)",
                 f"- average duration: {sum(lv) / len(lv):.2f} us",
                 f"- total per build: {sum(lv) / 1e3 / nb:.3f} ms"]
@@ -148,7 +149,7 @@ def main(argv=None):
     t.add_argument("dir")
     t.add_argument("--title", default="Kernel statistics")
     t.add_argument("--command", default="")
-    t.add_argument("--gemm", default=GEMM, help="kernel name of the level GEMM to summarise")
+    t.add_argument("--gemm", default=GEMM, help="kernel name prefix of the level GEMM to summarise")
     f = sub.add_parser("traffic")
     f.add_argument("--fetch", required=True)
     f.add_argument("--write", required=True)
