@@ -348,6 +348,7 @@ struct GemmBatch {
         for (auto& d : descs) {
             int64_t e = std::max(extent(d.M, d.K, d.lda, d.tA), extent(d.K, d.N, d.ldb, d.tB));
             if (d.K2 > 0) e = std::max({e, extent(d.M, d.K2, d.lda2, d.tA2), extent(d.K2, d.N, d.ldb2, d.tB2)});
+            e = std::max(e, extent(d.M, d.N, d.ldc, 0));
             if (e + 16 > (int64_t)GEMM_MAX_OPERAND_BYTES)
                 throw Error(RSD_EINVAL, "matrix block too large for the GEMM kernel (2 GiB operand limit)");
         }

@@ -293,6 +293,32 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
 
+    // 64-wide unsplit tiles with beta != 0 load their C tile before the K loop
+    // (masked buffer loads: zero outside C or in the beta-zero columns), so
+    // that short products do not wait for it afterwards
+    constexpr bool PREFETCH = TILE == 64;
+    T cpre[PREFETCH ? PER : 1];
+    const bool use_pre = PREFETCH && tr.nsplit == 1 && d.beta != T(0);
+    if constexpr (PREFETCH) {
+        if (use_pre) {
+            const __amdgpu_buffer_rsrc_t rc =
+                __builtin_amdgcn_make_buffer_rsrc((void*)d.C, (short)0, RSRC_RANGE, RSRC_WORD3);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int r, c;
+                        tile_coords<T, TILE>(t, i, j, v, r, c);
+                        const int gi = row0 + r, gj = col0 + c;
+                        const bool ok = (gi < d.M) & (gj < d.N) & !((gj >= d.zc0) & (gj < d.zc1));
+                        cpre[(i * NB + j) * 4 + v] =
+                            BufLoad<T>::at(rc, ok ? (gi + gj * d.ldc) * (int)sizeof(T) : OFF_MASKED);
+                    }
+        }
+    }
+
     // panels [st0, st1) of the concatenated K range: first segment, then second
     run_segment<T, TILE>(d.A, d.lda, d.tA, d.B, d.ldb, d.tB, d.M, d.N, d.K, row0, col0, min(st0, n1),
                          min(st1, n1), lds, acc);
@@ -308,6 +334,24 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
 #pragma unroll
                 for (int v = 0; v < 4; ++v) mine[((i * NB + j) * 4 + v) * 256 + t] = acc[i][j][v];
         return;
+    }
+    if constexpr (PREFETCH) {
+        if (use_pre) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int r, c;
+                        tile_coords<T, TILE>(t, i, j, v, r, c);
+                        const int gi = row0 + r, gj = col0 + c;
+                        if ((gi < d.M) & (gj < d.N))
+                            d.C[gi + (int64_t)gj * d.ldc] =
+                                d.alpha * acc[i][j][v] + d.beta * cpre[(i * NB + j) * 4 + v];
+                    }
+            return;
+        }
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i)

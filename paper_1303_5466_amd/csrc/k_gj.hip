@@ -24,6 +24,19 @@ namespace {
 constexpr int GJ_NB = 64;
 constexpr int CHUNK = 64;
 
+// 1 / x from the hardware reciprocal estimate and two Newton steps (each
+// squares the relative error), shorter than an IEEE division on the
+// elimination's critical path; x is a checked, normal pivot.
+__device__ inline double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+__device__ inline float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+
 // Inversion of the pivot block: thread t keeps the 4 x 4 tile (rows 4(t/16),
 // columns 4(t%16)) of P in registers; step c needs only pivot row c and pivot
 // column c, which their owners publish in a double-buffered LDS strip, so each
@@ -69,11 +82,12 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
 #pragma unroll
         for (int a = 0; a < 4; ++a) colb[0][ri + a] = p[a][0];
     __syncthreads();
-    // All 64 steps run (past nbe the block is the identity, which they leave
-    // unchanged); unrolled by four so that the pivot's position inside a
-    // thread's 4 x 4 tile is a compile-time index and only the ownership test
-    // is dynamic.
-    for (int c4 = 0; c4 < GJ_NB; c4 += 4) {
+    // Steps up to nbe rounded up to four run (past nbe the block is the
+    // identity, which they leave unchanged); unrolled by four so that the
+    // pivot's position inside a thread's 4 x 4 tile is a compile-time index
+    // and only the ownership test is dynamic.
+    const int nst = (nbe + 3) & ~3;
+    for (int c4 = 0; c4 < nst; c4 += 4) {
         const bool own_r = ri == c4, own_c = cj == c4;
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
@@ -81,7 +95,7 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
             const int buf = c & 1;
             const T piv = rowb[buf][c];
             if (t == 0 && !(fabs((double)piv) > 1e-300 && isfinite((double)piv))) bad = 1;
-            const T inv = T(1) / piv;
+            const T inv = recip(piv);
             T prs[4], pcv[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) prs[b] = rowb[buf][cj + b] * inv;
