@@ -29,10 +29,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-# per-source code generation options: the GEMM keeps its MFMA accumulators in
+# per-source code generation options: the MFMA kernels keep their accumulators in
 # ordinary vector registers (with accumulation registers the compiler copies
 # them between the two register files on every K panel)
-EXTRA = {"k_gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+EXTRA = {"k_gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"], "k_gj.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:

@@ -455,6 +455,14 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
 
 constexpr int GJ_NB = 64;   // Gauss-Jordan panel width (matches k_gj)
 
+// The Gauss-Jordan kernel addresses its block with 32-bit byte offsets.
+template <typename T>
+static void check_gj_block(const GJDesc<T>& g) {
+    const int64_t bytes = (int64_t)sizeof(T) * ((int64_t)(g.n - 1) + (int64_t)(g.ncols - 1) * g.ld + 1);
+    if (bytes + 16 > (int64_t)GEMM_MAX_OPERAND_BYTES)
+        throw Error(RSD_EINVAL, "matrix block too large for the Gauss-Jordan kernel (2 GiB limit)");
+}
+
 // ----------------------------------------------------------------------------
 // per-level execution plan (one precision per level)
 // ----------------------------------------------------------------------------
@@ -941,6 +949,7 @@ static void plan_level(Factor& f, LevelExec<T>& L, int t, std::vector<GemmBatch<
         if (r > 0) {
             GJDesc<T> g;
             g.X = Frs; g.ld = m; g.n = r; g.ncols = m; g.pcol = k;
+            check_gj_block(g);
             g.SR = nullptr; g.SC = nullptr; g.box = id;
             L.gj.push_back(g);
             sr += (int64_t)GJ_NB * m;
@@ -999,6 +1008,7 @@ static void plan_top(Factor& f, LevelExec<T>& L, T* SRb, T* SCb, std::vector<Gem
     T* Fss = Fbase<T>(f) + b.offF;
     GJDesc<T> g;
     g.X = Fss; g.ld = m; g.n = k; g.ncols = k; g.pcol = 0; g.SR = SRb; g.SC = SCb; g.box = f.plan.root;
+    check_gj_block(g);
     L.topgj.push_back(g);
     L.topgj_steps = (k + GJ_NB - 1) / GJ_NB;
     L.top_chunks = (k + 63) / 64;
@@ -1743,6 +1753,7 @@ static void dense_gj(int n, void* A, int lda) {
     RSD_HIP(hipMemset(err.p, 0, 4 * sizeof(int)));
     GJDesc<T> g;
     g.X = pA; g.ld = lda; g.n = n; g.ncols = n; g.pcol = 0; g.SR = sr.as<T>(); g.SC = sc.as<T>(); g.box = 0;
+    check_gj_block(g);
     dg.alloc(sizeof(g));
     RSD_HIP(hipMemcpy(dg.p, &g, sizeof(g), hipMemcpyHostToDevice));
     const int steps = (n + GJ_NB - 1) / GJ_NB;

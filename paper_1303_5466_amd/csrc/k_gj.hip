@@ -24,6 +24,41 @@ namespace {
 constexpr int GJ_NB = 64;
 constexpr int CHUNK = 64;
 
+// Buffer loads from the matrix with 32-bit byte offsets (the host keeps the
+// matrix below GJ_RSRC_RANGE bytes); the offset GJ_RSRC_RANGE itself is out
+// of range and reads zero.
+constexpr int GJ_RSRC_RANGE = 0x7ffffff0;
+constexpr int GJ_RSRC_WORD3 = 0x00020000;    // raw buffer, 32-bit data format
+
+template <typename T> __device__ inline T gj_load(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ inline double gj_load<double>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ inline float gj_load<float>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// MFMA 16x16x4 called with its operands swapped, step(b, a, acc): element
+// v of lane l is then C[l % 16][col(l, v)] of the product C = A B, where
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+typedef float gj_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct GjMfma;
+template <> struct GjMfma<double> {
+    typedef gj_d4 acc_t;
+    __device__ static inline int col(int lane, int v) { return (lane >> 4) + 4 * v; }
+    __device__ static inline acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct GjMfma<float> {
+    typedef gj_f4 acc_t;
+    __device__ static inline int col(int lane, int v) { return 4 * (lane >> 4) + v; }
+    __device__ static inline acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
 // 1 / x from the hardware reciprocal estimate and two Newton steps (each
 // squares the relative error), shorter than an IEEE division on the
 // elimination's critical path; x is a checked, normal pivot.
@@ -59,19 +94,39 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
     __shared__ __align__(16) T colb[2][GJ_NB];
     __shared__ int bad;
     const int pc0 = d.pcol + j0;
+    // every load of the pivot block and of the chunk's pivot rows is issued
+    // before the first is used: buffer loads, masked by an out-of-range offset
+    // (which reads zero), so that no branch separates them
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc((void*)d.X, (short)0, GJ_RSRC_RANGE, GJ_RSRC_WORD3);
     T p[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int i = ri + a, j = cj + b;
-            p[a][b] = (i < nbe && j < nbe) ? d.X[(j0 + i) + (int64_t)(pc0 + j) * d.ld]
-                                           : (i == j ? T(1) : T(0));
+            const bool ok = (i < nbe) & (j < nbe);
+            p[a][b] = gj_load<T>(rx, ok ? ((j0 + i) + (pc0 + j) * d.ld) * (int)sizeof(T) : GJ_RSRC_RANGE);
         }
-    for (int e = t; e < GJ_NB * CHUNK; e += 256) {
-        const int q = e & (GJ_NB - 1), cc = e / GJ_NB;
-        const int c = c_lo + cc;
-        Xp[q][cc] = (q < nbe && c < d.ncols) ? d.X[(j0 + q) + (int64_t)c * d.ld] : T(0);
+    T xv[GJ_NB * CHUNK / 256];
+#pragma unroll
+    for (int u = 0; u < GJ_NB * CHUNK / 256; ++u) {
+        const int e = t + 256 * u;
+        const int q = e & (GJ_NB - 1), c = c_lo + e / GJ_NB;
+        const bool ok = (q < nbe) & (c < d.ncols);
+        xv[u] = gj_load<T>(rx, ok ? ((j0 + q) + c * d.ld) * (int)sizeof(T) : GJ_RSRC_RANGE);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ri + a, j = cj + b;
+            if (!((i < nbe) & (j < nbe))) p[a][b] = i == j ? T(1) : T(0);
+        }
+#pragma unroll
+    for (int u = 0; u < GJ_NB * CHUNK / 256; ++u) {
+        const int e = t + 256 * u;
+        Xp[e & (GJ_NB - 1)][e / GJ_NB] = xv[u];
     }
     if (t == 0) bad = 0;
     // publish row 0 and column 0
@@ -133,39 +188,45 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         for (int b = 0; b < 4; ++b) Pi[ri + a][cj + b] = p[a][b];
     __syncthreads();
     if (t == 0 && bad && blockIdx.x == 0) atomicCAS(err, 0, d.box + 1);
-    // SR = P^{-1} X[piv rows, chunk]: 4 x 4 output tile per thread
+    // SR = P^{-1} X[piv rows, chunk] on the matrix cores: wave w owns the
+    // 32 x 32 block (rows 32 (w / 2), columns 32 (w % 2)) as 2 x 2 MFMA blocks
+    // over K = 64.  The MFMA computes the transposed block, so lane l holds
+    // rows q0 + l % 16 of SR (contiguous in memory) and the stores coalesce.
+    // Entries past nbe are zero in X and identity in P, so K runs to 64.
     {
-        T acc[4][4];
+        const int lane = t & 63, wave = t >> 6;
+        typename GjMfma<T>::acc_t acc[2][2];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-        // entries past nbe are zero in both operands, so the loop runs to 64
-#pragma unroll 8
-        for (int s2 = 0; s2 < GJ_NB; ++s2) {
-            T pa[4], xb[4];
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = typename GjMfma<T>::acc_t{0, 0, 0, 0};
+        const int qw = 32 * (wave >> 1), cw = 32 * (wave & 1);
+#pragma unroll 4
+        for (int kk = 0; kk < GJ_NB; kk += 4) {
+            const int k = kk + (lane >> 4);
+            T a[2], b[2];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) pa[a] = Pi[ri + a][s2];
+            for (int bi = 0; bi < 2; ++bi) a[bi] = Pi[qw + 16 * bi + (lane & 15)][k];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) xb[b] = Xp[s2][cj + b];
+            for (int bj = 0; bj < 2; ++bj) b[bj] = Xp[k][cw + 16 * bj + (lane & 15)];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += pa[a] * xb[b];
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = GjMfma<T>::step(b[bj], a[bi], acc[bi][bj]);
         }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int c = c_lo + cj + b;
-            if (c >= d.ncols) continue;
-            const bool pivc = c >= pc0 && c < pc0 + nbe;
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int q = ri + a;
-                if (q >= nbe) continue;
-                d.SR[q + (int64_t)c * nb] = pivc ? Pi[q][c - pc0] : acc[a][b];
-                if (!pivc) d.X[(j0 + q) + (int64_t)c * d.ld] = T(0);
-            }
-        }
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = qw + 16 * bi + (lane & 15);
+                    const int c = c_lo + cw + 16 * bj + GjMfma<T>::col(lane, v);
+                    if (q >= nbe || c >= d.ncols) continue;
+                    const bool pivc = c >= pc0 && c < pc0 + nbe;
+                    d.SR[q + (int64_t)c * nb] = pivc ? Pi[q][c - pc0] : acc[bi][bj][v];
+                    if (!pivc) d.X[(j0 + q) + (int64_t)c * d.ld] = T(0);
+                }
     }
     // SC = old pivot columns with -I in the pivot rows; rows split over the
     // workgroups of this box (nobody writes those columns in this kernel).
