@@ -29,6 +29,8 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <condition_variable>
 #include <type_traits>
 #include <vector>
 
@@ -857,12 +859,12 @@ struct QRChain {
         launch_qr_init<T>(Ab, daux->as<T>(), diaux->as<int>(), dq->as<QRProblemDev>(), np, max_k, s);
     }
 
-    // Enqueues window sw; returns the levels whose problems all finished
-    // (their back substitutions are enqueued on the solve stream, followed
-    // by an event recorded into level_waits).
-    void window(int sw, std::vector<int>& level_pending,
-                std::vector<std::vector<hipEvent_t>>& level_waits) {
-        if (sw >= S) return;
+    // Enqueues window sw.  For the problems that finish in it, the back
+    // substitutions follow on the chain's stream, then an event: returned,
+    // with the level of every finished (sector) problem appended to `done`
+    // (nullptr and nothing appended when no problem finishes).
+    hipEvent_t window(int sw, std::vector<int>& done) {
+        if (sw >= S) return nullptr;
         T* Ab = dA->as<T>();
         T* W = dws->as<T>();
         T* aux = daux->as<T>();
@@ -886,10 +888,9 @@ struct QRChain {
         g2[sw].run(s);
         launch_qr_norms<T>(Ab, aux, iaux, q, np, sw, max_k, s);
         const int ng = soff[sw + 1] - soff[sw];
-        if (ng == 0) return;
+        if (ng == 0) return nullptr;
         // back substitution for the problems finished in this window, on the
-        // chain's stream (four streams in all keep one hardware queue each
-        // under HIP's default of four)
+        // chain's stream
         int gr = 0;
         for (int g = soff[sw]; g < soff[sw + 1]; ++g) gr = std::max(gr, qp[sflat[g]].r);
         for (int st = 0; st < (int)gsolve[sw].size(); ++st) {
@@ -906,12 +907,8 @@ struct QRChain {
         hipEvent_t solved;
         RSD_HIP(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
         RSD_HIP(hipEventRecord(solved, s));
-        f->tmp_events.push_back(solved);
-        for (int g = soff[sw]; g < soff[sw + 1]; ++g) {
-            const int lev = prob_level[sflat[g]];
-            if (level_waits[lev].empty() || level_waits[lev].back() != solved) level_waits[lev].push_back(solved);
-            --level_pending[lev];
-        }
+        for (int g = soff[sw]; g < soff[sw + 1]; ++g) done.push_back(prob_level[sflat[g]]);
+        return solved;
     }
 };
 
@@ -1322,9 +1319,18 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         for (auto q : f->qr_stream) RSD_HIP(hipStreamWaitEvent(q, go, 0));
         (void)hipEventDestroy(go);
     }
-    // chains: (precision, narrow sub-panels) -> problems; the narrow chain
-    // holds the boxes too tall for 16-column sub-panels
-    std::vector<int> cp[2][2], cl[2][2];
+    // chains: (precision, class) -> problems.  Class 0 holds the problems
+    // done after one window (the lower levels, needed first), class 1 the
+    // longer ones, class 2 the boxes too tall for 16-column sub-panels; every
+    // chain advances its problems window by window, so the short problems do
+    // not wait for the first windows of the large ones.  Classes 0 and 2
+    // share a stream (class 0 is done almost at once), class 1 has the other:
+    // with the level pipeline's stream that is three streams, one hardware
+    // queue each under HIP's default of four per process (one is taken by
+    // the default stream).
+    constexpr int NCH = 3;
+    auto chain_stream = [&](int c) { return f->qr_stream[c == 1 ? 1 : 0]; };
+    std::vector<int> cp[2][NCH], cl[2][NCH];
     std::vector<int> pending(nlev, 0);
     for (size_t li = 0; li < P.layouts.size(); ++li) {
         if (P.layouts[li].idp < 0) continue;
@@ -1335,48 +1341,110 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         const int ip = interp_prec(*f, lev);
         const IDProblem& I = P.idps[P.layouts[li].idp];
         const bool sym = split_sym(*f, I, ip);
-        const int narrow = qr_panel_width(sym ? I.p / 4 : I.p, ip ? 4 : 8) < 16 ? 1 : 0;
-        cp[ip][narrow].push_back(P.layouts[li].idp);
-        cl[ip][narrow].push_back(lev);
+        const bool narrow = qr_panel_width(sym ? I.p / 4 : I.p, ip ? 4 : 8) < 16;
+        const int cls = narrow ? 2 : ((sym ? I.k / 4 : I.k) <= QR_WIN ? 0 : 1);
+        cp[ip][cls].push_back(P.layouts[li].idp);
+        cl[ip][cls].push_back(lev);
         pending[lev] += sym ? 4 : 1;     // one per (sector) problem
     }
+    // Levels are enqueued as soon as the events of their box types exist, so
+    // the level pipeline runs alongside the interpolation problems.  The
+    // chains' windows are enqueued by a second host thread (its launches go to
+    // the chain streams only), so neither the windows nor the levels wait for
+    // the host to enqueue the other; pending counts and events are shared
+    // under a lock.
     std::vector<std::vector<hipEvent_t>> level_waits(nlev);
-    // levels are enqueued as soon as the events of their box types exist, so the
-    // level pipeline runs alongside the interpolation problems
-    int next_level = 0;
-    auto enqueue_ready = [&]() {
-        while (next_level < nlev && pending[next_level] == 0) {
-            const int t = next_level++;
-            for (auto e : level_waits[t]) RSD_HIP(hipStreamWaitEvent(s, e, 0));
-            if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
-            else run_level<double>(*f, f->L64[exec_index[t]], s);
+    std::mutex mu;
+    std::condition_variable cv;
+    bool chains_done = false;
+    auto publish = [&](hipEvent_t ev, const std::vector<int>& done) {
+        if (!ev) return;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            f->tmp_events.push_back(ev);
+            for (int lev : done) {
+                if (level_waits[lev].empty() || level_waits[lev].back() != ev) level_waits[lev].push_back(ev);
+                --pending[lev];
+            }
         }
+        cv.notify_all();
+    };
+    int next_level = 0;
+    // enqueues the next level once its problems are done (block: wait for it)
+    auto enqueue_next = [&](bool block) {
+        std::vector<hipEvent_t> waits;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            if (block) cv.wait(lk, [&] { return pending[next_level] == 0 || chains_done; });
+            if (pending[next_level] != 0) return false;
+            waits = level_waits[next_level];
+        }
+        const int t = next_level++;
+        for (auto e : waits) RSD_HIP(hipStreamWaitEvent(s, e, 0));
+        if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
+        else run_level<double>(*f, f->L64[exec_index[t]], s);
+        return true;
     };
     {
-        QRChain<double> c64[2];
-        QRChain<float> c32[2];
+        QRChain<double> c64[NCH];
+        QRChain<float> c32[NCH];
         int S = 0;
-        for (int nw = 0; nw < 2; ++nw) {
-            if (!cp[0][nw].empty()) { c64[nw].setup(*f, cp[0][nw], cl[0][nw], f->qr_stream[nw]); S = std::max(S, c64[nw].S); }
-            if (!cp[1][nw].empty()) { c32[nw].setup(*f, cp[1][nw], cl[1][nw], f->qr_stream[nw]); S = std::max(S, c32[nw].S); }
+        double fl = 0, by = 0;
+        for (int c = 0; c < NCH; ++c) {
+            if (!cp[0][c].empty()) { c64[c].setup(*f, cp[0][c], cl[0][c], chain_stream(c)); S = std::max(S, c64[c].S); }
+            if (!cp[1][c].empty()) { c32[c].setup(*f, cp[1][c], cl[1][c], chain_stream(c)); S = std::max(S, c32[c].S); }
+            fl += c64[c].flops + c32[c].flops;
+            by += c64[c].bytes + c32[c].bytes;
         }
-        ProfScope ps(RSD_PROF_INTERP, f->qr_stream[1], c64[0].flops + c64[1].flops + c32[0].flops + c32[1].flops,
-                     c64[0].bytes + c64[1].bytes + c32[0].bytes + c32[1].bytes);
-        for (int sw = 0; sw < S; ++sw) {
-            for (int nw = 0; nw < 2; ++nw) {
-                c32[nw].window(sw, pending, level_waits);
-                c64[nw].window(sw, pending, level_waits);
+        ProfScope ps(RSD_PROF_INTERP, f->qr_stream[1], fl, by);
+        // the one-window chain first, on this thread
+        {
+            std::vector<int> done;
+            publish(c32[0].window(0, done), done);
+            done.clear();
+            publish(c64[0].window(0, done), done);
+        }
+        std::exception_ptr chain_err;
+        const int dev = f->device;
+        std::thread chains([&] {
+            try {
+                RSD_HIP(hipSetDevice(dev));
+                for (int sw = 0; sw < S; ++sw)
+                    for (int c = 0; c < NCH; ++c) {
+                        if (c == 0 && sw == 0) continue;
+                        std::vector<int> done;
+                        publish(c32[c].window(sw, done), done);
+                        done.clear();
+                        publish(c64[c].window(sw, done), done);
+                    }
+            } catch (...) {
+                chain_err = std::current_exception();
             }
-            enqueue_ready();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                chains_done = true;
+            }
+            cv.notify_all();
+        });
+        std::exception_ptr level_err;
+        try {
+            while (next_level < nlev && enqueue_next(true)) {
+            }
+        } catch (...) {
+            level_err = std::current_exception();
         }
-        // the interpolation profile ends when both chains have
-        hipEvent_t both;
-        RSD_HIP(hipEventCreateWithFlags(&both, hipEventDisableTiming));
-        RSD_HIP(hipEventRecord(both, f->qr_stream[0]));
-        RSD_HIP(hipStreamWaitEvent(f->qr_stream[1], both, 0));
-        f->tmp_events.push_back(both);
+        chains.join();
+        if (chain_err) std::rethrow_exception(chain_err);
+        if (level_err) std::rethrow_exception(level_err);
+        // the interpolation profile ends when both streams have
+        hipEvent_t done;
+        RSD_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        RSD_HIP(hipEventRecord(done, f->qr_stream[0]));
+        RSD_HIP(hipStreamWaitEvent(f->qr_stream[1], done, 0));
+        f->tmp_events.push_back(done);
     }
-    enqueue_ready();
+    while (next_level < nlev && enqueue_next(false)) {
+    }
     if (next_level != nlev) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
     RSD_HIP(hipEventRecord(e1, s));
     f->build_ev[0] = e0;
