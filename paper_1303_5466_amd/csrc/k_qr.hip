@@ -301,7 +301,7 @@ template <> struct Log2<1> { static constexpr int v = 0; };
 template <typename T, int N, int RS>
 __device__ inline const T* block_sum_n(T (&v)[N], T* red /* [2][RS] */, int& parity) {
     constexpr int LN = Log2<N>::v;
-    static_assert((1 << LN) == N && LN <= 6 && N * (PT / 64) <= RS, "power of two up to 64");
+    static_assert((1 << LN) == N && LN <= 6 && N * (PT / 64 + 1) <= RS, "power of two up to 64");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int s = 0; s < LN; ++s) {
@@ -325,13 +325,18 @@ __device__ inline const T* block_sum_n(T (&v)[N], T* red /* [2][RS] */, int& par
     T* r = red + parity * RS;
     if ((lane & ((64 >> LN) - 1)) == 0) r[(lane >> (6 - LN)) * (PT / 64) + wave] = v[0];
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
+    // thread j < N adds the wave partials of value j (fixed order, so every
+    // thread gets the same bits), then every thread reads the N totals
+    T* tot = r + N * (PT / 64);
+    if (threadIdx.x < N) {
         T s2 = T(0);
 #pragma unroll
-        for (int w = 0; w < PT / 64; ++w) s2 += r[j * (PT / 64) + w];
-        v[j] = s2;
+        for (int w = 0; w < PT / 64; ++w) s2 += r[threadIdx.x * (PT / 64) + w];
+        tot[threadIdx.x] = s2;
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = tot[j];
     parity ^= 1;
     return r;   // the wave partials of value j at r[j * (PT / 64) + w]
 }
@@ -407,7 +412,7 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     const QRProblemDev q = probs[plist[blockIdx.x]];
     Aux<T> X(aux, iaux, ws, q);
     const int t = threadIdx.x;
-    __shared__ T red[2 * W * (PT / 64)];
+    __shared__ __align__(16) T red[2 * W * (PT / 64 + 1)];
     __shared__ T rowc[W];     // row c of the sub-panel, published by its owner
     __shared__ T Tfs[W][W + 1];
     __shared__ int lperm[W];
@@ -455,7 +460,7 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
     static_for<0, W>([&](auto C) {
         constexpr int c = decltype(C)::value;
         if (stop || c >= nbe) return;
-        block_sum_n<T, W, W * (PT / 64)>(nr, red, parity);
+        block_sum_n<T, W, W * (PT / 64 + 1)>(nr, red, parity);
         int pv = c;
         T pn = T(-1);
 #pragma unroll
@@ -493,7 +498,7 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
 #pragma unroll
             for (int j = 0; j < W; ++j) d[j] += vc * x[j];
         }
-        block_sum_n<T, W, W * (PT / 64)>(d, red, parity);
+        block_sum_n<T, W, W * (PT / 64 + 1)>(d, red, parity);
         // compact-WY factor column c: T[:c, c] = -tau T[:c, :c] (V[:, :c]^T v_c)
         if (t <= c && t < W) {
             T s2 = T(0);
