@@ -334,8 +334,8 @@ struct GemmBatch {
         bytes += sizeof(T) * ((double)d.M * kk + kk * d.N + 2.0 * d.M * d.N);
     }
     bool empty() const { return descs.empty(); }
-    // Tile table.  128-wide tiles when the products are large and give every
-    // compute unit two tiles; otherwise 64.  When even the 64-wide tiles
+    // Tile table.  128-wide tiles when the products are large, have K > 128
+    // and give every compute unit two tiles; otherwise 64.  When even the 64-wide tiles
     // cannot give every compute unit one, long K ranges are split (at least
     // eight panels per split, at most 16 splits) and summed by a second
     // dispatch.
@@ -359,14 +359,18 @@ struct GemmBatch {
         ws_elems = 0;
         int64_t t64 = 0, t128 = 0;
         double big = 0, tot = 0;
+        int kmax = 0;
         for (auto& d : descs) {
+            kmax = std::max(kmax, std::max(d.K, 0) + std::max(d.K2, 0));
             t64 += (int64_t)((d.M + 63) / 64) * ((d.N + 63) / 64);
             t128 += (int64_t)((d.M + 127) / 128) * ((d.N + 127) / 128);
             const double w = (double)d.M * d.N * (std::max(d.K, 0) + std::max(d.K2, 0));
             tot += w;
             if (d.M >= 128 && d.N >= 128) big += w;
         }
-        tile = (t128 >= 2 * CUS && big >= 0.8 * tot) ? 128 : 64;
+        // short-K launches (the Gauss-Jordan updates) are bound by their C
+        // traffic: the 64-wide tiles load C before the K loop
+        tile = (t128 >= 2 * CUS && big >= 0.8 * tot && kmax > 128) ? 128 : 64;
         const int64_t nt = tile == 128 ? t128 : t64;
         const int bk = (sizeof(T) == 8 && tile == 128) ? 8 : 16;
         for (int id = 0; id < (int)descs.size(); ++id) {

@@ -27,8 +27,10 @@ def _need_gpu():
 @pytest.mark.parametrize("M,N,K,tA,tB", [(64, 64, 16, 0, 0), (1, 1, 1, 0, 0), (77, 130, 45, 0, 0),
                                          (150, 33, 70, 1, 0), (65, 97, 129, 0, 1), (40, 50, 60, 1, 1),
                                          (300, 17, 3, 0, 0),
-                                         # 128-wide tiles (2048 x 2048), ragged edges
-                                         (2048, 2048, 64, 0, 0), (2050, 2047, 37, 1, 1),
+                                         # 128-wide tiles (2048 x 2048, K > 128), ragged edges
+                                         (2048, 2048, 200, 0, 0), (2050, 2047, 137, 1, 1),
+                                         # short K on 64-wide tiles with C loaded up front
+                                         (2048, 2048, 64, 0, 0),
                                          # split K: two splits, sixteen splits, one tile of sixteen
                                          (1024, 1024, 1024, 0, 1), (130, 70, 3000, 1, 0),
                                          (16, 16, 5000, 0, 0)])
