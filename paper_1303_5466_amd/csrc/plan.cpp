@@ -1,8 +1,6 @@
 // Host planning: tree (Sec. 2.2), skeleton sets (Sec. 3.1), proxy rings.
 #include "plan.hpp"
 
-#include <unordered_map>
-#include <unordered_set>
 
 #include <algorithm>
 #include <cmath>
@@ -139,6 +137,9 @@ struct Builder {
         I.layout = lid;
         I.k = L.k;
         I.r = L.r;
+        const size_t ring = (size_t)(L.ax + 2 * P.m) * (L.ay + 2 * P.m) - (size_t)L.ax * L.ay;
+        I.zu.reserve(ring);
+        I.zv.reserve(ring);
         for (int zu = -P.m; zu < L.ax + P.m; ++zu)
             for (int zv = -P.m; zv < L.ay + P.m; ++zv) {
                 bool inside = zu >= 0 && zu < L.ax && zv >= 0 && zv < L.ay;
@@ -154,33 +155,44 @@ struct Builder {
 
     static void find_symmetry(const Layout& L, IDProblem& I) {
         const int ax = L.ax, ay = L.ay;
-        auto key = [](int u, int v) { return ((int64_t)u << 32) ^ (int64_t)(uint32_t)v; };
-        auto closed = [&](const int32_t* U, const int32_t* V, int n) {
-            std::unordered_set<int64_t> s;
-            for (int i = 0; i < n; ++i) s.insert(key(U[i], V[i]));
+        const int k = L.k, r = L.r;
+        // every point of the three sets lies in the rectangle the proxy ring
+        // spans (mirror images of points in it stay in it): dense marks and
+        // representative numbers over that rectangle
+        int u0 = 0, v0 = 0, u1 = ax - 1, v1 = ay - 1;
+        for (int i = 0; i < I.p; ++i) {
+            u0 = std::min(u0, I.zu[i]); u1 = std::max(u1, I.zu[i]);
+            v0 = std::min(v0, I.zv[i]); v1 = std::max(v1, I.zv[i]);
+        }
+        if (u0 + u1 != ax - 1 || v0 + v1 != ay - 1) return;   // ring not mirror-symmetric
+        const int nu = u1 - u0 + 1, nv = v1 - v0 + 1;
+        auto at = [&](int u, int v) { return (int64_t)(u - u0) * nv + (v - v0); };
+        std::vector<int32_t> mark((size_t)nu * nv, -1);
+        auto closed = [&](const int32_t* U, const int32_t* V, int n, int tag) {
+            for (int i = 0; i < n; ++i) mark[at(U[i], V[i])] = tag;
             for (int i = 0; i < n; ++i)
-                if (!s.count(key(ax - 1 - U[i], V[i])) || !s.count(key(U[i], ay - 1 - V[i]))) return false;
+                if (mark[at(ax - 1 - U[i], V[i])] != tag || mark[at(U[i], ay - 1 - V[i])] != tag) return false;
             return true;
         };
-        const int k = L.k, r = L.r;
-        if (!closed(I.zu.data(), I.zv.data(), I.p) || !closed(L.u.data(), L.v.data(), k) ||
-            !closed(L.u.data() + k, L.v.data() + k, r))
+        if (!closed(I.zu.data(), I.zv.data(), I.p, 0) || !closed(L.u.data(), L.v.data(), k, 1) ||
+            !closed(L.u.data() + k, L.v.data() + k, r, 2))
             return;
         // representatives in list order, then orbit / reflection of every point
         auto orbits = [&](const int32_t* U, const int32_t* V, int n, std::vector<int32_t>& ru,
                           std::vector<int32_t>& rv, std::vector<int32_t>* orb, std::vector<int32_t>* g) {
-            std::unordered_map<int64_t, int> rep;
             for (int i = 0; i < n; ++i)
                 if (U[i] < ax / 2 && V[i] < ay / 2) {
-                    rep[key(U[i], V[i])] = (int)ru.size();
+                    mark[at(U[i], V[i])] = (int)ru.size();
                     ru.push_back(U[i]);
                     rv.push_back(V[i]);
                 }
             if (!orb) return;
+            orb->reserve(n);
+            g->reserve(n);
             for (int i = 0; i < n; ++i) {
                 const int gx = U[i] >= ax / 2 ? 1 : 0, gy = V[i] >= ay / 2 ? 1 : 0;
                 const int fu = gx ? ax - 1 - U[i] : U[i], fv = gy ? ay - 1 - V[i] : V[i];
-                orb->push_back(rep.at(key(fu, fv)));
+                orb->push_back(mark[at(fu, fv)]);
                 g->push_back(gx + 2 * gy);
             }
         };
@@ -342,8 +354,9 @@ bool detect_grid(const double* pts, int64_t n, int64_t& nx, int64_t& ny, double&
     perm.assign(n, -1);
     const double ih = 1.0 / h;
     for (int64_t p = 0; p < n; ++p) {
+        // fi, fj >= 0 (x0, y0 are the minima): truncation rounds to nearest
         const double fi = (pts[2 * p] - x0) * ih, fj = (pts[2 * p + 1] - y0) * ih;
-        const int64_t i = (int64_t)std::floor(fi + 0.5), j = (int64_t)std::floor(fj + 0.5);
+        const int64_t i = (int64_t)(fi + 0.5), j = (int64_t)(fj + 0.5);
         if (std::fabs(fi - i) > 1e-6 || std::fabs(fj - j) > 1e-6 || i < 0 || j < 0 || i >= nx || j >= ny) {
             why = "point off the uniform grid";
             return false;
