@@ -90,7 +90,9 @@ struct TileRef {
 constexpr int64_t GEMM_MAX_OPERAND_BYTES = 0x7ffffff0;
 
 // ------------------------------- launchers ---------------------------------
-// tile: 64 or 128 (square output tiles); ws: split-K partial tiles;
+// tile: 64 or 128 (square output tiles), or 16 for the N <= 16 kernel (one
+// 16-row block of C per wave; d_tiles then lists one entry per wave, tm the
+// row block); ws: split-K partial tiles;
 // reduce: 0 = products (d_tiles: one entry per work-group), 1 = sum the
 // partials of the split tiles listed in d_tiles into C
 // role: 0 factor levels, 1 interpolation, 2 solve sweeps, 3 library calls

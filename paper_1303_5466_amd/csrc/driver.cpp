@@ -357,6 +357,33 @@ struct GemmBatch {
         tiles.clear();
         slots.clear();
         ws_elems = 0;
+        // the solve's products over at most 16 right-hand sides: one 16-row
+        // block per wave, K split until there are about four per compute unit
+        bool skinny = kernel_role() == 2;
+        for (auto& d : descs) skinny = skinny && d.N <= 16;
+        if (skinny) {
+            tile = 16;
+            int64_t blocks = 0;
+            for (auto& d : descs) blocks += (d.M + 15) / 16;
+            for (int id = 0; id < (int)descs.size(); ++id) {
+                const auto& d = descs[id];
+                const int ksteps = (std::max(d.K, 0) + 3) / 4 + (std::max(d.K2, 0) + 3) / 4;
+                int S = 1;
+                if (blocks < 4 * CUS)
+                    S = std::max(1, std::min<int>({(int)((4 * CUS + blocks - 1) / blocks), ksteps / 16, 32}));
+                for (int rb = 0; rb < (d.M + 15) / 16; ++rb) {
+                    if (S == 1) {
+                        tiles.push_back({id, rb, 0, 0, 1, 0});
+                        continue;
+                    }
+                    const int pbase = (int)(ws_elems / 256);
+                    for (int sp = 0; sp < S; ++sp) tiles.push_back({id, rb, 0, sp, S, pbase});
+                    slots.push_back({id, rb, 0, 0, S, pbase});
+                    ws_elems += (int64_t)S * 256;
+                }
+            }
+            return;
+        }
         int64_t t64 = 0, t128 = 0;
         double big = 0, tot = 0;
         int kmax = 0;
@@ -392,11 +419,14 @@ struct GemmBatch {
                 }
         }
     }
+    int kernel_role() const {
+        return role >= 0 ? role
+             : (prof_cls == RSD_PROF_FACTOR_GEMM_F64 || prof_cls == RSD_PROF_FACTOR_GEMM_F32) ? 0
+             : (prof_cls == RSD_PROF_SOLVE_GEMM ? 2 : 1);
+    }
     void run(hipStream_t s) const {
         if (tiles.empty()) return;
-        const int r = role >= 0 ? role
-                    : (prof_cls == RSD_PROF_FACTOR_GEMM_F64 || prof_cls == RSD_PROF_FACTOR_GEMM_F32) ? 0
-                    : (prof_cls == RSD_PROF_SOLVE_GEMM ? 2 : 1);
+        const int r = kernel_role();
         {
             ProfScope ps(prof_cls, s, flops, bytes, (int64_t)tiles.size());
             launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), tile, d_ws, 0, s, r);

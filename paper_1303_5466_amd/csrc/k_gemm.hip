@@ -365,8 +365,86 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
             }
 }
 
+// Products with N <= 16 (the solve's sweeps over a few right-hand sides):
+// every A element is used once, so operands go straight from memory to the
+// MFMA.  A wave owns one work item -- a 16-row block of C over part `split`
+// of `nsplit` of the concatenated K range -- and keeps 8 k-steps of A and B
+// loads in flight (masked buffer loads, no branches); four independent items
+// per work-group, no LDS, no barriers.  Split items write their 16 x 16
+// partial to the workspace, and a reduce dispatch (one wave per split block)
+// adds the partials in split order.
+template <typename T>
+__device__ inline void skinny_segment(const T* A, int lda, int tA, const T* B, int ldb, int tB, int M,
+                                      int N, int ka, int kb, int row0,
+                                      typename Mfma<T>::acc_t& acc) {
+    if (ka >= kb) return;
+    constexpr int U = 8;
+    const int lane = threadIdx.x & 63;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)A, (short)0, RSRC_RANGE, RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void*)B, (short)0, RSRC_RANGE, RSRC_WORD3);
+    const int row = row0 + (lane & 15), col = lane & 15, kl = lane >> 4;
+    const bool rok = row < M, cok = col < N;
+    // element offsets: A(row, k) and B(k, col) as (base + k * step)
+    const int abase = tA ? row * lda : row, astep = tA ? 1 : lda;
+    const int bbase = tB ? col : col * ldb, bstep = tB ? ldb : 1;
+    for (int k = ka; k < kb; k += 4 * U) {
+        T a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kk = k + 4 * u + kl;
+            const bool kok = kk < kb;
+            a[u] = BufLoad<T>::at(ra, (rok & kok) ? (abase + kk * astep) * (int)sizeof(T) : OFF_MASKED);
+            b[u] = BufLoad<T>::at(rb, (cok & kok) ? (bbase + kk * bstep) * (int)sizeof(T) : OFF_MASKED);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = Mfma<T>::step(b[u], a[u], acc);
+    }
+}
+
+template <typename T, int ROLE>
+__global__ void __launch_bounds__(256) gemm_skinny_kernel(const GemmDesc<T>* __restrict__ descs,
+                                                          const TileRef* __restrict__ items, int n_items,
+                                                          T* __restrict__ ws, int reduce) {
+    const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item >= n_items) return;
+    const int lane = threadIdx.x & 63;
+    const TileRef it = items[item];
+    const GemmDesc<T> d = descs[it.desc];
+    if (d.guard && *d.guard) return;
+    const int row0 = it.tm * 16;
+    typename Mfma<T>::acc_t acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    if (reduce) {
+        for (int sp = 0; sp < it.nsplit; ++sp) {
+            const T* p = ws + ((int64_t)it.pbase + sp) * 256 + lane;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += p[v * 64];
+        }
+    } else {
+        // K range of this item: k-steps of 4 over the concatenated segments
+        const int n1 = (max(d.K, 0) + 3) / 4, n2 = (max(d.K2, 0) + 3) / 4;
+        const int s0 = (int)((int64_t)it.split * (n1 + n2) / it.nsplit);
+        const int s1 = (int)((int64_t)(it.split + 1) * (n1 + n2) / it.nsplit);
+        skinny_segment<T>(d.A, d.lda, d.tA, d.B, d.ldb, d.tB, d.M, d.N, 4 * min(s0, n1),
+                          min(4 * min(s1, n1), d.K), row0, acc);
+        skinny_segment<T>(d.A2, d.lda2, d.tA2, d.B2, d.ldb2, d.tB2, d.M, d.N, 4 * (max(s0, n1) - n1),
+                          min(4 * (max(s1, n1) - n1), max(d.K2, 0)), row0, acc);
+        if (it.nsplit > 1) {
+            T* p = ws + ((int64_t)it.pbase + it.split) * 256 + lane;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) p[v * 64] = acc[v];
+            return;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) store_c<T, 16>(d, row0 + (lane & 15), Mfma<T>::col(lane, v), acc[v]);
+}
+
 template <typename T, int ROLE>
 void launch_role(const GemmDesc<T>* d, const TileRef* t, int n, int tile, T* ws, int reduce, hipStream_t s) {
+    if (tile == 16) {
+        hipLaunchKernelGGL((gemm_skinny_kernel<T, ROLE>), dim3((n + 3) / 4), dim3(256), 0, s, d, t, n, ws, reduce);
+        return;
+    }
     if (tile == 128)
         hipLaunchKernelGGL((gemm_kernel<T, ROLE, 128>), dim3(n), dim3(256), 0, s, d, t, ws, reduce);
     else
