@@ -369,35 +369,87 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
 // every A element is used once, so operands go straight from memory to the
 // MFMA.  A wave owns one work item -- a 16-row block of C over part `split`
 // of `nsplit` of the concatenated K range -- and keeps 8 k-steps of A and B
-// loads in flight (masked buffer loads, no branches); four independent items
-// per work-group, no LDS, no barriers.  Split items write their 16 x 16
+// loads in flight (masked buffer loads); four independent items per
+// work-group, no LDS, no barriers.  Split items write their 16 x 16
 // partial to the workspace, and a reduce dispatch (one wave per split block)
 // adds the partials in split order.
+// Four consecutive elements from a k-contiguous operand (one 16-byte load
+// per two doubles or four floats); the whole group is masked at once.
+template <typename T> struct BufLoad4;
+template <> struct BufLoad4<double> {
+    __device__ static inline void at(__amdgpu_buffer_rsrc_t r, int off, double (&x)[4]) {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        typedef double dd2 __attribute__((ext_vector_type(2)));
+        const u4 lo = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        const u4 hi = __builtin_amdgcn_raw_buffer_load_b128(r, off == OFF_MASKED ? off : off + 16, 0, 0);
+        const dd2 a = __builtin_bit_cast(dd2, lo), b = __builtin_bit_cast(dd2, hi);
+        x[0] = a[0]; x[1] = a[1]; x[2] = b[0]; x[3] = b[1];
+    }
+};
+template <> struct BufLoad4<float> {
+    __device__ static inline void at(__amdgpu_buffer_rsrc_t r, int off, float (&x)[4]) {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        typedef float ff4 __attribute__((ext_vector_type(4)));
+        const ff4 a = __builtin_bit_cast(ff4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+        x[0] = a[0]; x[1] = a[1]; x[2] = a[2]; x[3] = a[3];
+    }
+};
+
+// The k order inside a 16-wide chunk is free (it is a sum): lane group
+// g = lane / 16 takes k = 4 g + u in MFMA step u, so a lane reads four
+// consecutive k of its row -- one vector load when the operand is contiguous
+// along k, whole cache lines per instruction either way.
 template <typename T>
 __device__ inline void skinny_segment(const T* A, int lda, int tA, const T* B, int ldb, int tB, int M,
                                       int N, int ka, int kb, int row0,
                                       typename Mfma<T>::acc_t& acc) {
     if (ka >= kb) return;
-    constexpr int U = 8;
     const int lane = threadIdx.x & 63;
     const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)A, (short)0, RSRC_RANGE, RSRC_WORD3);
     const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void*)B, (short)0, RSRC_RANGE, RSRC_WORD3);
-    const int row = row0 + (lane & 15), col = lane & 15, kl = lane >> 4;
+    const int row = row0 + (lane & 15), col = lane & 15, g4 = 4 * (lane >> 4);
     const bool rok = row < M, cok = col < N;
     // element offsets: A(row, k) and B(k, col) as (base + k * step)
     const int abase = tA ? row * lda : row, astep = tA ? 1 : lda;
     const int bbase = tB ? col : col * ldb, bstep = tB ? ldb : 1;
-    for (int k = ka; k < kb; k += 4 * U) {
-        T a[U], b[U];
+    constexpr int SZ = (int)sizeof(T);
+    int k = ka;
+    // whole chunks, two at a time (16 elements in flight per lane)
+    for (; k + 32 <= kb; k += 32) {
+        T a[2][4], b[2][4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int kk = k + 4 * u + kl;
-            const bool kok = kk < kb;
-            a[u] = BufLoad<T>::at(ra, (rok & kok) ? (abase + kk * astep) * (int)sizeof(T) : OFF_MASKED);
-            b[u] = BufLoad<T>::at(rb, (cok & kok) ? (bbase + kk * bstep) * (int)sizeof(T) : OFF_MASKED);
+        for (int h = 0; h < 2; ++h) {
+            const int kk = k + 16 * h + g4;
+            if (tA) {
+                BufLoad4<T>::at(ra, rok ? (abase + kk) * SZ : OFF_MASKED, a[h]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[h][u] = BufLoad<T>::at(ra, rok ? (abase + (kk + u) * astep) * SZ : OFF_MASKED);
+            }
+            if (!tB) {
+                BufLoad4<T>::at(rb, cok ? (bbase + kk) * SZ : OFF_MASKED, b[h]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) b[h][u] = BufLoad<T>::at(rb, cok ? (bbase + (kk + u) * bstep) * SZ : OFF_MASKED);
+            }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc = Mfma<T>::step(b[u], a[u], acc);
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = Mfma<T>::step(b[h][u], a[h][u], acc);
+    }
+    // the rest, element by element with k masking
+    for (; k < kb; k += 16) {
+        T a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = k + g4 + u;
+            const bool kok = kk < kb;
+            a[u] = BufLoad<T>::at(ra, (rok & kok) ? (abase + kk * astep) * SZ : OFF_MASKED);
+            b[u] = BufLoad<T>::at(rb, (cok & kok) ? (bbase + kk * bstep) * SZ : OFF_MASKED);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = Mfma<T>::step(b[u], a[u], acc);
     }
 }
 
