@@ -125,10 +125,11 @@ rsd_status rsd_build_factor(const double* points, int64_t n_points,
 /* Several independent factorizations in one call (many grids of uneven size,
  * e.g. a batch of small problems).  Instance i is exactly what
  * rsd_build_factor(points[i], n_points[i], kernel, a[i], tol, opt, &out[i])
- * would build (same arithmetic, bitwise equal factors); the builds are
- * enqueued back to back, each on its own streams, with at most max_inflight
- * (<= 0 => 8) unfinished at once, so the host planning of one instance and
- * the device work of the others overlap and small instances share the GPU.
+ * would build (same arithmetic, bitwise equal factors).  The instances are
+ * built in groups of max_inflight (<= 0 => 64): the interpolation problems
+ * of every box type of a group are solved together (one launch per window
+ * serves all of them), then the level pipelines run level by level across
+ * the group, each instance on its own stream.
  *   points, n_points, a  arrays of n_inst entries (a may be NULL => all 1;
  *                        a[i] may be NULL).  Host or device pointers.
  *   opt                  shared by all instances; opt->hip_stream must be NULL.

@@ -115,11 +115,13 @@ void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes,
                          int max_r, hipStream_t s);
 template <typename T>
 // geo per problem: ax, ay, sector (-1: plain problem; 0..3: symmetry sector
-// ab = a + 2b, entries summed over the four reflections with signs (-1)^(a gx + b gy))
+// ab = a + 2b, entries summed over the four reflections with signs (-1)^(a gx + b gy));
+// logh_of: nullptr (every problem uses kd.logh) or log h per problem
 void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* k_of,
                          const int* r_of, const int* zoff, const int* zu, const int* zv,
-                         const int* xoff, const int* xu, const int* xv, const int* geo, int n_problems,
-                         int max_pn, KernelDesc kd, hipStream_t s);
+                         const int* xoff, const int* xu, const int* xv, const int* geo,
+                         const double* logh_of, int n_problems, int max_pn, KernelDesc kd,
+                         hipStream_t s);
 // T of a box type from solutions kept in a float64 sector arena: the four
 // sector solutions of a symmetric type combined, or a plain solution copied,
 // converted to the precision of the T arena (see k_gen.hip)
@@ -129,6 +131,7 @@ struct SymCombineDesc {
     int k, r;
     int off_sk, off_rs;   // into the orbit / reflection tables (sym only)
     int sym;
+    void* dst;         // nullptr: T at offT in the launch's arena; else the layout's T itself
 };
 template <typename TS, typename TD>
 void launch_sym_combine(TD* Tarena, const TS* Tsec, const SymCombineDesc* d, int n_desc,
@@ -190,6 +193,7 @@ struct GJDesc {
     T* SR;           // nb x ncols side buffer (ld = nb)
     T* SC;           // n x nb side buffer (ld = n)
     int box;         // for error reports
+    int* err = nullptr;   // error flag of the block's factor (nullptr: the launch's)
 };
 template <typename T>
 void launch_gj_pivot(const GJDesc<T>* d, int n_desc, int step, int nb, int max_chunks,

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -246,6 +247,45 @@ static void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
     if (!v.empty()) RSD_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// Non-blocking streams, kept per device and handed to later factors and
+// builds: creating and destroying the streams of a build costs a few hundred
+// microseconds of host time each, a large share of a small grid's build.  A
+// stream handed back may still hold queued work; its next owner's launches
+// queue behind it.
+class StreamPool {
+public:
+    static StreamPool& get() {
+        static StreamPool* pool = new StreamPool();   // outlives static destructors
+        return *pool;
+    }
+    // a stream of the current device
+    hipStream_t take() {
+        int dev = 0;
+        RSD_HIP(hipGetDevice(&dev));
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto& v = free_[dev];
+            if (!v.empty()) {
+                hipStream_t q = v.back();
+                v.pop_back();
+                return q;
+            }
+        }
+        hipStream_t q = nullptr;
+        RSD_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        return q;
+    }
+    void give(int dev, hipStream_t q) {
+        if (!q) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_[dev].push_back(q);
+    }
+
+private:
+    std::mutex mu_;
+    std::map<int, std::vector<hipStream_t>> free_;
+};
+
 static bool is_device_ptr(const void* p) {
     if (!p) return false;
     hipPointerAttribute_t attr;
@@ -326,6 +366,7 @@ struct GemmBatch {
     double flops = 0, bytes = 0;
     int prof_cls = -1;
     int role = -1;      // kernel instantiation (see launch_gemm); -1: from prof_cls
+    int max_split = 16; // 1: no split K, so every product's rounding is independent of the batch
     void add(const GemmDesc<T>& d) {
         if (d.M <= 0 || d.N <= 0) return;
         descs.push_back(d);
@@ -404,7 +445,7 @@ struct GemmBatch {
             const auto& d = descs[id];
             const int steps = (std::max(d.K, 0) + bk - 1) / bk + (std::max(d.K2, 0) + bk - 1) / bk;
             int S = 1;
-            if (nt < CUS) S = std::max(1, std::min<int>({(int)((2 * CUS + nt - 1) / nt), steps / 8, 16}));
+            if (nt < CUS) S = std::max(1, std::min<int>({(int)((2 * CUS + nt - 1) / nt), steps / 8, max_split}));
             const int tm = (d.M + tile - 1) / tile, tn = (d.N + tile - 1) / tile;
             for (int i = 0; i < tm; ++i)
                 for (int j = 0; j < tn; ++j) {
@@ -563,6 +604,10 @@ struct Factor {
     std::vector<BoxDev> hboxes;
     std::vector<LayoutDev> hlayouts;
     std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
+    std::vector<int> exec_index;    // level -> index into L64 or L32
+    std::vector<int> layout_level;  // layout -> level of its boxes
+    double gemm_flops = 0;          // flops of the level products
+    int layers = 0;
     rsd_factor_stats stats{};
     ~Factor() {
         if (stream) (void)hipStreamSynchronize(stream);
@@ -581,9 +626,8 @@ struct Factor {
         for (auto e : tmp_events) (void)hipEventDestroy(e);
         for (auto e : build_ev)
             if (e) (void)hipEventDestroy(e);
-        for (auto q : qr_stream)
-            if (q) (void)hipStreamDestroy(q);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        for (auto q : qr_stream) StreamPool::get().give(device, q);
+        if (own_stream) StreamPool::get().give(device, stream);
     }
     DevBuf& tmp() {
         scratch.push_back(std::make_unique<DevBuf>());
@@ -618,24 +662,33 @@ static int interp_prec(const Factor& f, int level) {
     return f.level_prec[level] && (f.flags & RSD_FLAG_FP32_INTERP) ? 1 : 0;
 }
 
+// One interpolation problem of a chain: the box type `id` of factor `f`,
+// whose level `level` needs its T; `tag` is reported when it is solved.
+struct ChainMember {
+    Factor* f;
+    int id, level, tag;
+};
+
 // One chain of interpolation problems: every problem of the chain advances
 // window by window through the same launches on the chain's stream, and the
-// problems finished after a window get their back substitution on the
-// factor's solve stream.  Problems of different sub-panel widths form
-// separate chains on separate streams, so a wide chain does not wait for the
-// narrow sub-panels of the largest boxes.
+// problems finished after a window get their back substitution right after
+// it, on the same stream.  The problems may belong to several factors (a
+// batch of grids): one launch then serves the same window of all of them.
 template <typename T>
 struct QRChain {
-    Factor* f = nullptr;
+    Factor* f = nullptr;               // first member's factor (tolerance, kernel, T arena)
+    bool several = false;              // problems of several factors: every solution staged
+    std::vector<std::unique_ptr<DevBuf>>* owner = nullptr;   // holds the chain's device buffers
     hipStream_t s = nullptr;
     std::vector<QRProblemDev> qp;
-    std::vector<int> prob_level;
+    std::vector<int> prob_tag;         // the member's tag of every (sector) problem
     int S = 0, np = 0, max_k = 0, max_n = 0, max_nch = 0, max_subs = 0;
     DevBuf *dA = nullptr, *daux = nullptr, *diaux = nullptr, *dws = nullptr, *dq = nullptr,
            *dlist = nullptr, *dsolve = nullptr, *dsec = nullptr, *dcomb = nullptr, *dorb = nullptr,
            *drefl = nullptr;
     std::vector<int64_t> sym_sec0;     // staging-arena offset of every staged problem
     std::vector<int> staged_prec;      // precision of its T arena (0 float64, 1 float32)
+    DevBuf* dlogh = nullptr;           // log h per problem (several factors only)
     std::vector<int> comb_off[2];      // staging descriptors per window, per destination precision
     int comb_max_kr = 0;
     std::vector<GemmBatch<T>> g1, gt, g2;
@@ -646,12 +699,24 @@ struct QRChain {
     double qr_tol = 0;
     double flops = 0, bytes = 0;
 
-    void setup(Factor& fac, const std::vector<int>& probs_ids, const std::vector<int>& levels,
-               hipStream_t stream) {
-        f = &fac;
+    DevBuf& tmp() {
+        owner->push_back(std::make_unique<DevBuf>());
+        return *owner->back();
+    }
+
+    // members: the problems, each with its factor, level and tag (reported by
+    // window() when it is solved).  With members of several factors every
+    // solution goes through the staging arena, whose combine step writes it
+    // into its own factor's T arena.
+    void setup(const std::vector<ChainMember>& members, bool of_several,
+               std::vector<std::unique_ptr<DevBuf>>& buffers, hipStream_t stream) {
+        f = members.front().f;
+        several = of_several;
+        owner = &buffers;
         s = stream;
-        Plan& P = f->plan;
         std::vector<int64_t> offA;
+        std::vector<double> lgh;
+        std::vector<Factor*> staged_fac;
         std::vector<int> pof, kof, rof, zoff, xoff, zu, zv, xu, xv, geo;
         int64_t A_el = 0, aux_el = 0, iaux_el = 0, ws_el = 0, sec_el = 0;
         int max_pn = 0, max_r = 0;
@@ -661,21 +726,24 @@ struct QRChain {
         // staged solutions: symmetric problems (sectors, then combined) and
         // problems whose level keeps T in another precision than this chain
         std::vector<int> staged_ids, staged_sym;
-        for (size_t pi = 0; pi < probs_ids.size(); ++pi) {
-            const int id = probs_ids[pi];
-            const IDProblem& I = P.idps[id];
-            const Layout& L = P.layouts[I.layout];
+        for (size_t pi = 0; pi < members.size(); ++pi) {
+            Factor& F = *members[pi].f;
+            const int id = members[pi].id, lev = members[pi].level;
+            const IDProblem& I = F.plan.idps[id];
+            const Layout& L = F.plan.layouts[I.layout];
             const int chain_prec = std::is_same<T, double>::value ? 0 : 1;
-            const bool sym = split_sym(*f, I, chain_prec);
-            const bool convert = f->level_prec[levels[pi]] != chain_prec;
+            const bool sym = split_sym(F, I, chain_prec);
+            const bool convert = F.level_prec[lev] != chain_prec;
+            const bool staged = sym || convert || several;
             const int nsec = sym ? 4 : 1;
             const int64_t sec0 = sec_el;
-            if (sym || convert) {
+            if (staged) {
                 sec_el += (int64_t)I.k * I.r / (sym ? 4 : 1);
                 staged_ids.push_back(id);
                 staged_sym.push_back(sym ? 1 : 0);
                 sym_sec0.push_back(sec0);
-                staged_prec.push_back(f->level_prec[levels[pi]]);
+                staged_prec.push_back(F.level_prec[lev]);
+                staged_fac.push_back(&F);
             }
             for (int sc = 0; sc < nsec; ++sc) {
                 QRProblemDev q;
@@ -683,13 +751,13 @@ struct QRChain {
                 q.k = sym ? I.k / 4 : I.k;
                 q.r = sym ? I.r / 4 : I.r;
                 q.sec = sym ? sc : -1;
-                q.staged = (sym || convert) ? 1 : 0;
+                q.staged = staged ? 1 : 0;
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));
                 if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
                 const int n = q.k + q.r;
                 const int nch = (q.p + QR_RC - 1) / QR_RC;
                 q.offA = A_el;
-                q.offT = (sym || convert) ? sec0 + (int64_t)sc * q.k * q.r : f->hlayouts[I.layout].offT;
+                q.offT = staged ? sec0 + (int64_t)sc * q.k * q.r : F.hlayouts[I.layout].offT;
                 q.offAux = aux_el;
                 q.offIaux = iaux_el;
                 q.offV = ws_el;
@@ -701,7 +769,8 @@ struct QRChain {
                 aux_el += 2 * q.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
                 iaux_el += q.k + 8 + 4 * QR_WIN;
                 qp.push_back(q);
-                prob_level.push_back(levels[pi]);
+                prob_tag.push_back(members[pi].tag);
+                lgh.push_back(F.kd.logh);
                 offA.push_back(q.offA);
                 pof.push_back(q.p); kof.push_back(q.k); rof.push_back(q.r);
                 zoff.push_back((int)zu.size());
@@ -729,11 +798,14 @@ struct QRChain {
             }
         }
         np = (int)qp.size();
-        DevBuf &doffA = f->tmp(), &dp = f->tmp(), &dk = f->tmp(), &dr = f->tmp(), &dzo = f->tmp(),
-               &dzu = f->tmp(), &dzv = f->tmp(), &dxo = f->tmp(), &dxu = f->tmp(), &dxv = f->tmp(),
-               &dgeo = f->tmp(), &dgemm = f->tmp();
-        dA = &f->tmp(); daux = &f->tmp(); diaux = &f->tmp(); dws = &f->tmp(); dq = &f->tmp();
-        dlist = &f->tmp(); dsolve = &f->tmp(); dsec = &f->tmp();
+        DevBuf &doffA = tmp(), &dp = tmp(), &dk = tmp(), &dr = tmp(), &dzo = tmp(), &dzu = tmp(),
+               &dzv = tmp(), &dxo = tmp(), &dxu = tmp(), &dxv = tmp(), &dgeo = tmp(), &dgemm = tmp();
+        dA = &tmp(); daux = &tmp(); diaux = &tmp(); dws = &tmp(); dq = &tmp();
+        dlist = &tmp(); dsolve = &tmp(); dsec = &tmp();
+        if (several) {
+            dlogh = &tmp();
+            upload(*dlogh, lgh, s);
+        }
         dA->alloc(A_el * sizeof(T));
         daux->alloc(aux_el * sizeof(T));
         diaux->alloc(iaux_el * sizeof(int));
@@ -749,10 +821,15 @@ struct QRChain {
             std::vector<int> orb, refl;
             std::vector<std::vector<SymCombineDesc>> by_win[2];
             for (size_t si = 0; si < staged_ids.size(); ++si) {
-                const IDProblem& I = P.idps[staged_ids[si]];
+                Factor& F = *staged_fac[si];
+                const IDProblem& I = F.plan.idps[staged_ids[si]];
                 const bool sym = staged_sym[si] != 0;
                 SymCombineDesc cd;
-                cd.offT = f->hlayouts[I.layout].offT;
+                cd.offT = F.hlayouts[I.layout].offT;
+                cd.dst = nullptr;
+                if (several)
+                    cd.dst = staged_prec[si] ? static_cast<void*>(Tbase<float>(F) + cd.offT)
+                                             : static_cast<void*>(Tbase<double>(F) + cd.offT);
                 cd.offS = sym_sec0[si];
                 cd.k = I.k;
                 cd.r = I.r;
@@ -784,7 +861,7 @@ struct QRChain {
             }
             orb.push_back(0);
             refl.push_back(0);
-            dcomb = &f->tmp(); dorb = &f->tmp(); drefl = &f->tmp();
+            dcomb = &tmp(); dorb = &tmp(); drefl = &tmp();
             upload(*dcomb, flatc, s); upload(*dorb, orb, s); upload(*drefl, refl, s);
         }
         // trailing-update products of every window, guarded by the problem's skip flag
@@ -857,10 +934,14 @@ struct QRChain {
                 }
             }
         }
+        // no split K: a problem's solution must not depend on the other
+        // problems of its chain (a grid built alone or in a batch gets the
+        // same bits)
         std::vector<GemmBatch<T>*> all;
         for (int sw = 0; sw < S; ++sw) { all.push_back(&g1[sw]); all.push_back(&gt[sw]); all.push_back(&g2[sw]); }
         for (auto& v : gsolve)
             for (auto& b : v) all.push_back(&b);
+        for (auto* b : all) b->max_split = 1;
         upload_batches<T>(dgemm, all, s);
         // sub-panel width classes
         const int widths[4] = {16, 8, 4, 2};
@@ -888,14 +969,14 @@ struct QRChain {
         qr_tol = std::is_same<T, float>::value ? std::max(f->tol, 1e-6) : f->tol;
         launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
                                dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
-                               dxo.as<int>(), dxu.as<int>(), dxv.as<int>(), dgeo.as<int>(), np,
-                               max_pn, f->kd, s);
+                               dxo.as<int>(), dxu.as<int>(), dxv.as<int>(), dgeo.as<int>(),
+                               several ? dlogh->as<double>() : nullptr, np, max_pn, f->kd, s);
         launch_qr_init<T>(Ab, daux->as<T>(), diaux->as<int>(), dq->as<QRProblemDev>(), np, max_k, s);
     }
 
     // Enqueues window sw.  For the problems that finish in it, the back
     // substitutions follow on the chain's stream, then an event: returned,
-    // with the level of every finished (sector) problem appended to `done`
+    // with the tag of every finished (sector) problem appended to `done`
     // (nullptr and nothing appended when no problem finishes).
     hipEvent_t window(int sw, std::vector<int>& done) {
         if (sw >= S) return nullptr;
@@ -941,7 +1022,7 @@ struct QRChain {
         hipEvent_t solved;
         RSD_HIP(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
         RSD_HIP(hipEventRecord(solved, s));
-        for (int g = soff[sw]; g < soff[sw + 1]; ++g) done.push_back(prob_level[sflat[g]]);
+        for (int g = soff[sw]; g < soff[sw + 1]; ++g) done.push_back(prob_tag[sflat[g]]);
         return solved;
     }
 };
@@ -1074,14 +1155,15 @@ static void upload_gj(DevBuf& buf, std::vector<LevelExec<T>>& Ls, hipStream_t s)
     for (auto& L : Ls) { L.d_topgj = buf.as<GJDesc<T>>() + o; o += L.topgj.size(); }
 }
 
+// F of every box of the level: leaf blocks, or the parent blocks assembled
+// from the children's E and the generated sibling blocks.
 template <typename T>
-static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
+static void run_assembly(Factor& f, LevelExec<T>& L, hipStream_t s) {
     const int t = L.level;
     const int n = (int)L.ids.size();
     T* F = Fbase<T>(f);
     const BoxDev* B = f.d_boxes.as<BoxDev>();
     const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
-    {
     ProfScope ps(RSD_PROF_ASSEMBLY, s);
     if (t == 0) {
         launch_leaf_F<T>(F, B, f.ids(t), n, LD, f.d_lu.as<int>(), f.d_lv.as<int>(), f.kd, L.max_m, s);
@@ -1101,13 +1183,23 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
                                               f.d_srci.as<int>(), f.kd, L.max_m, s);
         }
     }
-    }
+}
+
+// F'_rs = (F'_sr)^T for the level's boxes
+template <typename T>
+static void run_transpose(Factor& f, LevelExec<T>& L, hipStream_t s) {
+    if (L.g_sr.empty()) return;
+    ProfScope ps(RSD_PROF_ASSEMBLY, s);
+    launch_transpose_sr<T>(Fbase<T>(f), f.d_boxes.as<BoxDev>(), f.ids(L.level), (int)L.ids.size(),
+                           L.max_k, L.max_r, s);
+}
+
+template <typename T>
+static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
+    run_assembly<T>(f, L, s);
     L.g_sr.run(s);
     L.g_rr.run(s);
-    if (!L.g_sr.empty()) {
-        ProfScope ps(RSD_PROF_ASSEMBLY, s);
-        launch_transpose_sr<T>(F, B, f.ids(t), n, L.max_k, L.max_r, s);
-    }
+    run_transpose<T>(f, L, s);
     for (int st = 0; st < L.gj_steps; ++st) {
         {
             ProfScope ps(RSD_PROF_GJ_PIVOT, s);
@@ -1125,12 +1217,96 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
     }
 }
 
+// One level (and precision) of every factor of a batch group: each product
+// and each Gauss-Jordan step is one launch for the boxes of all of them.
+// Every descriptor keeps its own factor's addresses (and its error flag), so
+// merging changes nothing but the launch count and, through the tile table,
+// the split of long K ranges.
+template <typename T>
+struct GroupLevel {
+    std::vector<std::pair<Factor*, LevelExec<T>*>> members;
+    GemmBatch<T> g_sr, g_rr, g_E;
+    std::vector<GemmBatch<T>> g_gj, g_topgj;
+    std::vector<GJDesc<T>> gj, topgj;
+    const GJDesc<T>* d_gj = nullptr;
+    const GJDesc<T>* d_topgj = nullptr;
+    int gj_steps = 0, topgj_steps = 0, max_chunks = 0, top_chunks = 0;
+
+    void add(Factor& F, LevelExec<T>& L) {
+        members.push_back({&F, &L});
+        for (auto& d : L.g_sr.descs) g_sr.add(d);
+        for (auto& d : L.g_rr.descs) g_rr.add(d);
+        for (auto& d : L.g_E.descs) g_E.add(d);
+        if ((int)g_gj.size() < L.gj_steps) g_gj.resize(L.gj_steps);
+        for (int st = 0; st < L.gj_steps; ++st)
+            for (auto& d : L.g_gj[st].descs) g_gj[st].add(d);
+        if ((int)g_topgj.size() < L.topgj_steps) g_topgj.resize(L.topgj_steps);
+        for (int st = 0; st < L.topgj_steps; ++st)
+            for (auto& d : L.g_topgj[st].descs) g_topgj[st].add(d);
+        for (auto g : L.gj) {
+            g.err = F.d_err.as<int>();
+            gj.push_back(g);
+        }
+        for (auto g : L.topgj) {
+            g.err = F.d_err.as<int>();
+            topgj.push_back(g);
+        }
+        gj_steps = std::max(gj_steps, L.gj_steps);
+        topgj_steps = std::max(topgj_steps, L.topgj_steps);
+        max_chunks = std::max(max_chunks, L.max_chunks);
+        top_chunks = std::max(top_chunks, L.top_chunks);
+    }
+    void batches(std::vector<GemmBatch<T>*>& all) {
+        const int cls = std::is_same<T, double>::value ? RSD_PROF_FACTOR_GEMM_F64 : RSD_PROF_FACTOR_GEMM_F32;
+        for (auto* b : {&g_sr, &g_rr, &g_E}) {
+            b->prof_cls = cls;
+            all.push_back(b);
+        }
+        for (auto& b : g_gj) { b.prof_cls = cls; all.push_back(&b); }
+        for (auto& b : g_topgj) { b.prof_cls = RSD_PROF_FACTOR_GEMM_F64; all.push_back(&b); }
+    }
+    void run(hipStream_t s) {
+        if (members.empty()) return;
+        int* err0 = members.front().first->d_err.template as<int>();
+        for (auto& m : members) run_assembly<T>(*m.first, *m.second, s);
+        g_sr.run(s);
+        g_rr.run(s);
+        for (auto& m : members) run_transpose<T>(*m.first, *m.second, s);
+        for (int st = 0; st < gj_steps; ++st) {
+            {
+                ProfScope ps(RSD_PROF_GJ_PIVOT, s);
+                launch_gj_pivot<T>(d_gj, (int)gj.size(), st, GJ_NB, max_chunks, err0, s);
+            }
+            g_gj[st].run(s);
+        }
+        g_E.run(s);
+        for (int st = 0; st < topgj_steps; ++st) {
+            {
+                ProfScope ps(RSD_PROF_GJ_PIVOT, s);
+                launch_gj_pivot<T>(d_topgj, (int)topgj.size(), st, GJ_NB, top_chunks, err0, s);
+            }
+            g_topgj[st].run(s);
+        }
+    }
+};
+
+template <typename T>
+static void upload_group_gj(DevBuf& buf, std::vector<GroupLevel<T>>& G, hipStream_t s) {
+    std::vector<GJDesc<T>> host;
+    for (auto& g : G) host.insert(host.end(), g.gj.begin(), g.gj.end());
+    for (auto& g : G) host.insert(host.end(), g.topgj.begin(), g.topgj.end());
+    upload(buf, host, s);
+    size_t o = 0;
+    for (auto& g : G) { g.d_gj = buf.as<GJDesc<T>>() + o; o += g.gj.size(); }
+    for (auto& g : G) { g.d_topgj = buf.as<GJDesc<T>>() + o; o += g.topgj.size(); }
+}
+
 // ----------------------------------------------------------------------------
 // build
 // ----------------------------------------------------------------------------
-// Host planning, uploads and every launch of a build; returns without waiting
-// for the device (build_finish does).
-static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, const rsd_kernel* kernel,
+// Host planning of a build and the uploads of its tables (on the factor's
+// stream); no kernel is launched yet.
+static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, const rsd_kernel* kernel,
                                              const double* a, double tol, const rsd_options* opt) {
     if (!points || n <= 0) throw Error(RSD_EINVAL, "points must be non-null and n_points > 0");
     if (!(tol > 0) || !std::isfinite(tol)) throw Error(RSD_EINVAL, "tol must be a positive number");
@@ -1141,7 +1317,7 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     RSD_HIP(hipGetDevice(&f->device));
     if (o.hip_stream) f->stream = static_cast<hipStream_t>(o.hip_stream);
     else {
-        RSD_HIP(hipStreamCreateWithFlags(&f->stream, hipStreamNonBlocking));
+        f->stream = StreamPool::get().take();
         f->own_stream = true;
     }
     hipStream_t s = f->stream;
@@ -1197,7 +1373,6 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     f->level_prec.assign(nlev, 0);
     if (f->precision == RSD_PREC_FP32_REFINE)
         for (int t = 0; t < f->top; ++t) f->level_prec[t] = 1;
-    auto t_start = std::chrono::steady_clock::now();
     // ---- grid-ordered coefficients -----------------------------------------
     std::vector<double> ag, sbg;
     if (!ah.empty()) {
@@ -1339,13 +1514,46 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     upload_batches<float>(f->gemm32, b32, s);
     upload_gj<double>(f->gj64, f->L64, s);
     upload_gj<float>(f->gj32, f->L32, s);
-    // ---- device work ---------------------------------------------------------
-    hipEvent_t e0, e1;
-    RSD_HIP(hipEventCreate(&e0));
-    RSD_HIP(hipEventCreate(&e1));
-    RSD_HIP(hipEventRecord(e0, s));
+    f->exec_index = exec_index;
+    f->layout_level = layout_level;
+    f->layers = m;
+    for (auto* b : b64) f->gemm_flops += b->flops;
+    for (auto* b : b32) f->gemm_flops += b->flops;
+    RSD_HIP(hipEventCreate(&f->build_ev[0]));
+    RSD_HIP(hipEventCreate(&f->build_ev[1]));
+    RSD_HIP(hipEventRecord(f->build_ev[0], s));
+    return f;
+}
+
+// Chain class of a box type's interpolation problem, and how many (sector)
+// problems it makes.  Class 0 holds the problems done after one window (the
+// lower levels, needed first), class 1 the longer ones, class 2 the boxes too
+// tall for 16-column sub-panels.
+static int chain_class(const Factor& f, const IDProblem& I, int ip, int& nprob) {
+    const bool sym = split_sym(f, I, ip);
+    const bool narrow = qr_panel_width(sym ? I.p / 4 : I.p, ip ? 4 : 8) < 16;
+    nprob = sym ? 4 : 1;
+    return narrow ? 2 : ((sym ? I.k / 4 : I.k) <= QR_WIN ? 0 : 1);
+}
+
+template <typename T>
+static void run_level_of(Factor& f, int t, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) run_level<float>(f, f.L32[f.exec_index[t]], s);
+    else run_level<double>(f, f.L64[f.exec_index[t]], s);
+}
+
+// Every launch of a single build: the interpolation chains on two streams of
+// their own and the level pipeline on the factor's stream, each level as
+// soon as the events of its box types exist.
+static void enqueue_single(Factor& fr) {
+    Factor* f = &fr;
+    Plan& P = f->plan;
+    hipStream_t s = f->stream;
+    const int nlev = (int)P.levels.size();
+    const std::vector<int>& exec_index = f->exec_index;
+    const std::vector<int>& layout_level = f->layout_level;
     // interpolation problems on their own streams, overlapping the level pipeline
-    for (auto& q : f->qr_stream) RSD_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    for (auto& q : f->qr_stream) q = StreamPool::get().take();
     {
         hipEvent_t go;
         RSD_HIP(hipEventCreateWithFlags(&go, hipEventDisableTiming));
@@ -1353,10 +1561,8 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         for (auto q : f->qr_stream) RSD_HIP(hipStreamWaitEvent(q, go, 0));
         (void)hipEventDestroy(go);
     }
-    // chains: (precision, class) -> problems.  Class 0 holds the problems
-    // done after one window (the lower levels, needed first), class 1 the
-    // longer ones, class 2 the boxes too tall for 16-column sub-panels; every
-    // chain advances its problems window by window, so the short problems do
+    // chains: (precision, class) -> problems (chain_class); every chain
+    // advances its problems window by window, so the short problems do
     // not wait for the first windows of the large ones.  Classes 0 and 2
     // share a stream (class 0 is done almost at once), class 1 has the other:
     // with the level pipeline's stream that is three streams, one hardware
@@ -1364,7 +1570,7 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     // the default stream).
     constexpr int NCH = 3;
     auto chain_stream = [&](int c) { return f->qr_stream[c == 1 ? 1 : 0]; };
-    std::vector<int> cp[2][NCH], cl[2][NCH];
+    std::vector<ChainMember> cp[2][NCH];
     std::vector<int> pending(nlev, 0);
     for (size_t li = 0; li < P.layouts.size(); ++li) {
         if (P.layouts[li].idp < 0) continue;
@@ -1373,13 +1579,10 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         // computed in float64 and rounded into a float32 level's arena,
         // unless the caller asks for float32 interpolation as well
         const int ip = interp_prec(*f, lev);
-        const IDProblem& I = P.idps[P.layouts[li].idp];
-        const bool sym = split_sym(*f, I, ip);
-        const bool narrow = qr_panel_width(sym ? I.p / 4 : I.p, ip ? 4 : 8) < 16;
-        const int cls = narrow ? 2 : ((sym ? I.k / 4 : I.k) <= QR_WIN ? 0 : 1);
-        cp[ip][cls].push_back(P.layouts[li].idp);
-        cl[ip][cls].push_back(lev);
-        pending[lev] += sym ? 4 : 1;     // one per (sector) problem
+        int nprob = 1;
+        const int cls = chain_class(*f, P.idps[P.layouts[li].idp], ip, nprob);
+        cp[ip][cls].push_back({f, P.layouts[li].idp, lev, lev});
+        pending[lev] += nprob;     // one per (sector) problem
     }
     // Levels are enqueued as soon as the events of their box types exist, so
     // the level pipeline runs alongside the interpolation problems.  The
@@ -1415,8 +1618,8 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         }
         const int t = next_level++;
         for (auto e : waits) RSD_HIP(hipStreamWaitEvent(s, e, 0));
-        if (f->level_prec[t]) run_level<float>(*f, f->L32[exec_index[t]], s);
-        else run_level<double>(*f, f->L64[exec_index[t]], s);
+        if (f->level_prec[t]) run_level_of<float>(*f, t, s);
+        else run_level_of<double>(*f, t, s);
         return true;
     };
     {
@@ -1425,8 +1628,8 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         int S = 0;
         double fl = 0, by = 0;
         for (int c = 0; c < NCH; ++c) {
-            if (!cp[0][c].empty()) { c64[c].setup(*f, cp[0][c], cl[0][c], chain_stream(c)); S = std::max(S, c64[c].S); }
-            if (!cp[1][c].empty()) { c32[c].setup(*f, cp[1][c], cl[1][c], chain_stream(c)); S = std::max(S, c32[c].S); }
+            if (!cp[0][c].empty()) { c64[c].setup(cp[0][c], false, f->scratch, chain_stream(c)); S = std::max(S, c64[c].S); }
+            if (!cp[1][c].empty()) { c32[c].setup(cp[1][c], false, f->scratch, chain_stream(c)); S = std::max(S, c32[c].S); }
             fl += c64[c].flops + c32[c].flops;
             by += c64[c].bytes + c32[c].bytes;
         }
@@ -1480,22 +1683,24 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
     while (next_level < nlev && enqueue_next(false)) {
     }
     if (next_level != nlev) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
-    RSD_HIP(hipEventRecord(e1, s));
-    f->build_ev[0] = e0;
-    f->build_ev[1] = e1;
-    // ---- statistics (the build time is filled in by build_finish) -------------------
+    RSD_HIP(hipEventRecord(f->build_ev[1], s));
+}
+
+// Sizes and flop / byte counts of a prepared factor (the build time is
+// filled in by build_finish).
+static void build_stats(Factor& fr) {
+    Factor* f = &fr;
+    Plan& P = f->plan;
     rsd_factor_stats& st = f->stats;
-    st.n_points = n; st.nx = nx; st.ny = ny;
-    st.n_levels = nlev;
+    st.n_points = f->N; st.nx = f->nx; st.ny = f->ny;
+    st.n_levels = (int)P.levels.size();
     st.n_boxes = (int)P.boxes.size();
-    st.layers = m;
+    st.layers = f->layers;
     st.precision = f->precision;
     st.factor_bytes = (int64_t)(f->F64.bytes + f->F32.bytes + f->T64.bytes + f->T32.bytes);
-    double fl = 0;
-    for (auto* b : b64) fl += b->flops;
-    for (auto* b : b32) fl += b->flops;
+    double fl = f->gemm_flops;
     for (auto& I : P.idps) {
-        const double ns = split_sym(*f, I, interp_prec(*f, layout_level[I.layout])) ? 4 : 1;
+        const double ns = split_sym(*f, I, interp_prec(*f, f->layout_level[I.layout])) ? 4 : 1;
         const double p = I.p / ns, k = I.k / ns, r = I.r / ns;
         fl += ns * (2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r);
     }
@@ -1507,7 +1712,15 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
         if (b.level == f->top) sb += (double)es * b.k * b.k;
     }
     st.solve_bytes = sb;
-    (void)t_start;
+}
+
+// Host planning, uploads and every launch of a build; returns without waiting
+// for the device (build_finish does).
+static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, const rsd_kernel* kernel,
+                                             const double* a, double tol, const rsd_options* opt) {
+    auto f = build_prepare(points, n, kernel, a, tol, opt);
+    enqueue_single(*f);
+    build_stats(*f);
     return f;
 }
 
@@ -1515,7 +1728,8 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
 // pivot block if one was met.
 static void build_finish(Factor& f) {
     RSD_HIP(hipStreamSynchronize(f.stream));
-    for (auto q : f.qr_stream) RSD_HIP(hipStreamSynchronize(q));
+    for (auto q : f.qr_stream)
+        if (q) RSD_HIP(hipStreamSynchronize(q));
     {
         IdleScope idle;     // the build's streams have drained
         f.scratch.clear();
@@ -1535,6 +1749,150 @@ static void build_finish(Factor& f) {
         const int bx = err[0] - 1;
         throw Error(RSD_ESINGULAR, "singular pivot block in box " + std::to_string(bx) + " at level " +
                                        std::to_string(f.plan.boxes[bx].level));
+    }
+}
+
+// Streams and device buffers shared by the factors of a batch group (the
+// interpolation chains and the merged levels).  Released only after the
+// streams have drained, and before any factor of the group may be freed
+// (they write into the factors' arenas).
+struct GroupChains {
+    hipStream_t qs[3] = {nullptr, nullptr, nullptr};   // two chain streams, the level stream
+    int dev = 0;
+    std::vector<std::unique_ptr<DevBuf>> buffers;
+    std::vector<hipEvent_t> events;
+    DevBuf& buffer() {
+        buffers.push_back(std::make_unique<DevBuf>());
+        return *buffers.back();
+    }
+    ~GroupChains() {
+        for (auto q : qs)
+            if (q) (void)hipStreamSynchronize(q);
+        {
+            IdleScope idle;
+            buffers.clear();
+        }
+        for (auto e : events) (void)hipEventDestroy(e);
+        for (auto q : qs) StreamPool::get().give(dev, q);
+    }
+};
+
+// Enqueues the builds of a group of prepared factors together.  The
+// interpolation problems of all of them form one set of chains, so every
+// window is one launch per kernel for the whole group; then the levels,
+// counted from the leaves, each merged over the group (one launch per
+// product and per Gauss-Jordan step for the boxes of every factor), after
+// the events of their box types.  A factor's T is bitwise what a build of
+// its own computes; the merged level products may split long K ranges
+// differently, which changes only the rounding order.
+static void enqueue_group(const std::vector<Factor*>& group, GroupChains& gc) {
+    constexpr int NCH = 3;
+    constexpr int TAG_LEVELS = 256;   // tag = member * TAG_LEVELS + level
+    RSD_HIP(hipGetDevice(&gc.dev));
+    for (auto& q : gc.qs) q = StreamPool::get().take();
+    const int ng = (int)group.size();
+    std::vector<ChainMember> cp[2][NCH];
+    std::vector<std::vector<int>> pending(ng);
+    std::vector<std::vector<std::vector<hipEvent_t>>> waits(ng);
+    int max_lev = 0;
+    for (int i = 0; i < ng; ++i) {
+        Factor& F = *group[i];
+        Plan& P = F.plan;
+        const int nlev = (int)P.levels.size();
+        if (nlev > TAG_LEVELS) throw Error(RSD_EINVAL, "internal: too many levels");
+        max_lev = std::max(max_lev, nlev);
+        pending[i].assign(nlev, 0);
+        waits[i].resize(nlev);
+        for (size_t li = 0; li < P.layouts.size(); ++li) {
+            if (P.layouts[li].idp < 0) continue;
+            const int lev = F.layout_level[li];
+            const int ip = interp_prec(F, lev);
+            int nprob = 1;
+            const int cls = chain_class(F, P.idps[P.layouts[li].idp], ip, nprob);
+            cp[ip][cls].push_back({&F, P.layouts[li].idp, lev, i * TAG_LEVELS + lev});
+            pending[i][lev] += nprob;
+        }
+    }
+    auto chain_stream = [&](int c) { return gc.qs[c == 1 ? 1 : 0]; };
+    QRChain<double> c64[NCH];
+    QRChain<float> c32[NCH];
+    int S = 0;
+    double fl = 0, by = 0;
+    for (int c = 0; c < NCH; ++c) {
+        if (!cp[0][c].empty()) { c64[c].setup(cp[0][c], true, gc.buffers, chain_stream(c)); S = std::max(S, c64[c].S); }
+        if (!cp[1][c].empty()) { c32[c].setup(cp[1][c], true, gc.buffers, chain_stream(c)); S = std::max(S, c32[c].S); }
+        fl += c64[c].flops + c32[c].flops;
+        by += c64[c].bytes + c32[c].bytes;
+    }
+    auto publish = [&](hipEvent_t ev, const std::vector<int>& done) {
+        if (!ev) return;
+        gc.events.push_back(ev);
+        for (int tag : done) {
+            const int i = tag / TAG_LEVELS, lev = tag % TAG_LEVELS;
+            auto& w = waits[i][lev];
+            if (w.empty() || w.back() != ev) w.push_back(ev);
+            --pending[i][lev];
+        }
+    };
+    {
+        ProfScope ps(RSD_PROF_INTERP, gc.qs[1], fl, by);
+        for (int sw = 0; sw < S; ++sw)
+            for (int c = 0; c < NCH; ++c) {
+                std::vector<int> done;
+                publish(c32[c].window(sw, done), done);
+                done.clear();
+                publish(c64[c].window(sw, done), done);
+            }
+        hipEvent_t joined;
+        RSD_HIP(hipEventCreateWithFlags(&joined, hipEventDisableTiming));
+        gc.events.push_back(joined);
+        RSD_HIP(hipEventRecord(joined, gc.qs[0]));
+        RSD_HIP(hipStreamWaitEvent(gc.qs[1], joined, 0));
+    }
+    // the merged levels, on the group's level stream (after every factor's
+    // uploads)
+    hipStream_t ls = gc.qs[2];
+    for (auto* F : group) {
+        hipEvent_t up;
+        RSD_HIP(hipEventCreateWithFlags(&up, hipEventDisableTiming));
+        gc.events.push_back(up);
+        RSD_HIP(hipEventRecord(up, F->stream));
+        RSD_HIP(hipStreamWaitEvent(ls, up, 0));
+    }
+    std::vector<GroupLevel<float>> G32(max_lev);
+    std::vector<GroupLevel<double>> G64(max_lev);
+    for (auto* F : group)
+        for (int t = 0; t < (int)F->plan.levels.size(); ++t) {
+            if (F->level_prec[t]) G32[t].add(*F, F->L32[F->exec_index[t]]);
+            else G64[t].add(*F, F->L64[F->exec_index[t]]);
+        }
+    {
+        std::vector<GemmBatch<float>*> b32;
+        std::vector<GemmBatch<double>*> b64;
+        for (auto& g : G32) g.batches(b32);
+        for (auto& g : G64) g.batches(b64);
+        DevBuf &d32 = gc.buffer(), &d64 = gc.buffer(), &j32 = gc.buffer(), &j64 = gc.buffer();
+        upload_batches<float>(d32, b32, ls);
+        upload_batches<double>(d64, b64, ls);
+        upload_group_gj<float>(j32, G32, ls);
+        upload_group_gj<double>(j64, G64, ls);
+    }
+    for (int t = 0; t < max_lev; ++t) {
+        std::vector<hipEvent_t> w;
+        for (int i = 0; i < ng; ++i) {
+            if (t >= (int)group[i]->plan.levels.size()) continue;
+            if (pending[i][t] != 0) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
+            for (auto e : waits[i][t])
+                if (std::find(w.begin(), w.end(), e) == w.end()) w.push_back(e);
+        }
+        for (auto e : w) RSD_HIP(hipStreamWaitEvent(ls, e, 0));
+        G32[t].run(ls);
+        G64[t].run(ls);
+        for (auto* F : group)
+            if (t + 1 == (int)F->plan.levels.size()) {
+                RSD_HIP(hipEventRecord(F->build_ev[1], ls));
+                RSD_HIP(hipStreamWaitEvent(F->stream, F->build_ev[1], 0));
+            }
     }
 }
 
@@ -1961,20 +2319,49 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
         if (!out || !points || !n_points) throw rsd::Error(RSD_EINVAL, "null argument");
         if (n_inst <= 0) throw rsd::Error(RSD_EINVAL, "n_inst must be positive");
         if (opt && opt->hip_stream) throw rsd::Error(RSD_EINVAL, "batched builds use their own streams");
-        const int32_t window = max_inflight > 0 ? max_inflight : 8;
+        const int32_t group = max_inflight > 0 ? max_inflight : 64;
         fs.resize(n_inst);
-        int32_t done = 0;
-        for (int32_t i = 0; i < n_inst; ++i) {
-            where = i;
-            fs[i] = rsd::build_enqueue(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt);
-            while (i + 1 - done > window) {
-                where = done;
-                rsd::build_finish(*fs[done++]);
+        for (int32_t g0 = 0; g0 < n_inst; g0 += group) {
+            const int32_t g1 = std::min(n_inst, g0 + group);
+            // destroyed (its streams drained) before any factor can be freed
+            rsd::GroupChains chains;
+            // host planning of the group's instances on a few threads
+            {
+                int dev = 0;
+                RSD_HIP(hipGetDevice(&dev));
+                const int nw = (int)std::min<int64_t>(g1 - g0, 8);
+                std::vector<std::exception_ptr> errs(g1 - g0);
+                std::atomic<int32_t> next{g0};
+                auto work = [&]() {
+                    const bool on_dev = hipSetDevice(dev) == hipSuccess;
+                    for (int32_t i = next++; i < g1; i = next++) {
+                        try {
+                            if (!on_dev) throw rsd::HipError("hipSetDevice failed on a planning thread");
+                            fs[i] = rsd::build_prepare(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt);
+                        } catch (...) {
+                            errs[i - g0] = std::current_exception();
+                        }
+                    }
+                };
+                std::vector<std::thread> workers;
+                for (int w = 1; w < nw; ++w) workers.emplace_back(work);
+                work();
+                for (auto& t : workers) t.join();
+                for (int32_t i = g0; i < g1; ++i)
+                    if (errs[i - g0]) {
+                        where = i;
+                        std::rethrow_exception(errs[i - g0]);
+                    }
             }
-        }
-        while (done < n_inst) {
-            where = done;
-            rsd::build_finish(*fs[done++]);
+            std::vector<rsd::Factor*> members;
+            for (int32_t i = g0; i < g1; ++i) members.push_back(fs[i].get());
+            where = g0;
+            rsd::enqueue_group(members, chains);
+            for (int32_t i = g0; i < g1; ++i) {
+                where = i;
+                rsd::build_stats(*fs[i]);
+                rsd::build_finish(*fs[i]);
+            }
         }
         return RSD_OK;
     });

@@ -125,8 +125,10 @@ __global__ void __launch_bounds__(256) proxy_kernel(
     const int* __restrict__ k_of, const int* __restrict__ r_of, const int* __restrict__ zoff,
     const int* __restrict__ zu, const int* __restrict__ zv, const int* __restrict__ xoff,
     const int* __restrict__ xu, const int* __restrict__ xv, const int* __restrict__ geo,
-    KernelDesc kd) {
+    const double* __restrict__ logh_of, KernelDesc kdc) {
     const int pb = blockIdx.y;
+    KernelDesc kd = kdc;
+    if (logh_of) kd.logh = logh_of[pb];   // problems of grids with different spacings
     const int p = p_of[pb], n = k_of[pb] + r_of[pb];
     const int ax = geo[3 * pb], ay = geo[3 * pb + 1], sec = geo[3 * pb + 2];
     T* Ab = A + offA[pb];
@@ -161,12 +163,13 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, c
                                                           const int* __restrict__ orb,
                                                           const int* __restrict__ refl) {
     const SymCombineDesc d = descs[blockIdx.y];
+    TD* __restrict__ Tb = d.dst ? static_cast<TD*>(d.dst) : Ta + d.offT;
     const int k4 = d.k / 4, r4 = d.r / 4;
     const int64_t blk = (int64_t)k4 * r4;
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)d.k * d.r; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % d.k), j = (int)(e / d.k);
         if (!d.sym) {
-            Ta[d.offT + e] = TD(Ts[d.offS + e]);
+            Tb[e] = TD(Ts[d.offS + e]);
             continue;
         }
         const int oi = orb[d.off_sk + i], gi = refl[d.off_sk + i];
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, c
             const TS v = Ts[d.offS + ab * blk + at];
             acc += (__popc(ab & (gi ^ gj)) & 1) ? -v : v;
         }
-        Ta[d.offT + i + (int64_t)j * d.k] = TD(TS(0.25) * acc);
+        Tb[i + (int64_t)j * d.k] = TD(TS(0.25) * acc);
     }
 }
 
@@ -240,12 +243,13 @@ void launch_assemble_F(TD* F, const TS* Fchild, const BoxDev* boxes, const int* 
 template <typename T>
 void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* k_of,
                          const int* r_of, const int* zoff, const int* zu, const int* zv,
-                         const int* xoff, const int* xu, const int* xv, const int* geo, int n_problems,
-                         int max_pn, KernelDesc kd, hipStream_t s) {
+                         const int* xoff, const int* xu, const int* xv, const int* geo,
+                         const double* logh_of, int n_problems, int max_pn, KernelDesc kd,
+                         hipStream_t s) {
     if (n_problems <= 0) return;
     dim3 grid(chunks_for(max_pn), n_problems);
     hipLaunchKernelGGL(proxy_kernel<T>, grid, dim3(256), 0, s, A, offA, p_of, k_of, r_of, zoff, zu,
-                       zv, xoff, xu, xv, geo, kd);
+                       zv, xoff, xu, xv, geo, logh_of, kd);
 }
 
 template <typename TS, typename TD>
@@ -290,11 +294,11 @@ template void launch_assemble_F<float, double>(double*, const float*, const BoxD
                                                const int*, KernelDesc, int, hipStream_t);
 template void launch_proxy_matrix<double>(double*, const int64_t*, const int*, const int*,
                                           const int*, const int*, const int*, const int*,
-                                          const int*, const int*, const int*, const int*, int, int,
-                                          KernelDesc, hipStream_t);
+                                          const int*, const int*, const int*, const int*,
+                                          const double*, int, int, KernelDesc, hipStream_t);
 template void launch_proxy_matrix<float>(float*, const int64_t*, const int*, const int*,
                                          const int*, const int*, const int*, const int*,
-                                         const int*, const int*, const int*, const int*, int, int,
-                                         KernelDesc, hipStream_t);
+                                         const int*, const int*, const int*, const int*,
+                                         const double*, int, int, KernelDesc, hipStream_t);
 
 }  // namespace rsd

@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
 #pragma unroll
         for (int b = 0; b < 4; ++b) Pi[ri + a][cj + b] = p[a][b];
     __syncthreads();
-    if (t == 0 && bad && blockIdx.x == 0) atomicCAS(err, 0, d.box + 1);
+    if (t == 0 && bad && blockIdx.x == 0) atomicCAS(d.err ? d.err : err, 0, d.box + 1);
     // SR = P^{-1} X[piv rows, chunk] on the matrix cores: wave w owns the
     // 32 x 32 block (rows 32 (w / 2), columns 32 (w % 2)) as 2 x 2 MFMA blocks
     // over K = 64.  The MFMA computes the transposed block, so lane l holds
@@ -261,8 +261,10 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
 template <typename T>
 void launch_gj_pivot(const GJDesc<T>* d, int n_desc, int step, int nb, int max_chunks, int* err,
                      hipStream_t s) {
-    if (n_desc <= 0) return;
-    hipLaunchKernelGGL(gj_pivot_kernel<T>, dim3(max_chunks, n_desc), dim3(256), 0, s, d, step, nb, err);
+    constexpr int MAX_Y = 65535;   // grid y limit: blocks beyond it go to further launches
+    for (int o = 0; o < n_desc; o += MAX_Y)
+        hipLaunchKernelGGL(gj_pivot_kernel<T>, dim3(max_chunks, std::min(MAX_Y, n_desc - o)), dim3(256), 0, s,
+                           d + o, step, nb, err);
 }
 
 template void launch_gj_pivot<double>(const GJDesc<double>*, int, int, int, int, int*, hipStream_t);

@@ -328,8 +328,14 @@ def test_batched_build_equals_single_builds():
         x_b, _ = fac.solve(np.asfortranarray(f))
         single = rsd.Factor(p, a, 1e-10)
         x_s, _ = single.solve(np.asfortranarray(f))
-        # same arithmetic in the same order: bitwise equal
-        assert np.array_equal(x_b, x_s)
+        # the interpolation matrices are solved by the same launches' arithmetic
+        # whichever problems share a chain: bitwise equal
+        for box in range(single.stats()["n_boxes"]):
+            info = single.box_info(box)
+            if info["r"] > 0 and info["parent"] >= 0:
+                assert np.array_equal(fac.block(box, 0), single.block(box, 0)), box
+        # the merged level products may split K differently: rounding only
+        assert np.max(np.abs(x_b - x_s)) <= 1e-12 * np.max(np.abs(x_s))
         assert dense.rel_error(x_b, dense.solve(p, f, a)) < 1e-10
         single.close()
         fac.close()
