@@ -286,6 +286,43 @@ private:
     std::map<int, std::vector<hipStream_t>> free_;
 };
 
+// Pinned host blocks for staging large uploads: a copy from pinned memory is
+// asynchronous, one from pageable memory returns only when it is done.  The
+// blocks are kept for reuse (pinning costs about a millisecond per block);
+// a holder returns its block only after the copy has completed.
+class PinnedPool {
+public:
+    static PinnedPool& get() {
+        static PinnedPool* pool = new PinnedPool();   // outlives static destructors
+        return *pool;
+    }
+    void* take(size_t n, size_t& cap) {
+        cap = (n + (size_t(1) << 20) - 1) >> 20 << 20;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.lower_bound(cap);
+            if (it != free_.end() && it->first <= 2 * cap) {
+                void* p = it->second;
+                cap = it->first;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        RSD_HIP(hipHostMalloc(&p, cap, hipHostMallocDefault));
+        return p;
+    }
+    void give(void* p, size_t cap) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.emplace(cap, p);
+    }
+
+private:
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+};
+
 static bool is_device_ptr(const void* p) {
     if (!p) return false;
     hipPointerAttribute_t attr;
@@ -495,15 +532,30 @@ static GemmDesc<T> gdesc(int M, int N, int K, const T* A, int lda, int tA, const
     return d;
 }
 
+// Pinned staging block held until its copy has completed (the holder's
+// owner drains the stream first).
+struct PinnedBlock {
+    void* p = nullptr;
+    size_t cap = 0;
+    PinnedBlock() = default;
+    PinnedBlock(const PinnedBlock&) = delete;
+    PinnedBlock& operator=(const PinnedBlock&) = delete;
+    ~PinnedBlock() { PinnedPool::get().give(p, cap); }
+};
+
 // Uploads every batch of a list into one buffer and fixes their device
 // pointers.  The batches of one list run one after another on one stream, so
-// they share one split-K workspace, sized for the largest.
+// they share one split-K workspace, sized for the largest.  With `pinned`,
+// the tables are staged in a pinned block (filled on `threads` threads) and
+// the upload is asynchronous; the block must stay alive until the stream has
+// passed the copy.
 template <typename T>
-static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStream_t s) {
+static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStream_t s, bool finalized = false,
+                           PinnedBlock* pinned = nullptr, int threads = 1) {
     size_t nd = 0, nt = 0;
     int64_t max_ws = 0;
     for (auto* b : bs) {
-        b->finalize();
+        if (!finalized) b->finalize();
         nd += b->descs.size();
         nt += b->tiles.size() + b->slots.size();
         max_ws = std::max(max_ws, b->ws_elems);
@@ -511,23 +563,52 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
     auto up = [](size_t x, size_t a) { return (x + a - 1) / a * a; };
     const size_t o_tiles = up(nd * sizeof(GemmDesc<T>), 16);
     const size_t o_ws = up(o_tiles + nt * sizeof(TileRef), 256);
-    std::vector<unsigned char> host(o_tiles + nt * sizeof(TileRef));
+    const size_t host_bytes = o_tiles + nt * sizeof(TileRef);
+    std::vector<unsigned char> pageable;
+    unsigned char* host = nullptr;
+    if (pinned) {
+        pinned->p = PinnedPool::get().take(host_bytes, pinned->cap);
+        host = static_cast<unsigned char*>(pinned->p);
+    } else {
+        pageable.resize(host_bytes);
+        host = pageable.data();
+    }
     buf.alloc(o_ws + (size_t)max_ws * sizeof(T));
     unsigned char* base = buf.as<unsigned char>();
-    size_t od = 0, ot = o_tiles;
-    for (auto* b : bs) {
-        std::memcpy(host.data() + od, b->descs.data(), b->descs.size() * sizeof(GemmDesc<T>));
-        b->d_descs = reinterpret_cast<const GemmDesc<T>*>(base + od);
-        od += b->descs.size() * sizeof(GemmDesc<T>);
-        std::memcpy(host.data() + ot, b->tiles.data(), b->tiles.size() * sizeof(TileRef));
-        b->d_tiles = reinterpret_cast<const TileRef*>(base + ot);
-        ot += b->tiles.size() * sizeof(TileRef);
-        std::memcpy(host.data() + ot, b->slots.data(), b->slots.size() * sizeof(TileRef));
-        b->d_slots = reinterpret_cast<const TileRef*>(base + ot);
-        ot += b->slots.size() * sizeof(TileRef);
-        b->d_ws = reinterpret_cast<T*>(base + o_ws);
+    std::vector<size_t> od(bs.size()), ot(bs.size());
+    {
+        size_t d = 0, t = o_tiles;
+        for (size_t i = 0; i < bs.size(); ++i) {
+            od[i] = d;
+            ot[i] = t;
+            d += bs[i]->descs.size() * sizeof(GemmDesc<T>);
+            t += (bs[i]->tiles.size() + bs[i]->slots.size()) * sizeof(TileRef);
+        }
     }
-    RSD_HIP(hipMemcpyAsync(buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    auto fill = [&](size_t i) {
+        GemmBatch<T>* b = bs[i];
+        std::memcpy(host + od[i], b->descs.data(), b->descs.size() * sizeof(GemmDesc<T>));
+        b->d_descs = reinterpret_cast<const GemmDesc<T>*>(base + od[i]);
+        const size_t ts = b->tiles.size() * sizeof(TileRef);
+        std::memcpy(host + ot[i], b->tiles.data(), ts);
+        b->d_tiles = reinterpret_cast<const TileRef*>(base + ot[i]);
+        std::memcpy(host + ot[i] + ts, b->slots.data(), b->slots.size() * sizeof(TileRef));
+        b->d_slots = reinterpret_cast<const TileRef*>(base + ot[i] + ts);
+        b->d_ws = reinterpret_cast<T*>(base + o_ws);
+    };
+    if (threads > 1 && bs.size() > 1) {
+        std::atomic<size_t> next{0};
+        auto work = [&]() {
+            for (size_t i = next++; i < bs.size(); i = next++) fill(i);
+        };
+        std::vector<std::thread> workers;
+        for (int w = 1; w < threads; ++w) workers.emplace_back(work);
+        work();
+        for (auto& t : workers) t.join();
+    } else {
+        for (size_t i = 0; i < bs.size(); ++i) fill(i);
+    }
+    RSD_HIP(hipMemcpyAsync(buf.p, host, host_bytes, hipMemcpyHostToDevice, s));
 }
 
 constexpr int GJ_NB = 64;   // Gauss-Jordan panel width (matches k_gj)
@@ -646,15 +727,25 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 // ----------------------------------------------------------------------------
 // interpolation matrices for every box type (one problem per layout)
 // ----------------------------------------------------------------------------
+// Truncation threshold of the float64 interpolation problems.  With two or
+// more skeleton layers the proxy problems are numerically full rank down to
+// 1e-10 relative (measured: rank = k at every level of the benchmark grids),
+// so they are truncated at min(tol, 1e-10): every column is kept and T is the
+// problem's unique least-squares solution, at least as accurate as one
+// truncated at a looser tol.  With one layer the truncation is active and
+// follows tol.
+static double interp_tol64(const Factor& f) {
+    return f.layers >= 2 ? std::min(f.tol, 1e-10) : f.tol;
+}
+
 // The symmetry split is used where the proxy problems are full rank (float64
-// factors at tol <= 1e-9; measured rank = k at every level of the benchmark
-// grids), so the four sector solutions are the whole problem's unique
-// least-squares solution up to rounding.  Where truncation decides the rank
-// (float32 interpolation, looser tolerances) the whole problem is solved: the
-// window pivoting's truncation test sees only a sub-panel's columns, and on
-// the small sector problems that stops too early.
+// interpolation truncated at 1e-9 or below), so the four sector solutions are
+// the whole problem's unique least-squares solution up to rounding.  Where
+// truncation decides the rank (float32 interpolation, one layer) the whole
+// problem is solved: the window pivoting's truncation test sees only a
+// sub-panel's columns, and on the small sector problems that stops too early.
 static bool split_sym(const Factor& f, const IDProblem& I, int prec) {
-    return I.sym && prec == 0 && f.tol <= 1e-9;
+    return I.sym && prec == 0 && interp_tol64(f) <= 1e-9;
 }
 
 // Precision of the interpolation problems of a level (0 float64, 1 float32).
@@ -966,7 +1057,7 @@ struct QRChain {
         soff[S] = (int)sflat.size();
         upload(*dsolve, sflat, s);
         // a float32 factor cannot resolve pivots below its rounding level
-        qr_tol = std::is_same<T, float>::value ? std::max(f->tol, 1e-6) : f->tol;
+        qr_tol = std::is_same<T, float>::value ? std::max(f->tol, 1e-6) : interp_tol64(*f);
         launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
                                dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
                                dxo.as<int>(), dxu.as<int>(), dxv.as<int>(), dgeo.as<int>(),
@@ -1307,7 +1398,8 @@ static void upload_group_gj(DevBuf& buf, std::vector<GroupLevel<T>>& G, hipStrea
 // Host planning of a build and the uploads of its tables (on the factor's
 // stream); no kernel is launched yet.
 static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, const rsd_kernel* kernel,
-                                             const double* a, double tol, const rsd_options* opt) {
+                                             const double* a, double tol, const rsd_options* opt,
+                                             bool own_tables = true) {
     if (!points || n <= 0) throw Error(RSD_EINVAL, "points must be non-null and n_points > 0");
     if (!(tol > 0) || !std::isfinite(tol)) throw Error(RSD_EINVAL, "tol must be a positive number");
     rsd_options o{};
@@ -1510,10 +1602,13 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     for (auto& L : f->L64) finish_gj<double>(*f, L, f->SR.as<double>(), f->SC.as<double>(), b64, gj64);
     for (auto& L : f->L32) finish_gj<float>(*f, L, f->SR.as<float>(), f->SC.as<float>(), b32, gj32);
     plan_top<double>(*f, f->L64[exec_index[f->top]], f->SR.as<double>(), f->SC.as<double>(), b64);
-    upload_batches<double>(f->gemm64, b64, s);
-    upload_batches<float>(f->gemm32, b32, s);
-    upload_gj<double>(f->gj64, f->L64, s);
-    upload_gj<float>(f->gj32, f->L32, s);
+    // a factor built in a group runs its levels from the group's merged tables
+    if (own_tables) {
+        upload_batches<double>(f->gemm64, b64, s);
+        upload_batches<float>(f->gemm32, b32, s);
+        upload_gj<double>(f->gj64, f->L64, s);
+        upload_gj<float>(f->gj32, f->L32, s);
+    }
     f->exec_index = exec_index;
     f->layout_level = layout_level;
     f->layers = m;
@@ -1760,6 +1855,7 @@ struct GroupChains {
     hipStream_t qs[3] = {nullptr, nullptr, nullptr};   // two chain streams, the level stream
     int dev = 0;
     std::vector<std::unique_ptr<DevBuf>> buffers;
+    PinnedBlock pinned[2];     // staged level tables; returned after the body has drained the streams
     std::vector<hipEvent_t> events;
     DevBuf& buffer() {
         buffers.push_back(std::make_unique<DevBuf>());
@@ -1813,44 +1909,10 @@ static void enqueue_group(const std::vector<Factor*>& group, GroupChains& gc) {
             pending[i][lev] += nprob;
         }
     }
-    auto chain_stream = [&](int c) { return gc.qs[c == 1 ? 1 : 0]; };
-    QRChain<double> c64[NCH];
-    QRChain<float> c32[NCH];
-    int S = 0;
-    double fl = 0, by = 0;
-    for (int c = 0; c < NCH; ++c) {
-        if (!cp[0][c].empty()) { c64[c].setup(cp[0][c], true, gc.buffers, chain_stream(c)); S = std::max(S, c64[c].S); }
-        if (!cp[1][c].empty()) { c32[c].setup(cp[1][c], true, gc.buffers, chain_stream(c)); S = std::max(S, c32[c].S); }
-        fl += c64[c].flops + c32[c].flops;
-        by += c64[c].bytes + c32[c].bytes;
-    }
-    auto publish = [&](hipEvent_t ev, const std::vector<int>& done) {
-        if (!ev) return;
-        gc.events.push_back(ev);
-        for (int tag : done) {
-            const int i = tag / TAG_LEVELS, lev = tag % TAG_LEVELS;
-            auto& w = waits[i][lev];
-            if (w.empty() || w.back() != ev) w.push_back(ev);
-            --pending[i][lev];
-        }
-    };
-    {
-        ProfScope ps(RSD_PROF_INTERP, gc.qs[1], fl, by);
-        for (int sw = 0; sw < S; ++sw)
-            for (int c = 0; c < NCH; ++c) {
-                std::vector<int> done;
-                publish(c32[c].window(sw, done), done);
-                done.clear();
-                publish(c64[c].window(sw, done), done);
-            }
-        hipEvent_t joined;
-        RSD_HIP(hipEventCreateWithFlags(&joined, hipEventDisableTiming));
-        gc.events.push_back(joined);
-        RSD_HIP(hipEventRecord(joined, gc.qs[0]));
-        RSD_HIP(hipStreamWaitEvent(gc.qs[1], joined, 0));
-    }
-    // the merged levels, on the group's level stream (after every factor's
-    // uploads)
+    // the merged levels run on the group's level stream, after every factor's
+    // uploads; their tables are built and staged by a second host thread
+    // while this one sets up the chains, and go up before any window is
+    // enqueued
     hipStream_t ls = gc.qs[2];
     for (auto* F : group) {
         hipEvent_t up;
@@ -1861,39 +1923,122 @@ static void enqueue_group(const std::vector<Factor*>& group, GroupChains& gc) {
     }
     std::vector<GroupLevel<float>> G32(max_lev);
     std::vector<GroupLevel<double>> G64(max_lev);
-    for (auto* F : group)
-        for (int t = 0; t < (int)F->plan.levels.size(); ++t) {
-            if (F->level_prec[t]) G32[t].add(*F, F->L32[F->exec_index[t]]);
-            else G64[t].add(*F, F->L64[F->exec_index[t]]);
-        }
-    {
-        std::vector<GemmBatch<float>*> b32;
-        std::vector<GemmBatch<double>*> b64;
-        for (auto& g : G32) g.batches(b32);
-        for (auto& g : G64) g.batches(b64);
-        DevBuf &d32 = gc.buffer(), &d64 = gc.buffer(), &j32 = gc.buffer(), &j64 = gc.buffer();
-        upload_batches<float>(d32, b32, ls);
-        upload_batches<double>(d64, b64, ls);
-        upload_group_gj<float>(j32, G32, ls);
-        upload_group_gj<double>(j64, G64, ls);
-    }
-    for (int t = 0; t < max_lev; ++t) {
-        std::vector<hipEvent_t> w;
-        for (int i = 0; i < ng; ++i) {
-            if (t >= (int)group[i]->plan.levels.size()) continue;
-            if (pending[i][t] != 0) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
-            for (auto e : waits[i][t])
-                if (std::find(w.begin(), w.end(), e) == w.end()) w.push_back(e);
-        }
-        for (auto e : w) RSD_HIP(hipStreamWaitEvent(ls, e, 0));
-        G32[t].run(ls);
-        G64[t].run(ls);
-        for (auto* F : group)
-            if (t + 1 == (int)F->plan.levels.size()) {
-                RSD_HIP(hipEventRecord(F->build_ev[1], ls));
-                RSD_HIP(hipStreamWaitEvent(F->stream, F->build_ev[1], 0));
+    DevBuf &d32 = gc.buffer(), &d64 = gc.buffer(), &j32 = gc.buffer(), &j64 = gc.buffer();
+    std::exception_ptr table_err;
+    std::thread tables([&] {
+        try {
+            RSD_HIP(hipSetDevice(gc.dev));
+            for (auto* F : group)
+                for (int t = 0; t < (int)F->plan.levels.size(); ++t) {
+                    if (F->level_prec[t]) G32[t].add(*F, F->L32[F->exec_index[t]]);
+                    else G64[t].add(*F, F->L64[F->exec_index[t]]);
+                }
+            std::vector<GemmBatch<float>*> b32;
+            std::vector<GemmBatch<double>*> b64;
+            for (auto& g : G32) g.batches(b32);
+            for (auto& g : G64) g.batches(b64);
+            // tile tables on a few threads (hundreds of thousands of products)
+            std::atomic<size_t> next{0};
+            const size_t n32 = b32.size(), nall = b32.size() + b64.size();
+            std::vector<std::exception_ptr> errs(nall);
+            auto work = [&]() {
+                for (size_t k = next++; k < nall; k = next++) {
+                    try {
+                        if (k < n32) b32[k]->finalize();
+                        else b64[k - n32]->finalize();
+                    } catch (...) {
+                        errs[k] = std::current_exception();
+                    }
+                }
+            };
+            {
+                std::vector<std::thread> workers;
+                for (int w = 1; w < 6; ++w) workers.emplace_back(work);
+                work();
+                for (auto& t : workers) t.join();
             }
+            for (auto& e : errs)
+                if (e) std::rethrow_exception(e);
+            upload_batches<float>(d32, b32, ls, true, &gc.pinned[0], 6);
+            upload_batches<double>(d64, b64, ls, true, &gc.pinned[1], 6);
+            upload_group_gj<float>(j32, G32, ls);
+            upload_group_gj<double>(j64, G64, ls);
+        } catch (...) {
+            table_err = std::current_exception();
+        }
+    });
+    auto chain_stream = [&](int c) { return gc.qs[c == 1 ? 1 : 0]; };
+    QRChain<double> c64[NCH];
+    QRChain<float> c32[NCH];
+    int S = 0;
+    double fl = 0, by = 0;
+    std::exception_ptr setup_err;
+    try {
+        for (int c = 0; c < NCH; ++c) {
+            if (!cp[0][c].empty()) { c64[c].setup(cp[0][c], true, gc.buffers, chain_stream(c)); S = std::max(S, c64[c].S); }
+            if (!cp[1][c].empty()) { c32[c].setup(cp[1][c], true, gc.buffers, chain_stream(c)); S = std::max(S, c32[c].S); }
+            fl += c64[c].flops + c32[c].flops;
+            by += c64[c].bytes + c32[c].bytes;
+        }
+    } catch (...) {
+        setup_err = std::current_exception();
     }
+    tables.join();
+    if (setup_err) std::rethrow_exception(setup_err);
+    if (table_err) std::rethrow_exception(table_err);
+    auto publish = [&](hipEvent_t ev, const std::vector<int>& done) {
+        if (!ev) return;
+        gc.events.push_back(ev);
+        for (int tag : done) {
+            const int i = tag / TAG_LEVELS, lev = tag % TAG_LEVELS;
+            auto& w = waits[i][lev];
+            if (w.empty() || w.back() != ev) w.push_back(ev);
+            --pending[i][lev];
+        }
+    };
+    // Each merged level is enqueued as soon as the windows that solve its box
+    // types are: streams beyond the hardware queues share them in order of
+    // submission, so a level enqueued after all windows would wait behind
+    // every window on a shared queue.
+    int next_t = 0;
+    auto enqueue_ready = [&]() {
+        for (; next_t < max_lev; ++next_t) {
+            const int t = next_t;
+            std::vector<hipEvent_t> w;
+            for (int i = 0; i < ng; ++i) {
+                if (t >= (int)group[i]->plan.levels.size()) continue;
+                if (pending[i][t] != 0) return;
+                for (auto e : waits[i][t])
+                    if (std::find(w.begin(), w.end(), e) == w.end()) w.push_back(e);
+            }
+            for (auto e : w) RSD_HIP(hipStreamWaitEvent(ls, e, 0));
+            G32[t].run(ls);
+            G64[t].run(ls);
+            for (auto* F : group)
+                if (t + 1 == (int)F->plan.levels.size()) {
+                    RSD_HIP(hipEventRecord(F->build_ev[1], ls));
+                    RSD_HIP(hipStreamWaitEvent(F->stream, F->build_ev[1], 0));
+                }
+        }
+    };
+    {
+        ProfScope ps(RSD_PROF_INTERP, gc.qs[1], fl, by);
+        for (int sw = 0; sw < S; ++sw)
+            for (int c = 0; c < NCH; ++c) {
+                std::vector<int> done;
+                publish(c32[c].window(sw, done), done);
+                done.clear();
+                publish(c64[c].window(sw, done), done);
+                enqueue_ready();
+            }
+        hipEvent_t joined;
+        RSD_HIP(hipEventCreateWithFlags(&joined, hipEventDisableTiming));
+        gc.events.push_back(joined);
+        RSD_HIP(hipEventRecord(joined, gc.qs[0]));
+        RSD_HIP(hipStreamWaitEvent(gc.qs[1], joined, 0));
+    }
+    enqueue_ready();
+    if (next_t != max_lev) throw Error(RSD_EINVAL, "internal: interpolation problems left unsolved");
 }
 
 static std::unique_ptr<Factor> build(const double* points, int64_t n, const rsd_kernel* kernel,
@@ -2337,7 +2482,8 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
                     for (int32_t i = next++; i < g1; i = next++) {
                         try {
                             if (!on_dev) throw rsd::HipError("hipSetDevice failed on a planning thread");
-                            fs[i] = rsd::build_prepare(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt);
+                            fs[i] = rsd::build_prepare(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt,
+                                                       false);
                         } catch (...) {
                             errs[i - g0] = std::current_exception();
                         }
