@@ -62,7 +62,8 @@ def cpu_baseline(pts, a, f, budget_s=30.0):
 def batched_measure(torch, rsd, W, reps=2):
     """64 grids of uneven size (side 32..256), float32 factors + float64
     refinement to 1e-8, one right-hand side each: build all (batched call) +
-    solve each; inputs resident in HBM.  Returns a dict for the JSON line."""
+    solve all (batched call); inputs resident in HBM.  Returns a dict for the
+    JSON line."""
     pts, coefs, rhs, tol = W.make_batch()
     dev = torch.device("cuda:0")
     d_pts = [torch.from_numpy(p).to(dev) for p in pts]
@@ -76,11 +77,11 @@ def batched_measure(torch, rsd, W, reps=2):
     def once():
         nonlocal worst
         facs = rsd.build_batched(d_pts, d_a, tol=tol, precision=rsd.RSD_PREC_FP32_REFINE)
-        for fac, f, x in zip(facs, d_f, d_x):
-            st, info = fac.solve_raw(f.data_ptr(), 1, x.data_ptr())
-            if st != rsd.RSD_OK:
-                raise rsd.RsdError(st, lib.rsd_last_error().decode())
-            worst = max(worst, info.rel_residual)
+        st, infos = rsd.solve_batched_raw(facs, [f.data_ptr() for f in d_f], 1, [x.data_ptr() for x in d_x])
+        if st != rsd.RSD_OK:
+            raise rsd.RsdError(st, lib.rsd_last_error().decode())
+        worst = max([worst] + [i.rel_residual for i in infos])
+        for fac in facs:
             fac.close()
 
     once()

@@ -157,6 +157,19 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
 rsd_status rsd_solve(rsd_factor* f, const double* rhs, int64_t nrhs,
                      double* x, rsd_solve_info* info);
 
+/* Solves with several factors in one call: for every instance i,
+ * rsd_solve(factors[i], rhs[i], nrhs, x[i], info ? &info[i] : NULL), with the
+ * same results; the solves run on up to 8 host threads, each factor on its
+ * own stream, so that small solves and their refinement round trips overlap.
+ *   factors, rhs, x  arrays of n entries; the factors must be distinct.
+ *   info             NULL or n entries.
+ * Errors: EINVAL (n <= 0, a null or repeated factor: nothing is solved);
+ * otherwise every instance is attempted and the status of the first failing
+ * one (in instance order) is returned, with rsd_last_error naming it. */
+rsd_status rsd_solve_batched(int32_t n, rsd_factor* const* factors,
+                             const double* const* rhs, int64_t nrhs,
+                             double* const* x, rsd_solve_info* info);
+
 /* y = A x exactly in float64 (direct sum over all pairs, Sec. 5 general
  * formulation), same layouts as rsd_solve.  Used for residuals. */
 rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y);

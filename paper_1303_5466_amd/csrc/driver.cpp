@@ -2528,6 +2528,46 @@ rsd_status rsd_solve(rsd_factor* f, const double* rhs, int64_t nrhs, double* x, 
     });
 }
 
+rsd_status rsd_solve_batched(int32_t n, rsd_factor* const* factors, const double* const* rhs, int64_t nrhs,
+                             double* const* x, rsd_solve_info* info) {
+    std::vector<rsd_status> st(n > 0 ? n : 0, RSD_OK);
+    std::vector<std::string> msg(st.size());
+    const rsd_status pre = guarded([&]() {
+        if (n <= 0) throw rsd::Error(RSD_EINVAL, "n must be positive");
+        if (!factors || !rhs || !x) throw rsd::Error(RSD_EINVAL, "null argument");
+        std::vector<rsd_factor*> sorted(factors, factors + n);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            throw rsd::Error(RSD_EINVAL, "a factor appears twice");
+        for (auto* f : sorted)
+            if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
+        return RSD_OK;
+    });
+    if (pre != RSD_OK) return pre;
+    // every factor has its own stream: a few host threads keep several
+    // solves (and their refinement round trips) in flight at once
+    std::atomic<int32_t> next{0};
+    auto work = [&]() {
+        for (int32_t i = next++; i < n; i = next++) {
+            st[i] = guarded([&]() {
+                return rsd::solve(*factors[i]->impl, rhs[i], nrhs, x[i], info ? &info[i] : nullptr);
+            });
+            if (st[i] != RSD_OK) msg[i] = rsd::g_last_error;
+        }
+    };
+    std::vector<std::thread> workers;
+    for (int w = 1; w < std::min<int32_t>(n, 8); ++w) workers.emplace_back(work);
+    work();
+    for (auto& t : workers) t.join();
+    rsd::g_last_error.clear();
+    for (int32_t i = 0; i < n; ++i)
+        if (st[i] != RSD_OK) {
+            rsd::g_last_error = "instance " + std::to_string(i) + ": " + msg[i];
+            return st[i];
+        }
+    return RSD_OK;
+}
+
 rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
     return guarded([&]() {
         if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");

@@ -85,6 +85,8 @@ EXPORTS = {
                                            C.POINTER(rsd_options), C.c_int32, C.POINTER(C.c_void_p)]),
     "rsd_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                             C.POINTER(rsd_solve_info)]),
+    "rsd_solve_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int64,
+                                    C.POINTER(C.c_void_p), C.POINTER(rsd_solve_info)]),
     "rsd_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "rsd_free": (None, [C.c_void_p]),
     "rsd_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -292,6 +294,18 @@ def build_batched(points_list, a_list=None, tol=1e-10, precision=RSD_PREC_FP64, 
     _check(lib.rsd_build_factor_batched(n_inst, pts_p, npts, C.byref(kd), a_p, tol, C.byref(opt),
                                         max_inflight, out))
     return [Factor._adopt(C.c_void_p(out[i]), int(npts[i])) for i in range(n_inst)]
+
+
+def solve_batched_raw(factors, rhs_ptrs, nrhs, x_ptrs):
+    """rsd_solve_batched over raw pointers (host or device), one per factor;
+    returns (status, list of rsd_solve_info)."""
+    n = len(factors)
+    fs = (C.c_void_p * n)(*[f.handle.value for f in factors])
+    rp = (C.c_void_p * n)(*rhs_ptrs)
+    xp = (C.c_void_p * n)(*x_ptrs)
+    infos = (rsd_solve_info * n)()
+    st = load().rsd_solve_batched(n, fs, rp, nrhs, xp, infos)
+    return st, list(infos)
 
 
 class Server:

@@ -352,6 +352,24 @@ def test_batched_build_fp32_refine_and_host_device_mix():
         fac.close()
 
 
+def test_batched_solve_equals_single_solves():
+    pts, coefs, rhs, tol = W.make_batch(n_inst=6, seed=7, side_lo=16, side_hi=70)
+    facs = rsd.build_batched(pts, coefs, tol=tol, precision=rsd.RSD_PREC_FP32_REFINE)
+    F = [np.asfortranarray(np.stack([f, 2 * f], axis=1)) for f in rhs]
+    X = [np.zeros_like(f) for f in F]
+    st, infos = rsd.solve_batched_raw(facs, [f.ctypes.data for f in F], 2, [x.ctypes.data for x in X])
+    assert st == rsd.RSD_OK
+    for fac, f, x, info in zip(facs, F, X, infos):
+        x1, info1 = fac.solve(f)
+        assert np.array_equal(x, x1)          # same solve, same bits
+        assert info.refine_iters == info1.refine_iters and info.rel_residual <= tol
+    # a repeated factor is refused before any solve
+    st, _ = rsd.solve_batched_raw([facs[0], facs[0]], [F[0].ctypes.data] * 2, 2, [X[0].ctypes.data] * 2)
+    assert st == rsd.RSD_EINVAL
+    for fac in facs:
+        fac.close()
+
+
 def test_batched_build_reports_failing_instance():
     good = W.grid_points(16)
     bad = W.grid_points(16)[:-3]          # not a complete grid
