@@ -101,6 +101,30 @@ void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles
                  int reduce, hipStream_t s, int role);
 
 // generation / assembly
+// One factor of a batch group for the merged assembly launches: its arenas
+// (F of the level's precision, Fc of the children's) and plan tables.
+struct AsmInst {
+    void* F;
+    const void* Fc;
+    const BoxDev* boxes;
+    const LayoutDev* layouts;
+    const int* lu;
+    const int* lv;
+    const int* src_c;
+    const int* src_i;
+    KernelDesc kd;
+};
+struct GroupItem {
+    int inst, box;    // factor of the group, box of that factor
+};
+template <typename T>
+void launch_leaf_F_group(const AsmInst* insts, const GroupItem* items, int n_items, int max_m, hipStream_t s);
+template <typename TS, typename TD>
+void launch_assemble_F_group(const AsmInst* insts, const GroupItem* items, int n_items, int max_m,
+                             hipStream_t s);
+template <typename T>
+void launch_transpose_group(const AsmInst* insts, const GroupItem* items, int n_items, int max_k, int max_r,
+                            hipStream_t s);
 template <typename T>
 void launch_leaf_F(T* F, const BoxDev* boxes, const int* box_ids, int n_boxes,
                    const LayoutDev* layouts, const int* lu, const int* lv, KernelDesc kd,

@@ -1322,9 +1322,40 @@ struct GroupLevel {
     const GJDesc<T>* d_gj = nullptr;
     const GJDesc<T>* d_topgj = nullptr;
     int gj_steps = 0, topgj_steps = 0, max_chunks = 0, top_chunks = 0;
+    // assembly and transposes: per-member tables, and the boxes by the
+    // precision of their children (0 float64, 1 float32; leaves under 0)
+    int level = 0, max_m = 0, max_k = 0, max_r = 0;
+    std::vector<AsmInst> ainst;
+    std::vector<GroupItem> items[2], titems;
+    const AsmInst* d_ainst = nullptr;
+    const GroupItem* d_items[2] = {nullptr, nullptr};
+    const GroupItem* d_titems = nullptr;
 
     void add(Factor& F, LevelExec<T>& L) {
         members.push_back({&F, &L});
+        {
+            const int inst = (int)ainst.size();
+            const int child_prec = L.level > 0 ? F.level_prec[L.level - 1] : 0;
+            AsmInst a;
+            a.F = Fbase<T>(F);
+            a.Fc = L.level == 0 ? nullptr : (child_prec ? F.F32.p : F.F64.p);
+            a.boxes = F.d_boxes.as<BoxDev>();
+            a.layouts = F.d_layouts.as<LayoutDev>();
+            a.lu = F.d_lu.as<int>();
+            a.lv = F.d_lv.as<int>();
+            a.src_c = F.d_srcc.as<int>();
+            a.src_i = F.d_srci.as<int>();
+            a.kd = F.kd;
+            ainst.push_back(a);
+            for (int id : L.ids) {
+                items[child_prec].push_back({inst, id});
+                if (!L.g_sr.empty()) titems.push_back({inst, id});
+            }
+            level = L.level;
+            max_m = std::max(max_m, L.max_m);
+            max_k = std::max(max_k, L.max_k);
+            max_r = std::max(max_r, L.max_r);
+        }
         for (auto& d : L.g_sr.descs) g_sr.add(d);
         for (auto& d : L.g_rr.descs) g_rr.add(d);
         for (auto& d : L.g_E.descs) g_E.add(d);
@@ -1359,10 +1390,27 @@ struct GroupLevel {
     void run(hipStream_t s) {
         if (members.empty()) return;
         int* err0 = members.front().first->d_err.template as<int>();
-        for (auto& m : members) run_assembly<T>(*m.first, *m.second, s);
+        {
+            ProfScope ps(RSD_PROF_ASSEMBLY, s);
+            if (level == 0) {
+                launch_leaf_F_group<T>(d_ainst, d_items[0], (int)items[0].size(), max_m, s);
+            } else {
+                if (!items[1].empty())
+                    launch_assemble_F_group<float, T>(d_ainst, d_items[1], (int)items[1].size(), max_m, s);
+                if constexpr (std::is_same<T, double>::value) {
+                    if (!items[0].empty())
+                        launch_assemble_F_group<double, double>(d_ainst, d_items[0], (int)items[0].size(), max_m, s);
+                } else if (!items[0].empty()) {
+                    throw Error(RSD_EINVAL, "internal: float32 level above a float64 level");
+                }
+            }
+        }
         g_sr.run(s);
         g_rr.run(s);
-        for (auto& m : members) run_transpose<T>(*m.first, *m.second, s);
+        if (!titems.empty()) {
+            ProfScope ps(RSD_PROF_ASSEMBLY, s);
+            launch_transpose_group<T>(d_ainst, d_titems, (int)titems.size(), max_k, max_r, s);
+        }
         for (int st = 0; st < gj_steps; ++st) {
             {
                 ProfScope ps(RSD_PROF_GJ_PIVOT, s);
@@ -1380,6 +1428,30 @@ struct GroupLevel {
         }
     }
 };
+
+template <typename T>
+static void upload_group_asm(DevBuf& ibuf, DevBuf& tbuf, std::vector<GroupLevel<T>>& G, hipStream_t s) {
+    std::vector<AsmInst> insts;
+    std::vector<GroupItem> items;
+    for (auto& g : G) {
+        insts.insert(insts.end(), g.ainst.begin(), g.ainst.end());
+        for (int c = 0; c < 2; ++c) items.insert(items.end(), g.items[c].begin(), g.items[c].end());
+        items.insert(items.end(), g.titems.begin(), g.titems.end());
+    }
+    upload(ibuf, insts, s);
+    upload(tbuf, items, s);
+    size_t oi = 0, ot = 0;
+    for (auto& g : G) {
+        g.d_ainst = ibuf.as<AsmInst>() + oi;
+        oi += g.ainst.size();
+        for (int c = 0; c < 2; ++c) {
+            g.d_items[c] = tbuf.as<GroupItem>() + ot;
+            ot += g.items[c].size();
+        }
+        g.d_titems = tbuf.as<GroupItem>() + ot;
+        ot += g.titems.size();
+    }
+}
 
 template <typename T>
 static void upload_group_gj(DevBuf& buf, std::vector<GroupLevel<T>>& G, hipStream_t s) {
@@ -1955,6 +2027,7 @@ static void enqueue_group(const std::vector<Factor*>& group, GroupChains& gc) {
     std::vector<GroupLevel<float>> G32(max_lev);
     std::vector<GroupLevel<double>> G64(max_lev);
     DevBuf &d32 = gc.buffer(), &d64 = gc.buffer(), &j32 = gc.buffer(), &j64 = gc.buffer();
+    DevBuf &ai32 = gc.buffer(), &at32 = gc.buffer(), &ai64 = gc.buffer(), &at64 = gc.buffer();
     std::exception_ptr table_err;
     std::thread tables([&] {
         try {
@@ -1994,6 +2067,8 @@ static void enqueue_group(const std::vector<Factor*>& group, GroupChains& gc) {
             upload_batches<double>(d64, b64, ls, true, &gc.pinned[1], 6);
             upload_group_gj<float>(j32, G32, ls);
             upload_group_gj<double>(j64, G64, ls);
+            upload_group_asm<float>(ai32, at32, G32, ls);
+            upload_group_asm<double>(ai64, at64, G64, ls);
         } catch (...) {
             table_err = std::current_exception();
         }

@@ -48,13 +48,13 @@ __device__ inline T diag_val(const KernelDesc& kd, int64_t g) {
     return T((kd.a ? kd.a[g] : 1.0) + kd.sc_re);
 }
 
+// Leaf block D_i of one box: kernel entries off the diagonal, the
+// identity coefficient plus the self-cell integral on it.
 template <typename T>
-__global__ void __launch_bounds__(256) leaf_F_kernel(T* __restrict__ F, const BoxDev* __restrict__ boxes,
-                                                      const int* __restrict__ box_ids,
-                                                      const LayoutDev* __restrict__ layouts,
-                                                      const int* __restrict__ lu,
-                                                      const int* __restrict__ lv, KernelDesc kd) {
-    const BoxDev b = boxes[box_ids[blockIdx.y]];
+__device__ inline void leaf_F_box(T* __restrict__ F, const BoxDev* __restrict__ boxes, int box,
+                                  const LayoutDev* __restrict__ layouts, const int* __restrict__ lu,
+                                  const int* __restrict__ lv, const KernelDesc& kd) {
+    const BoxDev b = boxes[box];
     const LayoutDev L = layouts[b.layout];
     const int m = L.k + L.r;
     T* Fb = F + b.offF;
@@ -78,13 +78,34 @@ __global__ void __launch_bounds__(256) leaf_F_kernel(T* __restrict__ F, const Bo
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) leaf_F_kernel(T* __restrict__ F, const BoxDev* __restrict__ boxes,
+                                                      const int* __restrict__ box_ids,
+                                                      const LayoutDev* __restrict__ layouts,
+                                                      const int* __restrict__ lu,
+                                                      const int* __restrict__ lv, KernelDesc kd) {
+    leaf_F_box<T>(F, boxes, box_ids[blockIdx.y], layouts, lu, lv, kd);
+}
+
+// the boxes of several factors (a batch group): item y = (factor, box)
+template <typename T>
+__global__ void __launch_bounds__(256) leaf_F_group_kernel(const AsmInst* __restrict__ insts,
+                                                            const GroupItem* __restrict__ items) {
+    const GroupItem it = items[blockIdx.y];
+    const AsmInst& I = insts[it.inst];
+    leaf_F_box<T>(static_cast<T*>(I.F), I.boxes, it.box, I.layouts, I.lu, I.lv, I.kd);
+}
+
+// Parent block of one box: the children's E blocks where both points come
+// from one child, generated kernel entries where they come from different
+// children.
 template <typename TS, typename TD>
-__global__ void __launch_bounds__(256) assemble_kernel(
-    TD* __restrict__ F, const TS* __restrict__ Fc, const BoxDev* __restrict__ boxes,
-    const int* __restrict__ box_ids, const LayoutDev* __restrict__ layouts,
-    const int* __restrict__ lu, const int* __restrict__ lv, const int* __restrict__ src_c,
-    const int* __restrict__ src_i, KernelDesc kd) {
-    const BoxDev b = boxes[box_ids[blockIdx.y]];
+__device__ inline void assemble_box(TD* __restrict__ F, const TS* __restrict__ Fc,
+                                    const BoxDev* __restrict__ boxes, int box,
+                                    const LayoutDev* __restrict__ layouts, const int* __restrict__ lu,
+                                    const int* __restrict__ lv, const int* __restrict__ src_c,
+                                    const int* __restrict__ src_i, const KernelDesc& kd) {
+    const BoxDev b = boxes[box];
     const LayoutDev L = layouts[b.layout];
     const int m = L.k + L.r;
     const BoxDev c0 = boxes[b.child0], c1 = boxes[b.child1];
@@ -112,6 +133,24 @@ __global__ void __launch_bounds__(256) assemble_kernel(
         }
         Fb[e] = val;
     }
+}
+
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(256) assemble_kernel(
+    TD* __restrict__ F, const TS* __restrict__ Fc, const BoxDev* __restrict__ boxes,
+    const int* __restrict__ box_ids, const LayoutDev* __restrict__ layouts,
+    const int* __restrict__ lu, const int* __restrict__ lv, const int* __restrict__ src_c,
+    const int* __restrict__ src_i, KernelDesc kd) {
+    assemble_box<TS, TD>(F, Fc, boxes, box_ids[blockIdx.y], layouts, lu, lv, src_c, src_i, kd);
+}
+
+template <typename TS, typename TD>
+__global__ void __launch_bounds__(256) assemble_group_kernel(const AsmInst* __restrict__ insts,
+                                                              const GroupItem* __restrict__ items) {
+    const GroupItem it = items[blockIdx.y];
+    const AsmInst& I = insts[it.inst];
+    assemble_box<TS, TD>(static_cast<TD*>(I.F), static_cast<const TS*>(I.Fc), I.boxes, it.box, I.layouts,
+                         I.lu, I.lv, I.src_c, I.src_i, I.kd);
 }
 
 // Proxy matrix [K(Z, X^sk) | K(Z, X^rs)] of every interpolation problem
@@ -185,11 +224,10 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, c
     }
 }
 
-// F'_rs = (F'_sr)^T for every box of a level (32 x 32 tiles through LDS)
+// F'_rs = (F'_sr)^T for one box (32 x 32 tiles through LDS)
 template <typename T>
-__global__ void __launch_bounds__(256) transpose_kernel(T* __restrict__ F, const BoxDev* __restrict__ boxes,
-                                                         const int* __restrict__ ids) {
-    const BoxDev b = boxes[ids[blockIdx.y]];
+__device__ inline void transpose_box(T* __restrict__ F, const BoxDev* __restrict__ boxes, int box) {
+    const BoxDev b = boxes[box];
     const int k = b.k, r = b.r, m = k + r;
     __shared__ T tile[32][33];
     const int tiles_k = (k + 31) / 32, tiles_r = (r + 31) / 32;
@@ -209,6 +247,19 @@ __global__ void __launch_bounds__(256) transpose_kernel(T* __restrict__ F, const
             if (gi < k && gj < r) Fb[(k + gj) + (int64_t)gi * m] = tile[j][i];
         }
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) transpose_kernel(T* __restrict__ F, const BoxDev* __restrict__ boxes,
+                                                         const int* __restrict__ ids) {
+    transpose_box<T>(F, boxes, ids[blockIdx.y]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) transpose_group_kernel(const AsmInst* __restrict__ insts,
+                                                               const GroupItem* __restrict__ items) {
+    const GroupItem it = items[blockIdx.y];
+    transpose_box<T>(static_cast<T*>(insts[it.inst].F), insts[it.inst].boxes, it.box);
 }
 
 inline int chunks_for(int64_t elems) {
@@ -276,6 +327,44 @@ void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes,
     if (chunks > 1024) chunks = 1024;
     hipLaunchKernelGGL(transpose_kernel<T>, dim3(chunks, n_boxes), dim3(256), 0, s, F, boxes, ids);
 }
+// grid y is limited to 65535: longer item lists go to further launches
+constexpr int GROUP_MAX_Y = 65535;
+
+template <typename T>
+void launch_leaf_F_group(const AsmInst* insts, const GroupItem* items, int n_items, int max_m, hipStream_t s) {
+    for (int o = 0; o < n_items; o += GROUP_MAX_Y) {
+        dim3 grid(chunks_for((int64_t)max_m * max_m), std::min(GROUP_MAX_Y, n_items - o));
+        hipLaunchKernelGGL(leaf_F_group_kernel<T>, grid, dim3(256), 0, s, insts, items + o);
+    }
+}
+
+template <typename TS, typename TD>
+void launch_assemble_F_group(const AsmInst* insts, const GroupItem* items, int n_items, int max_m,
+                             hipStream_t s) {
+    for (int o = 0; o < n_items; o += GROUP_MAX_Y) {
+        dim3 grid(chunks_for((int64_t)max_m * max_m), std::min(GROUP_MAX_Y, n_items - o));
+        hipLaunchKernelGGL((assemble_group_kernel<TS, TD>), grid, dim3(256), 0, s, insts, items + o);
+    }
+}
+
+template <typename T>
+void launch_transpose_group(const AsmInst* insts, const GroupItem* items, int n_items, int max_k, int max_r,
+                            hipStream_t s) {
+    if (max_k <= 0 || max_r <= 0) return;
+    const int chunks = std::min(((max_k + 31) / 32) * ((max_r + 31) / 32), 1024);
+    for (int o = 0; o < n_items; o += GROUP_MAX_Y)
+        hipLaunchKernelGGL(transpose_group_kernel<T>, dim3(chunks, std::min(GROUP_MAX_Y, n_items - o)), dim3(256),
+                           0, s, insts, items + o);
+}
+
+template void launch_leaf_F_group<double>(const AsmInst*, const GroupItem*, int, int, hipStream_t);
+template void launch_leaf_F_group<float>(const AsmInst*, const GroupItem*, int, int, hipStream_t);
+template void launch_assemble_F_group<double, double>(const AsmInst*, const GroupItem*, int, int, hipStream_t);
+template void launch_assemble_F_group<float, float>(const AsmInst*, const GroupItem*, int, int, hipStream_t);
+template void launch_assemble_F_group<float, double>(const AsmInst*, const GroupItem*, int, int, hipStream_t);
+template void launch_transpose_group<double>(const AsmInst*, const GroupItem*, int, int, int, hipStream_t);
+template void launch_transpose_group<float>(const AsmInst*, const GroupItem*, int, int, int, hipStream_t);
+
 template void launch_transpose_sr<double>(double*, const BoxDev*, const int*, int, int, int, hipStream_t);
 template void launch_transpose_sr<float>(float*, const BoxDev*, const int*, int, int, int, hipStream_t);
 

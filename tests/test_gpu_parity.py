@@ -370,6 +370,38 @@ def test_batched_solve_equals_single_solves():
         fac.close()
 
 
+def test_batched_build_reports_singular_instance():
+    # the merged Gauss-Jordan launches flag the failing block's own factor
+    good16, good8 = W.grid_points(16), W.grid_points(8)
+    bad = W.grid_points(2)
+    a_bad = np.full(len(bad), -nystrom.self_cell_laplace(1 / 2))
+    with pytest.raises(rsd.RsdError) as ei:
+        rsd.build_batched([good16, bad, good8], [W.coef_sine(good16), a_bad, W.coef_sine(good8)],
+                          tol=1e-10, leaf_side=2)
+    assert ei.value.status == rsd.RSD_ESINGULAR
+    assert "instance 1" in str(ei.value)
+
+
+def test_plan_reuse_keeps_factors_independent():
+    # a cached plan is copied into each factor: a build without the symmetry
+    # split in between must not change a later build of the same shape
+    pts = W.grid_points(48)
+    a = W.coef_sine(pts)
+    f1 = rsd.Factor(pts, a, 1e-10)
+    f2 = rsd.Factor(pts, a, 1e-10, flags=rsd.RSD_FLAG_NO_SYMMETRY)
+    f3 = rsd.Factor(pts, a, 1e-10)
+    for b in range(f1.stats()["n_boxes"]):
+        info = f1.box_info(b)
+        if info["r"] > 0 and info["parent"] >= 0:
+            assert np.array_equal(f1.block(b, 0), f3.block(b, 0)), b
+    f = W.rhs_normal(len(pts), 1, 5)
+    x1, _ = f1.solve(f)
+    x3, _ = f3.solve(f)
+    assert np.array_equal(x1, x3)
+    for fac in (f1, f2, f3):
+        fac.close()
+
+
 def test_batched_build_reports_failing_instance():
     good = W.grid_points(16)
     bad = W.grid_points(16)[:-3]          # not a complete grid
