@@ -685,6 +685,7 @@ struct Factor {
     std::vector<BoxDev> hboxes;
     std::vector<LayoutDev> hlayouts;
     std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
+    int* h_flag = nullptr;          // pinned word for the right-hand side check
     std::vector<int> exec_index;    // level -> index into L64 or L32
     std::vector<int> layout_level;  // layout -> level of its boxes
     double gemm_flops = 0;          // flops of the level products
@@ -704,6 +705,7 @@ struct Factor {
                               &d_flag, &F64, &F32, &T64, &T32, &SR, &SC, &gemm64, &gemm32, &gj64, &gj32})
                 b->release();
         }
+        if (h_flag) (void)hipHostFree(h_flag);
         for (auto e : tmp_events) (void)hipEventDestroy(e);
         for (auto e : build_ev)
             if (e) (void)hipEventDestroy(e);
@@ -2321,15 +2323,21 @@ static void matvec_grid(Factor& f, const double* x, double* y, int nrhs) {
     launch_matvec(y, x, nrhs, f.d_table.as<double>(), f.nx, f.ny, f.kd, 0, f.stream);
 }
 
-static void check_finite_dev(Factor& f, const double* x, int64_t n) {
+// Enqueues the finiteness check of a right-hand side; its flag reaches a
+// pinned host word asynchronously, read by finite_check_failed after the
+// next synchronisation of the factor's stream (so the check costs no round
+// trip of its own).
+static void start_finite_check(Factor& f, const double* x, int64_t n) {
     DevBuf& flag = f.d_flag;
     if (!flag.p) flag.alloc(sizeof(int));
+    if (!f.h_flag) RSD_HIP(hipHostMalloc(reinterpret_cast<void**>(&f.h_flag), sizeof(int), hipHostMallocDefault));
     RSD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), f.stream));
     launch_check_finite(x, n, flag.as<int>(), f.stream);
-    int h = 0;
-    RSD_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, f.stream));
-    RSD_HIP(hipStreamSynchronize(f.stream));
-    if (h) throw Error(RSD_EINVAL, "non-finite value in the right-hand side");
+    RSD_HIP(hipMemcpyAsync(f.h_flag, flag.p, sizeof(int), hipMemcpyDeviceToHost, f.stream));
+}
+
+static void finite_check_failed(const Factor& f) {
+    if (*f.h_flag) throw Error(RSD_EINVAL, "non-finite value in the right-hand side");
 }
 
 static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, rsd_solve_info* info) {
@@ -2348,7 +2356,7 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
         RSD_HIP(hipMemcpyAsync(sp.in.p, rhs, tot * sizeof(double), hipMemcpyHostToDevice, s));
         fin = sp.in.as<double>();
     }
-    check_finite_dev(f, fin, tot);
+    start_finite_check(f, fin, tot);
     double* xo = xdev ? x : sp.out.as<double>();
     rsd_status status = RSD_OK;
     if (f.max_refine <= 0) {
@@ -2378,6 +2386,7 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
             launch_col_norms2(nb.as<double>() + nrhs, rg, f.N, (int)nrhs, s);
             RSD_HIP(hipMemcpyAsync(rn.data(), nb.as<double>() + nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
             RSD_HIP(hipStreamSynchronize(s));
+            finite_check_failed(f);
             worst = 0;
             for (int c = 0; c < nrhs; ++c) {
                 const double rel = fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]);
@@ -2395,6 +2404,7 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
     }
     if (!xdev) RSD_HIP(hipMemcpyAsync(x, xo, tot * sizeof(double), hipMemcpyDeviceToHost, s));
     RSD_HIP(hipStreamSynchronize(s));
+    finite_check_failed(f);
     if (status == RSD_ENOCONV)
         throw Error(RSD_ENOCONV, "iterative refinement did not reach the tolerance");
     return status;
