@@ -297,7 +297,7 @@ public:
         return *pool;
     }
     void* take(size_t n, size_t& cap) {
-        cap = (n + (size_t(1) << 20) - 1) >> 20 << 20;
+        cap = std::max<size_t>((n + (size_t(1) << 20) - 1) >> 20 << 20, size_t(1) << 20);
         {
             std::lock_guard<std::mutex> lk(mu_);
             auto it = free_.lower_bound(cap);
@@ -540,7 +540,12 @@ struct PinnedBlock {
     PinnedBlock() = default;
     PinnedBlock(const PinnedBlock&) = delete;
     PinnedBlock& operator=(const PinnedBlock&) = delete;
-    ~PinnedBlock() { PinnedPool::get().give(p, cap); }
+    ~PinnedBlock() { release(); }
+    void release() {
+        PinnedPool::get().give(p, cap);
+        p = nullptr;
+        cap = 0;
+    }
 };
 
 // Uploads every batch of a list into one buffer and fixes their device
@@ -566,7 +571,7 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
     const size_t host_bytes = o_tiles + nt * sizeof(TileRef);
     std::vector<unsigned char> pageable;
     unsigned char* host = nullptr;
-    if (pinned) {
+    if (pinned && host_bytes > 0) {
         pinned->p = PinnedPool::get().take(host_bytes, pinned->cap);
         host = static_cast<unsigned char*>(pinned->p);
     } else {
@@ -608,7 +613,7 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
     } else {
         for (size_t i = 0; i < bs.size(); ++i) fill(i);
     }
-    RSD_HIP(hipMemcpyAsync(buf.p, host, host_bytes, hipMemcpyHostToDevice, s));
+    if (host_bytes > 0) RSD_HIP(hipMemcpyAsync(buf.p, host, host_bytes, hipMemcpyHostToDevice, s));
 }
 
 constexpr int GJ_NB = 64;   // Gauss-Jordan panel width (matches k_gj)
@@ -686,6 +691,9 @@ struct Factor {
     std::vector<LayoutDev> hlayouts;
     std::map<int, std::unique_ptr<SolvePlan>> solve_plans;
     int* h_flag = nullptr;          // pinned word for the right-hand side check
+    std::vector<GemmBatch<double>*> tables64;   // the level products, uploaded by enqueue_single
+    std::vector<GemmBatch<float>*> tables32;
+    PinnedBlock staged[4];          // their pinned staging, returned by build_finish
     std::vector<int> exec_index;    // level -> index into L64 or L32
     std::vector<int> layout_level;  // layout -> level of its boxes
     double gemm_flops = 0;          // flops of the level products
@@ -1233,7 +1241,7 @@ static void plan_top(Factor& f, LevelExec<T>& L, T* SRb, T* SCb, std::vector<Gem
 }
 
 template <typename T>
-static void upload_gj(DevBuf& buf, std::vector<LevelExec<T>>& Ls, hipStream_t s) {
+static void upload_gj(DevBuf& buf, std::vector<LevelExec<T>>& Ls, hipStream_t s, PinnedBlock* pinned = nullptr) {
     size_t n = 0;
     for (auto& L : Ls) n += L.gj.size() + L.topgj.size();
     std::vector<GJDesc<T>> host;
@@ -1241,8 +1249,16 @@ static void upload_gj(DevBuf& buf, std::vector<LevelExec<T>>& Ls, hipStream_t s)
     for (auto& L : Ls) { host.insert(host.end(), L.gj.begin(), L.gj.end()); }
     for (auto& L : Ls) { host.insert(host.end(), L.topgj.begin(), L.topgj.end()); }
     buf.alloc(std::max<size_t>(1, host.size()) * sizeof(GJDesc<T>));
-    if (!host.empty())
-        RSD_HIP(hipMemcpyAsync(buf.p, host.data(), host.size() * sizeof(GJDesc<T>), hipMemcpyHostToDevice, s));
+    if (!host.empty()) {
+        const size_t bytes = host.size() * sizeof(GJDesc<T>);
+        const void* src = host.data();
+        if (pinned) {
+            pinned->p = PinnedPool::get().take(bytes, pinned->cap);
+            std::memcpy(pinned->p, src, bytes);
+            src = pinned->p;
+        }
+        RSD_HIP(hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, s));
+    }
     size_t o = 0;
     for (auto& L : Ls) { L.d_gj = buf.as<GJDesc<T>>() + o; o += L.gj.size(); }
     for (auto& L : Ls) { L.d_topgj = buf.as<GJDesc<T>>() + o; o += L.topgj.size(); }
@@ -1503,8 +1519,7 @@ static Plan cached_plan(int64_t nx, int64_t ny, int leaf, int m) {
 // Host planning of a build and the uploads of its tables (on the factor's
 // stream); no kernel is launched yet.
 static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, const rsd_kernel* kernel,
-                                             const double* a, double tol, const rsd_options* opt,
-                                             bool own_tables = true) {
+                                             const double* a, double tol, const rsd_options* opt) {
     if (!points || n <= 0) throw Error(RSD_EINVAL, "points must be non-null and n_points > 0");
     if (!(tol > 0) || !std::isfinite(tol)) throw Error(RSD_EINVAL, "tol must be a positive number");
     rsd_options o{};
@@ -1707,13 +1722,10 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     for (auto& L : f->L64) finish_gj<double>(*f, L, f->SR.as<double>(), f->SC.as<double>(), b64, gj64);
     for (auto& L : f->L32) finish_gj<float>(*f, L, f->SR.as<float>(), f->SC.as<float>(), b32, gj32);
     plan_top<double>(*f, f->L64[exec_index[f->top]], f->SR.as<double>(), f->SC.as<double>(), b64);
-    // a factor built in a group runs its levels from the group's merged tables
-    if (own_tables) {
-        upload_batches<double>(f->gemm64, b64, s);
-        upload_batches<float>(f->gemm32, b32, s);
-        upload_gj<double>(f->gj64, f->L64, s);
-        upload_gj<float>(f->gj32, f->L32, s);
-    }
+    // uploaded by enqueue_single once the first interpolation window is
+    // under way (a factor built in a group runs from the group's tables)
+    f->tables64 = b64;
+    f->tables32 = b32;
     f->exec_index = exec_index;
     f->layout_level = layout_level;
     f->layers = m;
@@ -1841,6 +1853,13 @@ static void enqueue_single(Factor& fr) {
             done.clear();
             publish(c64[0].window(0, done), done);
         }
+        // then the level tables, staged in pinned memory (a copy from
+        // pageable memory would wait for the kernels of a stream sharing the
+        // hardware queue)
+        upload_batches<double>(f->gemm64, f->tables64, s, false, &f->staged[0], 1);
+        upload_batches<float>(f->gemm32, f->tables32, s, false, &f->staged[1], 1);
+        upload_gj<double>(f->gj64, f->L64, s, &f->staged[2]);
+        upload_gj<float>(f->gj32, f->L32, s, &f->staged[3]);
         std::exception_ptr chain_err;
         const int dev = f->device;
         std::thread chains([&] {
@@ -1934,6 +1953,7 @@ static void build_finish(Factor& f) {
         IdleScope idle;     // the build's streams have drained
         f.scratch.clear();
     }
+    for (auto& b : f.staged) b.release();
     for (auto e : f.tmp_events) (void)hipEventDestroy(e);
     f.tmp_events.clear();
     float ms = 0;
@@ -2598,8 +2618,7 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
                     for (int32_t i = next++; i < g1; i = next++) {
                         try {
                             if (!on_dev) throw rsd::HipError("hipSetDevice failed on a planning thread");
-                            fs[i] = rsd::build_prepare(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt,
-                                                       false);
+                            fs[i] = rsd::build_prepare(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt);
                         } catch (...) {
                             errs[i - g0] = std::current_exception();
                         }
