@@ -1945,7 +1945,21 @@ static std::unique_ptr<Factor> build_enqueue(const double* points, int64_t n, co
 
 // Waits for an enqueued build, releases its temporaries and reports a singular
 // pivot block if one was met.
-static void build_finish(Factor& f) {
+// Right-hand-side count of the most recent solve.  While a build runs on the
+// device, the host prepares the new factor's solve plan for that count (a
+// repeated workload then finds it ready); a failure there is left to the
+// first solve to report.
+static std::atomic<int> g_last_nrhs{0};
+static SolvePlan& get_solve_plan(Factor& f, int nrhs);
+
+static void build_finish(Factor& f, bool plan_solve = true) {
+    if (const int n = g_last_nrhs.load(std::memory_order_relaxed); plan_solve && n > 0 && n <= 64) {
+        try {
+            get_solve_plan(f, n);
+        } catch (const std::exception&) {
+            f.solve_plans.erase(n);
+        }
+    }
     RSD_HIP(hipStreamSynchronize(f.stream));
     for (auto q : f.qr_stream)
         if (q) RSD_HIP(hipStreamSynchronize(q));
@@ -2368,6 +2382,7 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
     if (nrhs > 4096) throw Error(RSD_EINVAL, "nrhs > 4096");
     RSD_HIP(hipSetDevice(f.device));
     hipStream_t s = f.stream;
+    g_last_nrhs.store((int)nrhs, std::memory_order_relaxed);
     SolvePlan& sp = get_solve_plan(f, (int)nrhs);
     const int64_t tot = f.N * nrhs;
     const bool rdev = is_device_ptr(rhs), xdev = is_device_ptr(x);
@@ -2641,7 +2656,8 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
             for (int32_t i = g0; i < g1; ++i) {
                 where = i;
                 rsd::build_stats(*fs[i]);
-                rsd::build_finish(*fs[i]);
+                // (the batched solve makes its plans on several threads)
+                rsd::build_finish(*fs[i], false);
             }
         }
         return RSD_OK;
