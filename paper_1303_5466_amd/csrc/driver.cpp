@@ -241,6 +241,19 @@ struct DevBuf {
     template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Host tables packed into one byte buffer (each at a 256-byte boundary) so
+// that they go to the device in one copy.
+struct HostPack {
+    std::vector<unsigned char> bytes;
+    template <typename T>
+    size_t add(const std::vector<T>& v) {
+        const size_t o = (bytes.size() + 255) / 256 * 256;
+        bytes.resize(o + std::max<size_t>(v.size() * sizeof(T), 1));
+        if (!v.empty()) std::memcpy(bytes.data() + o, v.data(), v.size() * sizeof(T));
+        return o;
+    }
+};
+
 template <typename T>
 static void upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
     b.alloc(v.size() * sizeof(T));
@@ -784,12 +797,13 @@ struct QRChain {
     std::vector<QRProblemDev> qp;
     std::vector<int> prob_tag;         // the member's tag of every (sector) problem
     int S = 0, np = 0, max_k = 0, max_n = 0, max_nch = 0, max_subs = 0;
-    DevBuf *dA = nullptr, *daux = nullptr, *diaux = nullptr, *dws = nullptr, *dq = nullptr,
-           *dlist = nullptr, *dsolve = nullptr, *dsec = nullptr, *dcomb = nullptr, *dorb = nullptr,
-           *drefl = nullptr;
+    DevBuf *dA = nullptr, *daux = nullptr, *diaux = nullptr, *dws = nullptr, *dsec = nullptr;
+    // the chain's tables, uploaded together (one copy)
+    const QRProblemDev* q_dev = nullptr;
+    const int *list_dev = nullptr, *solve_dev = nullptr, *orb_dev = nullptr, *refl_dev = nullptr;
+    const SymCombineDesc* comb_dev = nullptr;
     std::vector<int64_t> sym_sec0;     // staging-arena offset of every staged problem
     std::vector<int> staged_prec;      // precision of its T arena (0 float64, 1 float32)
-    DevBuf* dlogh = nullptr;           // log h per problem (several factors only)
     std::vector<int> comb_off[2];      // staging descriptors per window, per destination precision
     int comb_max_kr = 0;
     std::vector<GemmBatch<T>> g1, gt, g2;
@@ -899,22 +913,19 @@ struct QRChain {
             }
         }
         np = (int)qp.size();
-        DevBuf &doffA = tmp(), &dp = tmp(), &dk = tmp(), &dr = tmp(), &dzo = tmp(), &dzu = tmp(),
-               &dzv = tmp(), &dxo = tmp(), &dxu = tmp(), &dxv = tmp(), &dgeo = tmp(), &dgemm = tmp();
-        dA = &tmp(); daux = &tmp(); diaux = &tmp(); dws = &tmp(); dq = &tmp();
-        dlist = &tmp(); dsolve = &tmp(); dsec = &tmp();
-        if (several) {
-            dlogh = &tmp();
-            upload(*dlogh, lgh, s);
-        }
+        DevBuf& dgemm = tmp();
+        dA = &tmp(); daux = &tmp(); diaux = &tmp(); dws = &tmp(); dsec = &tmp();
+        HostPack pk;
+        const size_t o_logh = several ? pk.add(lgh) : 0;
         dA->alloc(A_el * sizeof(T));
         daux->alloc(aux_el * sizeof(T));
         diaux->alloc(iaux_el * sizeof(int));
         dws->alloc(ws_el * sizeof(T));
         dsec->alloc(std::max<int64_t>(sec_el, 1) * sizeof(T));
-        upload(*dq, qp, s); upload(doffA, offA, s); upload(dp, pof, s); upload(dk, kof, s);
-        upload(dr, rof, s); upload(dzo, zoff, s); upload(dzu, zu, s); upload(dzv, zv, s);
-        upload(dxo, xoff, s); upload(dxu, xu, s); upload(dxv, xv, s); upload(dgeo, geo, s);
+        const size_t o_q = pk.add(qp), o_offA = pk.add(offA), o_p = pk.add(pof), o_k = pk.add(kof),
+                     o_r = pk.add(rof), o_zo = pk.add(zoff), o_zu = pk.add(zu), o_zv = pk.add(zv),
+                     o_xo = pk.add(xoff), o_xu = pk.add(xu), o_xv = pk.add(xv), o_geo = pk.add(geo);
+        size_t o_comb = 0, o_orb = 0, o_refl = 0;
         // staged solutions into the T arenas (combined for symmetric types,
         // converted to the level's precision), grouped by the window after
         // which their problems are complete, one list per destination precision
@@ -962,8 +973,9 @@ struct QRChain {
             }
             orb.push_back(0);
             refl.push_back(0);
-            dcomb = &tmp(); dorb = &tmp(); drefl = &tmp();
-            upload(*dcomb, flatc, s); upload(*dorb, orb, s); upload(*drefl, refl, s);
+            o_comb = pk.add(flatc);
+            o_orb = pk.add(orb);
+            o_refl = pk.add(refl);
         }
         // trailing-update products of every window, guarded by the problem's skip flag
         T* Ab = dA->as<T>();
@@ -1058,21 +1070,32 @@ struct QRChain {
             flat.insert(flat.end(), lists[c].begin(), lists[c].end());
             if (!lists[c].empty()) max_subs = std::max(max_subs, QR_WIN / widths[c]);
         }
-        upload(*dlist, flat, s);
+        const size_t o_list = pk.add(flat);
         soff.assign(S + 1, 0);
         for (int sw = 0; sw < S; ++sw) {
             soff[sw] = (int)sflat.size();
             sflat.insert(sflat.end(), done_after[sw].begin(), done_after[sw].end());
         }
         soff[S] = (int)sflat.size();
-        upload(*dsolve, sflat, s);
+        const size_t o_solve = pk.add(sflat);
+        DevBuf& dpk = tmp();
+        dpk.alloc(pk.bytes.size());
+        RSD_HIP(hipMemcpyAsync(dpk.p, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice, s));
+        auto at = [&](size_t o) { return static_cast<const void*>(dpk.as<unsigned char>() + o); };
+        q_dev = static_cast<const QRProblemDev*>(at(o_q));
+        list_dev = static_cast<const int*>(at(o_list));
+        solve_dev = static_cast<const int*>(at(o_solve));
+        comb_dev = static_cast<const SymCombineDesc*>(at(o_comb));
+        orb_dev = static_cast<const int*>(at(o_orb));
+        refl_dev = static_cast<const int*>(at(o_refl));
         // a float32 factor cannot resolve pivots below its rounding level
         qr_tol = std::is_same<T, float>::value ? std::max(f->tol, 1e-6) : interp_tol64(*f);
-        launch_proxy_matrix<T>(Ab, doffA.as<int64_t>(), dp.as<int>(), dk.as<int>(),
-                               dr.as<int>(), dzo.as<int>(), dzu.as<int>(), dzv.as<int>(),
-                               dxo.as<int>(), dxu.as<int>(), dxv.as<int>(), dgeo.as<int>(),
-                               several ? dlogh->as<double>() : nullptr, np, max_pn, f->kd, s);
-        launch_qr_init<T>(Ab, daux->as<T>(), diaux->as<int>(), dq->as<QRProblemDev>(), np, max_k, s);
+        auto ints = [&](size_t o) { return static_cast<const int*>(at(o)); };
+        launch_proxy_matrix<T>(Ab, static_cast<const int64_t*>(at(o_offA)), ints(o_p), ints(o_k), ints(o_r),
+                               ints(o_zo), ints(o_zu), ints(o_zv), ints(o_xo), ints(o_xu), ints(o_xv),
+                               ints(o_geo), several ? static_cast<const double*>(at(o_logh)) : nullptr, np,
+                               max_pn, f->kd, s);
+        launch_qr_init<T>(Ab, daux->as<T>(), diaux->as<int>(), q_dev, np, max_k, s);
     }
 
     // Enqueues window sw.  For the problems that finish in it, the back
@@ -1085,7 +1108,7 @@ struct QRChain {
         T* W = dws->as<T>();
         T* aux = daux->as<T>();
         int* iaux = diaux->as<int>();
-        const QRProblemDev* q = dq->as<QRProblemDev>();
+        const QRProblemDev* q = q_dev;
         const int widths[4] = {16, 8, 4, 2};
         launch_qr_select<T>(Ab, aux, iaux, W, q, np, sw, max_k, s);
         launch_qr_move<T>(Ab, iaux, W, q, np, 0, s);
@@ -1093,9 +1116,9 @@ struct QRChain {
         for (int sub = 0; sub < max_subs; ++sub)
             for (int c = 0; c < 4; ++c) {
                 if (lists[c].empty() || sub * widths[c] >= QR_WIN) continue;
-                launch_qr_panel<T>(Ab, aux, iaux, W, q, dlist->as<int>() + off[c], (int)lists[c].size(),
+                launch_qr_panel<T>(Ab, aux, iaux, W, q, list_dev + off[c], (int)lists[c].size(),
                                    widths[c], maxp[c], sw, sub, qr_tol, s);
-                launch_qr_inner<T>(Ab, aux, iaux, W, q, dlist->as<int>() + off[c], (int)lists[c].size(),
+                launch_qr_inner<T>(Ab, aux, iaux, W, q, list_dev + off[c], (int)lists[c].size(),
                                    widths[c], sw, sub, s);
             }
         g1[sw].run(s);
@@ -1110,15 +1133,15 @@ struct QRChain {
         int gr = 0;
         for (int g = soff[sw]; g < soff[sw + 1]; ++g) gr = std::max(gr, qp[sflat[g]].r);
         for (int st = 0; st < (int)gsolve[sw].size(); ++st) {
-            launch_qr_trsm<T>(Ab, aux, iaux, Tbase<T>(*f), dsec->as<T>(), q, dsolve->as<int>() + soff[sw], ng,
+            launch_qr_trsm<T>(Ab, aux, iaux, Tbase<T>(*f), dsec->as<T>(), q, solve_dev + soff[sw], ng,
                               gr, st, s);
             gsolve[sw][st].run(s);
         }
-        launch_sym_combine<T, double>(Tbase<double>(*f), dsec->as<T>(), dcomb->as<SymCombineDesc>() + comb_off[0][sw],
-                                      comb_off[0][sw + 1] - comb_off[0][sw], dorb->as<int>(), drefl->as<int>(),
+        launch_sym_combine<T, double>(Tbase<double>(*f), dsec->as<T>(), comb_dev + comb_off[0][sw],
+                                      comb_off[0][sw + 1] - comb_off[0][sw], orb_dev, refl_dev,
                                       comb_max_kr, s);
-        launch_sym_combine<T, float>(Tbase<float>(*f), dsec->as<T>(), dcomb->as<SymCombineDesc>() + comb_off[1][sw],
-                                     comb_off[1][sw + 1] - comb_off[1][sw], dorb->as<int>(), drefl->as<int>(),
+        launch_sym_combine<T, float>(Tbase<float>(*f), dsec->as<T>(), comb_dev + comb_off[1][sw],
+                                     comb_off[1][sw + 1] - comb_off[1][sw], orb_dev, refl_dev,
                                      comb_max_kr, s);
         hipEvent_t solved;
         RSD_HIP(hipEventCreateWithFlags(&solved, hipEventDisableTiming));
