@@ -1567,17 +1567,31 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     const int m = o.layers > 0 ? o.layers : layers_for_tol(tol);
     int ktype = kernel ? kernel->type : RSD_KERNEL_LAPLACE;
     if (ktype != RSD_KERNEL_LAPLACE) throw Error(RSD_EINVAL, "only the Laplace kernel is built into this library version");
-    // host copies of the inputs
-    std::vector<double> pts(2 * n), ah, bh;
-    if (is_device_ptr(points)) RSD_HIP(hipMemcpy(pts.data(), points, 2 * n * sizeof(double), hipMemcpyDeviceToHost));
-    else std::memcpy(pts.data(), points, 2 * n * sizeof(double));
-    if (a) {
-        ah.resize(n);
-        if (is_device_ptr(a)) RSD_HIP(hipMemcpy(ah.data(), a, n * sizeof(double), hipMemcpyDeviceToHost));
-        else std::memcpy(ah.data(), a, n * sizeof(double));
-        for (double v : ah)
-            if (!std::isfinite(v)) throw Error(RSD_EINVAL, "non-finite value in a");
+    // host views of the inputs: device arrays are read back into a pinned
+    // block (a direct copy), host arrays are read in place
+    PinnedBlock in_pin;
+    const double* pts = points;
+    const double* ha = a;
+    std::vector<double> bh;
+    {
+        const bool pdev = is_device_ptr(points), adev = a && is_device_ptr(a);
+        if (pdev || adev) {
+            const size_t np = pdev ? 2 * (size_t)n : 0, na = adev ? (size_t)n : 0;
+            in_pin.p = PinnedPool::get().take((np + na) * sizeof(double), in_pin.cap);
+            double* w = static_cast<double*>(in_pin.p);
+            if (pdev) {
+                RSD_HIP(hipMemcpy(w, points, np * sizeof(double), hipMemcpyDeviceToHost));
+                pts = w;
+            }
+            if (adev) {
+                RSD_HIP(hipMemcpy(w + np, a, na * sizeof(double), hipMemcpyDeviceToHost));
+                ha = w + np;
+            }
+        }
     }
+    if (ha)
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(ha[i])) throw Error(RSD_EINVAL, "non-finite value in a");
     const double* bptr = kernel ? kernel->contrast_b : nullptr;
     // the scattering form (sqrt(b) K sqrt(b), Sec. 5.4) needs a per-box scaling
     // of T that the device level pipeline does not apply
@@ -1593,7 +1607,7 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     double h, x0, y0;
     std::vector<int64_t> perm;
     std::string why;
-    if (!detect_grid(pts.data(), n, nx, ny, h, x0, y0, perm, why)) throw Error(RSD_ENOTGRID, why);
+    if (!detect_grid(pts, n, nx, ny, h, x0, y0, perm, why)) throw Error(RSD_ENOTGRID, why);
     f->N = n; f->nx = nx; f->ny = ny; f->h = h;
     try {
         f->plan = cached_plan(nx, ny, leaf, m);
@@ -1610,9 +1624,9 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
         for (int t = 0; t < f->top; ++t) f->level_prec[t] = 1;
     // ---- grid-ordered coefficients -----------------------------------------
     std::vector<double> ag, sbg;
-    if (!ah.empty()) {
+    if (ha) {
         ag.resize(n);
-        for (int64_t g = 0; g < n; ++g) ag[g] = ah[perm[g]];
+        for (int64_t g = 0; g < n; ++g) ag[g] = ha[perm[g]];
     }
     if (!bh.empty()) {
         sbg.resize(n);
