@@ -139,7 +139,8 @@ void launch_transpose_sr(T* F, const BoxDev* boxes, const int* ids, int n_boxes,
                          int max_r, hipStream_t s);
 template <typename T>
 // geo per problem: ax, ay, sector (-1: plain problem; 0..3: symmetry sector
-// ab = a + 2b, entries summed over the four reflections with signs (-1)^(a gx + b gy));
+// ab = a + 2b, entries summed over the reflections of the group with signs
+// (-1)^(a gx + b gy)), group (bit 0: u reflection, bit 1: v reflection);
 // logh_of: nullptr (every problem uses kd.logh) or log h per problem
 void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* k_of,
                          const int* r_of, const int* zoff, const int* zu, const int* zv,
@@ -151,10 +152,11 @@ void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* 
 // converted to the precision of the T arena (see k_gen.hip)
 struct SymCombineDesc {
     int64_t offT;      // layout T (k x r, ld k) in the T arena
-    int64_t offS;      // sym: sector ab block (k/4 x r/4, ld k/4) at offS + ab k r / 16; else k x r
+    int64_t offS;      // sym: sector sc block (k/ns x r/ns, ld k/ns) at offS + sc (k/ns)(r/ns); else k x r
     int k, r;
     int off_sk, off_rs;   // into the orbit / reflection tables (sym only)
     int sym;
+    int grp;           // reflection group of a symmetric type (bit 0: u, bit 1: v)
     void* dst;         // nullptr: T at offT in the launch's arena; else the layout's T itself
 };
 template <typename TS, typename TD>

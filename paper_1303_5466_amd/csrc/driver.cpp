@@ -850,10 +850,10 @@ struct QRChain {
             const bool sym = split_sym(F, I, chain_prec);
             const bool convert = F.level_prec[lev] != chain_prec;
             const bool staged = sym || convert || several;
-            const int nsec = sym ? 4 : 1;
+            const int nsec = sym ? I.nsec() : 1;
             const int64_t sec0 = sec_el;
             if (staged) {
-                sec_el += (int64_t)I.k * I.r / (sym ? 4 : 1);
+                sec_el += (int64_t)I.k * I.r / nsec;
                 staged_ids.push_back(id);
                 staged_sym.push_back(sym ? 1 : 0);
                 sym_sec0.push_back(sec0);
@@ -862,10 +862,11 @@ struct QRChain {
             }
             for (int sc = 0; sc < nsec; ++sc) {
                 QRProblemDev q;
-                q.p = sym ? I.p / 4 : I.p;
-                q.k = sym ? I.k / 4 : I.k;
-                q.r = sym ? I.r / 4 : I.r;
-                q.sec = sym ? sc : -1;
+                q.p = I.p / nsec;
+                q.k = I.k / nsec;
+                q.r = I.r / nsec;
+                // sector = character ab of the group (bit 0: u, bit 1: v reflection)
+                q.sec = sym ? (I.grp == 2 ? 2 * sc : sc) : -1;
                 q.staged = staged ? 1 : 0;
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));
                 if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
@@ -903,7 +904,7 @@ struct QRChain {
                     xu.insert(xu.end(), L.u.begin(), L.u.end());
                     xv.insert(xv.end(), L.v.begin(), L.v.end());
                 }
-                geo.push_back(L.ax); geo.push_back(L.ay); geo.push_back(q.sec);
+                geo.push_back(L.ax); geo.push_back(L.ay); geo.push_back(q.sec); geo.push_back(sym ? I.grp : 0);
                 max_pn = std::max(max_pn, q.p * n);
                 max_k = std::max(max_k, q.k);
                 max_r = std::max(max_r, q.r);
@@ -946,6 +947,7 @@ struct QRChain {
                 cd.k = I.k;
                 cd.r = I.r;
                 cd.sym = sym ? 1 : 0;
+                cd.grp = sym ? I.grp : 0;
                 cd.off_sk = (int)orb.size();
                 cd.off_rs = (int)orb.size();
                 if (sym) {
@@ -955,7 +957,7 @@ struct QRChain {
                     orb.insert(orb.end(), I.rs_orb.begin(), I.rs_orb.end());
                     refl.insert(refl.end(), I.rs_g.begin(), I.rs_g.end());
                 }
-                const int kq = sym ? I.k / 4 : I.k;
+                const int kq = sym ? I.k / I.nsec() : I.k;
                 const int w = (kq + QR_WIN - 1) / QR_WIN - 1;
                 auto& bw = by_win[staged_prec[si]];
                 if ((int)bw.size() <= w) bw.resize(w + 1);
@@ -1779,10 +1781,9 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
 // lower levels, needed first), class 1 the longer ones, class 2 the boxes too
 // tall for 16-column sub-panels.
 static int chain_class(const Factor& f, const IDProblem& I, int ip, int& nprob) {
-    const bool sym = split_sym(f, I, ip);
-    const bool narrow = qr_panel_width(sym ? I.p / 4 : I.p, ip ? 4 : 8) < 16;
-    nprob = sym ? 4 : 1;
-    return narrow ? 2 : ((sym ? I.k / 4 : I.k) <= QR_WIN ? 0 : 1);
+    nprob = split_sym(f, I, ip) ? I.nsec() : 1;
+    const bool narrow = qr_panel_width(I.p / nprob, ip ? 4 : 8) < 16;
+    return narrow ? 2 : (I.k / nprob <= QR_WIN ? 0 : 1);
 }
 
 template <typename T>
@@ -1956,7 +1957,7 @@ static void build_stats(Factor& fr) {
     st.factor_bytes = (int64_t)(f->F64.bytes + f->F32.bytes + f->T64.bytes + f->T32.bytes);
     double fl = f->gemm_flops;
     for (auto& I : P.idps) {
-        const double ns = split_sym(*f, I, interp_prec(*f, f->layout_level[I.layout])) ? 4 : 1;
+        const double ns = split_sym(*f, I, interp_prec(*f, f->layout_level[I.layout])) ? I.nsec() : 1;
         const double p = I.p / ns, k = I.k / ns, r = I.r / ns;
         fl += ns * (2 * k * k * (p - k / 3) + 4 * p * k * r - 2 * k * k * r + k * k * r);
     }

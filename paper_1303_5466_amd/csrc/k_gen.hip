@@ -154,9 +154,10 @@ __global__ void __launch_bounds__(256) assemble_group_kernel(const AsmInst* __re
 }
 
 // Proxy matrix [K(Z, X^sk) | K(Z, X^rs)] of every interpolation problem
-// (p x (k + r), ld p).  For a symmetry sector ab (geo[3 pb + 2] >= 0) rows and
-// columns are orbit representatives and an entry is the sector's block of the
-// kernel in the symmetry-adapted basis: sum over the four reflections g of
+// (p x (k + r), ld p).  geo per problem: ax, ay, sector ab, group.  For a
+// symmetry sector ab (>= 0) rows and columns are orbit representatives and
+// an entry is the sector's block of the kernel in the symmetry-adapted
+// basis: sum over the reflections g of the group (bit 0: u, bit 1: v) of
 // (-1)^(a gx + b gy) K(z - g x), evaluated in float64.
 template <typename T>
 __global__ void __launch_bounds__(256) proxy_kernel(
@@ -169,7 +170,7 @@ __global__ void __launch_bounds__(256) proxy_kernel(
     KernelDesc kd = kdc;
     if (logh_of) kd.logh = logh_of[pb];   // problems of grids with different spacings
     const int p = p_of[pb], n = k_of[pb] + r_of[pb];
-    const int ax = geo[3 * pb], ay = geo[3 * pb + 1], sec = geo[3 * pb + 2];
+    const int ax = geo[4 * pb], ay = geo[4 * pb + 1], sec = geo[4 * pb + 2], grp = geo[4 * pb + 3];
     T* Ab = A + offA[pb];
     const int* ZU = zu + zoff[pb];
     const int* ZV = zv + zoff[pb];
@@ -182,20 +183,21 @@ __global__ void __launch_bounds__(256) proxy_kernel(
         } else {
             const int u = XU[j], v = XV[j], um = ax - 1 - u, vm = ay - 1 - v;
             const double sa = (sec & 1) ? -1.0 : 1.0, sb = (sec & 2) ? -1.0 : 1.0;
-            const double val = KV<double>::proxy(kd, ZU[i] - u, ZV[i] - v) +
-                               sa * KV<double>::proxy(kd, ZU[i] - um, ZV[i] - v) +
-                               sb * KV<double>::proxy(kd, ZU[i] - u, ZV[i] - vm) +
-                               sa * sb * KV<double>::proxy(kd, ZU[i] - um, ZV[i] - vm);
+            double val = KV<double>::proxy(kd, ZU[i] - u, ZV[i] - v);
+            if (grp & 1) val += sa * KV<double>::proxy(kd, ZU[i] - um, ZV[i] - v);
+            if (grp & 2) val += sb * KV<double>::proxy(kd, ZU[i] - u, ZV[i] - vm);
+            if (grp == 3) val += sa * sb * KV<double>::proxy(kd, ZU[i] - um, ZV[i] - vm);
             Ab[e] = T(val);
         }
     }
 }
 
 // T of a box type from float64 solutions in the sector arena, converted to
-// the level's precision.  Symmetric type (d.sym): from its sector solutions
-// T^ab (orbit indices), T[i, j] = 1/4 sum_ab chi_ab(g_i) chi_ab(h_j)
-// T^ab[orb_i, orb_j] with chi_ab(g) = (-1)^popcount(ab & g) (the
-// symmetry-adapted basis is orthonormal); otherwise a plain copy.
+// the level's precision.  Symmetric type (d.sym) with a reflection group of
+// order ns (2 or 4): from its sector solutions T^ab (orbit indices), T[i, j]
+// = 1/ns sum_ab chi_ab(g_i) chi_ab(h_j) T^ab[orb_i, orb_j] over the group's
+// characters ab, chi_ab(g) = (-1)^popcount(ab & g) (the symmetry-adapted
+// basis is orthonormal); otherwise a plain copy.
 template <typename TS, typename TD>
 __global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, const TS* __restrict__ Ts,
                                                           const SymCombineDesc* __restrict__ descs,
@@ -203,8 +205,10 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, c
                                                           const int* __restrict__ refl) {
     const SymCombineDesc d = descs[blockIdx.y];
     TD* __restrict__ Tb = d.dst ? static_cast<TD*>(d.dst) : Ta + d.offT;
-    const int k4 = d.k / 4, r4 = d.r / 4;
-    const int64_t blk = (int64_t)k4 * r4;
+    const int ns = d.grp == 3 ? 4 : 2;
+    const int kq = d.k / ns, rq = d.r / ns;
+    const int64_t blk = (int64_t)kq * rq;
+    const TS scale = TS(1) / TS(ns);
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)d.k * d.r; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % d.k), j = (int)(e / d.k);
         if (!d.sym) {
@@ -213,14 +217,14 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, c
         }
         const int oi = orb[d.off_sk + i], gi = refl[d.off_sk + i];
         const int oj = orb[d.off_rs + j], gj = refl[d.off_rs + j];
-        const int64_t at = oi + (int64_t)oj * k4;
+        const int64_t at = oi + (int64_t)oj * kq;
         TS acc = TS(0);
-#pragma unroll
-        for (int ab = 0; ab < 4; ++ab) {
-            const TS v = Ts[d.offS + ab * blk + at];
+        for (int sc = 0; sc < ns; ++sc) {
+            const int ab = d.grp == 2 ? 2 * sc : sc;   // sector sc's character
+            const TS v = Ts[d.offS + sc * blk + at];
             acc += (__popc(ab & (gi ^ gj)) & 1) ? -v : v;
         }
-        Tb[i + (int64_t)j * d.k] = TD(TS(0.25) * acc);
+        Tb[i + (int64_t)j * d.k] = TD(scale * acc);
     }
 }
 

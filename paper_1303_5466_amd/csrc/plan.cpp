@@ -148,7 +148,7 @@ struct Builder {
                 I.zv.push_back(zv);
             }
         I.p = (int)I.zu.size();
-        if (L.ax % 2 == 0 && L.ay % 2 == 0) find_symmetry(L, I);
+        if (L.ax % 2 == 0 || L.ay % 2 == 0) find_symmetry(L, I);
         L.idp = (int)P.idps.size();
         P.idps.push_back(std::move(I));
     }
@@ -164,24 +164,36 @@ struct Builder {
             u0 = std::min(u0, I.zu[i]); u1 = std::max(u1, I.zu[i]);
             v0 = std::min(v0, I.zv[i]); v1 = std::max(v1, I.zv[i]);
         }
-        if (u0 + u1 != ax - 1 || v0 + v1 != ay - 1) return;   // ring not mirror-symmetric
+        // a reflection along an axis can apply only when the side is even
+        // (no fixed points) and the ring is mirror-symmetric along it
+        int grp = 0;
+        if (ax % 2 == 0 && u0 + u1 == ax - 1) grp |= 1;
+        if (ay % 2 == 0 && v0 + v1 == ay - 1) grp |= 2;
+        if (!grp) return;
         const int nu = u1 - u0 + 1, nv = v1 - v0 + 1;
         auto at = [&](int u, int v) { return (int64_t)(u - u0) * nv + (v - v0); };
         std::vector<int32_t> mark((size_t)nu * nv, -1);
+        // the reflections (of those in grp) mapping a set onto itself
         auto closed = [&](const int32_t* U, const int32_t* V, int n, int tag) {
             for (int i = 0; i < n; ++i) mark[at(U[i], V[i])] = tag;
-            for (int i = 0; i < n; ++i)
-                if (mark[at(ax - 1 - U[i], V[i])] != tag || mark[at(U[i], ay - 1 - V[i])] != tag) return false;
-            return true;
+            int ok = grp;
+            for (int i = 0; i < n && ok; ++i) {
+                if ((ok & 1) && mark[at(ax - 1 - U[i], V[i])] != tag) ok &= ~1;
+                if ((ok & 2) && mark[at(U[i], ay - 1 - V[i])] != tag) ok &= ~2;
+            }
+            return ok;
         };
-        if (!closed(I.zu.data(), I.zv.data(), I.p, 0) || !closed(L.u.data(), L.v.data(), k, 1) ||
-            !closed(L.u.data() + k, L.v.data() + k, r, 2))
-            return;
+        grp &= closed(I.zu.data(), I.zv.data(), I.p, 0);
+        if (grp) grp &= closed(L.u.data(), L.v.data(), k, 1);
+        if (grp) grp &= closed(L.u.data() + k, L.v.data() + k, r, 2);
+        if (!grp) return;
+        const int ord = grp == 3 ? 4 : 2;
+        const bool ru_ = grp & 1, rv_ = grp & 2;
         // representatives in list order, then orbit / reflection of every point
         auto orbits = [&](const int32_t* U, const int32_t* V, int n, std::vector<int32_t>& ru,
                           std::vector<int32_t>& rv, std::vector<int32_t>* orb, std::vector<int32_t>* g) {
             for (int i = 0; i < n; ++i)
-                if (U[i] < ax / 2 && V[i] < ay / 2) {
+                if ((!ru_ || U[i] < ax / 2) && (!rv_ || V[i] < ay / 2)) {
                     mark[at(U[i], V[i])] = (int)ru.size();
                     ru.push_back(U[i]);
                     rv.push_back(V[i]);
@@ -190,7 +202,7 @@ struct Builder {
             orb->reserve(n);
             g->reserve(n);
             for (int i = 0; i < n; ++i) {
-                const int gx = U[i] >= ax / 2 ? 1 : 0, gy = V[i] >= ay / 2 ? 1 : 0;
+                const int gx = ru_ && U[i] >= ax / 2 ? 1 : 0, gy = rv_ && V[i] >= ay / 2 ? 1 : 0;
                 const int fu = gx ? ax - 1 - U[i] : U[i], fv = gy ? ay - 1 - V[i] : V[i];
                 orb->push_back(mark[at(fu, fv)]);
                 g->push_back(gx + 2 * gy);
@@ -199,12 +211,14 @@ struct Builder {
         orbits(I.zu.data(), I.zv.data(), I.p, I.zr_u, I.zr_v, nullptr, nullptr);
         orbits(L.u.data(), L.v.data(), k, I.skr_u, I.skr_v, &I.sk_orb, &I.sk_g);
         orbits(L.u.data() + k, L.v.data() + k, r, I.rsr_u, I.rsr_v, &I.rs_orb, &I.rs_g);
-        if ((int)I.zr_u.size() * 4 != I.p || (int)I.skr_u.size() * 4 != k || (int)I.rsr_u.size() * 4 != r) {
+        if ((int)I.zr_u.size() * ord != I.p || (int)I.skr_u.size() * ord != k ||
+            (int)I.rsr_u.size() * ord != r) {
             I.zr_u.clear(); I.zr_v.clear(); I.skr_u.clear(); I.skr_v.clear(); I.rsr_u.clear(); I.rsr_v.clear();
             I.sk_orb.clear(); I.sk_g.clear(); I.rs_orb.clear(); I.rs_g.clear();
             return;
         }
         I.sym = true;
+        I.grp = grp;
     }
 };
 

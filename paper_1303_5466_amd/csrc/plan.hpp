@@ -38,17 +38,21 @@ struct IDProblem {
     int layout = -1;
     int p = 0, k = 0, r = 0;
     std::vector<int32_t> zu, zv;   // proxy nodes relative to the box origin
-    // Mirror symmetry: when both reflections of the box (u -> ax-1-u,
-    // v -> ay-1-v) map Z, I^sk and I^rs onto themselves without fixed points,
-    // every point lies in an orbit of four and the problem splits into four
-    // independent sector problems of a quarter the size.  Orbit
-    // representatives are the points of the lower-left quadrant; g in 0..3
-    // names the reflection (bit 0: u, bit 1: v) carrying the representative
-    // to the point.
+    // Mirror symmetry: when reflections of the box (u -> ax-1-u along an
+    // even side ax, v -> ay-1-v along an even side ay) map Z, I^sk and I^rs
+    // onto themselves (no fixed points, the sides being even), every point
+    // lies in an orbit of the group they generate (grp: bit 0 the u
+    // reflection, bit 1 the v reflection; order 2 or 4), and the problem
+    // splits into that many independent sector problems of 1/order the size.
+    // Orbit representatives are the points in the lower half along every
+    // reflected axis; g (bit 0: u, bit 1: v) names the reflection carrying
+    // the representative to the point.
     bool sym = false;
-    std::vector<int32_t> zr_u, zr_v;           // Z representatives (p / 4)
-    std::vector<int32_t> skr_u, skr_v;         // I^sk representatives (k / 4)
-    std::vector<int32_t> rsr_u, rsr_v;         // I^rs representatives (r / 4)
+    int grp = 0;
+    int nsec() const { return sym ? (grp == 3 ? 4 : 2) : 1; }
+    std::vector<int32_t> zr_u, zr_v;           // Z representatives (p / nsec)
+    std::vector<int32_t> skr_u, skr_v;         // I^sk representatives (k / nsec)
+    std::vector<int32_t> rsr_u, rsr_v;         // I^rs representatives (r / nsec)
     std::vector<int32_t> sk_orb, sk_g;         // per skeleton position: orbit, reflection
     std::vector<int32_t> rs_orb, rs_g;         // per residual position
 };

@@ -500,6 +500,31 @@ def test_symmetry_split_matches_whole_problems():
     fw.close()
 
 
+@pytest.mark.parametrize("n", [50, 75])
+def test_one_reflection_split_matches_whole_problems(n):
+    # odd halves: many box types are mirror-symmetric along one axis only
+    # (two sectors); compare every box's T and the solutions with the whole
+    # problems
+    pts = W.grid_points(n)
+    a = W.coef_sine(pts)
+    f = W.rhs_normal(len(pts), 2, 47)
+    fs = rsd.Factor(pts, a, 1e-10)
+    fw = rsd.Factor(pts, a, 1e-10, flags=rsd.RSD_FLAG_NO_SYMMETRY)
+    xs, _ = fs.solve(f)
+    xw, _ = fw.solve(f)
+    xd = dense.solve(pts, f, a)
+    assert dense.rel_error(xs, xd) < 1e-10 and dense.rel_error(xw, xd) < 1e-10
+    assert np.linalg.norm(xs - xw) <= 1e-11 * np.linalg.norm(xw)
+    for b in range(fs.stats()["n_boxes"]):
+        info = fs.box_info(b)
+        if info["r"] == 0 or info["parent"] < 0:
+            continue
+        Ts, Tw = fs.block(b, 0), fw.block(b, 0)
+        assert np.abs(Ts - Tw).max() <= 1e-6 * np.abs(Tw).max(), (b, info["ax"], info["ay"])
+    fs.close()
+    fw.close()
+
+
 @pytest.mark.parametrize("precision,flags", [(rsd.RSD_PREC_FP64, 0), (rsd.RSD_PREC_FP32_REFINE, 0),
                                              (rsd.RSD_PREC_FP32_REFINE, rsd.RSD_FLAG_FP32_INTERP)])
 def test_low_accuracy_tolerance(precision, flags):
