@@ -336,6 +336,37 @@ private:
     std::multimap<size_t, void*> free_;
 };
 
+// Pinned host words (flags read back by the host), handed out from 4 KiB
+// pages that live until the process ends: pinning and unpinning a page
+// costs hundreds of microseconds, more than a small solve.
+class PinnedWords {
+public:
+    static PinnedWords& get() {
+        static PinnedWords* w = new PinnedWords();   // outlives static destructors
+        return *w;
+    }
+    int* take() {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (free_.empty()) {
+            void* page = nullptr;
+            RSD_HIP(hipHostMalloc(&page, 4096, hipHostMallocDefault));
+            for (int i = 0; i < 4096 / 64; ++i) free_.push_back(static_cast<int*>(page) + 16 * i);
+        }
+        int* w = free_.back();
+        free_.pop_back();
+        return w;
+    }
+    void give(int* w) {
+        if (!w) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        free_.push_back(w);
+    }
+
+private:
+    std::mutex mu_;
+    std::vector<int*> free_;   // one word per 64-byte line
+};
+
 static bool is_device_ptr(const void* p) {
     if (!p) return false;
     hipPointerAttribute_t attr;
@@ -726,7 +757,7 @@ struct Factor {
                               &d_flag, &F64, &F32, &T64, &T32, &SR, &SC, &gemm64, &gemm32, &gj64, &gj32})
                 b->release();
         }
-        if (h_flag) (void)hipHostFree(h_flag);
+        PinnedWords::get().give(h_flag);
         for (auto e : tmp_events) (void)hipEventDestroy(e);
         for (auto e : build_ev)
             if (e) (void)hipEventDestroy(e);
@@ -1329,8 +1360,8 @@ static void run_transpose(Factor& f, LevelExec<T>& L, hipStream_t s) {
 }
 
 template <typename T>
-static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s) {
-    run_assembly<T>(f, L, s);
+static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s, bool assemble = true) {
+    if (assemble) run_assembly<T>(f, L, s);
     L.g_sr.run(s);
     L.g_rr.run(s);
     run_transpose<T>(f, L, s);
@@ -1786,12 +1817,6 @@ static int chain_class(const Factor& f, const IDProblem& I, int ip, int& nprob) 
     return narrow ? 2 : (I.k / nprob <= QR_WIN ? 0 : 1);
 }
 
-template <typename T>
-static void run_level_of(Factor& f, int t, hipStream_t s) {
-    if constexpr (std::is_same<T, float>::value) run_level<float>(f, f.L32[f.exec_index[t]], s);
-    else run_level<double>(f, f.L64[f.exec_index[t]], s);
-}
-
 // Every launch of a single build: the interpolation chains on two streams of
 // their own and the level pipeline on the factor's stream, each level as
 // soon as the events of its box types exist.
@@ -1867,9 +1892,17 @@ static void enqueue_single(Factor& fr) {
             waits = level_waits[next_level];
         }
         const int t = next_level++;
-        for (auto e : waits) RSD_HIP(hipStreamWaitEvent(s, e, 0));
-        if (f->level_prec[t]) run_level_of<float>(*f, t, s);
-        else run_level_of<double>(*f, t, s);
+        // the level's F blocks need only the level below: assembled before
+        // the wait for the level's interpolation
+        if (f->level_prec[t]) {
+            run_assembly<float>(*f, f->L32[exec_index[t]], s);
+            for (auto e : waits) RSD_HIP(hipStreamWaitEvent(s, e, 0));
+            run_level<float>(*f, f->L32[exec_index[t]], s, false);
+        } else {
+            run_assembly<double>(*f, f->L64[exec_index[t]], s);
+            for (auto e : waits) RSD_HIP(hipStreamWaitEvent(s, e, 0));
+            run_level<double>(*f, f->L64[exec_index[t]], s, false);
+        }
         return true;
     };
     {
@@ -2402,7 +2435,7 @@ static void matvec_grid(Factor& f, const double* x, double* y, int nrhs) {
 static void start_finite_check(Factor& f, const double* x, int64_t n) {
     DevBuf& flag = f.d_flag;
     if (!flag.p) flag.alloc(sizeof(int));
-    if (!f.h_flag) RSD_HIP(hipHostMalloc(reinterpret_cast<void**>(&f.h_flag), sizeof(int), hipHostMallocDefault));
+    if (!f.h_flag) f.h_flag = PinnedWords::get().take();
     RSD_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), f.stream));
     launch_check_finite(x, n, flag.as<int>(), f.stream);
     RSD_HIP(hipMemcpyAsync(f.h_flag, flag.p, sizeof(int), hipMemcpyDeviceToHost, f.stream));
