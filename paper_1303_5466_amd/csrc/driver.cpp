@@ -1910,14 +1910,16 @@ static void enqueue_single(Factor& fr) {
         QRChain<float> c32[NCH];
         int S = 0;
         double fl = 0, by = 0;
-        for (int c = 0; c < NCH; ++c) {
+        ProfScope ps(RSD_PROF_INTERP, f->qr_stream[1]);   // flops and bytes filled in below
+        auto set_up = [&](int c) {
             if (!cp[0][c].empty()) { c64[c].setup(cp[0][c], false, f->scratch, chain_stream(c)); S = std::max(S, c64[c].S); }
             if (!cp[1][c].empty()) { c32[c].setup(cp[1][c], false, f->scratch, chain_stream(c)); S = std::max(S, c32[c].S); }
             fl += c64[c].flops + c32[c].flops;
             by += c64[c].bytes + c32[c].bytes;
-        }
-        ProfScope ps(RSD_PROF_INTERP, f->qr_stream[1], fl, by);
-        // the one-window chain first, on this thread
+        };
+        // the one-window chain first, on this thread: set up and enqueued
+        // before anything else, since the lowest level waits for it
+        set_up(0);
         {
             std::vector<int> done;
             publish(c32[0].window(0, done), done);
@@ -1926,11 +1928,14 @@ static void enqueue_single(Factor& fr) {
         }
         // then the level tables, staged in pinned memory (a copy from
         // pageable memory would wait for the kernels of a stream sharing the
-        // hardware queue)
+        // hardware queue), then the other chains
         upload_batches<double>(f->gemm64, f->tables64, s, false, &f->staged[0], 1);
         upload_batches<float>(f->gemm32, f->tables32, s, false, &f->staged[1], 1);
         upload_gj<double>(f->gj64, f->L64, s, &f->staged[2]);
         upload_gj<float>(f->gj32, f->L32, s, &f->staged[3]);
+        for (int c = 1; c < NCH; ++c) set_up(c);
+        ps.rec.flops = fl;
+        ps.rec.bytes = by;
         std::exception_ptr chain_err;
         const int dev = f->device;
         std::thread chains([&] {
@@ -2024,6 +2029,9 @@ static std::atomic<int> g_last_nrhs{0};
 static SolvePlan& get_solve_plan(Factor& f, int nrhs);
 
 static void build_finish(Factor& f, bool plan_solve = true) {
+    // the error word comes back with the stream's own completion
+    if (!f.h_flag) f.h_flag = PinnedWords::get().take();
+    RSD_HIP(hipMemcpyAsync(f.h_flag, f.d_err.p, sizeof(int), hipMemcpyDeviceToHost, f.stream));
     if (const int n = g_last_nrhs.load(std::memory_order_relaxed); plan_solve && n > 0 && n <= 64) {
         try {
             get_solve_plan(f, n);
@@ -2048,10 +2056,8 @@ static void build_finish(Factor& f, bool plan_solve = true) {
         e = nullptr;
     }
     f.stats.build_ms = ms;
-    int err[4];
-    RSD_HIP(hipMemcpy(err, f.d_err.p, sizeof(err), hipMemcpyDeviceToHost));
-    if (err[0] != 0) {
-        const int bx = err[0] - 1;
+    if (const int err = *f.h_flag; err != 0) {
+        const int bx = err - 1;
         throw Error(RSD_ESINGULAR, "singular pivot block in box " + std::to_string(bx) + " at level " +
                                        std::to_string(f.plan.boxes[bx].level));
     }
