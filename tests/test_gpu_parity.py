@@ -29,8 +29,10 @@ def _need_gpu():
                                          (300, 17, 3, 0, 0),
                                          # 128-wide tiles (2048 x 2048, K > 128), ragged edges
                                          (2048, 2048, 200, 0, 0), (2050, 2047, 137, 1, 1),
-                                         # short K on 64-wide tiles with C loaded up front
-                                         (2048, 2048, 64, 0, 0),
+                                         # short K on 64-wide tiles with C loaded up front, every
+                                         # transpose, ragged tiles and k panels
+                                         (2048, 2048, 64, 0, 0), (2050, 2047, 64, 1, 1), (33, 65, 64, 1, 0),
+                                         (97, 31, 50, 0, 1), (5, 300, 17, 1, 0),
                                          # split K: two splits, sixteen splits, one tile of sixteen
                                          (1024, 1024, 1024, 0, 1), (130, 70, 3000, 1, 0),
                                          (16, 16, 5000, 0, 0)])
