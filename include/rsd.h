@@ -365,6 +365,13 @@ int32_t rsd_plan_n_levels(const rsd_plan* p);
 rsd_status rsd_plan_box_info(const rsd_plan* p, int32_t box, rsd_box_info* out);
 /* active point ids of a box, [skeleton; residual] order (k + r int64) */
 rsd_status rsd_plan_box_points(const rsd_plan* p, int32_t box, int64_t* dst);
+/* Mirror reflections of the box (u -> ax-1-u along an even side ax, v ->
+ * ay-1-v along an even side ay) that map its skeleton, residual and proxy
+ * sets onto themselves: *group = bit 0 the u reflection, bit 1 the v
+ * reflection (0: none, or a box without an interpolation problem).  The
+ * factorization splits such a box type's least-squares problem into 2 or 4
+ * sector problems. */
+rsd_status rsd_plan_box_symmetry(const rsd_plan* p, int32_t box, int32_t* group);
 void rsd_plan_free(rsd_plan* p);
 
 /* Grid detection used by rsd_build_factor: on success nx, ny, h and perm

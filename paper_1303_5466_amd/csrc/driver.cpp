@@ -3000,6 +3000,20 @@ rsd_status rsd_plan_box_points(const rsd_plan* p, int32_t box, int64_t* dst) {
     });
 }
 
+rsd_status rsd_plan_box_symmetry(const rsd_plan* p, int32_t box, int32_t* group) {
+    return guarded([&]() {
+        if (!p || !group) throw rsd::Error(RSD_EINVAL, "null argument");
+        if (box < 0 || box >= (int)p->plan.boxes.size()) throw rsd::Error(RSD_EINVAL, "box out of range");
+        const auto& L = p->plan.layouts[p->plan.boxes[box].layout];
+        *group = 0;
+        if (L.idp >= 0) {
+            const auto& I = p->plan.idps[L.idp];
+            if (I.sym) *group = I.grp;
+        }
+        return RSD_OK;
+    });
+}
+
 void rsd_plan_free(rsd_plan* p) { delete p; }
 
 rsd_status rsd_detect_grid(const double* points_host, int64_t n_points, int64_t* nx, int64_t* ny,

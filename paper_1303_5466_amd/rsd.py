@@ -113,6 +113,7 @@ EXPORTS = {
     "rsd_plan_n_levels": (C.c_int32, [C.c_void_p]),
     "rsd_plan_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
     "rsd_plan_box_points": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "rsd_plan_box_symmetry": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
     "rsd_plan_free": (None, [C.c_void_p]),
     "rsd_detect_grid": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_void_p]),
@@ -408,6 +409,12 @@ class Plan:
         b = rsd_box_info()
         _check(load().rsd_plan_box_info(self._h, box, C.byref(b)))
         return {f: getattr(b, f) for f, _ in rsd_box_info._fields_}
+
+    def box_symmetry(self, box):
+        """Reflection group of the box type (bit 0: u, bit 1: v)."""
+        g = C.c_int32()
+        _check(load().rsd_plan_box_symmetry(self._h, box, C.byref(g)))
+        return g.value
 
     def box_points(self, box):
         info = self.box_info(box)

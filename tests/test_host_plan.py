@@ -134,3 +134,35 @@ def test_plan_levels_golden():
 
 def test_layer_count_reads_tolerance():
     assert rskel.layers_for_tol(1e-10) == 2
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (50, 50), (75, 75), (37, 24), (40, 24)])
+def test_box_symmetry_by_brute_force(nx, ny):
+    """The reflection group the interpolation split uses: a mirror reflection
+    (along an even side) belongs to it exactly when it maps the box's skeleton
+    and residual sets onto themselves (the proxy ring is always symmetric)."""
+    P = rsd.Plan(nx, ny, 8, 2)
+    groups = []
+    for b in range(P.n_boxes):
+        info = P.box_info(b)
+        if info["r"] == 0 or info["parent"] < 0:
+            continue
+        ids = P.box_points(b)
+        k, ax, ay = info["k"], info["ax"], info["ay"]
+        u, v = ids // ny - info["x0"], ids % ny - info["y0"]
+        sk, rs = set(zip(u[:k], v[:k])), set(zip(u[k:], v[k:]))
+
+        def closed(flip):
+            return {flip(p) for p in sk} == sk and {flip(p) for p in rs} == rs
+
+        expect = 0
+        if ax % 2 == 0 and closed(lambda p: (ax - 1 - p[0], p[1])):
+            expect |= 1
+        if ay % 2 == 0 and closed(lambda p: (p[0], ay - 1 - p[1])):
+            expect |= 2
+        assert P.box_symmetry(b) == expect, (b, ax, ay)
+        groups.append(expect)
+    if nx == ny == 64:
+        assert set(groups) == {3}            # even halves all the way down
+    if nx == ny == 50:
+        assert {1, 2} <= set(groups)         # odd halves: one reflection only
