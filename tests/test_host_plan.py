@@ -166,3 +166,21 @@ def test_box_symmetry_by_brute_force(nx, ny):
         assert set(groups) == {3}            # even halves all the way down
     if nx == ny == 50:
         assert {1, 2} <= set(groups)         # odd halves: one reflection only
+
+
+def test_batched_entry_points_reject_bad_arguments_on_the_host():
+    """Argument errors of the batched calls are reported before any device
+    work (these run without a GPU)."""
+    import ctypes as C
+    lib = rsd.load()
+    out = (C.c_void_p * 1)()
+    pts = (C.c_void_p * 1)()
+    npts = (C.c_int64 * 1)(4)
+    kd = rsd.rsd_kernel(rsd.RSD_KERNEL_LAPLACE, 0.0, None)
+    assert lib.rsd_build_factor_batched(0, pts, npts, C.byref(kd), None, 1e-10, None, 0, out) == rsd.RSD_EINVAL
+    assert lib.rsd_build_factor_batched(1, None, npts, C.byref(kd), None, 1e-10, None, 0, out) == rsd.RSD_EINVAL
+    assert "null" in lib.rsd_last_error().decode()
+    fs = (C.c_void_p * 2)(None, None)
+    ptrs = (C.c_void_p * 2)(None, None)
+    assert lib.rsd_solve_batched(0, fs, ptrs, 1, ptrs, None) == rsd.RSD_EINVAL
+    assert lib.rsd_solve_batched(2, fs, ptrs, 1, ptrs, None) == rsd.RSD_EINVAL   # null factors
