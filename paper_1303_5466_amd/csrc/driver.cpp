@@ -30,6 +30,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <condition_variable>
 #include <type_traits>
@@ -65,6 +66,23 @@ struct IdleScope {
     IdleScope() { ++g_idle_depth; }
     ~IdleScope() { --g_idle_depth; }
 };
+
+// Runs `work` on the calling thread and on up to n - 1 more, then joins them.
+// The callers share their items through an atomic counter, so a thread
+// that cannot be started only leaves its share to the others.
+template <typename Fn>
+static void run_on_threads(int n, Fn&& work) {
+    std::vector<std::thread> ts;
+    for (int i = 1; i < n; ++i) {
+        try {
+            ts.emplace_back(work);
+        } catch (const std::system_error&) {
+            break;
+        }
+    }
+    work();
+    for (auto& t : ts) t.join();
+}
 
 class DevicePool {
 public:
@@ -650,10 +668,7 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
         auto work = [&]() {
             for (size_t i = next++; i < bs.size(); i = next++) fill(i);
         };
-        std::vector<std::thread> workers;
-        for (int w = 1; w < threads; ++w) workers.emplace_back(work);
-        work();
-        for (auto& t : workers) t.join();
+        run_on_threads(threads, work);
     } else {
         for (size_t i = 0; i < bs.size(); ++i) fill(i);
     }
@@ -2168,12 +2183,7 @@ static void enqueue_group(const std::vector<Factor*>& group, GroupChains& gc) {
                     }
                 }
             };
-            {
-                std::vector<std::thread> workers;
-                for (int w = 1; w < 6; ++w) workers.emplace_back(work);
-                work();
-                for (auto& t : workers) t.join();
-            }
+            run_on_threads(6, work);
             for (auto& e : errs)
                 if (e) std::rethrow_exception(e);
             upload_batches<float>(d32, b32, ls, true, &gc.pinned[0], 6);
@@ -2716,10 +2726,7 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
                         }
                     }
                 };
-                std::vector<std::thread> workers;
-                for (int w = 1; w < nw; ++w) workers.emplace_back(work);
-                work();
-                for (auto& t : workers) t.join();
+                rsd::run_on_threads(nw, work);
                 for (int32_t i = g0; i < g1; ++i)
                     if (errs[i - g0]) {
                         where = i;
@@ -2783,10 +2790,7 @@ rsd_status rsd_solve_batched(int32_t n, rsd_factor* const* factors, const double
             if (st[i] != RSD_OK) msg[i] = rsd::g_last_error;
         }
     };
-    std::vector<std::thread> workers;
-    for (int w = 1; w < std::min<int32_t>(n, 8); ++w) workers.emplace_back(work);
-    work();
-    for (auto& t : workers) t.join();
+    rsd::run_on_threads(std::min<int32_t>(n, 8), work);
     rsd::g_last_error.clear();
     for (int32_t i = 0; i < n; ++i)
         if (st[i] != RSD_OK) {

@@ -209,7 +209,12 @@ rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out) {
         }
         s->opt.mem_budget = (int64_t)(fr / 4 * 3);
     }
-    for (int i = 0; i < s->opt.n_workers; ++i) s->workers.emplace_back([s] { s->worker(); });
+    try {
+        for (int i = 0; i < s->opt.n_workers; ++i) s->workers.emplace_back([s] { s->worker(); });
+    } catch (const std::exception&) {
+        rsd_server_destroy(s);     // stops and joins the workers started so far
+        return RSD_ENOMEM;
+    }
     *out = s;
     return RSD_OK;
 }
