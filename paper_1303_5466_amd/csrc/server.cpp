@@ -185,6 +185,19 @@ struct rsd_server {
     }
 };
 
+// No C++ exception crosses the C interface: a failed allocation inside a
+// call is reported as RSD_ENOMEM.
+template <typename Fn>
+static rsd_status no_throw(Fn&& fn) {
+    try {
+        return fn();
+    } catch (const std::bad_alloc&) {
+        return RSD_ENOMEM;
+    } catch (const std::exception&) {
+        return RSD_EINVAL;
+    }
+}
+
 extern "C" {
 
 rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out) {
@@ -222,100 +235,108 @@ rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out) {
 rsd_status rsd_server_submit_factor(rsd_server* s, const double* points, int64_t n_points,
                                     const rsd_kernel* kernel, const double* a, double tol,
                                     const rsd_options* opt, int64_t* factor_id) {
-    if (!s || !factor_id) return RSD_EINVAL;
-    if (opt && opt->hip_stream) return RSD_EINVAL;
-    Slot sl;
-    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        return RSD_EDEVICE;
-    }
-    rsd_options o{};
-    if (opt) o = *opt;
-    o.hip_stream = sl.stream;
-    if (s->opt.device >= 0) o.device = s->opt.device;
-    rsd_status st = rsd_build_factor(points, n_points, kernel, a, tol, &o, &sl.f);
-    if (st != RSD_OK) {
-        (void)hipStreamDestroy(sl.stream);
-        return st;
-    }
-    rsd_factor_stats fs{};
-    (void)rsd_factor_get_stats(sl.f, &fs);
-    sl.n = n_points;
-    // the factor plus the coalescing buffers and solve vectors of a full batch
-    sl.bytes = fs.factor_bytes + (int64_t)(6 * n_points * s->opt.max_coalesce) * (int64_t)sizeof(double);
-    sl.last_use = Clock::now();
-    std::lock_guard<std::mutex> lk(s->mu);
-    while ((int64_t)s->slots.size() >= s->opt.max_slots || s->resident + sl.bytes > s->opt.mem_budget) {
-        auto victim = s->slots.end();
-        for (auto it = s->slots.begin(); it != s->slots.end(); ++it)
-            if (!it->second.busy && it->second.pending.empty() &&
-                (victim == s->slots.end() || it->second.last_use < victim->second.last_use))
-                victim = it;
-        if (victim == s->slots.end()) {
-            s->free_slot(sl);
-            return RSD_ENOMEM;
+    return no_throw([&]() -> rsd_status {
+        if (!s || !factor_id) return RSD_EINVAL;
+        if (opt && opt->hip_stream) return RSD_EINVAL;
+        Slot sl;
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return RSD_EDEVICE;
         }
-        s->resident -= victim->second.bytes;
-        s->free_slot(victim->second);
-        s->slots.erase(victim);
-        ++s->n_evicted;
-    }
-    const int64_t id = s->next_fid++;
-    s->resident += sl.bytes;
-    s->slots.emplace(id, std::move(sl));
-    *factor_id = id;
-    return RSD_OK;
+        rsd_options o{};
+        if (opt) o = *opt;
+        o.hip_stream = sl.stream;
+        if (s->opt.device >= 0) o.device = s->opt.device;
+        rsd_status st = rsd_build_factor(points, n_points, kernel, a, tol, &o, &sl.f);
+        if (st != RSD_OK) {
+            (void)hipStreamDestroy(sl.stream);
+            return st;
+        }
+        rsd_factor_stats fs{};
+        (void)rsd_factor_get_stats(sl.f, &fs);
+        sl.n = n_points;
+        // the factor plus the coalescing buffers and solve vectors of a full batch
+        sl.bytes = fs.factor_bytes + (int64_t)(6 * n_points * s->opt.max_coalesce) * (int64_t)sizeof(double);
+        sl.last_use = Clock::now();
+        std::lock_guard<std::mutex> lk(s->mu);
+        while ((int64_t)s->slots.size() >= s->opt.max_slots || s->resident + sl.bytes > s->opt.mem_budget) {
+            auto victim = s->slots.end();
+            for (auto it = s->slots.begin(); it != s->slots.end(); ++it)
+                if (!it->second.busy && it->second.pending.empty() &&
+                    (victim == s->slots.end() || it->second.last_use < victim->second.last_use))
+                    victim = it;
+            if (victim == s->slots.end()) {
+                s->free_slot(sl);
+                return RSD_ENOMEM;
+            }
+            s->resident -= victim->second.bytes;
+            s->free_slot(victim->second);
+            s->slots.erase(victim);
+            ++s->n_evicted;
+        }
+        const int64_t id = s->next_fid++;
+        s->resident += sl.bytes;
+        s->slots.emplace(id, std::move(sl));
+        *factor_id = id;
+        return RSD_OK;
+    });
 }
 
 rsd_status rsd_server_release_factor(rsd_server* s, int64_t factor_id) {
-    if (!s) return RSD_EINVAL;
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->slots.find(factor_id);
-    if (it == s->slots.end()) return RSD_EINVAL;
-    if (it->second.busy || !it->second.pending.empty()) return RSD_EAGAIN;
-    s->resident -= it->second.bytes;
-    s->free_slot(it->second);
-    s->slots.erase(it);
-    return RSD_OK;
+    return no_throw([&]() -> rsd_status {
+        if (!s) return RSD_EINVAL;
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->slots.find(factor_id);
+        if (it == s->slots.end()) return RSD_EINVAL;
+        if (it->second.busy || !it->second.pending.empty()) return RSD_EAGAIN;
+        s->resident -= it->second.bytes;
+        s->free_slot(it->second);
+        s->slots.erase(it);
+        return RSD_OK;
+    });
 }
 
 rsd_status rsd_server_submit_solve(rsd_server* s, int64_t factor_id, const double* rhs,
                                    int64_t nrhs, double* x, int64_t* ticket) {
-    if (!s || !ticket || !rhs || !x || nrhs <= 0) return RSD_EINVAL;
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->slots.find(factor_id);
-    if (it == s->slots.end()) return RSD_EINVAL;
-    if (nrhs > s->opt.max_coalesce) return RSD_EINVAL;
-    const int64_t tk = s->next_ticket++;
-    Request& r = s->reqs[tk];
-    r.fid = factor_id;
-    r.rhs = rhs;
-    r.x = x;
-    r.nrhs = nrhs;
-    r.t_submit = Clock::now();
-    if (!s->started) {
-        s->started = true;
-        s->t_first = r.t_submit;
-    }
-    it->second.pending.push_back(tk);
-    ++s->n_requests;
-    *ticket = tk;
-    s->cv_work.notify_one();
-    return RSD_OK;
+    return no_throw([&]() -> rsd_status {
+        if (!s || !ticket || !rhs || !x || nrhs <= 0) return RSD_EINVAL;
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->slots.find(factor_id);
+        if (it == s->slots.end()) return RSD_EINVAL;
+        if (nrhs > s->opt.max_coalesce) return RSD_EINVAL;
+        const int64_t tk = s->next_ticket++;
+        Request& r = s->reqs[tk];
+        r.fid = factor_id;
+        r.rhs = rhs;
+        r.x = x;
+        r.nrhs = nrhs;
+        r.t_submit = Clock::now();
+        if (!s->started) {
+            s->started = true;
+            s->t_first = r.t_submit;
+        }
+        it->second.pending.push_back(tk);
+        ++s->n_requests;
+        *ticket = tk;
+        s->cv_work.notify_one();
+        return RSD_OK;
+    });
 }
 
 rsd_status rsd_server_wait(rsd_server* s, int64_t ticket, int32_t timeout_ms, rsd_solve_info* info) {
-    if (!s) return RSD_EINVAL;
-    std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return RSD_EINVAL;
-    auto is_done = [&] { return s->reqs[ticket].done; };
-    if (timeout_ms < 0) s->cv_done.wait(lk, is_done);
-    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), is_done)) return RSD_EAGAIN;
-    Request r = s->reqs[ticket];
-    s->reqs.erase(ticket);
-    if (info) *info = r.info;
-    return r.status;
+    return no_throw([&]() -> rsd_status {
+        if (!s) return RSD_EINVAL;
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return RSD_EINVAL;
+        auto is_done = [&] { return s->reqs[ticket].done; };
+        if (timeout_ms < 0) s->cv_done.wait(lk, is_done);
+        else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), is_done)) return RSD_EAGAIN;
+        Request r = s->reqs[ticket];
+        s->reqs.erase(ticket);
+        if (info) *info = r.info;
+        return r.status;
+    });
 }
 
 int32_t rsd_server_poll(rsd_server* s, int64_t ticket) {
@@ -327,31 +348,33 @@ int32_t rsd_server_poll(rsd_server* s, int64_t ticket) {
 }
 
 rsd_status rsd_server_get_stats(rsd_server* s, rsd_server_stats* out) {
-    if (!s || !out) return RSD_EINVAL;
-    std::lock_guard<std::mutex> lk(s->mu);
-    std::memset(out, 0, sizeof(*out));
-    out->n_requests = s->n_requests;
-    out->n_done = s->n_done;
-    out->n_batches = s->n_batches;
-    out->n_factors = (int64_t)s->slots.size();
-    out->n_evicted = s->n_evicted;
-    out->resident_bytes = s->resident;
-    if (!s->lat_ms.empty()) {
-        std::vector<double> v = s->lat_ms;
-        std::sort(v.begin(), v.end());
-        auto pct = [&](double q) {
-            const size_t i = (size_t)std::min<double>((double)v.size() - 1, q * (double)(v.size() - 1) + 0.5);
-            return v[i];
-        };
-        out->p50_ms = pct(0.50);
-        out->p99_ms = pct(0.99);
-    }
-    out->mean_batch_rhs = s->n_batches ? (double)s->rhs_batched / (double)s->n_batches : 0.0;
-    if (s->started) {
-        const double el = std::chrono::duration<double>(Clock::now() - s->t_first).count();
-        out->rhs_per_s = el > 0 ? (double)s->rhs_done / el : 0.0;
-    }
-    return RSD_OK;
+    return no_throw([&]() -> rsd_status {
+        if (!s || !out) return RSD_EINVAL;
+        std::lock_guard<std::mutex> lk(s->mu);
+        std::memset(out, 0, sizeof(*out));
+        out->n_requests = s->n_requests;
+        out->n_done = s->n_done;
+        out->n_batches = s->n_batches;
+        out->n_factors = (int64_t)s->slots.size();
+        out->n_evicted = s->n_evicted;
+        out->resident_bytes = s->resident;
+        if (!s->lat_ms.empty()) {
+            std::vector<double> v = s->lat_ms;
+            std::sort(v.begin(), v.end());
+            auto pct = [&](double q) {
+                const size_t i = (size_t)std::min<double>((double)v.size() - 1, q * (double)(v.size() - 1) + 0.5);
+                return v[i];
+            };
+            out->p50_ms = pct(0.50);
+            out->p99_ms = pct(0.99);
+        }
+        out->mean_batch_rhs = s->n_batches ? (double)s->rhs_batched / (double)s->n_batches : 0.0;
+        if (s->started) {
+            const double el = std::chrono::duration<double>(Clock::now() - s->t_first).count();
+            out->rhs_per_s = el > 0 ? (double)s->rhs_done / el : 0.0;
+        }
+        return RSD_OK;
+    });
 }
 
 void rsd_server_destroy(rsd_server* s) {
