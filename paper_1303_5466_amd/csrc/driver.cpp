@@ -1824,12 +1824,17 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
 
 // Chain class of a box type's interpolation problem, and how many (sector)
 // problems it makes.  Class 0 holds the problems done after one window (the
-// lower levels, needed first), class 1 the longer ones, class 2 the boxes too
-// tall for 16-column sub-panels.
+// lowest levels, needed first), class 3 those done after two or three (the
+// middle levels), class 1 the longer ones (the top levels), class 2 the boxes
+// too tall for 16-column sub-panels.  A window's launches last as long as
+// their largest problem, so the middle levels do not wait for the top
+// levels' windows.
+constexpr int CHAIN_CLASSES = 4;
 static int chain_class(const Factor& f, const IDProblem& I, int ip, int& nprob) {
     nprob = split_sym(f, I, ip) ? I.nsec() : 1;
     const bool narrow = qr_panel_width(I.p / nprob, ip ? 4 : 8) < 16;
-    return narrow ? 2 : (I.k / nprob <= QR_WIN ? 0 : 1);
+    const int windows = (I.k / nprob + QR_WIN - 1) / QR_WIN;
+    return narrow ? 2 : (windows <= 1 ? 0 : (windows <= 3 ? 3 : 1));
 }
 
 // Every launch of a single build: the interpolation chains on two streams of
@@ -1853,12 +1858,12 @@ static void enqueue_single(Factor& fr) {
     }
     // chains: (precision, class) -> problems (chain_class); every chain
     // advances its problems window by window, so the short problems do
-    // not wait for the first windows of the large ones.  Classes 0 and 2
+    // not wait for the first windows of the large ones.  Classes 0, 2 and 3
     // share a stream (class 0 is done almost at once), class 1 has the other:
     // with the level pipeline's stream that is three streams, one hardware
     // queue each under HIP's default of four per process (one is taken by
     // the default stream).
-    constexpr int NCH = 3;
+    constexpr int NCH = CHAIN_CLASSES;
     auto chain_stream = [&](int c) { return f->qr_stream[c == 1 ? 1 : 0]; };
     std::vector<ChainMember> cp[2][NCH];
     std::vector<int> pending(nlev, 0);
@@ -2113,7 +2118,7 @@ struct GroupChains {
 // its own computes; the merged level products may split long K ranges
 // differently, which changes only the rounding order.
 static void enqueue_group(const std::vector<Factor*>& group, GroupChains& gc) {
-    constexpr int NCH = 3;
+    constexpr int NCH = CHAIN_CLASSES;
     constexpr int TAG_LEVELS = 256;   // tag = member * TAG_LEVELS + level
     RSD_HIP(hipGetDevice(&gc.dev));
     for (auto& q : gc.qs) q = StreamPool::get().take();
