@@ -1824,7 +1824,7 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
 
 // Chain class of a box type's interpolation problem, and how many (sector)
 // problems it makes.  Class 0 holds the problems done after one window (the
-// lowest levels, needed first), class 3 those done after two or three (the
+// lowest levels, needed first), class 3 those done after two to four (the
 // middle levels), class 1 the longer ones (the top levels), class 2 the boxes
 // too tall for 16-column sub-panels.  A window's launches last as long as
 // their largest problem, so the middle levels do not wait for the top
@@ -1834,7 +1834,7 @@ static int chain_class(const Factor& f, const IDProblem& I, int ip, int& nprob) 
     nprob = split_sym(f, I, ip) ? I.nsec() : 1;
     const bool narrow = qr_panel_width(I.p / nprob, ip ? 4 : 8) < 16;
     const int windows = (I.k / nprob + QR_WIN - 1) / QR_WIN;
-    return narrow ? 2 : (windows <= 1 ? 0 : (windows <= 3 ? 3 : 1));
+    return narrow ? 2 : (windows <= 1 ? 0 : (windows <= 4 ? 3 : 1));
 }
 
 // Every launch of a single build: the interpolation chains on two streams of
