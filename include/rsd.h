@@ -123,13 +123,15 @@ rsd_status rsd_build_factor(const double* points, int64_t n_points,
                             rsd_factor** out);
 
 /* Several independent factorizations in one call (many grids of uneven size,
- * e.g. a batch of small problems).  Instance i is exactly what
+ * e.g. a batch of small problems).  Instance i is the factor
  * rsd_build_factor(points[i], n_points[i], kernel, a[i], tol, opt, &out[i])
- * would build (same arithmetic, bitwise equal factors).  The instances are
- * built in groups of max_inflight (<= 0 => 64): the interpolation problems
- * of every box type of a group are solved together (one launch per window
- * serves all of them), then the level pipelines run level by level across
- * the group, each instance on its own stream.
+ * would build: the same interpolation matrices bit for bit, and the same
+ * level arithmetic up to the order of rounding (merged products may split
+ * their K ranges differently).  The instances are built in groups of
+ * max_inflight (<= 0 => 64): the interpolation problems of every box type of
+ * a group are solved together (one launch per window serves all of them),
+ * then every level, counted from the leaves, runs as one launch per kernel
+ * over the boxes of all instances of the group.
  *   points, n_points, a  arrays of n_inst entries (a may be NULL => all 1;
  *                        a[i] may be NULL).  Host or device pointers.
  *   opt                  shared by all instances; opt->hip_stream must be NULL.
