@@ -87,12 +87,13 @@ typedef struct rsd_options {
 /* Keep every box's E_i block after the build (for inspection). */
 #define RSD_FLAG_KEEP_E 1
 /* Solve every interpolation problem whole, without splitting mirror-symmetric
- * box types into their four symmetry sectors (same T up to rounding for
- * full-rank problems; for testing and comparison). */
+ * box types into their symmetry sectors (two or four; same T up to rounding
+ * for full-rank problems; for testing and comparison). */
 #define RSD_FLAG_NO_SYMMETRY 2
 /* FP32_REFINE factors: solve the interpolation problems of the float32 levels
  * in float32 too, truncated at max(tol, 1e-6).  By default they are solved in
- * float64 (to tol, symmetry split where full rank) and T is rounded to float32;
+ * float64 (truncated at min(tol, 1e-10) with two or more skeleton layers, at
+ * tol with one; symmetry split where full rank) and T is rounded to float32;
  * the float32 form trades interpolation accuracy for a float32-only build and
  * usually needs more refinement steps. */
 #define RSD_FLAG_FP32_INTERP 4
