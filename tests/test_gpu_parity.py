@@ -502,6 +502,22 @@ def test_symmetry_split_matches_whole_problems():
     fw.close()
 
 
+def test_two_layer_interpolation_truncates_at_1e10():
+    # with two skeleton layers the float64 interpolation keeps every column
+    # (truncation at min(tol, 1e-10)): a looser tolerance gives the same T
+    pts = W.grid_points(40, 24)
+    a = W.coef_sine(pts)
+    f8 = rsd.Factor(pts, a, 1e-8)
+    f10 = rsd.Factor(pts, a, 1e-10)
+    assert f8.stats()["layers"] == f10.stats()["layers"] == 2
+    for b in range(f10.stats()["n_boxes"]):
+        info = f10.box_info(b)
+        if info["r"] > 0 and info["parent"] >= 0:
+            assert np.array_equal(f8.block(b, 0), f10.block(b, 0)), b
+    f8.close()
+    f10.close()
+
+
 @pytest.mark.parametrize("n", [50, 75])
 def test_one_reflection_split_matches_whole_problems(n):
     # odd halves: many box types are mirror-symmetric along one axis only
