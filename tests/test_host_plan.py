@@ -184,3 +184,24 @@ def test_batched_entry_points_reject_bad_arguments_on_the_host():
     ptrs = (C.c_void_p * 2)(None, None)
     assert lib.rsd_solve_batched(0, fs, ptrs, 1, ptrs, None) == rsd.RSD_EINVAL
     assert lib.rsd_solve_batched(2, fs, ptrs, 1, ptrs, None) == rsd.RSD_EINVAL   # null factors
+
+
+def test_single_calls_reject_bad_arguments_on_the_host():
+    """Argument errors of build and solve come back as status codes with a
+    message, before any device work; NULL handles are harmless to free."""
+    import ctypes as C
+    lib = rsd.load()
+    kd = rsd.rsd_kernel(rsd.RSD_KERNEL_LAPLACE, 0.0, None)
+    pts = np.zeros((4, 2))
+    h = C.c_void_p()
+    p = pts.ctypes.data
+    assert lib.rsd_build_factor(None, 4, C.byref(kd), None, 1e-10, None, C.byref(h)) == rsd.RSD_EINVAL
+    assert h.value is None
+    assert lib.rsd_build_factor(p, 0, C.byref(kd), None, 1e-10, None, C.byref(h)) == rsd.RSD_EINVAL
+    for tol in (0.0, -1.0, float("nan"), float("inf")):
+        assert lib.rsd_build_factor(p, 4, C.byref(kd), None, tol, None, C.byref(h)) == rsd.RSD_EINVAL
+        assert "tol" in lib.rsd_last_error().decode()
+    x = np.zeros(4)
+    info = rsd.rsd_solve_info()
+    assert lib.rsd_solve(None, x.ctypes.data, 1, x.ctypes.data, C.byref(info)) == rsd.RSD_EINVAL
+    lib.rsd_free(None)
