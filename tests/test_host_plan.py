@@ -205,3 +205,58 @@ def test_single_calls_reject_bad_arguments_on_the_host():
     info = rsd.rsd_solve_info()
     assert lib.rsd_solve(None, x.ctypes.data, 1, x.ctypes.data, C.byref(info)) == rsd.RSD_EINVAL
     lib.rsd_free(None)
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (50, 50)])
+def test_sector_split_reproduces_the_whole_least_squares_solution(nx, ny):
+    """The symmetry-adapted split the device uses, checked in NumPy on the
+    plan's own sets: for a box type with reflection group G (order 2 or 4),
+    solving one least-squares problem per character ab of G, with entries
+    sum_g chi_ab(g) K(z - g x) on orbit representatives, and recombining
+    T[i, j] = 1/|G| sum_ab chi_ab(g_i) chi_ab(h_j) T_ab[orb_i, orb_j] gives
+    the whole problem's solution of K(Z, X_sk) T = K(Z, X_rs)."""
+    P = rsd.Plan(nx, ny, 8, 2)
+    m = 2
+    done = set()
+    for b in range(P.n_boxes):
+        info = P.box_info(b)
+        grp = P.box_symmetry(b)
+        if grp == 0 or info["r"] == 0 or info["parent"] < 0:
+            continue
+        ax, ay, k = info["ax"], info["ay"], info["k"]
+        if (ax, ay, grp) in done or max(ax, ay) > 40:
+            continue
+        done.add((ax, ay, grp))
+        ids = P.box_points(b)
+        X = np.stack([ids // ny - info["x0"], ids % ny - info["y0"]], axis=1)
+        Z = np.array([(u, v) for u in range(-m, ax + m) for v in range(-m, ay + m)
+                      if not (0 <= u < ax and 0 <= v < ay)])
+        K = lambda zs, xs: 0.5 * np.log(((zs[:, None, :] - xs[None, :, :]) ** 2).sum(-1))
+        T = np.linalg.lstsq(K(Z, X[:k]), K(Z, X[k:]), rcond=None)[0]
+        refl = [g for g in range(4) if (g & grp) == g]             # the group's elements
+        flip = lambda p, g: np.stack([np.where(g & 1, ax - 1 - p[:, 0], p[:, 0]),
+                                      np.where(g & 2, ay - 1 - p[:, 1], p[:, 1])], axis=1)
+        lower = lambda p: (((p[:, 0] < ax // 2) | (not grp & 1)) & ((p[:, 1] < ay // 2) | (not grp & 2)))
+
+        def orbits(pts):
+            rep = pts[lower(pts)]
+            g_of = (np.where(bool(grp & 1) & (pts[:, 0] >= ax // 2), 1, 0) +
+                    np.where(bool(grp & 2) & (pts[:, 1] >= ay // 2), 2, 0))
+            base = flip(pts, g_of)
+            index = {tuple(p): i for i, p in enumerate(rep)}
+            return rep, np.array([index[tuple(p)] for p in base]), g_of
+
+        zr = Z[lower(Z)]
+        skr, sk_orb, sk_g = orbits(X[:k])
+        rsr, rs_orb, rs_g = orbits(X[k:])
+        parity = np.array([0, 1, 1, 0])                             # popcount parity of 0..3
+        chi = lambda ab, g: 1.0 - 2.0 * parity[np.bitwise_and(ab, g)]
+        Trec = np.zeros_like(T)
+        for ab in refl:                                            # characters, labelled like the elements
+            A = sum(chi(ab, g) * K(zr, flip(skr, g)) for g in refl)
+            B = sum(chi(ab, g) * K(zr, flip(rsr, g)) for g in refl)
+            Tab = np.linalg.lstsq(A, B, rcond=None)[0]
+            Trec += (chi(ab, sk_g)[:, None] * chi(ab, rs_g)[None, :]) * Tab[np.ix_(sk_orb, rs_orb)]
+        Trec /= len(refl)
+        assert np.abs(Trec - T).max() <= 1e-6 * np.abs(T).max(), (ax, ay, grp)
+    assert done
