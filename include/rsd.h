@@ -173,8 +173,14 @@ rsd_status rsd_solve_batched(int32_t n, rsd_factor* const* factors,
                              const double* const* rhs, int64_t nrhs,
                              double* const* x, rsd_solve_info* info);
 
-/* y = A x exactly in float64 (direct sum over all pairs, Sec. 5 general
- * formulation), same layouts as rsd_solve.  Used for residuals. */
+/* y = A x with the exact Nystrom matrix in float64 (Sec. 5 general
+ * formulation; no compression), same layouts as rsd_solve; the product the
+ * refinement residual uses.  The off-diagonal part is a Toeplitz-block-
+ * Toeplitz product, computed by circulant embedding in a 2-D FFT of size
+ * Mx x My (powers of two >= 2 nx, 2 ny) when both are at most 4096, else by
+ * a direct sum over all pairs.  Both agree with the direct sum to rounding
+ * (relative 1e-13).  Device work space: 3 N nrhs doubles plus the FFT
+ * fields, allocated per call. */
 rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y);
 
 /* Release a factor and all its device memory.  NULL is a no-op. */
@@ -375,6 +381,26 @@ rsd_status rsd_plan_box_points(const rsd_plan* p, int32_t box, int64_t* dst);
  * factorization splits such a box type's least-squares problem into 2 or 4
  * sector problems. */
 rsd_status rsd_plan_box_symmetry(const rsd_plan* p, int32_t box, int32_t* group);
+/* The sector problems the interpolation of a plan is solved as (Sec. 3.1;
+ * the truncated pivoted QR of Sec. 2.1 per problem), one entry per problem in
+ * the order a chain of all the plan's box types lists them: 7 int32 per entry
+ *   owner  index of the box type's interpolation problem in the plan
+ *   sec    symmetry character solved (0..3), or -1 when solved whole
+ *   g0,gn  the sector group: list index of its first problem, and its size
+ *          (1, 2 or 4); the truncation scale |R11| of every problem is the
+ *          largest column norm over exactly [g0, g0 + gn)
+ *   p,k,r  rows, skeleton and residual columns of the (sector) problem
+ * split = 0 lists every problem whole.  table NULL => only *n_problems is set.
+ * The table is checked as rsd_check_interp_groups does before it is returned.
+ * Host only. */
+rsd_status rsd_plan_interp_groups(const rsd_plan* p, int32_t split, int32_t* n_problems,
+                                  int32_t* table);
+/* Checks a table in that format: every group lies inside the list, contains
+ * its problem and is made of consecutive sectors of one owner with the
+ * characters of one reflection group.  EINVAL (message names the entry) if
+ * not.  Host only; the build runs the same check before its kernels read the
+ * groups. */
+rsd_status rsd_check_interp_groups(int32_t n_problems, const int32_t* table);
 void rsd_plan_free(rsd_plan* p);
 
 /* Grid detection used by rsd_build_factor: on success nx, ny, h and perm

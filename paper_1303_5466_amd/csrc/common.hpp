@@ -171,6 +171,8 @@ struct QRProblemDev {
     int p, k, r, nb;   // nb: sub-panel width (16, 8, 4 or 2 by the LDS budget)
     int sec;           // -1, or the symmetry sector (0..3) this problem solves
     int staged;        // 0: T goes to the T arena; 1: to the staging arena (sector, or another precision)
+    int g0, gn;        // sector group: list index of its first problem and number of sectors
+                       // (g0 = own index and gn = 1 for a problem solved whole)
     int64_t offA;      // p x (k + r) matrix, ld = p
     int64_t offT;      // output T (k x r), ld = k, in the arena staged selects
     int64_t offAux;    // norms (k), tau (k), sub-panel WY (QR_NB^2), window WY (QR_WIN^2), r11

@@ -822,6 +822,73 @@ static int interp_prec(const Factor& f, int level) {
     return f.level_prec[level] && (f.flags & RSD_FLAG_FP32_INTERP) ? 1 : 0;
 }
 
+// The sector problems of one interpolation problem, appended to a chain's
+// problem list: nsec consecutive entries that share the group start g0 (the
+// list index of the first) and size gn = nsec, labelled by the group's
+// characters in order -- all four for two reflections, 0 and 1 for the u
+// reflection alone, 0 and 2 for the v reflection alone -- or one entry with
+// sec = -1 when the problem is solved whole.  Sizes are the problem's divided
+// by nsec; the caller fills in the offsets.
+static void append_sector_problems(std::vector<QRProblemDev>& qp, const IDProblem& I, bool sym) {
+    const int nsec = sym ? I.nsec() : 1;
+    const int g0 = (int)qp.size();
+    for (int sc = 0; sc < nsec; ++sc) {
+        QRProblemDev q{};
+        q.p = I.p / nsec;
+        q.k = I.k / nsec;
+        q.r = I.r / nsec;
+        q.sec = sym ? (I.grp == 2 ? 2 * sc : sc) : -1;
+        q.g0 = g0;
+        q.gn = nsec;
+        qp.push_back(q);
+    }
+}
+
+// Checks the sector groups of a chain's problem list before any kernel reads
+// them: every problem's group [g0, g0 + gn) lies inside the list, contains the
+// problem, and is made of gn consecutive sectors of one interpolation problem
+// (owner[i]: the member problem i came from) with distinct characters of one
+// group (gn = 4: 0..3; gn = 2: {0, 1} or {0, 2}; gn = 1: unsplit, sec = -1).
+static void check_sector_groups(const std::vector<QRProblemDev>& qp, const std::vector<int>& owner) {
+    const int np = (int)qp.size();
+    if ((int)owner.size() != np) throw Error(RSD_EINVAL, "interpolation groups: owner table size");
+    for (int i = 0; i < np; ++i) {
+        const QRProblemDev& q = qp[i];
+        const bool ok_range = q.gn >= 1 && q.g0 >= 0 && q.g0 + q.gn <= np && i >= q.g0 && i < q.g0 + q.gn;
+        if (!ok_range)
+            throw Error(RSD_EINVAL, "interpolation problem " + std::to_string(i) + ": sector group [" +
+                                        std::to_string(q.g0) + ", " + std::to_string(q.g0 + q.gn) +
+                                        ") outside the list of " + std::to_string(np));
+        if (q.gn != 1 && q.gn != 2 && q.gn != 4)
+            throw Error(RSD_EINVAL, "interpolation problem " + std::to_string(i) + ": group of " +
+                                        std::to_string(q.gn) + " sectors");
+        unsigned seen = 0;
+        for (int j = q.g0; j < q.g0 + q.gn; ++j) {
+            const QRProblemDev& o = qp[j];
+            const bool same = owner[j] == owner[i] && o.g0 == q.g0 && o.gn == q.gn && o.p == q.p &&
+                              o.k == q.k && o.r == q.r;
+            const bool lab = q.gn == 1 ? o.sec == -1 : (o.sec >= 0 && o.sec < 4);
+            if (!same || !lab || (lab && q.gn > 1 && (seen >> o.sec) & 1u))
+                throw Error(RSD_EINVAL, "interpolation problem " + std::to_string(i) +
+                                            ": sectors of its group are not one problem's");
+            if (q.gn > 1) seen |= 1u << o.sec;
+        }
+        const bool chars = q.gn == 1 || (q.gn == 4 && seen == 0xFu) ||
+                           (q.gn == 2 && (seen == 0x3u || seen == 0x5u));
+        if (!chars)
+            throw Error(RSD_EINVAL, "interpolation problem " + std::to_string(i) +
+                                        ": group characters do not form one reflection group");
+    }
+    // a member's problems form exactly one group
+    for (int i = 0; i < np;) {
+        const QRProblemDev& q = qp[i];
+        if (q.g0 != i) throw Error(RSD_EINVAL, "interpolation groups are not consecutive");
+        for (int j = i + q.gn; j < np && owner[j] == owner[i]; ++j)
+            throw Error(RSD_EINVAL, "interpolation problem split across groups");
+        i += q.gn;
+    }
+}
+
 // One interpolation problem of a chain: the box type `id` of factor `f`,
 // whose level `level` needs its T; `tag` is reported when it is solved.
 struct ChainMember {
@@ -887,6 +954,7 @@ struct QRChain {
         // staged solutions: symmetric problems (sectors, then combined) and
         // problems whose level keeps T in another precision than this chain
         std::vector<int> staged_ids, staged_sym;
+        std::vector<int> owner;            // member index of every (sector) problem
         for (size_t pi = 0; pi < members.size(); ++pi) {
             Factor& F = *members[pi].f;
             const int id = members[pi].id, lev = members[pi].level;
@@ -906,13 +974,12 @@ struct QRChain {
                 staged_prec.push_back(F.level_prec[lev]);
                 staged_fac.push_back(&F);
             }
+            std::vector<QRProblemDev> secs;
+            append_sector_problems(secs, I, sym);
             for (int sc = 0; sc < nsec; ++sc) {
-                QRProblemDev q;
-                q.p = I.p / nsec;
-                q.k = I.k / nsec;
-                q.r = I.r / nsec;
                 // sector = character ab of the group (bit 0: u, bit 1: v reflection)
-                q.sec = sym ? (I.grp == 2 ? 2 * sc : sc) : -1;
+                QRProblemDev q = secs[sc];
+                q.g0 += (int)qp.size();
                 q.staged = staged ? 1 : 0;
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));
                 if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
@@ -931,6 +998,7 @@ struct QRChain {
                 aux_el += 2 * q.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
                 iaux_el += q.k + 8 + 4 * QR_WIN;
                 qp.push_back(q);
+                owner.push_back((int)pi);
                 prob_tag.push_back(members[pi].tag);
                 lgh.push_back(F.kd.logh);
                 offA.push_back(q.offA);
@@ -960,6 +1028,7 @@ struct QRChain {
             }
         }
         np = (int)qp.size();
+        check_sector_groups(qp, owner);
         DevBuf& dgemm = tmp();
         dA = &tmp(); daux = &tmp(); diaux = &tmp(); dws = &tmp(); dsec = &tmp();
         HostPack pk;
@@ -3019,6 +3088,46 @@ rsd_status rsd_plan_box_symmetry(const rsd_plan* p, int32_t box, int32_t* group)
             const auto& I = p->plan.idps[L.idp];
             if (I.sym) *group = I.grp;
         }
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_plan_interp_groups(const rsd_plan* p, int32_t split, int32_t* n_problems,
+                                  int32_t* table) {
+    return guarded([&]() {
+        if (!p || !n_problems) throw rsd::Error(RSD_EINVAL, "null argument");
+        std::vector<rsd::QRProblemDev> qp;
+        std::vector<int> owner;
+        for (size_t id = 0; id < p->plan.idps.size(); ++id) {
+            const rsd::IDProblem& I = p->plan.idps[id];
+            rsd::append_sector_problems(qp, I, split != 0 && I.sym);
+            owner.resize(qp.size(), (int)id);
+        }
+        rsd::check_sector_groups(qp, owner);
+        *n_problems = (int32_t)qp.size();
+        if (table)
+            for (size_t i = 0; i < qp.size(); ++i) {
+                int32_t* t = table + 7 * i;
+                t[0] = owner[i]; t[1] = qp[i].sec; t[2] = qp[i].g0; t[3] = qp[i].gn;
+                t[4] = qp[i].p; t[5] = qp[i].k; t[6] = qp[i].r;
+            }
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_check_interp_groups(int32_t n_problems, const int32_t* table) {
+    return guarded([&]() {
+        if (n_problems < 0 || (n_problems > 0 && !table)) throw rsd::Error(RSD_EINVAL, "bad table");
+        std::vector<rsd::QRProblemDev> qp(n_problems);
+        std::vector<int> owner(n_problems);
+        for (int i = 0; i < n_problems; ++i) {
+            const int32_t* t = table + 7 * i;
+            owner[i] = t[0];
+            qp[i] = rsd::QRProblemDev{};
+            qp[i].sec = t[1]; qp[i].g0 = t[2]; qp[i].gn = t[3];
+            qp[i].p = t[4]; qp[i].k = t[5]; qp[i].r = t[6];
+        }
+        rsd::check_sector_groups(qp, owner);
         return RSD_OK;
     });
 }

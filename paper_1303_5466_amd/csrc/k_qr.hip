@@ -127,15 +127,16 @@ __global__ void __launch_bounds__(256) qr_init_kernel(T* __restrict__ A, T* __re
 }
 
 // Reference pivot of the truncation rule |R_jj| <= tol |R_11|: the largest
-// column norm of the problem, or, for the four sectors of a symmetric
-// problem (consecutive in the list), the largest over all four, so that a
-// split problem truncates against the same scale as the whole one.
+// column norm of the problem, or, for the sectors of a symmetric problem
+// (two or four, consecutive in the list from g0), the largest over all of
+// them, so that a split problem truncates against the same scale as the
+// whole one.  The host checks every group against the list before launch.
 template <typename T>
 __global__ void __launch_bounds__(256) qr_r11_kernel(T* __restrict__ aux, int* __restrict__ iaux,
                                                       const QRProblemDev* __restrict__ probs) {
     const int pi = blockIdx.x;
     const QRProblemDev q = probs[pi];
-    const int first = q.sec < 0 ? pi : pi - q.sec, count = q.sec < 0 ? 1 : 4;
+    const int first = q.g0, count = q.gn;
     T m = T(0);
     for (int g = 0; g < count; ++g) {
         const QRProblemDev qg = probs[first + g];

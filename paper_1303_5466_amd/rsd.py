@@ -114,6 +114,8 @@ EXPORTS = {
     "rsd_plan_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
     "rsd_plan_box_points": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "rsd_plan_box_symmetry": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "rsd_plan_interp_groups": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_void_p]),
+    "rsd_check_interp_groups": (C.c_int, [C.c_int32, C.c_void_p]),
     "rsd_plan_free": (None, [C.c_void_p]),
     "rsd_detect_grid": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int64), C.POINTER(C.c_double), C.c_void_p]),
@@ -320,6 +322,7 @@ class Server:
         _check(lib.rsd_server_create(C.byref(opt), C.byref(h)))
         self._h = h
         self._live = {}
+        self._n = {}          # factor id -> number of points
 
     def submit_factor(self, points, a=None, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0,
                       layers=0, max_refine=0, refine_tol=0.0):
@@ -334,22 +337,54 @@ class Server:
         fid = C.c_int64()
         _check(load().rsd_server_submit_factor(self._h, pp, points.shape[0], C.byref(kd), ap, tol,
                                                C.byref(opt), C.byref(fid)))
+        self._n[fid.value] = int(points.shape[0])
         return fid.value
 
     def release_factor(self, fid):
         _check(load().rsd_server_release_factor(self._h, fid))
+        self._n.pop(fid, None)
 
     def submit_solve(self, fid, rhs, out):
-        """rhs, out: N x nrhs column-major float64 (NumPy Fortran order or a
-        contiguous torch tensor of shape (nrhs, N))."""
+        """Queue out = A^{-1} rhs.  rhs, out: NumPy arrays of shape (N,) or
+        (N, nrhs) (any layout or float dtype for rhs; out must be float64 of
+        the same shape, and is filled when the ticket is waited), or contiguous
+        float64 torch tensors on the device of shape (N,) or (nrhs, N) (= N x
+        nrhs column-major).  Shapes are checked against the factor's N."""
+        n = self._n.get(fid)
+        if n is None:
+            raise RsdError(RSD_EINVAL, f"unknown factor {fid}")
+        copy_back = None
         if isinstance(rhs, np.ndarray):
+            if rhs.ndim not in (1, 2) or rhs.shape[0] != n:
+                raise RsdError(RSD_EINVAL, f"rhs shape {rhs.shape} does not match N = {n}")
             nrhs = 1 if rhs.ndim == 1 else rhs.shape[1]
+            if not isinstance(out, np.ndarray) or out.shape != rhs.shape or out.dtype != np.float64:
+                raise RsdError(RSD_EINVAL, "out must be a float64 NumPy array of the rhs shape")
+            rhs = np.asfortranarray(rhs, dtype=np.float64)
+            if not out.flags.f_contiguous:
+                copy_back = out
+                out = np.zeros(out.shape, dtype=np.float64, order="F")
         else:
-            nrhs = 1 if rhs.dim() == 1 else rhs.shape[0]
+            import torch
+            if not (isinstance(rhs, torch.Tensor) and isinstance(out, torch.Tensor)):
+                raise RsdError(RSD_EINVAL, "rhs and out must both be NumPy arrays or torch tensors")
+            if rhs.dim() == 1:
+                nrhs = 1
+                ok = rhs.shape[0] == n
+            else:
+                nrhs = rhs.shape[0]
+                ok = rhs.dim() == 2 and rhs.shape[1] == n
+            if not ok:
+                raise RsdError(RSD_EINVAL, f"rhs shape {tuple(rhs.shape)} is not (N,) or (nrhs, N), N = {n}")
+            for name, t in (("rhs", rhs), ("out", out)):
+                if t.dtype != torch.float64 or not t.is_contiguous():
+                    raise RsdError(RSD_EINVAL, f"{name} must be a contiguous float64 tensor")
+            if out.shape != rhs.shape or out.device != rhs.device:
+                raise RsdError(RSD_EINVAL, "out must have the shape and device of rhs")
         tk = C.c_int64()
         _check(load().rsd_server_submit_solve(self._h, fid, _ptr(rhs)[0], nrhs, _ptr(out)[0],
                                               C.byref(tk)))
-        self._live[tk.value] = (rhs, out)
+        self._live[tk.value] = (rhs, out, copy_back)
         return tk.value
 
     def wait(self, ticket, timeout_ms=-1):
@@ -357,7 +392,9 @@ class Server:
         info = rsd_solve_info()
         st = load().rsd_server_wait(self._h, ticket, timeout_ms, C.byref(info))
         if st != RSD_EAGAIN:
-            self._live.pop(ticket, None)
+            live = self._live.pop(ticket, None)
+            if live is not None and live[2] is not None:
+                live[2][...] = live[1]
         return st, info
 
     def poll(self, ticket):
@@ -416,11 +453,28 @@ class Plan:
         _check(load().rsd_plan_box_symmetry(self._h, box, C.byref(g)))
         return g.value
 
+    def interp_groups(self, split=True):
+        """Sector problems of the plan's interpolation (rsd_plan_interp_groups):
+        an (n, 7) int32 array of (owner, sec, g0, gn, p, k, r) rows."""
+        lib = load()
+        n = C.c_int32()
+        _check(lib.rsd_plan_interp_groups(self._h, int(bool(split)), C.byref(n), None))
+        out = np.zeros((n.value, 7), dtype=np.int32)
+        _check(lib.rsd_plan_interp_groups(self._h, int(bool(split)), C.byref(n), out.ctypes.data))
+        return out
+
     def box_points(self, box):
         info = self.box_info(box)
         out = np.zeros(info["k"] + info["r"], dtype=np.int64)
         _check(load().rsd_plan_box_points(self._h, box, out.ctypes.data))
         return out
+
+
+def check_interp_groups(table):
+    """Run the library's sector-group check on an (n, 7) int32 table; raises
+    RsdError (EINVAL) when a group is not one problem's consecutive sectors."""
+    t = np.ascontiguousarray(table, dtype=np.int32).reshape(-1, 7)
+    _check(load().rsd_check_interp_groups(t.shape[0], t.ctypes.data if t.size else None))
 
 
 PROF_CLASSES = ["factor_gemm_f64", "factor_gemm_f32", "interp", "gj_pivot", "assembly",

@@ -260,3 +260,102 @@ def test_sector_split_reproduces_the_whole_least_squares_solution(nx, ny):
         Trec /= len(refl)
         assert np.abs(Trec - T).max() <= 1e-6 * np.abs(T).max(), (ax, ay, grp)
     assert done
+
+
+def _sides_of_batch(n=6):
+    rng = np.random.default_rng(3)
+    return [int(s) for s in rng.integers(32, 257, size=n)]
+
+
+@pytest.mark.parametrize("nx,ny", [(40, 24), (37, 37), (50, 50), (75, 75), (64, 64)]
+                         + [(s, s) for s in _sides_of_batch()])
+def test_interp_sector_groups(nx, ny):
+    """Every interpolation (sector) problem's truncation-scale group is exactly
+    its own problem's sectors (Sec. 2.1: the ID truncates at tol |R11| of the
+    whole problem): consecutive, inside the list, one owner, the characters of
+    the box's reflection group.  The earlier kernel took [i - sec, i - sec + 4),
+    which is wrong for every two-sector group; check that such groups exist on
+    these grids where expected and that the checker rejects that grouping."""
+    plan = rsd.Plan(nx, ny, 8, 2)
+    t = plan.interp_groups(split=True)
+    n = t.shape[0]
+    assert n > 0
+    # the group sizes seen by box queries: every split owner's size is the
+    # order of some box's reflection group
+    orders = {[1, 2, 2, 4][plan.box_symmetry(b)] for b in range(plan.n_boxes)}
+    assert set(np.unique(t[:, 3]).tolist()) <= orders | {1}
+    two_sector = 0
+    i = 0
+    while i < n:
+        owner, sec, g0, gn, p, k, r = t[i]
+        assert g0 == i and gn in (1, 2, 4)
+        rows = t[i:i + gn]
+        assert (rows[:, 0] == owner).all() and (rows[:, 2] == g0).all() and (rows[:, 3] == gn).all()
+        secs = sorted(rows[:, 1].tolist())
+        if gn == 1:
+            assert secs == [-1]
+        elif gn == 2:
+            two_sector += 1
+            assert secs in ([0, 1], [0, 2])
+        else:
+            assert secs == [0, 1, 2, 3]
+        assert (rows[:, 4:] == rows[0, 4:]).all()
+        # the old rule's group for the last sector of a two-sector problem
+        if gn == 2:
+            last = i + 1
+            old_first = last - int(t[last, 1])
+            assert (old_first, old_first + 4) != (g0, g0 + gn)
+        i += gn
+    rsd.check_interp_groups(t)
+    # whole problems: one entry each, sizes add up to the split ones
+    w = plan.interp_groups(split=False)
+    assert (w[:, 1] == -1).all() and (w[:, 3] == 1).all()
+    assert (w[:, 2] == np.arange(w.shape[0])).all()
+    for o in np.unique(t[:, 0]):
+        ts = t[t[:, 0] == o]
+        wo = w[w[:, 0] == o]
+        assert wo.shape[0] == 1
+        assert (ts[:, 4:].sum(axis=0) == wo[0, 4:]).all()
+    # which groups have two sectors: odd-half grids have them, 64^2 has none
+    if (nx, ny) in [(40, 24), (50, 50), (75, 75)]:
+        assert two_sector > 0
+    if (nx, ny) == (64, 64):
+        assert two_sector == 0
+    # the earlier grouping (g0 = i - sec, gn = 4) is rejected wherever a
+    # two-sector group exists
+    bad = t.copy()
+    for j in range(n):
+        if bad[j, 1] >= 0:
+            bad[j, 2] = j - bad[j, 1]
+            bad[j, 3] = 4
+    if two_sector:
+        with pytest.raises(rsd.RsdError) as e:
+            rsd.check_interp_groups(bad)
+        assert e.value.status == rsd.RSD_EINVAL
+    else:
+        rsd.check_interp_groups(bad)
+
+
+def test_interp_group_checker_rejects_malformed_tables():
+    t = rsd.Plan(40, 24, 8, 2).interp_groups(split=True)
+    rsd.check_interp_groups(t)
+    gi = int(np.nonzero(t[:, 3] > 1)[0][0])
+    for mutate in (
+        lambda x: x.__setitem__((gi, 2), -1),               # group before the list
+        lambda x: x.__setitem__((gi, 3), 3),                # odd group size
+        lambda x: x.__setitem__((gi + 1, 1), x[gi, 1]),     # repeated character
+        lambda x: x.__setitem__((gi + 1, 0), x[gi, 0] + 1), # two owners in one group
+        lambda x: x.__setitem__((gi, 5), x[gi, 5] + 1),     # sectors of unequal size
+    ):
+        bad = t.copy()
+        mutate(bad)
+        with pytest.raises(rsd.RsdError):
+            rsd.check_interp_groups(bad)
+    last = t[-1:].copy()
+    last[0, 2], last[0, 3] = 0, 1
+    last[0, 1] = -1
+    rsd.check_interp_groups(last)
+    past = t.copy()
+    past[-1, 3] = past[-1, 3] + 1
+    with pytest.raises(rsd.RsdError):
+        rsd.check_interp_groups(past)
