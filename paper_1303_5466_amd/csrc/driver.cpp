@@ -974,12 +974,12 @@ struct QRChain {
                 staged_prec.push_back(F.level_prec[lev]);
                 staged_fac.push_back(&F);
             }
-            std::vector<QRProblemDev> secs;
-            append_sector_problems(secs, I, sym);
+            // the sectors (characters of the reflection group, bit 0: u, bit 1: v)
+            // are appended with their group; offsets follow
+            const size_t base = qp.size();
+            append_sector_problems(qp, I, sym);
             for (int sc = 0; sc < nsec; ++sc) {
-                // sector = character ab of the group (bit 0: u, bit 1: v reflection)
-                QRProblemDev q = secs[sc];
-                q.g0 += (int)qp.size();
+                QRProblemDev& q = qp[base + sc];
                 q.staged = staged ? 1 : 0;
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));
                 if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
@@ -997,7 +997,6 @@ struct QRChain {
                 A_el += (int64_t)q.p * n;
                 aux_el += 2 * q.k + QR_NB * QR_NB + QR_WIN * QR_WIN + 8;
                 iaux_el += q.k + 8 + 4 * QR_WIN;
-                qp.push_back(q);
                 owner.push_back((int)pi);
                 prob_tag.push_back(members[pi].tag);
                 lgh.push_back(F.kd.logh);
