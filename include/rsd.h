@@ -289,12 +289,23 @@ rsd_status rsd_profile_record(int64_t i, int32_t* cls, double* ms, double* flops
  *
  * A server keeps factors resident in device memory and answers solve
  * requests (Algorithm 6 applied to queued right-hand sides) from worker
- * threads.  Requests for one factor that are waiting together are coalesced
- * into one multi-RHS solve (padded to a power of two of columns, so each
- * factor keeps at most seven solve plans); different factors are served
- * concurrently, each on its own stream.  Admission is by memory and slots:
- * a new factor evicts the least recently used idle factors (no queued or
- * running solves) until it fits, else the submission fails with ENOMEM.
+ * threads; factor requests are built by a builder thread of its own, so a
+ * build overlaps on the device with the solves of resident factors.
+ * Requests for one factor that are waiting together are coalesced into one
+ * multi-RHS solve (padded to a power of two of columns, so each factor keeps
+ * at most seven solve plans); different factors are served concurrently,
+ * each on its own stream.
+ *
+ * Admission is by memory and slots, continuously: a factor request is
+ * queued (first come, first served) and admitted when its device bytes
+ * (rsd_estimate_factor_bytes plus the coalescing and solve vectors of a full
+ * batch, 6 N max_coalesce doubles) fit in the budget beside the resident
+ * factors and a slot is free.  With evict_idle = 1 the least recently used
+ * idle factors (no queued or running solves) are evicted to make room; with
+ * evict_idle = 0 the request waits until factors are released.  A request
+ * larger than the whole budget fails at once with ENOMEM.  Solves may be
+ * submitted for a factor that is still queued or building; they run once it
+ * is resident (or complete with the build's error status).
  * Latency = submission to completion (host clock). */
 typedef struct rsd_server rsd_server;
 
@@ -304,36 +315,49 @@ typedef struct rsd_server_options {
     int32_t n_workers;     /* solve threads; 0 => 2                            */
     int32_t max_coalesce;  /* right-hand sides per coalesced solve; 0 => 64    */
     int32_t device;        /* HIP device; < 0 => the current device            */
+    int32_t evict_idle;    /* 1 => evict idle factors (LRU) to admit new ones;
+                              0 => queue factor requests until memory frees    */
 } rsd_server_options;
 
 typedef struct rsd_server_stats {
     int64_t n_requests;    /* solve requests submitted                        */
     int64_t n_done;        /* completed (any status)                          */
     int64_t n_batches;     /* coalesced solves run                            */
-    int64_t n_factors;     /* resident factors                                */
+    int64_t n_factors;     /* resident factors (built and admitted)           */
     int64_t n_evicted;     /* factors evicted for admission                   */
-    int64_t resident_bytes;
+    int64_t resident_bytes;/* bytes of resident and building factors          */
     double p50_ms, p99_ms; /* request latency percentiles                     */
     double mean_batch_rhs; /* right-hand sides per coalesced solve (unpadded) */
     double rhs_per_s;      /* completed right-hand sides / seconds since the
                               first submission                                 */
+    int64_t n_queued_factors; /* factor requests waiting for admission or
+                                 being built                                   */
+    int64_t n_built;       /* factor builds completed (any status)            */
 } rsd_server_stats;
 
-/* opt NULL => defaults.  Starts the worker threads. */
+/* opt NULL => defaults.  Starts the worker threads and the builder thread. */
 rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out);
-/* Builds a factor (as rsd_build_factor; opt->hip_stream must be NULL, the
- * server gives each factor its own stream) and makes it resident.
- * *factor_id receives its handle for submit_solve.  ENOMEM when it cannot be
- * admitted even after evicting every idle factor. */
+/* Queues a factor request (as rsd_build_factor, Sec. 2.4 / Algorithm 1;
+ * opt->hip_stream must be NULL: the server gives each factor its own
+ * stream).  points, a (and kernel->contrast_b) are copied before the call
+ * returns (host or device pointers); the grid is checked at once (ENOTGRID,
+ * EINVAL).  *factor_id receives its handle for submit_solve and
+ * wait_factor.  ENOMEM at once when the factor alone exceeds the budget;
+ * otherwise the request waits for admission (see above). */
 rsd_status rsd_server_submit_factor(rsd_server* s, const double* points, int64_t n_points,
                                     const rsd_kernel* kernel, const double* a, double tol,
                                     const rsd_options* opt, int64_t* factor_id);
-/* Evicts a factor; EAGAIN while it has queued or running solves, EINVAL for
- * an unknown id. */
+/* Waits up to timeout_ms (< 0 => forever) until a factor request is built:
+ * OK once resident, the build's status if it failed, EAGAIN on timeout,
+ * EINVAL for an unknown or released id. */
+rsd_status rsd_server_wait_factor(rsd_server* s, int64_t factor_id, int32_t timeout_ms);
+/* Releases a factor (resident, or still queued); EAGAIN while it is being
+ * built or has queued or running solves, EINVAL for an unknown id. */
 rsd_status rsd_server_release_factor(rsd_server* s, int64_t factor_id);
 /* Queues x = A^{-1} rhs (N x nrhs column-major, host or device pointers).
  * Both buffers are borrowed until the request completes (rsd_server_wait).
- * *ticket identifies the request.  EINVAL for an unknown factor. */
+ * *ticket identifies the request.  EINVAL for an unknown factor or nrhs
+ * above max_coalesce. */
 rsd_status rsd_server_submit_solve(rsd_server* s, int64_t factor_id, const double* rhs,
                                    int64_t nrhs, double* x, int64_t* ticket);
 /* Waits up to timeout_ms (< 0 => forever) for a request; returns its status
@@ -343,7 +367,8 @@ rsd_status rsd_server_wait(rsd_server* s, int64_t ticket, int32_t timeout_ms, rs
 /* 1 when the request has completed, 0 while pending, -1 for an unknown ticket. */
 int32_t rsd_server_poll(rsd_server* s, int64_t ticket);
 rsd_status rsd_server_get_stats(rsd_server* s, rsd_server_stats* out);
-/* Finishes the queued requests, stops the workers and frees every factor. */
+/* Finishes the queued requests (builds included), stops the threads and
+ * frees every factor. */
 void rsd_server_destroy(rsd_server* s);
 
 /* ---- dense building blocks ------------------------------------------------ */
@@ -363,6 +388,12 @@ rsd_status rsd_gj_invert(int32_t dtype, int32_t n, void* A, int32_t lda);
 
 /* ---- host-only planning (no device needed) ------------------------------ */
 
+/* Device bytes of the factor rsd_build_factor would keep for an nx x ny grid
+ * with these options (the per-box (k + r)^2 blocks of Algorithm 1 in the
+ * Schur form and the interpolation blocks; equal to
+ * rsd_factor_stats.factor_bytes of the built factor).  Host only. */
+rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, double tol, const rsd_options* opt,
+                                     int64_t* bytes);
 /* Number of boxes and levels the tree of Sec. 2.2 / Sec. 3.1 produces for an
  * nx x ny grid, and per-box sizes.  Pure host computation, usable without a
  * GPU; boxes are numbered level by level from the leaves. */

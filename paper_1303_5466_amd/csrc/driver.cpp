@@ -3054,6 +3054,50 @@ rsd_status rsd_plan_create(int64_t nx, int64_t ny, int32_t leaf_side, int32_t la
     });
 }
 
+rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, double tol, const rsd_options* opt,
+                                     int64_t* bytes) {
+    return guarded([&]() {
+        if (!bytes) throw rsd::Error(RSD_EINVAL, "bytes is null");
+        *bytes = 0;
+        if (nx <= 0 || ny <= 0) throw rsd::Error(RSD_EINVAL, "grid sides must be positive");
+        if (!(tol > 0) || !std::isfinite(tol)) throw rsd::Error(RSD_EINVAL, "tol must be a positive number");
+        rsd_options o{};
+        if (opt) o = *opt;
+        if (o.precision != RSD_PREC_FP64 && o.precision != RSD_PREC_FP32_REFINE)
+            throw rsd::Error(RSD_EINVAL, "unknown precision");
+        const int leaf = o.leaf_side > 0 ? o.leaf_side : 8;
+        const int m = o.layers > 0 ? o.layers : rsd::layers_for_tol(tol);
+        rsd::Plan P;
+        try {
+            P = rsd::cached_plan(nx, ny, leaf, m);
+        } catch (const std::exception& e) {
+            throw rsd::Error(RSD_EINVAL, e.what());
+        }
+        // the arenas build_prepare allocates: one (k + r)^2 block per box and
+        // one k x r interpolation block per layout that has one, in the
+        // precision of the level (float32 below the root for FP32_REFINE)
+        const int top = (int)P.levels.size() - 1;
+        auto es = [&](int level) -> int64_t {
+            return o.precision == RSD_PREC_FP32_REFINE && level < top ? 4 : 8;
+        };
+        int64_t f64 = 0, f32 = 0, t64 = 0, t32 = 0;
+        std::vector<int> layout_level(P.layouts.size(), -1);
+        for (auto& b : P.boxes) {
+            layout_level[b.layout] = b.level;
+            const int64_t mm = (int64_t)b.k + b.r;
+            (es(b.level) == 4 ? f32 : f64) += mm * mm;
+        }
+        for (size_t li = 0; li < P.layouts.size(); ++li) {
+            const rsd::Layout& L = P.layouts[li];
+            if (L.idp < 0) continue;
+            (es(layout_level[li]) == 4 ? t32 : t64) += (int64_t)L.k * L.r;
+        }
+        *bytes = 8 * (std::max<int64_t>(f64, 1) + std::max<int64_t>(t64, 1)) +
+                 4 * (std::max<int64_t>(f32, 1) + std::max<int64_t>(t32, 1));
+        return RSD_OK;
+    });
+}
+
 int32_t rsd_plan_n_boxes(const rsd_plan* p) { return p ? (int32_t)p->plan.boxes.size() : 0; }
 int32_t rsd_plan_n_levels(const rsd_plan* p) { return p ? (int32_t)p->plan.levels.size() : 0; }
 

@@ -1,8 +1,11 @@
 // Serving runtime: resident factors in device memory, queued solve requests
 // coalesced per factor and answered by worker threads (the inverse apply of
-// Algorithm 6 for many clients).  Built only on the public interface of the
-// library (rsd_build_factor / rsd_solve / rsd_free) plus HIP streams and
-// copies, so a factor here is exactly what a direct call would build.
+// Algorithm 6 for many clients), and factor requests admitted by memory and
+// slots as they free up and built by a builder thread beside the solves.
+// Built only on the public interface of the library (rsd_build_factor /
+// rsd_solve / rsd_free / rsd_estimate_factor_bytes / rsd_detect_grid) plus
+// HIP streams and copies, so a factor here is exactly what a direct call
+// would build.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,6 +14,8 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
+#include <stdexcept>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -34,11 +39,24 @@ struct Request {
     rsd_solve_info info{0, -1.0};
 };
 
+// A factor request's inputs, owned by the server from submission until the
+// build (the caller's buffers are borrowed for the submit call only).
+struct FactorJob {
+    std::vector<double> points, a, b;
+    rsd_kernel kernel{};
+    double tol = 0;
+    rsd_options opt{};
+};
+
+enum SlotState { QUEUED = 0, BUILDING = 1, READY = 2 };
+
 struct Slot {
+    int state = QUEUED;
+    std::unique_ptr<FactorJob> job;  // QUEUED and BUILDING
     rsd_factor* f = nullptr;
     hipStream_t stream = nullptr;
     int64_t n = 0;
-    int64_t bytes = 0;
+    int64_t bytes = 0;               // admission size (estimate until built)
     bool busy = false;
     Clock::time_point last_use;
     std::deque<int64_t> pending;     // tickets, oldest first
@@ -57,26 +75,35 @@ int64_t pow2_at_least(int64_t v) {
 struct rsd_server {
     rsd_server_options opt{};
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::map<int64_t, Slot> slots;
+    std::condition_variable cv_work, cv_done, cv_build;
+    std::map<int64_t, Slot> slots;                 // QUEUED, BUILDING and READY factors
+    std::map<int64_t, rsd_status> failed;          // ids whose build failed
     std::unordered_map<int64_t, Request> reqs;
     std::vector<std::thread> workers;
+    std::thread builder;
     bool stop = false;
     int64_t next_fid = 1, next_ticket = 1;
-    int64_t resident = 0;
+    int64_t resident = 0;                          // READY + BUILDING bytes
     // statistics
     int64_t n_requests = 0, n_done = 0, n_batches = 0, n_evicted = 0, rhs_done = 0, rhs_batched = 0;
+    int64_t n_built = 0;
     std::vector<double> lat_ms;
     bool started = false;
     Clock::time_point t_first;
 
-    // slot with queued work, not busy, whose oldest request is the oldest overall
+    int64_t n_ready() const {
+        int64_t c = 0;
+        for (auto& kv : slots) c += kv.second.state != QUEUED;
+        return c;
+    }
+
+    // READY slot with queued work, not busy, whose oldest request is the oldest overall
     Slot* ready(int64_t* fid) {
         Slot* best = nullptr;
         int64_t best_ticket = INT64_MAX;
         for (auto& kv : slots) {
             Slot& sl = kv.second;
-            if (sl.busy || sl.pending.empty()) continue;
+            if (sl.state != READY || sl.busy || sl.pending.empty()) continue;
             if (sl.pending.front() < best_ticket) {
                 best_ticket = sl.pending.front();
                 best = &sl;
@@ -93,13 +120,127 @@ struct rsd_server {
         sl = Slot{};
     }
 
+    void complete(Request& r, rsd_status st, Clock::time_point now) {
+        r.done = true;
+        r.t_done = now;
+        r.status = st;
+        lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r.t_submit).count());
+        rhs_done += r.nrhs;
+        ++n_done;
+    }
+
+    // Frees room for `bytes` more (and one more slot) by evicting least
+    // recently used idle READY factors when allowed; true when it fits.
+    bool make_room(int64_t bytes) {
+        for (;;) {
+            if (n_ready() < opt.max_slots && resident + bytes <= opt.mem_budget) return true;
+            if (!opt.evict_idle) return false;
+            auto victim = slots.end();
+            for (auto it = slots.begin(); it != slots.end(); ++it) {
+                const Slot& v = it->second;
+                if (v.state == READY && !v.busy && v.pending.empty() &&
+                    (victim == slots.end() || v.last_use < victim->second.last_use))
+                    victim = it;
+            }
+            if (victim == slots.end()) return false;
+            resident -= victim->second.bytes;
+            free_slot(victim->second);
+            slots.erase(victim);
+            ++n_evicted;
+        }
+    }
+
+    // Admits queued factor requests in submission order as memory and slots
+    // free up, and builds them one at a time on their own streams (the solve
+    // workers keep serving resident factors meanwhile).
+    void build_loop() {
+        if (opt.device >= 0) (void)hipSetDevice(opt.device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            int64_t fid = 0;
+            Slot* sl = nullptr;
+            cv_build.wait(lk, [&] {
+                sl = nullptr;
+                for (auto& kv : slots)
+                    if (kv.second.state == QUEUED) { sl = &kv.second; fid = kv.first; break; }
+                return stop || (sl && make_room(sl->bytes));
+            });
+            if (!sl) return;   // stop and nothing queued
+            if (!make_room(sl->bytes)) {
+                // stopping with a request that cannot be admitted: fail it
+                fail_slot(fid, RSD_ENOMEM);
+                continue;
+            }
+            sl->state = BUILDING;
+            resident += sl->bytes;
+            FactorJob* job = sl->job.get();
+            lk.unlock();
+            rsd_factor* fac = nullptr;
+            hipStream_t stream = nullptr;
+            rsd_status st = RSD_OK;
+            if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipGetLastError();
+                stream = nullptr;
+                st = RSD_EDEVICE;
+            } else {
+                rsd_options o = job->opt;
+                o.hip_stream = stream;
+                if (opt.device >= 0) o.device = opt.device;
+                rsd_kernel kd = job->kernel;
+                kd.contrast_b = job->b.empty() ? nullptr : job->b.data();
+                st = rsd_build_factor(job->points.data(), (int64_t)job->points.size() / 2, &kd,
+                                      job->a.empty() ? nullptr : job->a.data(), job->tol, &o, &fac);
+            }
+            rsd_factor_stats fs{};
+            if (st == RSD_OK) (void)rsd_factor_get_stats(fac, &fs);
+            lk.lock();
+            ++n_built;
+            Slot& s2 = slots[fid];      // BUILDING slots are never erased
+            resident -= s2.bytes;
+            s2.job.reset();
+            if (st != RSD_OK) {
+                if (fac) rsd_free(fac);
+                if (stream) (void)hipStreamDestroy(stream);
+                fail_slot(fid, st);
+            } else {
+                s2.f = fac;
+                s2.stream = stream;
+                s2.bytes = fs.factor_bytes + batch_bytes(s2.n);
+                resident += s2.bytes;
+                s2.state = READY;
+                s2.last_use = Clock::now();
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();
+            cv_build.notify_all();
+        }
+    }
+
+    // removes a QUEUED or BUILDING slot whose build failed; its queued solves
+    // complete with the build's status
+    void fail_slot(int64_t fid, rsd_status st) {
+        auto it = slots.find(fid);
+        if (it == slots.end()) return;
+        const auto now = Clock::now();
+        for (int64_t tk : it->second.pending) complete(reqs[tk], st, now);
+        it->second.pending.clear();
+        slots.erase(it);
+        failed[fid] = st;
+        cv_done.notify_all();
+        cv_work.notify_all();
+    }
+
+    int64_t batch_bytes(int64_t n) const {
+        return (int64_t)(6 * n * opt.max_coalesce) * (int64_t)sizeof(double);
+    }
+
     void worker() {
         if (opt.device >= 0) (void)hipSetDevice(opt.device);
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             int64_t fid = 0;
             Slot* sl = nullptr;
-            cv_work.wait(lk, [&] { return (sl = ready(&fid)) != nullptr || stop; });
+            cv_work.wait(lk, [&] { return (sl = ready(&fid)) != nullptr || (stop && !building_or_queued()); });
             if (!sl) return;   // stop and nothing left
             sl->busy = true;
             std::vector<int64_t> batch;
@@ -118,14 +259,7 @@ struct rsd_server {
             rsd_status st = run_batch(*sl, rq, cols);
             lk.lock();
             const auto now = Clock::now();
-            for (Request* r : rq) {
-                r->done = true;
-                r->t_done = now;
-                if (st != RSD_OK && r->status == RSD_OK) r->status = st;
-                lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
-                rhs_done += r->nrhs;
-            }
-            n_done += (int64_t)rq.size();
+            for (Request* r : rq) complete(*r, (st != RSD_OK && r->status == RSD_OK) ? st : r->status, now);
             n_batches += 1;
             rhs_batched += cols;
             sl->busy = false;
@@ -133,7 +267,14 @@ struct rsd_server {
             (void)fid;
             cv_done.notify_all();
             cv_work.notify_all();
+            cv_build.notify_all();     // an idle factor may now be evicted
         }
+    }
+
+    bool building_or_queued() const {
+        for (auto& kv : slots)
+            if (kv.second.state != READY) return true;
+        return false;
     }
 
     // one coalesced solve: gather the right-hand sides into n x P columns (P a
@@ -213,6 +354,7 @@ rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out) {
     if (s->opt.max_slots <= 0) s->opt.max_slots = 16;
     if (s->opt.n_workers <= 0) s->opt.n_workers = 2;
     if (s->opt.max_coalesce <= 0) s->opt.max_coalesce = 64;
+    s->opt.evict_idle = s->opt.evict_idle ? 1 : 0;
     if (s->opt.mem_budget <= 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -223,62 +365,93 @@ rsd_status rsd_server_create(const rsd_server_options* opt, rsd_server** out) {
         s->opt.mem_budget = (int64_t)(fr / 4 * 3);
     }
     try {
+        s->builder = std::thread([s] { s->build_loop(); });
         for (int i = 0; i < s->opt.n_workers; ++i) s->workers.emplace_back([s] { s->worker(); });
     } catch (const std::exception&) {
-        rsd_server_destroy(s);     // stops and joins the workers started so far
+        rsd_server_destroy(s);     // stops and joins the threads started so far
         return RSD_ENOMEM;
     }
     *out = s;
     return RSD_OK;
 }
 
+static void copy_in(std::vector<double>& dst, const double* src, int64_t n) {
+    dst.resize((size_t)n);
+    if (n == 0) return;
+    hipPointerAttribute_t at{};
+    bool dev = false;
+    if (hipPointerGetAttributes(&at, src) == hipSuccess)
+        dev = at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+    else
+        (void)hipGetLastError();
+    if (dev) {
+        if (hipMemcpy(dst.data(), src, (size_t)n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+            (void)hipGetLastError();
+            throw std::runtime_error("copy of a device input failed");
+        }
+    } else {
+        std::memcpy(dst.data(), src, (size_t)n * sizeof(double));
+    }
+}
+
 rsd_status rsd_server_submit_factor(rsd_server* s, const double* points, int64_t n_points,
                                     const rsd_kernel* kernel, const double* a, double tol,
                                     const rsd_options* opt, int64_t* factor_id) {
     return no_throw([&]() -> rsd_status {
-        if (!s || !factor_id) return RSD_EINVAL;
+        if (!s || !factor_id || !points || n_points <= 0) return RSD_EINVAL;
         if (opt && opt->hip_stream) return RSD_EINVAL;
-        Slot sl;
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
-            (void)hipGetLastError();
-            return RSD_EDEVICE;
+        if (!(tol > 0)) return RSD_EINVAL;
+        auto job = std::make_unique<FactorJob>();
+        if (s->opt.device >= 0) (void)hipSetDevice(s->opt.device);
+        copy_in(job->points, points, 2 * n_points);
+        if (a) copy_in(job->a, a, n_points);
+        if (kernel) {
+            job->kernel = *kernel;
+            if (kernel->contrast_b) copy_in(job->b, kernel->contrast_b, n_points);
+        } else {
+            job->kernel.type = RSD_KERNEL_LAPLACE;
         }
-        rsd_options o{};
-        if (opt) o = *opt;
-        o.hip_stream = sl.stream;
-        if (s->opt.device >= 0) o.device = s->opt.device;
-        rsd_status st = rsd_build_factor(points, n_points, kernel, a, tol, &o, &sl.f);
-        if (st != RSD_OK) {
-            (void)hipStreamDestroy(sl.stream);
-            return st;
-        }
-        rsd_factor_stats fs{};
-        (void)rsd_factor_get_stats(sl.f, &fs);
-        sl.n = n_points;
-        // the factor plus the coalescing buffers and solve vectors of a full batch
-        sl.bytes = fs.factor_bytes + (int64_t)(6 * n_points * s->opt.max_coalesce) * (int64_t)sizeof(double);
-        sl.last_use = Clock::now();
+        job->kernel.contrast_b = nullptr;
+        job->tol = tol;
+        if (opt) job->opt = *opt;
+        job->opt.hip_stream = nullptr;
+        // grid and size now, so that a request that can never be built or
+        // admitted fails here rather than in the queue
+        int64_t nx = 0, ny = 0, est = 0;
+        double h = 0;
+        std::vector<int64_t> perm((size_t)n_points);
+        rsd_status st = rsd_detect_grid(job->points.data(), n_points, &nx, &ny, &h, perm.data());
+        if (st != RSD_OK) return st;
+        st = rsd_estimate_factor_bytes(nx, ny, tol, &job->opt, &est);
+        if (st != RSD_OK) return st;
         std::lock_guard<std::mutex> lk(s->mu);
-        while ((int64_t)s->slots.size() >= s->opt.max_slots || s->resident + sl.bytes > s->opt.mem_budget) {
-            auto victim = s->slots.end();
-            for (auto it = s->slots.begin(); it != s->slots.end(); ++it)
-                if (!it->second.busy && it->second.pending.empty() &&
-                    (victim == s->slots.end() || it->second.last_use < victim->second.last_use))
-                    victim = it;
-            if (victim == s->slots.end()) {
-                s->free_slot(sl);
-                return RSD_ENOMEM;
-            }
-            s->resident -= victim->second.bytes;
-            s->free_slot(victim->second);
-            s->slots.erase(victim);
-            ++s->n_evicted;
-        }
+        const int64_t bytes = est + s->batch_bytes(n_points);
+        if (bytes > s->opt.mem_budget) return RSD_ENOMEM;
         const int64_t id = s->next_fid++;
-        s->resident += sl.bytes;
-        s->slots.emplace(id, std::move(sl));
+        Slot& sl = s->slots[id];
+        sl.job = std::move(job);
+        sl.n = n_points;
+        sl.bytes = bytes;
+        sl.state = QUEUED;
         *factor_id = id;
+        s->cv_build.notify_all();
         return RSD_OK;
+    });
+}
+
+rsd_status rsd_server_wait_factor(rsd_server* s, int64_t factor_id, int32_t timeout_ms) {
+    return no_throw([&]() -> rsd_status {
+        if (!s) return RSD_EINVAL;
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto settled = [&] {
+            auto it = s->slots.find(factor_id);
+            return it == s->slots.end() || it->second.state == READY;
+        };
+        if (timeout_ms < 0) s->cv_done.wait(lk, settled);
+        else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), settled)) return RSD_EAGAIN;
+        if (s->slots.count(factor_id)) return RSD_OK;
+        auto f = s->failed.find(factor_id);
+        return f != s->failed.end() ? f->second : RSD_EINVAL;
     });
 }
 
@@ -288,10 +461,12 @@ rsd_status rsd_server_release_factor(rsd_server* s, int64_t factor_id) {
         std::lock_guard<std::mutex> lk(s->mu);
         auto it = s->slots.find(factor_id);
         if (it == s->slots.end()) return RSD_EINVAL;
-        if (it->second.busy || !it->second.pending.empty()) return RSD_EAGAIN;
-        s->resident -= it->second.bytes;
-        s->free_slot(it->second);
+        Slot& sl = it->second;
+        if (sl.state == BUILDING || sl.busy || !sl.pending.empty()) return RSD_EAGAIN;
+        if (sl.state == READY) s->resident -= sl.bytes;
+        s->free_slot(sl);
         s->slots.erase(it);
+        s->cv_build.notify_all();     // memory and a slot freed: admit the next request
         return RSD_OK;
     });
 }
@@ -355,7 +530,11 @@ rsd_status rsd_server_get_stats(rsd_server* s, rsd_server_stats* out) {
         out->n_requests = s->n_requests;
         out->n_done = s->n_done;
         out->n_batches = s->n_batches;
-        out->n_factors = (int64_t)s->slots.size();
+        int64_t ready = 0, queued = 0;
+        for (auto& kv : s->slots) (kv.second.state == READY ? ready : queued) += 1;
+        out->n_factors = ready;
+        out->n_queued_factors = queued;
+        out->n_built = s->n_built;
         out->n_evicted = s->n_evicted;
         out->resident_bytes = s->resident;
         if (!s->lat_ms.empty()) {
@@ -382,6 +561,12 @@ void rsd_server_destroy(rsd_server* s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
+    }
+    s->cv_build.notify_all();
+    s->cv_work.notify_all();
+    if (s->builder.joinable()) s->builder.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
     }
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();

@@ -56,14 +56,14 @@ class rsd_box_info(C.Structure):
 
 class rsd_server_options(C.Structure):
     _fields_ = [("mem_budget", C.c_int64), ("max_slots", C.c_int32), ("n_workers", C.c_int32),
-                ("max_coalesce", C.c_int32), ("device", C.c_int32)]
+                ("max_coalesce", C.c_int32), ("device", C.c_int32), ("evict_idle", C.c_int32)]
 
 
 class rsd_server_stats(C.Structure):
     _fields_ = [("n_requests", C.c_int64), ("n_done", C.c_int64), ("n_batches", C.c_int64),
                 ("n_factors", C.c_int64), ("n_evicted", C.c_int64), ("resident_bytes", C.c_int64),
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_batch_rhs", C.c_double),
-                ("rhs_per_s", C.c_double)]
+                ("rhs_per_s", C.c_double), ("n_queued_factors", C.c_int64), ("n_built", C.c_int64)]
 
 
 EXPORTS = {
@@ -72,6 +72,9 @@ EXPORTS = {
                                            C.c_void_p, C.c_double, C.POINTER(rsd_options),
                                            C.POINTER(C.c_int64)]),
     "rsd_server_release_factor": (C.c_int, [C.c_void_p, C.c_int64]),
+    "rsd_server_wait_factor": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32]),
+    "rsd_estimate_factor_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_double, C.POINTER(rsd_options),
+                                            C.POINTER(C.c_int64)]),
     "rsd_server_submit_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                           C.POINTER(C.c_int64)]),
     "rsd_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(rsd_solve_info)]),
@@ -315,17 +318,21 @@ class Server:
     """Resident factors + queued, coalesced solves (rsd_server_*).  Buffers
     passed to submit_solve are kept alive here until their ticket is waited."""
 
-    def __init__(self, mem_budget=0, max_slots=0, n_workers=0, max_coalesce=0, device=-1):
+    def __init__(self, mem_budget=0, max_slots=0, n_workers=0, max_coalesce=0, device=-1,
+                 evict_idle=False):
         lib = load()
         h = C.c_void_p()
-        opt = rsd_server_options(mem_budget, max_slots, n_workers, max_coalesce, device)
+        opt = rsd_server_options(mem_budget, max_slots, n_workers, max_coalesce, device,
+                                 1 if evict_idle else 0)
         _check(lib.rsd_server_create(C.byref(opt), C.byref(h)))
         self._h = h
         self._live = {}
         self._n = {}          # factor id -> number of points
 
     def submit_factor(self, points, a=None, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0,
-                      layers=0, max_refine=0, refine_tol=0.0):
+                      layers=0, max_refine=0, refine_tol=0.0, wait=True):
+        """Queue a factor request; with wait=True return once it is resident
+        (raises the build's error), else at once (see wait_factor)."""
         if isinstance(points, np.ndarray):
             points = np.ascontiguousarray(points, dtype=np.float64)
         if isinstance(a, np.ndarray):
@@ -338,7 +345,17 @@ class Server:
         _check(load().rsd_server_submit_factor(self._h, pp, points.shape[0], C.byref(kd), ap, tol,
                                                C.byref(opt), C.byref(fid)))
         self._n[fid.value] = int(points.shape[0])
+        if wait:
+            self.wait_factor(fid.value)
         return fid.value
+
+    def wait_factor(self, fid, timeout_ms=-1):
+        """RSD_OK once resident, RSD_EAGAIN on timeout; raises on a failed build."""
+        st = load().rsd_server_wait_factor(self._h, fid, timeout_ms)
+        if st not in (RSD_OK, RSD_EAGAIN):
+            self._n.pop(fid, None)
+            _check(st)
+        return st
 
     def release_factor(self, fid):
         _check(load().rsd_server_release_factor(self._h, fid))
@@ -564,3 +581,11 @@ def detect_grid(points):
     _check(load().rsd_detect_grid(pts.ctypes.data, pts.shape[0], C.byref(nx), C.byref(ny),
                                   C.byref(h), perm.ctypes.data))
     return nx.value, ny.value, h.value, perm
+
+
+def estimate_factor_bytes(nx, ny, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0, layers=0):
+    """Device bytes of the factor of an nx x ny grid (host only)."""
+    opt = rsd_options(leaf_side, layers, precision, 0, 0.0, None, -1, 0)
+    out = C.c_int64()
+    _check(load().rsd_estimate_factor_bytes(nx, ny, tol, C.byref(opt), C.byref(out)))
+    return out.value

@@ -483,7 +483,7 @@ def test_server_coalesced_solves_match_dense():
 
 
 def test_server_admission_and_errors():
-    srv = rsd.Server(max_slots=2)
+    srv = rsd.Server(max_slots=2, evict_idle=True)
     p16, p20, p24 = W.grid_points(16), W.grid_points(20), W.grid_points(24)
     fa = srv.submit_factor(p16)
     fb = srv.submit_factor(p20)
@@ -513,23 +513,27 @@ def test_server_admission_and_errors():
 
 
 def test_server_memory_budget_admission():
-    # a budget below one factor's size admits nothing (ENOMEM, nothing held);
-    # a budget for about one factor evicts the idle one for the next
+    # the server sizes a factor before building it: the estimate equals the
+    # built factor's bytes; a request larger than the budget fails at once
     p32 = W.grid_points(32)
     probe = rsd.Factor(p32, None, 1e-10)
     fb = probe.stats()["factor_bytes"]
     probe.close()
+    assert rsd.estimate_factor_bytes(32, 32, 1e-10) == fb
     srv = rsd.Server(mem_budget=fb // 2)
     with pytest.raises(rsd.RsdError) as ei:
         srv.submit_factor(p32)
     assert ei.value.status == rsd.RSD_ENOMEM
     assert srv.stats()["n_factors"] == 0 and srv.stats()["resident_bytes"] == 0
     srv.close()
-    srv = rsd.Server(mem_budget=int(fb * 1.5))
+    # admission size = factor + coalescing/solve vectors of a full batch
+    slot = fb + 6 * len(p32) * 8 * 8
+    srv = rsd.Server(mem_budget=int(slot * 1.5), max_coalesce=8, evict_idle=True)
     f1 = srv.submit_factor(p32)
+    assert srv.stats()["resident_bytes"] == slot
     f2 = srv.submit_factor(p32, W.coef_sine(p32))
     s = srv.stats()
-    assert s["n_factors"] == 1 and s["n_evicted"] == 1 and s["resident_bytes"] <= fb * 1.5
+    assert s["n_factors"] == 1 and s["n_evicted"] == 1 and s["resident_bytes"] <= slot * 1.5
     f = np.asfortranarray(W.rhs_normal(len(p32), 1, 2))
     x = np.zeros_like(f)
     st, _ = srv.wait(srv.submit_solve(f2, f, x))
@@ -538,6 +542,103 @@ def test_server_memory_budget_admission():
     with pytest.raises(rsd.RsdError):
         srv.submit_solve(f1, f, np.zeros_like(f))     # evicted
     srv.close()
+
+
+def test_server_queues_factor_requests_until_memory_frees():
+    # without eviction a second factor waits in the queue until the first is
+    # released; solves submitted for it meanwhile run once it is resident
+    p32 = W.grid_points(32)
+    slot = rsd.estimate_factor_bytes(32, 32, 1e-10) + 6 * len(p32) * 8 * 8
+    srv = rsd.Server(mem_budget=int(slot * 1.5), max_coalesce=8)
+    f1 = srv.submit_factor(p32)
+    a2 = W.coef_sine(p32)
+    f2 = srv.submit_factor(p32, a2, wait=False)
+    assert srv.wait_factor(f2, timeout_ms=300) == rsd.RSD_EAGAIN
+    s = srv.stats()
+    assert s["n_factors"] == 1 and s["n_queued_factors"] == 1 and s["n_evicted"] == 0
+    f = np.asfortranarray(W.rhs_normal(len(p32), 2, 5))
+    x2 = np.zeros_like(f)
+    tk2 = srv.submit_solve(f2, f, x2)             # queued behind the admission
+    assert srv.poll(tk2) == 0
+    x1 = np.zeros_like(f)
+    st, _ = srv.wait(srv.submit_solve(f1, f, x1))
+    assert st == rsd.RSD_OK
+    srv.release_factor(f1)                         # frees the memory: f2 is admitted and built
+    st, _ = srv.wait(tk2, timeout_ms=60000)
+    assert st == rsd.RSD_OK
+    assert srv.wait_factor(f2) == rsd.RSD_OK
+    assert dense.rel_error(x1, dense.solve(p32, f)) < 1e-10
+    assert dense.rel_error(x2, dense.solve(p32, f, a2)) < 1e-10
+    s = srv.stats()
+    assert s["n_factors"] == 1 and s["n_queued_factors"] == 0 and s["n_built"] == 2
+    # a request that fails to build reports its status to its waiters
+    bad = np.array([[0.0, 0.0], [0.3, 0.0], [0.0, 1.0]])
+    with pytest.raises(rsd.RsdError) as ei:
+        srv.submit_factor(bad)
+    assert ei.value.status == rsd.RSD_ENOTGRID
+    srv.close()
+
+
+def test_server_results_alone_and_in_the_mix():
+    # continuous serving: factor requests of different sizes arrive while
+    # solves of resident factors run (Poisson arrivals from two client
+    # threads, right-hand-side counts 1..5); every result is compared with the
+    # same right-hand side solved alone on a directly built factor
+    import threading
+    import time
+    rng = np.random.default_rng(77)
+    grids = [W.grid_points(48), W.grid_points(32, 40), W.grid_points(64), W.grid_points(24)]
+    coefs = [W.coef_bumps(p, rng) for p in grids]
+    alone = []
+    for p, a in zip(grids, coefs):
+        fac = rsd.Factor(p, a, 1e-10)
+        alone.append(fac)
+    srv = rsd.Server(n_workers=2, max_coalesce=16)
+    fids = [srv.submit_factor(grids[0], coefs[0]), srv.submit_factor(grids[1], coefs[1])]
+    work = []
+    lock = threading.Lock()
+
+    def client(seed, which):
+        r = np.random.default_rng(seed)
+        for i in range(24):
+            time.sleep(r.exponential(1.0 / 400.0))
+            with lock:
+                g = which[i % len(which)]
+                fid = fids[g] if g < len(fids) else None
+            if fid is None:
+                continue
+            nr = int(r.integers(1, 6))
+            f = np.asfortranarray(r.standard_normal((grids[g].shape[0], nr)))
+            x = np.zeros_like(f)
+            tk = srv.submit_solve(fid, f, x)
+            with lock:
+                work.append((g, f, x, tk))
+
+    th = [threading.Thread(target=client, args=(1, [0, 1, 2, 3])),
+          threading.Thread(target=client, args=(2, [1, 0, 3, 2]))]
+    for t in th:
+        t.start()
+    time.sleep(0.01)
+    # two more factor requests arrive while the clients are solving
+    f3 = srv.submit_factor(grids[2], coefs[2], wait=False)
+    f4 = srv.submit_factor(grids[3], coefs[3], wait=False)
+    with lock:
+        fids.extend([f3, f4])
+    for t in th:
+        t.join()
+    assert srv.wait_factor(f3) == rsd.RSD_OK and srv.wait_factor(f4) == rsd.RSD_OK
+    assert len(work) > 20
+    for g, f, x, tk in work:
+        st, _ = srv.wait(tk, timeout_ms=120000)
+        assert st == rsd.RSD_OK
+        xa, _ = alone[g].solve(f)
+        assert np.linalg.norm(x - xa) <= 1e-12 * np.linalg.norm(xa)
+        assert dense.rel_error(x, dense.solve(grids[g], f, coefs[g])) < 1e-10
+    s = srv.stats()
+    assert s["n_built"] == 4 and s["n_done"] == len(work)
+    srv.close()
+    for fac in alone:
+        fac.close()
 
 
 def test_server_binding_checks_buffers():

@@ -359,3 +359,21 @@ def test_interp_group_checker_rejects_malformed_tables():
     past[-1, 3] = past[-1, 3] + 1
     with pytest.raises(rsd.RsdError):
         rsd.check_interp_groups(past)
+
+
+@pytest.mark.parametrize("nx,ny", [(32, 32), (40, 24), (256, 256)])
+def test_factor_bytes_estimate_counts_every_block(nx, ny):
+    # one (k + r)^2 block per box (float64), plus the interpolation blocks:
+    # at least the box blocks, and the float32 form keeps all levels below the
+    # root in half the bytes
+    p = rsd.Plan(nx, ny, 8, 2)
+    boxes = [p.box_info(b) for b in range(p.n_boxes)]
+    blocks = sum((b["k"] + b["r"]) ** 2 for b in boxes)
+    e64 = rsd.estimate_factor_bytes(nx, ny, 1e-10)
+    e32 = rsd.estimate_factor_bytes(nx, ny, 1e-10, precision=rsd.RSD_PREC_FP32_REFINE)
+    assert e64 >= 8 * blocks
+    top = max(b["level"] for b in boxes)
+    root = sum((b["k"] + b["r"]) ** 2 for b in boxes if b["level"] == top)
+    assert e32 >= 4 * (blocks - root) + 8 * root and e32 < e64
+    with pytest.raises(rsd.RsdError):
+        rsd.estimate_factor_bytes(0, 4, 1e-10)
