@@ -14,4 +14,8 @@ Contents (plain, slow, obviously correct, float64 / complex128):
   rskel    -- the paper's recursive-skeletonisation inverse (Algorithm 1 with
               the boundary-layer skeletons of Sec. 3.1 and proxy interpolation)
               followed by the inverse apply, written in the paper's notation
+  hssc     -- the compressed-block (HSS-C) inverse of Sec. 3.3: HSS1D and
+              low-rank arithmetic, INTER_LOWRANK, BUILD_Finv / APPLY_Finv,
+              BUILD_E (Algorithms 3-5) and the inverse apply (Algorithm 6)
+              for boxes above a skeleton size k_cut
 """
