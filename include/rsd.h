@@ -182,6 +182,19 @@ rsd_status rsd_solve_batched(int32_t n, rsd_factor* const* factors,
  * (relative 1e-13).  Device work space: 3 N nrhs doubles plus the FFT
  * fields, allocated per call. */
 rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y);
+/* rsd_matvec without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same product and result as rsd_matvec; x and y
+ * must be device buffers (N x nrhs column-major, caller's point order;
+ * EINVAL for host pointers).  Its work space (2 N nrhs doubles plus the FFT
+ * spectrum and field, 3 Mx My doubles; or N doubles of kernel table on the
+ * direct-sum path) lives in one 64 MiB device array per GPU, held from the
+ * first call on that GPU until the process ends; larger requests fail with
+ * EINVAL before anything is launched.  Every call on one GPU shares that
+ * array: calls that overlap in time on the same GPU (from several threads
+ * or streams) race and must be serialised by the caller.  Runs on the
+ * factor's stream and returns after it completes. */
+rsd_status rsd_matvec_noalloc(rsd_factor* f, const double* x, int64_t nrhs, double* y);
 
 /* Release a factor and all its device memory.  NULL is a no-op. */
 void rsd_free(rsd_factor* f);

@@ -2626,6 +2626,68 @@ static void matvec(Factor& f, const double* xin, int64_t nrhs, double* y) {
     RSD_HIP(hipStreamSynchronize(s));
 }
 
+// ---- the exact product without device allocations ---------------------------
+// Work space of rsd_matvec_noalloc: the grid-ordered copies of x and y, the
+// circulant spectrum and the FFT field (or the direct sum's kernel table), in
+// one file-scope device array per GPU.  Host code never passes the array's
+// name to a kernel: its device address is looked up once per device
+// (noalloc_scratch) and only that address is used.
+constexpr int64_t NOALLOC_SCRATCH_BYTES = 64ll << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+static double* noalloc_scratch(int device) {
+    static std::mutex mu;
+    static std::vector<double*> ptrs;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)ptrs.size() <= device) ptrs.resize(device + 1, nullptr);
+    if (!ptrs[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw Error(RSD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        ptrs[device] = static_cast<double*>(p);
+    }
+    return ptrs[device];
+}
+
+static void matvec_noalloc(Factor& f, const double* x, int64_t nrhs, double* y) {
+    if (nrhs < 0 || !x || !y) throw Error(RSD_EINVAL, "bad matvec arguments");
+    if (nrhs == 0) return;
+    RSD_HIP(hipSetDevice(f.device));
+    if (!is_device_ptr(x) || !is_device_ptr(y))
+        throw Error(RSD_EINVAL, "rsd_matvec_noalloc takes device buffers only");
+    const int64_t tot = f.N * nrhs;
+    int mx = 0, my = 0;
+    const bool fft = fft_matvec_sizes(f.nx, f.ny, &mx, &my);
+    const int64_t n = (int64_t)mx * my;
+    const int64_t need = 2 * tot + (fft ? 3 * n : f.N);   // doubles
+    const int64_t cap = NOALLOC_SCRATCH_BYTES / (int64_t)sizeof(double);
+    if (need > cap)
+        throw Error(RSD_EINVAL, "rsd_matvec_noalloc: " + std::to_string(need * 8) + " bytes of work space for N = " +
+                                    std::to_string(f.N) + ", nrhs = " + std::to_string(nrhs) + " exceed its " +
+                                    std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte maximum");
+    double* base = noalloc_scratch(f.device);
+    hipStream_t s = f.stream;
+    double* xg = base;
+    double* yg = xg + tot;
+    double* rest = yg + tot;
+    launch_permute(xg, x, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 1, s);
+    if (fft) {
+        double* spec = rest;
+        double2* work = reinterpret_cast<double2*>(spec + n);   // 16-byte aligned: 2 tot and n are even
+        launch_fft_spectrum(spec, work, f.nx, f.ny, mx, my, f.kd, s);
+        launch_fft_matvec(yg, xg, (int)nrhs, spec, work, f.nx, f.ny, mx, my, f.kd, s);
+    } else {
+        double* table = rest;
+        launch_matvec_table(table, f.nx, f.ny, f.kd, s);
+        launch_matvec(yg, xg, (int)nrhs, table, f.nx, f.ny, f.kd, 0, s);
+    }
+    launch_permute(y, yg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 0, s);
+    RSD_HIP(hipStreamSynchronize(s));
+}
+
 // ---- dense building blocks exposed for direct use ---------------------------
 template <typename T>
 static void dense_gemm(int M, int N, int K, int tA, int tB, double alpha, const void* A, int lda,
@@ -2877,6 +2939,14 @@ rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
     return guarded([&]() {
         if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
         rsd::matvec(*f->impl, x, nrhs, y);
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_matvec_noalloc(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
+    return guarded([&]() {
+        if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
+        rsd::matvec_noalloc(*f->impl, x, nrhs, y);
         return RSD_OK;
     });
 }

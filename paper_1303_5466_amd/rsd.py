@@ -91,6 +91,7 @@ EXPORTS = {
     "rsd_solve_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int64,
                                     C.POINTER(C.c_void_p), C.POINTER(rsd_solve_info)]),
     "rsd_matvec": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "rsd_matvec_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "rsd_free": (None, [C.c_void_p]),
     "rsd_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                            C.c_double, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
@@ -270,6 +271,11 @@ class Factor:
         Y = np.zeros_like(X, order="F")
         _check(load().rsd_matvec(self._h, X.ctypes.data, X.shape[1], Y.ctypes.data))
         return Y[:, 0] if vec else Y
+
+    def matvec_noalloc_raw(self, x_ptr, nrhs, y_ptr):
+        """rsd_matvec_noalloc on device pointers (N x nrhs column-major);
+        returns the status."""
+        return load().rsd_matvec_noalloc(self._h, x_ptr, nrhs, y_ptr)
 
 
 def build_batched(points_list, a_list=None, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0,
