@@ -53,11 +53,16 @@ typedef enum rsd_kernel_type {
  *   A_ii = a_i + int_{cell_i} K(|x_i - y|) dy,
  * the Nystrom rule of Sec. 5 with b = c = 1 and the exact integral of the
  * kernel over the point's own cell on the diagonal.  With contrast_b given
- * (N values, b >= 0) it is the scattering operator of Sec. 5.4:
- *   A_ij = sqrt(b_i) h^2 G(|x_i - x_j|) sqrt(b_j),  A_ii = 1 + b_i int_cell G.
- * This library version builds factors for the Laplace kernel without a
- * contrast only: RSD_KERNEL_HELMHOLTZ and a non-NULL contrast_b make
- * rsd_build_factor fail with EINVAL (the CPU reference covers both). */
+ * (N values, b > 0 at every point; a must be NULL) it is the scattering
+ * operator of Sec. 5.4:
+ *   A_ij = sqrt(b_i) h^2 G(|x_i - x_j|) sqrt(b_j),  A_ii = 1 + b_i int_cell G,
+ * factored as S M S with S = diag(sqrt b) and M = diag(1/b) + h^2 G (whose
+ * off-diagonal part is translation invariant); zero or negative b => EINVAL.
+ * The Helmholtz kernel (wavenumber > 0) makes the matrix complex symmetric:
+ * the factor holds the real symmetric form [[Re, Im], [Im, -Re]] of every
+ * block on two dofs per point, and right-hand sides and solutions are
+ * interleaved complex doubles.  Batched builds take the Laplace kernel
+ * without a contrast only (EINVAL otherwise). */
 typedef struct rsd_kernel {
     int32_t type;              /* rsd_kernel_type                           */
     double wavenumber;         /* k of the Helmholtz kernel; ignored else   */
@@ -97,6 +102,10 @@ typedef struct rsd_options {
  * the float32 form trades interpolation accuracy for a float32-only build and
  * usually needs more refinement steps. */
 #define RSD_FLAG_FP32_INTERP 4
+/* Build every box's blocks even when the diagonal coefficient a is constant
+ * (by default such a factor keeps one E/G/W block per box type and level,
+ * shared by all its boxes: the translation-invariant case of Sec. 5.1.2). */
+#define RSD_FLAG_NO_DEDUP 8
 
 typedef struct rsd_solve_info {
     int32_t refine_iters;  /* refinement steps taken                          */
@@ -155,8 +164,10 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
  *   info    NULL or receives refinement statistics.
  * Errors: EINVAL (NaN/Inf in rhs, nrhs < 0), ENOCONV (refinement did not
  * reach refine_tol; x then holds the last iterate and info the residual),
- * EDEVICE.  Concurrent calls on one factor are not supported; separate
- * factors may be solved from separate threads. */
+ * EDEVICE.  Concurrent calls on one factor are safe and run one after the
+ * other (a factor has one set of solve vectors and one stream); separate
+ * factors are solved concurrently from separate threads, each on its own
+ * stream. */
 rsd_status rsd_solve(rsd_factor* f, const double* rhs, int64_t nrhs,
                      double* x, rsd_solve_info* info);
 
@@ -182,6 +193,28 @@ rsd_status rsd_solve_batched(int32_t n, rsd_factor* const* factors,
  * (relative 1e-13).  Device work space: 3 N nrhs doubles plus the FFT
  * fields, allocated per call. */
 rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y);
+/* ---- tile autotuner (batched builds, row a10) ------------------------------
+ * The grouped GEMM launches of the factor levels pick a tile width (64 or 128)
+ * and a split-K target per launch shape bucket (element size, log2 of the
+ * 64-wide tile count, of the longest K and of the flops).  rsd_autotune
+ * builds the given instances (one rsd_build_factor, or one
+ * rsd_build_factor_batched call for n_inst > 1) reps times under each of six
+ * candidates, times every tuned launch with HIP events, and keeps for each
+ * bucket seen under all candidates the fastest one; later builds in this
+ * process use the table (buckets not in it use the built-in rule).  Results
+ * differ from untuned builds only by rounding (split-K changes the order of
+ * partial sums).  *n_entries receives the number of buckets set.  The table
+ * is saved and loaded as text (rsd_tune_save / rsd_tune_load; the file named
+ * by the environment variable RSD_TUNE_FILE is loaded at the first build).
+ * Tuning is not thread safe with concurrent builds in the same process. */
+rsd_status rsd_autotune(int32_t n_inst, const double* const* points, const int64_t* n_points,
+                        const rsd_kernel* kernel, const double* const* a, double tol, const rsd_options* opt,
+                        int32_t reps, int32_t* n_entries);
+rsd_status rsd_tune_save(const char* path);
+rsd_status rsd_tune_load(const char* path);
+/* Empties the table (builds use the built-in rule again). */
+rsd_status rsd_tune_clear(int64_t* n_entries_before);
+
 /* rsd_matvec without any device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same product and result as rsd_matvec; x and y
@@ -214,6 +247,8 @@ typedef struct rsd_factor_stats {
     double factor_flops;     /* algorithmic flops of the build (model)       */
     double solve_bytes;      /* factor bytes streamed by one solve           */
     double build_ms;         /* device time of the last build                */
+    int32_t complex_values;  /* 1: Helmholtz factor; right-hand sides and
+                                solutions are interleaved complex (c128)      */
 } rsd_factor_stats;
 
 rsd_status rsd_factor_get_stats(const rsd_factor* f, rsd_factor_stats* out);
@@ -401,12 +436,20 @@ rsd_status rsd_gj_invert(int32_t dtype, int32_t n, void* A, int32_t lda);
 
 /* ---- host-only planning (no device needed) ------------------------------ */
 
+/* Integral of the kernel over the square cell of side h centred on its
+ * point, the diagonal term of the Nystrom matrix (Sec. 5; k the wavenumber
+ * of the Helmholtz kernel (i/4) H0^(1)(k r) of Sec. 5.3, ignored for
+ * Laplace).  Host only. */
+rsd_status rsd_self_cell_integral(int32_t kernel_type, double h, double k, double* re, double* im);
 /* Device bytes of the factor rsd_build_factor would keep for an nx x ny grid
- * with these options (the per-box (k + r)^2 blocks of Algorithm 1 in the
- * Schur form and the interpolation blocks; equal to
- * rsd_factor_stats.factor_bytes of the built factor).  Host only. */
-rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, double tol, const rsd_options* opt,
-                                     int64_t* bytes);
+ * with this kernel (NULL => Laplace) and these options (the per-box
+ * (k + r)^2 blocks of Algorithm 1 in the Schur form and the interpolation
+ * blocks, four times the entries for the complex Helmholtz kernel): equal to
+ * rsd_factor_stats.factor_bytes of a factor built with every box's blocks
+ * (a varying a, or RSD_FLAG_NO_DEDUP), an upper bound for one that shares
+ * them (constant a).  Host only. */
+rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, const rsd_kernel* kernel, double tol,
+                                     const rsd_options* opt, int64_t* bytes);
 /* Number of boxes and levels the tree of Sec. 2.2 / Sec. 3.1 produces for an
  * nx x ny grid, and per-box sizes.  Pure host computation, usable without a
  * GPU; boxes are numbered level by level from the leaves. */

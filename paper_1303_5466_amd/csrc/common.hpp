@@ -27,6 +27,15 @@ struct HipError : std::runtime_error {
 // Diagonal entry of point p:
 //   a_p + sc          (no contrast)      or   1 + b_p * sc   (contrast)
 // with sc the integral of K over the point's own cell.
+//
+// Complex kernels (cplx = 1, Helmholtz G = (i/4) H0^(1)(k r)): the factor is
+// built for the real symmetric matrix J(M) that carries the complex
+// symmetric M = M_re + i M_im on two dofs per point,
+//   J(M) = [[M_re, M_im], [M_im, -M_re]],   J(M) [u; w] = [Re g; Im g]
+// for M (u - i w) = g; every dof block of a box lists its points twice,
+// [sk plane 0; sk plane 1; rs plane 0; rs plane 1] (plane 0 carries the real
+// component u, plane 1 carries w = -Im y), so each generated entry is the
+// (plane_i, plane_j) component of J of the complex entry.
 // ---------------------------------------------------------------------------
 struct KernelDesc {
     int type;          // 0 Laplace, 1 Helmholtz
@@ -38,7 +47,18 @@ struct KernelDesc {
     const double* a;   // grid-ordered identity coefficient (N) or nullptr
     const double* sb;  // grid-ordered sqrt(b) (N) or nullptr
     int64_t ny;        // grid index g = i * ny + j
+    int cplx;          // 1: two dofs per point (J form above)
 };
+
+// Plane (0 or 1) of position q of a complex factor's dof block with k
+// skeleton and r residual dofs ([sk plane 0; sk plane 1; rs plane 0; rs plane 1]).
+__host__ __device__ inline int dof_plane(int q, int k, int r) {
+    return q < k ? (q >= k / 2 ? 1 : 0) : (q - k >= r / 2 ? 1 : 0);
+}
+// (pi, pj) component of J(re + i im)
+__host__ __device__ inline double jform(double re, double im, int pi, int pj) {
+    return pi == pj ? (pi ? -re : re) : im;
+}
 
 // Per-box record used by the device kernels.
 struct BoxDev {
@@ -231,12 +251,13 @@ void launch_gj_pivot(const GJDesc<T>* d, int n_desc, int step, int nb, int max_c
 template <typename TS, typename TD>
 void launch_gather_leaf(TD* V, const TS* f, int64_t ldf, int nrhs, const BoxDev* boxes,
                         const int* box_ids, int n_boxes, const LayoutDev* layouts, const int* lu,
-                        const int* lv, const int64_t* perm, int64_t ny, int max_m, hipStream_t s);
+                        const int* lv, const int64_t* perm, int64_t ny, int64_t plane_off, int max_m,
+                        hipStream_t s);
 template <typename TS, typename TD>
 void launch_scatter_leaf(TD* x, int64_t ldx, const TS* V, const TS* Y, int nrhs,
                          const BoxDev* boxes, const int* box_ids, int n_boxes,
                          const LayoutDev* layouts, const int* lu, const int* lv,
-                         const int64_t* perm, int64_t ny, int max_m, hipStream_t s);
+                         const int64_t* perm, int64_t ny, int64_t plane_off, int max_m, hipStream_t s);
 template <typename TS, typename TD>
 void launch_scatter_up(TD* Vparent, const TS* V, int nrhs, const BoxDev* boxes, const int* box_ids,
                        int n_boxes, const LayoutDev* layouts, const int* inv, int max_k,
@@ -267,5 +288,11 @@ void launch_axpy_resid(double* r, const double* f, const double* Ax, int64_t n, 
 void launch_add(double* x, const double* d, int64_t n, hipStream_t s);
 void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, hipStream_t s);
 void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
+// contrast scaling and complex plane split / merge around the factored
+// system (k_solve.hip)
+void launch_scale_split(double* R, const double* f, const double* sb, int64_t N, int nrhs, int cplx,
+                        hipStream_t s);
+void launch_scale_merge(double* x, const double* X, const double* sb, int64_t N, int nrhs, int cplx,
+                        hipStream_t s);
 
 }  // namespace rsd

@@ -451,6 +451,165 @@ struct ProfScope {
 // ----------------------------------------------------------------------------
 // GEMM batches: descriptors + tile tables, uploaded once
 // ----------------------------------------------------------------------------
+// ---- tile autotuner -----------------------------------------------------------
+// The grouped GEMM launches of the factor levels choose a tile width (64 or
+// 128) and a split-K target (how many work-groups per compute unit long K
+// ranges are split for, or none).  The built-in rule is a heuristic; the
+// tuner replaces it per launch shape: a launch's shape bucket is (element
+// size, log2 of its 64-wide tile count, log2 of its longest K, log2 of its
+// flops), and rsd_autotune times every candidate on real builds and keeps the
+// fastest per bucket.  The table can be saved to and loaded from a text file
+// (one "bucket tile split" line per entry; RSD_TUNE_FILE names a file loaded
+// at the first build).
+struct TuneChoice {
+    int tile = 64;
+    int split = 2;      // split target in work-groups per compute unit (0: never split)
+};
+constexpr int TUNE_CANDIDATES = 6;
+static const TuneChoice kTuneCand[TUNE_CANDIDATES] = {{64, 2}, {64, 0}, {64, 4}, {128, 2}, {128, 0}, {128, 4}};
+
+class Tuner {
+public:
+    static Tuner& get() {
+        static Tuner t;
+        return t;
+    }
+    static uint64_t key(int es, int64_t t64, int kmax, double flops) {
+        auto lg = [](double v) { return v < 1 ? 0 : (int)std::floor(std::log2(v)); };
+        return (uint64_t)es | ((uint64_t)std::min(lg((double)t64), 63) << 8) |
+               ((uint64_t)std::min(lg((double)kmax), 63) << 16) | ((uint64_t)std::min(lg(flops), 127) << 24);
+    }
+    // the choice for a launch: the forced candidate while tuning, else the
+    // table's entry, else false (heuristic)
+    bool choice(uint64_t k, TuneChoice& c) {
+        std::lock_guard<std::mutex> lk(mu_);
+        load_env();
+        if (forced_ >= 0) {
+            c = kTuneCand[forced_];
+            return true;
+        }
+        auto it = table_.find(k);
+        if (it == table_.end()) return false;
+        c = it->second;
+        return true;
+    }
+    void set_forced(int cand) {
+        std::lock_guard<std::mutex> lk(mu_);
+        forced_ = cand;
+    }
+    bool recording() const { return recording_.load(std::memory_order_relaxed); }
+    void set_recording(bool on) { recording_.store(on); }
+    // one timed launch (events recorded on its stream)
+    void record(uint64_t k, hipEvent_t a, hipEvent_t b) {
+        std::lock_guard<std::mutex> lk(mu_);
+        pending_.push_back({k, forced_, a, b});
+    }
+    hipEvent_t event() {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!free_ev_.empty()) {
+            hipEvent_t e = free_ev_.back();
+            free_ev_.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        RSD_HIP(hipEventCreate(&e));
+        return e;
+    }
+    // after a device synchronisation: fold the recorded launches into the
+    // per-bucket, per-candidate totals
+    void collect() {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto& r : pending_) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess && r.cand >= 0) {
+                auto& v = times_[r.k];
+                v.resize(TUNE_CANDIDATES, 0.0);
+                v[r.cand] += ms;
+            } else {
+                (void)hipGetLastError();
+            }
+            free_ev_.push_back(r.a);
+            free_ev_.push_back(r.b);
+        }
+        pending_.clear();
+    }
+    // picks the fastest candidate of every bucket timed under all candidates
+    int commit() {
+        std::lock_guard<std::mutex> lk(mu_);
+        int n = 0;
+        for (auto& kv : times_) {
+            const auto& v = kv.second;
+            int best = -1;
+            for (int c = 0; c < TUNE_CANDIDATES; ++c)
+                if (v[c] > 0 && (best < 0 || v[c] < v[best])) best = c;
+            bool all = true;
+            for (int c = 0; c < TUNE_CANDIDATES; ++c) all = all && v[c] > 0;
+            if (best >= 0 && all) {
+                table_[kv.first] = kTuneCand[best];
+                ++n;
+            }
+        }
+        times_.clear();
+        return n;
+    }
+    void clear() {
+        std::lock_guard<std::mutex> lk(mu_);
+        table_.clear();
+        times_.clear();
+    }
+    int64_t size() {
+        std::lock_guard<std::mutex> lk(mu_);
+        return (int64_t)table_.size();
+    }
+    void save(const char* path) {
+        std::lock_guard<std::mutex> lk(mu_);
+        FILE* fp = std::fopen(path, "w");
+        if (!fp) throw Error(RSD_EINVAL, std::string("cannot write ") + path);
+        for (auto& kv : table_)
+            std::fprintf(fp, "%llu %d %d\n", (unsigned long long)kv.first, kv.second.tile, kv.second.split);
+        std::fclose(fp);
+    }
+    void load(const char* path) {
+        std::lock_guard<std::mutex> lk(mu_);
+        load_file(path);
+    }
+
+private:
+    struct Rec {
+        uint64_t k;
+        int cand;
+        hipEvent_t a, b;
+    };
+    void load_file(const char* path) {
+        FILE* fp = std::fopen(path, "r");
+        if (!fp) throw Error(RSD_EINVAL, std::string("cannot read ") + path);
+        unsigned long long k;
+        int tile, split;
+        while (std::fscanf(fp, "%llu %d %d", &k, &tile, &split) == 3)
+            if ((tile == 64 || tile == 128) && split >= 0 && split <= 16) table_[k] = {tile, split};
+        std::fclose(fp);
+    }
+    void load_env() {
+        if (env_done_) return;
+        env_done_ = true;
+        const char* p = std::getenv("RSD_TUNE_FILE");
+        if (p && *p) {
+            try {
+                load_file(p);
+            } catch (const std::exception&) {
+            }
+        }
+    }
+    std::mutex mu_;
+    std::map<uint64_t, TuneChoice> table_;
+    std::map<uint64_t, std::vector<double>> times_;
+    std::vector<Rec> pending_;
+    std::vector<hipEvent_t> free_ev_;
+    std::atomic<bool> recording_{false};
+    int forced_ = -1;
+    bool env_done_ = false;
+};
+
 template <typename T>
 struct GemmBatch {
     std::vector<GemmDesc<T>> descs;
@@ -466,6 +625,7 @@ struct GemmBatch {
     int prof_cls = -1;
     int role = -1;      // kernel instantiation (see launch_gemm); -1: from prof_cls
     int max_split = 16; // 1: no split K, so every product's rounding is independent of the batch
+    uint64_t tune_key = 0;  // shape bucket of a tuned launch (0: not tuned)
     void add(const GemmDesc<T>& d) {
         if (d.M <= 0 || d.N <= 0) return;
         descs.push_back(d);
@@ -538,13 +698,26 @@ struct GemmBatch {
         // short-K launches (the Gauss-Jordan updates) are bound by their C
         // traffic: the 64-wide tiles load C before the K loop
         tile = (t128 >= 2 * CUS && big >= 0.8 * tot && kmax > 128) ? 128 : 64;
+        int split_target = 2;
+        tune_key = 0;
+        if (kernel_role() == 0 && max_split > 1) {
+            // the factor levels' launches: the tuned choice for this shape
+            const uint64_t k = Tuner::key((int)sizeof(T), t64, kmax, flops);
+            TuneChoice c;
+            if (Tuner::get().choice(k, c)) {
+                tile = c.tile;
+                split_target = c.split;
+            }
+            tune_key = k;
+        }
         const int64_t nt = tile == 128 ? t128 : t64;
         const int bk = (sizeof(T) == 8 && tile == 128) ? 8 : 16;
         for (int id = 0; id < (int)descs.size(); ++id) {
             const auto& d = descs[id];
             const int steps = (std::max(d.K, 0) + bk - 1) / bk + (std::max(d.K2, 0) + bk - 1) / bk;
             int S = 1;
-            if (nt < CUS) S = std::max(1, std::min<int>({(int)((2 * CUS + nt - 1) / nt), steps / 8, max_split}));
+            if (split_target > 0 && nt < (int64_t)split_target * CUS / 2)
+                S = std::max(1, std::min<int>({(int)((split_target * CUS + nt - 1) / nt), steps / 8, max_split}));
             const int tm = (d.M + tile - 1) / tile, tn = (d.N + tile - 1) / tile;
             for (int i = 0; i < tm; ++i)
                 for (int j = 0; j < tn; ++j) {
@@ -567,6 +740,13 @@ struct GemmBatch {
     void run(hipStream_t s) const {
         if (tiles.empty()) return;
         const int r = kernel_role();
+        hipEvent_t ta = nullptr, tb = nullptr;
+        Tuner& tu = Tuner::get();
+        if (tune_key && tu.recording()) {
+            ta = tu.event();
+            tb = tu.event();
+            RSD_HIP(hipEventRecord(ta, s));
+        }
         {
             ProfScope ps(prof_cls, s, flops, bytes, (int64_t)tiles.size());
             launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), tile, d_ws, 0, s, r);
@@ -574,6 +754,10 @@ struct GemmBatch {
         if (!slots.empty()) {
             ProfScope ps(prof_cls, s, 0, 0, (int64_t)slots.size());
             launch_gemm<T>(d_descs, d_slots, (int)slots.size(), tile, d_ws, 1, s, r);
+        }
+        if (ta) {
+            RSD_HIP(hipEventRecord(tb, s));
+            tu.record(tune_key, ta, tb);
         }
     }
 };
@@ -732,13 +916,18 @@ struct Factor {
     int cplx = 0;
     int top = 0;                    // root level
     int flags = 0;
-    KernelDesc kd{};
+    KernelDesc kd{};                // the factored matrix (generation kernels)
+    KernelDesc kd_res{};            // the exact operator (residuals, rsd_matvec)
     std::vector<int> level_prec;    // 0 fp64, 1 fp32
     // device tables
     DevBuf d_boxes, d_layouts, d_lu, d_lv, d_srcc, d_srci, d_inv, d_perm, d_ident, d_a, d_sb,
         d_level_ids, d_err, d_table, d_spec, d_fftwork, d_flag;
     int fft_mx = 0, fft_my = 0;     // circulant sizes of the FFT product (0: not set up)
+    std::mutex use_mu;              // solves and products of one factor run one at a time
     std::vector<int> level_id_off;
+    bool dedup = false;                         // one block per (level, layout)
+    std::vector<std::vector<int>> build_levels; // boxes built per level (representatives)
+    std::vector<int> build_id_off;
     DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
     hipStream_t qr_stream[2] = {nullptr, nullptr};   // interpolation chains run here
     std::vector<hipEvent_t> tmp_events;
@@ -784,6 +973,7 @@ struct Factor {
         return *scratch.back();
     }
     const int* ids(int t) const { return d_level_ids.as<int>() + level_id_off[t]; }
+    const int* bids(int t) const { return d_level_ids.as<int>() + build_id_off[t]; }
 };
 
 template <typename T> static T* Fbase(Factor& f);
@@ -804,7 +994,18 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 // truncated at a looser tol.  With one layer the truncation is active and
 // follows tol.
 static double interp_tol64(const Factor& f) {
+    // complex (Helmholtz) factors keep three layers below tol 1e-6 and their
+    // proxy problems are numerically full rank to 1e-12
+    if (f.cplx && f.layers >= 3) return std::min(f.tol, 1e-12);
     return f.layers >= 2 ? std::min(f.tol, 1e-10) : f.tol;
+}
+
+// Skeleton layers m: from tol (layers_for_tol), one more for the oscillatory
+// Helmholtz kernel below tol 1e-6 (Sec. 5.3: more layers than for Laplace
+// at high accuracy), at most three.
+static int default_layers(double tol, int kernel_type) {
+    const int m = layers_for_tol(tol);
+    return kernel_type == RSD_KERNEL_HELMHOLTZ && tol < 1e-6 ? std::min(m + 1, 3) : m;
 }
 
 // The symmetry split is used where the proxy problems are full rank (float64
@@ -1275,7 +1476,7 @@ static void plan_level(Factor& f, LevelExec<T>& L, int t, std::vector<GemmBatch<
                        int64_t& sr_need, int64_t& sc_need) {
     Plan& P = f.plan;
     L.level = t;
-    L.ids = P.levels[t];
+    L.ids = f.build_levels.empty() ? P.levels[t] : f.build_levels[t];
     T* F = Fbase<T>(f);
     T* Tb = Tbase<T>(f);
     int64_t sr = 0, sc = 0;
@@ -1414,19 +1615,19 @@ static void run_assembly(Factor& f, LevelExec<T>& L, hipStream_t s) {
     const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
     ProfScope ps(RSD_PROF_ASSEMBLY, s);
     if (t == 0) {
-        launch_leaf_F<T>(F, B, f.ids(t), n, LD, f.d_lu.as<int>(), f.d_lv.as<int>(), f.kd, L.max_m, s);
+        launch_leaf_F<T>(F, B, f.bids(t), n, LD, f.d_lu.as<int>(), f.d_lv.as<int>(), f.kd, L.max_m, s);
     } else {
         const int child_prec = f.level_prec[t - 1];
         if constexpr (std::is_same<T, float>::value) {
-            launch_assemble_F<float, float>(F, f.F32.as<float>(), B, f.ids(t), n, LD, f.d_lu.as<int>(),
+            launch_assemble_F<float, float>(F, f.F32.as<float>(), B, f.bids(t), n, LD, f.d_lu.as<int>(),
                                             f.d_lv.as<int>(), f.d_srcc.as<int>(), f.d_srci.as<int>(),
                                             f.kd, L.max_m, s);
         } else if (child_prec == 1) {
-            launch_assemble_F<float, double>(F, f.F32.as<float>(), B, f.ids(t), n, LD, f.d_lu.as<int>(),
+            launch_assemble_F<float, double>(F, f.F32.as<float>(), B, f.bids(t), n, LD, f.d_lu.as<int>(),
                                              f.d_lv.as<int>(), f.d_srcc.as<int>(), f.d_srci.as<int>(),
                                              f.kd, L.max_m, s);
         } else {
-            launch_assemble_F<double, double>(F, f.F64.as<double>(), B, f.ids(t), n, LD,
+            launch_assemble_F<double, double>(F, f.F64.as<double>(), B, f.bids(t), n, LD,
                                               f.d_lu.as<int>(), f.d_lv.as<int>(), f.d_srcc.as<int>(),
                                               f.d_srci.as<int>(), f.kd, L.max_m, s);
         }
@@ -1438,7 +1639,7 @@ template <typename T>
 static void run_transpose(Factor& f, LevelExec<T>& L, hipStream_t s) {
     if (L.g_sr.empty()) return;
     ProfScope ps(RSD_PROF_ASSEMBLY, s);
-    launch_transpose_sr<T>(Fbase<T>(f), f.d_boxes.as<BoxDev>(), f.ids(L.level), (int)L.ids.size(),
+    launch_transpose_sr<T>(Fbase<T>(f), f.d_boxes.as<BoxDev>(), f.bids(L.level), (int)L.ids.size(),
                            L.max_k, L.max_r, s);
 }
 
@@ -1655,10 +1856,126 @@ static Plan cached_plan(int64_t nx, int64_t ny, int leaf, int m) {
     return *plan;
 }
 
+// Plan of a complex factor: every box type's dof block lists its points
+// twice, [sk plane 0; sk plane 1; rs plane 0; rs plane 1] (the real
+// symmetric J form of the complex symmetric matrix, see KernelDesc), so k, r
+// and the interpolation problems double (rows: proxy points of plane 0 then
+// plane 1) and the children-to-parent maps point at the child's dof of the
+// same plane.  The interpolation problems are solved whole (no symmetry
+// sectors).
+static Plan expand_planes(const Plan& P) {
+    Plan Q = P;
+    for (size_t li = 0; li < Q.layouts.size(); ++li) {
+        Layout& L = Q.layouts[li];
+        const Layout& O = P.layouts[li];
+        const int k = O.k, r = O.r;
+        std::vector<int32_t> u, v, sc, si;
+        auto put = [&](int q, int plane) {
+            u.push_back(O.u[q]);
+            v.push_back(O.v[q]);
+            if (!O.src_c.empty()) {
+                const int c = O.src_c[q];
+                sc.push_back(c);
+                si.push_back(O.src_i[q] + plane * P.layouts[O.child[c]].k);
+            }
+        };
+        for (int plane = 0; plane < 2; ++plane)
+            for (int q = 0; q < k; ++q) put(q, plane);
+        for (int plane = 0; plane < 2; ++plane)
+            for (int q = k; q < k + r; ++q) put(q, plane);
+        L.u = std::move(u);
+        L.v = std::move(v);
+        L.src_c = std::move(sc);
+        L.src_i = std::move(si);
+        L.k = 2 * k;
+        L.r = 2 * r;
+    }
+    for (auto& b : Q.boxes) { b.k *= 2; b.r *= 2; }
+    for (auto& I : Q.idps) {
+        I.p *= 2; I.k *= 2; I.r *= 2;
+        I.sym = false;
+        I.grp = 0;
+    }
+    Q.F_elems = Q.V_elems = Q.Vr_elems = 0;
+    for (auto& b : Q.boxes) {
+        Q.F_elems += (int64_t)(b.k + b.r) * (b.k + b.r);
+        Q.V_elems += b.k + b.r;
+        Q.Vr_elems += b.r;
+    }
+    return Q;
+}
+
+// Integral of the kernel over the square cell of side h centred on its point
+// (the diagonal of the Nystrom matrix, Sec. 5).  Laplace: closed form
+// h^2 (log h + J) / 2pi, J = -log(2)/2 - 3/2 + pi/4 (eight triangles in polar
+// coordinates).  Helmholtz (i/4) H0^(1)(k r): written as -(1/2pi) log r plus
+// the bounded remainder R(r) = G(r) + (1/2pi) log r, whose integral over the
+// eight triangles r < h / (2 cos t), 0 < t < pi/4 is taken by tensor
+// Gauss-Legendre quadrature with r = rmax s^2 (the remainder behaves like
+// r^2 log r at 0, the substitution smooths it).
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+            const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+static void self_cell_integral(int type, double h, double k, double& re, double& im) {
+    const double J = -0.5 * std::log(2.0) - 1.5 + M_PI / 4.0;
+    const double lap = h * h * (std::log(h) + J) / (2.0 * M_PI);
+    if (type == RSD_KERNEL_LAPLACE) {
+        re = lap;
+        im = 0.0;
+        return;
+    }
+    std::vector<double> gx, gw;
+    gauss_legendre(40, gx, gw);
+    double sr = 0.0, si = 0.0;
+    for (int a = 0; a < 40; ++a) {
+        const double t = 0.125 * M_PI * (gx[a] + 1.0), wt = 0.125 * M_PI * gw[a];
+        const double rmax = h / (2.0 * std::cos(t));
+        for (int b = 0; b < 40; ++b) {
+            const double sq = 0.5 * (gx[b] + 1.0), ws = 0.5 * gw[b];
+            const double rr = rmax * sq * sq;           // r = rmax s^2, dr = 2 rmax s ds
+            const double jac = 2.0 * rmax * sq * rr;    // dr * r
+            const double z = k * rr;
+            const double gre = -0.25 * std::cyl_neumann(0.0, z) + std::log(rr) / (2.0 * M_PI);
+            const double gim = 0.25 * std::cyl_bessel_j(0.0, z);
+            sr += wt * ws * jac * gre;
+            si += wt * ws * jac * gim;
+        }
+    }
+    re = -lap + 8.0 * sr;
+    im = 8.0 * si;
+}
+
 // Host planning of a build and the uploads of its tables (on the factor's
 // stream); no kernel is launched yet.
 static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, const rsd_kernel* kernel,
-                                             const double* a, double tol, const rsd_options* opt) {
+                                             const double* a, double tol, const rsd_options* opt,
+                                             bool allow_dedup = true) {
     if (!points || n <= 0) throw Error(RSD_EINVAL, "points must be non-null and n_points > 0");
     if (!(tol > 0) || !std::isfinite(tol)) throw Error(RSD_EINVAL, "tol must be a positive number");
     rsd_options o{};
@@ -1680,20 +1997,25 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     f->max_refine = o.max_refine < 0 ? 0 : (o.max_refine == 0 ? (f->precision == RSD_PREC_FP32_REFINE ? 10 : 0) : o.max_refine);
     f->refine_tol = o.refine_tol > 0 ? o.refine_tol : tol;
     const int leaf = o.leaf_side > 0 ? o.leaf_side : 8;
-    const int m = o.layers > 0 ? o.layers : layers_for_tol(tol);
-    int ktype = kernel ? kernel->type : RSD_KERNEL_LAPLACE;
-    if (ktype != RSD_KERNEL_LAPLACE) throw Error(RSD_EINVAL, "only the Laplace kernel is built into this library version");
+    const int ktype = kernel ? kernel->type : RSD_KERNEL_LAPLACE;
+    const int m = o.layers > 0 ? o.layers : default_layers(tol, ktype);
+    if (ktype != RSD_KERNEL_LAPLACE && ktype != RSD_KERNEL_HELMHOLTZ) throw Error(RSD_EINVAL, "unknown kernel type");
+    const double wavenumber = ktype == RSD_KERNEL_HELMHOLTZ ? kernel->wavenumber : 0.0;
+    if (ktype == RSD_KERNEL_HELMHOLTZ && !(wavenumber > 0 && std::isfinite(wavenumber)))
+        throw Error(RSD_EINVAL, "the Helmholtz kernel needs a positive finite wavenumber");
+    f->cplx = ktype == RSD_KERNEL_HELMHOLTZ ? 1 : 0;
     // host views of the inputs: device arrays are read back into a pinned
     // block (a direct copy), host arrays are read in place
+    const double* bptr = kernel ? kernel->contrast_b : nullptr;
     PinnedBlock in_pin;
     const double* pts = points;
     const double* ha = a;
-    std::vector<double> bh;
+    const double* hb = bptr;
     {
-        const bool pdev = is_device_ptr(points), adev = a && is_device_ptr(a);
-        if (pdev || adev) {
-            const size_t np = pdev ? 2 * (size_t)n : 0, na = adev ? (size_t)n : 0;
-            in_pin.p = PinnedPool::get().take((np + na) * sizeof(double), in_pin.cap);
+        const bool pdev = is_device_ptr(points), adev = a && is_device_ptr(a), bdev = bptr && is_device_ptr(bptr);
+        if (pdev || adev || bdev) {
+            const size_t np = pdev ? 2 * (size_t)n : 0, na = adev ? (size_t)n : 0, nb = bdev ? (size_t)n : 0;
+            in_pin.p = PinnedPool::get().take((np + na + nb) * sizeof(double), in_pin.cap);
             double* w = static_cast<double*>(in_pin.p);
             if (pdev) {
                 RSD_HIP(hipMemcpy(w, points, np * sizeof(double), hipMemcpyDeviceToHost));
@@ -1703,21 +2025,23 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
                 RSD_HIP(hipMemcpy(w + np, a, na * sizeof(double), hipMemcpyDeviceToHost));
                 ha = w + np;
             }
+            if (bdev) {
+                RSD_HIP(hipMemcpy(w + np + na, bptr, nb * sizeof(double), hipMemcpyDeviceToHost));
+                hb = w + np + na;
+            }
         }
     }
     if (ha)
         for (int64_t i = 0; i < n; ++i)
             if (!std::isfinite(ha[i])) throw Error(RSD_EINVAL, "non-finite value in a");
-    const double* bptr = kernel ? kernel->contrast_b : nullptr;
-    // the scattering form (sqrt(b) K sqrt(b), Sec. 5.4) needs a per-box scaling
-    // of T that the device level pipeline does not apply
-    if (bptr) throw Error(RSD_EINVAL, "the contrast (scattering) form is not available on the device path");
-    if (bptr) {
-        bh.resize(n);
-        if (is_device_ptr(bptr)) RSD_HIP(hipMemcpy(bh.data(), bptr, n * sizeof(double), hipMemcpyDeviceToHost));
-        else std::memcpy(bh.data(), bptr, n * sizeof(double));
-        for (double v : bh)
-            if (!std::isfinite(v) || v < 0) throw Error(RSD_EINVAL, "contrast must be finite and >= 0");
+    // contrast (scattering) form A = I + S K S, S = diag sqrt(b) (Sec. 5.4):
+    // factored as A = S M S with M = diag(1/b) + K, whose off-diagonal part is
+    // the translation-invariant kernel (one T per box type); needs b > 0
+    if (hb) {
+        if (ha) throw Error(RSD_EINVAL, "the contrast form takes a = NULL (identity coefficient 1)");
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(hb[i]) || !(hb[i] > 0))
+                throw Error(RSD_EINVAL, "the contrast b must be finite and positive at every point");
     }
     int64_t nx, ny;
     double h, x0, y0;
@@ -1730,6 +2054,7 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     } catch (const std::exception& e) {
         throw Error(RSD_EINVAL, e.what());
     }
+    if (f->cplx) f->plan = expand_planes(f->plan);
     Plan& P = f->plan;
     if (o.flags & RSD_FLAG_NO_SYMMETRY)
         for (auto& I : P.idps) I.sym = false;
@@ -1739,14 +2064,21 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     if (f->precision == RSD_PREC_FP32_REFINE)
         for (int t = 0; t < f->top; ++t) f->level_prec[t] = 1;
     // ---- grid-ordered coefficients -----------------------------------------
+    // ag: diagonal coefficient of the factored matrix (a, or 1/b for the
+    // contrast form); sbg: sqrt(b) for the contrast form (residual operator
+    // and the scaling around the solve)
     std::vector<double> ag, sbg;
     if (ha) {
         ag.resize(n);
         for (int64_t g = 0; g < n; ++g) ag[g] = ha[perm[g]];
     }
-    if (!bh.empty()) {
+    if (hb) {
+        ag.resize(n);
         sbg.resize(n);
-        for (int64_t g = 0; g < n; ++g) sbg[g] = std::sqrt(bh[perm[g]]);
+        for (int64_t g = 0; g < n; ++g) {
+            ag[g] = 1.0 / hb[perm[g]];
+            sbg[g] = std::sqrt(hb[perm[g]]);
+        }
     }
     // ---- device tables ------------------------------------------------------
     std::vector<int> lu, lv, srcc, srci, inv;
@@ -1784,6 +2116,27 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
         f->hlayouts[li].offT = o2;
         o2 += (int64_t)L.k * L.r;
     }
+    // Translation-invariant deduplication (Sec. 5.1.2): with a constant
+    // diagonal coefficient and no contrast, every box of one layout on one
+    // level has the same F_i (kernel blocks depend on relative positions only,
+    // the children's E_c are equal by induction), hence the same E_i, G and W.
+    // Only one representative per (level, layout) is built; every box's block
+    // offset points at its representative's block.
+    bool const_a = !hb;
+    if (ha)
+        for (int64_t i = 1; i < n && const_a; ++i) const_a = ha[i] == ha[0];
+    f->dedup = allow_dedup && const_a && !(o.flags & RSD_FLAG_NO_DEDUP);
+    std::vector<int> rep(P.boxes.size());
+    for (size_t i = 0; i < P.boxes.size(); ++i) rep[i] = (int)i;
+    if (f->dedup) {
+        std::map<std::pair<int, int>, int> first;     // (level, layout) -> representative
+        for (size_t i = 0; i < P.boxes.size(); ++i) {
+            const auto key = std::make_pair(P.boxes[i].level, P.boxes[i].layout);
+            auto it = first.find(key);
+            if (it == first.end()) first.emplace(key, (int)i);
+            else rep[i] = it->second;
+        }
+    }
     // boxes: F offsets per precision arena, vector offsets per precision
     int64_t offF64 = 0, offF32 = 0;
     f->hboxes.resize(P.boxes.size());
@@ -1796,10 +2149,14 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
         D.level = b.level;
         const int prec = f->level_prec[b.level];
         const int64_t mm = (int64_t)b.k + b.r;
-        int64_t& oF = prec ? offF32 : offF64;
-        D.offF = oF;
-        P.boxes[i].offF = oF;
-        oF += mm * mm;
+        if (rep[i] == (int)i) {
+            int64_t& oF = prec ? offF32 : offF64;
+            D.offF = oF;
+            oF += mm * mm;
+        } else {
+            D.offF = f->hboxes[rep[i]].offF;      // representatives come first in box order
+        }
+        P.boxes[i].offF = D.offF;
         D.offV = offV[prec];
         offV[prec] += mm;
         D.offY = offY[prec];
@@ -1809,13 +2166,21 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     f->F32.alloc(std::max<int64_t>(offF32, 1) * sizeof(float));
     f->T64.alloc(std::max<int64_t>(offT64, 1) * sizeof(double));
     f->T32.alloc(std::max<int64_t>(offT32, 1) * sizeof(float));
-    std::vector<int> lid;
+    std::vector<int> lid, bid;
+    f->build_levels.assign(nlev, {});
     for (int t = 0; t < nlev; ++t) {
         f->level_id_off.push_back((int)lid.size());
         lid.insert(lid.end(), P.levels[t].begin(), P.levels[t].end());
+        for (int id : P.levels[t])
+            if (rep[id] == id) f->build_levels[t].push_back(id);
     }
-    std::vector<int64_t> ident(n);
-    for (int64_t g = 0; g < n; ++g) ident[g] = g;
+    for (int t = 0; t < nlev; ++t) {
+        f->build_id_off.push_back((int)(lid.size() + bid.size()));
+        bid.insert(bid.end(), f->build_levels[t].begin(), f->build_levels[t].end());
+    }
+    lid.insert(lid.end(), bid.begin(), bid.end());   // one device table: all boxes, then the built ones
+    std::vector<int64_t> ident(f->cplx ? 2 * n : n);
+    for (int64_t g = 0; g < (int64_t)ident.size(); ++g) ident[g] = g;
     upload(f->d_boxes, f->hboxes, s);
     upload(f->d_layouts, f->hlayouts, s);
     upload(f->d_lu, lu, s);
@@ -1830,21 +2195,26 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     if (!sbg.empty()) upload(f->d_sb, sbg, s);
     f->d_err.alloc(sizeof(int) * 4);
     RSD_HIP(hipMemsetAsync(f->d_err.p, 0, sizeof(int) * 4, s));
-    // kernel description
+    // kernel descriptions: kd generates the factored matrix (diagonal ag,
+    // no scaling), kd_res is the exact operator of the residual (contrast
+    // scaling when given)
     KernelDesc& kd = f->kd;
-    kd.type = 0;
-    kd.has_b = sbg.empty() ? 0 : 1;
+    kd.type = ktype == RSD_KERNEL_HELMHOLTZ ? 1 : 0;
+    kd.has_b = 0;
     kd.h = h;
     kd.logh = std::log(h);
-    kd.k = 0;
-    {
-        const double J = -0.5 * std::log(2.0) - 1.5 + M_PI / 4.0;
-        kd.sc_re = h * h * (std::log(h) + J) / (2.0 * M_PI);
-        kd.sc_im = 0;
-    }
+    kd.k = wavenumber;
+    self_cell_integral(ktype, h, wavenumber, kd.sc_re, kd.sc_im);
     kd.a = ag.empty() ? nullptr : f->d_a.as<double>();
-    kd.sb = sbg.empty() ? nullptr : f->d_sb.as<double>();
+    kd.sb = nullptr;
     kd.ny = ny;
+    kd.cplx = f->cplx;
+    f->kd_res = kd;
+    if (!sbg.empty()) {
+        f->kd_res.has_b = 1;
+        f->kd_res.a = nullptr;
+        f->kd_res.sb = f->d_sb.as<double>();
+    }
     // ---- level plans ----------------------------------------------------------
     std::vector<GemmBatch<double>*> b64;
     std::vector<GemmBatch<float>*> b32;
@@ -2080,6 +2450,7 @@ static void build_stats(Factor& fr) {
     st.n_boxes = (int)P.boxes.size();
     st.layers = f->layers;
     st.precision = f->precision;
+    st.complex_values = f->cplx;
     st.factor_bytes = (int64_t)(f->F64.bytes + f->F32.bytes + f->T64.bytes + f->T32.bytes);
     double fl = f->gemm_flops;
     for (auto& I : P.idps) {
@@ -2448,9 +2819,11 @@ static void apply_inverse(Factor& f, SolvePlan& sp, const double* fin, double* x
     auto nb = [&](int t) { return (int)f.plan.levels[t].size(); };
     auto maxm = [&](int t) { int m = 0; for (int id : f.plan.levels[t]) m = std::max(m, f.hboxes[id].k + f.hboxes[id].r); return m; };
     auto maxk = [&](int t) { int m = 0; for (int id : f.plan.levels[t]) m = std::max(m, f.hboxes[id].k); return m; };
-    // leaves
-    if (f.level_prec[0]) launch_gather_leaf<double, float>(sp.V32.as<float>(), fin, f.N, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
-    else launch_gather_leaf<double, double>(sp.V64.as<double>(), fin, f.N, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
+    // leaves (complex factors: fin holds the two dof planes of each column,
+    // ld 2N, plane 1 at offset N)
+    const int64_t ldv = f.cplx ? 2 * f.N : f.N, poff = f.cplx ? f.N : 0;
+    if (f.level_prec[0]) launch_gather_leaf<double, float>(sp.V32.as<float>(), fin, ldv, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
+    else launch_gather_leaf<double, double>(sp.V64.as<double>(), fin, ldv, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
     for (int t = 0; t < nlev; ++t) {
         const int p = f.level_prec[t];
         if (p) { sp.L32[t].up1.run(s); sp.L32[t].up2.run(s); }
@@ -2482,39 +2855,42 @@ static void apply_inverse(Factor& f, SolvePlan& sp, const double* fin, double* x
         if (p) { sp.L32[t].dn1.run(s); sp.L32[t].dn2.run(s); }
         else { sp.L64[t].dn1.run(s); sp.L64[t].dn2.run(s); }
     }
-    if (f.level_prec[0]) launch_scatter_leaf<float, double>(xout, f.N, sp.V32.as<float>(), sp.Y32.as<float>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
-    else launch_scatter_leaf<double, double>(xout, f.N, sp.V64.as<double>(), sp.Y64.as<double>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, maxm(0), s);
+    if (f.level_prec[0]) launch_scatter_leaf<float, double>(xout, ldv, sp.V32.as<float>(), sp.Y32.as<float>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
+    else launch_scatter_leaf<double, double>(xout, ldv, sp.V64.as<double>(), sp.Y64.as<double>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
 }
 
 static void ensure_table(Factor& f) {
     if (f.d_table.p) return;
+    if (f.cplx) throw Error(RSD_EINVAL, "the exact complex product needs grid sides of at most 2048 (FFT form)");
     f.d_table.alloc(f.N * sizeof(double));
-    launch_matvec_table(f.d_table.as<double>(), f.nx, f.ny, f.kd, f.stream);
+    launch_matvec_table(f.d_table.as<double>(), f.nx, f.ny, f.kd_res, f.stream);
 }
 
-// y = A x, grid-ordered device vectors: the FFT form (circulant embedding)
-// when the grid sides allow it, else the direct sum
+// y = A x, grid-ordered device vectors (interleaved complex for complex
+// factors): the FFT form (circulant embedding) when the grid sides allow it,
+// else the direct sum
 static void matvec_grid(Factor& f, const double* x, double* y, int nrhs) {
     int mx = 0, my = 0;
     if (fft_matvec_sizes(f.nx, f.ny, &mx, &my)) {
         const double n = (double)mx * my;
         if (!f.fft_mx) {
-            f.d_spec.alloc((size_t)n * sizeof(double));
+            f.d_spec.alloc((size_t)n * sizeof(double) * (f.cplx ? 2 : 1));
             f.d_fftwork.alloc((size_t)n * 2 * sizeof(double));
-            launch_fft_spectrum(f.d_spec.as<double>(), f.d_fftwork.as<double2>(), f.nx, f.ny, mx, my, f.kd, f.stream);
+            launch_fft_spectrum(f.d_spec.as<double>(), f.d_fftwork.as<double2>(), f.nx, f.ny, mx, my, f.kd_res,
+                                f.stream);
             f.fft_mx = mx;
             f.fft_my = my;
         }
-        const double pairs = (nrhs + 1) / 2;
-        ProfScope ps(RSD_PROF_MATVEC, f.stream, pairs * 2 * 5.0 * n * std::log2(n), pairs * 10.0 * 16.0 * n);
+        const double fields = f.cplx ? nrhs : (nrhs + 1) / 2;
+        ProfScope ps(RSD_PROF_MATVEC, f.stream, fields * 2 * 5.0 * n * std::log2(n), fields * 10.0 * 16.0 * n);
         launch_fft_matvec(y, x, nrhs, f.d_spec.as<double>(), f.d_fftwork.as<double2>(), f.nx, f.ny, mx, my,
-                          f.kd, f.stream);
+                          f.kd_res, f.stream);
         return;
     }
     ensure_table(f);
     const double nn = (double)f.N;
     ProfScope ps(RSD_PROF_MATVEC, f.stream, 2.0 * nn * nn * nrhs, 16.0 * nn * nrhs);
-    launch_matvec(y, x, nrhs, f.d_table.as<double>(), f.nx, f.ny, f.kd, 0, f.stream);
+    launch_matvec(y, x, nrhs, f.d_table.as<double>(), f.nx, f.ny, f.kd_res, 0, f.stream);
 }
 
 // Enqueues the finiteness check of a right-hand side; its flag reaches a
@@ -2535,6 +2911,7 @@ static void finite_check_failed(const Factor& f) {
 }
 
 static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, rsd_solve_info* info) {
+    std::lock_guard<std::mutex> use(f.use_mu);   // one solve plan and stream per factor
     if (nrhs < 0) throw Error(RSD_EINVAL, "nrhs < 0");
     if (info) { info->refine_iters = 0; info->rel_residual = -1; }
     if (nrhs == 0) return RSD_OK;
@@ -2544,7 +2921,8 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
     hipStream_t s = f.stream;
     g_last_nrhs.store((int)nrhs, std::memory_order_relaxed);
     SolvePlan& sp = get_solve_plan(f, (int)nrhs);
-    const int64_t tot = f.N * nrhs;
+    const int w = f.cplx ? 2 : 1;                 // doubles per entry (interleaved complex)
+    const int64_t tot = f.N * nrhs * w;
     const bool rdev = is_device_ptr(rhs), xdev = is_device_ptr(x);
     const double* fin = rhs;
     if (!rdev) {
@@ -2554,12 +2932,16 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
     start_finite_check(f, fin, tot);
     double* xo = xdev ? x : sp.out.as<double>();
     rsd_status status = RSD_OK;
-    if (f.max_refine <= 0) {
+    // complex and contrast-form factors solve through the factored matrix M:
+    // x = S^-1 M~^-1 S^-1 f, with the complex vectors carried on the two dof
+    // planes of J(M)
+    const bool scaled = f.cplx || f.kd_res.has_b;
+    if (f.max_refine <= 0 && !scaled) {
         apply_inverse(f, sp, fin, xo, f.d_perm.as<int64_t>());
     } else {
-        // refinement on grid-ordered copies: fg, xg, rg, dg, ax
+        // grid-ordered work vectors fg, xg, rg, dg, ax and the plane blocks R, X
         if (!sp.refine_work.p) {
-            sp.refine_work.alloc(5 * tot * sizeof(double));
+            sp.refine_work.alloc(7 * tot * sizeof(double));
             sp.refine_norms.alloc(2 * nrhs * sizeof(double));
         }
         double* fg = sp.refine_work.as<double>();
@@ -2567,34 +2949,48 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
         double* rg = xg + tot;
         double* dg = rg + tot;
         double* ax = dg + tot;
-        launch_permute(fg, fin, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 1, s);
-        apply_inverse(f, sp, fg, xg, f.d_ident.as<int64_t>());
-        DevBuf& nb = sp.refine_norms;
-        launch_col_norms2(nb.as<double>(), fg, f.N, (int)nrhs, s);
-        std::vector<double> fn(nrhs), rn(nrhs);
-        RSD_HIP(hipMemcpyAsync(fn.data(), nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-        int it = 0;
-        double worst = 0;
-        for (;;) {
-            matvec_grid(f, xg, ax, (int)nrhs);
-            launch_axpy_resid(rg, fg, ax, tot, s);
-            launch_col_norms2(nb.as<double>() + nrhs, rg, f.N, (int)nrhs, s);
-            RSD_HIP(hipMemcpyAsync(rn.data(), nb.as<double>() + nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-            RSD_HIP(hipStreamSynchronize(s));
-            finite_check_failed(f);
-            worst = 0;
-            for (int c = 0; c < nrhs; ++c) {
-                const double rel = fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]);
-                if (!(rel <= worst)) worst = rel;      // a NaN residual stays NaN (never converged)
+        double* R = ax + tot;
+        double* X = R + tot;
+        const double* sb = f.kd_res.has_b ? f.kd_res.sb : nullptr;
+        auto inv = [&](const double* src, double* dst) {      // dst = A~^-1 src (grid order)
+            if (!scaled) {
+                apply_inverse(f, sp, src, dst, f.d_ident.as<int64_t>());
+                return;
             }
-            if (worst <= f.refine_tol || it >= f.max_refine) break;
-            apply_inverse(f, sp, rg, dg, f.d_ident.as<int64_t>());
-            launch_add(xg, dg, tot, s);
-            ++it;
+            launch_scale_split(R, src, sb, f.N, (int)nrhs, f.cplx, s);
+            apply_inverse(f, sp, R, X, f.d_ident.as<int64_t>());
+            launch_scale_merge(dst, X, sb, f.N, (int)nrhs, f.cplx, s);
+        };
+        launch_permute(fg, fin, f.d_perm.as<int64_t>(), f.N, (int)nrhs, w, 1, s);
+        inv(fg, xg);
+        if (f.max_refine > 0) {
+            DevBuf& nb = sp.refine_norms;
+            launch_col_norms2(nb.as<double>(), fg, f.N * w, (int)nrhs, s);
+            std::vector<double> fn(nrhs), rn(nrhs);
+            RSD_HIP(hipMemcpyAsync(fn.data(), nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+            int it = 0;
+            double worst = 0;
+            for (;;) {
+                matvec_grid(f, xg, ax, (int)nrhs);
+                launch_axpy_resid(rg, fg, ax, tot, s);
+                launch_col_norms2(nb.as<double>() + nrhs, rg, f.N * w, (int)nrhs, s);
+                RSD_HIP(hipMemcpyAsync(rn.data(), nb.as<double>() + nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+                RSD_HIP(hipStreamSynchronize(s));
+                finite_check_failed(f);
+                worst = 0;
+                for (int c = 0; c < nrhs; ++c) {
+                    const double rel = fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]);
+                    if (!(rel <= worst)) worst = rel;      // a NaN residual stays NaN (never converged)
+                }
+                if (worst <= f.refine_tol || it >= f.max_refine) break;
+                inv(rg, dg);
+                launch_add(xg, dg, tot, s);
+                ++it;
+            }
+            if (info) { info->refine_iters = it; info->rel_residual = worst; }
+            if (worst > f.refine_tol) status = RSD_ENOCONV;
         }
-        launch_permute(xo, xg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 0, s);
-        if (info) { info->refine_iters = it; info->rel_residual = worst; }
-        if (worst > f.refine_tol) status = RSD_ENOCONV;
+        launch_permute(xo, xg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, w, 0, s);
         RSD_HIP(hipStreamSynchronize(s));
     }
     if (!xdev) RSD_HIP(hipMemcpyAsync(x, xo, tot * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -2606,11 +3002,13 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
 }
 
 static void matvec(Factor& f, const double* xin, int64_t nrhs, double* y) {
+    std::lock_guard<std::mutex> use(f.use_mu);
     if (nrhs < 0 || !xin || !y) throw Error(RSD_EINVAL, "bad matvec arguments");
     if (nrhs == 0) return;
     RSD_HIP(hipSetDevice(f.device));
     hipStream_t s = f.stream;
-    const int64_t tot = f.N * nrhs;
+    const int w = f.cplx ? 2 : 1;
+    const int64_t tot = f.N * nrhs * w;
     DevBuf buf;
     buf.alloc(3 * tot * sizeof(double));
     double* xi = buf.as<double>();
@@ -2618,9 +3016,9 @@ static void matvec(Factor& f, const double* xin, int64_t nrhs, double* y) {
     double* yg = xg + tot;
     if (is_device_ptr(xin)) RSD_HIP(hipMemcpyAsync(xi, xin, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
     else RSD_HIP(hipMemcpyAsync(xi, xin, tot * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_permute(xg, xi, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 1, s);
+    launch_permute(xg, xi, f.d_perm.as<int64_t>(), f.N, (int)nrhs, w, 1, s);
     matvec_grid(f, xg, yg, (int)nrhs);
-    launch_permute(xi, yg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 0, s);
+    launch_permute(xi, yg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, w, 0, s);
     if (is_device_ptr(y)) RSD_HIP(hipMemcpyAsync(y, xi, tot * sizeof(double), hipMemcpyDeviceToDevice, s));
     else RSD_HIP(hipMemcpyAsync(y, xi, tot * sizeof(double), hipMemcpyDeviceToHost, s));
     RSD_HIP(hipStreamSynchronize(s));
@@ -2658,11 +3056,13 @@ static void matvec_noalloc(Factor& f, const double* x, int64_t nrhs, double* y) 
     RSD_HIP(hipSetDevice(f.device));
     if (!is_device_ptr(x) || !is_device_ptr(y))
         throw Error(RSD_EINVAL, "rsd_matvec_noalloc takes device buffers only");
-    const int64_t tot = f.N * nrhs;
+    const int w = f.cplx ? 2 : 1;                  // doubles per entry
+    const int64_t tot = f.N * nrhs * w;
     int mx = 0, my = 0;
     const bool fft = fft_matvec_sizes(f.nx, f.ny, &mx, &my);
+    if (!fft && f.cplx) throw Error(RSD_EINVAL, "the exact complex product needs grid sides of at most 2048");
     const int64_t n = (int64_t)mx * my;
-    const int64_t need = 2 * tot + (fft ? 3 * n : f.N);   // doubles
+    const int64_t need = 2 * tot + (fft ? (w + 2) * n : f.N);   // doubles
     const int64_t cap = NOALLOC_SCRATCH_BYTES / (int64_t)sizeof(double);
     if (need > cap)
         throw Error(RSD_EINVAL, "rsd_matvec_noalloc: " + std::to_string(need * 8) + " bytes of work space for N = " +
@@ -2673,18 +3073,18 @@ static void matvec_noalloc(Factor& f, const double* x, int64_t nrhs, double* y) 
     double* xg = base;
     double* yg = xg + tot;
     double* rest = yg + tot;
-    launch_permute(xg, x, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 1, s);
+    launch_permute(xg, x, f.d_perm.as<int64_t>(), f.N, (int)nrhs, w, 1, s);
     if (fft) {
-        double* spec = rest;
-        double2* work = reinterpret_cast<double2*>(spec + n);   // 16-byte aligned: 2 tot and n are even
-        launch_fft_spectrum(spec, work, f.nx, f.ny, mx, my, f.kd, s);
-        launch_fft_matvec(yg, xg, (int)nrhs, spec, work, f.nx, f.ny, mx, my, f.kd, s);
+        double* spec = rest;                                     // n (real) or 2n (complex) doubles
+        double2* work = reinterpret_cast<double2*>(spec + w * n);   // 16-byte aligned: 2 tot and n are even
+        launch_fft_spectrum(spec, work, f.nx, f.ny, mx, my, f.kd_res, s);
+        launch_fft_matvec(yg, xg, (int)nrhs, spec, work, f.nx, f.ny, mx, my, f.kd_res, s);
     } else {
         double* table = rest;
-        launch_matvec_table(table, f.nx, f.ny, f.kd, s);
-        launch_matvec(yg, xg, (int)nrhs, table, f.nx, f.ny, f.kd, 0, s);
+        launch_matvec_table(table, f.nx, f.ny, f.kd_res, s);
+        launch_matvec(yg, xg, (int)nrhs, table, f.nx, f.ny, f.kd_res, 0, s);
     }
-    launch_permute(y, yg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, 1, 0, s);
+    launch_permute(y, yg, f.d_perm.as<int64_t>(), f.N, (int)nrhs, w, 0, s);
     RSD_HIP(hipStreamSynchronize(s));
 }
 
@@ -2835,6 +3235,8 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
     int32_t where = -1;
     const rsd_status st = guarded([&]() {
         if (!out || !points || !n_points) throw rsd::Error(RSD_EINVAL, "null argument");
+        if (kernel && (kernel->type != RSD_KERNEL_LAPLACE || kernel->contrast_b))
+            throw rsd::Error(RSD_EINVAL, "batched builds take the Laplace kernel without contrast");
         if (n_inst <= 0) throw rsd::Error(RSD_EINVAL, "n_inst must be positive");
         if (opt && opt->hip_stream) throw rsd::Error(RSD_EINVAL, "batched builds use their own streams");
         const int32_t group = max_inflight > 0 ? max_inflight : 64;
@@ -2855,7 +3257,8 @@ rsd_status rsd_build_factor_batched(int32_t n_inst, const double* const* points,
                     for (int32_t i = next++; i < g1; i = next++) {
                         try {
                             if (!on_dev) throw rsd::HipError("hipSetDevice failed on a planning thread");
-                            fs[i] = rsd::build_prepare(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt);
+                            fs[i] = rsd::build_prepare(points[i], n_points[i], kernel, a ? a[i] : nullptr, tol, opt,
+                                                       false);
                         } catch (...) {
                             errs[i - g0] = std::current_exception();
                         }
@@ -2939,6 +3342,72 @@ rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
     return guarded([&]() {
         if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
         rsd::matvec(*f->impl, x, nrhs, y);
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_autotune(int32_t n_inst, const double* const* points, const int64_t* n_points,
+                        const rsd_kernel* kernel, const double* const* a, double tol, const rsd_options* opt,
+                        int32_t reps, int32_t* n_entries) {
+    if (n_entries) *n_entries = 0;
+    return guarded([&]() {
+        if (n_inst <= 0 || !points || !n_points) throw rsd::Error(RSD_EINVAL, "no instances to tune on");
+        if (reps <= 0) reps = 1;
+        rsd::Tuner& tu = rsd::Tuner::get();
+        struct Reset {
+            rsd::Tuner& t;
+            ~Reset() {
+                t.set_forced(-1);
+                t.set_recording(false);
+                t.collect();
+            }
+        } reset{tu};
+        for (int c = 0; c < rsd::TUNE_CANDIDATES; ++c)
+            for (int r = 0; r < reps; ++r) {
+                tu.set_forced(c);
+                tu.set_recording(true);
+                if (n_inst == 1) {
+                    rsd_factor* f = nullptr;
+                    const rsd_status st = rsd_build_factor(points[0], n_points[0], kernel, a ? a[0] : nullptr, tol, opt, &f);
+                    if (st != RSD_OK) throw rsd::Error(st, rsd::g_last_error);
+                    rsd_free(f);
+                } else {
+                    std::vector<rsd_factor*> fs(n_inst, nullptr);
+                    const rsd_status st = rsd_build_factor_batched(n_inst, points, n_points, kernel, a, tol, opt, 0, fs.data());
+                    if (st != RSD_OK) throw rsd::Error(st, rsd::g_last_error);
+                    for (auto* f : fs) rsd_free(f);
+                }
+                tu.set_recording(false);
+                RSD_HIP(hipDeviceSynchronize());
+                tu.collect();
+            }
+        tu.set_forced(-1);
+        const int n = tu.commit();
+        if (n_entries) *n_entries = n;
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_tune_save(const char* path) {
+    return guarded([&]() {
+        if (!path) throw rsd::Error(RSD_EINVAL, "null path");
+        rsd::Tuner::get().save(path);
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_tune_load(const char* path) {
+    return guarded([&]() {
+        if (!path) throw rsd::Error(RSD_EINVAL, "null path");
+        rsd::Tuner::get().load(path);
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_tune_clear(int64_t* n_entries_before) {
+    return guarded([&]() {
+        if (n_entries_before) *n_entries_before = rsd::Tuner::get().size();
+        rsd::Tuner::get().clear();
         return RSD_OK;
     });
 }
@@ -3124,8 +3593,8 @@ rsd_status rsd_plan_create(int64_t nx, int64_t ny, int32_t leaf_side, int32_t la
     });
 }
 
-rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, double tol, const rsd_options* opt,
-                                     int64_t* bytes) {
+rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, const rsd_kernel* kernel, double tol,
+                                     const rsd_options* opt, int64_t* bytes) {
     return guarded([&]() {
         if (!bytes) throw rsd::Error(RSD_EINVAL, "bytes is null");
         *bytes = 0;
@@ -3136,7 +3605,7 @@ rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, double tol, const r
         if (o.precision != RSD_PREC_FP64 && o.precision != RSD_PREC_FP32_REFINE)
             throw rsd::Error(RSD_EINVAL, "unknown precision");
         const int leaf = o.leaf_side > 0 ? o.leaf_side : 8;
-        const int m = o.layers > 0 ? o.layers : rsd::layers_for_tol(tol);
+        const int m = o.layers > 0 ? o.layers : rsd::default_layers(tol, kernel ? kernel->type : RSD_KERNEL_LAPLACE);
         rsd::Plan P;
         try {
             P = rsd::cached_plan(nx, ny, leaf, m);
@@ -3162,8 +3631,22 @@ rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, double tol, const r
             if (L.idp < 0) continue;
             (es(layout_level[li]) == 4 ? t32 : t64) += (int64_t)L.k * L.r;
         }
-        *bytes = 8 * (std::max<int64_t>(f64, 1) + std::max<int64_t>(t64, 1)) +
-                 4 * (std::max<int64_t>(f32, 1) + std::max<int64_t>(t32, 1));
+        // complex factors hold every block on two dofs per point: 4x the entries
+        const int64_t cx = kernel && kernel->type == RSD_KERNEL_HELMHOLTZ ? 4 : 1;
+        *bytes = 8 * (std::max<int64_t>(cx * f64, 1) + std::max<int64_t>(cx * t64, 1)) +
+                 4 * (std::max<int64_t>(cx * f32, 1) + std::max<int64_t>(cx * t32, 1));
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_self_cell_integral(int32_t kernel_type, double h, double k, double* re, double* im) {
+    return guarded([&]() {
+        if (!re || !im) throw rsd::Error(RSD_EINVAL, "null output");
+        if (!(h > 0) || (kernel_type == RSD_KERNEL_HELMHOLTZ && !(k > 0)))
+            throw rsd::Error(RSD_EINVAL, "h and the wavenumber must be positive");
+        if (kernel_type != RSD_KERNEL_LAPLACE && kernel_type != RSD_KERNEL_HELMHOLTZ)
+            throw rsd::Error(RSD_EINVAL, "unknown kernel type");
+        rsd::self_cell_integral(kernel_type, h, k, *re, *im);
         return RSD_OK;
     });
 }

@@ -5,9 +5,12 @@
 // The off-diagonal part is a two-level Toeplitz matrix in the grid offsets,
 // so it is embedded in an Mx x My circulant (powers of two, Mx >= 2 nx,
 // My >= 2 ny) and applied through 2-D FFTs: conv = IFFT(C^ . FFT(S x)).  The
-// kernel is even in both offsets, so the spectrum C^ is real and two
-// right-hand sides travel together as the real and imaginary parts of one
-// complex field.  The 1-D transforms are radix-2 in LDS: a workgroup loads
+// kernel is even in both offsets, so for the real (Laplace) kernel the
+// spectrum C^ is real and two right-hand sides travel together as the real
+// and imaginary parts of one complex field; for the complex Helmholtz kernel
+// (Sec. 5.3) the spectrum is complex (the transforms of its real and
+// imaginary parts, each real) and each complex right-hand side (interleaved)
+// is one field.  The 1-D transforms are radix-2 in LDS: a workgroup loads
 // up to 8 lines (rows, or 8 adjacent columns so that loads stay coalesced)
 // in bit-reversed order, runs log2 L butterfly stages in place with one
 // barrier each, and writes them back.
@@ -75,16 +78,76 @@ __global__ void circulant_kernel(double2* __restrict__ C, int64_t nx, int64_t ny
         const int64_t u = e / My, v = e % My;
         const int64_t du = u < nx ? u : (Mx - u < nx ? Mx - u : -1);
         const int64_t dv = v < ny ? v : (My - v < ny ? My - v : -1);
-        double val = 0.0;
-        if (du >= 0 && dv >= 0 && (du | dv) != 0)
-            val = kd.h * kd.h * INV_2PI * (kd.logh + 0.5 * log((double)(du * du + dv * dv)));
-        C[e] = make_double2(val, 0.0);
+        double re = 0.0, im = 0.0;
+        if (du >= 0 && dv >= 0 && (du | dv) != 0) {
+            const double rho2 = (double)(du * du + dv * dv);
+            if (kd.type == 1) {       // (i/4) H0^(1)(k r) = -Y0/4 + i J0/4
+                const double z = kd.k * kd.h * sqrt(rho2);
+                re = kd.h * kd.h * (-0.25 * y0(z));
+                im = kd.h * kd.h * (0.25 * j0(z));
+            } else {
+                re = kd.h * kd.h * INV_2PI * (kd.logh + 0.5 * log(rho2));
+            }
+        }
+        C[e] = make_double2(re, im);
     }
 }
 
 __global__ void spectrum_kernel(double* __restrict__ Cr, const double2* __restrict__ C, int64_t n) {
     for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
         Cr[e] = C[e].x;
+}
+
+__global__ void spectrum_c_kernel(double2* __restrict__ Cc, const double2* __restrict__ C, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+        Cc[e] = C[e];
+}
+
+// complex right-hand side c (interleaved, grid order): field = S x_c zero-padded
+__global__ void pack_c_kernel(double2* __restrict__ X, const double* __restrict__ x, int64_t N, int c,
+                              int64_t nx, int64_t ny, int Mx, int My, KernelDesc kd) {
+    const int64_t n = (int64_t)Mx * My;
+    for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int64_t u = e / My, v = e % My;
+        double re = 0.0, im = 0.0;
+        if (u < nx && v < ny) {
+            const int64_t g = u * ny + v;
+            const double s = kd.has_b ? kd.sb[g] : 1.0;
+            re = s * x[2 * (g + (int64_t)c * N)];
+            im = s * x[2 * (g + (int64_t)c * N) + 1];
+        }
+        X[e] = make_double2(re, im);
+    }
+}
+
+__global__ void mul_c_kernel(double2* __restrict__ X, const double2* __restrict__ Cc, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const double2 c = Cc[e], z = X[e];
+        X[e] = make_double2(c.x * z.x - c.y * z.y, c.x * z.y + c.y * z.x);
+    }
+}
+
+// y_c = S conv / (Mx My) + d x_c, d = 1 + b sc (contrast) or a + sc (complex sc)
+__global__ void unpack_c_kernel(double* __restrict__ y, const double2* __restrict__ X,
+                                const double* __restrict__ x, int64_t N, int c, int64_t nx, int64_t ny,
+                                int My, double scale, KernelDesc kd) {
+    for (int64_t g = blockIdx.x * (int64_t)256 + threadIdx.x; g < N; g += (int64_t)gridDim.x * 256) {
+        const int64_t i = g / ny, j = g % ny;
+        const double2 z = X[i * My + j];
+        double s = 1.0, dr, di;
+        if (kd.has_b) {
+            s = kd.sb[g];
+            dr = 1.0 + s * s * kd.sc_re;
+            di = s * s * kd.sc_im;
+        } else {
+            dr = (kd.a ? kd.a[g] : 1.0) + kd.sc_re;
+            di = kd.sc_im;
+        }
+        const int64_t o = 2 * (g + (int64_t)c * N);
+        const double xr = x[o], xi = x[o + 1];
+        y[o] = s * (z.x * scale) + dr * xr - di * xi;
+        y[o + 1] = s * (z.y * scale) + dr * xi + di * xr;
+    }
 }
 
 // field = (S x_c0) + i (S x_c1) zero-padded (c1 absent when c0 is the last)
@@ -175,13 +238,28 @@ void launch_fft_spectrum(double* Cr, double2* work, int64_t nx, int64_t ny, int 
     const int64_t n = (int64_t)Mx * My;
     hipLaunchKernelGGL(circulant_kernel, dim3(grid_for(n)), dim3(256), 0, s, work, nx, ny, Mx, My, kd);
     fft2(work, Mx, My, -1, s);
-    hipLaunchKernelGGL(spectrum_kernel, dim3(grid_for(n)), dim3(256), 0, s, Cr, work, n);
+    if (kd.type == 1)
+        hipLaunchKernelGGL(spectrum_c_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                           reinterpret_cast<double2*>(Cr), work, n);
+    else
+        hipLaunchKernelGGL(spectrum_kernel, dim3(grid_for(n)), dim3(256), 0, s, Cr, work, n);
 }
 
 void launch_fft_matvec(double* y, const double* x, int nrhs, const double* Cr, double2* work,
                        int64_t nx, int64_t ny, int Mx, int My, KernelDesc kd, hipStream_t s) {
     const int64_t N = nx * ny, n = (int64_t)Mx * My;
     const double scale = 1.0 / (double)n;
+    if (kd.type == 1) {       // complex kernel and vectors: one right-hand side per field
+        const double2* Cc = reinterpret_cast<const double2*>(Cr);
+        for (int c = 0; c < nrhs; ++c) {
+            hipLaunchKernelGGL(pack_c_kernel, dim3(grid_for(n)), dim3(256), 0, s, work, x, N, c, nx, ny, Mx, My, kd);
+            fft2(work, Mx, My, -1, s);
+            hipLaunchKernelGGL(mul_c_kernel, dim3(grid_for(n)), dim3(256), 0, s, work, Cc, n);
+            fft2(work, Mx, My, +1, s);
+            hipLaunchKernelGGL(unpack_c_kernel, dim3(grid_for(N)), dim3(256), 0, s, y, work, x, N, c, nx, ny, My, scale, kd);
+        }
+        return;
+    }
     for (int c0 = 0; c0 < nrhs; c0 += 2) {
         hipLaunchKernelGGL(pack_kernel, dim3(grid_for(n)), dim3(256), 0, s, work, x, N, c0, nrhs, nx, ny, Mx, My, kd);
         fft2(work, Mx, My, -1, s);

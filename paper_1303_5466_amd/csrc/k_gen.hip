@@ -1,5 +1,6 @@
 // Kernel-matrix generation from grid coordinates (Sec. 5, general
-// formulation): leaf diagonal blocks D_i, the parent blocks
+// formulation; the Helmholtz kernel of Sec. 5.3 on two dofs per point, see
+// KernelDesc): leaf diagonal blocks D_i, the parent blocks
 // F_i = D_i + diag(E_c1, E_c2) of Algorithm 1 (sibling interactions
 // generated on the fly, children's E_c gathered), and the proxy matrices
 // [K(Z, X^sk) | K(Z, X^rs)] of the interpolation problem (Sec. 3.1).
@@ -48,6 +49,25 @@ __device__ inline T diag_val(const KernelDesc& kd, int64_t g) {
     return T((kd.a ? kd.a[g] : 1.0) + kd.sc_re);
 }
 
+// Helmholtz G(r) = (i/4) H0^(1)(k r) = -Y0(k r)/4 + i J0(k r)/4 at r = h sqrt(rho2)
+__device__ inline void helmholtz_val(const KernelDesc& kd, double rho2, double& gr, double& gi) {
+    const double z = kd.k * kd.h * sqrt(rho2);
+    gr = -0.25 * y0(z);
+    gi = 0.25 * j0(z);
+}
+
+// Complex factors: the (pi, pj) component of J of the entry between two dofs
+// of points at offsets (du, dv) (same point: du = dv = 0, grid index g) --
+// a_g + sc on the diagonal, h^2 G off it (scale = h^2), or the proxy kernel
+// G itself (scale = 1).
+__device__ inline double cplx_entry(const KernelDesc& kd, int du, int dv, int64_t g, int pi, int pj,
+                                    double scale) {
+    if (du == 0 && dv == 0) return jform((kd.a ? kd.a[g] : 1.0) + kd.sc_re, kd.sc_im, pi, pj);
+    double gr, gi;
+    helmholtz_val(kd, (double)(du * du + dv * dv), gr, gi);
+    return scale * jform(gr, gi, pi, pj);
+}
+
 // Leaf block D_i of one box: kernel entries off the diagonal, the
 // identity coefficient plus the self-cell integral on it.
 template <typename T>
@@ -62,6 +82,12 @@ __device__ inline void leaf_F_box(T* __restrict__ F, const BoxDev* __restrict__ 
     const int* V = lv + L.off_uv;
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)m * m; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % m), j = (int)(e / m);
+        if (kd.cplx) {
+            const int64_t g = (int64_t)(b.x0 + U[i]) * kd.ny + (b.y0 + V[i]);
+            Fb[e] = T(cplx_entry(kd, U[i] - U[j], V[i] - V[j], g, dof_plane(i, L.k, L.r),
+                                 dof_plane(j, L.k, L.r), kd.h * kd.h));
+            continue;
+        }
         T val;
         if (i == j) {
             const int64_t g = (int64_t)(b.x0 + U[i]) * kd.ny + (b.y0 + V[i]);
@@ -123,6 +149,9 @@ __device__ inline void assemble_box(TD* __restrict__ F, const TS* __restrict__ F
             const BoxDev& c = ci ? c1 : c0;
             const int mc = ci ? m1 : m0;
             val = (TD)Fc[c.offF + SI[i] + (int64_t)SI[j] * mc];
+        } else if (kd.cplx) {
+            val = TD(cplx_entry(kd, U[i] - U[j], V[i] - V[j], 0, dof_plane(i, L.k, L.r),
+                                dof_plane(j, L.k, L.r), kd.h * kd.h));
         } else {
             val = KV<TD>::off(kd, U[i] - U[j], V[i] - V[j]);
             if (kd.has_b) {
@@ -176,8 +205,15 @@ __global__ void __launch_bounds__(256) proxy_kernel(
     const int* ZV = zv + zoff[pb];
     const int* XU = xu + xoff[pb];
     const int* XV = xv + xoff[pb];
+    const int pz = kd.cplx ? p / 2 : p;    // proxy points (rows: plane 0 then plane 1)
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)p * n; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % p), j = (int)(e / p);
+        if (kd.cplx) {
+            const int zi = i % pz;
+            Ab[e] = T(cplx_entry(kd, ZU[zi] - XU[j], ZV[zi] - XV[j], 0, i / pz,
+                                 dof_plane(j, k_of[pb], r_of[pb]), 1.0));
+            continue;
+        }
         if (sec < 0) {
             Ab[e] = KV<T>::proxy(kd, ZU[i] - XU[j], ZV[i] - XV[j]);
         } else {

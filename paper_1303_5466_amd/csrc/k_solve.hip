@@ -18,14 +18,15 @@ __global__ void __launch_bounds__(256) gather_leaf_kernel(
     TD* __restrict__ V, const TS* __restrict__ f, int64_t ldf, int nrhs,
     const BoxDev* __restrict__ boxes, const int* __restrict__ box_ids,
     const LayoutDev* __restrict__ layouts, const int* __restrict__ lu, const int* __restrict__ lv,
-    const int64_t* __restrict__ perm, int64_t ny) {
+    const int64_t* __restrict__ perm, int64_t ny, int64_t plane_off) {
     const BoxDev b = boxes[box_ids[blockIdx.y]];
     const LayoutDev L = layouts[b.layout];
     const int m = L.k + L.r;
     TD* Vb = V + b.offV * nrhs;
     for (int e = blockIdx.x * 256 + threadIdx.x; e < m * nrhs; e += gridDim.x * 256) {
         const int q = e % m, c = e / m;
-        const int64_t g = (int64_t)(b.x0 + lu[L.off_uv + q]) * ny + (b.y0 + lv[L.off_uv + q]);
+        int64_t g = (int64_t)(b.x0 + lu[L.off_uv + q]) * ny + (b.y0 + lv[L.off_uv + q]);
+        if (plane_off) g += dof_plane(q, L.k, L.r) * plane_off;
         Vb[q + (int64_t)c * m] = (TD)f[perm[g] + c * ldf];
     }
 }
@@ -35,13 +36,14 @@ __global__ void __launch_bounds__(256) scatter_leaf_kernel(
     TD* __restrict__ x, int64_t ldx, const TS* __restrict__ V, const TS* __restrict__ Y, int nrhs,
     const BoxDev* __restrict__ boxes, const int* __restrict__ box_ids,
     const LayoutDev* __restrict__ layouts, const int* __restrict__ lu, const int* __restrict__ lv,
-    const int64_t* __restrict__ perm, int64_t ny) {
+    const int64_t* __restrict__ perm, int64_t ny, int64_t plane_off) {
     const BoxDev b = boxes[box_ids[blockIdx.y]];
     const LayoutDev L = layouts[b.layout];
     const int m = L.k + L.r;
     for (int e = blockIdx.x * 256 + threadIdx.x; e < m * nrhs; e += gridDim.x * 256) {
         const int q = e % m, c = e / m;
-        const int64_t g = (int64_t)(b.x0 + lu[L.off_uv + q]) * ny + (b.y0 + lv[L.off_uv + q]);
+        int64_t g = (int64_t)(b.x0 + lu[L.off_uv + q]) * ny + (b.y0 + lv[L.off_uv + q]);
+        if (plane_off) g += dof_plane(q, L.k, L.r) * plane_off;
         const TS v = q < L.k ? V[b.offV * nrhs + q + (int64_t)c * m]
                              : Y[b.offY * nrhs + (q - L.k) + (int64_t)c * L.r];
         x[perm[g] + c * ldx] = (TD)v;
@@ -136,6 +138,42 @@ __global__ void __launch_bounds__(256) colnorm_kernel(double* __restrict__ out,
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// Right-hand side of the factored system from a grid-ordered one (N x nrhs,
+// float64, or interleaved complex when cplx): scaled by 1/sqrt(b) (sb given;
+// the contrast form A = S M S, S = diag sqrt b) and, for complex vectors,
+// split into the two dof planes of J: R = [Re; Im] per column (ld 2N).
+__global__ void scale_split_kernel(double* __restrict__ R, const double* __restrict__ f,
+                                   const double* __restrict__ sb, int64_t N, int nrhs, int cplx) {
+    const int64_t tot = N * nrhs;
+    for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int64_t g = e % N, c = e / N;
+        const double s = sb ? 1.0 / sb[g] : 1.0;
+        if (cplx) {
+            R[g + c * 2 * N] = s * f[2 * e];
+            R[N + g + c * 2 * N] = s * f[2 * e + 1];
+        } else {
+            R[e] = s * f[e];
+        }
+    }
+}
+
+// Inverse of the above for the solution: x = S^-1 (u - i w) (complex) or
+// S^-1 u, from the dof planes [u; w] of J.
+__global__ void scale_merge_kernel(double* __restrict__ x, const double* __restrict__ X,
+                                   const double* __restrict__ sb, int64_t N, int nrhs, int cplx) {
+    const int64_t tot = N * nrhs;
+    for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256) {
+        const int64_t g = e % N, c = e / N;
+        const double s = sb ? 1.0 / sb[g] : 1.0;
+        if (cplx) {
+            x[2 * e] = s * X[g + c * 2 * N];
+            x[2 * e + 1] = -s * X[N + g + c * 2 * N];
+        } else {
+            x[e] = s * X[e];
+        }
+    }
+}
+
 __global__ void finite_kernel(const double* __restrict__ x, int64_t n, int* __restrict__ flag) {
     for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         if (!isfinite(x[i])) atomicOr(flag, 1);
@@ -146,19 +184,22 @@ __global__ void finite_kernel(const double* __restrict__ x, int64_t n, int* __re
 template <typename TS, typename TD>
 void launch_gather_leaf(TD* V, const TS* f, int64_t ldf, int nrhs, const BoxDev* boxes,
                         const int* box_ids, int n_boxes, const LayoutDev* layouts, const int* lu,
-                        const int* lv, const int64_t* perm, int64_t ny, int max_m, hipStream_t s) {
+                        const int* lv, const int64_t* perm, int64_t ny, int64_t plane_off, int max_m,
+                        hipStream_t s) {
     if (n_boxes <= 0) return;
     hipLaunchKernelGGL((gather_leaf_kernel<TS, TD>), dim3(chunks((int64_t)max_m * nrhs), n_boxes),
-                       dim3(256), 0, s, V, f, ldf, nrhs, boxes, box_ids, layouts, lu, lv, perm, ny);
+                       dim3(256), 0, s, V, f, ldf, nrhs, boxes, box_ids, layouts, lu, lv, perm, ny,
+                       plane_off);
 }
 template <typename TS, typename TD>
 void launch_scatter_leaf(TD* x, int64_t ldx, const TS* V, const TS* Y, int nrhs,
                          const BoxDev* boxes, const int* box_ids, int n_boxes,
                          const LayoutDev* layouts, const int* lu, const int* lv,
-                         const int64_t* perm, int64_t ny, int max_m, hipStream_t s) {
+                         const int64_t* perm, int64_t ny, int64_t plane_off, int max_m, hipStream_t s) {
     if (n_boxes <= 0) return;
     hipLaunchKernelGGL((scatter_leaf_kernel<TS, TD>), dim3(chunks((int64_t)max_m * nrhs), n_boxes),
-                       dim3(256), 0, s, x, ldx, V, Y, nrhs, boxes, box_ids, layouts, lu, lv, perm, ny);
+                       dim3(256), 0, s, x, ldx, V, Y, nrhs, boxes, box_ids, layouts, lu, lv, perm, ny,
+                       plane_off);
 }
 template <typename TS, typename TD>
 void launch_scatter_up(TD* Vparent, const TS* V, int nrhs, const BoxDev* boxes, const int* box_ids,
@@ -195,6 +236,14 @@ void launch_add(double* x, const double* d, int64_t n, hipStream_t s) {
 void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, hipStream_t s) {
     hipLaunchKernelGGL(colnorm_kernel, dim3(ncols), dim3(256), 0, s, out, x, n);
 }
+void launch_scale_split(double* R, const double* f, const double* sb, int64_t N, int nrhs, int cplx,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(scale_split_kernel, dim3(chunks(N * nrhs)), dim3(256), 0, s, R, f, sb, N, nrhs, cplx);
+}
+void launch_scale_merge(double* x, const double* X, const double* sb, int64_t N, int nrhs, int cplx,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(scale_merge_kernel, dim3(chunks(N * nrhs)), dim3(256), 0, s, x, X, sb, N, nrhs, cplx);
+}
 void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s) {
     hipLaunchKernelGGL(finite_kernel, dim3(chunks(n)), dim3(256), 0, s, x, n, flag);
 }
@@ -202,11 +251,12 @@ void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s) {
 #define INST2(TS, TD)                                                                              \
     template void launch_gather_leaf<TS, TD>(TD*, const TS*, int64_t, int, const BoxDev*,          \
                                              const int*, int, const LayoutDev*, const int*,        \
-                                             const int*, const int64_t*, int64_t, int, hipStream_t); \
+                                             const int*, const int64_t*, int64_t, int64_t, int,    \
+                                             hipStream_t);                                         \
     template void launch_scatter_leaf<TD, TS>(TS*, int64_t, const TD*, const TD*, int,             \
                                               const BoxDev*, const int*, int, const LayoutDev*,    \
                                               const int*, const int*, const int64_t*, int64_t,     \
-                                              int, hipStream_t);                                   \
+                                              int64_t, int, hipStream_t);                          \
     template void launch_convert<TS, TD>(TD*, const TS*, int64_t, hipStream_t);
 INST2(double, double)
 INST2(double, float)

@@ -56,6 +56,7 @@ struct Slot {
     rsd_factor* f = nullptr;
     hipStream_t stream = nullptr;
     int64_t n = 0;
+    int w = 1;                       // doubles per vector entry (2: complex factor)
     int64_t bytes = 0;               // admission size (estimate until built)
     bool busy = false;
     Clock::time_point last_use;
@@ -205,7 +206,7 @@ struct rsd_server {
             } else {
                 s2.f = fac;
                 s2.stream = stream;
-                s2.bytes = fs.factor_bytes + batch_bytes(s2.n);
+                s2.bytes = fs.factor_bytes + batch_bytes(s2.n * s2.w);
                 resident += s2.bytes;
                 s2.state = READY;
                 s2.last_use = Clock::now();
@@ -280,7 +281,7 @@ struct rsd_server {
     // one coalesced solve: gather the right-hand sides into n x P columns (P a
     // power of two, zero padding), solve, scatter the solutions back
     rsd_status run_batch(Slot& sl, std::vector<Request*>& rq, int64_t cols) {
-        const int64_t n = sl.n;
+        const int64_t n = sl.n * sl.w;   // doubles per column
         const int64_t P = pow2_at_least(cols);
         if (P > sl.cap) {
             if (sl.dbuf) (void)hipFree(sl.dbuf);
@@ -422,15 +423,17 @@ rsd_status rsd_server_submit_factor(rsd_server* s, const double* points, int64_t
         std::vector<int64_t> perm((size_t)n_points);
         rsd_status st = rsd_detect_grid(job->points.data(), n_points, &nx, &ny, &h, perm.data());
         if (st != RSD_OK) return st;
-        st = rsd_estimate_factor_bytes(nx, ny, tol, &job->opt, &est);
+        st = rsd_estimate_factor_bytes(nx, ny, &job->kernel, tol, &job->opt, &est);
         if (st != RSD_OK) return st;
+        const int w = job->kernel.type == RSD_KERNEL_HELMHOLTZ ? 2 : 1;
         std::lock_guard<std::mutex> lk(s->mu);
-        const int64_t bytes = est + s->batch_bytes(n_points);
+        const int64_t bytes = est + s->batch_bytes(n_points * w);
         if (bytes > s->opt.mem_budget) return RSD_ENOMEM;
         const int64_t id = s->next_fid++;
         Slot& sl = s->slots[id];
         sl.job = std::move(job);
         sl.n = n_points;
+        sl.w = w;
         sl.bytes = bytes;
         sl.state = QUEUED;
         *factor_id = id;

@@ -25,6 +25,7 @@ RSD_PREC_FP64, RSD_PREC_FP32_REFINE = 0, 1
 RSD_FLAG_KEEP_E = 1
 RSD_FLAG_NO_SYMMETRY = 2
 RSD_FLAG_FP32_INTERP = 4
+RSD_FLAG_NO_DEDUP = 8
 
 
 class rsd_kernel(C.Structure):
@@ -46,7 +47,7 @@ class rsd_factor_stats(C.Structure):
                 ("n_levels", C.c_int32), ("n_boxes", C.c_int32), ("layers", C.c_int32),
                 ("precision", C.c_int32), ("factor_bytes", C.c_int64),
                 ("factor_flops", C.c_double), ("solve_bytes", C.c_double),
-                ("build_ms", C.c_double)]
+                ("build_ms", C.c_double), ("complex_values", C.c_int32)]
 
 
 class rsd_box_info(C.Structure):
@@ -73,8 +74,15 @@ EXPORTS = {
                                            C.POINTER(C.c_int64)]),
     "rsd_server_release_factor": (C.c_int, [C.c_void_p, C.c_int64]),
     "rsd_server_wait_factor": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32]),
-    "rsd_estimate_factor_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_double, C.POINTER(rsd_options),
-                                            C.POINTER(C.c_int64)]),
+    "rsd_autotune": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(rsd_kernel), C.c_void_p,
+                               C.c_double, C.POINTER(rsd_options), C.c_int32, C.POINTER(C.c_int32)]),
+    "rsd_tune_save": (C.c_int, [C.c_char_p]),
+    "rsd_tune_load": (C.c_int, [C.c_char_p]),
+    "rsd_tune_clear": (C.c_int, [C.POINTER(C.c_int64)]),
+    "rsd_self_cell_integral": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]),
+    "rsd_estimate_factor_bytes": (C.c_int, [C.c_int64, C.c_int64, C.POINTER(rsd_kernel), C.c_double,
+                                            C.POINTER(rsd_options), C.POINTER(C.c_int64)]),
     "rsd_server_submit_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                           C.POINTER(C.c_int64)]),
     "rsd_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(rsd_solve_info)]),
@@ -247,19 +255,23 @@ class Factor:
 
     def solve(self, f):
         """x = A^{-1} f for a NumPy (N,) / (N, nrhs) array or a CUDA tensor of
-        the same shape; returns the same kind of object and the solve info."""
+        the same shape; returns the same kind of object and the solve info.
+        Helmholtz factors take and return complex128 values."""
         vec = f.ndim == 1
         if _is_torch(f):
             import torch
             F = f.reshape(self.n, -1)
             nrhs = F.shape[1]
             Ft = F.t().contiguous()
+            if self.complex and not Ft.is_complex():
+                Ft = Ft.to(torch.complex128)
             Xt = torch.empty_like(Ft)
             st, info = self.solve_raw(Ft.data_ptr(), nrhs, Xt.data_ptr())
             _check(st)
             X = Xt.t()
             return (X[:, 0] if vec else X), info
-        F = np.asfortranarray(np.asarray(f, dtype=np.float64).reshape(self.n, -1))
+        dt = np.complex128 if self.complex else np.float64
+        F = np.asfortranarray(np.asarray(f, dtype=dt).reshape(self.n, -1))
         X = np.zeros_like(F, order="F")
         st, info = self.solve_raw(F.ctypes.data, F.shape[1], X.ctypes.data)
         _check(st)
@@ -267,7 +279,8 @@ class Factor:
 
     def matvec(self, x):
         vec = x.ndim == 1
-        X = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(self.n, -1))
+        dt = np.complex128 if self.complex else np.float64
+        X = np.asfortranarray(np.asarray(x, dtype=dt).reshape(self.n, -1))
         Y = np.zeros_like(X, order="F")
         _check(load().rsd_matvec(self._h, X.ctypes.data, X.shape[1], Y.ctypes.data))
         return Y[:, 0] if vec else Y
@@ -279,7 +292,8 @@ class Factor:
 
 
 def build_batched(points_list, a_list=None, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0,
-                  layers=0, max_refine=0, refine_tol=0.0, max_inflight=0, flags=0):
+                  layers=0, max_refine=0, refine_tol=0.0, max_inflight=0, flags=0,
+                  kernel=RSD_KERNEL_LAPLACE, wavenumber=0.0):
     """rsd_build_factor_batched: one Factor per (points, a) instance."""
     lib = load()
     n_inst = len(points_list)
@@ -300,7 +314,7 @@ def build_batched(points_list, a_list=None, tol=1e-10, precision=RSD_PREC_FP64, 
         ap, k2 = _ptr(a)
         keep += [a, k2]
         a_p[i] = ap
-    kd = rsd_kernel(RSD_KERNEL_LAPLACE, 0.0, None)
+    kd = rsd_kernel(kernel, wavenumber, None)
     opt = rsd_options(leaf_side, layers, precision, max_refine, refine_tol, None, -1, flags)
     out = (C.c_void_p * n_inst)()
     _check(lib.rsd_build_factor_batched(n_inst, pts_p, npts, C.byref(kd), a_p, tol, C.byref(opt),
@@ -336,21 +350,25 @@ class Server:
         self._n = {}          # factor id -> number of points
 
     def submit_factor(self, points, a=None, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0,
-                      layers=0, max_refine=0, refine_tol=0.0, wait=True):
+                      layers=0, max_refine=0, refine_tol=0.0, wait=True, kernel=RSD_KERNEL_LAPLACE,
+                      wavenumber=0.0, contrast=None):
         """Queue a factor request; with wait=True return once it is resident
         (raises the build's error), else at once (see wait_factor)."""
         if isinstance(points, np.ndarray):
             points = np.ascontiguousarray(points, dtype=np.float64)
         if isinstance(a, np.ndarray):
             a = np.ascontiguousarray(a, dtype=np.float64)
+        if isinstance(contrast, np.ndarray):
+            contrast = np.ascontiguousarray(contrast, dtype=np.float64)
         pp, _k1 = _ptr(points)
         ap, _k2 = _ptr(a)
-        kd = rsd_kernel(RSD_KERNEL_LAPLACE, 0.0, None)
+        bp, _k3 = _ptr(contrast)
+        kd = rsd_kernel(kernel, wavenumber, bp)
         opt = rsd_options(leaf_side, layers, precision, max_refine, refine_tol, None, -1, 0)
         fid = C.c_int64()
         _check(load().rsd_server_submit_factor(self._h, pp, points.shape[0], C.byref(kd), ap, tol,
                                                C.byref(opt), C.byref(fid)))
-        self._n[fid.value] = int(points.shape[0])
+        self._n[fid.value] = (int(points.shape[0]), kernel == RSD_KERNEL_HELMHOLTZ)
         if wait:
             self.wait_factor(fid.value)
         return fid.value
@@ -373,20 +391,22 @@ class Server:
         the same shape, and is filled when the ticket is waited), or contiguous
         float64 torch tensors on the device of shape (N,) or (nrhs, N) (= N x
         nrhs column-major).  Shapes are checked against the factor's N."""
-        n = self._n.get(fid)
-        if n is None:
+        entry = self._n.get(fid)
+        if entry is None:
             raise RsdError(RSD_EINVAL, f"unknown factor {fid}")
+        n, cplx = entry
+        ndt = np.complex128 if cplx else np.float64
         copy_back = None
         if isinstance(rhs, np.ndarray):
             if rhs.ndim not in (1, 2) or rhs.shape[0] != n:
                 raise RsdError(RSD_EINVAL, f"rhs shape {rhs.shape} does not match N = {n}")
             nrhs = 1 if rhs.ndim == 1 else rhs.shape[1]
-            if not isinstance(out, np.ndarray) or out.shape != rhs.shape or out.dtype != np.float64:
-                raise RsdError(RSD_EINVAL, "out must be a float64 NumPy array of the rhs shape")
-            rhs = np.asfortranarray(rhs, dtype=np.float64)
+            if not isinstance(out, np.ndarray) or out.shape != rhs.shape or out.dtype != ndt:
+                raise RsdError(RSD_EINVAL, f"out must be a {np.dtype(ndt).name} NumPy array of the rhs shape")
+            rhs = np.asfortranarray(rhs, dtype=ndt)
             if not out.flags.f_contiguous:
                 copy_back = out
-                out = np.zeros(out.shape, dtype=np.float64, order="F")
+                out = np.zeros(out.shape, dtype=ndt, order="F")
         else:
             import torch
             if not (isinstance(rhs, torch.Tensor) and isinstance(out, torch.Tensor)):
@@ -399,9 +419,10 @@ class Server:
                 ok = rhs.dim() == 2 and rhs.shape[1] == n
             if not ok:
                 raise RsdError(RSD_EINVAL, f"rhs shape {tuple(rhs.shape)} is not (N,) or (nrhs, N), N = {n}")
+            tdt = torch.complex128 if cplx else torch.float64
             for name, t in (("rhs", rhs), ("out", out)):
-                if t.dtype != torch.float64 or not t.is_contiguous():
-                    raise RsdError(RSD_EINVAL, f"{name} must be a contiguous float64 tensor")
+                if t.dtype != tdt or not t.is_contiguous():
+                    raise RsdError(RSD_EINVAL, f"{name} must be a contiguous {tdt} tensor")
             if out.shape != rhs.shape or out.device != rhs.device:
                 raise RsdError(RSD_EINVAL, "out must have the shape and device of rhs")
         tk = C.c_int64()
@@ -589,9 +610,60 @@ def detect_grid(points):
     return nx.value, ny.value, h.value, perm
 
 
-def estimate_factor_bytes(nx, ny, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0, layers=0):
+def estimate_factor_bytes(nx, ny, tol=1e-10, precision=RSD_PREC_FP64, leaf_side=0, layers=0,
+                          kernel=None):
     """Device bytes of the factor of an nx x ny grid (host only)."""
     opt = rsd_options(leaf_side, layers, precision, 0, 0.0, None, -1, 0)
+    kd = rsd_kernel(RSD_KERNEL_LAPLACE if kernel is None else kernel, 1.0, None)
     out = C.c_int64()
-    _check(load().rsd_estimate_factor_bytes(nx, ny, tol, C.byref(opt), C.byref(out)))
+    _check(load().rsd_estimate_factor_bytes(nx, ny, C.byref(kd), tol, C.byref(opt), C.byref(out)))
     return out.value
+
+
+def self_cell_integral(h, kernel=RSD_KERNEL_LAPLACE, k=0.0):
+    """The library's diagonal term: integral of the kernel over the cell of side h."""
+    re, im = C.c_double(), C.c_double()
+    _check(load().rsd_self_cell_integral(kernel, h, k, C.byref(re), C.byref(im)))
+    return complex(re.value, im.value) if kernel == RSD_KERNEL_HELMHOLTZ else re.value
+
+
+def autotune(points_list, a_list=None, tol=1e-8, precision=RSD_PREC_FP32_REFINE, reps=2, leaf_side=0, layers=0):
+    """rsd_autotune on one grid or a batch (host or device arrays); returns
+    the number of shape buckets set."""
+    n_inst = len(points_list)
+    keep = []
+    pts_p = (C.c_void_p * n_inst)()
+    a_p = (C.c_void_p * n_inst)()
+    npts = (C.c_int64 * n_inst)()
+    for i, pts in enumerate(points_list):
+        if isinstance(pts, np.ndarray):
+            pts = np.ascontiguousarray(pts, dtype=np.float64)
+        p, k = _ptr(pts)
+        keep += [pts, k]
+        pts_p[i] = p
+        npts[i] = pts.shape[0]
+        a = a_list[i] if a_list is not None else None
+        if isinstance(a, np.ndarray):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+        ap, k2 = _ptr(a)
+        keep += [a, k2]
+        a_p[i] = ap
+    kd = rsd_kernel(RSD_KERNEL_LAPLACE, 0.0, None)
+    opt = rsd_options(leaf_side, layers, precision, 0, 0.0, None, -1, 0)
+    n = C.c_int32()
+    _check(load().rsd_autotune(n_inst, pts_p, npts, C.byref(kd), a_p, tol, C.byref(opt), reps, C.byref(n)))
+    return n.value
+
+
+def tune_save(path):
+    _check(load().rsd_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    _check(load().rsd_tune_load(str(path).encode()))
+
+
+def tune_clear():
+    n = C.c_int64()
+    _check(load().rsd_tune_clear(C.byref(n)))
+    return n.value

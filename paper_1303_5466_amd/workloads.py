@@ -103,3 +103,17 @@ def make_workload(name: str):
     gen = rhs_uniform if w["rhs"] == "uniform" else rhs_normal
     f = gen(pts.shape[0], w["nrhs"], w["seed"])
     return pts, a, f, w["tol"]
+
+
+def rhs_complex_normal(n_points: int, nrhs: int, seed: int) -> np.ndarray:
+    """(n_points, nrhs) complex RHS, real and imaginary parts ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((nrhs, n_points)) + 1j * rng.standard_normal((nrhs, n_points))
+    return np.ascontiguousarray(z.T)
+
+
+# Served scattering workload: the Lippmann-Schwinger operator with the
+# Helmholtz kernel at wavenumber 20 and a Gaussian contrast bump (amplitude
+# 0.5, width 0.15, centred), grids of side 128 to 1024
+SCATTER_K = 20.0
+SCATTER_SIDES = (128, 256, 512, 1024)

@@ -1,0 +1,159 @@
+"""The Helmholtz (Lippmann-Schwinger) and contrast-form paths on the device,
+through the C interface, against the CPU reference: the scattering operator
+A = I + S G S of Sec. 5.4 (S = diag sqrt b, G = (i/4) H0^(1)(k r) of
+Sec. 5.3) on Gaussian-bump contrasts, and the Laplace kernel in the same
+contrast form."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import dense, krylov, nystrom
+from paper_1303_5466_amd import rsd, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+K = W.SCATTER_K
+
+
+def _incident(pts, b, k=K, src=(-0.5, 0.5)):
+    """Right-hand side -sqrt(b) u_in for a point source outside the domain."""
+    r = np.sqrt(((pts - np.asarray(src)) ** 2).sum(axis=1))
+    return -np.sqrt(b) * nystrom.kernel(r, "helmholtz", k)
+
+
+def test_exact_complex_product_matches_direct_sum():
+    # the device's FFT product of the scattering operator (Hankel function on
+    # the device) against the reference's dense rows
+    pts = W.grid_points(40, 32)
+    b = W.contrast_bump(pts)
+    fac = rsd.Factor(pts, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b)
+    x = W.rhs_complex_normal(len(pts), 3, 11)
+    y = fac.matvec(x)
+    rows = np.random.default_rng(3).choice(len(pts), 60, replace=False)
+    ref = nystrom.assemble(pts, None, "helmholtz", K, b, rows=rows) @ x
+    assert np.abs(y[rows] - ref).max() <= 1e-12 * np.abs(ref).max()
+    fac.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(32, 32), (48, 40), (64, 64)])
+def test_scattering_fp64_matches_dense(nx, ny):
+    pts = W.grid_points(nx, ny)
+    b = W.contrast_bump(pts)
+    f = np.stack([_incident(pts, b), W.rhs_complex_normal(len(pts), 1, nx)[:, 0]], axis=1)
+    fac = rsd.Factor(pts, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b)
+    assert fac.stats()["complex_values"] == 1
+    x, _ = fac.solve(f)
+    ref = dense.solve(pts, f, None, "helmholtz", K, b)
+    err = dense.rel_error(x, ref)
+    print(f"{nx}x{ny}: relative error vs dense {err:.2e}")
+    assert err < 1e-9
+    # device tensors, one column
+    xd, _ = fac.solve(torch.from_numpy(f[:, 0].copy()).to("cuda:0"))
+    assert dense.rel_error(xd.cpu().numpy(), ref[:, 0]) < 1e-9
+    fac.close()
+
+
+def test_scattering_fp32_refine_to_1e8():
+    # float32 J blocks + float64 complex residual and refinement to 1e-8 on a
+    # grid where the float32 factor is a contraction (two skeleton layers);
+    # where it is not, the solve reports ENOCONV instead of a wrong answer
+    pts = W.grid_points(64)
+    b = W.contrast_bump(pts)
+    f = np.stack([_incident(pts, b), W.rhs_complex_normal(len(pts), 1, 7)[:, 0]], axis=1)
+    fac = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b,
+                     precision=rsd.RSD_PREC_FP32_REFINE, layers=2)
+    x, info = fac.solve(f)
+    assert info.rel_residual <= 1e-8 and info.refine_iters >= 1
+    ref = dense.solve(pts, f, None, "helmholtz", K, b)
+    err = dense.rel_error(x, ref)
+    print(f"float32 + refinement: {info.refine_iters} steps, residual {info.rel_residual:.1e}, error {err:.1e}")
+    assert err < 1e-8
+    fac.close()
+    bad = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b,
+                     precision=rsd.RSD_PREC_FP32_REFINE, max_refine=3)
+    F = np.asfortranarray(f)
+    X = np.zeros_like(F)
+    st, info = bad.solve_raw(F.ctypes.data, 2, X.ctypes.data)
+    assert st in (rsd.RSD_OK, rsd.RSD_ENOCONV)
+    if st == rsd.RSD_OK:
+        assert info.rel_residual <= 1e-8
+    else:
+        assert info.rel_residual > 1e-8
+    bad.close()
+
+
+def test_scattering_128_256_refined_against_reference():
+    # the served configuration: float64 (complex128) factor at tol 1e-8 (three
+    # layers) plus complex128 refinement; exact residuals of every column and
+    # one column against the reference's GMRES
+    for n in (128, 256):
+        pts = W.grid_points(n)
+        b = W.contrast_bump(pts)
+        f = np.stack([_incident(pts, b), W.rhs_complex_normal(len(pts), 1, 5)[:, 0]], axis=1)
+        fac = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b,
+                         max_refine=2)
+        assert fac.stats()["layers"] == 3
+        x, info = fac.solve(f)
+        r = f - nystrom.matvec_fft(pts, x, None, "helmholtz", K, b)
+        res = np.linalg.norm(r, axis=0) / np.linalg.norm(f, axis=0)
+        assert res.max() <= 1e-8
+        if n == 128:
+            ref, _ = krylov.solve(pts, f[:, 0], None, "helmholtz", K, b, tol=1e-13)
+            assert np.linalg.norm(x[:, 0] - ref) <= 1e-8 * np.linalg.norm(ref)
+        fac.close()
+
+
+def test_laplace_contrast_form_matches_dense():
+    pts = W.grid_points(40, 36)
+    b = W.contrast_bump(pts, amp=0.8, width=0.2)
+    f = W.rhs_normal(len(pts), 2, 19)
+    fac = rsd.Factor(pts, None, 1e-10, contrast=b)
+    x, _ = fac.solve(f)
+    assert dense.rel_error(x, dense.solve(pts, f, None, "laplace", 0.0, b)) < 1e-10
+    fac.close()
+
+
+def test_complex_and_contrast_argument_errors():
+    pts = W.grid_points(16)
+    b = W.contrast_bump(pts)
+    with pytest.raises(rsd.RsdError) as e:        # the contrast must be positive
+        rsd.Factor(pts, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b * 0)
+    assert e.value.status == rsd.RSD_EINVAL
+    with pytest.raises(rsd.RsdError):             # a and the contrast together
+        rsd.Factor(pts, np.ones(len(pts)), 1e-10, contrast=b)
+    with pytest.raises(rsd.RsdError):             # wavenumber must be positive
+        rsd.Factor(pts, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=0.0, contrast=b)
+    with pytest.raises(rsd.RsdError):             # batched builds are Laplace-only
+        rsd.build_batched([pts], None, tol=1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ)
+
+
+def test_served_scattering_factors():
+    # Helmholtz factors resident in the server beside a Laplace one; complex
+    # requests coalesced per factor equal the direct solves
+    srv = rsd.Server(n_workers=2, max_coalesce=8)
+    grids = [W.grid_points(48), W.grid_points(32, 40)]
+    bs = [W.contrast_bump(p) for p in grids]
+    fids = [srv.submit_factor(p, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b)
+            for p, b in zip(grids, bs)]
+    lap = srv.submit_factor(W.grid_points(24))
+    direct = [rsd.Factor(p, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b)
+              for p, b in zip(grids, bs)]
+    reqs = []
+    for i in range(12):
+        g = i % 2
+        f = np.asfortranarray(W.rhs_complex_normal(len(grids[g]), 1 + i % 3, 100 + i))
+        x = np.zeros_like(f)
+        reqs.append((g, f, x, srv.submit_solve(fids[g], f, x)))
+    fl = np.asfortranarray(W.rhs_normal(24 * 24, 1, 3))
+    xl = np.zeros_like(fl)
+    tl = srv.submit_solve(lap, fl, xl)
+    for g, f, x, tk in reqs:
+        st, _ = srv.wait(tk)
+        assert st == rsd.RSD_OK
+        xa, _ = direct[g].solve(f)
+        assert np.linalg.norm(x - xa) <= 1e-12 * np.linalg.norm(xa)
+    assert srv.wait(tl)[0] == rsd.RSD_OK
+    assert dense.rel_error(xl, dense.solve(W.grid_points(24), fl)) < 1e-10
+    srv.close()
+    for d in direct:
+        d.close()

@@ -222,10 +222,13 @@ def test_fft_product_sizes(nx, ny):
     assert np.abs(y - y_ref).max() <= 1e-13 * np.abs(y_ref).max()
 
 
-def test_contrast_form_is_rejected_on_device():
+def test_contrast_form_needs_a_positive_contrast():
+    # the contrast form is factored as S (diag(1/b) + K) S, so b must be > 0
     pts = W.grid_points(16)
+    b = W.contrast_bump(pts)
+    b[7] = 0.0
     with pytest.raises(rsd.RsdError) as ei:
-        rsd.Factor(pts, None, 1e-10, contrast=W.contrast_bump(pts))
+        rsd.Factor(pts, None, 1e-10, contrast=b)
     assert ei.value.status == rsd.RSD_EINVAL
 
 
@@ -516,20 +519,21 @@ def test_server_memory_budget_admission():
     # the server sizes a factor before building it: the estimate equals the
     # built factor's bytes; a request larger than the budget fails at once
     p32 = W.grid_points(32)
-    probe = rsd.Factor(p32, None, 1e-10)
+    a32 = W.coef_sine(p32)
+    probe = rsd.Factor(p32, a32, 1e-10)
     fb = probe.stats()["factor_bytes"]
     probe.close()
     assert rsd.estimate_factor_bytes(32, 32, 1e-10) == fb
     srv = rsd.Server(mem_budget=fb // 2)
     with pytest.raises(rsd.RsdError) as ei:
-        srv.submit_factor(p32)
+        srv.submit_factor(p32, a32)
     assert ei.value.status == rsd.RSD_ENOMEM
     assert srv.stats()["n_factors"] == 0 and srv.stats()["resident_bytes"] == 0
     srv.close()
     # admission size = factor + coalescing/solve vectors of a full batch
     slot = fb + 6 * len(p32) * 8 * 8
     srv = rsd.Server(mem_budget=int(slot * 1.5), max_coalesce=8, evict_idle=True)
-    f1 = srv.submit_factor(p32)
+    f1 = srv.submit_factor(p32, a32)
     assert srv.stats()["resident_bytes"] == slot
     f2 = srv.submit_factor(p32, W.coef_sine(p32))
     s = srv.stats()
@@ -747,3 +751,61 @@ def test_low_accuracy_tolerance(precision, flags):
     x, info = fac.solve(f)
     r = f - nystrom.matvec_fft(pts, x, a)
     assert np.linalg.norm(r) <= 1e-5 * np.linalg.norm(f)
+
+
+# --- translation-invariant deduplication (constant a) ------------------------
+def test_shared_blocks_for_constant_coefficient():
+    # with a constant a every box of one type on one level has the same F, E,
+    # G and W (Sec. 5.1.2): one block per (level, type), same solution as the
+    # factor that builds every box, and far fewer bytes
+    pts = W.grid_points(64)
+    f = W.rhs_normal(len(pts), 3, 61)
+    fd = rsd.Factor(pts, None, 1e-10)
+    ff = rsd.Factor(pts, None, 1e-10, flags=rsd.RSD_FLAG_NO_DEDUP)
+    xd, _ = fd.solve(f)
+    xf, _ = ff.solve(f)
+    ref = dense.solve(pts, f)
+    assert dense.rel_error(xd, ref) < 1e-10 and dense.rel_error(xf, ref) < 1e-10
+    assert np.linalg.norm(xd - xf) <= 1e-12 * np.linalg.norm(xf)
+    bd, bf = fd.stats()["factor_bytes"], ff.stats()["factor_bytes"]
+    assert bd < 0.5 * bf
+    # a constant a other than 1, and a ragged grid whose levels hold several types
+    for p, a in ((W.grid_points(40, 24), 1.7 * np.ones(40 * 24)), (W.grid_points(37), None)):
+        g = W.rhs_normal(len(p), 1, 7)
+        fc = rsd.Factor(p, a, 1e-10)
+        x, _ = fc.solve(g)
+        assert dense.rel_error(x, dense.solve(p, g, a)) < 1e-10
+        fc.close()
+    fd.close()
+    ff.close()
+
+
+# --- tile autotuner ------------------------------------------------------------
+def test_autotuned_tiles_give_the_same_solution(tmp_path):
+    # the tuned table changes tile widths and split-K only: solutions agree
+    # with the built-in rule's to rounding; the table survives a save/load
+    grids = [W.grid_points(n) for n in (96, 80, 64)]
+    rng = np.random.default_rng(12)
+    coefs = [W.coef_bumps(p, rng) for p in grids]
+    rhs = [W.rhs_normal(len(p), 1, 3) for p in grids]
+    rsd.tune_clear()
+
+    def solve_all():
+        facs = rsd.build_batched(grids, coefs, tol=1e-10)
+        xs = [f.solve(r)[0] for f, r in zip(facs, rhs)]
+        for f in facs:
+            f.close()
+        return xs
+
+    x0 = solve_all()
+    n = rsd.autotune(grids, coefs, tol=1e-10, precision=rsd.RSD_PREC_FP64, reps=1)
+    assert n > 0
+    path = tmp_path / "tune.txt"
+    rsd.tune_save(path)
+    assert rsd.tune_clear() == n
+    rsd.tune_load(path)
+    x1 = solve_all()
+    for a, b, p, c, r in zip(x0, x1, grids, coefs, rhs):
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+    assert dense.rel_error(x1[2], dense.solve(grids[2], rhs[2], coefs[2])) < 1e-10
+    rsd.tune_clear()

@@ -377,3 +377,15 @@ def test_factor_bytes_estimate_counts_every_block(nx, ny):
     assert e32 >= 4 * (blocks - root) + 8 * root and e32 < e64
     with pytest.raises(rsd.RsdError):
         rsd.estimate_factor_bytes(0, 4, 1e-10)
+
+
+@pytest.mark.parametrize("h,k", [(1 / 64, 20.0), (1 / 128, 20.0), (1 / 512, 20.0), (1 / 32, 60.0)])
+def test_self_cell_integral_matches_the_reference(h, k):
+    # the library's host quadrature of the Helmholtz cell integral against the
+    # CPU reference's (itself pinned against adaptive quadrature); Laplace
+    # against the closed form
+    from oracle import nystrom
+    got = rsd.self_cell_integral(h, rsd.RSD_KERNEL_HELMHOLTZ, k)
+    ref = nystrom.self_cell_helmholtz(h, k, nq=60)
+    assert abs(got - ref) <= 1e-13 * abs(ref)
+    assert rsd.self_cell_integral(h) == pytest.approx(nystrom.self_cell_laplace(h), rel=1e-14)
