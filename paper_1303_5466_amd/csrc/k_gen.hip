@@ -70,7 +70,7 @@ __device__ inline double cplx_entry(const KernelDesc& kd, int du, int dv, int64_
 
 // Leaf block D_i of one box: kernel entries off the diagonal, the
 // identity coefficient plus the self-cell integral on it.
-template <typename T>
+template <typename T, bool CPLX>
 __device__ inline void leaf_F_box(T* __restrict__ F, const BoxDev* __restrict__ boxes, int box,
                                   const LayoutDev* __restrict__ layouts, const int* __restrict__ lu,
                                   const int* __restrict__ lv, const KernelDesc& kd) {
@@ -82,7 +82,7 @@ __device__ inline void leaf_F_box(T* __restrict__ F, const BoxDev* __restrict__ 
     const int* V = lv + L.off_uv;
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)m * m; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % m), j = (int)(e / m);
-        if (kd.cplx) {
+        if constexpr (CPLX) {
             const int64_t g = (int64_t)(b.x0 + U[i]) * kd.ny + (b.y0 + V[i]);
             Fb[e] = T(cplx_entry(kd, U[i] - U[j], V[i] - V[j], g, dof_plane(i, L.k, L.r),
                                  dof_plane(j, L.k, L.r), kd.h * kd.h));
@@ -104,13 +104,13 @@ __device__ inline void leaf_F_box(T* __restrict__ F, const BoxDev* __restrict__ 
     }
 }
 
-template <typename T>
+template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) leaf_F_kernel(T* __restrict__ F, const BoxDev* __restrict__ boxes,
                                                       const int* __restrict__ box_ids,
                                                       const LayoutDev* __restrict__ layouts,
                                                       const int* __restrict__ lu,
                                                       const int* __restrict__ lv, KernelDesc kd) {
-    leaf_F_box<T>(F, boxes, box_ids[blockIdx.y], layouts, lu, lv, kd);
+    leaf_F_box<T, CPLX>(F, boxes, box_ids[blockIdx.y], layouts, lu, lv, kd);
 }
 
 // the boxes of several factors (a batch group): item y = (factor, box)
@@ -119,13 +119,13 @@ __global__ void __launch_bounds__(256) leaf_F_group_kernel(const AsmInst* __rest
                                                             const GroupItem* __restrict__ items) {
     const GroupItem it = items[blockIdx.y];
     const AsmInst& I = insts[it.inst];
-    leaf_F_box<T>(static_cast<T*>(I.F), I.boxes, it.box, I.layouts, I.lu, I.lv, I.kd);
+    leaf_F_box<T, false>(static_cast<T*>(I.F), I.boxes, it.box, I.layouts, I.lu, I.lv, I.kd);
 }
 
 // Parent block of one box: the children's E blocks where both points come
 // from one child, generated kernel entries where they come from different
 // children.
-template <typename TS, typename TD>
+template <typename TS, typename TD, bool CPLX>
 __device__ inline void assemble_box(TD* __restrict__ F, const TS* __restrict__ Fc,
                                     const BoxDev* __restrict__ boxes, int box,
                                     const LayoutDev* __restrict__ layouts, const int* __restrict__ lu,
@@ -149,7 +149,7 @@ __device__ inline void assemble_box(TD* __restrict__ F, const TS* __restrict__ F
             const BoxDev& c = ci ? c1 : c0;
             const int mc = ci ? m1 : m0;
             val = (TD)Fc[c.offF + SI[i] + (int64_t)SI[j] * mc];
-        } else if (kd.cplx) {
+        } else if constexpr (CPLX) {
             val = TD(cplx_entry(kd, U[i] - U[j], V[i] - V[j], 0, dof_plane(i, L.k, L.r),
                                 dof_plane(j, L.k, L.r), kd.h * kd.h));
         } else {
@@ -164,13 +164,13 @@ __device__ inline void assemble_box(TD* __restrict__ F, const TS* __restrict__ F
     }
 }
 
-template <typename TS, typename TD>
+template <typename TS, typename TD, bool CPLX>
 __global__ void __launch_bounds__(256) assemble_kernel(
     TD* __restrict__ F, const TS* __restrict__ Fc, const BoxDev* __restrict__ boxes,
     const int* __restrict__ box_ids, const LayoutDev* __restrict__ layouts,
     const int* __restrict__ lu, const int* __restrict__ lv, const int* __restrict__ src_c,
     const int* __restrict__ src_i, KernelDesc kd) {
-    assemble_box<TS, TD>(F, Fc, boxes, box_ids[blockIdx.y], layouts, lu, lv, src_c, src_i, kd);
+    assemble_box<TS, TD, CPLX>(F, Fc, boxes, box_ids[blockIdx.y], layouts, lu, lv, src_c, src_i, kd);
 }
 
 template <typename TS, typename TD>
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) assemble_group_kernel(const AsmInst* __re
                                                               const GroupItem* __restrict__ items) {
     const GroupItem it = items[blockIdx.y];
     const AsmInst& I = insts[it.inst];
-    assemble_box<TS, TD>(static_cast<TD*>(I.F), static_cast<const TS*>(I.Fc), I.boxes, it.box, I.layouts,
+    assemble_box<TS, TD, false>(static_cast<TD*>(I.F), static_cast<const TS*>(I.Fc), I.boxes, it.box, I.layouts,
                          I.lu, I.lv, I.src_c, I.src_i, I.kd);
 }
 
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) assemble_group_kernel(const AsmInst* __re
 // an entry is the sector's block of the kernel in the symmetry-adapted
 // basis: sum over the reflections g of the group (bit 0: u, bit 1: v) of
 // (-1)^(a gx + b gy) K(z - g x), evaluated in float64.
-template <typename T>
+template <typename T, bool CPLX>
 __global__ void __launch_bounds__(256) proxy_kernel(
     T* __restrict__ A, const int64_t* __restrict__ offA, const int* __restrict__ p_of,
     const int* __restrict__ k_of, const int* __restrict__ r_of, const int* __restrict__ zoff,
@@ -205,10 +205,10 @@ __global__ void __launch_bounds__(256) proxy_kernel(
     const int* ZV = zv + zoff[pb];
     const int* XU = xu + xoff[pb];
     const int* XV = xv + xoff[pb];
-    const int pz = kd.cplx ? p / 2 : p;    // proxy points (rows: plane 0 then plane 1)
+    const int pz = CPLX ? p / 2 : p;    // proxy points (rows: plane 0 then plane 1)
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)p * n; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % p), j = (int)(e / p);
-        if (kd.cplx) {
+        if constexpr (CPLX) {
             const int zi = i % pz;
             Ab[e] = T(cplx_entry(kd, ZU[zi] - XU[j], ZV[zi] - XV[j], 0, i / pz,
                                  dof_plane(j, k_of[pb], r_of[pb]), 1.0));
@@ -317,7 +317,10 @@ void launch_leaf_F(T* F, const BoxDev* boxes, const int* box_ids, int n_boxes,
                    int max_m, hipStream_t s) {
     if (n_boxes <= 0) return;
     dim3 grid(chunks_for((int64_t)max_m * max_m), n_boxes);
-    hipLaunchKernelGGL(leaf_F_kernel<T>, grid, dim3(256), 0, s, F, boxes, box_ids, layouts, lu, lv, kd);
+    if (kd.cplx)
+        hipLaunchKernelGGL((leaf_F_kernel<T, true>), grid, dim3(256), 0, s, F, boxes, box_ids, layouts, lu, lv, kd);
+    else
+        hipLaunchKernelGGL((leaf_F_kernel<T, false>), grid, dim3(256), 0, s, F, boxes, box_ids, layouts, lu, lv, kd);
 }
 
 template <typename TS, typename TD>
@@ -327,8 +330,12 @@ void launch_assemble_F(TD* F, const TS* Fchild, const BoxDev* boxes, const int* 
                        hipStream_t s) {
     if (n_boxes <= 0) return;
     dim3 grid(chunks_for((int64_t)max_m * max_m), n_boxes);
-    hipLaunchKernelGGL((assemble_kernel<TS, TD>), grid, dim3(256), 0, s, F, Fchild, boxes, box_ids,
-                       layouts, lu, lv, src_c, src_i, kd);
+    if (kd.cplx)
+        hipLaunchKernelGGL((assemble_kernel<TS, TD, true>), grid, dim3(256), 0, s, F, Fchild, boxes, box_ids,
+                           layouts, lu, lv, src_c, src_i, kd);
+    else
+        hipLaunchKernelGGL((assemble_kernel<TS, TD, false>), grid, dim3(256), 0, s, F, Fchild, boxes, box_ids,
+                           layouts, lu, lv, src_c, src_i, kd);
 }
 
 template <typename T>
@@ -339,8 +346,12 @@ void launch_proxy_matrix(T* A, const int64_t* offA, const int* p_of, const int* 
                          hipStream_t s) {
     if (n_problems <= 0) return;
     dim3 grid(chunks_for(max_pn), n_problems);
-    hipLaunchKernelGGL(proxy_kernel<T>, grid, dim3(256), 0, s, A, offA, p_of, k_of, r_of, zoff, zu,
-                       zv, xoff, xu, xv, geo, logh_of, kd);
+    if (kd.cplx)
+        hipLaunchKernelGGL((proxy_kernel<T, true>), grid, dim3(256), 0, s, A, offA, p_of, k_of, r_of, zoff, zu,
+                           zv, xoff, xu, xv, geo, logh_of, kd);
+    else
+        hipLaunchKernelGGL((proxy_kernel<T, false>), grid, dim3(256), 0, s, A, offA, p_of, k_of, r_of, zoff, zu,
+                           zv, xoff, xu, xv, geo, logh_of, kd);
 }
 
 template <typename TS, typename TD>
