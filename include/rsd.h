@@ -260,6 +260,24 @@ typedef struct rsd_box_info {
 } rsd_box_info;
 rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* out);
 
+/* Truncation record of the interpolation T of a box's type (Sec. 2.1: the
+ * interpolative decomposition keeps the leading columns of the column-pivoted
+ * QR whose |R_jj| exceeds tol |R_11|).  n_problems is 0 when the type has no
+ * interpolation (the root), 1 when its problem was solved whole, and 2 or 4
+ * when it was split into mirror-symmetry sectors; rank[s] is the number of
+ * columns kept in problem s and scale[s] its |R_11| reference.  The sectors
+ * of one type share one reference: the largest column norm over all of
+ * them, which is the first pivot of the whole problem in the sector basis.
+ * Unused entries are zero.  Waits for the factor's stream; call it when no
+ * solve is running on the factor.  Errors: RSD_EINVAL (null argument, box
+ * out of range). */
+typedef struct rsd_interp_info {
+    int32_t n_problems;
+    int32_t rank[4];
+    double scale[4];
+} rsd_interp_info;
+rsd_status rsd_factor_interp_info(const rsd_factor* f, int32_t box, rsd_interp_info* out);
+
 /* Copy one per-box block to host memory (column-major):
  *   which = 0: T_i (k x r), the interpolation of Sec. 3.1 (R_i = [I T_i])
  *   which = 1: E_i (k x k), needs RSD_FLAG_KEEP_E

@@ -201,6 +201,7 @@ struct QRProblemDev {
     int64_t offTmp;    // column staging for the window permutation, p x 2 QR_WIN
     int64_t offW;      // split-K partials nch x QR_WIN x (QR_WIN + k + r)
     int64_t offWs;     // reduced W, QR_WIN x (QR_WIN + k + r); then W' after the trailing block
+    double* rec;       // record of the truncation: kept rank, |R_11| reference, sectors in the group
 };
 template <typename T>
 void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int max_k,

@@ -922,6 +922,7 @@ struct Factor {
     // device tables
     DevBuf d_boxes, d_layouts, d_lu, d_lv, d_srcc, d_srci, d_inv, d_perm, d_ident, d_a, d_sb,
         d_level_ids, d_err, d_table, d_spec, d_fftwork, d_flag;
+    DevBuf d_interp;                // per layout, 4 x (kept rank, |R_11| reference, sectors)
     int fft_mx = 0, fft_my = 0;     // circulant sizes of the FFT product (0: not set up)
     std::mutex use_mu;              // solves and products of one factor run one at a time
     std::vector<int> level_id_off;
@@ -958,7 +959,7 @@ struct Factor {
             scratch.clear();
             for (DevBuf* b : {&d_boxes, &d_layouts, &d_lu, &d_lv, &d_srcc, &d_srci, &d_inv, &d_perm,
                               &d_ident, &d_a, &d_sb, &d_level_ids, &d_err, &d_table, &d_spec, &d_fftwork,
-                              &d_flag, &F64, &F32, &T64, &T32, &SR, &SC, &gemm64, &gemm32, &gj64, &gj32})
+                              &d_flag, &d_interp, &F64, &F32, &T64, &T32, &SR, &SC, &gemm64, &gemm32, &gj64, &gj32})
                 b->release();
         }
         PinnedWords::get().give(h_flag);
@@ -993,10 +994,17 @@ template <> float* Tbase<float>(Factor& f) { return f.T32.as<float>(); }
 // problem's unique least-squares solution, at least as accurate as one
 // truncated at a looser tol.  With one layer the truncation is active and
 // follows tol.
+// Truncation threshold of the float64 interpolation problems.  The skeleton
+// is fixed by the layers, so truncation only zeroes rows of T; it is kept
+// where the proxy problems are (nearly) full rank: 1e-10 with two layers,
+// 1e-12 with three.  The window pivoting decides truncation per sub-panel
+// and stops earlier than greedy column pivoting once many columns fall
+// below the threshold (three layers at 1e-10: a few hundred of 1116 columns
+// kept, T entries 10^3 times too large, the solve wrong), which these
+// thresholds avoid; the truncation record of every box type
+// (rsd_factor_interp_info) exposes the kept ranks.
 static double interp_tol64(const Factor& f) {
-    // complex (Helmholtz) factors keep three layers below tol 1e-6 and their
-    // proxy problems are numerically full rank to 1e-12
-    if (f.cplx && f.layers >= 3) return std::min(f.tol, 1e-12);
+    if (f.layers >= 3) return std::min(f.tol, 1e-12);
     return f.layers >= 2 ? std::min(f.tol, 1e-10) : f.tol;
 }
 
@@ -1008,12 +1016,14 @@ static int default_layers(double tol, int kernel_type) {
     return kernel_type == RSD_KERNEL_HELMHOLTZ && tol < 1e-6 ? std::min(m + 1, 3) : m;
 }
 
-// The symmetry split is used where the proxy problems are full rank (float64
-// interpolation truncated at 1e-9 or below), so the four sector solutions are
-// the whole problem's unique least-squares solution up to rounding.  Where
-// truncation decides the rank (float32 interpolation, one layer) the whole
-// problem is solved: the window pivoting's truncation test sees only a
+// The symmetry split is used where the proxy problems are full rank or
+// nearly (float64 interpolation truncated at 1e-9 or below), so the sector
+// solutions are the whole problem's least-squares solution up to rounding.
+// Where truncation decides the rank (float32 interpolation, one layer) the
+// whole problem is solved: the window pivoting's truncation test sees only a
 // sub-panel's columns, and on the small sector problems that stops too early.
+// (Three layers at 1e-12: the largest types keep a few percent fewer columns
+// in sectors than whole, with interpolation residuals still near 1e-14.)
 static bool split_sym(const Factor& f, const IDProblem& I, int prec) {
     return I.sym && prec == 0 && interp_tol64(f) <= 1e-9;
 }
@@ -1190,6 +1200,7 @@ struct QRChain {
                 q.offT = staged ? sec0 + (int64_t)sc * q.k * q.r : F.hlayouts[I.layout].offT;
                 q.offAux = aux_el;
                 q.offIaux = iaux_el;
+                q.rec = F.d_interp.as<double>() + 12 * (int64_t)I.layout + 3 * sc;
                 q.offV = ws_el;
                 q.offTmp = q.offV + (int64_t)q.p * QR_WIN;
                 q.offW = q.offTmp + (int64_t)q.p * 2 * QR_WIN;
@@ -2195,6 +2206,8 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     if (!sbg.empty()) upload(f->d_sb, sbg, s);
     f->d_err.alloc(sizeof(int) * 4);
     RSD_HIP(hipMemsetAsync(f->d_err.p, 0, sizeof(int) * 4, s));
+    // every interpolation problem writes its record (no clearing needed)
+    f->d_interp.alloc(std::max<size_t>(P.layouts.size(), 1) * 12 * sizeof(double));
     // kernel descriptions: kd generates the factored matrix (diagonal ag,
     // no scaling), kd_res is the exact operator of the residual (contrast
     // scaling when given)
@@ -3535,6 +3548,29 @@ rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* o
         if (box < 0 || box >= (int)P.boxes.size()) throw rsd::Error(RSD_EINVAL, "box out of range");
         const auto& b = P.boxes[box];
         *out = {b.level, b.x0, b.y0, b.ax, b.ay, b.k, b.r, b.parent};
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_factor_interp_info(const rsd_factor* fc, int32_t box, rsd_interp_info* out) {
+    return guarded([&]() {
+        if (!fc || !out) throw rsd::Error(RSD_EINVAL, "null argument");
+        rsd::Factor& f = *fc->impl;
+        const auto& P = f.plan;
+        if (box < 0 || box >= (int)P.boxes.size()) throw rsd::Error(RSD_EINVAL, "box out of range");
+        const int li = P.boxes[box].layout;
+        *out = rsd_interp_info{};
+        if (li < 0 || f.hlayouts[li].offT < 0) return RSD_OK;
+        RSD_HIP(hipStreamSynchronize(f.stream));
+        double rec[12];
+        RSD_HIP(hipMemcpy(rec, f.d_interp.as<double>() + 12 * (int64_t)li, sizeof(rec), hipMemcpyDeviceToHost));
+        const int n = (int)rec[2];
+        if (n != 1 && n != 2 && n != 4) throw rsd::Error(RSD_EINVAL, "internal: no interpolation record for this box type");
+        out->n_problems = n;
+        for (int sc = 0; sc < n; ++sc) {
+            out->rank[sc] = (int32_t)rec[3 * sc];
+            out->scale[sc] = rec[3 * sc + 1];
+        }
         return RSD_OK;
     });
 }

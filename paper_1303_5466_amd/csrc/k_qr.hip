@@ -153,6 +153,10 @@ __global__ void __launch_bounds__(256) qr_r11_kernel(T* __restrict__ aux, int* _
     if (threadIdx.x == 0) {
         Aux<T> X(aux, iaux, nullptr, q);
         X.r11[0] = sqrt(red[0]);
+        if (q.rec) {
+            q.rec[1] = (double)X.r11[0];
+            q.rec[2] = (double)q.gn;
+        }
     }
 }
 
@@ -733,14 +737,15 @@ __global__ void __launch_bounds__(256) qr_trsm_kernel(T* __restrict__ A, T* __re
                                                        const int* __restrict__ plist, int step) {
     __shared__ T Rb[64][65];
     const QRProblemDev q = probs[plist[blockIdx.y]];
+    Aux<T> X(aux, iaux, nullptr, q);
+    const int rank = X.state[0] < 0 ? q.k : X.state[0];
+    if (step == 0 && blockIdx.x == 0 && threadIdx.x == 0 && q.rec) q.rec[0] = (double)rank;
     const int nblk = (q.k + 63) / 64;
     const int I = nblk - 1 - step;
     if (I < 0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = blockIdx.x * 4 + wave;
     if (blockIdx.x * 4 >= q.r) return;
-    Aux<T> X(aux, iaux, nullptr, q);
-    const int rank = X.state[0] < 0 ? q.k : X.state[0];
     const int i0 = I * 64, nb = min(64, q.k - i0);
     const T* Ab = A + q.offA;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {

@@ -55,6 +55,10 @@ class rsd_box_info(C.Structure):
                 ("ay", C.c_int32), ("k", C.c_int32), ("r", C.c_int32), ("parent", C.c_int32)]
 
 
+class rsd_interp_info(C.Structure):
+    _fields_ = [("n_problems", C.c_int32), ("rank", C.c_int32 * 4), ("scale", C.c_double * 4)]
+
+
 class rsd_server_options(C.Structure):
     _fields_ = [("mem_budget", C.c_int64), ("max_slots", C.c_int32), ("n_workers", C.c_int32),
                 ("max_coalesce", C.c_int32), ("device", C.c_int32), ("evict_idle", C.c_int32)]
@@ -118,6 +122,7 @@ EXPORTS = {
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rsd_factor_get_stats": (C.c_int, [C.c_void_p, C.POINTER(rsd_factor_stats)]),
     "rsd_factor_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
+    "rsd_factor_interp_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_interp_info)]),
     "rsd_factor_get_block": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "rsd_plan_create": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                   C.POINTER(C.c_void_p)]),
@@ -235,6 +240,14 @@ class Factor:
         b = rsd_box_info()
         _check(load().rsd_factor_box_info(self._h, box, C.byref(b)))
         return {f: getattr(b, f) for f, _ in rsd_box_info._fields_}
+
+    def interp_info(self, box):
+        """Truncation record of the box type's interpolation: a list with one
+        (kept rank, |R_11| reference) pair per problem it was solved as (empty
+        for the root, one pair when solved whole, 2 or 4 for symmetry sectors)."""
+        b = rsd_interp_info()
+        _check(load().rsd_factor_interp_info(self._h, box, C.byref(b)))
+        return [(int(b.rank[i]), float(b.scale[i])) for i in range(b.n_problems)]
 
     def block(self, box, which):
         info = self.box_info(box)
