@@ -97,8 +97,9 @@ typedef struct rsd_options {
 #define RSD_FLAG_NO_SYMMETRY 2
 /* FP32_REFINE factors: solve the interpolation problems of the float32 levels
  * in float32 too, truncated at max(tol, 1e-6).  By default they are solved in
- * float64 (truncated at min(tol, 1e-10) with two or more skeleton layers, at
- * tol with one; symmetry split where full rank) and T is rounded to float32;
+ * float64 (truncated at min(tol, 1e-10) with two skeleton layers, min(tol,
+ * 1e-12) with three, tol with one; symmetry split where full rank) and T is
+ * rounded to float32;
  * the float32 form trades interpolation accuracy for a float32-only build and
  * usually needs more refinement steps. */
 #define RSD_FLAG_FP32_INTERP 4
@@ -106,6 +107,13 @@ typedef struct rsd_options {
  * (by default such a factor keeps one E/G/W block per box type and level,
  * shared by all its boxes: the translation-invariant case of Sec. 5.1.2). */
 #define RSD_FLAG_NO_DEDUP 8
+/* Capture the up sweep, root and down sweep of each solve width once into a
+ * HIP graph and replay it (same kernels, same results; needs a non-blocking
+ * stream, else the sweeps are launched one by one).  On MI355X at 256^2 with
+ * 16 right-hand sides the replay is no faster than the launches one by one
+ * (their own durations bound the sweeps), so it is off by default; it helps
+ * callers whose host thread is the bottleneck of launch submission. */
+#define RSD_FLAG_SOLVE_GRAPH 16
 
 typedef struct rsd_solve_info {
     int32_t refine_iters;  /* refinement steps taken                          */
@@ -249,6 +257,8 @@ typedef struct rsd_factor_stats {
     double build_ms;         /* device time of the last build                */
     int32_t complex_values;  /* 1: Helmholtz factor; right-hand sides and
                                 solutions are interleaved complex (c128)      */
+    int32_t solve_graphs;    /* solve widths whose sweeps replay a captured
+                                graph (RSD_FLAG_SOLVE_GRAPH)                  */
 } rsd_factor_stats;
 
 rsd_status rsd_factor_get_stats(const rsd_factor* f, rsd_factor_stats* out);

@@ -900,6 +900,14 @@ struct SolvePlan {
     DevBuf refine_work, refine_norms;   // refinement vectors, allocated on first use
     std::vector<SolveLevel<float>> L32;
     std::vector<SolveLevel<double>> L64;
+    hipGraphExec_t sweeps = nullptr;    // the sweeps between leaf gather and scatter, captured once
+    bool sweeps_failed = false;         // capture or instantiation refused: launched one by one
+    SolvePlan() = default;
+    SolvePlan(const SolvePlan&) = delete;
+    SolvePlan& operator=(const SolvePlan&) = delete;
+    ~SolvePlan() {
+        if (sweeps) (void)hipGraphExecDestroy(sweeps);
+    }
 };
 
 struct Factor {
@@ -2819,24 +2827,17 @@ static SolvePlan& get_solve_plan(Factor& f, int nrhs) {
 }
 
 // x (grid or caller order per `perm`) = A^{-1} f, both device buffers with ld N
-static void apply_inverse(Factor& f, SolvePlan& sp, const double* fin, double* xout,
-                          const int64_t* perm) {
-    hipStream_t s = f.stream;
+// The up sweep, the root and the down sweep of the inverse apply (Algorithm
+// 6) between the leaf gather and the leaf scatter: every launch reads and
+// writes only the solve plan's buffers and the factor's blocks.
+static void apply_sweeps(Factor& f, SolvePlan& sp, hipStream_t s) {
     const int nr = sp.nrhs;
     const BoxDev* B = f.d_boxes.as<BoxDev>();
     const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
-    const int* lu = f.d_lu.as<int>();
-    const int* lv = f.d_lv.as<int>();
     const int* inv = f.d_inv.as<int>();
     const int nlev = (int)f.plan.levels.size();
     auto nb = [&](int t) { return (int)f.plan.levels[t].size(); };
-    auto maxm = [&](int t) { int m = 0; for (int id : f.plan.levels[t]) m = std::max(m, f.hboxes[id].k + f.hboxes[id].r); return m; };
     auto maxk = [&](int t) { int m = 0; for (int id : f.plan.levels[t]) m = std::max(m, f.hboxes[id].k); return m; };
-    // leaves (complex factors: fin holds the two dof planes of each column,
-    // ld 2N, plane 1 at offset N)
-    const int64_t ldv = f.cplx ? 2 * f.N : f.N, poff = f.cplx ? f.N : 0;
-    if (f.level_prec[0]) launch_gather_leaf<double, float>(sp.V32.as<float>(), fin, ldv, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
-    else launch_gather_leaf<double, double>(sp.V64.as<double>(), fin, ldv, nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
     for (int t = 0; t < nlev; ++t) {
         const int p = f.level_prec[t];
         if (p) { sp.L32[t].up1.run(s); sp.L32[t].up2.run(s); }
@@ -2868,8 +2869,64 @@ static void apply_inverse(Factor& f, SolvePlan& sp, const double* fin, double* x
         if (p) { sp.L32[t].dn1.run(s); sp.L32[t].dn2.run(s); }
         else { sp.L64[t].dn1.run(s); sp.L64[t].dn2.run(s); }
     }
-    if (f.level_prec[0]) launch_scatter_leaf<float, double>(xout, ldv, sp.V32.as<float>(), sp.Y32.as<float>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
-    else launch_scatter_leaf<double, double>(xout, ldv, sp.V64.as<double>(), sp.Y64.as<double>(), nr, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, poff, maxm(0), s);
+}
+
+// Whether the sweeps run as a captured graph: asked for, no profiler or
+// tuner events to record, and a non-blocking stream (no implicit
+// synchronisation with other threads' default-stream work during capture).
+static bool sweeps_as_graph(const Factor& f) {
+    if (!(f.flags & RSD_FLAG_SOLVE_GRAPH) || g_prof.on || Tuner::get().recording()) return false;
+    unsigned int fl = 0;
+    if (!f.stream || hipStreamGetFlags(f.stream, &fl) != hipSuccess) return false;
+    return (fl & hipStreamNonBlocking) != 0;
+}
+
+// Captures the sweeps of a solve plan into a graph on first use (about a
+// hundred launches replayed as one); falls back to launching them one by one
+// when the runtime refuses the capture.
+static void run_sweeps(Factor& f, SolvePlan& sp, hipStream_t s) {
+    if (!sp.sweeps_failed && !sp.sweeps && sweeps_as_graph(f)) {
+        hipGraph_t g = nullptr;
+        RSD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            apply_sweeps(f, sp, s);
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        const hipError_t e = hipStreamEndCapture(s, &g);
+        hipGraphExec_t ge = nullptr;
+        if (e == hipSuccess && g && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess) sp.sweeps = ge;
+        else {
+            (void)hipGetLastError();
+            sp.sweeps_failed = true;
+        }
+        if (g) (void)hipGraphDestroy(g);
+    }
+    if (sp.sweeps && sweeps_as_graph(f)) RSD_HIP(hipGraphLaunch(sp.sweeps, s));
+    else apply_sweeps(f, sp, s);
+}
+
+static void apply_inverse(Factor& f, SolvePlan& sp, const double* fin, double* xout,
+                          const int64_t* perm) {
+    hipStream_t s = f.stream;
+    const int nr = sp.nrhs;
+    const BoxDev* B = f.d_boxes.as<BoxDev>();
+    const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
+    const int* lu = f.d_lu.as<int>();
+    const int* lv = f.d_lv.as<int>();
+    const int nb0 = (int)f.plan.levels[0].size();
+    int maxm0 = 0;
+    for (int id : f.plan.levels[0]) maxm0 = std::max(maxm0, f.hboxes[id].k + f.hboxes[id].r);
+    // leaves (complex factors: fin holds the two dof planes of each column,
+    // ld 2N, plane 1 at offset N)
+    const int64_t ldv = f.cplx ? 2 * f.N : f.N, poff = f.cplx ? f.N : 0;
+    if (f.level_prec[0]) launch_gather_leaf<double, float>(sp.V32.as<float>(), fin, ldv, nr, B, f.ids(0), nb0, LD, lu, lv, perm, f.ny, poff, maxm0, s);
+    else launch_gather_leaf<double, double>(sp.V64.as<double>(), fin, ldv, nr, B, f.ids(0), nb0, LD, lu, lv, perm, f.ny, poff, maxm0, s);
+    run_sweeps(f, sp, s);
+    if (f.level_prec[0]) launch_scatter_leaf<float, double>(xout, ldv, sp.V32.as<float>(), sp.Y32.as<float>(), nr, B, f.ids(0), nb0, LD, lu, lv, perm, f.ny, poff, maxm0, s);
+    else launch_scatter_leaf<double, double>(xout, ldv, sp.V64.as<double>(), sp.Y64.as<double>(), nr, B, f.ids(0), nb0, LD, lu, lv, perm, f.ny, poff, maxm0, s);
 }
 
 static void ensure_table(Factor& f) {
@@ -3536,7 +3593,11 @@ const char* rsd_last_error(void) { return g_last_error.c_str(); }
 rsd_status rsd_factor_get_stats(const rsd_factor* f, rsd_factor_stats* out) {
     return guarded([&]() {
         if (!f || !out) throw rsd::Error(RSD_EINVAL, "null argument");
-        *out = f->impl->stats;
+        rsd::Factor& F = *f->impl;
+        *out = F.stats;
+        std::lock_guard<std::mutex> use(F.use_mu);
+        out->solve_graphs = 0;
+        for (const auto& kv : F.solve_plans) out->solve_graphs += kv.second->sweeps ? 1 : 0;
         return RSD_OK;
     });
 }

@@ -26,6 +26,7 @@ RSD_FLAG_KEEP_E = 1
 RSD_FLAG_NO_SYMMETRY = 2
 RSD_FLAG_FP32_INTERP = 4
 RSD_FLAG_NO_DEDUP = 8
+RSD_FLAG_SOLVE_GRAPH = 16
 
 
 class rsd_kernel(C.Structure):
@@ -47,7 +48,7 @@ class rsd_factor_stats(C.Structure):
                 ("n_levels", C.c_int32), ("n_boxes", C.c_int32), ("layers", C.c_int32),
                 ("precision", C.c_int32), ("factor_bytes", C.c_int64),
                 ("factor_flops", C.c_double), ("solve_bytes", C.c_double),
-                ("build_ms", C.c_double), ("complex_values", C.c_int32)]
+                ("build_ms", C.c_double), ("complex_values", C.c_int32), ("solve_graphs", C.c_int32)]
 
 
 class rsd_box_info(C.Structure):

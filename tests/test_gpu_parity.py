@@ -672,6 +672,50 @@ def test_server_binding_checks_buffers():
     srv.close()
 
 
+# --- solve sweeps replayed as a HIP graph -------------------------------------
+@pytest.mark.parametrize("precision", [rsd.RSD_PREC_FP64, rsd.RSD_PREC_FP32_REFINE])
+def test_solve_sweeps_as_graph_match_launches_one_by_one(precision):
+    # the up sweep, root and down sweep of each solve width are captured once
+    # and replayed; every replay, with the program's own eager work and
+    # synchronisations in between (products, host and device inputs, other
+    # widths), gives the bits of a factor that launches them one by one
+    pts = W.grid_points(96, 80)
+    a = W.coef_sine(pts)
+    fg = rsd.Factor(pts, a, 1e-10, precision=precision, flags=rsd.RSD_FLAG_SOLVE_GRAPH)
+    fe = rsd.Factor(pts, a, 1e-10, precision=precision)
+    for rep in range(5):
+        nrhs = 3 if rep % 2 == 0 else 1
+        f = W.rhs_normal(len(pts), nrhs, 60 + rep)
+        if rep == 3:
+            xg, ig = fg.solve(_dev(f))
+            xg = xg.cpu().numpy()
+        else:
+            xg, ig = fg.solve(f)
+        xe, ie = fe.solve(f)
+        assert np.array_equal(xg, xe), rep
+        assert ig.refine_iters == ie.refine_iters
+        y = fg.matvec(xg)
+        assert np.linalg.norm(y - f) <= 1e-9 * np.linalg.norm(f), rep
+    assert fg.stats()["solve_graphs"] == 2 and fe.stats()["solve_graphs"] == 0
+    fg.close()
+    fe.close()
+
+
+def test_complex_solve_sweeps_as_graph():
+    pts = W.grid_points(48)
+    b = 1.0 + 0.3 * np.sin(3 * pts[:, 0]) ** 2
+    kw = dict(kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=W.SCATTER_K, contrast=b)
+    fg = rsd.Factor(pts, None, 1e-10, flags=rsd.RSD_FLAG_SOLVE_GRAPH, **kw)
+    fe = rsd.Factor(pts, None, 1e-10, **kw)
+    for rep in range(3):
+        f = W.rhs_complex_normal(len(pts), 2, 70 + rep)
+        xg, _ = fg.solve(f)
+        xe, _ = fe.solve(f)
+        assert np.array_equal(xg, xe), rep
+    fg.close()
+    fe.close()
+
+
 # --- symmetry split of the interpolation problems ------------------------------------
 def test_symmetry_split_matches_whole_problems():
     pts = W.grid_points(64)
