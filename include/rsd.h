@@ -87,6 +87,12 @@ typedef struct rsd_options {
     void* hip_stream;      /* hipStream_t to run on; NULL => a library stream  */
     int32_t device;        /* HIP device ordinal; < 0 => the current device    */
     int32_t flags;         /* RSD_FLAG_* bits                                  */
+    double interface_ppw;  /* Helmholtz kernel: skeleton points per wavelength
+                              kept on the cut between the children of every
+                              box above the leaves (Sec. 5.3: needed as the
+                              wavenumber grows), spaced floor(2 pi / (k h
+                              ppw)) grid cells apart on the two grid lines
+                              beside the cut; 0 => none; ignored for Laplace */
 } rsd_options;
 
 /* Keep every box's E_i block after the build (for inspection). */
@@ -114,6 +120,15 @@ typedef struct rsd_options {
  * (their own durations bound the sweeps), so it is off by default; it helps
  * callers whose host thread is the bottleneck of launch submission. */
 #define RSD_FLAG_SOLVE_GRAPH 16
+/* Solve the interpolation problems with truncation only.  By default, where
+ * truncation would decide the rank (three skeleton layers in float64, and
+ * float32 interpolation), they are solved as damped least squares instead,
+ * min |K(Z, X^sk) T - K(Z, X^rs)|^2 + (tol |R_11|)^2 |T|^2 (tol: max(tol,
+ * 1e-6) in float32), by the same QR on k more rows: the window pivoting
+ * decides truncation per sub-panel and stops earlier than column pivoting
+ * over all columns, the damped problem has no pivot below tol |R_11| and
+ * bounds T.  For comparison and testing. */
+#define RSD_FLAG_NO_DAMPING 32
 
 typedef struct rsd_solve_info {
     int32_t refine_iters;  /* refinement steps taken                          */
@@ -457,9 +472,13 @@ rsd_status rsd_gemm(int32_t dtype, int32_t M, int32_t N, int32_t K, int32_t tA, 
                     double beta, void* C, int32_t ldc);
 
 /* In-place inverse of an n x n matrix by the library's blocked Gauss-Jordan
- * elimination in natural order (no pivoting: for symmetric positive definite
- * or diagonally dominant matrices, the blocks the solver inverts).
- * Returns ESINGULAR when a pivot block is singular. */
+ * elimination in natural order (no row exchanges: for symmetric positive
+ * definite or diagonally dominant matrices, the blocks the solver inverts).
+ * dtype bit 0: float32 (else float64); bit 1: paired pivots, the form used
+ * for complex factors (n even; rows and columns 2i, 2i + 1 hold the real
+ * form [[re, im], [im, -re]] of a complex entry, and each step eliminates
+ * such a pair with its 2 x 2 inverse).  Returns ESINGULAR when a pivot
+ * (pair) is singular. */
 rsd_status rsd_gj_invert(int32_t dtype, int32_t n, void* A, int32_t lda);
 
 /* ---- host-only planning (no device needed) ------------------------------ */
@@ -475,15 +494,18 @@ rsd_status rsd_self_cell_integral(int32_t kernel_type, double h, double k, doubl
  * blocks, four times the entries for the complex Helmholtz kernel): equal to
  * rsd_factor_stats.factor_bytes of a factor built with every box's blocks
  * (a varying a, or RSD_FLAG_NO_DEDUP), an upper bound for one that shares
- * them (constant a).  Host only. */
+ * them (constant a).  Interface skeleton points (interface_ppw) are placed
+ * for the grid spacing 1 / max(nx, ny) of the unit square.  Host only. */
 rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, const rsd_kernel* kernel, double tol,
                                      const rsd_options* opt, int64_t* bytes);
 /* Number of boxes and levels the tree of Sec. 2.2 / Sec. 3.1 produces for an
  * nx x ny grid, and per-box sizes.  Pure host computation, usable without a
- * GPU; boxes are numbered level by level from the leaves. */
+ * GPU; boxes are numbered level by level from the leaves.  interface_step:
+ * spacing in grid cells of the interface skeleton points (see
+ * rsd_options.interface_ppw), 0 for none. */
 typedef struct rsd_plan rsd_plan;
 rsd_status rsd_plan_create(int64_t nx, int64_t ny, int32_t leaf_side, int32_t layers,
-                           rsd_plan** out);
+                           int32_t interface_step, rsd_plan** out);
 int32_t rsd_plan_n_boxes(const rsd_plan* p);
 int32_t rsd_plan_n_levels(const rsd_plan* p);
 rsd_status rsd_plan_box_info(const rsd_plan* p, int32_t box, rsd_box_info* out);

@@ -118,10 +118,40 @@ def build_tree(nx: int, ny: int, leaf: int = 8) -> tuple[Box, list[list[Box]]]:
     return root, levels
 
 
-def index_sets(nx: int, ny: int, leaf: int, m: int):
+def interface_step(k: float, h: float, ppw: float) -> int:
+    """Spacing in grid cells of the interface skeleton points for ppw points
+    per wavelength 2 pi / k (Sec. 5.3, skeleton structure of the Helmholtz
+    kernel); at least one cell."""
+    return max(1, int(np.floor(2.0 * np.pi / (k * h * ppw))))
+
+
+def skeleton_mask(b: Box, i, j, m: int, step: int = 0):
+    """Which points (grid indices i, j) of box b's active set are skeleton:
+    the m layers next to its boundary (Sec. 3.1), and with step > 0 also the
+    points of the two grid lines on either side of the cut between its
+    children whose distance past the boundary layers, along the cut, is
+    step // 2 modulo step (a few points per wavelength on the interface,
+    Sec. 5.3)."""
+    d = np.minimum.reduce([i - b.x0, b.x1 - 1 - i, j - b.y0, b.y1 - 1 - j])
+    sk = d < m
+    if step > 0 and b.children:
+        c1, c2 = b.children
+        if c1.x1 == c2.x0:                       # cut across x
+            line = (i == c1.x1 - 1) | (i == c1.x1)
+            along, length = j - b.y0, b.y1 - b.y0
+        else:                                    # cut across y
+            line = (j == c1.y1 - 1) | (j == c1.y1)
+            along, length = i - b.x0, b.x1 - b.x0
+        past = np.minimum(along, length - 1 - along) - m
+        sk = sk | (line & (past >= 0) & (past % step == step // 2))
+    return sk
+
+
+def index_sets(nx: int, ny: int, leaf: int, m: int, step: int = 0):
     """Active, skeleton and residual sets of every box (Sec. 3.1), without any
     kernel arithmetic.  Points are numbered p = i * ny + j.  Returns the tree
-    levels with b.act (global ids), b.sk and b.rs (positions into b.act)."""
+    levels with b.act (global ids), b.sk and b.rs (positions into b.act);
+    step > 0 adds interface points (skeleton_mask)."""
     root, levels = build_tree(nx, ny, leaf)
     for depth in range(len(levels) - 1, -1, -1):
         for b in levels[depth]:
@@ -132,9 +162,9 @@ def index_sets(nx: int, ny: int, leaf: int, m: int):
                 c1, c2 = b.children
                 b.act = np.concatenate([c1.act[c1.sk], c2.act[c2.sk]])
             i, j = b.act // ny, b.act % ny
-            d = np.minimum.reduce([i - b.x0, b.x1 - 1 - i, j - b.y0, b.y1 - 1 - j])
-            b.sk = np.nonzero(d < m)[0]
-            b.rs = np.nonzero(d >= m)[0]
+            msk = skeleton_mask(b, i, j, m, step)
+            b.sk = np.nonzero(msk)[0]
+            b.rs = np.nonzero(~msk)[0]
     return root, levels
 
 
@@ -142,7 +172,7 @@ class RSkel:
     """Dense-block recursive-skeletonisation inverse of the Nystrom matrix."""
 
     def __init__(self, points, a=None, tol=1e-10, leaf=8, layers=None,
-                 kind="laplace", k=0.0, bvec=None):
+                 kind="laplace", k=0.0, bvec=None, ppw=0.0):
         self.points = np.asarray(points, dtype=float)
         self.N = self.points.shape[0]
         self.a = np.ones(self.N) if a is None else np.asarray(a, dtype=float)
@@ -156,6 +186,8 @@ class RSkel:
         self.gid[ix, iy] = np.arange(self.N)
         self.x0 = self.points[:, 0].min() - 0.5 * h
         self.y0 = self.points[:, 1].min() - 0.5 * h
+        # interface skeleton points per wavelength (Helmholtz only)
+        self.step = interface_step(k, h, ppw) if kind == "helmholtz" and ppw > 0 else 0
         self.root, self.levels = build_tree(nx, ny, leaf)
         self.dtype = complex if kind == "helmholtz" else float
         self.T_cache = {}
@@ -173,9 +205,7 @@ class RSkel:
 
     # -- skeletons (Sec. 3.1) ----------------------------------------------
     def _in_layers(self, b: Box, idx):
-        i, j = self.ix[idx], self.iy[idx]
-        d = np.minimum.reduce([i - b.x0, b.x1 - 1 - i, j - b.y0, b.y1 - 1 - j])
-        return d < self.m
+        return skeleton_mask(b, self.ix[idx], self.iy[idx], self.m, self.step)
 
     def _proxy(self, b: Box):
         """Z: grid nodes within m layers outside the box (may lie outside the domain)."""

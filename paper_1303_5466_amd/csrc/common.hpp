@@ -51,9 +51,13 @@ struct KernelDesc {
 };
 
 // Plane (0 or 1) of position q of a complex factor's dof block with k
-// skeleton and r residual dofs ([sk plane 0; sk plane 1; rs plane 0; rs plane 1]).
+// skeleton and r residual dofs: every point's two dofs are adjacent (plane 0,
+// then plane 1), skeleton points first, so the elimination in natural order
+// pivots on whole complex entries (a 2 x 2 block [[re, im], [im, -re]] of
+// determinant -|z|^2) rather than on real parts alone.
 __host__ __device__ inline int dof_plane(int q, int k, int r) {
-    return q < k ? (q >= k / 2 ? 1 : 0) : (q - k >= r / 2 ? 1 : 0);
+    (void)k; (void)r;
+    return q & 1;
 }
 // (pi, pj) component of J(re + i im)
 __host__ __device__ inline double jform(double re, double im, int pi, int pj) {
@@ -189,6 +193,7 @@ constexpr int QR_WIN = 64;    // pivoting window / block width of the trailing u
 constexpr int QR_RC = 256;    // row chunk of the split-K reflector products
 struct QRProblemDev {
     int p, k, r, nb;   // nb: sub-panel width (16, 8, 4 or 2 by the LDS budget)
+    int pz;            // rows holding the proxy kernel; rows pz .. p - 1 the damping rows (k or none)
     int sec;           // -1, or the symmetry sector (0..3) this problem solves
     int staged;        // 0: T goes to the T arena; 1: to the staging arena (sector, or another precision)
     int g0, gn;        // sector group: list index of its first problem and number of sectors
@@ -202,9 +207,15 @@ struct QRProblemDev {
     int64_t offW;      // split-K partials nch x QR_WIN x (QR_WIN + k + r)
     int64_t offWs;     // reduced W, QR_WIN x (QR_WIN + k + r); then W' after the trailing block
     double* rec;       // record of the truncation: kept rank, |R_11| reference, sectors in the group
+    double ttol;       // truncation threshold |R_jj| <= ttol |R_11|
+    double damp;       // > 0: rows pz + j hold damp |R_11| in column j (damped least squares)
 };
 template <typename T>
 void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int max_k,
+                    hipStream_t s);
+// the damping rows of the problems with damp > 0 (after launch_qr_init)
+template <typename T>
+void launch_qr_damp(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int max_k,
                     hipStream_t s);
 template <typename T>
 void launch_qr_select(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_probs,
@@ -212,11 +223,11 @@ void launch_qr_select(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs,
 template <typename T>
 void launch_qr_move(T* A, int* iaux, T* ws, const QRProblemDev* probs, int n_probs, int phase,
                     hipStream_t s);
-// plist: problem ids of one sub-panel width class
+// plist: problem ids of one sub-panel width class; the truncation threshold
+// is each problem's ttol
 template <typename T>
 void launch_qr_panel(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, const int* plist,
-                     int n_list, int nb_class, int max_p, int outer, int sub, double tol,
-                     hipStream_t s);
+                     int n_list, int nb_class, int max_p, int outer, int sub, hipStream_t s);
 template <typename T>
 void launch_qr_inner(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, const int* plist,
                      int n_list, int nb_class, int outer, int sub, hipStream_t s);
@@ -246,7 +257,7 @@ struct GJDesc {
 };
 template <typename T>
 void launch_gj_pivot(const GJDesc<T>* d, int n_desc, int step, int nb, int max_chunks,
-                     int* err, hipStream_t s);
+                     int* err, int pair, hipStream_t s);
 
 // solve-phase gathers and scatters
 template <typename TS, typename TD>

@@ -1054,6 +1054,7 @@ static void append_sector_problems(std::vector<QRProblemDev>& qp, const IDProble
     for (int sc = 0; sc < nsec; ++sc) {
         QRProblemDev q{};
         q.p = I.p / nsec;
+        q.pz = q.p;
         q.k = I.k / nsec;
         q.r = I.r / nsec;
         q.sec = sym ? (I.grp == 2 ? 2 * sc : sc) : -1;
@@ -1143,7 +1144,7 @@ struct QRChain {
     std::vector<int> lists[4];
     int off[4] = {0, 0, 0, 0}, maxp[4] = {0, 0, 0, 0};
     std::vector<int> sflat, soff;
-    double qr_tol = 0;
+    bool any_damp = false;
     double flops = 0, bytes = 0;
 
     DevBuf& tmp() {
@@ -1197,9 +1198,24 @@ struct QRChain {
             // are appended with their group; offsets follow
             const size_t base = qp.size();
             append_sector_problems(qp, I, sym);
+            // truncation, or damped least squares where truncation would be
+            // active (three layers in float64, float32 interpolation): the
+            // window pivoting tests truncation per sub-panel and stops too
+            // early there, the damped problem needs no truncation
+            const bool f32 = !std::is_same<T, double>::value;
+            const double plain_tol = f32 ? std::max(F.tol, 1e-6) : interp_tol64(F);
+            const double damp_rel = f32 ? std::max(F.tol, 1e-6) : F.tol;
+            const bool want_damp = (f32 || F.layers >= 3) && !(F.flags & RSD_FLAG_NO_DAMPING);
             for (int sc = 0; sc < nsec; ++sc) {
                 QRProblemDev& q = qp[base + sc];
                 q.staged = staged ? 1 : 0;
+                q.ttol = plain_tol;
+                if (want_damp && qr_panel_width(q.pz + q.k, (int)sizeof(T)) > 0) {
+                    q.p = q.pz + q.k;
+                    q.damp = damp_rel;
+                    q.ttol = 1e-3 * damp_rel;    // a guard only: no pivot falls below damp |R_11|
+                    any_damp = true;
+                }
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));
                 if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
                 const int n = q.k + q.r;
@@ -1238,6 +1254,7 @@ struct QRChain {
                     xv.insert(xv.end(), L.v.begin(), L.v.end());
                 }
                 geo.push_back(L.ax); geo.push_back(L.ay); geo.push_back(q.sec); geo.push_back(sym ? I.grp : 0);
+                geo.push_back(q.pz);
                 max_pn = std::max(max_pn, q.p * n);
                 max_k = std::max(max_k, q.k);
                 max_r = std::max(max_r, q.r);
@@ -1424,14 +1441,13 @@ struct QRChain {
         comb_dev = static_cast<const SymCombineDesc*>(at(o_comb));
         orb_dev = static_cast<const int*>(at(o_orb));
         refl_dev = static_cast<const int*>(at(o_refl));
-        // a float32 factor cannot resolve pivots below its rounding level
-        qr_tol = std::is_same<T, float>::value ? std::max(f->tol, 1e-6) : interp_tol64(*f);
         auto ints = [&](size_t o) { return static_cast<const int*>(at(o)); };
         launch_proxy_matrix<T>(Ab, static_cast<const int64_t*>(at(o_offA)), ints(o_p), ints(o_k), ints(o_r),
                                ints(o_zo), ints(o_zu), ints(o_zv), ints(o_xo), ints(o_xu), ints(o_xv),
                                ints(o_geo), several ? static_cast<const double*>(at(o_logh)) : nullptr, np,
                                max_pn, f->kd, s);
         launch_qr_init<T>(Ab, daux->as<T>(), diaux->as<int>(), q_dev, np, max_k, s);
+        if (any_damp) launch_qr_damp<T>(Ab, daux->as<T>(), diaux->as<int>(), q_dev, np, max_k, s);
     }
 
     // Enqueues window sw.  For the problems that finish in it, the back
@@ -1453,7 +1469,7 @@ struct QRChain {
             for (int c = 0; c < 4; ++c) {
                 if (lists[c].empty() || sub * widths[c] >= QR_WIN) continue;
                 launch_qr_panel<T>(Ab, aux, iaux, W, q, list_dev + off[c], (int)lists[c].size(),
-                                   widths[c], maxp[c], sw, sub, qr_tol, s);
+                                   widths[c], maxp[c], sw, sub, s);
                 launch_qr_inner<T>(Ab, aux, iaux, W, q, list_dev + off[c], (int)lists[c].size(),
                                    widths[c], sw, sub, s);
             }
@@ -1671,7 +1687,7 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s, bool assemble =
     for (int st = 0; st < L.gj_steps; ++st) {
         {
             ProfScope ps(RSD_PROF_GJ_PIVOT, s);
-            launch_gj_pivot<T>(L.d_gj, (int)L.gj.size(), st, GJ_NB, L.max_chunks, f.d_err.as<int>(), s);
+            launch_gj_pivot<T>(L.d_gj, (int)L.gj.size(), st, GJ_NB, L.max_chunks, f.d_err.as<int>(), f.cplx, s);
         }
         L.g_gj[st].run(s);
     }
@@ -1679,7 +1695,7 @@ static void run_level(Factor& f, LevelExec<T>& L, hipStream_t s, bool assemble =
     for (int st = 0; st < L.topgj_steps; ++st) {
         {
             ProfScope ps(RSD_PROF_GJ_PIVOT, s);
-            launch_gj_pivot<T>(L.d_topgj, 1, st, GJ_NB, L.top_chunks, f.d_err.as<int>(), s);
+            launch_gj_pivot<T>(L.d_topgj, 1, st, GJ_NB, L.top_chunks, f.d_err.as<int>(), f.cplx, s);
         }
         L.g_topgj[st].run(s);
     }
@@ -1767,6 +1783,7 @@ struct GroupLevel {
     void run(hipStream_t s) {
         if (members.empty()) return;
         int* err0 = members.front().first->d_err.template as<int>();
+        const int cplx = members.front().first->cplx;   // groups hold one kind of factor
         {
             ProfScope ps(RSD_PROF_ASSEMBLY, s);
             if (level == 0) {
@@ -1791,7 +1808,7 @@ struct GroupLevel {
         for (int st = 0; st < gj_steps; ++st) {
             {
                 ProfScope ps(RSD_PROF_GJ_PIVOT, s);
-                launch_gj_pivot<T>(d_gj, (int)gj.size(), st, GJ_NB, max_chunks, err0, s);
+                launch_gj_pivot<T>(d_gj, (int)gj.size(), st, GJ_NB, max_chunks, err0, cplx, s);
             }
             g_gj[st].run(s);
         }
@@ -1799,7 +1816,7 @@ struct GroupLevel {
         for (int st = 0; st < topgj_steps; ++st) {
             {
                 ProfScope ps(RSD_PROF_GJ_PIVOT, s);
-                launch_gj_pivot<T>(d_topgj, (int)topgj.size(), st, GJ_NB, top_chunks, err0, s);
+                launch_gj_pivot<T>(d_topgj, (int)topgj.size(), st, GJ_NB, top_chunks, err0, cplx, s);
             }
             g_topgj[st].run(s);
         }
@@ -1844,13 +1861,23 @@ static void upload_group_gj(DevBuf& buf, std::vector<GroupLevel<T>>& G, hipStrea
 // ----------------------------------------------------------------------------
 // build
 // ----------------------------------------------------------------------------
-// The plan depends on the grid's shape, the leaf side and the layer count
-// only; the last few plans are kept (building one is most of a build's host
+// Spacing in grid cells of the interface skeleton points of a Helmholtz
+// factor with ppw points per wavelength 2 pi / k (Sec. 5.3), at least one
+// cell; 0 (none) for Laplace or ppw = 0.
+static int interface_step(int ktype, double k, double h, double ppw) {
+    if (!(ppw >= 0) || !std::isfinite(ppw)) throw Error(RSD_EINVAL, "interface_ppw must be finite and >= 0");
+    if (ktype != RSD_KERNEL_HELMHOLTZ || ppw == 0) return 0;
+    const double cells = std::floor(2.0 * M_PI / (k * h * ppw));
+    return cells < 1 ? 1 : (cells > 1e6 ? 1000000 : (int)cells);
+}
+
+// The plan depends on the grid's shape, the leaf side, the layer count and
+// the interface spacing only; the last few plans are kept (building one is most of a build's host
 // planning, ~0.9 ms at 256x256, copying it a fraction of that).
-static Plan cached_plan(int64_t nx, int64_t ny, int leaf, int m) {
+static Plan cached_plan(int64_t nx, int64_t ny, int leaf, int m, int iface) {
     struct Entry {
         int64_t nx, ny;
-        int leaf, m;
+        int leaf, m, iface;
         std::shared_ptr<const Plan> plan;
     };
     static std::mutex mu;
@@ -1860,7 +1887,7 @@ static Plan cached_plan(int64_t nx, int64_t ny, int leaf, int m) {
         std::lock_guard<std::mutex> lk(mu);
         for (size_t i = 0; i < cache.size(); ++i) {
             const Entry& e = cache[i];
-            if (e.nx == nx && e.ny == ny && e.leaf == leaf && e.m == m) {
+            if (e.nx == nx && e.ny == ny && e.leaf == leaf && e.m == m && e.iface == iface) {
                 Entry hit = e;
                 cache.erase(cache.begin() + i);
                 cache.push_back(hit);
@@ -1868,16 +1895,17 @@ static Plan cached_plan(int64_t nx, int64_t ny, int leaf, int m) {
             }
         }
     }
-    auto plan = std::make_shared<const Plan>(make_plan(nx, ny, leaf, m));
+    auto plan = std::make_shared<const Plan>(make_plan(nx, ny, leaf, m, iface));
     std::lock_guard<std::mutex> lk(mu);
-    cache.push_back({nx, ny, leaf, m, plan});
+    cache.push_back({nx, ny, leaf, m, iface, plan});
     if (cache.size() > KEEP) cache.erase(cache.begin());
     return *plan;
 }
 
-// Plan of a complex factor: every box type's dof block lists its points
-// twice, [sk plane 0; sk plane 1; rs plane 0; rs plane 1] (the real
-// symmetric J form of the complex symmetric matrix, see KernelDesc), so k, r
+// Plan of a complex factor: every box type's dof block lists each point
+// twice, its plane-0 and plane-1 dofs adjacent, skeleton points first (the
+// real symmetric J form of the complex symmetric matrix, see KernelDesc; the
+// pairing makes the pivot-free elimination pivot on complex entries), so k, r
 // and the interpolation problems double (rows: proxy points of plane 0 then
 // plane 1) and the children-to-parent maps point at the child's dof of the
 // same plane.  The interpolation problems are solved whole (no symmetry
@@ -1893,15 +1921,14 @@ static Plan expand_planes(const Plan& P) {
             u.push_back(O.u[q]);
             v.push_back(O.v[q]);
             if (!O.src_c.empty()) {
-                const int c = O.src_c[q];
-                sc.push_back(c);
-                si.push_back(O.src_i[q] + plane * P.layouts[O.child[c]].k);
+                sc.push_back(O.src_c[q]);
+                si.push_back(2 * O.src_i[q] + plane);   // the child's skeleton dofs are paired too
             }
         };
-        for (int plane = 0; plane < 2; ++plane)
-            for (int q = 0; q < k; ++q) put(q, plane);
-        for (int plane = 0; plane < 2; ++plane)
-            for (int q = k; q < k + r; ++q) put(q, plane);
+        for (int q = 0; q < k + r; ++q) {
+            put(q, 0);
+            put(q, 1);
+        }
         L.u = std::move(u);
         L.v = std::move(v);
         L.src_c = std::move(sc);
@@ -2069,7 +2096,7 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     if (!detect_grid(pts, n, nx, ny, h, x0, y0, perm, why)) throw Error(RSD_ENOTGRID, why);
     f->N = n; f->nx = nx; f->ny = ny; f->h = h;
     try {
-        f->plan = cached_plan(nx, ny, leaf, m);
+        f->plan = cached_plan(nx, ny, leaf, m, interface_step(ktype, wavenumber, h, o.interface_ppw));
     } catch (const std::exception& e) {
         throw Error(RSD_EINVAL, e.what());
     }
@@ -3187,8 +3214,9 @@ static void dense_gemm(int M, int N, int K, int tA, int tB, double alpha, const 
 }
 
 template <typename T>
-static void dense_gj(int n, void* A, int lda) {
+static void dense_gj(int n, void* A, int lda, int pair) {
     if (n < 0 || lda < std::max(1, n)) throw Error(RSD_EINVAL, "bad size");
+    if (pair && (n & 1)) throw Error(RSD_EINVAL, "paired pivots need an even n");
     if (n == 0) return;
     hipStream_t s = nullptr;
     DevBuf dA, sr, sc, err, dd, dg;
@@ -3216,7 +3244,7 @@ static void dense_gj(int n, void* A, int lda) {
     }
     upload_batches<T>(dd, all, s);
     for (int st = 0; st < steps; ++st) {
-        launch_gj_pivot<T>(dg.as<GJDesc<T>>(), 1, st, GJ_NB, (n + 63) / 64, err.as<int>(), s);
+        launch_gj_pivot<T>(dg.as<GJDesc<T>>(), 1, st, GJ_NB, (n + 63) / 64, err.as<int>(), pair, s);
         bs[st].run(s);
     }
     RSD_HIP(hipStreamSynchronize(s));
@@ -3581,9 +3609,10 @@ rsd_status rsd_gemm(int32_t dtype, int32_t M, int32_t N, int32_t K, int32_t tA, 
 rsd_status rsd_gj_invert(int32_t dtype, int32_t n, void* A, int32_t lda) {
     return guarded([&]() {
         if (!A) throw rsd::Error(RSD_EINVAL, "null matrix");
-        if (dtype == 0) rsd::dense_gj<double>(n, A, lda);
-        else if (dtype == 1) rsd::dense_gj<float>(n, A, lda);
-        else throw rsd::Error(RSD_EINVAL, "dtype must be 0 or 1");
+        if (dtype & ~3) throw rsd::Error(RSD_EINVAL, "dtype must be 0..3");
+        const int pair = (dtype & 2) ? 1 : 0;
+        if (dtype & 1) rsd::dense_gj<float>(n, A, lda, pair);
+        else rsd::dense_gj<double>(n, A, lda, pair);
         return RSD_OK;
     });
 }
@@ -3679,12 +3708,14 @@ rsd_status rsd_factor_get_block(const rsd_factor* fc, int32_t box, int32_t which
     });
 }
 
-rsd_status rsd_plan_create(int64_t nx, int64_t ny, int32_t leaf_side, int32_t layers, rsd_plan** out) {
+rsd_status rsd_plan_create(int64_t nx, int64_t ny, int32_t leaf_side, int32_t layers,
+                           int32_t interface_step, rsd_plan** out) {
     if (out) *out = nullptr;
     return guarded([&]() {
         if (!out) throw rsd::Error(RSD_EINVAL, "out is null");
+        if (interface_step < 0) throw rsd::Error(RSD_EINVAL, "interface_step must be >= 0");
         auto p = std::make_unique<rsd_plan>();
-        p->plan = rsd::make_plan(nx, ny, leaf_side > 0 ? leaf_side : 8, layers > 0 ? layers : 2);
+        p->plan = rsd::make_plan(nx, ny, leaf_side > 0 ? leaf_side : 8, layers > 0 ? layers : 2, interface_step);
         *out = p.release();
         return RSD_OK;
     });
@@ -3705,7 +3736,11 @@ rsd_status rsd_estimate_factor_bytes(int64_t nx, int64_t ny, const rsd_kernel* k
         const int m = o.layers > 0 ? o.layers : rsd::default_layers(tol, kernel ? kernel->type : RSD_KERNEL_LAPLACE);
         rsd::Plan P;
         try {
-            P = rsd::cached_plan(nx, ny, leaf, m);
+            // the interface spacing takes the unit-square spacing h = 1 / max(nx, ny)
+            P = rsd::cached_plan(nx, ny, leaf, m,
+                                 rsd::interface_step(kernel ? kernel->type : RSD_KERNEL_LAPLACE,
+                                                     kernel ? kernel->wavenumber : 0.0,
+                                                     1.0 / (double)std::max(nx, ny), o.interface_ppw));
         } catch (const std::exception& e) {
             throw rsd::Error(RSD_EINVAL, e.what());
         }

@@ -199,15 +199,20 @@ __global__ void __launch_bounds__(256) proxy_kernel(
     KernelDesc kd = kdc;
     if (logh_of) kd.logh = logh_of[pb];   // problems of grids with different spacings
     const int p = p_of[pb], n = k_of[pb] + r_of[pb];
-    const int ax = geo[4 * pb], ay = geo[4 * pb + 1], sec = geo[4 * pb + 2], grp = geo[4 * pb + 3];
+    const int ax = geo[5 * pb], ay = geo[5 * pb + 1], sec = geo[5 * pb + 2], grp = geo[5 * pb + 3];
+    const int prow = geo[5 * pb + 4];   // kernel rows; the rows below them (damping) start at zero
     T* Ab = A + offA[pb];
     const int* ZU = zu + zoff[pb];
     const int* ZV = zv + zoff[pb];
     const int* XU = xu + xoff[pb];
     const int* XV = xv + xoff[pb];
-    const int pz = CPLX ? p / 2 : p;    // proxy points (rows: plane 0 then plane 1)
+    const int pz = CPLX ? prow / 2 : prow;    // proxy points (rows: plane 0 then plane 1)
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)p * n; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % p), j = (int)(e / p);
+        if (i >= prow) {
+            Ab[e] = T(0);
+            continue;
+        }
         if constexpr (CPLX) {
             const int zi = i % pz;
             Ab[e] = T(cplx_entry(kd, ZU[zi] - XU[j], ZV[zi] - XV[j], 0, i / pz,

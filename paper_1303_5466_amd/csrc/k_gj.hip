@@ -77,7 +77,14 @@ __device__ inline float recip(float x) {
 // column c, which their owners publish in a double-buffered LDS strip, so each
 // elimination step costs one barrier.  The step is straight-line code: every
 // element computes the generic update and selects the pivot-row/column forms.
-template <typename T>
+//
+// PAIR (complex factors, whose dofs come in adjacent pairs forming the 2 x 2
+// real form [[re, im], [im, -re]] of a complex entry): the steps eliminate
+// two pivots at a time with the inverse of their 2 x 2 block, so that the
+// pivot is the complex entry (determinant -|z|^2) and never its real part
+// alone, which vanishes where the Schur complements turn (interpolation
+// matrices of boxes about a wavelength across).
+template <typename T, bool PAIR>
 __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restrict__ descs, int step,
                                                         int nb, int* __restrict__ err) {
     const GJDesc<T> d = descs[blockIdx.y];
@@ -90,8 +97,9 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
     const int ri = 4 * (t >> 4), cj = 4 * (t & 15);
     __shared__ T Pi[GJ_NB][GJ_NB + 1];
     __shared__ T Xp[GJ_NB][CHUNK + 1];
-    __shared__ __align__(16) T rowb[2][GJ_NB];
-    __shared__ __align__(16) T colb[2][GJ_NB];
+    // published pivot rows / columns, double buffered (PAIR: two of each)
+    __shared__ __align__(16) T rowb[2][PAIR ? 2 : 1][GJ_NB];
+    __shared__ __align__(16) T colb[2][PAIR ? 2 : 1][GJ_NB];
     __shared__ int bad;
     const int pc0 = d.pcol + j0;
     // every load of the pivot block and of the chunk's pivot rows is issued
@@ -129,57 +137,123 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         Xp[e & (GJ_NB - 1)][e / GJ_NB] = xv[u];
     }
     if (t == 0) bad = 0;
-    // publish row 0 and column 0
-    if (ri == 0)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) rowb[0][cj + b] = p[0][b];
-    if (cj == 0)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) colb[0][ri + a] = p[a][0];
-    __syncthreads();
     // Steps up to nbe rounded up to four run (past nbe the block is the
     // identity, which they leave unchanged); unrolled by four so that the
     // pivot's position inside a thread's 4 x 4 tile is a compile-time index
     // and only the ownership test is dynamic.
     const int nst = (nbe + 3) & ~3;
-    for (int c4 = 0; c4 < nst; c4 += 4) {
-        const bool own_r = ri == c4, own_c = cj == c4;
+    if constexpr (!PAIR) {
+        // publish row 0 and column 0
+        if (ri == 0)
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            const int c = c4 + l;
-            const int buf = c & 1;
-            const T piv = rowb[buf][c];
-            if (t == 0 && !(fabs((double)piv) > 1e-300 && isfinite((double)piv))) bad = 1;
-            const T inv = recip(piv);
-            T prs[4], pcv[4];
+            for (int b = 0; b < 4; ++b) rowb[0][0][cj + b] = p[0][b];
+        if (cj == 0)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) prs[b] = rowb[buf][cj + b] * inv;
+            for (int a = 0; a < 4; ++a) colb[0][0][ri + a] = p[a][0];
+        __syncthreads();
+        for (int c4 = 0; c4 < nst; c4 += 4) {
+            const bool own_r = ri == c4, own_c = cj == c4;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) pcv[a] = colb[buf][ri + a];
+            for (int l = 0; l < 4; ++l) {
+                const int c = c4 + l;
+                const int buf = c & 1;
+                const T piv = rowb[buf][0][c];
+                if (t == 0 && !(fabs((double)piv) > 1e-300 && isfinite((double)piv))) bad = 1;
+                const T inv = recip(piv);
+                T prs[4], pcv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) prs[b] = rowb[buf][0][cj + b] * inv;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) p[a][b] -= pcv[a] * prs[b];
-            if (own_c)
+                for (int a = 0; a < 4; ++a) pcv[a] = colb[buf][0][ri + a];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) p[a][l] = -pcv[a] * inv;
-            if (own_r)
+                for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) p[l][b] = prs[b];
-            if (own_r && own_c) p[l][l] = inv;
-            // publish row and column c + 1
-            const int c1 = c + 1, nb2 = buf ^ 1;
-            if (c1 < GJ_NB) {
-                const int l1 = (l + 1) & 3;
-                const bool r1 = ri == (c1 & ~3), k1 = cj == (c1 & ~3);
-                if (r1)
+                    for (int b = 0; b < 4; ++b) p[a][b] -= pcv[a] * prs[b];
+                if (own_c)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) rowb[nb2][cj + b] = p[l1][b];
-                if (k1)
+                    for (int a = 0; a < 4; ++a) p[a][l] = -pcv[a] * inv;
+                if (own_r)
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) colb[nb2][ri + a] = p[a][l1];
+                    for (int b = 0; b < 4; ++b) p[l][b] = prs[b];
+                if (own_r && own_c) p[l][l] = inv;
+                // publish row and column c + 1
+                const int c1 = c + 1, nb2 = buf ^ 1;
+                if (c1 < GJ_NB) {
+                    const int l1 = (l + 1) & 3;
+                    const bool r1 = ri == (c1 & ~3), k1 = cj == (c1 & ~3);
+                    if (r1)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) rowb[nb2][0][cj + b] = p[l1][b];
+                    if (k1)
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) colb[nb2][0][ri + a] = p[a][l1];
+                }
+                __syncthreads();
             }
-            __syncthreads();
+        }
+    } else {
+        // publish rows 0, 1 and columns 0, 1
+        if (ri == 0)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) { rowb[0][0][cj + b] = p[0][b]; rowb[0][1][cj + b] = p[1][b]; }
+        if (cj == 0)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) { colb[0][0][ri + a] = p[a][0]; colb[0][1][ri + a] = p[a][1]; }
+        __syncthreads();
+        for (int c4 = 0; c4 < nst; c4 += 4) {
+            const bool own_r = ri == c4, own_c = cj == c4;
+#pragma unroll
+            for (int l = 0; l < 4; l += 2) {
+                const int c = c4 + l;
+                const int buf = (c >> 1) & 1;
+                // 2 x 2 pivot block and its inverse
+                const T b00 = rowb[buf][0][c], b01 = rowb[buf][0][c + 1];
+                const T b10 = rowb[buf][1][c], b11 = rowb[buf][1][c + 1];
+                const T det = b00 * b11 - b01 * b10;
+                if (t == 0 && !(fabs((double)det) > 1e-300 && isfinite((double)det))) bad = 1;
+                const T id = T(1) / det;
+                const T i00 = b11 * id, i01 = -b01 * id, i10 = -b10 * id, i11 = b00 * id;
+                // the pivot rows times the inverse, and the old pivot columns
+                T r0[4], r1[4], c0[4], c1v[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const T x0 = rowb[buf][0][cj + b], x1 = rowb[buf][1][cj + b];
+                    r0[b] = i00 * x0 + i01 * x1;
+                    r1[b] = i10 * x0 + i11 * x1;
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) { c0[a] = colb[buf][0][ri + a]; c1v[a] = colb[buf][1][ri + a]; }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) p[a][b] -= c0[a] * r0[b] + c1v[a] * r1[b];
+                if (own_c)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        p[a][l] = -(c0[a] * i00 + c1v[a] * i10);
+                        p[a][l + 1] = -(c0[a] * i01 + c1v[a] * i11);
+                    }
+                if (own_r)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) { p[l][b] = r0[b]; p[l + 1][b] = r1[b]; }
+                if (own_r && own_c) {
+                    p[l][l] = i00; p[l][l + 1] = i01;
+                    p[l + 1][l] = i10; p[l + 1][l + 1] = i11;
+                }
+                // publish rows and columns c + 2, c + 3
+                const int c2 = c + 2, nb2 = buf ^ 1;
+                if (c2 < GJ_NB) {
+                    const int l2 = (l + 2) & 3;
+                    const bool rr = ri == (c2 & ~3), kk = cj == (c2 & ~3);
+                    if (rr)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) { rowb[nb2][0][cj + b] = p[l2][b]; rowb[nb2][1][cj + b] = p[l2 + 1][b]; }
+                    if (kk)
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) { colb[nb2][0][ri + a] = p[a][l2]; colb[nb2][1][ri + a] = p[a][l2 + 1]; }
+                }
+                __syncthreads();
+            }
         }
     }
 #pragma unroll
@@ -260,14 +334,18 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
 
 template <typename T>
 void launch_gj_pivot(const GJDesc<T>* d, int n_desc, int step, int nb, int max_chunks, int* err,
-                     hipStream_t s) {
+                     int pair, hipStream_t s) {
     constexpr int MAX_Y = 65535;   // grid y limit: blocks beyond it go to further launches
-    for (int o = 0; o < n_desc; o += MAX_Y)
-        hipLaunchKernelGGL(gj_pivot_kernel<T>, dim3(max_chunks, std::min(MAX_Y, n_desc - o)), dim3(256), 0, s,
-                           d + o, step, nb, err);
+    for (int o = 0; o < n_desc; o += MAX_Y) {
+        const dim3 grid(max_chunks, std::min(MAX_Y, n_desc - o));
+        if (pair)
+            hipLaunchKernelGGL((gj_pivot_kernel<T, true>), grid, dim3(256), 0, s, d + o, step, nb, err);
+        else
+            hipLaunchKernelGGL((gj_pivot_kernel<T, false>), grid, dim3(256), 0, s, d + o, step, nb, err);
+    }
 }
 
-template void launch_gj_pivot<double>(const GJDesc<double>*, int, int, int, int, int*, hipStream_t);
-template void launch_gj_pivot<float>(const GJDesc<float>*, int, int, int, int, int*, hipStream_t);
+template void launch_gj_pivot<double>(const GJDesc<double>*, int, int, int, int, int*, int, hipStream_t);
+template void launch_gj_pivot<float>(const GJDesc<float>*, int, int, int, int, int*, int, hipStream_t);
 
 }  // namespace rsd

@@ -160,6 +160,24 @@ __global__ void __launch_bounds__(256) qr_r11_kernel(T* __restrict__ aux, int* _
     }
 }
 
+// Damped least squares: row pz + j of column j takes lambda = damp |R_11|
+// (the rows were zero so far), and the column's squared norm grows by
+// lambda^2.  The problem becomes min |K T - B|^2 + lambda^2 |T|^2, whose R
+// has no pivot below lambda.
+template <typename T>
+__global__ void __launch_bounds__(256) qr_damp_kernel(T* __restrict__ A, T* __restrict__ aux,
+                                                       int* __restrict__ iaux,
+                                                       const QRProblemDev* __restrict__ probs) {
+    const QRProblemDev q = probs[blockIdx.y];
+    if (!(q.damp > 0)) return;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= q.k || q.pz + j >= q.p) return;
+    Aux<T> X(aux, iaux, nullptr, q);
+    const T lam = T(q.damp) * X.r11[0];
+    A[q.offA + (q.pz + j) + (int64_t)j * q.p] = lam;
+    X.norms[j] += lam * lam;
+}
+
 // Window selection and the permutation that realises it.  The remaining
 // candidates are ordered by (trailing norm descending, column ascending) with
 // a bitonic sort in LDS (nsort, a power of two at least the number of
@@ -409,8 +427,7 @@ template <typename T, int W>
 __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __restrict__ aux,
                                                       int* __restrict__ iaux, T* __restrict__ ws,
                                                       const QRProblemDev* __restrict__ probs,
-                                                      const int* __restrict__ plist, int sub,
-                                                      double tol) {
+                                                      const int* __restrict__ plist, int sub) {
     constexpr int S = panel_stride<T, W>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* P = reinterpret_cast<T*>(smem_raw);
@@ -481,7 +498,7 @@ __global__ void __launch_bounds__(PT) qr_panel_kernel(T* __restrict__ A, T* __re
             if (t == 0) { const int y = lperm[c]; lperm[c] = lperm[pv]; lperm[pv] = y; }
         }
         const T normx = sqrt(pn);
-        if (!(normx > T(tol) * r11)) { nref = c; stop = true; return; }
+        if (!(normx > T(q.ttol) * r11)) { nref = c; stop = true; return; }
         const T beta = x0 >= T(0) ? -normx : normx;
         const T tau = (beta - x0) / beta;
         const T scl = T(1) / (x0 - beta);
@@ -814,6 +831,14 @@ void launch_qr_init(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_pr
 }
 
 template <typename T>
+void launch_qr_damp(T* A, T* aux, int* iaux, const QRProblemDev* probs, int n_probs, int max_k,
+                    hipStream_t s) {
+    if (n_probs <= 0 || max_k <= 0) return;
+    hipLaunchKernelGGL(qr_damp_kernel<T>, dim3((max_k + 255) / 256, n_probs), dim3(256), 0, s, A, aux, iaux,
+                       probs);
+}
+
+template <typename T>
 void launch_qr_select(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, int n_probs,
                       int outer, int max_k, hipStream_t s) {
     if (n_probs <= 0) return;
@@ -834,24 +859,22 @@ void launch_qr_move(T* A, int* iaux, T* ws, const QRProblemDev* probs, int n_pro
 
 template <typename T, int W>
 static void panel_launch(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs,
-                         const int* plist, int n_list, int sub, double tol, int max_p,
-                         hipStream_t s) {
+                         const int* plist, int n_list, int sub, int max_p, hipStream_t s) {
     auto kfn = qr_panel_kernel<T, W>;
     const size_t shm = (size_t)max_p * panel_stride<T, W>() * sizeof(T);
     if (allow_lds((const void*)kfn) < shm) throw HipError("interpolation panel exceeds LDS");
-    hipLaunchKernelGGL(kfn, dim3(n_list), dim3(PT), shm, s, A, aux, iaux, ws, probs, plist, sub, tol);
+    hipLaunchKernelGGL(kfn, dim3(n_list), dim3(PT), shm, s, A, aux, iaux, ws, probs, plist, sub);
 }
 
 template <typename T>
 void launch_qr_panel(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, const int* plist,
-                     int n_list, int nb_class, int max_p, int outer, int sub, double tol,
-                     hipStream_t s) {
+                     int n_list, int nb_class, int max_p, int outer, int sub, hipStream_t s) {
     (void)outer;
     if (n_list <= 0) return;
-    if (nb_class == 16) panel_launch<T, 16>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
-    else if (nb_class == 8) panel_launch<T, 8>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
-    else if (nb_class == 4) panel_launch<T, 4>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
-    else if (nb_class == 2) panel_launch<T, 2>(A, aux, iaux, ws, probs, plist, n_list, sub, tol, max_p, s);
+    if (nb_class == 16) panel_launch<T, 16>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
+    else if (nb_class == 8) panel_launch<T, 8>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
+    else if (nb_class == 4) panel_launch<T, 4>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
+    else if (nb_class == 2) panel_launch<T, 2>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
     else throw HipError("bad panel width");
 }
 
@@ -896,11 +919,12 @@ void launch_qr_trsm(T* A, T* aux, int* iaux, T* Tout, T* Tsec, const QRProblemDe
 
 #define INST(T)                                                                                   \
     template void launch_qr_init<T>(T*, T*, int*, const QRProblemDev*, int, int, hipStream_t);     \
+    template void launch_qr_damp<T>(T*, T*, int*, const QRProblemDev*, int, int, hipStream_t);     \
     template void launch_qr_select<T>(T*, T*, int*, T*, const QRProblemDev*, int, int, int,        \
                                       hipStream_t);                                               \
     template void launch_qr_move<T>(T*, int*, T*, const QRProblemDev*, int, int, hipStream_t);     \
     template void launch_qr_panel<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,  \
-                                     int, int, int, double, hipStream_t);                         \
+                                     int, int, int, hipStream_t);                                 \
     template void launch_qr_inner<T>(T*, T*, int*, T*, const QRProblemDev*, const int*, int, int,  \
                                      int, int, hipStream_t);                                      \
     template void launch_qr_wsum<T>(T*, int*, T*, const QRProblemDev*, int, int, int, int,         \

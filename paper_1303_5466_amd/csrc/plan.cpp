@@ -103,8 +103,11 @@ struct Builder {
             // block elimination at the top: residual = first child, skeleton = second
             for (int q = 0; q < (int)pts.size(); ++q) (srcc[q] == 0 ? rs : sk).push_back(q);
         } else {
-            for (int q = 0; q < (int)pts.size(); ++q)
-                (depth_in(pts[q].u, pts[q].v, a, b) < P.m ? sk : rs).push_back(q);
+            for (int q = 0; q < (int)pts.size(); ++q) {
+                const bool keep = depth_in(pts[q].u, pts[q].v, a, b) < P.m ||
+                                  on_interface(pts[q], a, b, split, split == 0 ? a1 : b1);
+                (keep ? sk : rs).push_back(q);
+            }
             order_points(sk, rs, pts, a, b, split);
         }
         finish(L, pts, sk, rs, srcc, srci);
@@ -112,6 +115,20 @@ struct Builder {
         P.layouts.push_back(std::move(L));
         layout_of[key] = id;
         return id;
+    }
+
+    // Interface skeleton points (Sec. 5.3: a few points per wavelength kept on
+    // the cut between the children): on the two grid lines either side of
+    // the cut at c (u = c - 1, c for a cut across u; v likewise), those whose
+    // distance past the boundary layers along the cut is iface / 2 modulo
+    // iface.  Off when iface = 0.
+    bool on_interface(const Pt& p, int a, int b, int split, int c) const {
+        if (P.iface <= 0 || split < 0) return false;
+        const int across = split == 0 ? p.u : p.v;
+        if (across != c - 1 && across != c) return false;
+        const int along = split == 0 ? p.v : p.u, len = split == 0 ? b : a;
+        const int past = std::min(along, len - 1 - along) - P.m;
+        return past >= 0 && past % P.iface == P.iface / 2;
     }
 
     void finish(Layout& L, const std::vector<Pt>& pts, const std::vector<int>& sk,
@@ -224,11 +241,11 @@ struct Builder {
 
 }  // namespace
 
-Plan make_plan(int64_t nx, int64_t ny, int leaf, int m) {
-    if (nx < 1 || ny < 1 || leaf < 1 || m < 1) throw std::runtime_error("invalid plan arguments");
+Plan make_plan(int64_t nx, int64_t ny, int leaf, int m, int iface) {
+    if (nx < 1 || ny < 1 || leaf < 1 || m < 1 || iface < 0) throw std::runtime_error("invalid plan arguments");
     if (nx > (1 << 20) || ny > (1 << 20)) throw std::runtime_error("grid too large");
     Plan P;
-    P.nx = nx; P.ny = ny; P.leaf = leaf; P.m = m;
+    P.nx = nx; P.ny = ny; P.leaf = leaf; P.m = m; P.iface = iface;
     const int sx = n_splits(nx, leaf), sy = n_splits(ny, leaf);
     // global split schedule: longer remaining segment first, x on ties
     std::vector<int> sched;

@@ -72,6 +72,7 @@ struct Box {
 struct Plan {
     int64_t nx = 0, ny = 0;
     int leaf = 8, m = 2;
+    int iface = 0;                        // spacing of the interface skeleton points (0: none)
     std::vector<Box> boxes;               // level by level from the leaves
     std::vector<std::vector<int>> levels; // box ids per level (0 = leaves)
     std::vector<Layout> layouts;
@@ -83,7 +84,7 @@ struct Plan {
 };
 
 // Build the plan for an nx x ny grid; throws std::runtime_error on bad input.
-Plan make_plan(int64_t nx, int64_t ny, int leaf, int m);
+Plan make_plan(int64_t nx, int64_t ny, int leaf, int m, int iface = 0);
 
 // Active point ids (grid index i * ny + j) of a box in [sk; rs] order.
 std::vector<int64_t> box_points(const Plan& p, int box);

@@ -27,6 +27,7 @@ RSD_FLAG_NO_SYMMETRY = 2
 RSD_FLAG_FP32_INTERP = 4
 RSD_FLAG_NO_DEDUP = 8
 RSD_FLAG_SOLVE_GRAPH = 16
+RSD_FLAG_NO_DAMPING = 32
 
 
 class rsd_kernel(C.Structure):
@@ -36,7 +37,7 @@ class rsd_kernel(C.Structure):
 class rsd_options(C.Structure):
     _fields_ = [("leaf_side", C.c_int32), ("layers", C.c_int32), ("precision", C.c_int32),
                 ("max_refine", C.c_int32), ("refine_tol", C.c_double), ("hip_stream", C.c_void_p),
-                ("device", C.c_int32), ("flags", C.c_int32)]
+                ("device", C.c_int32), ("flags", C.c_int32), ("interface_ppw", C.c_double)]
 
 
 class rsd_solve_info(C.Structure):
@@ -125,7 +126,7 @@ EXPORTS = {
     "rsd_factor_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
     "rsd_factor_interp_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_interp_info)]),
     "rsd_factor_get_block": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
-    "rsd_plan_create": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+    "rsd_plan_create": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(C.c_void_p)]),
     "rsd_plan_n_boxes": (C.c_int32, [C.c_void_p]),
     "rsd_plan_n_levels": (C.c_int32, [C.c_void_p]),
@@ -187,7 +188,7 @@ class Factor:
 
     def __init__(self, points, a=None, tol=1e-10, kernel=RSD_KERNEL_LAPLACE, wavenumber=0.0,
                  contrast=None, leaf_side=0, layers=0, precision=RSD_PREC_FP64, max_refine=0,
-                 refine_tol=0.0, stream=None, device=-1, flags=0):
+                 refine_tol=0.0, stream=None, device=-1, flags=0, interface_ppw=0.0):
         lib = load()
         if isinstance(points, np.ndarray):
             points = np.ascontiguousarray(points, dtype=np.float64)
@@ -201,7 +202,7 @@ class Factor:
         bp, _k3 = _ptr(contrast)
         kd = rsd_kernel(kernel, wavenumber, bp)
         opt = rsd_options(leaf_side, layers, precision, max_refine, refine_tol,
-                          stream if stream is not None else None, device, flags)
+                          stream if stream is not None else None, device, flags, interface_ppw)
         h = C.c_void_p()
         self._h = None
         _check(lib.rsd_build_factor(pp, n, C.byref(kd), ap, tol, C.byref(opt), C.byref(h)))
@@ -479,10 +480,10 @@ class Server:
 class Plan:
     """Host-only tree / skeleton plan (no device needed)."""
 
-    def __init__(self, nx, ny, leaf_side=8, layers=2):
+    def __init__(self, nx, ny, leaf_side=8, layers=2, interface_step=0):
         lib = load()
         h = C.c_void_p()
-        _check(lib.rsd_plan_create(nx, ny, leaf_side, layers, C.byref(h)))
+        _check(lib.rsd_plan_create(nx, ny, leaf_side, layers, interface_step, C.byref(h)))
         self._h = h
 
     def __del__(self):
@@ -607,9 +608,10 @@ def gemm(A, B, C=None, alpha=1.0, beta=0.0, tA=False, tB=False):
     return C
 
 
-def gj_invert(A):
-    """Inverse by the library's blocked Gauss-Jordan (NumPy in and out)."""
-    code = 0 if A.dtype == np.float64 else 1
+def gj_invert(A, paired=False):
+    """Inverse by the library's blocked Gauss-Jordan (NumPy in and out);
+    paired: eliminate pivots two at a time (complex entries in real form)."""
+    code = (0 if A.dtype == np.float64 else 1) | (2 if paired else 0)
     X = np.asfortranarray(A.copy())
     _check(load().rsd_gj_invert(code, X.shape[0], X.ctypes.data, X.shape[0]))
     return X

@@ -47,6 +47,41 @@ def test_gemm_matches_numpy(dt, tol, M, N, K, tA, tB):
     assert np.abs(C - ref).max() <= tol * (np.abs(ref).max() + 1) * max(1, K) ** 0.5
 
 
+def _real_form(Z):
+    """Real form of a complex matrix with each entry's two dofs adjacent:
+    entry (i, j) becomes the 2 x 2 block [[re, im], [im, -re]]."""
+    n = Z.shape[0]
+    X = np.zeros((2 * n, 2 * n))
+    X[0::2, 0::2] = Z.real
+    X[0::2, 1::2] = Z.imag
+    X[1::2, 0::2] = Z.imag
+    X[1::2, 1::2] = -Z.real
+    return X
+
+
+@pytest.mark.parametrize("n", [1, 7, 32, 33, 100, 130])
+def test_gj_paired_pivots_invert_complex_real_forms(n):
+    # complex symmetric matrices with an imaginary diagonal: the real part of
+    # the first pivot is zero, the complex pivots are not.  The paired
+    # elimination inverts the real form; the scalar one does not.
+    rng = np.random.default_rng(n)
+    d = 1j * (1.0 + rng.random(n))
+    B = 0.1 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    B = B + B.T
+    np.fill_diagonal(B, 0.0)
+    Z = np.diag(d) + B
+    X = _real_form(Z)
+    inv = np.linalg.inv(X)
+    P = rsd.gj_invert(X, paired=True)
+    assert np.abs(P - inv).max() <= 1e-12 * np.abs(inv).max()
+    if n >= 7:
+        try:
+            S = rsd.gj_invert(X, paired=False)
+            assert np.abs(S - inv).max() > 1e-6 * np.abs(inv).max()
+        except rsd.RsdError:
+            pass
+
+
 def test_split_k_gemm_is_repeatable():
     # the partial tiles are summed in split order whichever work-group is last
     rng = np.random.default_rng(4)
@@ -887,17 +922,20 @@ def test_interpolation_truncation_record(nx, ny):
     fw.close()
 
 
-@pytest.mark.parametrize("n,tol,layers,precision,flags,truncating", [
-    (128, 1e-6, 0, rsd.RSD_PREC_FP64, 0, False), (64, 1e-8, 0, rsd.RSD_PREC_FP64, 0, False),
-    (128, 1e-10, 3, rsd.RSD_PREC_FP64, rsd.RSD_FLAG_NO_SYMMETRY, True),
-    (128, 1e-6, 2, rsd.RSD_PREC_FP32_REFINE, rsd.RSD_FLAG_FP32_INTERP, True)])
-def test_interpolation_rank_matches_lapack_pivoting(n, tol, layers, precision, flags, truncating):
-    # against LAPACK's column-pivoted QR (geqp3) at the same threshold: the
-    # default configurations keep every column in both; where truncation is
-    # active the windowed pivoting decides it per sub-panel, so it may stop
-    # earlier than greedy pivoting, but never keeps more than a few columns
-    # beyond it, and its T interpolates the proxy field as well as the
-    # truncated LAPACK solution up to the threshold
+@pytest.mark.parametrize("n,tol,layers,precision,flags,mode", [
+    (128, 1e-6, 0, rsd.RSD_PREC_FP64, 0, "full"), (64, 1e-8, 0, rsd.RSD_PREC_FP64, 0, "full"),
+    (128, 1e-10, 3, rsd.RSD_PREC_FP64, rsd.RSD_FLAG_NO_SYMMETRY, "damped"),
+    (128, 1e-10, 3, rsd.RSD_PREC_FP64, 0, "damped"),
+    (128, 1e-10, 3, rsd.RSD_PREC_FP64, rsd.RSD_FLAG_NO_DAMPING, "truncated"),
+    (128, 1e-6, 2, rsd.RSD_PREC_FP32_REFINE, rsd.RSD_FLAG_FP32_INTERP, "damped")])
+def test_interpolation_rank_matches_lapack_pivoting(n, tol, layers, precision, flags, mode):
+    # against LAPACK's column-pivoted QR (geqp3) on the same proxy matrices:
+    # the default two-layer and one-layer configurations keep every column in
+    # both; where truncation would be active (three layers, float32
+    # interpolation) the damped least squares keeps every column and its T
+    # interpolates the proxy field as well as LAPACK's solution truncated at
+    # the damping level; truncation alone (RSD_FLAG_NO_DAMPING, threshold
+    # 1e-12 with three layers) keeps within a few columns of LAPACK's rank
     pts = W.grid_points(n)
     a = W.coef_sine(pts)
     h = 1.0 / n
@@ -906,6 +944,8 @@ def test_interpolation_rank_matches_lapack_pivoting(n, tol, layers, precision, f
     m = f.stats()["layers"]
     if flags & rsd.RSD_FLAG_FP32_INTERP:
         qtol = max(tol, 1e-6)
+    elif mode == "damped":
+        qtol = tol
     else:
         qtol = min(tol, 1e-12) if m >= 3 else min(tol, 1e-10) if m == 2 else tol
     seen = set()
@@ -931,26 +971,35 @@ def test_interpolation_rank_matches_lapack_pivoting(n, tol, layers, precision, f
         Tref = rskel.truncated_qrcp_lstsq(Ks, Kr, qtol)
         res_ref = np.linalg.norm(Ks @ Tref - Kr) / np.linalg.norm(Kr)
         print(key, "rank", ranks, "geqp3", rho, "of", k, "residual %.2e (geqp3 %.2e)" % (res, res_ref))
-        if truncating:
-            assert ranks <= rho + max(2, k // 100), (key, ranks, rho)
+        if mode == "truncated":
+            assert abs(ranks - rho) <= max(2, k // 100), (key, ranks, rho)
+        elif mode == "damped":
+            assert ranks == k, (key, ranks)
         else:
             assert ranks == rho == k, (key, ranks, rho)
         assert res <= 2 * res_ref + 5 * qtol, (key, res, res_ref)
+        if mode == "damped":
+            # the damping bounds T like the truncation does
+            assert np.abs(T).max() <= 10 * np.abs(Tref).max() + 1, (key, np.abs(T).max(), np.abs(Tref).max())
     f.close()
 
 
-@pytest.mark.parametrize("flags", [0, rsd.RSD_FLAG_NO_SYMMETRY])
+@pytest.mark.parametrize("flags", [0, rsd.RSD_FLAG_NO_SYMMETRY, rsd.RSD_FLAG_NO_DAMPING])
 def test_three_layers_at_a_loose_tolerance(flags):
-    # three skeleton layers asked for at tol 1e-10: the float64 interpolation
-    # truncates at 1e-12, where its problems are full rank (at 1e-10 the
-    # window pivoting stopped far too early and the solve was wrong)
+    # three skeleton layers asked for at tol 1e-10: the interpolation
+    # problems are rank deficient at 1e-10; damped at 1e-10 (default) or
+    # truncated at 1e-12 (no damping) the solve meets the tolerance (truncated
+    # at 1e-10, the window pivoting stopped far too early and the solve was
+    # wrong)
     pts = W.grid_points(64)
     a = W.coef_sine(pts)
     f = W.rhs_normal(len(pts), 2, 53)
     fac = rsd.Factor(pts, a, 1e-10, layers=3, flags=flags)
     assert fac.stats()["layers"] == 3
     x, _ = fac.solve(f)
-    assert dense.rel_error(x, dense.solve(pts, f, a)) < 1e-12
+    err = dense.rel_error(x, dense.solve(pts, f, a))
+    print("three layers at 1e-10, flags", flags, "error vs dense %.2e" % err)
+    assert err < 1e-10
     fac.close()
 
 

@@ -103,6 +103,70 @@ def test_plan_matches_reference_sets(nx, ny, leaf, m):
     assert box == plan.n_boxes
 
 
+@pytest.mark.parametrize("nx,ny,m,step", [(64, 64, 3, 3), (50, 40, 2, 1), (96, 64, 3, 5), (37, 37, 3, 2)])
+def test_plan_interface_points_match_reference_sets(nx, ny, m, step):
+    """With interface skeleton points (Sec. 5.3) every box's skeleton and
+    residual sets still equal the reference's."""
+    plan = rsd.Plan(nx, ny, 8, m, interface_step=step)
+    root, levels = rskel.index_sets(nx, ny, 8, m, step)
+    D = len(levels) - 1
+    box = 0
+    extra = 0
+    for t in range(D + 1):
+        for b in levels[D - t]:
+            info = plan.box_info(box)
+            pts = plan.box_points(box)
+            k = info["k"]
+            if t < D:
+                assert set(pts[:k].tolist()) == set(b.act[b.sk].tolist())
+                assert set(pts[k:].tolist()) == set(b.act[b.rs].tolist())
+                i, j = b.act[b.sk] // ny, b.act[b.sk] % ny
+                d = np.minimum.reduce([i - b.x0, b.x1 - 1 - i, j - b.y0, b.y1 - 1 - j])
+                extra += int(np.sum(d >= m))
+            box += 1
+    assert extra > 0
+
+
+@pytest.mark.parametrize("ax,ay,m,step", [(32, 16, 3, 3), (64, 32, 2, 4), (16, 16, 3, 1), (40, 20, 3, 6)])
+def test_interface_points_rule(ax, ay, m, step):
+    """The reference's interface rule on one box cut across x: the extra
+    skeleton points lie on the two grid lines beside the cut, mirror
+    symmetric about the box's centre lines, consecutive ones step cells
+    apart along the cut in each half (at most 2 step across the middle),
+    none inside the boundary layers."""
+    b = rskel.Box(0, ax, 0, ay, 0)
+    c1 = rskel.Box(0, ax // 2, 0, ay, 1)
+    c2 = rskel.Box(ax // 2, ax, 0, ay, 1)
+    b.children = [c1, c2]
+    ii, jj = np.meshgrid(np.arange(ax), np.arange(ay), indexing="ij")
+    i, j = ii.ravel(), jj.ravel()
+    base = rskel.skeleton_mask(b, i, j, m, 0)
+    with_iface = rskel.skeleton_mask(b, i, j, m, step)
+    assert np.all(with_iface[base])
+    ex = with_iface & ~base
+    ei, ej = i[ex], j[ex]
+    assert set(ei.tolist()) == {ax // 2 - 1, ax // 2}
+    pts = set(zip(ei.tolist(), ej.tolist()))
+    assert all((ax - 1 - u, v) in pts and (u, ay - 1 - v) in pts for u, v in pts)
+    assert ej.min() >= m and ej.max() <= ay - 1 - m
+    for u in (ax // 2 - 1, ax // 2):
+        vs = np.sort(ej[ei == u])
+        lower = vs[vs <= (ay - 1) / 2]
+        assert np.all(np.diff(lower) == step)
+        assert np.all(np.diff(vs) <= 2 * step)
+        assert len(vs) >= (ay - 2 * m) // step - 1
+    # a leaf (no children) gets no interface points
+    leaf = rskel.Box(0, ax, 0, ay, 0)
+    assert np.array_equal(rskel.skeleton_mask(leaf, i, j, m, step), base)
+
+
+def test_interface_step_from_wavenumber():
+    """floor(2 pi / (k h ppw)) cells for ppw points per wavelength."""
+    assert rskel.interface_step(100.0, 1.0 / 128, 4.0) == 2      # 8.04 cells per wavelength
+    assert rskel.interface_step(20.0, 1.0 / 256, 4.0) == 20      # 80.4 cells
+    assert rskel.interface_step(200.0, 1.0 / 64, 8.0) == 1       # under a cell: one
+
+
 def test_plan_levels_golden():
     """Per-depth box shapes and sizes stored in tests/golden/levels.txt."""
     path = os.path.join(ROOT, "tests", "golden", "levels.txt")
