@@ -167,10 +167,11 @@ def serving_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4):
 def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, sides=(128, 256)):
     """The served scattering workload: Lippmann-Schwinger factors (Helmholtz
     kernel, wavenumber 20, Gaussian contrast bump) of the given sides,
-    complex128 factors (float64 J form, three layers, tol 1e-8) with complex128
-    refinement (at most two steps), submitted while single-RHS complex solve
-    requests arrive as a Poisson process on the factors already resident;
-    returns latency percentiles, throughput and the worst residual."""
+    complex64 factors (float32 J form, three layers, root block in float64)
+    with complex128 refinement to 1e-8 (at most four steps), submitted while
+    single-RHS complex solve requests arrive as a Poisson process on the
+    factors already resident; returns latency percentiles, throughput and the
+    worst residual."""
     rng = np.random.default_rng(seed)
     dev = torch.device("cuda:0")
     srv = rsd.Server(n_workers=2, max_coalesce=64)
@@ -179,7 +180,8 @@ def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, side
     for n in sides:
         pts = W.grid_points(n)
         b = W.contrast_bump(pts)
-        fids.append(srv.submit_factor(torch.from_numpy(pts).to(dev), None, tol=1e-8, max_refine=2,
+        fids.append(srv.submit_factor(torch.from_numpy(pts).to(dev), None, tol=1e-8,
+                                      precision=rsd.RSD_PREC_FP32_REFINE, max_refine=4, refine_tol=1e-8,
                                       kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=W.SCATTER_K,
                                       contrast=torch.from_numpy(b).to(dev), wait=False))
         sizes.append(pts.shape[0])
@@ -221,7 +223,7 @@ def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, side
     t_all = time.perf_counter() - t0
     srv.close()
     return {"workload": f"Lippmann-Schwinger, Helmholtz k={W.SCATTER_K:g}, contrast bump 0.5/0.15, sides {list(sides)}; "
-                        f"factors submitted at t=0 (complex128: float64 J form, tol 1e-8, complex128 refinement), "
+                        f"factors submitted at t=0 (complex64 bulk: float32 J form, tol 1e-8, complex128 refinement), "
                         f"Poisson arrivals {rate:.0f}/s for {seconds:.0f} s, 1 complex RHS each",
             "requests": st["n_done"], "failed": bad, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
             "mean_batch_rhs": st["mean_batch_rhs"], "rhs_per_s": st["rhs_per_s"], "max_rel_residual": worst,

@@ -293,13 +293,16 @@ rsd_status rsd_factor_box_info(const rsd_factor* f, int32_t box, rsd_box_info* o
  * columns kept in problem s and scale[s] its |R_11| reference.  The sectors
  * of one type share one reference: the largest column norm over all of
  * them, which is the first pivot of the whole problem in the sector basis.
- * Unused entries are zero.  Waits for the factor's stream; call it when no
- * solve is running on the factor.  Errors: RSD_EINVAL (null argument, box
+ * Unused entries are zero.  A damped problem keeps every column (rank = k);
+ * problems too large for the damping rows in the panel kernel's local
+ * memory fall back to truncation (damped = 0).  Waits for the factor's
+ * stream; call it when no solve is running on the factor.  Errors: RSD_EINVAL (null argument, box
  * out of range). */
 typedef struct rsd_interp_info {
     int32_t n_problems;
     int32_t rank[4];
     double scale[4];
+    int32_t damped;        /* 1: solved as damped least squares (RSD_FLAG_NO_DAMPING) */
 } rsd_interp_info;
 rsd_status rsd_factor_interp_info(const rsd_factor* f, int32_t box, rsd_interp_info* out);
 

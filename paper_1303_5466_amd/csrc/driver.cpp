@@ -931,6 +931,7 @@ struct Factor {
     DevBuf d_boxes, d_layouts, d_lu, d_lv, d_srcc, d_srci, d_inv, d_perm, d_ident, d_a, d_sb,
         d_level_ids, d_err, d_table, d_spec, d_fftwork, d_flag;
     DevBuf d_interp;                // per layout, 4 x (kept rank, |R_11| reference, sectors)
+    std::vector<int8_t> layout_damped;   // per layout: interpolation solved as damped least squares
     int fft_mx = 0, fft_my = 0;     // circulant sizes of the FFT product (0: not set up)
     std::mutex use_mu;              // solves and products of one factor run one at a time
     std::vector<int> level_id_off;
@@ -1205,7 +1206,7 @@ struct QRChain {
             const bool f32 = !std::is_same<T, double>::value;
             const double plain_tol = f32 ? std::max(F.tol, 1e-6) : interp_tol64(F);
             const double damp_rel = f32 ? std::max(F.tol, 1e-6) : F.tol;
-            const bool want_damp = (f32 || F.layers >= 3) && !(F.flags & RSD_FLAG_NO_DAMPING);
+            const bool want_damp = (f32 || F.layers >= 3 || F.cplx) && !(F.flags & RSD_FLAG_NO_DAMPING);
             for (int sc = 0; sc < nsec; ++sc) {
                 QRProblemDev& q = qp[base + sc];
                 q.staged = staged ? 1 : 0;
@@ -1216,6 +1217,7 @@ struct QRChain {
                     q.ttol = 1e-3 * damp_rel;    // a guard only: no pivot falls below damp |R_11|
                     any_damp = true;
                 }
+                if ((size_t)I.layout < F.layout_damped.size()) F.layout_damped[I.layout] = q.damp > 0 ? 1 : 0;
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));
                 if (q.nb == 0) throw Error(RSD_EINVAL, "box too large for the interpolation kernels");
                 const int n = q.k + q.r;
@@ -2243,6 +2245,7 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     RSD_HIP(hipMemsetAsync(f->d_err.p, 0, sizeof(int) * 4, s));
     // every interpolation problem writes its record (no clearing needed)
     f->d_interp.alloc(std::max<size_t>(P.layouts.size(), 1) * 12 * sizeof(double));
+    f->layout_damped.assign(P.layouts.size(), 0);
     // kernel descriptions: kd generates the factored matrix (diagonal ag,
     // no scaling), kd_res is the exact operator of the residual (contrast
     // scaling when given)
@@ -3657,6 +3660,7 @@ rsd_status rsd_factor_interp_info(const rsd_factor* fc, int32_t box, rsd_interp_
         const int n = (int)rec[2];
         if (n != 1 && n != 2 && n != 4) throw rsd::Error(RSD_EINVAL, "internal: no interpolation record for this box type");
         out->n_problems = n;
+        out->damped = f.layout_damped[li];
         for (int sc = 0; sc < n; ++sc) {
             out->rank[sc] = (int32_t)rec[3 * sc];
             out->scale[sc] = rec[3 * sc + 1];

@@ -58,7 +58,8 @@ class rsd_box_info(C.Structure):
 
 
 class rsd_interp_info(C.Structure):
-    _fields_ = [("n_problems", C.c_int32), ("rank", C.c_int32 * 4), ("scale", C.c_double * 4)]
+    _fields_ = [("n_problems", C.c_int32), ("rank", C.c_int32 * 4), ("scale", C.c_double * 4),
+                ("damped", C.c_int32)]
 
 
 class rsd_server_options(C.Structure):
@@ -250,6 +251,12 @@ class Factor:
         b = rsd_interp_info()
         _check(load().rsd_factor_interp_info(self._h, box, C.byref(b)))
         return [(int(b.rank[i]), float(b.scale[i])) for i in range(b.n_problems)]
+
+    def interp_damped(self, box):
+        """Whether the box type's interpolation was solved as damped least squares."""
+        b = rsd_interp_info()
+        _check(load().rsd_factor_interp_info(self._h, box, C.byref(b)))
+        return bool(b.damped)
 
     def block(self, box, which):
         info = self.box_info(box)

@@ -157,3 +157,51 @@ def test_served_scattering_factors():
     srv.close()
     for d in direct:
         d.close()
+
+
+# --- interface skeleton points and higher wavenumbers (Sec. 5.3) --------------
+def test_interface_points_scattering_matches_dense():
+    # a few points per wavelength kept on the cut between the children of
+    # every box: larger skeletons, same solution as the dense solve
+    pts = W.grid_points(64)
+    b = W.contrast_bump(pts)
+    k = 60.0
+    f = W.rhs_complex_normal(len(pts), 2, 81)
+    fi = rsd.Factor(pts, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=k, contrast=b,
+                    interface_ppw=2.0)
+    f0 = rsd.Factor(pts, None, 1e-10, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=k, contrast=b)
+    grown = 0
+    for bx in range(fi.stats()["n_boxes"]):
+        a, c = fi.box_info(bx), f0.box_info(bx)
+        assert a["k"] >= c["k"]
+        grown += a["k"] > c["k"]
+    assert grown > 0
+    x, _ = fi.solve(f)
+    ref = dense.solve(pts, f, None, "helmholtz", k, b)
+    err = dense.rel_error(x, ref)
+    print("interface points (step 3): error vs dense %.2e" % err)
+    assert err < 1e-10
+    fi.close()
+    f0.close()
+
+
+@pytest.mark.parametrize("k,ppw,precision", [(100.0, 0.0, rsd.RSD_PREC_FP64), (100.0, 4.0, rsd.RSD_PREC_FP64),
+                                             (100.0, 0.0, rsd.RSD_PREC_FP32_REFINE),
+                                             (200.0, 0.0, rsd.RSD_PREC_FP64)])
+def test_higher_wavenumber_scattering(k, ppw, precision):
+    # wavelengths of 8 and 4 grid cells (a leaf box or half of one) on 128^2:
+    # with the damped interpolation the three-layer factor stays at the
+    # tolerance, with and without interface points, and a complex64 factor
+    # refines to it
+    pts = W.grid_points(128)
+    b = W.contrast_bump(pts)
+    f = W.rhs_complex_normal(len(pts), 1, 83)
+    fac = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=k, contrast=b,
+                     interface_ppw=ppw, precision=precision,
+                     max_refine=10 if precision == rsd.RSD_PREC_FP32_REFINE else 0, refine_tol=1e-10)
+    x, info = fac.solve(f)
+    r = fac.matvec(x) - f
+    res = np.linalg.norm(r) / np.linalg.norm(f)
+    print(f"k={k:g} ppw={ppw:g}: residual {res:.2e}, {info.refine_iters} refinement steps")
+    assert res <= 1e-10
+    fac.close()

@@ -971,6 +971,7 @@ def test_interpolation_rank_matches_lapack_pivoting(n, tol, layers, precision, f
         Tref = rskel.truncated_qrcp_lstsq(Ks, Kr, qtol)
         res_ref = np.linalg.norm(Ks @ Tref - Kr) / np.linalg.norm(Kr)
         print(key, "rank", ranks, "geqp3", rho, "of", k, "residual %.2e (geqp3 %.2e)" % (res, res_ref))
+        assert f.interp_damped(b) == (mode == "damped"), key
         if mode == "truncated":
             assert abs(ranks - rho) <= max(2, k // 100), (key, ranks, rho)
         elif mode == "damped":
