@@ -164,14 +164,16 @@ def serving_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4):
             "mean_batch_rhs": st["mean_batch_rhs"], "rhs_per_s": st["rhs_per_s"]}
 
 
-def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, sides=(128, 256)):
+def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, sides=(128, 256), bulk="c64"):
     """The served scattering workload: Lippmann-Schwinger factors (Helmholtz
-    kernel, wavenumber 20, Gaussian contrast bump) of the given sides,
-    complex64 factors (float32 J form, three layers, root block in float64)
-    with complex128 refinement to 1e-8 (at most four steps), submitted while
-    single-RHS complex solve requests arrive as a Poisson process on the
-    factors already resident; returns latency percentiles, throughput and the
-    worst residual."""
+    kernel, wavenumber 20, Gaussian contrast bump) of the given sides, with
+    complex128 refinement to 1e-8; bulk "c64": complex64 factors (float32 J
+    form, three layers, root block in float64, at most eight refinement
+    steps), "c128": complex128 factors (float64 J form, at most two steps).
+    The factors are submitted while single-RHS complex solve requests arrive
+    as a Poisson process on the factors already resident; returns latency
+    percentiles, throughput and the worst residual."""
+    c64 = bulk == "c64"
     rng = np.random.default_rng(seed)
     dev = torch.device("cuda:0")
     srv = rsd.Server(n_workers=2, max_coalesce=64)
@@ -181,7 +183,8 @@ def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, side
         pts = W.grid_points(n)
         b = W.contrast_bump(pts)
         fids.append(srv.submit_factor(torch.from_numpy(pts).to(dev), None, tol=1e-8,
-                                      precision=rsd.RSD_PREC_FP32_REFINE, max_refine=4, refine_tol=1e-8,
+                                      precision=rsd.RSD_PREC_FP32_REFINE if c64 else rsd.RSD_PREC_FP64,
+                                      max_refine=8 if c64 else 2, refine_tol=1e-8,
                                       kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=W.SCATTER_K,
                                       contrast=torch.from_numpy(b).to(dev), wait=False))
         sizes.append(pts.shape[0])
@@ -223,7 +226,9 @@ def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, side
     t_all = time.perf_counter() - t0
     srv.close()
     return {"workload": f"Lippmann-Schwinger, Helmholtz k={W.SCATTER_K:g}, contrast bump 0.5/0.15, sides {list(sides)}; "
-                        f"factors submitted at t=0 (complex64 bulk: float32 J form, tol 1e-8, complex128 refinement), "
+                        f"factors submitted at t=0 ("
+                        + ("complex64 bulk: float32 J form" if c64 else "complex128 bulk: float64 J form")
+                        + ", tol 1e-8, complex128 refinement), "
                         f"Poisson arrivals {rate:.0f}/s for {seconds:.0f} s, 1 complex RHS each",
             "requests": st["n_done"], "failed": bad, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
             "mean_batch_rhs": st["mean_batch_rhs"], "rhs_per_s": st["rhs_per_s"], "max_rel_residual": worst,
@@ -462,11 +467,12 @@ def main():
         sv = out["serving"]
         log(f"  {sv['requests']} requests, p50 {sv['p50_ms']:.2f} ms, p99 {sv['p99_ms']:.2f} ms, "
             f"{sv['mean_batch_rhs']:.2f} RHS per coalesced solve")
-        log("served scattering workload: Helmholtz Lippmann-Schwinger factors + Poisson solves ...")
-        out["serving_scatter"] = serving_scatter_measure(torch, rsd, W)
-        sv = out["serving_scatter"]
-        log(f"  {sv['requests']} requests ({sv['failed']} failed), p50 {sv['p50_ms']:.2f} ms, p99 {sv['p99_ms']:.2f} ms, "
-            f"residual {sv['max_rel_residual']:.1e}")
+        for key, bulk in (("serving_scatter", "c64"), ("serving_scatter_c128", "c128")):
+            log(f"served scattering workload ({bulk} factors): Helmholtz Lippmann-Schwinger factors + Poisson solves ...")
+            out[key] = serving_scatter_measure(torch, rsd, W, bulk=bulk)
+            sv = out[key]
+            log(f"  {sv['requests']} requests ({sv['failed']} failed), p50 {sv['p50_ms']:.2f} ms, "
+                f"p99 {sv['p99_ms']:.2f} ms, residual {sv['max_rel_residual']:.1e}")
     if not args.no_cpu_baseline:
         log("timing the CPU reference on a bounded sample ...")
         out["cpu_baseline"], sols = cpu_baseline(pts, a, f)

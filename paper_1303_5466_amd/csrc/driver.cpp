@@ -1216,6 +1216,14 @@ struct QRChain {
                     q.damp = damp_rel;
                     q.ttol = 1e-3 * damp_rel;    // a guard only: no pivot falls below damp |R_11|
                     any_damp = true;
+                } else if (want_damp && F.cplx) {
+                    // complex factors are not accurate with truncation alone (their
+                    // least-squares solutions turn ill-conditioned)
+                    throw Error(RSD_EINVAL, "interpolation problem of a " + std::to_string(L.ax) + "x" +
+                                                std::to_string(L.ay) + " box type (" + std::to_string(q.pz) +
+                                                " x " + std::to_string(q.k) +
+                                                ") too large for the damped least squares; use fewer interface "
+                                                "points or RSD_FLAG_FP32_INTERP");
                 }
                 if ((size_t)I.layout < F.layout_damped.size()) F.layout_damped[I.layout] = q.damp > 0 ? 1 : 0;
                 q.nb = qr_panel_width(q.p, (int)sizeof(T));

@@ -205,3 +205,23 @@ def test_higher_wavenumber_scattering(k, ppw, precision):
     print(f"k={k:g} ppw={ppw:g}: residual {res:.2e}, {info.refine_iters} refinement steps")
     assert res <= 1e-10
     fac.close()
+
+
+def test_complex_interpolation_too_large_for_damping_is_rejected():
+    # interface points every grid cell at k = 300 on 256^2 make the 128 x 256
+    # box type's damped problem too large for the panel kernel's local memory;
+    # truncation alone is not accurate for complex factors, so the build stops
+    pts = W.grid_points(256)
+    b = W.contrast_bump(pts)
+    with pytest.raises(rsd.RsdError) as e:
+        rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=300.0, contrast=b,
+                   interface_ppw=4.0)
+    assert e.value.status == rsd.RSD_EINVAL
+    assert "damped" in str(e.value)
+    # the same grid with half the interface points builds and meets the tolerance
+    fac = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=300.0, contrast=b,
+                     interface_ppw=2.0)
+    f = W.rhs_complex_normal(len(pts), 1, 85)
+    x, _ = fac.solve(f)
+    assert np.linalg.norm(fac.matvec(x) - f) <= 1e-10 * np.linalg.norm(f)
+    fac.close()
