@@ -278,6 +278,51 @@ class RSkel:
                 b.Dt = Finv @ (np.eye(F.shape[0]) - L @ b.Rt)
                 b.Lt = Finv @ L @ E
 
+    # -- compressed forward product (Sec. 2.3, the factorization of A itself) --
+    def forward_matvec(self, x):
+        """y ~ A x through the skeletonization alone, in O(N) work: the block
+        of A between two distinct boxes i, j is L_i A(sk_i, sk_j) R_j (the
+        interpolation of Sec. 2.1 holds for every point outside a box), so A =
+        D + L A~ R with D the leaf blocks and A~ the kernel on the skeletons,
+        which telescopes up the tree.  Up: skeleton charges x^_b = R_b x_b
+        (x_b the box's active vector, its children's charges).  Across: at
+        every box above the leaves, each child's skeleton receives the kernel
+        block to its sibling's skeleton times the sibling's charges.  Down:
+        the potential y^_b on a skeleton spreads to the active points as
+        L_b y^_b = R_b^T y^_b and into the children; leaves add their own
+        dense block A(I_i, I_i) x_i."""
+        x = np.asarray(x)
+        X = x.reshape(self.N, -1).astype(np.result_type(x.dtype, self.dtype))
+        charge = {}
+        for depth in range(len(self.levels) - 1, 0, -1):
+            for b in self.levels[depth]:
+                if not b.children:
+                    v = X[b.act]
+                else:
+                    v = np.concatenate([charge[id(c)] for c in b.children])
+                charge[id(b)] = b.R @ v
+        pot = {id(b): np.zeros_like(charge[id(b)]) for lev in self.levels[1:] for b in lev}
+        for lev in self.levels:
+            for b in lev:
+                if b.children:
+                    c1, c2 = b.children
+                    s1, s2 = c1.act[c1.sk], c2.act[c2.sk]
+                    pot[id(c1)] += self.A(s1, s2) @ charge[id(c2)]
+                    pot[id(c2)] += self.A(s2, s1) @ charge[id(c1)]
+        Y = np.zeros_like(X)
+        for depth in range(1, len(self.levels)):
+            for b in self.levels[depth]:
+                spread = b.R.T @ pot[id(b)]          # on the active points
+                if not b.children:
+                    Y[b.act] = spread + self.A(b.act, b.act) @ X[b.act]
+                else:
+                    k1 = len(b.children[0].sk)
+                    pot[id(b.children[0])] += spread[:k1]
+                    pot[id(b.children[1])] += spread[k1:]
+        if len(self.levels) == 1:                   # a single box: no compression
+            Y = self.A(self.root.act, self.root.act) @ X
+        return Y[:, 0] if x.ndim == 1 else Y
+
     # -- apply: A^{-1} f = D~ f + L~ (A~^{l-1})^{-1} R~ f --------------------
     def solve(self, f):
         f = np.asarray(f)

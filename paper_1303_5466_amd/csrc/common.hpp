@@ -298,7 +298,9 @@ void launch_permute(double* dst, const double* src, const int64_t* perm, int64_t
                     int width, int to_grid, hipStream_t s);
 void launch_axpy_resid(double* r, const double* f, const double* Ax, int64_t n, hipStream_t s);
 void launch_add(double* x, const double* d, int64_t n, hipStream_t s);
-void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, hipStream_t s);
+// squared norms of ncols columns of length n; ws: COLNORM_WS_PER_COL * ncols doubles
+constexpr int COLNORM_WS_PER_COL = 128;
+void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, double* ws, hipStream_t s);
 void launch_check_finite(const double* x, int64_t n, int* flag, hipStream_t s);
 // contrast scaling and complex plane split / merge around the factored
 // system (k_solve.hip)

@@ -3050,7 +3050,7 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
         // grid-ordered work vectors fg, xg, rg, dg, ax and the plane blocks R, X
         if (!sp.refine_work.p) {
             sp.refine_work.alloc(7 * tot * sizeof(double));
-            sp.refine_norms.alloc(2 * nrhs * sizeof(double));
+            sp.refine_norms.alloc((2 + COLNORM_WS_PER_COL) * nrhs * sizeof(double));
         }
         double* fg = sp.refine_work.as<double>();
         double* xg = fg + tot;
@@ -3073,7 +3073,8 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
         inv(fg, xg);
         if (f.max_refine > 0) {
             DevBuf& nb = sp.refine_norms;
-            launch_col_norms2(nb.as<double>(), fg, f.N * w, (int)nrhs, s);
+            double* nws = nb.as<double>() + 2 * nrhs;       // the norms' partial sums
+            launch_col_norms2(nb.as<double>(), fg, f.N * w, (int)nrhs, nws, s);
             std::vector<double> fn(nrhs), rn(nrhs);
             RSD_HIP(hipMemcpyAsync(fn.data(), nb.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
             int it = 0;
@@ -3081,7 +3082,7 @@ static rsd_status solve(Factor& f, const double* rhs, int64_t nrhs, double* x, r
             for (;;) {
                 matvec_grid(f, xg, ax, (int)nrhs);
                 launch_axpy_resid(rg, fg, ax, tot, s);
-                launch_col_norms2(nb.as<double>() + nrhs, rg, f.N * w, (int)nrhs, s);
+                launch_col_norms2(nb.as<double>() + nrhs, rg, f.N * w, (int)nrhs, nws, s);
                 RSD_HIP(hipMemcpyAsync(rn.data(), nb.as<double>() + nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
                 RSD_HIP(hipStreamSynchronize(s));
                 finite_check_failed(f);

@@ -123,19 +123,41 @@ __global__ void add_kernel(double* __restrict__ x, const double* __restrict__ d,
 }
 
 // out[c] = sum_i x[i + c*n]^2, one workgroup per column (fixed reduction order)
-__global__ void __launch_bounds__(256) colnorm_kernel(double* __restrict__ out,
-                                                      const double* __restrict__ x, int64_t n) {
-    __shared__ double red[256];
-    const double* col = x + blockIdx.x * n;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += col[i] * col[i];
+// Squared column norms in two passes with a fixed summation order (the
+// refinement's convergence test gives the same decision on every run):
+// pass 1, COLNORM_PARTS workgroups per column, each a contiguous part;
+// pass 2, one workgroup per column adds the parts.
+constexpr int COLNORM_PARTS = COLNORM_WS_PER_COL;
+static_assert(COLNORM_PARTS <= 256, "one partial per thread of the summing workgroup");
+
+__device__ inline double block_sum256(double s, double* red) {
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+    return red[0];
+}
+
+__global__ void __launch_bounds__(256) colnorm_part_kernel(double* __restrict__ part,
+                                                           const double* __restrict__ x, int64_t n) {
+    __shared__ double red[256];
+    const double* col = x + blockIdx.y * n;
+    const int64_t len = (n + COLNORM_PARTS - 1) / COLNORM_PARTS;
+    const int64_t i0 = blockIdx.x * len, i1 = min(n, i0 + len);
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += col[i] * col[i];
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0) part[blockIdx.y * COLNORM_PARTS + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) colnorm_sum_kernel(double* __restrict__ out,
+                                                          const double* __restrict__ part) {
+    __shared__ double red[256];
+    const double s = threadIdx.x < COLNORM_PARTS ? part[blockIdx.x * COLNORM_PARTS + threadIdx.x] : 0.0;
+    const double t = block_sum256(s, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // Right-hand side of the factored system from a grid-ordered one (N x nrhs,
@@ -233,8 +255,10 @@ void launch_axpy_resid(double* r, const double* f, const double* Ax, int64_t n, 
 void launch_add(double* x, const double* d, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(add_kernel, dim3(chunks(n)), dim3(256), 0, s, x, d, n);
 }
-void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, hipStream_t s) {
-    hipLaunchKernelGGL(colnorm_kernel, dim3(ncols), dim3(256), 0, s, out, x, n);
+void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, double* ws, hipStream_t s) {
+    if (ncols <= 0) return;
+    hipLaunchKernelGGL(colnorm_part_kernel, dim3(COLNORM_PARTS, ncols), dim3(256), 0, s, ws, x, n);
+    hipLaunchKernelGGL(colnorm_sum_kernel, dim3(ncols), dim3(256), 0, s, out, ws);
 }
 void launch_scale_split(double* R, const double* f, const double* sb, int64_t N, int nrhs, int cplx,
                         hipStream_t s) {

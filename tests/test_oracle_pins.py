@@ -315,3 +315,82 @@ def test_planted_mistakes_are_caught(monkeypatch):
     bad = rskel.RSkel(pts, None, tol=1e-10).solve(f)
     assert dense.rel_error(bad, good) > 1e-6
     assert dense.rel_error(rs.solve(f), good) < 1e-10
+
+
+# --- compressed forward product (Sec. 2.3) --------------------------------------
+@pytest.mark.parametrize("nx,ny,tol", [(32, 32, 1e-10), (64, 64, 1e-10), (40, 24, 1e-6)])
+def test_forward_matvec_matches_direct_sum(nx, ny, tol):
+    """The skeletonization's own product L A~ R + D against the exact direct
+    sum: error at the interpolation tolerance."""
+    pts = W.grid_points(nx, ny)
+    a = W.coef_sine(pts)
+    R = rskel.RSkel(pts, a, tol)
+    x = W.rhs_normal(len(pts), 2, 3)
+    y = R.forward_matvec(x)
+    yd = nystrom.matvec_direct(pts, x, a)
+    assert np.linalg.norm(y - yd) <= 10 * tol * np.linalg.norm(yd)
+
+
+def test_forward_matvec_helmholtz_contrast():
+    pts = W.grid_points(32)
+    b = W.contrast_bump(pts)
+    R = rskel.RSkel(pts, None, 1e-10, kind="helmholtz", k=W.SCATTER_K, bvec=b)
+    x = W.rhs_complex_normal(len(pts), 1, 5)
+    y = R.forward_matvec(x)
+    yd = nystrom.matvec_direct(pts, x, None, "helmholtz", W.SCATTER_K, b)
+    assert np.linalg.norm(y - yd) <= 1e-9 * np.linalg.norm(yd)
+
+
+def test_forward_matvec_single_box_is_exact():
+    pts = W.grid_points(8)
+    R = rskel.RSkel(pts, None, 1e-10)
+    x = W.rhs_normal(64, 1, 1)
+    yd = nystrom.matvec_direct(pts, x)
+    assert np.linalg.norm(R.forward_matvec(x) - yd) <= 1e-14 * np.linalg.norm(yd)
+
+
+def test_forward_matvec_is_symmetric():
+    """D and A~ are symmetric and the down pass uses R^T, so the compressed
+    operator is exactly symmetric (complex symmetric: no conjugation)."""
+    pts = W.grid_points(32, 24)
+    for kind, k, b in (("laplace", 0.0, None), ("helmholtz", W.SCATTER_K, W.contrast_bump(W.grid_points(32, 24)))):
+        R = rskel.RSkel(pts, None, 1e-8, kind=kind, k=k, bvec=b)
+        rng = np.random.default_rng(7)
+        u, v = rng.standard_normal(len(pts)), rng.standard_normal(len(pts))
+        hu, hv = R.forward_matvec(u), R.forward_matvec(v)
+        assert abs(u @ hv - v @ hu) <= 1e-13 * abs(u @ hv)
+
+
+def test_forward_matvec_planted_mistakes_are_caught(monkeypatch):
+    """Dropping the sibling blocks of one level, or a sign slip in the
+    interpolation, is far outside the tolerance."""
+    pts = W.grid_points(32)
+    R = rskel.RSkel(pts, None, 1e-10)
+    x = W.rhs_normal(len(pts), 1, 9)
+    yd = nystrom.matvec_direct(pts, x)
+    good = R.forward_matvec(x)
+    assert np.linalg.norm(good - yd) <= 1e-9 * np.linalg.norm(yd)
+    orig_A = rskel.RSkel.A
+    lv = R.levels[2]
+    sk_sets = {tuple(c.act[c.sk]) for b in lv for c in b.children}
+
+    def A_drop(self, rows, cols):
+        M = orig_A(self, rows, cols)
+        if tuple(rows) in sk_sets and tuple(cols) in sk_sets and not np.array_equal(rows, cols):
+            return 0 * M
+        return M
+    monkeypatch.setattr(rskel.RSkel, "A", A_drop)
+    bad = R.forward_matvec(x)
+    monkeypatch.setattr(rskel.RSkel, "A", orig_A)
+    assert np.linalg.norm(bad - yd) > 1e-4 * np.linalg.norm(yd)
+    saved = {id(b): b.R for lev in R.levels[1:] for b in lev}
+    for lev in R.levels[1:]:
+        for b in lev:
+            T = b.R[:, b.rs]
+            b.R = b.R.copy()
+            b.R[:, b.rs] = -T
+    bad2 = R.forward_matvec(x)
+    for lev in R.levels[1:]:
+        for b in lev:
+            b.R = saved[id(b)]
+    assert np.linalg.norm(bad2 - yd) > 1e-4 * np.linalg.norm(yd)
