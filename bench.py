@@ -235,6 +235,37 @@ def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, side
             "factors_built": st["n_built"], "wall_s": t_all}
 
 
+def compressed_product_measure(torch, rsd, W, reps=10):
+    """The factor's compressed forward product (recursive-skeleton form of A,
+    O(N) work) against the exact FFT product on the 256^2 workload's factor:
+    device buffers, 1 and 16 right-hand sides, median over reps; relative
+    difference of the two products."""
+    pts, a, f, tol = W.make_workload("laplace256")
+    dev = torch.device("cuda:0")
+    fac = rsd.Factor(torch.from_numpy(pts).to(dev), torch.from_numpy(a).to(dev), tol)
+    out = {"workload": "laplace256 factor (float64, tol 1e-10), x ~ N(0,1)"}
+    for nrhs in (1, 16):
+        x = torch.from_numpy(np.ascontiguousarray(W.rhs_normal(len(pts), nrhs, 3).T)).to(dev)
+        ye, yc = torch.empty_like(x), torch.empty_like(x)
+        times = {}
+        for key, fn, y in (("exact_ms", fac.matvec_raw, ye), ("compressed_ms", fac.matvec_compressed_raw, yc)):
+            fn(x.data_ptr(), nrhs, y.data_ptr())
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = fn(x.data_ptr(), nrhs, y.data_ptr())
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                if st != rsd.RSD_OK:
+                    raise rsd.RsdError(st, rsd.load().rsd_last_error().decode())
+            times[key] = 1e3 * float(np.median(ts))
+        rel = float(torch.linalg.norm(yc - ye) / torch.linalg.norm(ye))
+        out[f"nrhs{nrhs}"] = {**times, "rel_diff": rel}
+    fac.close()
+    return out
+
+
 def measure(torch, rsd, W, workload, precision, steps, warmup, fp32_interp=False, latency_solves=30,
             tol=None, with_breakdown=True):
     """Timed factor + solve steps of one workload (inputs resident in HBM).
@@ -456,6 +487,12 @@ def main():
     if not args.no_accuracy and args.workload == "laplace256":
         log("accuracy ratio study: tol 1e-5 vs 1e-10 ...")
         out["accuracy_ratio"] = accuracy_ratio(torch, rsd, W)
+        log("compressed forward product vs the exact product ...")
+        out["compressed_product"] = compressed_product_measure(torch, rsd, W)
+        for key in ("nrhs1", "nrhs16"):
+            r = out["compressed_product"][key]
+            log(f"  {key}: compressed {r['compressed_ms']:.3f} ms, exact {r['exact_ms']:.3f} ms, "
+                f"difference {r['rel_diff']:.1e}")
     if not args.no_batched and args.workload == "laplace256":
         log("batched builds: 64 grids of uneven size ...")
         out["batched"] = batched_measure(torch, rsd, W)

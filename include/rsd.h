@@ -238,6 +238,20 @@ rsd_status rsd_tune_load(const char* path);
 /* Empties the table (builds use the built-in rule again). */
 rsd_status rsd_tune_clear(int64_t* n_entries_before);
 
+/* y ~ A x through the factor's own skeletonization (Sec. 2.3: the matrix in
+ * recursive-skeleton form, A = D + L A~ R telescoped over the tree), in O(N)
+ * work: skeleton charges x^ = x_sk + T x_rs up the tree, at every box above
+ * the leaves the kernel block between its two children's skeletons applied
+ * to the sibling's charges (kernel values generated on the fly), the
+ * potentials spread down as [p; T^T p], and the dense leaf blocks.  Accurate
+ * to the factor's interpolation (about tol relative; T in float32 on the
+ * float32 levels of an FP32_REFINE factor).  Laplace factors without a
+ * contrast (EINVAL otherwise); same layouts as rsd_matvec (host or device,
+ * caller's point order); work space 2 N nrhs + 3 V nrhs doubles (V: the
+ * total active-set length over the boxes, about 2 N), allocated per call;
+ * returns after the factor's stream completes. */
+rsd_status rsd_matvec_compressed(rsd_factor* f, const double* x, int64_t nrhs, double* y);
+
 /* rsd_matvec without any device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Same product and result as rsd_matvec; x and y

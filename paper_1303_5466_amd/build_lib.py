@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librsd.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["plan.cpp", "driver.cpp", "k_gemm.hip", "k_gen.hip", "k_gj.hip", "k_qr.hip",
-           "k_solve.hip", "k_matvec.hip", "k_fft.hip", "server.cpp"]
+           "k_solve.hip", "k_matvec.hip", "k_fft.hip", "k_hmatvec.hip", "server.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -298,6 +298,25 @@ void launch_permute(double* dst, const double* src, const int64_t* perm, int64_t
                     int width, int to_grid, hipStream_t s);
 void launch_axpy_resid(double* r, const double* f, const double* Ax, int64_t n, hipStream_t s);
 void launch_add(double* x, const double* d, int64_t n, hipStream_t s);
+// compressed forward product (k_hmatvec.hip): charges up, sibling blocks
+// across, potentials down, dense leaf blocks; float64 vectors, T in its
+// level's precision
+template <typename TT>
+void launch_hmv_up(const double* X, double* Xpar, const TT* Tarena, int nrhs, const BoxDev* boxes, const int* ids,
+                   int n_boxes, const LayoutDev* layouts, const int* inv, int max_k, hipStream_t s);
+void launch_hmv_sibling(double* Pot, const double* Xpar, int nrhs, const BoxDev* boxes, const int* ids, int n_boxes,
+                        const LayoutDev* layouts, const int* lu, const int* lv, const int* inv, int max_kk,
+                        const KernelDesc& kd, hipStream_t s);
+template <typename TT>
+void launch_hmv_spread(double* Y, const double* Pot, const TT* Tarena, int nrhs, const BoxDev* boxes,
+                       const int* ids, int n_boxes, const LayoutDev* layouts, int max_m, hipStream_t s);
+void launch_hmv_push(double* Pot, const double* Ypar, int nrhs, const BoxDev* boxes, const int* ids, int n_boxes,
+                     const LayoutDev* layouts, const int* inv, int max_k, hipStream_t s);
+template <typename TT>
+void launch_hmv_leaf(double* y, int64_t ldy, const double* X, const double* Pot, const TT* Tarena, int nrhs,
+                     const BoxDev* boxes, const int* ids, int n_boxes, const LayoutDev* layouts, const int* lu,
+                     const int* lv, const int64_t* perm, int max_m, const KernelDesc& kd, hipStream_t s);
+
 // squared norms of ncols columns of length n; ws: COLNORM_WS_PER_COL * ncols doubles
 constexpr int COLNORM_WS_PER_COL = 128;
 void launch_col_norms2(double* out, const double* x, int64_t n, int ncols, double* ws, hipStream_t s);

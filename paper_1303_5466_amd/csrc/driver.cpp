@@ -3133,6 +3133,86 @@ static void matvec(Factor& f, const double* xin, int64_t nrhs, double* y) {
     RSD_HIP(hipStreamSynchronize(s));
 }
 
+// ---- the compressed forward product (Sec. 2.3) ----------------------------------
+// y ~ A x through the factor's skeletonization: charges up the tree, sibling
+// blocks across, potentials down, the dense leaf blocks at the bottom (see
+// k_hmatvec.hip).  O(N) work; accurate to the factor's interpolation.
+static void matvec_compressed(Factor& f, const double* xin, int64_t nrhs, double* y) {
+    std::lock_guard<std::mutex> use(f.use_mu);
+    if (nrhs < 0 || !xin || !y) throw Error(RSD_EINVAL, "bad matvec arguments");
+    if (f.cplx || f.kd.has_b || f.kd.type != 0)
+        throw Error(RSD_EINVAL, "the compressed product is built for Laplace factors without a contrast");
+    if (nrhs == 0) return;
+    if (nrhs > 4096) throw Error(RSD_EINVAL, "nrhs > 4096");
+    RSD_HIP(hipSetDevice(f.device));
+    hipStream_t s = f.stream;
+    const Plan& P = f.plan;
+    const int nlev = (int)P.levels.size();
+    const int64_t tot = f.N * nrhs;
+    // box offsets count separately on float32 and float64 levels (as in the
+    // solve's arenas): float32-level boxes first, float64-level ones after
+    int64_t v[2] = {0, 0};
+    for (auto& b : f.hboxes) v[f.level_prec[b.level]] += b.k + b.r;
+    const int64_t varena = std::max<int64_t>(v[0] + v[1], 1) * nrhs;
+    DevBuf buf;
+    buf.alloc((2 * tot + 3 * varena) * sizeof(double));
+    double* xi = buf.as<double>();
+    double* yo = xi + tot;
+    double* X = yo + tot;
+    double* Y = X + varena;
+    double* Pot = Y + varena;
+    const bool xdev = is_device_ptr(xin), ydev = is_device_ptr(y);
+    RSD_HIP(hipMemcpyAsync(xi, xin, tot * sizeof(double), xdev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    RSD_HIP(hipMemsetAsync(Pot, 0, varena * sizeof(double), s));
+    const BoxDev* B = f.d_boxes.as<BoxDev>();
+    const LayoutDev* LD = f.d_layouts.as<LayoutDev>();
+    const int* lu = f.d_lu.as<int>();
+    const int* lv = f.d_lv.as<int>();
+    const int* inv = f.d_inv.as<int>();
+    const int64_t* perm = f.d_perm.as<int64_t>();
+    auto nb = [&](int t) { return (int)P.levels[t].size(); };
+    auto maxk = [&](int t) { int m = 0; for (int id : P.levels[t]) m = std::max(m, f.hboxes[id].k); return m; };
+    auto maxm = [&](int t) { int m = 0; for (int id : P.levels[t]) m = std::max(m, f.hboxes[id].k + f.hboxes[id].r); return m; };
+    auto maxkk = [&](int t) {   // children's skeletons of a parent level
+        int m = 0;
+        for (int id : P.levels[t]) {
+            const Box& b = P.boxes[id];
+            if (b.child[0] >= 0) m = std::max(m, P.boxes[b.child[0]].k + P.boxes[b.child[1]].k);
+        }
+        return m;
+    };
+    // base of a level's boxes in each arena
+    const int64_t o64 = v[1] * nrhs;
+    auto at = [&](double* arena, int t) { return arena + (f.level_prec[t] ? 0 : o64); };
+    launch_gather_leaf<double, double>(at(X, 0), xi, f.N, (int)nrhs, B, f.ids(0), nb(0), LD, lu, lv, perm, f.ny, 0,
+                                       maxm(0), s);
+    for (int t = 0; t < f.top; ++t) {   // charges up
+        if (f.level_prec[t])
+            launch_hmv_up<float>(at(X, t), at(X, t + 1), Tbase<float>(f), (int)nrhs, B, f.ids(t), nb(t), LD, inv,
+                                 maxk(t), s);
+        else
+            launch_hmv_up<double>(at(X, t), at(X, t + 1), Tbase<double>(f), (int)nrhs, B, f.ids(t), nb(t), LD, inv,
+                                  maxk(t), s);
+    }
+    for (int t = 1; t < nlev; ++t)      // sibling blocks across
+        launch_hmv_sibling(at(Pot, t - 1), at(X, t), (int)nrhs, B, f.ids(t), nb(t), LD, lu, lv, inv, maxkk(t), f.kd, s);
+    for (int t = f.top - 1; t >= 1; --t) {   // potentials down
+        if (f.level_prec[t])
+            launch_hmv_spread<float>(at(Y, t), at(Pot, t), Tbase<float>(f), (int)nrhs, B, f.ids(t), nb(t), LD, maxm(t), s);
+        else
+            launch_hmv_spread<double>(at(Y, t), at(Pot, t), Tbase<double>(f), (int)nrhs, B, f.ids(t), nb(t), LD, maxm(t), s);
+        launch_hmv_push(at(Pot, t - 1), at(Y, t), (int)nrhs, B, f.ids(t - 1), nb(t - 1), LD, inv, maxk(t - 1), s);
+    }
+    if (f.level_prec[0])
+        launch_hmv_leaf<float>(yo, f.N, at(X, 0), at(Pot, 0), Tbase<float>(f), (int)nrhs, B, f.ids(0), nb(0), LD, lu,
+                               lv, perm, maxm(0), f.kd, s);
+    else
+        launch_hmv_leaf<double>(yo, f.N, at(X, 0), at(Pot, 0), Tbase<double>(f), (int)nrhs, B, f.ids(0), nb(0), LD,
+                                lu, lv, perm, maxm(0), f.kd, s);
+    RSD_HIP(hipMemcpyAsync(y, yo, tot * sizeof(double), ydev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    RSD_HIP(hipStreamSynchronize(s));
+}
+
 // ---- the exact product without device allocations ---------------------------
 // Work space of rsd_matvec_noalloc: the grid-ordered copies of x and y, the
 // circulant spectrum and the FFT field (or the direct sum's kernel table), in
@@ -3452,6 +3532,14 @@ rsd_status rsd_matvec(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
     return guarded([&]() {
         if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
         rsd::matvec(*f->impl, x, nrhs, y);
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_matvec_compressed(rsd_factor* f, const double* x, int64_t nrhs, double* y) {
+    return guarded([&]() {
+        if (!f) throw rsd::Error(RSD_EINVAL, "factor is null");
+        rsd::matvec_compressed(*f->impl, x, nrhs, y);
         return RSD_OK;
     });
 }

@@ -125,6 +125,7 @@ EXPORTS = {
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "rsd_factor_get_stats": (C.c_int, [C.c_void_p, C.POINTER(rsd_factor_stats)]),
     "rsd_factor_box_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_box_info)]),
+    "rsd_matvec_compressed": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "rsd_factor_interp_info": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(rsd_interp_info)]),
     "rsd_factor_get_block": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "rsd_plan_create": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
@@ -299,6 +300,15 @@ class Factor:
         _check(st)
         return (X[:, 0] if vec else X), info
 
+    def matvec_compressed(self, x):
+        """y ~ A x through the factor's skeletonization (O(N), at the factor's
+        tolerance); NumPy (N,) / (N, nrhs) in and out, Laplace factors."""
+        vec = x.ndim == 1
+        X = np.asfortranarray(np.asarray(x, dtype=np.float64).reshape(self.n, -1))
+        Y = np.zeros_like(X, order="F")
+        _check(load().rsd_matvec_compressed(self._h, X.ctypes.data, X.shape[1], Y.ctypes.data))
+        return Y[:, 0] if vec else Y
+
     def matvec(self, x):
         vec = x.ndim == 1
         dt = np.complex128 if self.complex else np.float64
@@ -306,6 +316,14 @@ class Factor:
         Y = np.zeros_like(X, order="F")
         _check(load().rsd_matvec(self._h, X.ctypes.data, X.shape[1], Y.ctypes.data))
         return Y[:, 0] if vec else Y
+
+    def matvec_raw(self, x_ptr, nrhs, y_ptr):
+        """rsd_matvec on device (or host) pointers; returns the status."""
+        return load().rsd_matvec(self._h, x_ptr, nrhs, y_ptr)
+
+    def matvec_compressed_raw(self, x_ptr, nrhs, y_ptr):
+        """rsd_matvec_compressed on device (or host) pointers; returns the status."""
+        return load().rsd_matvec_compressed(self._h, x_ptr, nrhs, y_ptr)
 
     def matvec_noalloc_raw(self, x_ptr, nrhs, y_ptr):
         """rsd_matvec_noalloc on device pointers (N x nrhs column-major);

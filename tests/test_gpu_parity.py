@@ -751,6 +751,50 @@ def test_complex_solve_sweeps_as_graph():
     fe.close()
 
 
+# --- compressed forward product (Sec. 2.3) ---------------------------------------
+@pytest.mark.parametrize("nx,ny,tol,precision", [(64, 64, 1e-10, rsd.RSD_PREC_FP64),
+                                                 (50, 40, 1e-10, rsd.RSD_PREC_FP64),
+                                                 (37, 37, 1e-6, rsd.RSD_PREC_FP64),
+                                                 (256, 256, 1e-10, rsd.RSD_PREC_FP64),
+                                                 (128, 128, 1e-10, rsd.RSD_PREC_FP32_REFINE),
+                                                 (8, 8, 1e-10, rsd.RSD_PREC_FP64)])
+def test_compressed_product_matches_exact(nx, ny, tol, precision):
+    # the factor's own recursive-skeleton product against the exact product
+    # (FFT, float64) and, at sizes the reference finishes, against the
+    # reference's compressed product (same skeletons, same T up to rounding
+    # where the interpolation problems are full rank)
+    pts = W.grid_points(nx, ny)
+    a = W.coef_sine(pts)
+    fac = rsd.Factor(pts, a, tol, precision=precision)
+    x = W.rhs_normal(len(pts), 3, nx + ny)
+    yc = fac.matvec_compressed(x)
+    ye = fac.matvec(x)
+    rel = np.linalg.norm(yc - ye) / np.linalg.norm(ye)
+    bound = 1e-6 if precision == rsd.RSD_PREC_FP32_REFINE else (1e-14 if nx * ny <= 64 else 10 * tol)
+    print(f"{nx}x{ny} tol {tol:g}: compressed vs exact {rel:.2e}")
+    assert rel <= bound
+    if len(pts) <= 4096 and precision == rsd.RSD_PREC_FP64:
+        R = rskel.RSkel(pts, a, tol)
+        yo = R.forward_matvec(x)
+        dr = np.linalg.norm(yc - yo) / np.linalg.norm(yo)
+        print(f"  vs the reference's compressed product {dr:.2e}")
+        assert dr <= (1e-12 if tol <= 1e-10 else 1e-6)
+    fac.close()
+
+
+def test_compressed_product_arguments():
+    pts = W.grid_points(32)
+    b = W.contrast_bump(pts)
+    fh = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=W.SCATTER_K, contrast=b)
+    with pytest.raises(rsd.RsdError) as e:
+        fh.matvec_compressed(np.ones(len(pts)))
+    assert e.value.status == rsd.RSD_EINVAL
+    fh.close()
+    fl = rsd.Factor(pts, None, 1e-10)
+    assert np.array_equal(fl.matvec_compressed(np.zeros((len(pts), 0))), np.zeros((len(pts), 0)))
+    fl.close()
+
+
 # --- symmetry split of the interpolation problems ------------------------------------
 def test_symmetry_split_matches_whole_problems():
     pts = W.grid_points(64)
