@@ -176,7 +176,7 @@ def serving_scatter_measure(torch, rsd, W, seconds=3.0, rate=200.0, seed=4, side
     c64 = bulk == "c64"
     rng = np.random.default_rng(seed)
     dev = torch.device("cuda:0")
-    srv = rsd.Server(n_workers=2, max_coalesce=64)
+    srv = rsd.Server(n_workers=2, max_coalesce=64, mem_budget=64 << 30)
     fids, sizes = [], []
     t0 = time.perf_counter()
     for n in sides:
@@ -504,9 +504,10 @@ def main():
         sv = out["serving"]
         log(f"  {sv['requests']} requests, p50 {sv['p50_ms']:.2f} ms, p99 {sv['p99_ms']:.2f} ms, "
             f"{sv['mean_batch_rhs']:.2f} RHS per coalesced solve")
-        for key, bulk in (("serving_scatter", "c64"), ("serving_scatter_c128", "c128")):
-            log(f"served scattering workload ({bulk} factors): Helmholtz Lippmann-Schwinger factors + Poisson solves ...")
-            out[key] = serving_scatter_measure(torch, rsd, W, bulk=bulk)
+        for key, bulk, sides in (("serving_scatter", "c64", (128, 256)), ("serving_scatter_c128", "c128", (128, 256, 512))):
+            log(f"served scattering workload ({bulk} factors, sides {sides}): Helmholtz Lippmann-Schwinger factors "
+                f"+ Poisson solves ...")
+            out[key] = serving_scatter_measure(torch, rsd, W, bulk=bulk, sides=sides)
             sv = out[key]
             log(f"  {sv['requests']} requests ({sv['failed']} failed), p50 {sv['p50_ms']:.2f} ms, "
                 f"p99 {sv['p99_ms']:.2f} ms, residual {sv['max_rel_residual']:.1e}")

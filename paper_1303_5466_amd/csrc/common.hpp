@@ -192,7 +192,7 @@ constexpr int QR_NB = 16;     // largest sub-panel width
 constexpr int QR_WIN = 64;    // pivoting window / block width of the trailing update
 constexpr int QR_RC = 256;    // row chunk of the split-K reflector products
 struct QRProblemDev {
-    int p, k, r, nb;   // nb: sub-panel width (16, 8, 4 or 2 by the LDS budget)
+    int p, k, r, nb;   // nb: sub-panel width (16, 8, 4, 2 or 1 by the LDS budget)
     int pz;            // rows holding the proxy kernel; rows pz .. p - 1 the damping rows (k or none)
     int sec;           // -1, or the symmetry sector (0..3) this problem solves
     int staged;        // 0: T goes to the T arena; 1: to the staging arena (sector, or another precision)

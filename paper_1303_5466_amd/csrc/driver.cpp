@@ -641,18 +641,21 @@ struct GemmBatch {
     // dispatch.
     void finalize() {
         constexpr int CUS = 256;
-        // the kernel addresses each operand with 32-bit byte offsets
-        auto extent = [](int rows, int cols, int ld, int tr) {
+        // the kernel addresses each operand with 32-bit byte offsets from the
+        // tile's first row / column (at most 128 of them, all of K)
+        auto reach = [](int rows, int cols, int ld, int tr) {
             if (rows <= 0 || cols <= 0) return (int64_t)0;
+            rows = std::min(rows, 128);   // rows: the tile's dimension; cols: K
             return (int64_t)sizeof(T) * ((tr ? (int64_t)(cols - 1) + (int64_t)(rows - 1) * ld
                                              : (int64_t)(rows - 1) + (int64_t)(cols - 1) * ld) + 1);
         };
         for (auto& d : descs) {
-            int64_t e = std::max(extent(d.M, d.K, d.lda, d.tA), extent(d.K, d.N, d.ldb, d.tB));
-            if (d.K2 > 0) e = std::max({e, extent(d.M, d.K2, d.lda2, d.tA2), extent(d.K2, d.N, d.ldb2, d.tB2)});
-            e = std::max(e, extent(d.M, d.N, d.ldc, 0));
+            // A is M x K (tA: stored K x M), B is K x N (tB: stored N x K)
+            int64_t e = std::max(reach(d.M, d.K, d.lda, d.tA), reach(d.N, d.K, d.ldb, !d.tB));
+            if (d.K2 > 0) e = std::max({e, reach(d.M, d.K2, d.lda2, d.tA2), reach(d.N, d.K2, d.ldb2, !d.tB2)});
+            e = std::max(e, reach(std::min(d.M, 128), std::min(d.N, 128), d.ldc, 0));
             if (e + 16 > (int64_t)GEMM_MAX_OPERAND_BYTES)
-                throw Error(RSD_EINVAL, "matrix block too large for the GEMM kernel (2 GiB operand limit)");
+                throw Error(RSD_EINVAL, "matrix block too large for the GEMM kernel (2 GiB reach of a tile)");
         }
         tiles.clear();
         slots.clear();
@@ -864,9 +867,10 @@ constexpr int GJ_NB = 64;   // Gauss-Jordan panel width (matches k_gj)
 // The Gauss-Jordan kernel addresses its block with 32-bit byte offsets.
 template <typename T>
 static void check_gj_block(const GJDesc<T>& g) {
-    const int64_t bytes = (int64_t)sizeof(T) * ((int64_t)(g.n - 1) + (int64_t)(g.ncols - 1) * g.ld + 1);
+    // the pivot kernel addresses 64 rows x 64 columns from one descriptor base
+    const int64_t bytes = (int64_t)sizeof(T) * ((int64_t)GJ_NB + (int64_t)GJ_NB * g.ld);
     if (bytes + 16 > (int64_t)GEMM_MAX_OPERAND_BYTES)
-        throw Error(RSD_EINVAL, "matrix block too large for the Gauss-Jordan kernel (2 GiB limit)");
+        throw Error(RSD_EINVAL, "matrix block too large for the Gauss-Jordan kernel (leading dimension)");
 }
 
 // ----------------------------------------------------------------------------
@@ -1142,8 +1146,9 @@ struct QRChain {
     int comb_max_kr = 0;
     std::vector<GemmBatch<T>> g1, gt, g2;
     std::vector<std::vector<GemmBatch<T>>> gsolve;
-    std::vector<int> lists[4];
-    int off[4] = {0, 0, 0, 0}, maxp[4] = {0, 0, 0, 0};
+    static constexpr int NWIDTH = 5;   // sub-panel width classes 16, 8, 4, 2, 1
+    std::vector<int> lists[NWIDTH];
+    int off[NWIDTH] = {0, 0, 0, 0, 0}, maxp[NWIDTH] = {0, 0, 0, 0, 0};
     std::vector<int> sflat, soff;
     bool any_damp = false;
     double flops = 0, bytes = 0;
@@ -1420,7 +1425,7 @@ struct QRChain {
         for (auto* b : all) b->max_split = 1;
         upload_batches<T>(dgemm, all, s);
         // sub-panel width classes
-        const int widths[4] = {16, 8, 4, 2};
+        const int widths[NWIDTH] = {16, 8, 4, 2, 1};
         for (int i = 0; i < np; ++i) {
             int c = 0;
             while (widths[c] != qp[i].nb) ++c;
@@ -1428,7 +1433,7 @@ struct QRChain {
             maxp[c] = std::max(maxp[c], qp[i].p);
         }
         std::vector<int> flat;
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NWIDTH; ++c) {
             off[c] = (int)flat.size();
             flat.insert(flat.end(), lists[c].begin(), lists[c].end());
             if (!lists[c].empty()) max_subs = std::max(max_subs, QR_WIN / widths[c]);
@@ -1471,12 +1476,12 @@ struct QRChain {
         T* aux = daux->as<T>();
         int* iaux = diaux->as<int>();
         const QRProblemDev* q = q_dev;
-        const int widths[4] = {16, 8, 4, 2};
+        const int widths[NWIDTH] = {16, 8, 4, 2, 1};
         launch_qr_select<T>(Ab, aux, iaux, W, q, np, sw, max_k, s);
         launch_qr_move<T>(Ab, iaux, W, q, np, 0, s);
         launch_qr_move<T>(Ab, iaux, W, q, np, 1, s);
         for (int sub = 0; sub < max_subs; ++sub)
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < NWIDTH; ++c) {
                 if (lists[c].empty() || sub * widths[c] >= QR_WIN) continue;
                 launch_qr_panel<T>(Ab, aux, iaux, W, q, list_dev + off[c], (int)lists[c].size(),
                                    widths[c], maxp[c], sw, sub, s);

@@ -78,8 +78,9 @@ struct Cfg {
 // Loads go through buffer instructions: an element outside the product
 // (row or column past M / N, k past K) gets an offset past the descriptor's
 // range, for which the hardware returns zero, so the masked loads need no
-// branches.  Offsets are 32-bit bytes from the operand's base pointer; the
-// host keeps every operand's extent below RSRC_RANGE, and a masked element's
+// branches.  Offsets are 32-bit bytes from a base pointer moved to the tile's
+// first row / column (so an operand may exceed 2 GiB); the host keeps what
+// one tile reaches from there below RSRC_RANGE, and a masked element's
 // offset is RSRC_RANGE itself, the first out-of-range byte.
 constexpr int RSRC_RANGE = 0x7ffffff0;
 constexpr int OFF_MASKED = RSRC_RANGE;
@@ -122,10 +123,12 @@ __device__ inline PlanOf<T, TILE> panel_plan(const T* X, int ld, bool along_rows
     constexpr int BK = C_::BK, LD = C_::LD;
     const int t = threadIdx.x;
     PlanOf<T, TILE> P;
-    P.rs = __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, RSRC_RANGE, RSRC_WORD3);
+    // the tile's first row (column) as the descriptor's base
+    const T* Xb = along_rows ? X + base : X + (int64_t)base * ld;
+    P.rs = __builtin_amdgcn_make_buffer_rsrc((void*)Xb, (short)0, RSRC_RANGE, RSRC_WORD3);
     if (along_rows) {   // element (i = t % TILE, kk = t / TILE + q 256 / TILE)
         const int i = t % TILE, kk = t / TILE;
-        P.off0 = base + i + kk * ld;
+        P.off0 = i + kk * ld;
         P.qs = (256 / TILE) * ld;
         P.ps = BK * ld;
         P.r0 = base + i; P.rq = 0; P.rmax = lim;
@@ -137,7 +140,7 @@ __device__ inline PlanOf<T, TILE> panel_plan(const T* X, int ld, bool along_rows
         }
     } else {            // element (kk = t % BK, i = t / BK + q 256 / BK)
         const int kk = t % BK, i = t / BK;
-        P.off0 = kk + (base + i) * ld;
+        P.off0 = kk + i * ld;
         P.qs = (256 / BK) * ld;
         P.ps = BK;
         P.r0 = base + i; P.rq = 256 / BK; P.rmax = lim;
@@ -301,8 +304,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
     const bool use_pre = PREFETCH && tr.nsplit == 1 && d.beta != T(0);
     if constexpr (PREFETCH) {
         if (use_pre) {
-            const __amdgpu_buffer_rsrc_t rc =
-                __builtin_amdgcn_make_buffer_rsrc((void*)d.C, (short)0, RSRC_RANGE, RSRC_WORD3);
+            const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(d.C + row0 + (int64_t)col0 * d.ldc), (short)0, RSRC_RANGE, RSRC_WORD3);
 #pragma unroll
             for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -314,7 +317,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmDesc<T>* __restrict
                         const int gi = row0 + r, gj = col0 + c;
                         const bool ok = (gi < d.M) & (gj < d.N) & !((gj >= d.zc0) & (gj < d.zc1));
                         cpre[(i * NB + j) * 4 + v] =
-                            BufLoad<T>::at(rc, ok ? (gi + gj * d.ldc) * (int)sizeof(T) : OFF_MASKED);
+                            BufLoad<T>::at(rc, ok ? (r + c * d.ldc) * (int)sizeof(T) : OFF_MASKED);
                     }
         }
     }
@@ -405,15 +408,21 @@ __device__ inline void skinny_segment(const T* A, int lda, int tA, const T* B, i
                                       typename Mfma<T>::acc_t& acc) {
     if (ka >= kb) return;
     const int lane = threadIdx.x & 63;
-    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)A, (short)0, RSRC_RANGE, RSRC_WORD3);
-    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void*)B, (short)0, RSRC_RANGE, RSRC_WORD3);
     const int row = row0 + (lane & 15), col = lane & 15, g4 = 4 * (lane >> 4);
     const bool rok = row < M, cok = col < N;
-    // element offsets: A(row, k) and B(k, col) as (base + k * step)
-    const int abase = tA ? row * lda : row, astep = tA ? 1 : lda;
-    const int bbase = tB ? col : col * ldb, bstep = tB ? ldb : 1;
+    // element offsets: A(row, k) and B(k, col) as (base + (k - ka) * step),
+    // from descriptors based at the item's first row and at k = ka
+    const int astep = tA ? 1 : lda, bstep = tB ? ldb : 1;
+    const int abase = tA ? (lane & 15) * lda : (lane & 15);
+    const int bbase = tB ? col : col * ldb;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(A + (tA ? (int64_t)row0 * lda : (int64_t)row0) + (int64_t)ka * astep), (short)0, RSRC_RANGE,
+        RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void*)(B + (int64_t)ka * bstep), (short)0,
+                                                                        RSRC_RANGE, RSRC_WORD3);
     constexpr int SZ = (int)sizeof(T);
-    int k = ka;
+    kb -= ka;
+    int k = 0;
     // whole chunks, two at a time (16 elements in flight per lane)
     for (; k + 32 <= kb; k += 32) {
         T a[2][4], b[2][4];

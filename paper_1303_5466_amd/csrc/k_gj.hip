@@ -24,9 +24,10 @@ namespace {
 constexpr int GJ_NB = 64;
 constexpr int CHUNK = 64;
 
-// Buffer loads from the matrix with 32-bit byte offsets (the host keeps the
-// matrix below GJ_RSRC_RANGE bytes); the offset GJ_RSRC_RANGE itself is out
-// of range and reads zero.
+// Buffer loads from the matrix with 32-bit byte offsets from descriptors based
+// at the pivot block and at the work-group's column chunk (the host keeps the
+// 64 columns such a descriptor reaches below GJ_RSRC_RANGE bytes); the offset
+// GJ_RSRC_RANGE itself is out of range and reads zero.
 constexpr int GJ_RSRC_RANGE = 0x7ffffff0;
 constexpr int GJ_RSRC_WORD3 = 0x00020000;    // raw buffer, 32-bit data format
 
@@ -105,8 +106,10 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
     // every load of the pivot block and of the chunk's pivot rows is issued
     // before the first is used: buffer loads, masked by an out-of-range offset
     // (which reads zero), so that no branch separates them
-    const __amdgpu_buffer_rsrc_t rx =
-        __builtin_amdgcn_make_buffer_rsrc((void*)d.X, (short)0, GJ_RSRC_RANGE, GJ_RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(d.X + j0 + (int64_t)pc0 * d.ld), (short)0, GJ_RSRC_RANGE, GJ_RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(d.X + j0 + (int64_t)c_lo * d.ld), (short)0, GJ_RSRC_RANGE, GJ_RSRC_WORD3);
     T p[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -114,7 +117,7 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         for (int b = 0; b < 4; ++b) {
             const int i = ri + a, j = cj + b;
             const bool ok = (i < nbe) & (j < nbe);
-            p[a][b] = gj_load<T>(rx, ok ? ((j0 + i) + (pc0 + j) * d.ld) * (int)sizeof(T) : GJ_RSRC_RANGE);
+            p[a][b] = gj_load<T>(rp, ok ? (i + j * d.ld) * (int)sizeof(T) : GJ_RSRC_RANGE);
         }
     T xv[GJ_NB * CHUNK / 256];
 #pragma unroll
@@ -122,7 +125,7 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         const int e = t + 256 * u;
         const int q = e & (GJ_NB - 1), c = c_lo + e / GJ_NB;
         const bool ok = (q < nbe) & (c < d.ncols);
-        xv[u] = gj_load<T>(rx, ok ? ((j0 + q) + c * d.ld) * (int)sizeof(T) : GJ_RSRC_RANGE);
+        xv[u] = gj_load<T>(rx, ok ? (q + (c - c_lo) * d.ld) * (int)sizeof(T) : GJ_RSRC_RANGE);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)

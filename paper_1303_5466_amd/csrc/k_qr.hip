@@ -183,13 +183,15 @@ __global__ void __launch_bounds__(256) qr_damp_kernel(T* __restrict__ A, T* __re
 // a bitonic sort in LDS (nsort, a power of two at least the number of
 // candidates, padded with keys below every norm); the first QR_WIN entries
 // are the window, in that order.  The moves are then derived by wave 0.
-template <typename T>
+// K: the sort key type, T, or float where T keys would not fit the LDS (the
+// largest problems; the order then follows the norms rounded to float).
+template <typename T, typename K = T>
 __global__ void __launch_bounds__(256) qr_select_kernel(T* __restrict__ A, T* __restrict__ aux,
                                                          int* __restrict__ iaux, T* __restrict__ ws,
                                                          const QRProblemDev* __restrict__ probs,
                                                          int outer, int nsort) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* key = reinterpret_cast<T*>(smem_raw);
+    K* key = reinterpret_cast<K*>(smem_raw);
     int* idx = reinterpret_cast<int*>(key + nsort);
     const QRProblemDev q = probs[blockIdx.x];
     Aux<T> X(aux, iaux, ws, q);
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(256) qr_select_kernel(T* __restrict__ A, T* __
     const int WO = min(WIN, q.k - J0);
     const int nrem = q.k - J0;
     for (int i = t; i < nsort; i += 256) {
-        key[i] = i < nrem ? X.norms[J0 + i] : T(-1);
+        key[i] = i < nrem ? K(X.norms[J0 + i]) : K(-1);
         idx[i] = i;
     }
     if (t < WIN && J0 + t < q.k) X.tau[J0 + t] = T(0);
@@ -225,7 +227,7 @@ __global__ void __launch_bounds__(256) qr_select_kernel(T* __restrict__ A, T* __
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int e = t; e < (nsort >> 1); e += 256) {
                 const int i = 2 * stride * (e / stride) + (e % stride), j = i + stride;
-                const T ki = key[i], kj = key[j];
+                const K ki = key[i], kj = key[j];
                 const int ii = idx[i], ij = idx[j];
                 // does j belong before i?
                 const bool jfirst = kj > ki || (kj == ki && ij < ii);
@@ -366,9 +368,11 @@ __device__ inline const T* block_sum_n(T (&v)[N], T* red /* [2][RS] */, int& par
 
 // Sub-panel rows in LDS: row-major, W entries per row, the row stride padded
 // to 4 (mod 8) dwords so that 16-byte row reads by consecutive lanes are
-// free of bank conflicts.
+// free of bank conflicts; single columns (W = 1, the largest problems) are
+// read one element per lane and stored unpadded.
 template <typename T, int W>
 constexpr int panel_stride() {
+    if (W == 1) return 1;
     int s = (int)(W * sizeof(T) / 4);
     while (s % 8 != 4) ++s;
     return s * 4 / (int)sizeof(T);
@@ -812,12 +816,14 @@ int qr_panel_width(int p, int elem_bytes) {
         if ((size_t)panel_stride<float, 8>() * p * eb <= LDS_BUDGET) return 8;
         if ((size_t)panel_stride<float, 4>() * p * eb <= LDS_BUDGET) return 4;
         if ((size_t)panel_stride<float, 2>() * p * eb <= LDS_BUDGET) return 2;
+        if ((size_t)panel_stride<float, 1>() * p * eb <= LDS_BUDGET) return 1;
         return 0;
     }
     if ((size_t)panel_stride<double, 16>() * p * eb <= LDS_BUDGET) return 16;
     if ((size_t)panel_stride<double, 8>() * p * eb <= LDS_BUDGET) return 8;
     if ((size_t)panel_stride<double, 4>() * p * eb <= LDS_BUDGET) return 4;
     if ((size_t)panel_stride<double, 2>() * p * eb <= LDS_BUDGET) return 2;
+    if ((size_t)panel_stride<double, 1>() * p * eb <= LDS_BUDGET) return 1;
     return 0;
 }
 
@@ -845,8 +851,15 @@ void launch_qr_select(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs,
     int nsort = 2;
     while (nsort < max_k - outer * WIN) nsort <<= 1;
     const size_t shm = (sizeof(T) + sizeof(int)) * (size_t)nsort;
-    if (allow_lds((const void*)qr_select_kernel<T>) < shm) throw HipError("window selection exceeds LDS");
-    hipLaunchKernelGGL(qr_select_kernel<T>, dim3(n_probs), dim3(256), shm, s, A, aux, iaux, ws, probs, outer, nsort);
+    if (allow_lds((const void*)qr_select_kernel<T, T>) >= shm) {
+        hipLaunchKernelGGL((qr_select_kernel<T, T>), dim3(n_probs), dim3(256), shm, s, A, aux, iaux, ws, probs, outer,
+                           nsort);
+        return;
+    }
+    const size_t shm_f = (sizeof(float) + sizeof(int)) * (size_t)nsort;
+    if (allow_lds((const void*)qr_select_kernel<T, float>) < shm_f) throw HipError("window selection exceeds LDS");
+    hipLaunchKernelGGL((qr_select_kernel<T, float>), dim3(n_probs), dim3(256), shm_f, s, A, aux, iaux, ws, probs,
+                       outer, nsort);
 }
 
 template <typename T>
@@ -875,6 +888,7 @@ void launch_qr_panel(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, 
     else if (nb_class == 8) panel_launch<T, 8>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
     else if (nb_class == 4) panel_launch<T, 4>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
     else if (nb_class == 2) panel_launch<T, 2>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
+    else if (nb_class == 1) panel_launch<T, 1>(A, aux, iaux, ws, probs, plist, n_list, sub, max_p, s);
     else throw HipError("bad panel width");
 }
 
@@ -888,6 +902,7 @@ void launch_qr_inner(T* A, T* aux, int* iaux, T* ws, const QRProblemDev* probs, 
     else if (nb_class == 8) hipLaunchKernelGGL((qr_inner_kernel<T, 8>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
     else if (nb_class == 4) hipLaunchKernelGGL((qr_inner_kernel<T, 4>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
     else if (nb_class == 2) hipLaunchKernelGGL((qr_inner_kernel<T, 2>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
+    else if (nb_class == 1) hipLaunchKernelGGL((qr_inner_kernel<T, 1>), grid, dim3(256), 0, s, A, aux, iaux, ws, probs, plist, sub);
     else throw HipError("bad panel width");
 }
 

@@ -207,21 +207,38 @@ def test_higher_wavenumber_scattering(k, ppw, precision):
     fac.close()
 
 
-def test_complex_interpolation_too_large_for_damping_is_rejected():
+def test_largest_damped_problems_use_single_column_sub_panels():
     # interface points every grid cell at k = 300 on 256^2 make the 128 x 256
-    # box type's damped problem too large for the panel kernel's local memory;
-    # truncation alone is not accurate for complex factors, so the build stops
+    # box type's damped problem about 10000 rows tall: solved with
+    # single-column sub-panels (the panel kernel's local memory), damped, and
+    # the factor meets the tolerance
     pts = W.grid_points(256)
     b = W.contrast_bump(pts)
-    with pytest.raises(rsd.RsdError) as e:
-        rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=300.0, contrast=b,
-                   interface_ppw=4.0)
-    assert e.value.status == rsd.RSD_EINVAL
-    assert "damped" in str(e.value)
-    # the same grid with half the interface points builds and meets the tolerance
     fac = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=300.0, contrast=b,
-                     interface_ppw=2.0)
+                     interface_ppw=4.0)
+    for bx in range(fac.stats()["n_boxes"]):
+        info = fac.box_info(bx)
+        if info["r"] > 0 and info["parent"] >= 0:
+            assert fac.interp_damped(bx), info
     f = W.rhs_complex_normal(len(pts), 1, 85)
     x, _ = fac.solve(f)
     assert np.linalg.norm(fac.matvec(x) - f) <= 1e-10 * np.linalg.norm(f)
+    fac.close()
+
+
+def test_scattering_512_complex128():
+    # the scattering workload on 512^2: the complex root block (18288^2 in the
+    # float64 real form, 2.7 GB) exceeds 2 GiB (descriptors based per tile),
+    # the damped problems of the two largest types need single-column
+    # sub-panels and float sort keys; complex128 factor, 26 GB
+    pts = W.grid_points(512)
+    b = W.contrast_bump(pts)
+    fac = rsd.Factor(pts, None, 1e-8, kernel=rsd.RSD_KERNEL_HELMHOLTZ, wavenumber=K, contrast=b,
+                     max_refine=2, refine_tol=1e-8)
+    f = W.rhs_complex_normal(len(pts), 1, 87)
+    x, info = fac.solve(f)
+    res = np.linalg.norm(fac.matvec(x) - f) / np.linalg.norm(f)
+    print(f"512^2 complex128: {info.refine_iters} refinement steps, residual {res:.2e}, "
+          f"{fac.stats()['factor_bytes'] / 1e9:.1f} GB")
+    assert res <= 1e-10
     fac.close()

@@ -82,6 +82,33 @@ def test_gj_paired_pivots_invert_complex_real_forms(n):
             pass
 
 
+def test_gemm_and_gj_beyond_2gib():
+    # operands larger than 2 GiB (the buffer descriptors are based at each
+    # tile's first row / column): a 17000 x 17000 float64 C (2.3 GB) updated
+    # by a K = 64 product, and the Gauss-Jordan inverse of such a matrix;
+    # checked on sampled rows and columns
+    n, K = 17000, 64
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((n, K))
+    B = rng.standard_normal((K, n))
+    C0 = np.asfortranarray(rng.standard_normal((n, n)))
+    C = rsd.gemm(A, B, C0, alpha=-0.5, beta=2.0)
+    rows = rng.integers(0, n, 40)
+    cols = np.concatenate([rng.integers(0, n, 40), [0, n - 1]])
+    ref = -0.5 * (A[rows] @ B[:, cols]) + 2.0 * C0[np.ix_(rows, cols)]
+    assert np.abs(C[np.ix_(rows, cols)] - ref).max() <= 1e-12 * np.abs(ref).max()
+    ref_last = -0.5 * (A[-1] @ B) + 2.0 * C0[-1]
+    assert np.abs(C[-1] - ref_last).max() <= 1e-12 * np.abs(ref_last).max()
+    del C, C0
+    M = np.asfortranarray(rng.standard_normal((n, n)) * (0.5 / np.sqrt(n)))
+    M[np.diag_indices(n)] += 2.0
+    X = rsd.gj_invert(M)
+    for c in (0, 1234, n - 1):
+        e = np.zeros(n)
+        e[c] = 1.0
+        assert np.abs(M @ X[:, c] - e).max() <= 1e-12
+
+
 def test_split_k_gemm_is_repeatable():
     # the partial tiles are summed in split order whichever work-group is last
     rng = np.random.default_rng(4)
