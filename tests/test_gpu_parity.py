@@ -128,6 +128,39 @@ def test_gj_inverse_matches_numpy(n):
     assert np.abs(X - np.linalg.inv(A)).max() <= 1e-12 * np.abs(np.linalg.inv(A)).max()
 
 
+@pytest.mark.parametrize("n", [65, 150, 320])
+def test_gj_inverse_float32_several_steps(n):
+    # after the first step every pivot block is inverted by the update tile
+    # that produces it; float32 blocks take the same route
+    rng = np.random.default_rng(100 + n)
+    B = rng.standard_normal((n, n))
+    A = (B @ B.T / n + 2.0 * np.eye(n)).astype(np.float32)
+    X = rsd.gj_invert(A)
+    inv = np.linalg.inv(A.astype(np.float64))
+    assert X.dtype == np.float32
+    assert np.abs(X - inv).max() <= 2e-5 * np.abs(inv).max()
+
+
+@pytest.mark.parametrize("paired", [False, True])
+@pytest.mark.parametrize("where", [0, 64, 130])
+def test_gj_reports_zero_pivot_at_any_step(where, paired):
+    # block diagonal [I, Z] with Z's first entry zero: the pivot of step
+    # where / 64 is exactly zero (no rounding reaches it), whether the pivot
+    # kernel inverts the block (first step) or the previous update's tile does
+    n = 200
+    A = np.eye(n)
+    A[where, where] = 0.0
+    if paired:
+        A[where + 1, where + 1] = 0.0   # the 2 x 2 block [[0, 0], [0, 0]]
+    with pytest.raises(rsd.RsdError):
+        rsd.gj_invert(A, paired=paired)
+    A[where, where] = 3.0
+    if paired:
+        A[where + 1, where + 1] = -3.0
+    X = rsd.gj_invert(A, paired=paired)
+    assert np.abs(X - np.linalg.inv(A)).max() <= 1e-15
+
+
 # --- interpolation matrices (Sec. 3.1 proxy least squares) ----------------
 def test_interpolation_matches_reference_qr():
     pts = W.grid_points(64)
