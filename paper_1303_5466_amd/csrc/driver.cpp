@@ -38,6 +38,7 @@
 
 #include "../../include/rsd.h"
 #include "common.hpp"
+#include "hostpool.hpp"
 #include "plan.hpp"
 
 namespace rsd {
@@ -808,8 +809,30 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
                            PinnedBlock* pinned = nullptr, int threads = 1) {
     size_t nd = 0, nt = 0;
     int64_t max_ws = 0;
+    size_t n_descs = 0;
+    for (auto* b : bs) n_descs += b->descs.size();
+    // large lists only: below that, waking the pool costs more than it saves
+    const bool pooled = n_descs >= 16384;
+    if (!finalized && !pooled) {
+        for (auto* b : bs) b->finalize();
+    } else if (!finalized) {
+        // tile tables of the batches on the host pool (a reach error is
+        // rethrown here)
+        std::mutex emu;
+        std::exception_ptr err;
+        HostPool::get().parallel_for((int64_t)bs.size(), 4, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) {
+                try {
+                    bs[i]->finalize();
+                } catch (...) {
+                    std::lock_guard<std::mutex> lk(emu);
+                    if (!err) err = std::current_exception();
+                }
+            }
+        });
+        if (err) std::rethrow_exception(err);
+    }
     for (auto* b : bs) {
-        if (!finalized) b->finalize();
         nd += b->descs.size();
         nt += b->tiles.size() + b->slots.size();
         max_ws = std::max(max_ws, b->ws_elems);
@@ -856,6 +879,10 @@ static void upload_batches(DevBuf& buf, std::vector<GemmBatch<T>*>& bs, hipStrea
             for (size_t i = next++; i < bs.size(); i = next++) fill(i);
         };
         run_on_threads(threads, work);
+    } else if (pooled) {
+        HostPool::get().parallel_for((int64_t)bs.size(), 4, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) fill((size_t)i);
+        });
     } else {
         for (size_t i = 0; i < bs.size(); ++i) fill(i);
     }
@@ -2092,17 +2119,27 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
             }
         }
     }
-    if (ha)
-        for (int64_t i = 0; i < n; ++i)
-            if (!std::isfinite(ha[i])) throw Error(RSD_EINVAL, "non-finite value in a");
+    HostPool& pool = HostPool::get();
+    // below about 10^5 points waking the pool costs more than the loops
+    const int64_t GRAIN = n >= (int64_t(1) << 17) ? 16384 : n;
+    // every point's value checked on the host pool (flags, no throws inside)
+    auto all_of = [&](const double* v, auto pred) {
+        std::atomic<int> bad{0};
+        pool.parallel_for(n, GRAIN, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i)
+                if (!pred(v[i])) { bad.store(1, std::memory_order_relaxed); return; }
+        });
+        return bad.load() == 0;
+    };
+    if (ha && !all_of(ha, [](double x) { return std::isfinite(x); }))
+        throw Error(RSD_EINVAL, "non-finite value in a");
     // contrast (scattering) form A = I + S K S, S = diag sqrt(b) (Sec. 5.4):
     // factored as A = S M S with M = diag(1/b) + K, whose off-diagonal part is
     // the translation-invariant kernel (one T per box type); needs b > 0
     if (hb) {
         if (ha) throw Error(RSD_EINVAL, "the contrast form takes a = NULL (identity coefficient 1)");
-        for (int64_t i = 0; i < n; ++i)
-            if (!std::isfinite(hb[i]) || !(hb[i] > 0))
-                throw Error(RSD_EINVAL, "the contrast b must be finite and positive at every point");
+        if (!all_of(hb, [](double x) { return std::isfinite(x) && x > 0; }))
+            throw Error(RSD_EINVAL, "the contrast b must be finite and positive at every point");
     }
     int64_t nx, ny;
     double h, x0, y0;
@@ -2131,15 +2168,19 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     std::vector<double> ag, sbg;
     if (ha) {
         ag.resize(n);
-        for (int64_t g = 0; g < n; ++g) ag[g] = ha[perm[g]];
+        pool.parallel_for(n, GRAIN, [&](int64_t lo, int64_t hi) {
+            for (int64_t g = lo; g < hi; ++g) ag[g] = ha[perm[g]];
+        });
     }
     if (hb) {
         ag.resize(n);
         sbg.resize(n);
-        for (int64_t g = 0; g < n; ++g) {
-            ag[g] = 1.0 / hb[perm[g]];
-            sbg[g] = std::sqrt(hb[perm[g]]);
-        }
+        pool.parallel_for(n, GRAIN, [&](int64_t lo, int64_t hi) {
+            for (int64_t g = lo; g < hi; ++g) {
+                ag[g] = 1.0 / hb[perm[g]];
+                sbg[g] = std::sqrt(hb[perm[g]]);
+            }
+        });
     }
     // ---- device tables ------------------------------------------------------
     std::vector<int> lu, lv, srcc, srci, inv;
@@ -2184,8 +2225,10 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     // Only one representative per (level, layout) is built; every box's block
     // offset points at its representative's block.
     bool const_a = !hb;
-    if (ha)
-        for (int64_t i = 1; i < n && const_a; ++i) const_a = ha[i] == ha[0];
+    if (ha && const_a) {
+        const double a0 = ha[0];
+        const_a = all_of(ha, [a0](double x) { return x == a0; });
+    }
     f->dedup = allow_dedup && const_a && !(o.flags & RSD_FLAG_NO_DEDUP);
     std::vector<int> rep(P.boxes.size());
     for (size_t i = 0; i < P.boxes.size(); ++i) rep[i] = (int)i;

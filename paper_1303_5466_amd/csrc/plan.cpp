@@ -1,5 +1,6 @@
 // Host planning: tree (Sec. 2.2), skeleton sets (Sec. 3.1), proxy rings.
 #include "plan.hpp"
+#include "hostpool.hpp"
 
 
 #include <algorithm>
@@ -347,22 +348,44 @@ bool detect_grid(const double* pts, int64_t n, int64_t& nx, int64_t& ny, double&
     if (n < 1) { why = "no points"; return false; }
     // one pass for the extent, one for the second grid line of each axis (the
     // smallest coordinate above the minimum), which gives the spacing; the
-    // placement pass below then checks every point against that grid
+    // placement pass below then checks every point against that grid.  Each
+    // pass runs over chunks of points on the host pool; chunks combine their
+    // partial results under a lock.
+    HostPool& pool = HostPool::get();
+    // below about 10^5 points waking the pool costs more than the passes
+    const int64_t GRAIN = n >= (int64_t(1) << 17) ? 16384 : n;
+    std::mutex mu;
     double xmin = pts[0], xmax = pts[0], ymin = pts[1], ymax = pts[1];
-    for (int64_t i = 0; i < n; ++i) {
-        const double x = pts[2 * i], y = pts[2 * i + 1];
-        if (!std::isfinite(x) || !std::isfinite(y)) { why = "non-finite coordinate"; return false; }
-        xmin = std::min(xmin, x); xmax = std::max(xmax, x);
-        ymin = std::min(ymin, y); ymax = std::max(ymax, y);
-    }
+    bool finite = true;
+    pool.parallel_for(n, GRAIN, [&](int64_t lo, int64_t hi) {
+        double a0 = pts[2 * lo], a1 = a0, b0 = pts[2 * lo + 1], b1 = b0;
+        bool ok = true;
+        for (int64_t i = lo; i < hi; ++i) {
+            const double x = pts[2 * i], y = pts[2 * i + 1];
+            ok = ok && std::isfinite(x) && std::isfinite(y);
+            a0 = std::min(a0, x); a1 = std::max(a1, x);
+            b0 = std::min(b0, y); b1 = std::max(b1, y);
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        finite = finite && ok;
+        xmin = std::min(xmin, a0); xmax = std::max(xmax, a1);
+        ymin = std::min(ymin, b0); ymax = std::max(ymax, b1);
+    });
+    if (!finite) { why = "non-finite coordinate"; return false; }
     const double span = std::max(xmax - xmin, ymax - ymin);
     const double eps = 1e-9 * std::max(1.0, span);
     double x1 = HUGE_VAL, y1 = HUGE_VAL;
-    for (int64_t i = 0; i < n; ++i) {
-        const double x = pts[2 * i], y = pts[2 * i + 1];
-        if (x - xmin > eps) x1 = std::min(x1, x);
-        if (y - ymin > eps) y1 = std::min(y1, y);
-    }
+    pool.parallel_for(n, GRAIN, [&](int64_t lo, int64_t hi) {
+        double a = HUGE_VAL, b = HUGE_VAL;
+        for (int64_t i = lo; i < hi; ++i) {
+            const double x = pts[2 * i], y = pts[2 * i + 1];
+            if (x - xmin > eps) a = std::min(a, x);
+            if (y - ymin > eps) b = std::min(b, y);
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        x1 = std::min(x1, a);
+        y1 = std::min(y1, b);
+    });
     auto lines = [&](double lo, double hi, double second, int64_t& cnt) {
         if (second == HUGE_VAL) { cnt = 1; return true; }
         const double q = (hi - lo) / (second - lo);
@@ -384,18 +407,27 @@ bool detect_grid(const double* pts, int64_t n, int64_t& nx, int64_t& ny, double&
     y0 = ymin;
     perm.assign(n, -1);
     const double ih = 1.0 / h;
-    for (int64_t p = 0; p < n; ++p) {
-        // fi, fj >= 0 (x0, y0 are the minima): truncation rounds to nearest
-        const double fi = (pts[2 * p] - x0) * ih, fj = (pts[2 * p + 1] - y0) * ih;
-        const int64_t i = (int64_t)(fi + 0.5), j = (int64_t)(fj + 0.5);
-        if (std::fabs(fi - i) > 1e-6 || std::fabs(fj - j) > 1e-6 || i < 0 || j < 0 || i >= nx || j >= ny) {
-            why = "point off the uniform grid";
-            return false;
+    std::atomic<int> off{0}, dup{0};
+    int64_t* pm = perm.data();
+    pool.parallel_for(n, GRAIN, [&](int64_t lo, int64_t hi) {
+        for (int64_t p = lo; p < hi; ++p) {
+            // fi, fj >= 0 (x0, y0 are the minima): truncation rounds to nearest
+            const double fi = (pts[2 * p] - x0) * ih, fj = (pts[2 * p + 1] - y0) * ih;
+            const int64_t i = (int64_t)(fi + 0.5), j = (int64_t)(fj + 0.5);
+            if (std::fabs(fi - i) > 1e-6 || std::fabs(fj - j) > 1e-6 || i < 0 || j < 0 || i >= nx || j >= ny) {
+                off.store(1, std::memory_order_relaxed);
+                return;
+            }
+            int64_t expect = -1;
+            if (!__atomic_compare_exchange_n(pm + i * ny + j, &expect, p, false, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED)) {
+                dup.store(1, std::memory_order_relaxed);
+                return;
+            }
         }
-        int64_t g = i * ny + j;
-        if (perm[g] >= 0) { why = "duplicate grid point"; return false; }
-        perm[g] = p;
-    }
+    });
+    if (off.load()) { why = "point off the uniform grid"; return false; }
+    if (dup.load()) { why = "duplicate grid point"; return false; }
     return true;
 }
 
