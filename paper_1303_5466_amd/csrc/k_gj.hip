@@ -127,6 +127,34 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
         const bool ok = (q < nbe) & (c < d.ncols);
         xv[u] = gj_load<T>(rx, ok ? (q + (c - c_lo) * d.ld) * (int)sizeof(T) : GJ_RSRC_RANGE);
     }
+    // SC = old pivot columns with -I in the pivot rows; rows split over the
+    // workgroups of this box (nobody writes those columns in this kernel).
+    // Copied before the elimination, which does not need it: its loads
+    // overlap the pivot block's and its stores drain during the elimination.
+    // Unrolled so that eight independent loads are in flight per thread.
+    const int nwg = (d.ncols + CHUNK - 1) / CHUNK;
+    const int rows_per = (d.n + nwg - 1) / nwg;
+    const int r0 = blockIdx.x * rows_per, r1 = min(d.n, r0 + rows_per);
+    const int nr = max(0, r1 - r0);
+    const int tot = nr * nbe;
+    for (int e0 = 0; e0 < tot; e0 += 8 * 256) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256 + t;
+            const int q2 = e / max(nr, 1), i = r0 + (e - q2 * nr);
+            v[u] = (e < tot && !(i >= j0 && i < j0 + nbe)) ? d.X[i + (int64_t)(pc0 + q2) * d.ld] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * 256 + t;
+            if (e < tot) {
+                const int q2 = e / nr, i = r0 + (e - q2 * nr);
+                const T w = (i >= j0 && i < j0 + nbe) ? ((i - j0 == q2) ? T(-1) : T(0)) : v[u];
+                d.SC[i + (int64_t)q2 * d.n] = w;
+            }
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -304,32 +332,6 @@ __global__ void __launch_bounds__(256) gj_pivot_kernel(const GJDesc<T>* __restri
                     d.SR[q + (int64_t)c * nb] = pivc ? Pi[q][c - pc0] : acc[bi][bj][v];
                     if (!pivc) d.X[(j0 + q) + (int64_t)c * d.ld] = T(0);
                 }
-    }
-    // SC = old pivot columns with -I in the pivot rows; rows split over the
-    // workgroups of this box (nobody writes those columns in this kernel).
-    // Unrolled so that eight independent loads are in flight per thread.
-    const int nwg = (d.ncols + CHUNK - 1) / CHUNK;
-    const int rows_per = (d.n + nwg - 1) / nwg;
-    const int r0 = blockIdx.x * rows_per, r1 = min(d.n, r0 + rows_per);
-    const int nr = max(0, r1 - r0);
-    const int tot = nr * nbe;
-    for (int e0 = 0; e0 < tot; e0 += 8 * 256) {
-        T v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * 256 + t;
-            const int q2 = e / max(nr, 1), i = r0 + (e - q2 * nr);
-            v[u] = (e < tot && !(i >= j0 && i < j0 + nbe)) ? d.X[i + (int64_t)(pc0 + q2) * d.ld] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = e0 + u * 256 + t;
-            if (e < tot) {
-                const int q2 = e / nr, i = r0 + (e - q2 * nr);
-                const T w = (i >= j0 && i < j0 + nbe) ? ((i - j0 == q2) ? T(-1) : T(0)) : v[u];
-                d.SC[i + (int64_t)q2 * d.n] = w;
-            }
-        }
     }
 }
 
