@@ -2501,13 +2501,19 @@ static void enqueue_single(Factor& fr) {
         for (int c = 1; c < NCH; ++c) set_up(c);
         ps.rec.flops = fl;
         ps.rec.bytes = by;
-        std::exception_ptr chain_err;
+        // two enqueue threads, one per chain stream: the long class 1 chain
+        // (the top levels, many launches per window) on its own, so that its
+        // enqueue does not hold back the windows that finish the middle
+        // levels, which the level pipeline reaches first
+        std::exception_ptr chain_err[2];
         const int dev = f->device;
-        std::thread chains([&] {
+        int running = 2;
+        auto chain_thread = [&](int which) {
             try {
                 RSD_HIP(hipSetDevice(dev));
                 for (int sw = 0; sw < S; ++sw)
                     for (int c = 0; c < NCH; ++c) {
+                        if ((c == 1) != (which == 1)) continue;
                         if (c == 0 && sw == 0) continue;
                         std::vector<int> done;
                         publish(c32[c].window(sw, done), done);
@@ -2515,14 +2521,21 @@ static void enqueue_single(Factor& fr) {
                         publish(c64[c].window(sw, done), done);
                     }
             } catch (...) {
-                chain_err = std::current_exception();
+                chain_err[which] = std::current_exception();
             }
             {
                 std::lock_guard<std::mutex> lk(mu);
-                chains_done = true;
+                if (--running == 0) chains_done = true;
             }
             cv.notify_all();
-        });
+        };
+        std::thread chains0(chain_thread, 0);
+        std::thread chains1;
+        try {
+            chains1 = std::thread(chain_thread, 1);
+        } catch (const std::system_error&) {
+            chain_thread(1);   // no second thread: the same work on this one
+        }
         std::exception_ptr level_err;
         try {
             while (next_level < nlev && enqueue_next(true)) {
@@ -2530,8 +2543,10 @@ static void enqueue_single(Factor& fr) {
         } catch (...) {
             level_err = std::current_exception();
         }
-        chains.join();
-        if (chain_err) std::rethrow_exception(chain_err);
+        chains0.join();
+        if (chains1.joinable()) chains1.join();
+        for (auto& e : chain_err)
+            if (e) std::rethrow_exception(e);
         if (level_err) std::rethrow_exception(level_err);
         // the interpolation profile ends when both streams have
         hipEvent_t done;
