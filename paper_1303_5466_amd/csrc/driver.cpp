@@ -2061,6 +2061,35 @@ static void self_cell_integral(int type, double h, double k, double& re, double&
 
 // Host planning of a build and the uploads of its tables (on the factor's
 // stream); no kernel is launched yet.
+// Grid detection of the most recent distinct point set: repeated builds on
+// one grid (new coefficients, tolerances or kernels) compare the points with
+// it exactly and reuse its result, which is a function of the points alone.
+struct GridCache {
+    std::mutex mu;
+    std::vector<double> pts;
+    int64_t nx = 0, ny = 0;
+    double h = 0, x0 = 0, y0 = 0;
+    std::vector<int64_t> perm;
+};
+static bool detect_grid_cached(const double* pts, int64_t n, int64_t& nx, int64_t& ny, double& h, double& x0,
+                               double& y0, std::vector<int64_t>& perm, std::string& why) {
+    static GridCache* cache = new GridCache();   // outlives static destructors
+    {
+        std::lock_guard<std::mutex> lk(cache->mu);
+        if ((int64_t)cache->pts.size() == 2 * n && std::memcmp(cache->pts.data(), pts, 2 * n * sizeof(double)) == 0) {
+            nx = cache->nx; ny = cache->ny; h = cache->h; x0 = cache->x0; y0 = cache->y0;
+            perm = cache->perm;
+            return true;
+        }
+    }
+    if (!detect_grid(pts, n, nx, ny, h, x0, y0, perm, why)) return false;
+    std::lock_guard<std::mutex> lk(cache->mu);
+    cache->pts.assign(pts, pts + 2 * n);
+    cache->nx = nx; cache->ny = ny; cache->h = h; cache->x0 = x0; cache->y0 = y0;
+    cache->perm = perm;
+    return true;
+}
+
 static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, const rsd_kernel* kernel,
                                              const double* a, double tol, const rsd_options* opt,
                                              bool allow_dedup = true) {
@@ -2145,7 +2174,7 @@ static std::unique_ptr<Factor> build_prepare(const double* points, int64_t n, co
     double h, x0, y0;
     std::vector<int64_t> perm;
     std::string why;
-    if (!detect_grid(pts, n, nx, ny, h, x0, y0, perm, why)) throw Error(RSD_ENOTGRID, why);
+    if (!detect_grid_cached(pts, n, nx, ny, h, x0, y0, perm, why)) throw Error(RSD_ENOTGRID, why);
     f->N = n; f->nx = nx; f->ny = ny; f->h = h;
     try {
         f->plan = cached_plan(nx, ny, leaf, m, interface_step(ktype, wavenumber, h, o.interface_ppw));

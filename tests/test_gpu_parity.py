@@ -245,6 +245,30 @@ def test_shuffled_points_and_host_pointers():
     assert dense.rel_error(x, ref[perm]) < 1e-10
 
 
+def test_repeated_grid_in_another_order():
+    # builds alternate between two orders of one point set, so the grid
+    # detection of the previous build is reused (same points) or redone
+    # (another order); the grid-ordered factor is the same either way, so the
+    # solutions agree bitwise once mapped through the permutation
+    pts = W.grid_points(40)
+    a = W.coef_sine(pts)
+    f = W.rhs_normal(len(pts), 2, 9)
+    sp, perm = W.shuffled(pts, 3)
+    xs = []
+    for use_shuffled in (False, False, True, False, True, True):
+        if use_shuffled:
+            x, _ = rsd.Factor(sp, a[perm], 1e-10).solve(f[perm])
+            back = np.empty_like(x)
+            back[perm] = x
+            xs.append(back)
+        else:
+            x, _ = rsd.Factor(pts, a, 1e-10).solve(f)
+            xs.append(x)
+    for x in xs[1:]:
+        assert np.array_equal(x, xs[0])
+    assert dense.rel_error(xs[0], dense.solve(pts, f, a)) < 1e-10
+
+
 def test_device_pointers_for_every_input():
     pts = W.grid_points(40)
     a = W.coef_sine(pts)
