@@ -120,9 +120,12 @@ constexpr int64_t GEMM_MAX_OPERAND_BYTES = 0x7ffffff0;
 // reduce: 0 = products (d_tiles: one entry per work-group), 1 = sum the
 // partials of the split tiles listed in d_tiles into C
 // role: 0 factor levels, 1 interpolation, 2 solve sweeps, 3 library calls
+// ev_start / ev_stop (optional): events set to the launch's kernel start
+// and end (timing carried by the dispatch, no marker packets)
 template <typename T>
 void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, int tile, T* ws,
-                 int reduce, hipStream_t s, int role);
+                 int reduce, hipStream_t s, int role, hipEvent_t ev_start = nullptr,
+                 hipEvent_t ev_stop = nullptr);
 
 // generation / assembly
 // One factor of a batch group for the merged assembly launches: its arenas

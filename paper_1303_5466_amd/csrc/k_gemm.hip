@@ -26,6 +26,8 @@
 // which work-group ran first.
 #include "common.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace rsd {
 
 namespace {
@@ -500,35 +502,45 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(const GemmDesc<T>* __r
     for (int v = 0; v < 4; ++v) store_c<T, 16>(d, row0 + (lane & 15), Mfma<T>::col(lane, v), acc[v]);
 }
 
+// A launch with optional timing events attached to the dispatch.
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kernel, grid, dim3(256), 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, args...);
+}
+
 template <typename T, int ROLE>
-void launch_role(const GemmDesc<T>* d, const TileRef* t, int n, int tile, T* ws, int reduce, hipStream_t s) {
+void launch_role(const GemmDesc<T>* d, const TileRef* t, int n, int tile, T* ws, int reduce, hipStream_t s,
+                 hipEvent_t e0, hipEvent_t e1) {
     if (tile == 16) {
-        hipLaunchKernelGGL((gemm_skinny_kernel<T, ROLE>), dim3((n + 3) / 4), dim3(256), 0, s, d, t, n, ws, reduce);
+        launch_timed(gemm_skinny_kernel<T, ROLE>, dim3((n + 3) / 4), s, e0, e1, d, t, n, ws, reduce);
         return;
     }
     if (tile == 128)
-        hipLaunchKernelGGL((gemm_kernel<T, ROLE, 128>), dim3(n), dim3(256), 0, s, d, t, ws, reduce);
+        launch_timed(gemm_kernel<T, ROLE, 128>, dim3(n), s, e0, e1, d, t, ws, reduce);
     else
-        hipLaunchKernelGGL((gemm_kernel<T, ROLE, 64>), dim3(n), dim3(256), 0, s, d, t, ws, reduce);
+        launch_timed(gemm_kernel<T, ROLE, 64>, dim3(n), s, e0, e1, d, t, ws, reduce);
 }
 
 }  // namespace
 
 template <typename T>
 void launch_gemm(const GemmDesc<T>* d_descs, const TileRef* d_tiles, int n_tiles, int tile, T* ws,
-                 int reduce, hipStream_t s, int role) {
+                 int reduce, hipStream_t s, int role, hipEvent_t ev_start, hipEvent_t ev_stop) {
     if (n_tiles <= 0) return;
     switch (role) {
-        case 0: launch_role<T, 0>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
-        case 1: launch_role<T, 1>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
-        case 2: launch_role<T, 2>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
-        default: launch_role<T, 3>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s); break;
+        case 0: launch_role<T, 0>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s, ev_start, ev_stop); break;
+        case 1: launch_role<T, 1>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s, ev_start, ev_stop); break;
+        case 2: launch_role<T, 2>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s, ev_start, ev_stop); break;
+        default: launch_role<T, 3>(d_descs, d_tiles, n_tiles, tile, ws, reduce, s, ev_start, ev_stop); break;
     }
 }
 
 template void launch_gemm<double>(const GemmDesc<double>*, const TileRef*, int, int, double*, int,
-                                  hipStream_t, int);
+                                  hipStream_t, int, hipEvent_t, hipEvent_t);
 template void launch_gemm<float>(const GemmDesc<float>*, const TileRef*, int, int, float*, int,
-                                 hipStream_t, int);
+                                 hipStream_t, int, hipEvent_t, hipEvent_t);
 
 }  // namespace rsd
