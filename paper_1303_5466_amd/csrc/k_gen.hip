@@ -15,6 +15,31 @@ namespace rsd {
 
 namespace {
 
+// Walk over the elements e = i + j * rows of a column-major block, from e0 in
+// steps of `stride`: the row and column are carried from step to step, so the
+// loop needs no 64-bit division per element (only the first position is
+// divided out).  rows > 0.
+struct ColWalk {
+    int64_t e;
+    int i, j, di, dj, rows;
+    __device__ ColWalk(int64_t e0, int64_t stride, int rows_) : e(e0), rows(rows_) {
+        i = (int)(e0 % rows_);
+        j = (int)(e0 / rows_);
+        di = (int)(stride % rows_);
+        dj = (int)(stride / rows_);
+    }
+    __device__ void next(int64_t stride) {
+        e += stride;
+        i += di;
+        j += dj;
+        if (i >= rows) {
+            i -= rows;
+            ++j;
+        }
+    }
+};
+
+
 constexpr double INV_2PI = 0.15915494309189533576888376337251;
 
 // K(h * sqrt(rho2)) for rho2 > 0 (Laplace: (1/2pi) log r)
@@ -80,8 +105,11 @@ __device__ inline void leaf_F_box(T* __restrict__ F, const BoxDev* __restrict__ 
     T* Fb = F + b.offF;
     const int* U = lu + L.off_uv;
     const int* V = lv + L.off_uv;
-    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)m * m; e += (int64_t)gridDim.x * 256) {
-        const int i = (int)(e % m), j = (int)(e / m);
+    const int64_t stride_ = (int64_t)gridDim.x * 256;
+    if ((int64_t)m * m > 0)
+    for (ColWalk w(blockIdx.x * 256 + threadIdx.x, stride_, m); w.e < (int64_t)m * m; w.next(stride_)) {
+        const int64_t e = w.e;
+        const int i = w.i, j = w.j;
         if constexpr (CPLX) {
             const int64_t g = (int64_t)(b.x0 + U[i]) * kd.ny + (b.y0 + V[i]);
             Fb[e] = T(cplx_entry(kd, U[i] - U[j], V[i] - V[j], g, dof_plane(i, L.k, L.r),
@@ -141,8 +169,11 @@ __device__ inline void assemble_box(TD* __restrict__ F, const TS* __restrict__ F
     const int* V = lv + L.off_uv;
     const int* SC = src_c + L.off_uv;
     const int* SI = src_i + L.off_uv;
-    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)m * m; e += (int64_t)gridDim.x * 256) {
-        const int i = (int)(e % m), j = (int)(e / m);
+    const int64_t stride_ = (int64_t)gridDim.x * 256;
+    if ((int64_t)m * m > 0)
+    for (ColWalk w(blockIdx.x * 256 + threadIdx.x, stride_, m); w.e < (int64_t)m * m; w.next(stride_)) {
+        const int64_t e = w.e;
+        const int i = w.i, j = w.j;
         const int ci = SC[i], cj = SC[j];
         TD val;
         if (ci == cj) {
@@ -207,8 +238,11 @@ __global__ void __launch_bounds__(256) proxy_kernel(
     const int* XU = xu + xoff[pb];
     const int* XV = xv + xoff[pb];
     const int pz = CPLX ? prow / 2 : prow;    // proxy points (rows: plane 0 then plane 1)
-    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)p * n; e += (int64_t)gridDim.x * 256) {
-        const int i = (int)(e % p), j = (int)(e / p);
+    const int64_t stride_ = (int64_t)gridDim.x * 256;
+    if ((int64_t)p * n > 0)
+    for (ColWalk w(blockIdx.x * 256 + threadIdx.x, stride_, p); w.e < (int64_t)p * n; w.next(stride_)) {
+        const int64_t e = w.e;
+        const int i = w.i, j = w.j;
         if (i >= prow) {
             Ab[e] = T(0);
             continue;
@@ -250,8 +284,11 @@ __global__ void __launch_bounds__(256) sym_combine_kernel(TD* __restrict__ Ta, c
     const int kq = d.k / ns, rq = d.r / ns;
     const int64_t blk = (int64_t)kq * rq;
     const TS scale = TS(1) / TS(ns);
-    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < (int64_t)d.k * d.r; e += (int64_t)gridDim.x * 256) {
-        const int i = (int)(e % d.k), j = (int)(e / d.k);
+    const int64_t stride_ = (int64_t)gridDim.x * 256;
+    if ((int64_t)d.k * d.r > 0)
+    for (ColWalk w(blockIdx.x * 256 + threadIdx.x, stride_, d.k); w.e < (int64_t)d.k * d.r; w.next(stride_)) {
+        const int64_t e = w.e;
+        const int i = w.i, j = w.j;
         if (!d.sym) {
             Tb[e] = TD(Ts[d.offS + e]);
             continue;
