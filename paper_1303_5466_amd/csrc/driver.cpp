@@ -2529,13 +2529,8 @@ static void enqueue_single(Factor& fr) {
             done.clear();
             publish(c64[0].window(0, done), done);
         }
-        // then the level tables, staged in pinned memory (a copy from
-        // pageable memory would wait for the kernels of a stream sharing the
-        // hardware queue), then the other chains
-        upload_batches<double>(f->gemm64, f->tables64, s, false, &f->staged[0], 1);
-        upload_batches<float>(f->gemm32, f->tables32, s, false, &f->staged[1], 1);
-        upload_gj<double>(f->gj64, f->L64, s, &f->staged[2]);
-        upload_gj<float>(f->gj32, f->L32, s, &f->staged[3]);
+        // then the other chains, whose enqueue threads start before the
+        // level tables are built (the top levels' chain is the longest)
         for (int c = 1; c < NCH; ++c) set_up(c);
         ps.rec.flops = fl;
         ps.rec.bytes = by;
@@ -2576,6 +2571,13 @@ static void enqueue_single(Factor& fr) {
         }
         std::exception_ptr level_err;
         try {
+            // the level tables, staged in pinned memory (a copy from pageable
+            // memory would wait for the kernels of a stream sharing the
+            // hardware queue), while the chain threads enqueue their windows
+            upload_batches<double>(f->gemm64, f->tables64, s, false, &f->staged[0], 1);
+            upload_batches<float>(f->gemm32, f->tables32, s, false, &f->staged[1], 1);
+            upload_gj<double>(f->gj64, f->L64, s, &f->staged[2]);
+            upload_gj<float>(f->gj32, f->L32, s, &f->staged[3]);
             while (next_level < nlev && enqueue_next(true)) {
             }
         } catch (...) {
