@@ -978,7 +978,7 @@ struct Factor {
     bool dedup = false;                         // one block per (level, layout)
     std::vector<std::vector<int>> build_levels; // boxes built per level (representatives)
     std::vector<int> build_id_off;
-    DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gj64, gj32;
+    DevBuf F64, F32, T64, T32, SR, SC, gemm64, gemm32, gemm64e, gemm32e, gj64, gj32;
     hipStream_t qr_stream[2] = {nullptr, nullptr};   // interpolation chains run here
     std::vector<hipEvent_t> tmp_events;
     hipEvent_t build_ev[2] = {nullptr, nullptr};     // start / end of the device build
@@ -991,7 +991,7 @@ struct Factor {
     int* h_flag = nullptr;          // pinned word for the right-hand side check
     std::vector<GemmBatch<double>*> tables64;   // the level products, uploaded by enqueue_single
     std::vector<GemmBatch<float>*> tables32;
-    PinnedBlock staged[4];          // their pinned staging, returned by build_finish
+    PinnedBlock staged[6];          // their pinned staging, returned by build_finish
     std::vector<int> exec_index;    // level -> index into L64 or L32
     std::vector<int> layout_level;  // layout -> level of its boxes
     double gemm_flops = 0;          // flops of the level products
@@ -1008,7 +1008,7 @@ struct Factor {
             scratch.clear();
             for (DevBuf* b : {&d_boxes, &d_layouts, &d_lu, &d_lv, &d_srcc, &d_srci, &d_inv, &d_perm,
                               &d_ident, &d_a, &d_sb, &d_level_ids, &d_err, &d_table, &d_spec, &d_fftwork,
-                              &d_flag, &d_interp, &F64, &F32, &T64, &T32, &SR, &SC, &gemm64, &gemm32, &gj64, &gj32})
+                              &d_flag, &d_interp, &F64, &F32, &T64, &T32, &SR, &SC, &gemm64, &gemm32, &gemm64e, &gemm32e, &gj64, &gj32})
                 b->release();
         }
         PinnedWords::get().give(h_flag);
@@ -2573,11 +2573,42 @@ static void enqueue_single(Factor& fr) {
         try {
             // the level tables, staged in pinned memory (a copy from pageable
             // memory would wait for the kernels of a stream sharing the
-            // hardware queue), while the chain threads enqueue their windows
-            upload_batches<double>(f->gemm64, f->tables64, s, false, &f->staged[0], 1);
-            upload_batches<float>(f->gemm32, f->tables32, s, false, &f->staged[1], 1);
+            // hardware queue), while the chain threads enqueue their windows:
+            // first the Gauss-Jordan descriptors and the tables of the lowest
+            // levels, whose interpolation the first window published, which
+            // are enqueued at once, then the other levels' tables
             upload_gj<double>(f->gj64, f->L64, s, &f->staged[2]);
             upload_gj<float>(f->gj32, f->L32, s, &f->staged[3]);
+            int n_early = 0;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                while (n_early < nlev - 1 && pending[n_early] == 0) ++n_early;
+            }
+            std::vector<GemmBatch<double>*> e64, r64;
+            std::vector<GemmBatch<float>*> e32, r32;
+            auto split = [&](auto& all, auto& Ls, int prec, auto& early, auto& rest) {
+                std::vector<const void*> mine;
+                for (int t = 0; t < n_early; ++t) {
+                    if (f->level_prec[t] != prec) continue;
+                    auto& L = Ls[exec_index[t]];
+                    for (const void* b : {(const void*)&L.g_sr, (const void*)&L.g_rr, (const void*)&L.g_E})
+                        mine.push_back(b);
+                    for (auto& b : L.g_gj) mine.push_back(&b);
+                    for (auto& b : L.g_topgj) mine.push_back(&b);
+                }
+                for (auto* b : all)
+                    (std::find(mine.begin(), mine.end(), (const void*)b) != mine.end() ? early : rest).push_back(b);
+            };
+            split(f->tables64, f->L64, 0, e64, r64);
+            split(f->tables32, f->L32, 1, e32, r32);
+            if (n_early > 0) {
+                upload_batches<double>(f->gemm64e, e64, s, false, &f->staged[4], 1);
+                upload_batches<float>(f->gemm32e, e32, s, false, &f->staged[5], 1);
+                while (next_level < n_early && enqueue_next(false)) {
+                }
+            }
+            upload_batches<double>(f->gemm64, r64, s, false, &f->staged[0], 1);
+            upload_batches<float>(f->gemm32, r32, s, false, &f->staged[1], 1);
             while (next_level < nlev && enqueue_next(true)) {
             }
         } catch (...) {
