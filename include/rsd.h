@@ -367,7 +367,9 @@ typedef enum rsd_prof_class {
 
 /* Enable (on != 0) or disable the profiler and clear its records.  While
  * enabled, every launch of a timed class is bracketed by HIP events on the
- * stream it runs on; totals are read with rsd_profile_query.  The profiler is
+ * stream it runs on (the GEMM launches carry theirs in the dispatch, so they
+ * time the kernel alone; the other classes record marker events around their
+ * launches); totals are read with rsd_profile_query.  The profiler is
  * process-wide; records from several threads are collected under a lock, but
  * enabling or querying while other threads launch work is not supported. */
 rsd_status rsd_profile_enable(int32_t on);
