@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6e12, "f32": 157.3e12}   # dense MFMA, MI355X
 HBM_PEAK = 8.0e12
+PROF_EVERY = 5   # one timed step in PROF_EVERY carries the roofline kernel's events
 
 
 def log(*a):
@@ -297,18 +298,25 @@ def measure(torch, rsd, W, workload, precision, steps, warmup, fp32_interp=False
     dt = "f64" if precision == "fp64" else "f32"
     gemm_cls = "factor_gemm_f64" if dt == "f64" else "factor_gemm_f32"
     # the timed steps bracket only the roofline kernel's launches with HIP
-    # events (on the stream each runs on); the warmup creates those events
+    # events (on the stream each runs on), in every PROF_EVERY-th step: the
+    # kernel's average duration is sampled across the timed region while the
+    # other steps run without events; the warmup creates those events
     rsd.profile_enable(True, classes=[gemm_cls])
     for i in range(warmup):
         stats, info = step()
         log(f"warmup {i}: build {stats['build_ms']:.2f} ms (device)")
     torch.cuda.synchronize()
     rsd.profile_enable(True, classes=[gemm_cls])
+    prof_steps = 0
     t0 = time.perf_counter()
     for i in range(steps):
+        sampled = i % PROF_EVERY == 0
+        rsd.profile_pause(not sampled)
+        prof_steps += sampled
         stats, info = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    rsd.profile_pause(False)
     g = rsd.profile_query()[gemm_cls]
     rsd.profile_enable(False)
     ms_step = (t1 - t0) * 1e3 / steps
@@ -359,7 +367,8 @@ def measure(torch, rsd, W, workload, precision, steps, warmup, fp32_interp=False
     roof = {"bound": "mfma", "kernel": "gemm_kernel<" + ("double" if dt == "f64" else "float") + ", 0, *>",
             "class": gemm_cls, "achieved": achieved / 1e12, "peak": PEAK[dt] / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK[dt], "traffic": traffic,
-            "launches_per_step": g["launches"] // steps,
+            "launches_per_step": g["launches"] // max(prof_steps, 1),
+            "sampled_steps": prof_steps,
             "flops_per_launch": g["flops"] / max(g["launches"], 1),
             "algorithmic_bytes_per_launch": g["bytes"] / max(g["launches"], 1),
             "avg_launch_us": g["ms"] * 1e3 / max(g["launches"], 1),

@@ -380,6 +380,13 @@ rsd_status rsd_profile_enable(int32_t on);
  * time. */
 rsd_status rsd_profile_enable_mask(uint32_t mask);
 
+/* Pause (paused != 0) or resume an enabled profiler without clearing its
+ * records: while paused no launch is bracketed, so a caller can time a
+ * sample of its steps and run the others without events.  Enabling clears
+ * the pause.  Like enabling, not to be called while other threads launch
+ * work. */
+rsd_status rsd_profile_pause(int32_t paused);
+
 /* Totals for one class since the last enable: summed device time of its
  * launches (ms), launch count, algorithmic flops and algorithmic bytes
  * (operands read + written once) of those launches.  Synchronises the

@@ -408,6 +408,7 @@ struct ProfRec {
 };
 struct Profiler {
     bool on = false;
+    bool paused = false;        // on, but nothing bracketed until resumed (records kept)
     uint32_t mask = ~0u;        // classes bracketed while on
     std::mutex mu;              // solves of different factors may run on several threads
     std::vector<ProfRec> recs;
@@ -431,7 +432,7 @@ struct Profiler {
 };
 static Profiler g_prof;
 
-static bool prof_active(int cls) { return g_prof.on && cls >= 0 && cls < 32 && ((g_prof.mask >> cls) & 1u); }
+static bool prof_active(int cls) { return g_prof.on && !g_prof.paused && cls >= 0 && cls < 32 && ((g_prof.mask >> cls) & 1u); }
 
 struct ProfScope {
     bool act;
@@ -3759,6 +3760,7 @@ rsd_status rsd_profile_enable(int32_t on) {
         if (!rsd::g_prof.recs.empty()) RSD_HIP(hipDeviceSynchronize());
         rsd::g_prof.clear();
         rsd::g_prof.on = on != 0;
+        rsd::g_prof.paused = false;
         rsd::g_prof.mask = ~0u;
         return RSD_OK;
     });
@@ -3769,7 +3771,15 @@ rsd_status rsd_profile_enable_mask(uint32_t mask) {
         if (!rsd::g_prof.recs.empty()) RSD_HIP(hipDeviceSynchronize());
         rsd::g_prof.clear();
         rsd::g_prof.on = mask != 0;
+        rsd::g_prof.paused = false;
         rsd::g_prof.mask = mask;
+        return RSD_OK;
+    });
+}
+
+rsd_status rsd_profile_pause(int32_t paused) {
+    return guarded([&]() {
+        rsd::g_prof.paused = paused != 0;
         return RSD_OK;
     });
 }

@@ -115,6 +115,7 @@ EXPORTS = {
     "rsd_last_error": (C.c_char_p, []),
     "rsd_profile_enable": (C.c_int, [C.c_int32]),
     "rsd_profile_enable_mask": (C.c_int, [C.c_uint32]),
+    "rsd_profile_pause": (C.c_int, [C.c_int32]),
     "rsd_profile_record_count": (C.c_int, [C.POINTER(C.c_int64)]),
     "rsd_profile_record": (C.c_int, [C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -591,6 +592,11 @@ def profile_enable(on=True, classes=None):
         for c in classes:
             mask |= 1 << PROF_CLASSES.index(c)
         _check(load().rsd_profile_enable_mask(mask if on else 0))
+
+
+def profile_pause(paused=True):
+    """Stop (or resume) bracketing launches without clearing the records."""
+    _check(load().rsd_profile_pause(1 if paused else 0))
 
 
 def profile_records():

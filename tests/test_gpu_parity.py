@@ -1201,3 +1201,37 @@ def test_autotuned_tiles_give_the_same_solution(tmp_path):
         assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
     assert dense.rel_error(x1[2], dense.solve(grids[2], rhs[2], coefs[2])) < 1e-10
     rsd.tune_clear()
+
+
+def test_profiler_pause_keeps_records_and_skips_paused_launches():
+    # the roofline figure samples some timed steps: launches made while the
+    # profiler is paused are not bracketed, the records of the others stay
+    pts = W.grid_points(64)
+    a = W.coef_sine(pts)
+    f = W.rhs_normal(len(pts), 1, 5)
+
+    def build():
+        fac = rsd.Factor(pts, a, 1e-10)
+        x, _ = fac.solve(f)
+        fac.close()
+        return x
+
+    try:
+        rsd.profile_enable(True, classes=["factor_gemm_f64"])
+        x1 = build()
+        one = rsd.profile_query()["factor_gemm_f64"]
+        assert one["launches"] > 0 and one["ms"] > 0
+        rsd.profile_enable(True, classes=["factor_gemm_f64"])
+        rsd.profile_pause(True)
+        x2 = build()
+        assert rsd.profile_query()["factor_gemm_f64"]["launches"] == 0
+        rsd.profile_pause(False)
+        x3 = build()
+        rsd.profile_pause(True)
+        build()
+        rsd.profile_pause(False)
+        q = rsd.profile_query()["factor_gemm_f64"]
+        assert q["launches"] == one["launches"] and q["flops"] == one["flops"]
+    finally:
+        rsd.profile_enable(False)
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
