@@ -109,6 +109,10 @@ struct TileRef {
     int split, nsplit, pbase;
 };
 
+// Most waves of one work-group of the N <= 16 product kernel with split K
+// summed in the work-group (launch_gemm, tile 16, reduce < 0).
+constexpr int SKINNY_WG_WAVES = 16;
+
 // Largest byte extent of one GEMM operand from its base pointer (the kernel
 // uses 32-bit buffer offsets).
 constexpr int64_t GEMM_MAX_OPERAND_BYTES = 0x7ffffff0;
@@ -118,7 +122,9 @@ constexpr int64_t GEMM_MAX_OPERAND_BYTES = 0x7ffffff0;
 // 16-row block of C per wave; d_tiles then lists one entry per wave, tm the
 // row block); ws: split-K partial tiles;
 // reduce: 0 = products (d_tiles: one entry per work-group), 1 = sum the
-// partials of the split tiles listed in d_tiles into C
+// partials of the split tiles listed in d_tiles into C; with tile 16, -w =
+// one work-group of w waves per 16-row item (d_tiles one entry per item, its
+// nsplit K parts summed in the work-group, no partials in ws)
 // role: 0 factor levels, 1 interpolation, 2 solve sweeps, 3 library calls
 // ev_start / ev_stop (optional): events set to the launch's kernel start
 // and end (timing carried by the dispatch, no marker packets)

@@ -629,6 +629,7 @@ struct GemmBatch {
     int prof_cls = -1;
     int role = -1;      // kernel instantiation (see launch_gemm); -1: from prof_cls
     int max_split = 16; // 1: no split K, so every product's rounding is independent of the batch
+    int wg_waves = 0;   // solve products: > 0, one work-group of this many waves per 16-row item
     uint64_t tune_key = 0;  // shape bucket of a tuned launch (0: not tuned)
     void add(const GemmDesc<T>& d) {
         if (d.M <= 0 || d.N <= 0) return;
@@ -665,30 +666,29 @@ struct GemmBatch {
         slots.clear();
         ws_elems = 0;
         // the solve's products over at most 16 right-hand sides: one 16-row
-        // block per wave, K split until there are about four per compute unit
+        // block per wave, K split until there are about four per compute
+        // unit; a split item's waves form one work-group and sum their parts
+        // in LDS (no second dispatch)
         bool skinny = kernel_role() == 2;
         for (auto& d : descs) skinny = skinny && d.N <= 16;
+        wg_waves = 0;
         if (skinny) {
             tile = 16;
             int64_t blocks = 0;
             for (auto& d : descs) blocks += (d.M + 15) / 16;
+            std::vector<int> S(descs.size(), 1);
+            int smax = 1;
             for (int id = 0; id < (int)descs.size(); ++id) {
                 const auto& d = descs[id];
                 const int ksteps = (std::max(d.K, 0) + 3) / 4 + (std::max(d.K2, 0) + 3) / 4;
-                int S = 1;
                 if (blocks < 4 * CUS)
-                    S = std::max(1, std::min<int>({(int)((4 * CUS + blocks - 1) / blocks), ksteps / 16, 32}));
-                for (int rb = 0; rb < (d.M + 15) / 16; ++rb) {
-                    if (S == 1) {
-                        tiles.push_back({id, rb, 0, 0, 1, 0});
-                        continue;
-                    }
-                    const int pbase = (int)(ws_elems / 256);
-                    for (int sp = 0; sp < S; ++sp) tiles.push_back({id, rb, 0, sp, S, pbase});
-                    slots.push_back({id, rb, 0, 0, S, pbase});
-                    ws_elems += (int64_t)S * 256;
-                }
+                    S[id] = std::max(1, std::min<int>({(int)((4 * CUS + blocks - 1) / blocks), ksteps / 16,
+                                                       SKINNY_WG_WAVES}));
+                smax = std::max(smax, S[id]);
             }
+            if (smax > 1) wg_waves = smax;
+            for (int id = 0; id < (int)descs.size(); ++id)
+                for (int rb = 0; rb < (descs[id].M + 15) / 16; ++rb) tiles.push_back({id, rb, 0, 0, S[id], 0});
             return;
         }
         int64_t t64 = 0, t128 = 0;
@@ -758,7 +758,7 @@ struct GemmBatch {
         // (kernel start and end, no marker packets between the kernels)
         if (prof_active(prof_cls)) {
             ProfRec rec{prof_cls, g_prof.get(), g_prof.get(), flops, bytes, (int64_t)tiles.size()};
-            launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), tile, d_ws, 0, s, r, rec.a, rec.b);
+            launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), tile, d_ws, -wg_waves, s, r, rec.a, rec.b);
             g_prof.add(rec);
             if (!slots.empty()) {
                 ProfRec red{prof_cls, g_prof.get(), g_prof.get(), 0, 0, (int64_t)slots.size()};
@@ -766,7 +766,7 @@ struct GemmBatch {
                 g_prof.add(red);
             }
         } else {
-            launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), tile, d_ws, 0, s, r);
+            launch_gemm<T>(d_descs, d_tiles, (int)tiles.size(), tile, d_ws, -wg_waves, s, r);
             if (!slots.empty()) launch_gemm<T>(d_descs, d_slots, (int)slots.size(), tile, d_ws, 1, s, r);
         }
         if (ta) {

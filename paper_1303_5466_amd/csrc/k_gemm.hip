@@ -502,19 +502,71 @@ __global__ void __launch_bounds__(256) gemm_skinny_kernel(const GemmDesc<T>* __r
     for (int v = 0; v < 4; ++v) store_c<T, 16>(d, row0 + (lane & 15), Mfma<T>::col(lane, v), acc[v]);
 }
 
+// The solve's products with split K summed inside the work-group: one
+// work-group per 16-row item, wave w takes part w of the item's nsplit K
+// parts (the partition of gemm_skinny_kernel), the waves' partials meet in
+// LDS and wave 0 adds them in part order (0 + p0 + p1 + ..., the order of
+// the two-dispatch form) and stores C.  Waves beyond nsplit contribute
+// nothing but still pass the barrier.
+template <typename T, int ROLE>
+__global__ void __launch_bounds__(64 * SKINNY_WG_WAVES) gemm_skinny_wg_kernel(
+    const GemmDesc<T>* __restrict__ descs, const TileRef* __restrict__ items) {
+    extern __shared__ __align__(16) unsigned char skinny_smem[];
+    T* part = reinterpret_cast<T*>(skinny_smem);   // [waves - 1][4][64]
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const TileRef it = items[blockIdx.x];
+    const GemmDesc<T> d = descs[it.desc];
+    if (d.guard && *d.guard) return;   // the whole work-group (one item)
+    const int row0 = it.tm * 16;
+    typename Mfma<T>::acc_t acc = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    if (w < it.nsplit) {
+        const int n1 = (max(d.K, 0) + 3) / 4, n2 = (max(d.K2, 0) + 3) / 4;
+        const int s0 = (int)((int64_t)w * (n1 + n2) / it.nsplit);
+        const int s1 = (int)((int64_t)(w + 1) * (n1 + n2) / it.nsplit);
+        skinny_segment<T>(d.A, d.lda, d.tA, d.B, d.ldb, d.tB, d.M, d.N, 4 * min(s0, n1),
+                          min(4 * min(s1, n1), d.K), row0, acc);
+        skinny_segment<T>(d.A2, d.lda2, d.tA2, d.B2, d.ldb2, d.tB2, d.M, d.N, 4 * (max(s0, n1) - n1),
+                          min(4 * (max(s1, n1) - n1), max(d.K2, 0)), row0, acc);
+    }
+    if (w > 0 && w < it.nsplit)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[((w - 1) * 4 + v) * 64 + lane] = acc[v];
+    __syncthreads();
+    if (w != 0) return;
+    typename Mfma<T>::acc_t sum = typename Mfma<T>::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sum[v] += acc[v];
+    for (int sp = 1; sp < it.nsplit; ++sp)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum[v] += part[((sp - 1) * 4 + v) * 64 + lane];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) store_c<T, 16>(d, row0 + (lane & 15), Mfma<T>::col(lane, v), sum[v]);
+}
+
 // A launch with optional timing events attached to the dispatch.
 template <typename F, typename... Args>
-inline void launch_timed(F kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+inline void launch_timed_b(F kernel, dim3 grid, dim3 block, size_t shm, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1, Args... args) {
     if (e0 || e1)
-        hipExtLaunchKernelGGL(kernel, grid, dim3(256), 0, s, e0, e1, 0, args...);
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, e0, e1, 0, args...);
     else
-        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, args...);
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+}
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1, Args... args) {
+    launch_timed_b(kernel, grid, dim3(256), 0, s, e0, e1, args...);
 }
 
 template <typename T, int ROLE>
 void launch_role(const GemmDesc<T>* d, const TileRef* t, int n, int tile, T* ws, int reduce, hipStream_t s,
                  hipEvent_t e0, hipEvent_t e1) {
     if (tile == 16) {
+        if (reduce < 0) {   // -reduce waves per item, split K summed in the work-group
+            const int waves = std::min(-reduce, SKINNY_WG_WAVES);
+            launch_timed_b(gemm_skinny_wg_kernel<T, ROLE>, dim3(n), dim3(64 * waves),
+                           (size_t)(waves - 1) * 256 * sizeof(T), s, e0, e1, d, t);
+            return;
+        }
         launch_timed(gemm_skinny_kernel<T, ROLE>, dim3((n + 3) / 4), s, e0, e1, d, t, n, ws, reduce);
         return;
     }
